@@ -1,0 +1,255 @@
+"""LASSO quantities and the Polyatomic Frank-Wolfe solver (TEST INFRASTRUCTURE).
+
+Paper passages followed:
+  * LASSO objective  P(x) = 1/2 ||V - Phi x||^2 + lambda ||x||_1   (Eq. lasso).
+  * lambda_max = ||Phi* V||_inf (Eq. lmax); lambda = alpha lambda_max (Eq. lambda).
+  * dual certificate mu = Phi*(V - Phi x) / lambda (Eq. dual_certif), with
+    ||mu||_inf <= 1 and <mu, x> = ||x||_1 at a solution (Eqs. dual-saturation).
+  * Polyatomic Frank-Wolfe of quality delta (Alg. 2):
+        Delta = (1 - delta) ||Phi* V||_inf,  x_0 = 0, S_0 = {}
+        for k = 0, 1, ...:
+            eta_k = Phi*(V - Phi x_k)                      (dirty residual)
+            I     = { j : |eta_k|_j >= ||eta_k||_inf - 2 Delta / (k + 2) }
+            S     = S u I
+            x     = argmin over supp(x) in S of the LASSO  (restricted solve)
+            S     = supp(x)                                 (prune)
+            stop if a criterion holds.
+  * The restricted solve is an accelerated proximal gradient (APGD / FISTA,
+    Sect. 3.4), stopped early with an accuracy that tightens over the FW
+    iterations (Sect. 5.1, "The algorithmic steps").
+
+Readings of points the paper leaves open (shared with the GPU path):
+  * delta is a parameter (its value is never printed);
+  * inner stop: ||x_{t+1} - x_t|| <= tau_k ||x_{t+1}||, tau_k =
+    max(tau_min, tau_0 / (k + 1)), plus an iteration cap;
+  * warm start: the previous weights, new atoms start at zero;
+  * step size 1 / L_ip with L_ip the largest eigenvalue of the restricted
+    normal matrix (computed exactly here);
+  * relative improvement |P_k - P_{k-1}| / P_{k-1} with P_{-1} = P(0);
+  * duality gap: primal P(x) minus the dual value D(nu) = Re<V, nu> - ||nu||^2/2
+    at the rescaled residual nu = min(1, lambda / ||Phi* r||_inf) r;
+  * ties in the exploration threshold are inclusive (">=", as printed).
+
+The restricted problem is solved with the exact normal matrix
+G_S = Re(Phi_S^H Phi_S) and b_S = Phi_S^* V, a different route from the GPU's
+operator applications that computes the same mathematics.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+from .geometry import pixel_coords
+from .operator import adjoint, forward
+
+_CHUNK_ELEMS = 1 << 22
+
+
+def soft(z: np.ndarray, t: float) -> np.ndarray:
+    """Proximal map of t ||.||_1 (soft thresholding)."""
+    return np.sign(z) * np.maximum(np.abs(z) - t, 0.0)
+
+
+def objective(vis, fit, weight, lam: float) -> float:
+    """P(x) = 1/2 ||V - Phi x||^2 + lambda ||x||_1 (Eq. lasso)."""
+    r = np.asarray(vis, np.complex128) - np.asarray(fit, np.complex128)
+    return 0.5 * float(np.vdot(r, r).real) + lam * float(np.sum(np.abs(weight)))
+
+
+def dual_gap(vis, resid, adj_resid_inf: float, primal: float, lam: float):
+    """(gap, dual) for the rescaled-residual dual point."""
+    vis = np.asarray(vis, np.complex128)
+    resid = np.asarray(resid, np.complex128)
+    s = 1.0 if adj_resid_inf <= lam else lam / adj_resid_inf
+    nu = s * resid
+    dual = float(np.vdot(vis, nu).real) - 0.5 * float(np.vdot(nu, nu).real)
+    return primal - dual, dual
+
+
+class GramCache:
+    """Columns of G = Re(Phi^H Phi) for every pixel ever activated.
+
+    G[p, q] = Re sum_k exp(+j2pi t_kp) exp(-j2pi t_kq) / (n_p n_q), with
+    t_kp = u_k l_p + v_k m_p.  Computed with complex128 matrix products over
+    chunks of visibilities; only pairs involving new pixels are computed.
+    """
+
+    def __init__(self, uv, npix: int, fov_rad: float):
+        self.uv = np.asarray(uv, np.float64)
+        self.npix, self.fov = npix, fov_rad
+        self.pix = np.zeros(0, np.int64)
+        self.G = np.zeros((0, 0))
+
+    def _cols(self, pix):
+        lp, mp, npp = pixel_coords(pix, self.npix, self.fov)
+        return lp, mp, npp
+
+    def ensure(self, pix_new: np.ndarray):
+        pix_new = np.setdiff1d(np.asarray(pix_new, np.int64), self.pix)
+        if pix_new.size == 0:
+            return
+        old = self.pix
+        allp = np.concatenate([old, pix_new])
+        lo, mo, no = self._cols(old)
+        ln, mn, nn = self._cols(pix_new)
+        u, v = self.uv[:, 0], self.uv[:, 1]
+        g_no = np.zeros((pix_new.size, old.size))
+        g_nn = np.zeros((pix_new.size, pix_new.size))
+        step = max(1, _CHUNK_ELEMS // max(1, allp.size))
+        for s in range(0, u.size, step):
+            us, vs = u[s:s + step], v[s:s + step]
+            en = np.exp(-2j * np.pi * (np.outer(us, ln) + np.outer(vs, mn))) / nn
+            g_nn += (en.conj().T @ en).real
+            if old.size:
+                eo = np.exp(-2j * np.pi * (np.outer(us, lo) + np.outer(vs, mo))) / no
+                g_no += (en.conj().T @ eo).real
+        G = np.zeros((allp.size, allp.size))
+        G[:old.size, :old.size] = self.G
+        G[old.size:, :old.size] = g_no
+        G[:old.size, old.size:] = g_no.T
+        G[old.size:, old.size:] = g_nn
+        order = np.argsort(allp)
+        self.pix = allp[order]
+        self.G = G[np.ix_(order, order)]
+
+    def sub(self, pix: np.ndarray) -> np.ndarray:
+        idx = np.searchsorted(self.pix, pix)
+        return self.G[np.ix_(idx, idx)]
+
+
+def fista_restricted(G: np.ndarray, b: np.ndarray, lam: float, x0: np.ndarray,
+                     tol: float, max_iter: int, lip: Optional[float] = None):
+    """argmin_x 1/2 x^T G x - b^T x + lam ||x||_1 by FISTA (Beck & Teboulle).
+
+    Gradient step 1/L with L the largest eigenvalue of G, soft-threshold at
+    lam/L, momentum t+ = (1 + sqrt(1 + 4 t^2))/2.  Stops when
+    ||x+ - x|| <= tol ||x+|| or after max_iter iterations.
+    Returns (x, iterations).
+    """
+    if lip is None:
+        lip = float(np.linalg.eigvalsh(G)[-1]) if G.size else 1.0
+    x = x0.astype(np.float64).copy()
+    y = x.copy()
+    t = 1.0
+    it = 0
+    for it in range(1, max_iter + 1):
+        z = y - (G @ y - b) / lip
+        xn = soft(z, lam / lip)
+        tn = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+        y = xn + ((t - 1.0) / tn) * (xn - x)
+        diff = float(np.linalg.norm(xn - x))
+        nrm = float(np.linalg.norm(xn))
+        x, t = xn, tn
+        if diff <= tol * nrm:
+            break
+    return x, it
+
+
+@dataclasses.dataclass
+class IterLog:
+    k: int
+    n_active: int
+    n_new: int
+    eta_inf: float
+    objective: float
+    rel_gap: float
+    inner_iters: int
+
+
+@dataclasses.dataclass
+class SolveResult:
+    pix: np.ndarray
+    weight: np.ndarray
+    objective: float
+    rel_gap: float
+    lam: float
+    lambda_max: float
+    iters: int
+    converged: bool
+    eta: np.ndarray          # final dirty residual Phi*(V - Phi x), (n, n)
+    fit: np.ndarray          # Phi x, (L,)
+    log: List[IterLog]
+
+    @property
+    def certificate(self) -> np.ndarray:
+        return self.eta / self.lam
+
+
+def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
+              lam: Optional[float] = None, delta: float = 0.99,
+              max_iter: int = 50, rel_obj_tol: float = 0.0,
+              rel_gap_tol: float = 0.0, inner_tol0: float = 1e-1,
+              inner_tol_min: float = 1e-6, inner_max_iter: int = 500,
+              dirty: Optional[np.ndarray] = None) -> SolveResult:
+    """Polyatomic Frank-Wolfe for the point-source LASSO (Alg. 2).
+
+    ``alpha`` sets lambda = alpha * lambda_max unless ``lam`` > 0 is given.
+    Stops after the prune of iteration k when k + 1 = max_iter, or when the
+    relative objective improvement is <= rel_obj_tol, or when the relative
+    duality gap is <= rel_gap_tol (a tolerance <= 0 disables that test).
+    """
+    vis = np.asarray(vis, np.complex128)
+    if dirty is None:
+        dirty = adjoint(uv, npix, fov_rad, vis)
+    lmax = float(np.max(np.abs(dirty)))
+    if lam is None or lam <= 0:
+        lam = alpha * lmax
+    big_delta = (1.0 - delta) * lmax
+    gram = GramCache(uv, npix, fov_rad)
+    b_all = dirty.reshape(-1)                       # Phi_S^* V = dirty image on S
+    S = np.zeros(0, np.int64)
+    x = np.zeros(0)
+    eta = dirty.copy()
+    p_prev = 0.5 * float(np.vdot(vis, vis).real)    # P(x_0 = 0)
+    log: List[IterLog] = []
+    fit = np.zeros_like(vis)
+    rel_gap = np.inf
+    converged = False
+    k = 0
+    for k in range(max_iter):
+        a = np.abs(eta).reshape(-1)
+        tau = float(a.max()) - 2.0 * big_delta / (k + 2)
+        new = np.flatnonzero(a >= tau)
+        S_new = np.union1d(S, new)
+        xw = np.zeros(S_new.size)
+        if S.size:
+            xw[np.searchsorted(S_new, S)] = x
+        gram.ensure(S_new)
+        G = gram.sub(S_new)
+        tol = max(inner_tol_min, inner_tol0 / (k + 1))
+        x, nin = fista_restricted(G, b_all[S_new], lam, xw, tol, inner_max_iter)
+        keep = x != 0.0
+        S, x = S_new[keep], x[keep]
+        fit = forward(uv, npix, fov_rad, S, x)
+        resid = vis - fit
+        eta = adjoint(uv, npix, fov_rad, resid)
+        p = objective(vis, fit, x, lam)
+        gap, _ = dual_gap(vis, resid, float(np.max(np.abs(eta))), p, lam)
+        rel_gap = gap / p if p > 0 else 0.0
+        rel_imp = abs(p - p_prev) / p_prev if p_prev > 0 else 0.0
+        log.append(IterLog(k, int(S.size), int(new.size), float(a.max()), p, rel_gap, nin))
+        p_prev = p
+        if rel_obj_tol > 0 and rel_imp <= rel_obj_tol:
+            converged = True
+            break
+        if rel_gap_tol > 0 and rel_gap <= rel_gap_tol:
+            converged = True
+            break
+    p_final = objective(vis, fit, x, lam)
+    return SolveResult(S, x, p_final, float(rel_gap), float(lam), lmax, k + 1,
+                       converged, eta, fit, log)
+
+
+def certificate(uv, npix, fov_rad, vis, pix, weight, lam: float) -> np.ndarray:
+    """mu = Phi*(V - Phi x) / lambda (Eq. dual_certif) as an (n, n) image."""
+    fit = forward(uv, npix, fov_rad, pix, weight)
+    return adjoint(uv, npix, fov_rad, np.asarray(vis, np.complex128) - fit) / lam
+
+
+def argmax_abs(img: np.ndarray):
+    """(max |img|, lowest flat index attaining it)."""
+    a = np.abs(np.asarray(img)).reshape(-1)
+    m = a.max()
+    return float(m), int(np.flatnonzero(a == m)[0])

@@ -1,0 +1,158 @@
+"""Pins for the oracle's LASSO / Polyatomic Frank-Wolfe solver (T10-T16).
+
+Pinned against: the closed-form LASSO solution of an orthogonal design,
+the optimality conditions of the certificate (Eqs. dual-saturation1/2), the
+alpha identity of Sect. 5.3, Hermitian doubling, the lambda >= lambda_max
+case (Eq. lmax), an independent coordinate-descent solver, and the delta = 1
+special case of Alg. 2.
+"""
+import numpy as np
+import pytest
+
+import sim
+from oracle import brute, geometry, operator, solver
+
+TIGHT = dict(rel_gap_tol=1e-12, inner_tol0=1e-6, inner_tol_min=1e-15,
+             inner_max_iter=50000, max_iter=200)
+
+
+def _problem(seed, L=160, n=8, fov=0.25, n_src=3, noise=0.05):
+    rng = np.random.default_rng(seed)
+    uv = rng.uniform(-12, 12, size=(L, 2))
+    pix = rng.choice(n * n, n_src, replace=False)
+    amp = np.exp(rng.normal(size=n_src))
+    V = operator.forward(uv, n, fov, pix, amp)
+    V = V + noise * np.max(np.abs(V)) * (rng.normal(size=L) + 1j * rng.normal(size=L))
+    return uv, n, fov, V
+
+
+def test_soft_threshold():
+    z = np.array([-3.0, -1.0, 0.0, 0.5, 2.0])
+    assert np.array_equal(solver.soft(z, 1.0), [-2.0, -0.0, 0.0, 0.0, 1.0])
+
+
+def test_orthogonal_design_closed_form():
+    """T10: uv on the DFT frequencies => x_p = soft((Phi*V)_p, lam) n_p^2 / n^2."""
+    n, fov = 8, 0.3
+    uv = sim.orthogonal_uv(n, fov)
+    rng = np.random.default_rng(11)
+    V = rng.normal(size=uv.shape[0]) + 1j * rng.normal(size=uv.shape[0])
+    res = solver.pfw_solve(uv, n, fov, V, alpha=0.3, delta=0.5, **TIGHT)
+    b = operator.adjoint(uv, n, fov, V).reshape(-1)
+    nn = geometry.n_term(n, fov).reshape(-1)
+    want = solver.soft(b, res.lam) * nn ** 2 / n ** 2
+    got = np.zeros(n * n)
+    got[res.pix] = res.weight
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+    assert np.array_equal(res.pix, np.flatnonzero(want))
+
+
+def test_brute_force_matches_orthogonal_closed_form():
+    n, fov = 6, 0.3
+    uv = sim.orthogonal_uv(n, fov)
+    rng = np.random.default_rng(12)
+    V = rng.normal(size=uv.shape[0]) + 1j * rng.normal(size=uv.shape[0])
+    A = brute.explicit_matrix(uv, n, fov)
+    y = np.concatenate([V.real, V.imag])
+    b = operator.adjoint(uv, n, fov, V).reshape(-1)
+    lam = 0.4 * np.max(np.abs(b))
+    x, obj, rel, _ = brute.lasso_cd(A, y, lam)
+    nn = geometry.n_term(n, fov).reshape(-1)
+    assert np.allclose(x, solver.soft(b, lam) * nn ** 2 / n ** 2, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pfw_matches_coordinate_descent(seed):
+    """T15: PFW and brute-force CD agree on objective (1e-9) and fit."""
+    uv, n, fov, V = _problem(seed)
+    res = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=0.9, **TIGHT)
+    A = brute.explicit_matrix(uv, n, fov)
+    y = np.concatenate([V.real, V.imag])
+    x, obj, rel, _ = brute.lasso_cd(A, y, res.lam)
+    assert abs(res.objective - obj) <= 1e-9 * obj
+    fit_cd = A @ x
+    fit_fw = np.concatenate([res.fit.real, res.fit.imag])
+    assert np.linalg.norm(fit_fw - fit_cd) <= 1e-5 * np.linalg.norm(fit_cd)
+
+
+def test_kkt_and_alpha_identity():
+    """T11 + T12: ||mu||_inf <= 1 + 1e-6, mu = sign(x) on the support, and
+    ||Phi*(V - Phi x)||_inf / ||Phi* V||_inf = alpha."""
+    uv, n, fov, V = _problem(3, L=220, n=10)
+    alpha = 0.08
+    res = solver.pfw_solve(uv, n, fov, V, alpha=alpha, delta=0.9, **TIGHT)
+    assert res.rel_gap <= 1e-12 and res.pix.size > 0
+    mu = res.certificate.reshape(-1)
+    assert np.max(np.abs(mu)) <= 1 + 1e-6
+    assert np.allclose(mu[res.pix], np.sign(res.weight), atol=1e-6, rtol=0)
+    # <mu, x> = ||x||_1 (Eq. dual-saturation1)
+    assert abs(mu[res.pix] @ res.weight - np.abs(res.weight).sum()) <= 1e-6 * np.abs(res.weight).sum()
+    assert abs(np.max(np.abs(res.eta)) / res.lambda_max - alpha) <= 1e-6 * alpha
+    # certificate helper agrees with the solver's own final residual image
+    mu2 = solver.certificate(uv, n, fov, V, res.pix, res.weight, res.lam)
+    assert np.allclose(mu2.reshape(-1), mu, rtol=1e-10, atol=1e-10)
+
+
+def test_hermitian_doubling():
+    """T13: duplicating the conjugate half doubles P and lambda_max and keeps x."""
+    uv, n, fov, V = _problem(4)
+    r1 = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=0.9, **TIGHT)
+    r2 = solver.pfw_solve(np.concatenate([uv, -uv]), n, fov, np.concatenate([V, V.conj()]),
+                          alpha=0.1, delta=0.9, **TIGHT)
+    assert abs(r2.lambda_max - 2 * r1.lambda_max) <= 1e-10 * r1.lambda_max
+    assert abs(r2.objective - 2 * r1.objective) <= 1e-9 * r1.objective
+    x1 = np.zeros(n * n); x1[r1.pix] = r1.weight
+    x2 = np.zeros(n * n); x2[r2.pix] = r2.weight
+    assert np.linalg.norm(x1 - x2) <= 1e-5 * np.linalg.norm(x1)
+
+
+def test_lambda_above_lambda_max_gives_zero():
+    """T14: alpha > 1 => empty support, P = ||V||^2/2, zero gap (Eq. lmax)."""
+    uv, n, fov, V = _problem(5)
+    res = solver.pfw_solve(uv, n, fov, V, alpha=1.0001, delta=0.9, max_iter=5,
+                           rel_gap_tol=1e-12)
+    assert res.pix.size == 0
+    half = 0.5 * float(np.vdot(V, V).real)
+    assert abs(res.objective - half) <= 1e-15 * half
+    assert abs(res.rel_gap) <= 1e-14
+    assert res.iters == 1 and res.converged
+
+
+def test_delta_one_adds_only_the_argmax():
+    """T16: delta = 1 => Delta = 0 => each exploration adds the argmax set."""
+    uv, n, fov, V = _problem(6)
+    dirty = operator.adjoint(uv, n, fov, V)
+    res = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=1.0, max_iter=4)
+    assert all(it.n_new == 1 for it in res.log)
+    m, idx = solver.argmax_abs(dirty)
+    # first iteration: the only atom is the dirty-image argmax
+    r1 = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=1.0, max_iter=1)
+    assert r1.pix.tolist() == [idx]
+
+
+def test_exploration_band_size_grows_with_delta_gap():
+    """Smaller delta admits at least as many candidates at k = 0."""
+    uv, n, fov, V = _problem(7)
+    a = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=0.99, max_iter=1)
+    b = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=0.5, max_iter=1)
+    assert b.log[0].n_new >= a.log[0].n_new
+
+
+def test_objective_and_gap_helpers():
+    uv, n, fov, V = _problem(8)
+    p = solver.objective(V, np.zeros_like(V), np.zeros(0), 1.0)
+    assert p == 0.5 * float(np.vdot(V, V).real)
+    lmax = np.max(np.abs(operator.adjoint(uv, n, fov, V)))
+    gap, dual = solver.dual_gap(V, V, lmax, p, lmax)
+    assert abs(gap) <= 1e-12 * p
+
+
+def test_stop_rules():
+    uv, n, fov, V = _problem(9)
+    r = solver.pfw_solve(uv, n, fov, V, alpha=0.05, delta=0.9, max_iter=3)
+    assert r.iters == 3 and not r.converged
+    r = solver.pfw_solve(uv, n, fov, V, alpha=0.05, delta=0.9, max_iter=100,
+                         rel_obj_tol=1e-4)
+    assert r.converged
+    objs = [it.objective for it in r.log]
+    assert abs(objs[-1] - objs[-2]) / objs[-2] <= 1e-4
