@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: PolyCLEAN solves on the LOFAR-like workload (one MI355X).
+
+A step is one full PolyCLEAN solve (Alg. 2: dirty image, polyatomic
+exploration, APGD on the active set with the direct sparse forward and
+restricted adjoint, pruning, dirty residual by the gridded adjoint, duality
+gap stop) of the LOFAR-like problem: 60 stations (48 in a 300 m Gaussian
+core, 12 in a 1-10 km ring), 240 snapshots over 4 h -> 424,800 complex64
+visibilities, 1024^2 grid, FOV 4 deg, 150 log-normal point sources at 20 dB,
+lambda = 0.05 lambda_max, stop at relative duality gap 1e-4.  Inputs are
+synthesised from the seeded generator and resident in HBM before timing; the
+plan (geometry, sort) is built once, outside the timed region, and its build
+time is reported separately.
+
+value = adjoint throughput in Mvis/s: visibilities gridded per second of
+device time of the gridded adjoint (spread, fold, two FFT passes, correction),
+measured with HIP events by the library around every adjoint of the timed
+solves.  The line also carries solves/s, the per-kernel roofline of the
+dominant kernel of a profiled solve and the FP64 oracle timed on the host.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "adjoint Mvis/s (%HBM roofline); solves/s + p50/p99 latency vs plain @1e-4"
+HBM_PEAK_GBS = 8000.0
+# Direct-DFT pair rate ceiling (pairs/s), derived in the design doc from the gfx950
+# VALU issue rates and the instruction mix of one visibility-atom pair.
+DFT_PEAK_GPAIRS = float(os.environ.get("PC_DFT_PEAK_GPAIRS", "0")) or None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--adjoint-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def synth_inputs(api, torch, p):
+    """Noisy visibilities of the sky: forward of the sky atoms on the GPU plus
+    the generator's noise draw scaled to the PSNR (input synthesis only)."""
+    import numpy as np
+    import sim
+    plan = api.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    pix = torch.from_numpy(p.sky_pix.astype(np.int32)).cuda()
+    amp = torch.from_numpy(p.sky_amp.astype(np.float32)).cuda()
+    vclean = api.pc_forward_sparse(plan, pix, amp).cpu().numpy().astype(np.complex128)
+    vis = sim.add_noise(vclean, p.noise, p.psnr_db).astype(np.complex64)
+    return plan, vis
+
+
+def dominant_roofline(stats, plan_info):
+    """Roofline object for the kernel with the largest device time."""
+    top = max(stats, key=lambda s: s["ms"])
+    avg_ms = top["ms"] / top["launches"]
+    name = top["name"]
+    if name in ("forward_sparse", "adjoint_sparse"):
+        pairs = top["work"] / top["launches"]
+        achieved = pairs / (avg_ms * 1e-3) / 1e9
+        return {"kernel": name, "bound": "alu", "achieved": achieved,
+                "peak": DFT_PEAK_GPAIRS, "unit": "Gpair/s",
+                "frac": (achieved / DFT_PEAK_GPAIRS) if DFT_PEAK_GPAIRS else None,
+                "traffic": None, "avg_ms": avg_ms, "launches": top["launches"],
+                "work_per_launch": pairs}
+    b = top["bytes"] / top["launches"]
+    achieved = b / (avg_ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_ms": avg_ms, "launches": top["launches"], "bytes_per_launch": b}
+
+
+def cpu_baseline(p, vis, seconds):
+    """FP64 oracle adjoint on a bounded sample (a visibility subset, full
+    image) on the host cores, in Mvis/s."""
+    import numpy as np
+    from oracle import operator
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    v = vis.astype(np.complex128)
+    n0 = 2048
+    t = time.perf_counter()
+    operator.adjoint(p.uv[:n0], p.npix, p.fov_rad, v[:n0])
+    dt = time.perf_counter() - t
+    m = int(min(len(v), max(n0, n0 * seconds / max(dt, 1e-3))))
+    t = time.perf_counter()
+    operator.adjoint(p.uv[:m], p.npix, p.fov_rad, v[:m])
+    dt = time.perf_counter() - t
+    return {"value": m / dt / 1e6, "unit": "Mvis/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"FP64 exact adjoint (direct sum as chunked complex GEMM) of the first {m} "
+                      f"of {len(v)} visibilities onto the full {p.npix}^2 image, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
+              "part of this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import sim
+    from paper_2406_01342_amd import api
+
+    torch.cuda.set_device(0)
+    p = sim.config_c2()
+    log("workload C2", p.nvis, "visibilities", p.npix, "pixels")
+    t = time.perf_counter()
+    plan0, vis = synth_inputs(api, torch, p)
+    del plan0
+    t = time.perf_counter()
+    plan = api.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t) * 1e3
+    log("plan", f"{plan_ms:.1f} ms", plan.info)
+    dv = torch.from_numpy(vis).cuda()
+    prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter, rel_gap_tol=p.rel_gap_tol)
+
+    for w in range(args.warmup):
+        r = api.pc_polyclean_solve(plan, dv, **prm)
+        log("warmup", w, {k: r[k] for k in ("iters", "natoms", "objective", "rel_gap", "seconds")})
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for k in range(args.steps):
+        r = api.pc_polyclean_solve(plan, dv, **prm)
+        results.append(r)
+        log("step", k, {kk: r[kk] for kk in ("iters", "inner_iters", "natoms", "objective",
+                                              "rel_gap", "seconds", "adjoint_calls")})
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    adj_calls = sum(r["adjoint_calls"] for r in results)
+    adj_s = sum(r["adjoint_seconds"] for r in results)
+    value = p.nvis * adj_calls / adj_s / 1e6
+
+    # standalone adjoint (caller-order input) timed with events on its stream
+    img = torch.empty((p.npix, p.npix), dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.adjoint_reps):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    e1.record(s)
+    e1.synchronize()
+    adj_ms = e0.elapsed_time(e1) / args.adjoint_reps
+
+    # one profiled solve: per-kernel device time and algorithmic bytes / work
+    api.pc_plan_profile(plan, True)
+    api.pc_polyclean_solve(plan, dv, **prm)
+    stats = api.pc_plan_kernel_stats(plan)
+    api.pc_plan_profile(plan, True)
+    for _ in range(args.adjoint_reps):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    adj_stats = api.pc_plan_kernel_stats(plan)
+    api.pc_plan_profile(plan, False)
+    roof = dominant_roofline(stats, plan.info)
+    adj_roof = dominant_roofline(adj_stats, plan.info)
+    adj_bytes = sum(st["bytes"] for st in adj_stats) / args.adjoint_reps
+    adj_dev_ms = sum(st["ms"] for st in adj_stats) / args.adjoint_reps
+    n = p.npix
+    b_model_f1 = 16 * p.nvis + 100 * n * n
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mvis/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "LOFAR-like PolyCLEAN solve: 60 stations (48-station 300 m "
+                               "Gaussian core + 12 in a 1-10 km ring), 240 snapshots over 4 h, "
+                               "424,800 complex64 visibilities, 1024^2 grid, FOV 4 deg, 150 "
+                               "log-normal sources, 20 dB, lambda = 0.05 lambda_max, stop at "
+                               "relative duality gap 1e-4",
+                   "nvis": p.nvis, "npix": n, "fine_grid": plan.info["fine"],
+                   "kernel_width": plan.info["kernel_width"], "band_wraps": plan.info["wraps"]},
+        "roofline": roof,
+        "solves_per_s": args.steps / wall,
+        "solve": {"iters": results[-1]["iters"], "inner_iters": results[-1]["inner_iters"],
+                  "natoms": results[-1]["natoms"], "objective": results[-1]["objective"],
+                  "rel_gap": results[-1]["rel_gap"], "adjoint_calls_per_solve": adj_calls / args.steps},
+        "plan_ms": plan_ms,
+        "adjoint": {"ms_standalone": adj_ms, "mvis_per_s_standalone": p.nvis / adj_ms / 1e3,
+                    "device_ms_sum_of_kernels": adj_dev_ms,
+                    "algorithmic_bytes": adj_bytes, "hbm_frac_implemented": adj_bytes / (adj_dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "bytes_model_f1": b_model_f1,
+                    "hbm_frac_f1": b_model_f1 / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "dominant_kernel": adj_roof},
+        "kernels": sorted(({"name": s_["name"], "launches": s_["launches"], "ms": round(s_["ms"], 3)}
+                           for s_ in stats), key=lambda d: -d["ms"])[:8],
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(p, vis, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

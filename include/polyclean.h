@@ -1,0 +1,278 @@
+/*
+ * polyclean.h -- C ABI of the MI355X (gfx950) PolyCLEAN measurement-operator
+ * library (libpolyclean.so).
+ *
+ * Method: Jarret et al. 2024, "PolyCLEAN: Atomic Optimization for
+ * Super-Resolution Imaging and Uncertainty Estimation in Radio
+ * Interferometry".  The library computes
+ *   - the discrete forward operator Phi (Sect. 2.2, Eq. phi-discrete):
+ *       V_k = sum_p x_p / n_p * exp(-j 2 pi (u_k l_p + v_k m_p)),
+ *   - its adjoint Phi* (Sect. 2.2, Eq. adjoint-phi):
+ *       eta[i,j] = Re sum_k h_k / n_ij * exp(+j 2 pi (u_k l_i + v_k m_j)),
+ *   - the dual certificate mu = Phi*(V - Phi x) / lambda (Sect. 4.2,
+ *     Eq. dual_certif),
+ *   - the LASSO solve of Eq. lasso by the Polyatomic Frank-Wolfe algorithm
+ *     (Sect. 5.1, Alg. 2) with an APGD restricted step,
+ * for coplanar arrays (w = 0, the coplanar remark of Sect. 2.1).
+ *
+ * Conventions shared by every entry point
+ *   Geometry   (u, v) in wavelengths (Sect. 2.1; metres are converted with the
+ *              frequency).  Pixel step dl = fov / npix; l_i = (i - npix/2) dl,
+ *              m_j = (j - npix/2) dl, so pixel (npix/2, npix/2) is the phase
+ *              centre; n_ij = sqrt(1 - l_i^2 - m_j^2).
+ *   Images     row-major float [npix][npix]; flat index p = i*npix + j with i
+ *              the l (u) axis and j the m (v) axis.
+ *   Vis.       interleaved complex (re, im) in the CALLER's order, one
+ *              Hermitian half; float pairs (complex64) for FP32 plans, double
+ *              pairs (complex128) for the FP64 entry points.
+ *   Memory     every buffer argument marked "dev" is device memory on the
+ *              plan's GPU; "host" is ordinary host memory.  The caller owns all
+ *              input and output buffers; the library never frees them.  The
+ *              plan owns its workspace (allocated once in pc_plan_create, size
+ *              reported by pc_plan_footprint).
+ *   Streams    `stream` is a hipStream_t passed as void* (NULL = the null
+ *              stream).  Calls are asynchronous on it, except that any host
+ *              scalar output (max_abs, argmax, solve results) synchronises the
+ *              stream before returning.  A plan must not be used from two host
+ *              threads at once.
+ *   Errors     every function returns a pc_status.  Argument errors are
+ *              detected on the host before any device work; no C++ exception
+ *              crosses the ABI.  pc_last_error() returns a thread-local
+ *              message describing the last failure on the calling thread.
+ */
+#ifndef POLYCLEAN_H
+#define POLYCLEAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Symbols are exported from the shared library; nothing else is. */
+#if defined(PC_BUILD)
+#define PC_API __attribute__((visibility("default")))
+#else
+#define PC_API
+#endif
+
+typedef enum {
+  PC_OK = 0,
+  PC_WARN_NOT_CONVERGED = 1, /* solve hit max_iter; the result is filled in */
+  PC_ERR_INVALID_ARG = -1,   /* a NULL pointer, a bad size or a bad value   */
+  PC_ERR_OUT_OF_MEMORY = -2, /* device allocation failed                    */
+  PC_ERR_DEVICE = -3,        /* a HIP runtime call or kernel launch failed  */
+  PC_ERR_CAPACITY = -4,      /* an output array is too small (see result)   */
+  PC_ERR_UNSUPPORTED = -5    /* a valid request this build does not handle  */
+} pc_status;
+
+enum { PC_UV_WAVELENGTHS = 0, PC_UV_METRES = 1 };
+enum { PC_PREC_FP32 = 0, PC_PREC_FP64 = 1 };
+
+typedef struct pc_plan pc_plan;
+
+/* Imaging geometry (Sect. 2.1-2.2).  All pointers are host memory and are
+ * only read during pc_plan_create / pc_plan_footprint. */
+typedef struct {
+  int64_t nvis;          /* L > 0: number of visibilities                     */
+  const double* u;       /* [nvis] baseline u (units below)                   */
+  const double* v;       /* [nvis] baseline v                                 */
+  const double* w;       /* [nvis] or NULL; must be all zero (coplanar)       */
+  int32_t uv_units;      /* PC_UV_WAVELENGTHS or PC_UV_METRES                 */
+  double freq_hz;        /* observing frequency; used only for PC_UV_METRES   */
+  int32_t npix;          /* n: image side, even, 16 <= n <= 8192              */
+  double fov_rad;        /* field of view (side) in radians, > 0              */
+  double nufft_eps;      /* requested gridding accuracy; <= 0 selects 1e-5    */
+  double upsamp;         /* fine-grid upsampling sigma; <= 0 selects 2; only 2 */
+  int32_t precision;     /* PC_PREC_FP32, or PC_PREC_FP64 for the FP64 twin   */
+} pc_geometry;
+
+/* Read-only facts about a plan (for reporting and byte models). */
+typedef struct {
+  int64_t nvis;
+  int32_t npix;
+  int32_t fine;          /* M = sigma * n, fine-grid side                     */
+  int32_t kernel_width;  /* w, exponential-of-semicircle kernel support       */
+  double kernel_beta;    /* beta of phi(z) = exp(beta (sqrt(1 - z^2) - 1))     */
+  int32_t band_u0, band_nu; /* occupied fine-grid band along u (cells)        */
+  int32_t band_v0, band_nv; /* occupied fine-grid band along v                */
+  int32_t wraps;         /* 1 if the band is the whole (periodic) grid        */
+  int32_t tile;          /* spreading tile side in cells                      */
+  int64_t n_tiles;       /* tiles in the band                                 */
+  int64_t n_chunks;      /* spreading work items                              */
+  int64_t n_partials;    /* partial tiles folded for split hot tiles          */
+  size_t footprint;      /* device bytes owned by the plan                    */
+  int32_t precision;
+} pc_plan_info;
+
+/* Device bytes pc_plan_create would allocate for this geometry (host-only
+ * computation, used for admission control).  It needs the uv coordinates
+ * because the occupied band and the tile work list depend on them. */
+PC_API pc_status pc_plan_footprint(const pc_geometry* geom, size_t* bytes);
+
+/* Build a plan on the current HIP device: validates the geometry, computes
+ * the per-visibility phases (FP64), the fine-grid cells and offsets, the tile
+ * sort and work list, the kernel correction and FFT twiddle tables, and
+ * uploads them.  `stream` orders the uploads.  On success *out owns all of it.
+ * Errors: PC_ERR_INVALID_ARG (NULL, nvis <= 0, odd or out-of-range npix,
+ * fov <= 0, non-finite uv, a nonzero w, a field reaching l^2 + m^2 >= 1),
+ * PC_ERR_UNSUPPORTED (upsamp != 2), PC_ERR_OUT_OF_MEMORY, PC_ERR_DEVICE. */
+PC_API pc_status pc_plan_create(const pc_geometry* geom, void* stream, pc_plan** out);
+PC_API void pc_plan_destroy(pc_plan* plan);
+PC_API pc_status pc_plan_get_info(const pc_plan* plan, pc_plan_info* info);
+
+/* Per-kernel instrumentation.  While enabled, every kernel the plan launches
+ * (operators and solver) is bracketed by HIP events on its stream, and
+ * launches, device milliseconds, algorithmic bytes (the minimum data each
+ * launch must move) and work units (visibility-atom pairs for the direct
+ * DFTs, visibilities for gridding, FFT points for the passes) are summed per
+ * kernel name.  Enabling or disabling resets the sums.  Reading a statistic
+ * synchronises the device. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double ms;
+  double bytes;
+  double work;
+} pc_kernel_stat;
+PC_API pc_status pc_plan_profile(pc_plan* plan, int32_t enable);
+PC_API int32_t pc_plan_kernel_stat_count(pc_plan* plan);
+PC_API pc_status pc_plan_kernel_stat(pc_plan* plan, int32_t index, pc_kernel_stat* out);
+
+/* Thread-local description of the last failure (never NULL). */
+PC_API const char* pc_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Operators (FP32 plans)
+ * ------------------------------------------------------------------------- */
+
+/* Adjoint Phi* (Eq. adjoint-phi): the full-grid image of `vis`.
+ * vis     dev complex64 [nvis], caller order.
+ * image   dev float [npix*npix], written entirely.
+ * max_abs host double or NULL: max |image|.
+ * argmax  host int64 or NULL: lowest flat index attaining max |image|.
+ * Method: exponential-of-semicircle gridding on a 2x fine grid, a pruned 2-D
+ * inverse FFT and apodisation plus 1/n correction (a type-1 non-uniform FFT,
+ * Sect. 5.2).  Relative L2 error against the exact sum ~ nufft_eps. */
+PC_API pc_status pc_adjoint_grid(pc_plan* plan, const void* vis, float* image,
+                          double* max_abs, int64_t* argmax, void* stream);
+
+/* Forward Phi (Eq. phi-discrete) of a sparse image by direct summation.
+ * pix     dev int32 [natoms], flat pixel indices in [0, npix^2).
+ * weight  dev float [natoms], pixel values (Jy/pixel).
+ * vis_out dev complex64 [nvis], caller order, overwritten.
+ * natoms == 0 writes zeros.  Phases are formed and range-reduced in FP64,
+ * sin/cos and accumulation are FP32. */
+PC_API pc_status pc_forward_sparse(pc_plan* plan, int64_t natoms, const int32_t* pix,
+                            const float* weight, void* vis_out, void* stream);
+
+/* Forward Phi of a dense image by interpolation (a type-2 non-uniform FFT,
+ * Sect. 5.2): apodisation pre-correction, zero-padded 2-D FFT, gridding-kernel
+ * interpolation.  image dev float [npix*npix]; vis_out as above. */
+PC_API pc_status pc_forward_grid(pc_plan* plan, const float* image, void* vis_out, void* stream);
+
+/* Restricted adjoint Phi_S* (Eq. adjoint-phi at the pixels of S only), by
+ * direct summation: out[p] = Re sum_k vis_k exp(+j2pi(u_k l_p + v_k m_p)) / n_p.
+ * vis dev complex64 [nvis] caller order; pix dev int32 [natoms];
+ * out dev double [natoms]. */
+PC_API pc_status pc_adjoint_sparse(pc_plan* plan, const void* vis, int64_t natoms,
+                            const int32_t* pix, double* out, void* stream);
+
+/* Dual certificate mu = Phi*(V - Phi x) / lambda (Eq. dual_certif) of the
+ * sparse image x = (pix, weight).  vis dev complex64 [nvis] caller order;
+ * cert dev float [npix*npix]; lambda > 0; max_abs/argmax as for
+ * pc_adjoint_grid (of mu). */
+PC_API pc_status pc_dual_certificate(pc_plan* plan, const void* vis, int64_t natoms,
+                              const int32_t* pix, const float* weight, double lambda,
+                              float* cert, double* max_abs, int64_t* argmax,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
+ * FP64 twin (plans created with precision = PC_PREC_FP64): the same
+ * algorithms entirely in double, for per-stage error reports.
+ * vis complex128, images double.  PC_ERR_UNSUPPORTED for fine grids larger
+ * than 8192 (the double row no longer fits in one workgroup's LDS).
+ * ------------------------------------------------------------------------- */
+PC_API pc_status pc_adjoint_grid_f64(pc_plan* plan, const void* vis, double* image,
+                              double* max_abs, int64_t* argmax, void* stream);
+PC_API pc_status pc_forward_sparse_f64(pc_plan* plan, int64_t natoms, const int32_t* pix,
+                                const double* weight, void* vis_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * PolyCLEAN solve (Alg. 2)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double lambda;          /* > 0: absolute lambda; else alpha * lambda_max    */
+  double alpha;           /* lambda = alpha * ||Phi* V||_inf (Eqs. lmax, lambda) */
+  double delta;           /* PFW quality in (0, 1] (Alg. 2)                   */
+  int32_t max_iter;       /* FW iterations cap (>= 1)                         */
+  double rel_obj_tol;     /* stop on relative objective improvement; <= 0 off */
+  double rel_gap_tol;     /* stop on relative duality gap; <= 0 off           */
+  double inner_tol0;      /* APGD stops when the restricted problem's relative */
+  double inner_tol_min;   /*   duality gap <= max(inner_tol_min, inner_tol0 g), */
+                          /*   g = the full problem's relative gap at x_k     */
+  int32_t inner_max_iter; /* APGD iteration cap per FW iteration              */
+  int32_t positivity;     /* must be 0 (positivity: PC_ERR_UNSUPPORTED)       */
+  int32_t want_certificate; /* 1: write mu to result->cert                    */
+  int32_t log_every;      /* > 0: print an iteration log line every n iters   */
+} pc_solve_params;
+
+typedef struct {
+  int64_t capacity;       /* in: length of pix/weight                         */
+  int32_t* pix;           /* in: host int32 [capacity]; out: active atoms     */
+  double* weight;         /* in: host double [capacity]; out: their weights   */
+  float* cert;            /* in: dev float [npix^2] or NULL                   */
+  int64_t natoms;         /* out: atoms in the solution (required if CAPACITY) */
+  double objective;       /* out: 1/2 ||V - Phi x||^2 + lambda ||x||_1         */
+  double rel_gap;         /* out: relative duality gap at the returned x      */
+  double lambda;          /* out: lambda used                                 */
+  double lambda_max;      /* out: ||Phi* V||_inf                              */
+  double cert_max;        /* out: ||mu||_inf                                  */
+  int64_t cert_argmax;    /* out: lowest flat index attaining it              */
+  int32_t iters;          /* out: FW iterations run                           */
+  int32_t inner_iters;    /* out: total APGD iterations                       */
+  int32_t converged;      /* out: 1 if a tolerance test stopped the solve     */
+  double seconds;         /* out: wall time of the solve                      */
+  double adjoint_seconds; /* out: device time in the adjoint operator         */
+  int32_t adjoint_calls;  /* out: number of adjoint applications              */
+} pc_solve_result;
+
+/* Fill params with the defaults: alpha 0.01, delta 0.99, max_iter 50,
+ * tolerances off, inner_tol0 0.1, inner_tol_min 1e-8, inner_max_iter 2000. */
+PC_API void pc_solve_params_default(pc_solve_params* params);
+
+/* Solve the LASSO for the visibilities `vis` (dev complex64 [nvis], caller
+ * order).  Returns PC_OK when a tolerance stopped the solve, or
+ * PC_WARN_NOT_CONVERGED when max_iter did (result complete in both cases),
+ * PC_ERR_CAPACITY if result->capacity < natoms (result->natoms then holds the
+ * required size and the other outputs are filled).  Synchronous. */
+PC_API pc_status pc_polyclean_solve(pc_plan* plan, const void* vis, const pc_solve_params* params,
+                             pc_solve_result* result, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Step-wise solve, for schedulers that interleave several jobs: the same
+ * algorithm as pc_polyclean_solve, one Frank-Wolfe iteration per
+ * pc_solver_step.  The solver keeps its job's state (sorted visibilities,
+ * residual, active set, weights, dirty-residual image) resident in device
+ * memory until pc_solver_destroy.  `stream` (given at creation) orders all of
+ * the job's work; different jobs may use different streams.
+ * ------------------------------------------------------------------------- */
+typedef struct pc_solver pc_solver;
+
+/* Validates like pc_polyclean_solve and computes the dirty image,
+ * lambda_max and lambda.  vis is read only during this call. */
+PC_API pc_status pc_solver_create(pc_plan* plan, const void* vis, const pc_solve_params* params,
+                                  void* stream, pc_solver** out);
+/* One Frank-Wolfe iteration; *done (host, nullable) becomes 1 once a stop
+ * rule has fired (further steps do nothing). */
+PC_API pc_status pc_solver_step(pc_solver* solver, int32_t* done);
+/* Current iterate as a result (same semantics as pc_polyclean_solve). */
+PC_API pc_status pc_solver_result(pc_solver* solver, pc_solve_result* result);
+PC_API void pc_solver_destroy(pc_solver* solver);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYCLEAN_H */

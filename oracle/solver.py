@@ -20,8 +20,11 @@ Paper passages followed:
 
 Readings of points the paper leaves open (shared with the GPU path):
   * delta is a parameter (its value is never printed);
-  * inner stop: ||x_{t+1} - x_t|| <= tau_k ||x_{t+1}||, tau_k =
-    max(tau_min, tau_0 / (k + 1)), plus an iteration cap;
+  * inner accuracy: the restricted solve stops when the relative duality
+    gap of the restricted problem is <= tau_k = max(tau_min, tau_0 g_k),
+    with g_k the relative duality gap of the full problem at the current
+    iterate x_k (so the accuracy rises as the outer iteration converges),
+    plus an iteration cap;
   * warm start: the previous weights, new atoms start at zero;
   * step size 1 / L_ip with L_ip the largest eigenvalue of the restricted
     normal matrix (computed exactly here);
@@ -119,14 +122,29 @@ class GramCache:
         return self.G[np.ix_(idx, idx)]
 
 
-def fista_restricted(G: np.ndarray, b: np.ndarray, lam: float, x0: np.ndarray,
+def restricted_gap(G: np.ndarray, b: np.ndarray, vv: float, lam: float, y: np.ndarray):
+    """(P_S(y), gap) of the LASSO restricted to S at y, from the normal
+    equations: ||V - Phi_S y||^2 = vv - 2 b.y + y.G.y, Re<V, r> = vv - b.y,
+    Phi_S^* r = b - G y (vv = ||V||^2), with the rescaled-residual dual point."""
+    gy = b - G @ y
+    r2 = vv - 2.0 * float(b @ y) + float(y @ G @ y)
+    vr = vv - float(b @ y)
+    p = 0.5 * r2 + lam * float(np.sum(np.abs(y)))
+    c = float(np.max(np.abs(gy))) if gy.size else 0.0
+    s = 1.0 if c <= lam else lam / c
+    return p, p - (s * vr - 0.5 * s * s * r2), gy
+
+
+def fista_restricted(G: np.ndarray, b: np.ndarray, vv: float, lam: float, x0: np.ndarray,
                      tol: float, max_iter: int, lip: Optional[float] = None):
     """argmin_x 1/2 x^T G x - b^T x + lam ||x||_1 by FISTA (Beck & Teboulle).
 
-    Gradient step 1/L with L the largest eigenvalue of G, soft-threshold at
-    lam/L, momentum t+ = (1 + sqrt(1 + 4 t^2))/2.  Stops when
-    ||x+ - x|| <= tol ||x+|| or after max_iter iterations.
-    Returns (x, iterations).
+    Each step evaluates the gradient at the extrapolated point y, takes the
+    proximal step x+ = soft(y + (b - G y)/L, lam/L) with L the largest
+    eigenvalue of G, and updates the momentum t+ = (1 + sqrt(1 + 4 t^2))/2,
+    y+ = x+ + ((t - 1)/t+)(x+ - x).  It stops, returning x+, when the relative
+    duality gap of the restricted problem at y is <= tol (x+ is then at least
+    as good as y) or after max_iter steps.  Returns (x, steps).
     """
     if lip is None:
         lip = float(np.linalg.eigvalsh(G)[-1]) if G.size else 1.0
@@ -135,15 +153,13 @@ def fista_restricted(G: np.ndarray, b: np.ndarray, lam: float, x0: np.ndarray,
     t = 1.0
     it = 0
     for it in range(1, max_iter + 1):
-        z = y - (G @ y - b) / lip
-        xn = soft(z, lam / lip)
+        p, gap, gy = restricted_gap(G, b, vv, lam, y)
+        xn = soft(y + gy / lip, lam / lip)
+        if gap <= tol * p:
+            return xn, it
         tn = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
         y = xn + ((t - 1.0) / tn) * (xn - x)
-        diff = float(np.linalg.norm(xn - x))
-        nrm = float(np.linalg.norm(xn))
         x, t = xn, tn
-        if diff <= tol * nrm:
-            break
     return x, it
 
 
@@ -181,7 +197,7 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
               lam: Optional[float] = None, delta: float = 0.99,
               max_iter: int = 50, rel_obj_tol: float = 0.0,
               rel_gap_tol: float = 0.0, inner_tol0: float = 1e-1,
-              inner_tol_min: float = 1e-6, inner_max_iter: int = 500,
+              inner_tol_min: float = 1e-8, inner_max_iter: int = 2000,
               dirty: Optional[np.ndarray] = None) -> SolveResult:
     """Polyatomic Frank-Wolfe for the point-source LASSO (Alg. 2).
 
@@ -202,10 +218,12 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
     S = np.zeros(0, np.int64)
     x = np.zeros(0)
     eta = dirty.copy()
-    p_prev = 0.5 * float(np.vdot(vis, vis).real)    # P(x_0 = 0)
+    vv = float(np.vdot(vis, vis).real)
+    p_prev = 0.5 * vv                               # P(x_0 = 0)
     log: List[IterLog] = []
     fit = np.zeros_like(vis)
-    rel_gap = np.inf
+    gap0, _ = dual_gap(vis, vis, lmax, p_prev, lam)
+    rel_gap = gap0 / p_prev if p_prev > 0 else 0.0
     converged = False
     k = 0
     for k in range(max_iter):
@@ -218,8 +236,8 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
             xw[np.searchsorted(S_new, S)] = x
         gram.ensure(S_new)
         G = gram.sub(S_new)
-        tol = max(inner_tol_min, inner_tol0 / (k + 1))
-        x, nin = fista_restricted(G, b_all[S_new], lam, xw, tol, inner_max_iter)
+        tol = max(inner_tol_min, inner_tol0 * rel_gap)
+        x, nin = fista_restricted(G, b_all[S_new], vv, lam, xw, tol, inner_max_iter)
         keep = x != 0.0
         S, x = S_new[keep], x[keep]
         fit = forward(uv, npix, fov_rad, S, x)

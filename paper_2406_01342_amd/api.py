@@ -1,0 +1,272 @@
+"""Python binding of libpolyclean.so: the C ABI's functions under the same
+names, taking torch device tensors for device buffers and numpy arrays for
+host inputs.  Argument marshalling only; every operator step runs in the HIP
+library.  Device buffers come from torch (its caching allocator) and calls
+are issued on torch's current stream unless a stream is passed.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (PC_PREC_FP32, PC_PREC_FP64, PC_UV_METRES, PC_UV_WAVELENGTHS,  # noqa: F401
+                   PcGeometry, PcKernelStat, PcPlanInfo, PcSolveParams, PcSolveResult,
+                   PolycleanError, check)
+
+LIB = _lib.load()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev(t: torch.Tensor, dtype, numel: int, name: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Plan:
+    """Owns a pc_plan handle (destroyed with the object)."""
+
+    def __init__(self, handle: C.c_void_p, device: torch.device):
+        self._h = handle
+        self.device = device
+        info = PcPlanInfo()
+        check(LIB.pc_plan_get_info(self._h, C.byref(info)), "pc_plan_get_info")
+        self.info = {k: getattr(info, k) for k, _ in PcPlanInfo._fields_}
+        self.nvis = int(info.nvis)
+        self.npix = int(info.npix)
+        self.precision = int(info.precision)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            LIB.pc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _geometry(uv, npix, fov_rad, w, uv_units, freq_hz, nufft_eps, upsamp, precision):
+    uv = np.ascontiguousarray(np.asarray(uv, dtype=np.float64))
+    if uv.ndim != 2 or uv.shape[1] != 2:
+        raise ValueError("uv must have shape (L, 2)")
+    u = np.ascontiguousarray(uv[:, 0])
+    v = np.ascontiguousarray(uv[:, 1])
+    keep = [u, v]
+    g = PcGeometry()
+    g.nvis = uv.shape[0]
+    g.u = u.ctypes.data_as(C.POINTER(C.c_double))
+    g.v = v.ctypes.data_as(C.POINTER(C.c_double))
+    if w is not None:
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+        keep.append(w)
+        g.w = w.ctypes.data_as(C.POINTER(C.c_double))
+    g.uv_units = int(uv_units)
+    g.freq_hz = float(freq_hz)
+    g.npix = int(npix)
+    g.fov_rad = float(fov_rad)
+    g.nufft_eps = float(nufft_eps)
+    g.upsamp = float(upsamp)
+    g.precision = int(precision)
+    return g, keep
+
+
+def pc_plan_footprint(uv, npix: int, fov_rad: float, *, w=None, uv_units=PC_UV_WAVELENGTHS,
+                      freq_hz: float = 0.0, nufft_eps: float = 1e-5, upsamp: float = 2.0,
+                      precision: int = PC_PREC_FP32) -> int:
+    g, keep = _geometry(uv, npix, fov_rad, w, uv_units, freq_hz, nufft_eps, upsamp, precision)
+    out = C.c_size_t(0)
+    check(LIB.pc_plan_footprint(C.byref(g), C.byref(out)), "pc_plan_footprint")
+    return int(out.value)
+
+
+def pc_plan_create(uv, npix: int, fov_rad: float, *, w=None, uv_units=PC_UV_WAVELENGTHS,
+                   freq_hz: float = 0.0, nufft_eps: float = 1e-5, upsamp: float = 2.0,
+                   precision: int = PC_PREC_FP32, stream=None) -> Plan:
+    g, keep = _geometry(uv, npix, fov_rad, w, uv_units, freq_hz, nufft_eps, upsamp, precision)
+    h = C.c_void_p()
+    check(LIB.pc_plan_create(C.byref(g), C.c_void_p(_stream(stream)), C.byref(h)),
+          "pc_plan_create")
+    return Plan(h, torch.device("cuda", torch.cuda.current_device()))
+
+
+def _new(plan: Plan, shape, dtype):
+    return torch.empty(shape, dtype=dtype, device=plan.device)
+
+
+def pc_adjoint_grid(plan: Plan, vis: torch.Tensor, image: Optional[torch.Tensor] = None,
+                    want_max: bool = True, stream=None):
+    """Phi* vis -> (image [n, n] float32, max|image| or None, argmax or None)."""
+    n = plan.npix
+    if image is None:
+        image = _new(plan, (n, n), torch.float32)
+    mx, am = C.c_double(0), C.c_int64(-1)
+    check(LIB.pc_adjoint_grid(plan.handle, C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")),
+                              C.c_void_p(_dev(image, torch.float32, n * n, "image")),
+                              C.byref(mx) if want_max else None, C.byref(am) if want_max else None,
+                              C.c_void_p(_stream(stream))), "pc_adjoint_grid")
+    return image, (mx.value if want_max else None), (am.value if want_max else None)
+
+
+def pc_adjoint_grid_f64(plan: Plan, vis: torch.Tensor, image: Optional[torch.Tensor] = None,
+                        want_max: bool = True, stream=None):
+    n = plan.npix
+    if image is None:
+        image = _new(plan, (n, n), torch.float64)
+    mx, am = C.c_double(0), C.c_int64(-1)
+    check(LIB.pc_adjoint_grid_f64(plan.handle,
+                                  C.c_void_p(_dev(vis, torch.complex128, plan.nvis, "vis")),
+                                  C.c_void_p(_dev(image, torch.float64, n * n, "image")),
+                                  C.byref(mx) if want_max else None,
+                                  C.byref(am) if want_max else None,
+                                  C.c_void_p(_stream(stream))), "pc_adjoint_grid_f64")
+    return image, (mx.value if want_max else None), (am.value if want_max else None)
+
+
+def pc_forward_sparse(plan: Plan, pix: torch.Tensor, weight: torch.Tensor,
+                      out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    na = int(pix.numel())
+    if out is None:
+        out = _new(plan, (plan.nvis,), torch.complex64)
+    check(LIB.pc_forward_sparse(plan.handle, na, C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+                                C.c_void_p(_dev(weight, torch.float32, na, "weight")),
+                                C.c_void_p(_dev(out, torch.complex64, plan.nvis, "out")),
+                                C.c_void_p(_stream(stream))), "pc_forward_sparse")
+    return out
+
+
+def pc_forward_sparse_f64(plan: Plan, pix: torch.Tensor, weight: torch.Tensor,
+                          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    na = int(pix.numel())
+    if out is None:
+        out = _new(plan, (plan.nvis,), torch.complex128)
+    check(LIB.pc_forward_sparse_f64(plan.handle, na,
+                                    C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+                                    C.c_void_p(_dev(weight, torch.float64, na, "weight")),
+                                    C.c_void_p(_dev(out, torch.complex128, plan.nvis, "out")),
+                                    C.c_void_p(_stream(stream))), "pc_forward_sparse_f64")
+    return out
+
+
+def pc_forward_grid(plan: Plan, image: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+    n = plan.npix
+    if out is None:
+        out = _new(plan, (plan.nvis,), torch.complex64)
+    check(LIB.pc_forward_grid(plan.handle, C.c_void_p(_dev(image, torch.float32, n * n, "image")),
+                              C.c_void_p(_dev(out, torch.complex64, plan.nvis, "out")),
+                              C.c_void_p(_stream(stream))), "pc_forward_grid")
+    return out
+
+
+def pc_adjoint_sparse(plan: Plan, vis: torch.Tensor, pix: torch.Tensor,
+                      out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    na = int(pix.numel())
+    if out is None:
+        out = _new(plan, (na,), torch.float64)
+    check(LIB.pc_adjoint_sparse(plan.handle,
+                                C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")), na,
+                                C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+                                C.c_void_p(_dev(out, torch.float64, na, "out")),
+                                C.c_void_p(_stream(stream))), "pc_adjoint_sparse")
+    return out
+
+
+def pc_dual_certificate(plan: Plan, vis: torch.Tensor, pix: torch.Tensor, weight: torch.Tensor,
+                        lam: float, cert: Optional[torch.Tensor] = None, want_max: bool = True,
+                        stream=None):
+    n, na = plan.npix, int(pix.numel())
+    if cert is None:
+        cert = _new(plan, (n, n), torch.float32)
+    mx, am = C.c_double(0), C.c_int64(-1)
+    check(LIB.pc_dual_certificate(plan.handle,
+                                  C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")), na,
+                                  C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+                                  C.c_void_p(_dev(weight, torch.float32, na, "weight")),
+                                  float(lam), C.c_void_p(_dev(cert, torch.float32, n * n, "cert")),
+                                  C.byref(mx) if want_max else None,
+                                  C.byref(am) if want_max else None,
+                                  C.c_void_p(_stream(stream))), "pc_dual_certificate")
+    return cert, (mx.value if want_max else None), (am.value if want_max else None)
+
+
+def solve_params(**kw) -> PcSolveParams:
+    p = PcSolveParams()
+    LIB.pc_solve_params_default(C.byref(p))
+    for k, v in kw.items():
+        key = "lambda_" if k in ("lam", "lambda") else k
+        if not hasattr(p, key):
+            raise KeyError(k)
+        setattr(p, key, v)
+    return p
+
+
+def pc_polyclean_solve(plan: Plan, vis: torch.Tensor, params: Optional[PcSolveParams] = None,
+                       capacity: int = 65536, cert: Optional[torch.Tensor] = None, stream=None,
+                       **kw):
+    """Run Alg. 2; returns a dict with the atoms, weights and scalars."""
+    if params is None:
+        params = solve_params(**kw)
+    elif kw:
+        raise ValueError("pass either params or keyword parameters")
+    n = plan.npix
+    pix = np.zeros(capacity, dtype=np.int32)
+    wgt = np.zeros(capacity, dtype=np.float64)
+    res = PcSolveResult()
+    res.capacity = capacity
+    res.pix = pix.ctypes.data_as(C.POINTER(C.c_int32))
+    res.weight = wgt.ctypes.data_as(C.POINTER(C.c_double))
+    res.cert = C.c_void_p(_dev(cert, torch.float32, n * n, "cert")) if cert is not None else None
+    st = LIB.pc_polyclean_solve(plan.handle, C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")),
+                                C.byref(params), C.byref(res), C.c_void_p(_stream(stream)))
+    check(st, "pc_polyclean_solve")
+    out = {k: getattr(res, k) for k, _ in PcSolveResult._fields_
+           if k not in ("pix", "weight", "cert", "capacity")}
+    out["lambda"] = out.pop("lambda_")
+    out["status"] = st
+    na = int(res.natoms)
+    out["pix"] = pix[:na].astype(np.int64)
+    out["weight"] = wgt[:na].copy()
+    return out
+
+
+def pc_plan_profile(plan: Plan, enable: bool = True) -> None:
+    """Enable (and reset) or disable per-kernel event timing on the plan."""
+    check(LIB.pc_plan_profile(plan.handle, 1 if enable else 0), "pc_plan_profile")
+
+
+def pc_plan_kernel_stats(plan: Plan):
+    """Per-kernel sums since profiling was enabled: list of dicts with name,
+    launches, ms, bytes (algorithmic) and work units."""
+    out = []
+    for i in range(LIB.pc_plan_kernel_stat_count(plan.handle)):
+        st = PcKernelStat()
+        check(LIB.pc_plan_kernel_stat(plan.handle, i, C.byref(st)), "pc_plan_kernel_stat")
+        out.append({"name": st.name.decode(), "launches": int(st.launches), "ms": float(st.ms),
+                    "bytes": float(st.bytes), "work": float(st.work)})
+    return out

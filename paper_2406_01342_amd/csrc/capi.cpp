@@ -1,0 +1,201 @@
+// The extern "C" boundary: argument validation, error capture, dispatch.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+extern "C" pc_status pc_plan_footprint_impl(const pc_geometry* geom, size_t* bytes);
+extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, pc_plan** out);
+
+namespace pc {
+
+static thread_local std::string g_last_error = "no error";
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(pc_status s, const std::string& msg) { throw Error(s, msg); }
+
+template <typename F>
+static pc_status guard(const char* fn, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(std::string(fn) + ": " + e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error(std::string(fn) + ": host allocation failed");
+    return PC_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    set_last_error(std::string(fn) + ": " + e.what());
+    return PC_ERR_DEVICE;
+  } catch (...) {
+    set_last_error(std::string(fn) + ": unknown failure");
+    return PC_ERR_DEVICE;
+  }
+}
+
+static void check_plan(const pc_plan* p, int precision) {
+  PC_REQUIRE(p != nullptr, "plan is NULL");
+  if (p->precision != precision)
+    fail(PC_ERR_INVALID_ARG, precision == PC_PREC_FP64
+                                 ? "this entry point needs a plan created with PC_PREC_FP64"
+                                 : "this entry point needs a plan created with PC_PREC_FP32");
+}
+
+static void check_atoms(const pc_plan* p, int64_t natoms, const void* pix, const void* weight,
+                        bool need_weight) {
+  PC_REQUIRE(natoms >= 0, "natoms must be >= 0");
+  PC_REQUIRE(natoms <= (int64_t)p->g.n * p->g.n, "natoms exceeds npix^2");
+  if (natoms > 0) {
+    PC_REQUIRE(pix != nullptr, "pix is NULL");
+    if (need_weight) PC_REQUIRE(weight != nullptr, "weight is NULL");
+  }
+}
+
+static void set_device(const pc_plan* p) { PC_HIP(hipSetDevice(p->device)); }
+
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" {
+
+const char* pc_last_error(void) { return g_last_error.c_str(); }
+
+pc_status pc_plan_footprint(const pc_geometry* geom, size_t* bytes) {
+  return guard("pc_plan_footprint", [&] { return pc_plan_footprint_impl(geom, bytes); });
+}
+
+pc_status pc_plan_create(const pc_geometry* geom, void* stream, pc_plan** out) {
+  return guard("pc_plan_create", [&] { return pc_plan_create_impl(geom, stream, out); });
+}
+
+void pc_plan_destroy(pc_plan* plan) {
+  if (!plan) return;
+  (void)hipSetDevice(plan->device);
+  (void)hipDeviceSynchronize();
+  plan_release(plan);
+  delete plan;
+}
+
+pc_status pc_plan_get_info(const pc_plan* p, pc_plan_info* info) {
+  return guard("pc_plan_get_info", [&] {
+    PC_REQUIRE(p != nullptr && info != nullptr, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->nvis = p->L;
+    info->npix = p->g.n;
+    info->fine = p->g.M;
+    info->kernel_width = p->g.W;
+    info->kernel_beta = p->g.beta64;
+    info->band_u0 = p->g.u0;
+    info->band_nu = p->g.nu;
+    info->band_v0 = p->g.v0;
+    info->band_nv = p->g.nv;
+    info->wraps = p->g.wrap;
+    info->tile = kTile;
+    info->n_tiles = (int64_t)p->g.ntu * p->g.ntv;
+    info->n_chunks = p->n_chunks;
+    info->n_partials = p->n_partials;
+    info->footprint = p->footprint;
+    info->precision = p->precision;
+    return PC_OK;
+  });
+}
+
+pc_status pc_adjoint_grid(pc_plan* p, const void* vis, float* image, double* max_abs,
+                          int64_t* argmax, void* stream) {
+  return guard("pc_adjoint_grid", [&] {
+    check_plan(p, PC_PREC_FP32);
+    PC_REQUIRE(vis != nullptr && image != nullptr, "vis and image must not be NULL");
+    set_device(p);
+    hipStream_t s = (hipStream_t)stream;
+    adjoint_grid<float>(p, (const c32*)vis, false, image, 1.0f, s);
+    if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
+    return PC_OK;
+  });
+}
+
+pc_status pc_adjoint_grid_f64(pc_plan* p, const void* vis, double* image, double* max_abs,
+                              int64_t* argmax, void* stream) {
+  return guard("pc_adjoint_grid_f64", [&] {
+    check_plan(p, PC_PREC_FP64);
+    PC_REQUIRE(vis != nullptr && image != nullptr, "vis and image must not be NULL");
+    if (p->g.M > 8192) fail(PC_ERR_UNSUPPORTED, "FP64 twin supports fine grids up to 8192");
+    set_device(p);
+    hipStream_t s = (hipStream_t)stream;
+    adjoint_grid<double>(p, (const c64*)vis, false, image, 1.0, s);
+    if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
+    return PC_OK;
+  });
+}
+
+pc_status pc_forward_sparse(pc_plan* p, int64_t natoms, const int32_t* pix, const float* weight,
+                            void* vis_out, void* stream) {
+  return guard("pc_forward_sparse", [&] {
+    check_plan(p, PC_PREC_FP32);
+    check_atoms(p, natoms, pix, weight, true);
+    PC_REQUIRE(vis_out != nullptr, "vis_out is NULL");
+    set_device(p);
+    forward_sparse<float>(p, natoms, pix, weight, nullptr, false, (c32*)vis_out, false,
+                          (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
+pc_status pc_forward_sparse_f64(pc_plan* p, int64_t natoms, const int32_t* pix,
+                                const double* weight, void* vis_out, void* stream) {
+  return guard("pc_forward_sparse_f64", [&] {
+    check_plan(p, PC_PREC_FP64);
+    check_atoms(p, natoms, pix, weight, true);
+    PC_REQUIRE(vis_out != nullptr, "vis_out is NULL");
+    set_device(p);
+    forward_sparse<double>(p, natoms, pix, weight, nullptr, false, (c64*)vis_out, false,
+                           (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
+pc_status pc_forward_grid(pc_plan* p, const float* image, void* vis_out, void* stream) {
+  return guard("pc_forward_grid", [&] {
+    check_plan(p, PC_PREC_FP32);
+    PC_REQUIRE(image != nullptr && vis_out != nullptr, "image and vis_out must not be NULL");
+    set_device(p);
+    forward_grid<float>(p, image, (c32*)vis_out, false, (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
+pc_status pc_adjoint_sparse(pc_plan* p, const void* vis, int64_t natoms, const int32_t* pix,
+                            double* out, void* stream) {
+  return guard("pc_adjoint_sparse", [&] {
+    check_plan(p, PC_PREC_FP32);
+    check_atoms(p, natoms, pix, nullptr, false);
+    PC_REQUIRE(vis != nullptr, "vis is NULL");
+    if (natoms > 0) PC_REQUIRE(out != nullptr, "out is NULL");
+    set_device(p);
+    adjoint_sparse<float>(p, (const c32*)vis, false, natoms, pix, out, (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
+pc_status pc_dual_certificate(pc_plan* p, const void* vis, int64_t natoms, const int32_t* pix,
+                              const float* weight, double lambda, float* cert, double* max_abs,
+                              int64_t* argmax, void* stream) {
+  return guard("pc_dual_certificate", [&] {
+    check_plan(p, PC_PREC_FP32);
+    check_atoms(p, natoms, pix, weight, true);
+    PC_REQUIRE(vis != nullptr && cert != nullptr, "vis and cert must not be NULL");
+    PC_REQUIRE(std::isfinite(lambda) && lambda > 0, "lambda must be finite and > 0");
+    set_device(p);
+    hipStream_t s = (hipStream_t)stream;
+    c32* r = (c32*)p->vis_scratch;
+    // residual in plan order: r = V - Phi x
+    forward_sparse<float>(p, natoms, pix, weight, (const c32*)vis, false, r, true, s);
+    adjoint_grid<float>(p, r, true, cert, (float)(1.0 / lambda), s);
+    if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
+    return PC_OK;
+  });
+}
+
+}  // extern "C"

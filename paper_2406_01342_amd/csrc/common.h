@@ -1,0 +1,222 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/polyclean.h"
+
+namespace pc {
+
+// ----------------------------------------------------------------------------
+// Errors: thrown inside the library, converted to pc_status at the ABI.
+// ----------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  pc_status status;
+  Error(pc_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] void fail(pc_status s, const std::string& msg);
+void set_last_error(const std::string& msg);
+
+#define PC_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      ::pc::fail(e_ == hipErrorOutOfMemory ? PC_ERR_OUT_OF_MEMORY : PC_ERR_DEVICE, \
+                 std::string(#call) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+#define PC_LAUNCH_CHECK(name)                                                     \
+  do {                                                                            \
+    hipError_t e_ = hipGetLastError();                                            \
+    if (e_ != hipSuccess)                                                         \
+      ::pc::fail(PC_ERR_DEVICE, std::string("launch ") + name + ": " +            \
+                                    hipGetErrorString(e_));                       \
+  } while (0)
+
+#define PC_REQUIRE(cond, msg)                                                     \
+  do {                                                                            \
+    if (!(cond)) ::pc::fail(PC_ERR_INVALID_ARG, msg);                             \
+  } while (0)
+
+// ----------------------------------------------------------------------------
+// Complex value types (interleaved, matching complex64 / complex128 buffers).
+// ----------------------------------------------------------------------------
+template <typename R>
+struct cpx {
+  R x, y;
+};
+using c32 = cpx<float>;
+using c64 = cpx<double>;
+
+// Spreading tile side in fine-grid cells.  A visibility's footprint (w <= 16
+// cells) therefore touches at most the next tile along each axis.
+constexpr int kTile = 32;
+constexpr int kMaxWidth = 16;
+
+// One spreading work item: an output tile plus the (sub)ranges of sorted
+// visibilities that reach it from the tile itself and from its left, upper
+// and upper-left neighbours.  slot >= 0 means the tile is split across
+// several items and this item writes partial tile `slot`.
+struct SpreadChunk {
+  int32_t tile;
+  int32_t slot;
+  int32_t beg[4];
+  int32_t end[4];
+};
+
+// A split ("hot") tile: its partial tiles occupy slots [first, first+count).
+struct FoldItem {
+  int32_t tile;
+  int32_t first;
+  int32_t count;
+  int32_t pad;
+};
+
+// Device-side geometry of the fine grid band, passed by value to kernels.
+struct GridGeom {
+  int32_t n;       // image side
+  int32_t M;       // fine grid side
+  int32_t W;       // kernel width
+  float beta;      // kernel shape
+  double beta64;
+  int32_t u0, nu;  // band origin / extent along u (cells, multiple of kTile)
+  int32_t v0, nv;  // band along v
+  int32_t ntu, ntv;
+  int32_t wrap;
+  double dl;       // pixel step (direction cosine)
+};
+
+struct DeviceBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// One active atom of a sparse image: pixel offsets from the phase centre
+// (a = i - n/2, b = j - n/2), 1/n(l, m), and the forward weight x / n(l, m).
+template <typename R>
+struct Atom {
+  double a, b;
+  double inv_n;
+  R w;
+  R pad;
+};
+
+// Per-kernel instrumentation (optional): launches bracketed by HIP events on
+// the launch stream, accumulated per kernel name with the algorithmic bytes
+// and work units (visibility-atom pairs, FFT points, ...) of each launch.
+struct KStat {
+  std::string name;
+  int64_t launches = 0;
+  double ms = 0, bytes = 0, work = 0;
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<KStat> stats;
+  struct Pending {
+    int idx;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+}  // namespace pc
+
+// The opaque plan.
+struct pc_plan {
+  int device = 0;
+  int precision = PC_PREC_FP32;
+  int64_t L = 0;
+  pc::GridGeom g{};
+  int64_t n_chunks = 0, n_partials = 0, n_fold = 0;
+  size_t footprint = 0;
+
+  // Per-visibility data in plan (tile-sorted) order.
+  int32_t* perm = nullptr;      // sorted index -> caller index
+  double* AB = nullptr;         // [2L] (u dl, v dl) turns per pixel, FP64
+  uint32_t* cell = nullptr;     // [L] packed first cell (v << 16 | u), absolute
+  void* off = nullptr;          // [2L] float or double: (s_u, s_v) offsets
+  // Spreading work list.
+  pc::SpreadChunk* chunks = nullptr;
+  pc::FoldItem* fold = nullptr;
+  // Fine grid band, pass-A output, split-tile partials.
+  void* grid = nullptr;         // complex [nv][nu]
+  void* H = nullptr;            // complex [nv][n]
+  void* partials = nullptr;     // complex [n_partials][kTile][kTile]
+  // Tables.
+  void* twiddle = nullptr;      // complex [M]: exp(+2 pi i t / M)
+  void* corr = nullptr;         // real [n]: (-1)^a / psi(a), a = i - n/2
+  // Small scratch.
+  unsigned long long* maxkey = nullptr;  // packed (|x| bits, ~index)
+  void* vis_scratch = nullptr;  // complex [L] in plan order (residual etc.)
+  void* atom_scratch = nullptr; // per-atom staging
+  size_t atom_capacity = 0;
+  double* red_scratch = nullptr;  // reduction partials
+  size_t red_capacity = 0;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  pc::Prof prof;
+
+  std::vector<pc::DeviceBuf> owned;
+};
+
+namespace pc {
+
+// profile.cpp
+struct ProfScope {
+  pc_plan* p;
+  hipStream_t s;
+  const char* name;
+  double bytes, work;
+  hipEvent_t a = nullptr;
+  ProfScope(pc_plan* plan, hipStream_t stream, const char* kname, double b, double w);
+  ~ProfScope();
+};
+void prof_flush(pc_plan* p);
+void prof_reset(pc_plan* p);
+void prof_release(pc_plan* p);
+
+// plan.cpp
+void* dalloc(pc_plan* p, size_t bytes);
+void plan_release(pc_plan* p);
+void* ensure_atom_scratch(pc_plan* p, size_t bytes);
+double* ensure_red_scratch(pc_plan* p, size_t count);
+
+// kernels_grid.hip
+template <typename R>
+void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R scale,
+                  hipStream_t s);
+template <typename R>
+void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted,
+                  hipStream_t s);
+void maxkey_reset(pc_plan* p, hipStream_t s);
+void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax);
+
+// kernels_dft.hip
+template <typename R>
+void forward_sparse(pc_plan* p, int64_t natoms, const int32_t* pix, const R* weight,
+                    const cpx<R>* vis_base, bool base_sorted, cpx<R>* out, bool out_sorted,
+                    hipStream_t s);
+template <typename R>
+void adjoint_sparse(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
+                    const int32_t* pix, double* out, hipStream_t s);
+// Variants on a prepared atom table (the solver keeps one per active set).
+template <typename R>
+void prep_atoms_into(pc_plan* p, int64_t natoms, const int32_t* pix, const R* weight,
+                     Atom<R>* atoms, hipStream_t s);
+template <typename R>
+void forward_atoms(pc_plan* p, int64_t natoms, const Atom<R>* atoms, const cpx<R>* vis_base,
+                   bool base_sorted, cpx<R>* out, bool out_sorted, hipStream_t s);
+template <typename R>
+void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
+                   const Atom<R>* atoms, double* partial, double* out, hipStream_t s);
+int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms);
+
+}  // namespace pc

@@ -1,0 +1,135 @@
+// LDS-resident Stockham FFT for batches of power-of-two sequences.
+//
+// Each stage of radix R with current sub-transform length Ns reads input
+// j + r (M/R), applies the twiddle w^(r k), k = j mod Ns, w = exp(s 2 pi i /
+// (Ns R)), does a radix-R DFT in registers and writes output
+// (j / Ns) Ns R + k + r Ns (the autosorting Stockham ordering), so the result
+// is in natural order without a bit-reversal pass.  Stages: one radix-2^(p mod
+// 4) stage first (no twiddles) when p = log2 M is not a multiple of 4, then
+// radix-16 stages.  Twiddles come from a table of exp(+2 pi i t / M), t < M,
+// computed in FP64 on the host and rounded once.
+#pragma once
+
+#include "common.h"
+
+namespace pc {
+
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// exp(SIGN 2 pi i K / N) applied to v, with exact handling of the trivial
+// angles (multiples of pi/2) so that no multiplication by 0/1 is emitted.
+template <typename R, int N, int SIGN>
+__device__ __forceinline__ cpx<R> rot(cpx<R> v, int K) {
+  // cos / sin of 2 pi k / 16, k = 0..4 (first quadrant), exact decimal values
+  const double c16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                         0.38268343236508977173, 0.0};
+  const int k16 = (K * 16 / N) & 15;  // angle in units of 2 pi / 16
+  if (k16 == 0) return v;
+  if (k16 == 4) return SIGN > 0 ? cpx<R>{-v.y, v.x} : cpx<R>{v.y, -v.x};
+  if (k16 == 8) return {-v.x, -v.y};
+  if (k16 == 12) return SIGN > 0 ? cpx<R>{v.y, -v.x} : cpx<R>{-v.y, v.x};
+  const int q = k16 & 3, quad = k16 >> 2;
+  R c = (R)c16[q], s = (R)c16[4 - q];
+  // rotate (c, s) by quad quarter turns
+  for (int t = 0; t < quad; ++t) {
+    R nc = -s, ns = c;
+    c = nc;
+    s = ns;
+  }
+  if (SIGN < 0) s = -s;
+  return {v.x * c - v.y * s, v.x * s + v.y * c};
+}
+
+// In-register DFT of length N (N = 2, 4, 8, 16) with sign SIGN, radix-2 DIT.
+template <typename R, int N, int SIGN>
+__device__ __forceinline__ void dft(cpx<R>* x) {
+  if constexpr (N == 1) {
+    return;
+  } else if constexpr (N == 2) {
+    cpx<R> a = x[0], b = x[1];
+    x[0] = {a.x + b.x, a.y + b.y};
+    x[1] = {a.x - b.x, a.y - b.y};
+  } else {
+    cpx<R> e[N / 2], o[N / 2];
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      e[i] = x[2 * i];
+      o[i] = x[2 * i + 1];
+    }
+    dft<R, N / 2, SIGN>(e);
+    dft<R, N / 2, SIGN>(o);
+#pragma unroll
+    for (int k = 0; k < N / 2; ++k) {
+      cpx<R> t = rot<R, N, SIGN>(o[k], k);
+      x[k] = {e[k].x + t.x, e[k].y + t.y};
+      x[k + N / 2] = {e[k].x - t.x, e[k].y - t.y};
+    }
+  }
+}
+
+constexpr int ilog2(int m) { return m <= 1 ? 0 : 1 + ilog2(m / 2); }
+constexpr int first_radix(int m) { return (ilog2(m) % 4) ? (1 << (ilog2(m) % 4)) : 16; }
+
+template <typename R, int RAD, int M, int NB, int NT, int SIGN, int NS>
+__device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+  constexpr int NBF = M / RAD;
+  constexpr int TOT = NB * NBF;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  cpx<R> y[PER][RAD];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int bi = (int)threadIdx.x + q * NT;
+    if (TOT % NT == 0 || bi < TOT) {
+      const int b = bi / NBF, j = bi - b * NBF;
+      const int k = j & (NS - 1);
+      cpx<R> x[RAD];
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) x[r] = buf[b * M + j + r * NBF];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cpx<R> t = tw[r * k * (M / (NS * RAD))];
+          if (SIGN < 0) t.y = -t.y;
+          x[r] = cmul(x[r], t);
+        }
+      }
+      dft<R, RAD, SIGN>(x);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) y[q][r] = x[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int bi = (int)threadIdx.x + q * NT;
+    if (TOT % NT == 0 || bi < TOT) {
+      const int b = bi / NBF, j = bi - b * NBF;
+      const int k = j & (NS - 1);
+      const int base = b * M + (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[base + r * NS] = y[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int M, int NB, int NT, int SIGN, int NS>
+__device__ __forceinline__ void fft_stages(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+  if constexpr (NS < M) {
+    constexpr int RAD = (NS == 1) ? first_radix(M) : 16;
+    fft_stage<R, RAD, M, NB, NT, SIGN, NS>(buf, tw);
+    fft_stages<R, M, NB, NT, SIGN, NS * RAD>(buf, tw);
+  }
+}
+
+// In-place FFT of NB sequences of length M stored contiguously in LDS.
+// Must be called by all NT threads of the block; ends with a barrier.
+template <typename R, int M, int NB, int NT, int SIGN>
+__device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+  fft_stages<R, M, NB, NT, SIGN, 1>(buf, tw);
+}
+
+}  // namespace pc

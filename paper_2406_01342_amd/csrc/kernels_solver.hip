@@ -1,0 +1,247 @@
+// Small kernels of the Polyatomic Frank-Wolfe solve (Alg. 2): visibility
+// permutation, FP64 residual reductions for the objective and duality gap,
+// candidate selection for the polyatomic exploration, and the single-workgroup
+// FP64 vector updates of the APGD (FISTA) restricted solve and of the power
+// iteration that estimates its step size.
+#include <algorithm>
+
+#include "common.h"
+#include "solver_kernels.h"
+
+namespace pc {
+
+__global__ void gather_kernel(int64_t L, const int32_t* __restrict__ perm,
+                              const c32* __restrict__ in, c32* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < L) out[s] = in[perm[s]];
+}
+
+// Block partials of (sum |r|^2, sum Re(conj(V) r)) in FP64.
+__global__ __launch_bounds__(256) void resid_partial_kernel(int64_t L, const c32* __restrict__ r,
+                                                            const c32* __restrict__ V,
+                                                            double* __restrict__ partial) {
+  double a = 0, b = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < L;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const c32 x = r[k], v = V[k];
+    a += (double)x.x * x.x + (double)x.y * x.y;
+    b += (double)v.x * x.x + (double)v.y * x.y;
+  }
+  __shared__ double sa[256], sb[256];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sa[0];
+    partial[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+__global__ void resid_final_kernel(int nblocks, const double* __restrict__ partial,
+                                   double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double a = 0, b = 0;
+    for (int i = 0; i < nblocks; ++i) {
+      a += partial[2 * i];
+      b += partial[2 * i + 1];
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+// Candidates {j : |eta_j| >= tau} (Alg. 2, step 1.a); order is fixed on the
+// host by sorting.
+__global__ void select_kernel(int64_t N, const float* __restrict__ eta, float tau,
+                              unsigned int* __restrict__ count, int32_t* __restrict__ out,
+                              int64_t cap) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  if (fabsf(eta[j]) >= tau) {
+    const unsigned int q = atomicAdd(count, 1u);
+    if ((int64_t)q < cap) out[q] = (int32_t)j;
+  }
+}
+
+__global__ void zero_u32_kernel(unsigned int* p) { *p = 0u; }
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < NT / 64; ++w) t = fmax(t, sh[w]);
+  __syncthreads();
+  return t;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < NT / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// One FISTA step on the active set (single workgroup):
+//   z = y + g / Lip        (g = Phi_S^*(V - Phi_S y): minus the gradient)
+//   x+ = soft(z, lam / Lip)
+//   t+ = (1 + sqrt(1 + 4 t^2)) / 2,  y+ = x+ + ((t - 1) / t+)(x+ - x)
+// writes the forward weights y+ / n for the next residual, and the
+// statistics ||x+ - x||^2, ||x+||^2, ||y||_1 and max |g| (the last two at the
+// gradient point y, for the restricted duality gap).
+__global__ __launch_bounds__(1024) void fista_kernel(int64_t nS, const double* __restrict__ g,
+                                                     double* __restrict__ x, double* __restrict__ y,
+                                                     Atom<float>* __restrict__ atoms,
+                                                     double* __restrict__ scal, double lam) {
+  __shared__ double sh[16];
+  const double lip = scal[kScalLip];
+  const double t = scal[kScalT];
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  const double mom = (t - 1.0) / tn;
+  const double thr = lam / lip;
+  double d2 = 0, n2 = 0, yl1 = 0, gmax = 0;
+  for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) {
+    yl1 += fabs(y[p]);
+    gmax = fmax(gmax, fabs(g[p]));
+    const double z = y[p] + g[p] / lip;
+    const double az = fabs(z) - thr;
+    const double xn = az > 0 ? copysign(az, z) : 0.0;
+    const double xo = x[p];
+    const double yn = xn + mom * (xn - xo);
+    d2 += (xn - xo) * (xn - xo);
+    n2 += xn * xn;
+    x[p] = xn;
+    y[p] = yn;
+    atoms[p].w = (float)(yn * atoms[p].inv_n);
+  }
+  d2 = block_sum<1024>(d2, sh);
+  n2 = block_sum<1024>(n2, sh);
+  yl1 = block_sum<1024>(yl1, sh);
+  gmax = block_max<1024>(gmax, sh);
+  if (threadIdx.x == 0) {
+    scal[kScalT] = tn;
+    scal[kScalDiff2] = d2;
+    scal[kScalNorm2] = n2;
+    scal[kScalYL1] = yl1;
+    scal[kScalGmax] = gmax;
+  }
+}
+
+// Power iteration on G = Re(Phi_S^H Phi_S): given gv = G v with ||v|| = 1,
+// records ||G v|| and sets v <- G v / ||G v|| as the next forward weights.
+__global__ __launch_bounds__(1024) void power_kernel(int64_t nS, const double* __restrict__ gv,
+                                                     double* __restrict__ v,
+                                                     Atom<float>* __restrict__ atoms,
+                                                     double* __restrict__ scal) {
+  __shared__ double sh[16];
+  double s = 0;
+  for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) s += gv[p] * gv[p];
+  s = block_sum<1024>(s, sh);
+  const double nrm = sqrt(s);
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) {
+    const double vn = gv[p] * inv;
+    v[p] = vn;
+    atoms[p].w = (float)(vn * atoms[p].inv_n);
+  }
+  if (threadIdx.x == 0) {
+    scal[kScalPrevEig] = scal[kScalEig];
+    scal[kScalEig] = nrm;
+  }
+}
+
+// v = 1/sqrt(nS) (deterministic start) as forward weights.
+__global__ void power_init_kernel(int64_t nS, double* __restrict__ v,
+                                  Atom<float>* __restrict__ atoms) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nS) return;
+  const double a = 1.0 / sqrt((double)nS);
+  v[p] = a;
+  atoms[p].w = (float)(a * atoms[p].inv_n);
+}
+
+// Forward weights from an FP64 vector: atoms[p].w = x[p] / n_p.
+__global__ void weights_kernel(int64_t nS, const double* __restrict__ x,
+                               Atom<float>* __restrict__ atoms) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nS) atoms[p].w = (float)(x[p] * atoms[p].inv_n);
+}
+
+__global__ void scale_kernel(int64_t N, const float* __restrict__ in, float s,
+                             float* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) out[j] = in[j] * s;
+}
+
+// ----------------------------------------------------------------------------
+static unsigned blocks(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+void k_gather(pc_plan* p, int64_t L, const int32_t* perm, const c32* in, c32* out, hipStream_t s) {
+  ProfScope ps(p, s, "gather", 20.0 * L, (double)L);
+  hipLaunchKernelGGL(gather_kernel, dim3(blocks(L, 256)), dim3(256), 0, s, L, perm, in, out);
+  PC_LAUNCH_CHECK("gather");
+}
+
+int k_resid_blocks(int64_t L) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (L + 255) / 256)); }
+
+void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial, double* out, hipStream_t s) {
+  ProfScope ps(p, s, "resid_reduce", 16.0 * L, (double)L);
+  const int nb = k_resid_blocks(L);
+  hipLaunchKernelGGL(resid_partial_kernel, dim3(nb), dim3(256), 0, s, L, r, V, partial);
+  PC_LAUNCH_CHECK("resid_partial");
+  hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(64), 0, s, nb, partial, out);
+  PC_LAUNCH_CHECK("resid_final");
+}
+
+void k_select(pc_plan* p, int64_t N, const float* eta, float tau, unsigned* count, int32_t* out, int64_t cap,
+              hipStream_t s) {
+  ProfScope ps(p, s, "select", 4.0 * N, (double)N);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, count);
+  hipLaunchKernelGGL(select_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, eta, tau, count, out,
+                     cap);
+  PC_LAUNCH_CHECK("select");
+}
+
+void k_fista(pc_plan* p, int64_t nS, const double* g, double* x, double* y, Atom<float>* atoms, double* scal,
+             double lam, hipStream_t s) {
+  ProfScope ps(p, s, "fista", 64.0 * nS, (double)nS);
+  hipLaunchKernelGGL(fista_kernel, dim3(1), dim3(1024), 0, s, nS, g, x, y, atoms, scal, lam);
+  PC_LAUNCH_CHECK("fista");
+}
+
+void k_power(pc_plan* p, int64_t nS, const double* gv, double* v, Atom<float>* atoms, double* scal,
+             hipStream_t s) {
+  ProfScope ps(p, s, "power", 40.0 * nS, (double)nS);
+  hipLaunchKernelGGL(power_kernel, dim3(1), dim3(1024), 0, s, nS, gv, v, atoms, scal);
+  PC_LAUNCH_CHECK("power");
+}
+
+void k_power_init(pc_plan* p, int64_t nS, double* v, Atom<float>* atoms, hipStream_t s) {
+  hipLaunchKernelGGL(power_init_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, v, atoms);
+  PC_LAUNCH_CHECK("power_init");
+}
+
+void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s) {
+  if (nS <= 0) return;
+  hipLaunchKernelGGL(weights_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, x, atoms);
+  PC_LAUNCH_CHECK("weights");
+}
+
+void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, in, sc, out);
+  PC_LAUNCH_CHECK("scale");
+}
+
+}  // namespace pc

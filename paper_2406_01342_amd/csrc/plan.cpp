@@ -1,0 +1,453 @@
+// Plan construction: host-side FP64 geometry, tile sort, spreading work list,
+// kernel correction and twiddle tables, and the device uploads.
+//
+// Geometry (paper Sect. 2.1-2.2): pixel step dl = fov / n, l_i = (i - n/2) dl,
+// m_j = (j - n/2) dl.  The adjoint sum exp(+j 2 pi u_k l_i) with l_i = a dl,
+// a = i - n/2, depends on u only through A_k = u_k dl modulo 1 (a is an
+// integer), so each visibility sits at the periodic fine-grid coordinate
+// X_k = M frac(A_k + 1/2) in cells (M = 2n; the +1/2 puts zero frequency at
+// cell M/2 and costs a sign (-1)^a in the output, folded into the correction).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+
+namespace pc {
+
+void* dalloc(pc_plan* p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* ptr = nullptr;
+  PC_HIP(hipMalloc(&ptr, bytes));
+  p->owned.push_back({ptr, bytes});
+  p->footprint += bytes;
+  return ptr;
+}
+
+void plan_release(pc_plan* p) {
+  prof_release(p);
+  for (auto& b : p->owned) (void)hipFree(b.ptr);
+  p->owned.clear();
+  if (p->ev_a) (void)hipEventDestroy(p->ev_a);
+  if (p->ev_b) (void)hipEventDestroy(p->ev_b);
+}
+
+static void* grow(pc_plan* p, void** slot, size_t* cap, size_t bytes) {
+  if (*slot && *cap >= bytes) return *slot;
+  if (*slot) {
+    for (auto it = p->owned.begin(); it != p->owned.end(); ++it)
+      if (it->ptr == *slot) {
+        p->footprint -= it->bytes;
+        (void)hipFree(it->ptr);
+        p->owned.erase(it);
+        break;
+      }
+  }
+  size_t want = std::max<size_t>(bytes, 4096);
+  *slot = dalloc(p, want);
+  *cap = want;
+  return *slot;
+}
+
+void* ensure_atom_scratch(pc_plan* p, size_t bytes) {
+  return grow(p, &p->atom_scratch, &p->atom_capacity, bytes);
+}
+
+double* ensure_red_scratch(pc_plan* p, size_t count) {
+  size_t cap = p->red_capacity * sizeof(double);
+  void* slot = p->red_scratch;
+  void* r = grow(p, &slot, &cap, count * sizeof(double));
+  p->red_scratch = static_cast<double*>(r);
+  p->red_capacity = cap / sizeof(double);
+  return p->red_scratch;
+}
+
+// ----------------------------------------------------------------------------
+// Host layout: everything pc_plan_create computes before touching the device.
+// ----------------------------------------------------------------------------
+struct Layout {
+  GridGeom g{};
+  int64_t L = 0;
+  std::vector<int32_t> perm;            // sorted -> caller
+  std::vector<double> AB;               // sorted, interleaved (A, B)
+  std::vector<uint32_t> cell;           // sorted
+  std::vector<double> off;              // sorted, interleaved (s_u, s_v)
+  std::vector<SpreadChunk> chunks;
+  std::vector<FoldItem> fold;
+  int64_t n_partials = 0;
+};
+
+static double kernel_beta(int W) { return 2.30 * W; }
+
+static int kernel_width(double eps) {
+  if (!(eps > 0)) eps = 1e-5;
+  int W = (int)std::ceil(std::log10(1.0 / eps)) + 1;
+  return std::min(std::max(W, 2), kMaxWidth);
+}
+
+static void validate(const pc_geometry* g) {
+  PC_REQUIRE(g != nullptr, "geometry is NULL");
+  PC_REQUIRE(g->nvis > 0, "nvis must be > 0");
+  PC_REQUIRE(g->nvis < (int64_t(1) << 31) - 1, "nvis must fit in int32");
+  PC_REQUIRE(g->u != nullptr && g->v != nullptr, "u and v must not be NULL");
+  PC_REQUIRE(g->npix >= 16 && g->npix <= 8192 && g->npix % 2 == 0,
+             "npix must be even and in [16, 8192]");
+  PC_REQUIRE(std::isfinite(g->fov_rad) && g->fov_rad > 0, "fov_rad must be finite and > 0");
+  PC_REQUIRE(g->uv_units == PC_UV_WAVELENGTHS || g->uv_units == PC_UV_METRES,
+             "uv_units must be PC_UV_WAVELENGTHS or PC_UV_METRES");
+  if (g->uv_units == PC_UV_METRES)
+    PC_REQUIRE(std::isfinite(g->freq_hz) && g->freq_hz > 0, "freq_hz must be > 0 for metres");
+  PC_REQUIRE(g->precision == PC_PREC_FP32 || g->precision == PC_PREC_FP64,
+             "precision must be PC_PREC_FP32 or PC_PREC_FP64");
+  const double dl = g->fov_rad / g->npix;
+  const double lmax = (g->npix / 2) * dl;
+  PC_REQUIRE(2.0 * lmax * lmax < 1.0, "field of view reaches l^2 + m^2 >= 1");
+  if (g->upsamp > 0 && g->upsamp != 2.0) fail(PC_ERR_UNSUPPORTED, "only upsamp = 2 is supported");
+  for (int64_t k = 0; k < g->nvis; ++k) {
+    if (!std::isfinite(g->u[k]) || !std::isfinite(g->v[k]))
+      fail(PC_ERR_INVALID_ARG, "non-finite uv at index " + std::to_string(k));
+    if (g->w && g->w[k] != 0.0)
+      fail(PC_ERR_INVALID_ARG, "nonzero w at index " + std::to_string(k) +
+                                   " (only coplanar arrays are supported)");
+  }
+}
+
+static Layout build_layout(const pc_geometry* geo, bool full) {
+  validate(geo);
+  Layout lay;
+  const int64_t L = geo->nvis;
+  const int n = geo->npix, M = 2 * n, W = kernel_width(geo->nufft_eps);
+  const double dl = geo->fov_rad / n;
+  const double scale = geo->uv_units == PC_UV_METRES ? geo->freq_hz / 299792458.0 : 1.0;
+  GridGeom& g = lay.g;
+  g.n = n;
+  g.M = M;
+  g.W = W;
+  g.beta64 = kernel_beta(W);
+  g.beta = (float)g.beta64;
+  g.dl = dl;
+  lay.L = L;
+
+  // Per-visibility phase rates and first cells (unwrapped, in [-W/2, M)).
+  std::vector<double> A(L), B(L);
+  std::vector<int32_t> c0u(L), c0v(L);
+  std::vector<double> su(L), sv(L);
+  int64_t lo_u = INT64_MAX, hi_u = INT64_MIN, lo_v = INT64_MAX, hi_v = INT64_MIN;
+  for (int64_t k = 0; k < L; ++k) {
+    const double a = geo->u[k] * scale * dl, b = geo->v[k] * scale * dl;
+    A[k] = a;
+    B[k] = b;
+    const double xu = M * (a + 0.5 - std::floor(a + 0.5));
+    const double xv = M * (b + 0.5 - std::floor(b + 0.5));
+    const double mu = std::ceil(xu - 0.5 * W), mv = std::ceil(xv - 0.5 * W);
+    c0u[k] = (int32_t)mu;
+    c0v[k] = (int32_t)mv;
+    su[k] = mu - xu;  // in (-W/2, -W/2 + 1]
+    sv[k] = mv - xv;
+    lo_u = std::min<int64_t>(lo_u, c0u[k]);
+    hi_u = std::max<int64_t>(hi_u, c0u[k] + W - 1);
+    lo_v = std::min<int64_t>(lo_v, c0v[k]);
+    hi_v = std::max<int64_t>(hi_v, c0v[k] + W - 1);
+  }
+  // Band: a tile-aligned window holding every footprint without wrapping, or
+  // the whole periodic grid when footprints cross the grid edge.
+  const int T = kTile;
+  auto band = [&](int64_t lo, int64_t hi, int32_t& b0, int32_t& nb) {
+    if (lo < 0 || hi > M - 1) {
+      b0 = 0;
+      nb = M;
+      return true;
+    }
+    b0 = (int32_t)(lo / T) * T;
+    int64_t b1 = ((hi + 1 + T - 1) / T) * T;
+    nb = (int32_t)(std::min<int64_t>(b1, M) - b0);
+    return false;
+  };
+  const bool wu = band(lo_u, hi_u, g.u0, g.nu);
+  const bool wv = band(lo_v, hi_v, g.v0, g.nv);
+  g.wrap = (wu || wv) ? 1 : 0;
+  if (g.wrap) {  // one periodic mode for both axes keeps the kernels simple
+    g.u0 = g.v0 = 0;
+    g.nu = g.nv = M;
+  }
+  g.ntu = g.nu / T;
+  g.ntv = g.nv / T;
+  const int ntu = g.ntu, ntv = g.ntv;
+  const int64_t ntiles = (int64_t)ntu * ntv;
+
+  // Tile and spill class of each visibility.  Class order inside a tile:
+  // 0 none, 1 spills down (+v) only, 2 spills both ways, 3 spills right (+u)
+  // only, so that the sets {down, both}, {both, right}, {both} are ranges.
+  std::vector<int64_t> key(L);
+  for (int64_t k = 0; k < L; ++k) {
+    int32_t cu = ((c0u[k] % M) + M) % M, cv = ((c0v[k] % M) + M) % M;
+    int32_t ru = cu - g.u0, rv = cv - g.v0;
+    int32_t tu = ru / T, tv = rv / T;
+    bool sr = (ru % T) > T - W, sd = (rv % T) > T - W;
+    int cls = sd ? (sr ? 2 : 1) : (sr ? 3 : 0);
+    key[k] = ((int64_t)tv * ntu + tu) * 4 + cls;
+    c0u[k] = cu;
+    c0v[k] = cv;
+  }
+  // Stable counting sort by key.
+  std::vector<int64_t> cnt(ntiles * 4 + 1, 0);
+  for (int64_t k = 0; k < L; ++k) cnt[key[k] + 1]++;
+  for (int64_t i = 0; i < ntiles * 4; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int64_t> bstart(cnt.begin(), cnt.end());  // class starts
+  lay.perm.resize(L);
+  {
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t k = 0; k < L; ++k) lay.perm[pos[key[k]]++] = (int32_t)k;
+  }
+  if (full) {
+    lay.AB.resize(2 * L);
+    lay.cell.resize(L);
+    lay.off.resize(2 * L);
+    for (int64_t s = 0; s < L; ++s) {
+      const int32_t k = lay.perm[s];
+      lay.AB[2 * s] = A[k];
+      lay.AB[2 * s + 1] = B[k];
+      lay.cell[s] = ((uint32_t)c0v[k] << 16) | (uint32_t)c0u[k];
+      lay.off[2 * s] = su[k];
+      lay.off[2 * s + 1] = sv[k];
+    }
+  }
+  // Work list.  Split tiles whose gathered count exceeds kChunk.
+  const int64_t kChunk = 2048;
+  auto tid = [&](int tv, int tu) -> int64_t {
+    if (g.wrap) {
+      tv = (tv + ntv) % ntv;
+      tu = (tu + ntu) % ntu;
+    } else if (tv < 0 || tu < 0) {
+      return -1;
+    }
+    return (int64_t)tv * ntu + tu;
+  };
+  auto cls_beg = [&](int64_t t, int c) { return bstart[t * 4 + c]; };
+  for (int tv = 0; tv < ntv; ++tv)
+    for (int tu = 0; tu < ntu; ++tu) {
+      const int64_t t = (int64_t)tv * ntu + tu;
+      int64_t rb[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0};
+      rb[0] = cls_beg(t, 0);
+      re[0] = bstart[t * 4 + 4];  // end of tile t
+      int64_t tl = tid(tv, tu - 1), tup = tid(tv - 1, tu), tul = tid(tv - 1, tu - 1);
+      if (tl >= 0 && tl != t) {  // left neighbour: classes both + right
+        rb[1] = cls_beg(tl, 2);
+        re[1] = bstart[tl * 4 + 4];
+      }
+      if (tup >= 0 && tup != t) {  // upper neighbour: classes down + both
+        rb[2] = cls_beg(tup, 1);
+        re[2] = cls_beg(tup, 3);
+      }
+      if (tul >= 0 && tul != t) {  // upper-left neighbour: class both
+        rb[3] = cls_beg(tul, 2);
+        re[3] = cls_beg(tul, 3);
+      }
+      int64_t total = 0;
+      for (int r = 0; r < 4; ++r) total += re[r] - rb[r];
+      const int64_t nch = std::max<int64_t>(1, (total + kChunk - 1) / kChunk);
+      if (nch == 1) {
+        SpreadChunk c{};
+        c.tile = (int32_t)t;
+        c.slot = -1;
+        for (int r = 0; r < 4; ++r) {
+          c.beg[r] = (int32_t)rb[r];
+          c.end[r] = (int32_t)re[r];
+        }
+        lay.chunks.push_back(c);
+        continue;
+      }
+      FoldItem f{(int32_t)t, (int32_t)lay.n_partials, (int32_t)nch, 0};
+      lay.fold.push_back(f);
+      for (int64_t c = 0; c < nch; ++c) {
+        const int64_t q0 = total * c / nch, q1 = total * (c + 1) / nch;
+        SpreadChunk ch{};
+        ch.tile = (int32_t)t;
+        ch.slot = (int32_t)(lay.n_partials + c);
+        int64_t acc = 0;
+        for (int r = 0; r < 4; ++r) {
+          const int64_t len = re[r] - rb[r];
+          const int64_t a = std::max<int64_t>(q0, acc), b = std::min<int64_t>(q1, acc + len);
+          if (b > a) {
+            ch.beg[r] = (int32_t)(rb[r] + (a - acc));
+            ch.end[r] = (int32_t)(rb[r] + (b - acc));
+          } else {
+            ch.beg[r] = ch.end[r] = 0;
+          }
+          acc += len;
+        }
+        lay.chunks.push_back(ch);
+      }
+      lay.n_partials += nch;
+    }
+  return lay;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_q).
+static void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (z * p1 - p0) / (z * z - 1.0);
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// psi(a) = (W/2) int_{-1}^{1} phi(z) cos(pi a W z / M) dz, the Fourier
+// transform of the spreading kernel at output frequency a; corr = (-1)^a/psi.
+static std::vector<double> correction_table(const GridGeom& g) {
+  std::vector<double> x, w;
+  gauss_legendre(2 * g.W + 120, x, w);
+  std::vector<double> c(g.n);
+  for (int i = 0; i < g.n; ++i) {
+    const int a = i - g.n / 2;
+    double s = 0;
+    for (size_t q = 0; q < x.size(); ++q) {
+      const double phi = std::exp(g.beta64 * (std::sqrt(1.0 - x[q] * x[q]) - 1.0));
+      s += w[q] * phi * std::cos(M_PI * a * g.W * x[q] / g.M);
+    }
+    const double psi = 0.5 * g.W * s;
+    c[i] = ((a & 1) ? -1.0 : 1.0) / psi;
+  }
+  return c;
+}
+
+static size_t layout_bytes(const Layout& lay, int prec) {
+  const GridGeom& g = lay.g;
+  const size_t cb = prec == PC_PREC_FP64 ? 16 : 8, rb = cb / 2;
+  size_t b = 0;
+  auto add = [&](size_t x) { b += std::max<size_t>(x, 256); };
+  add(lay.L * 4);                            // perm
+  add(lay.L * 16);                           // AB
+  add(lay.L * 4);                            // cell
+  add(lay.L * 2 * rb);                       // off
+  add(lay.chunks.size() * sizeof(SpreadChunk));
+  add(lay.fold.size() * sizeof(FoldItem));
+  add((size_t)g.nu * g.nv * cb);             // grid band
+  add((size_t)g.nv * g.n * cb);              // H
+  add((size_t)lay.n_partials * kTile * kTile * cb);
+  add((size_t)g.M * cb);                     // twiddles
+  add((size_t)g.n * rb);                     // correction
+  add(256);                                  // max key
+  add(lay.L * cb);                           // vis scratch
+  return b;
+}
+
+}  // namespace pc
+
+using namespace pc;
+
+extern "C" pc_status pc_plan_footprint_impl(const pc_geometry* geom, size_t* bytes) {
+  PC_REQUIRE(bytes != nullptr, "bytes is NULL");
+  Layout lay = build_layout(geom, false);
+  *bytes = layout_bytes(lay, geom->precision);
+  return PC_OK;
+}
+
+extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, pc_plan** out) {
+  PC_REQUIRE(out != nullptr, "out is NULL");
+  *out = nullptr;
+  Layout lay = build_layout(geom, true);
+  hipStream_t s = (hipStream_t)stream;
+  pc_plan* p = new pc_plan();
+  try {
+    PC_HIP(hipGetDevice(&p->device));
+    p->precision = geom->precision;
+    p->L = lay.L;
+    p->g = lay.g;
+    p->n_chunks = (int64_t)lay.chunks.size();
+    p->n_partials = lay.n_partials;
+    p->n_fold = (int64_t)lay.fold.size();
+    const GridGeom& g = lay.g;
+    const bool f64 = geom->precision == PC_PREC_FP64;
+    const size_t cb = f64 ? 16 : 8, rb = cb / 2;
+    const int64_t L = lay.L;
+
+    p->perm = (int32_t*)dalloc(p, L * 4);
+    p->AB = (double*)dalloc(p, L * 16);
+    p->cell = (uint32_t*)dalloc(p, L * 4);
+    p->off = dalloc(p, L * 2 * rb);
+    p->chunks = (SpreadChunk*)dalloc(p, lay.chunks.size() * sizeof(SpreadChunk));
+    p->fold = (FoldItem*)dalloc(p, lay.fold.size() * sizeof(FoldItem));
+    p->grid = dalloc(p, (size_t)g.nu * g.nv * cb);
+    p->H = dalloc(p, (size_t)g.nv * g.n * cb);
+    p->partials = dalloc(p, (size_t)lay.n_partials * kTile * kTile * cb);
+    p->twiddle = dalloc(p, (size_t)g.M * cb);
+    p->corr = dalloc(p, (size_t)g.n * rb);
+    p->maxkey = (unsigned long long*)dalloc(p, 256);
+    p->vis_scratch = dalloc(p, L * cb);
+
+    // Host staging of converted tables; copies complete before return.
+    PC_HIP(hipMemcpyAsync(p->perm, lay.perm.data(), L * 4, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(p->AB, lay.AB.data(), L * 16, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(p->cell, lay.cell.data(), L * 4, hipMemcpyHostToDevice, s));
+    std::vector<float> off32;
+    if (f64) {
+      PC_HIP(hipMemcpyAsync(p->off, lay.off.data(), L * 16, hipMemcpyHostToDevice, s));
+    } else {
+      off32.resize(2 * L);
+      for (int64_t i = 0; i < 2 * L; ++i) off32[i] = (float)lay.off[i];
+      PC_HIP(hipMemcpyAsync(p->off, off32.data(), L * 8, hipMemcpyHostToDevice, s));
+    }
+    if (!lay.chunks.empty())
+      PC_HIP(hipMemcpyAsync(p->chunks, lay.chunks.data(), lay.chunks.size() * sizeof(SpreadChunk),
+                            hipMemcpyHostToDevice, s));
+    if (!lay.fold.empty())
+      PC_HIP(hipMemcpyAsync(p->fold, lay.fold.data(), lay.fold.size() * sizeof(FoldItem),
+                            hipMemcpyHostToDevice, s));
+    // Twiddles exp(+2 pi i t / M), computed in FP64 and rounded once.
+    std::vector<double> tw64(2 * (size_t)g.M);
+    for (int t = 0; t < g.M; ++t) {
+      // exact symmetric evaluation: reduce t to the first octant
+      const double ang = 2.0 * M_PI * (double)t / g.M;
+      tw64[2 * t] = std::cos(ang);
+      tw64[2 * t + 1] = std::sin(ang);
+    }
+    std::vector<double> corr64 = correction_table(g);
+    std::vector<float> tw32, corr32;
+    if (f64) {
+      PC_HIP(hipMemcpyAsync(p->twiddle, tw64.data(), g.M * 16, hipMemcpyHostToDevice, s));
+      PC_HIP(hipMemcpyAsync(p->corr, corr64.data(), g.n * 8, hipMemcpyHostToDevice, s));
+    } else {
+      tw32.resize(2 * (size_t)g.M);
+      for (size_t i = 0; i < tw32.size(); ++i) tw32[i] = (float)tw64[i];
+      corr32.resize(g.n);
+      for (int i = 0; i < g.n; ++i) corr32[i] = (float)corr64[i];
+      PC_HIP(hipMemcpyAsync(p->twiddle, tw32.data(), g.M * 8, hipMemcpyHostToDevice, s));
+      PC_HIP(hipMemcpyAsync(p->corr, corr32.data(), g.n * 4, hipMemcpyHostToDevice, s));
+    }
+    PC_HIP(hipEventCreate(&p->ev_a));
+    PC_HIP(hipEventCreate(&p->ev_b));
+    PC_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    plan_release(p);
+    delete p;
+    throw;
+  }
+  *out = p;
+  return PC_OK;
+}

@@ -1,0 +1,399 @@
+// Polyatomic Frank-Wolfe LASSO solve (paper Sect. 5.1, Alg. 2) on the GPU.
+//
+//   eta_0 = Phi* V, lambda_max = ||eta_0||_inf (Eq. lmax), lambda = alpha
+//   lambda_max (Eq. lambda), Delta = (1 - delta) lambda_max.
+//   for k = 0, 1, ...
+//     I  = { j : |eta_k|_j >= ||eta_k||_inf - 2 Delta / (k + 2) }   (1.a)
+//     S  = S u I                                                    (1.b)
+//     x  = APGD on the LASSO restricted to S, warm-started          (2)
+//     S  = supp(x)                                                  (3)
+//     r  = V - Phi x, eta_{k+1} = Phi* r, objective and duality gap (4)
+//
+// Precision: the operator applications (gridded adjoint, direct sparse
+// forward and restricted adjoint) are FP32 with FP64 phases; the APGD
+// iterates, the step size (power iteration), the objective and the duality
+// gap are FP64.  The restricted solve stops when the relative duality gap
+// of the restricted problem at the gradient point y is <= tau_k =
+// max(tau_min, tau_0 g_k), g_k the full problem's relative gap at the current
+// iterate (tested at steps 1, 1 + kCheck, ...), returning the proximal step
+// taken from y, or at the iteration cap.  Duality gaps use the dual point
+// nu = min(1, lambda / ||Phi* r||_inf) r.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "solver_kernels.h"
+
+namespace pc {
+
+template <typename T>
+struct DevArray {
+  T* ptr = nullptr;
+  int64_t cap = 0;
+  void ensure(int64_t n) {
+    if (n <= cap && ptr) return;
+    int64_t want = std::max<int64_t>(n, std::max<int64_t>(2 * cap, 256));
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    PC_HIP(hipMalloc(&ptr, want * sizeof(T)));
+    cap = want;
+  }
+  ~DevArray() {
+    if (ptr) (void)hipFree(ptr);
+  }
+};
+
+constexpr int kCheck = 4;        // APGD convergence test cadence
+constexpr int kPowerIters = 30;  // power iterations per active set
+constexpr double kLipMargin = 1.01;
+
+struct Pfw {
+  pc_plan* p;
+  hipStream_t s;
+  pc_solve_params prm;
+  int64_t L, N;
+  DevArray<c32> V, r;
+  DevArray<float> eta;
+  DevArray<int32_t> cand, pix;
+  DevArray<unsigned> cand_count;
+  DevArray<Atom<float>> atoms;
+  DevArray<double> x, y, g, v, adj_partial, red_partial, scal;
+  std::vector<int32_t> S;
+  std::vector<double> xs;
+  double lam = 0, lmax = 0, Delta = 0, eta_inf = 0, P_prev = 0, P = 0, rel_gap = 0, gap = 0;
+  int64_t eta_argmax = -1;
+  int k = 0, inner_total = 0;
+  bool done = false, converged = false;
+  double adj_ms = 0;
+  int adj_calls = 0;
+  double t0 = 0;
+
+  Pfw(pc_plan* plan, hipStream_t stream, const pc_solve_params& params)
+      : p(plan), s(stream), prm(params), L(plan->L), N((int64_t)plan->g.n * plan->g.n) {}
+
+  static double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+  }
+
+  void adjoint_timed(const c32* vis_sorted) {
+    PC_HIP(hipEventRecord(p->ev_a, s));
+    adjoint_grid<float>(p, vis_sorted, true, eta.ptr, 1.0f, s);
+    PC_HIP(hipEventRecord(p->ev_b, s));
+    double mx;
+    int64_t am;
+    maxkey_read(p, s, &mx, &am);  // synchronises
+    float ms = 0;
+    PC_HIP(hipEventElapsedTime(&ms, p->ev_a, p->ev_b));
+    adj_ms += ms;
+    adj_calls++;
+    eta_inf = mx;
+    eta_argmax = am;
+  }
+
+  void read_scal(double* host, int first, int count) {
+    PC_HIP(hipMemcpyAsync(host, scal.ptr + first, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    PC_HIP(hipStreamSynchronize(s));
+  }
+
+  void residual_stats(double& r2, double& vr) {
+    red_partial.ensure(2 * k_resid_blocks(L));
+    k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
+    double h[2];
+    read_scal(h, kScalResid, 2);
+    r2 = h[0];
+    vr = h[1];
+  }
+
+  // Upload an active set and prepare its atom table (weights from xs_host).
+  void load_active(const std::vector<int32_t>& set, const std::vector<double>& xs_host) {
+    const int64_t nS = (int64_t)set.size();
+    pix.ensure(nS);
+    atoms.ensure(nS);
+    x.ensure(nS);
+    y.ensure(nS);
+    g.ensure(nS);
+    v.ensure(nS);
+    adj_partial.ensure(adjoint_partial_count(p, nS));
+    if (nS == 0) return;
+    PC_HIP(hipMemcpyAsync(pix.ptr, set.data(), nS * 4, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(x.ptr, xs_host.data(), nS * 8, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(y.ptr, xs_host.data(), nS * 8, hipMemcpyHostToDevice, s));
+    prep_atoms_into<float>(p, nS, pix.ptr, (const float*)nullptr, atoms.ptr, s);
+    k_weights(p, nS, x.ptr, atoms.ptr, s);
+    // pageable host sources: make sure the copies completed before reuse
+    PC_HIP(hipStreamSynchronize(s));
+  }
+
+  void init(const void* vis_caller) {
+    t0 = now();
+    V.ensure(L);
+    r.ensure(L);
+    eta.ensure(N);
+    scal.ensure(kScalCount);
+    cand_count.ensure(1);
+    cand.ensure(65536);
+    k_gather(p, L, p->perm, (const c32*)vis_caller, V.ptr, s);
+    adjoint_timed(V.ptr);
+    lmax = eta_inf;
+    lam = prm.lambda > 0 ? prm.lambda : prm.alpha * lmax;
+    Delta = (1.0 - prm.delta) * lmax;
+    // P(0) = ||V||^2 / 2
+    PC_HIP(hipMemcpyAsync(r.ptr, V.ptr, L * sizeof(c32), hipMemcpyDeviceToDevice, s));
+    double r2, vr;
+    residual_stats(r2, vr);
+    P_prev = 0.5 * r2;
+    P = P_prev;
+    const double sc = (eta_inf <= lam) ? 1.0 : lam / eta_inf;
+    gap = P - (sc * vr - 0.5 * sc * sc * r2);
+    rel_gap = P > 0 ? gap / P : 0.0;
+    if (!(lmax > 0) || !(lam > 0)) {  // zero data: x = 0 is the solution
+      done = true;
+      converged = true;
+    }
+  }
+
+  double power_iteration(int64_t nS) {
+    k_power_init(p, nS, v.ptr, atoms.ptr, s);
+    for (int it = 0; it < kPowerIters; ++it) {
+      forward_atoms<float>(p, nS, atoms.ptr, nullptr, true, r.ptr, true, s);
+      adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, g.ptr, s);
+      k_power(p, nS, g.ptr, v.ptr, atoms.ptr, scal.ptr, s);
+    }
+    double e[2];
+    read_scal(e, kScalEig, 2);
+    return e[0];
+  }
+
+  void step() {
+    if (done) return;
+    // 1.a polyatomic exploration: threshold in FP64, compared in FP32
+    const double tau = eta_inf - 2.0 * Delta / (k + 2);
+    const float tau_f = (float)tau;
+    unsigned count = 0;
+    for (;;) {
+      k_select(p, N, eta.ptr, tau_f, cand_count.ptr, cand.ptr, cand.cap, s);
+      PC_HIP(hipMemcpyAsync(&count, cand_count.ptr, 4, hipMemcpyDeviceToHost, s));
+      PC_HIP(hipStreamSynchronize(s));
+      if ((int64_t)count <= cand.cap) break;
+      cand.ensure(count);
+    }
+    std::vector<int32_t> I(count);
+    if (count) {
+      PC_HIP(hipMemcpyAsync(I.data(), cand.ptr, count * 4, hipMemcpyDeviceToHost, s));
+      PC_HIP(hipStreamSynchronize(s));
+    }
+    std::sort(I.begin(), I.end());
+    // 1.b S u I with warm-start weights (new atoms at zero)
+    std::vector<int32_t> Sn;
+    Sn.reserve(S.size() + I.size());
+    std::set_union(S.begin(), S.end(), I.begin(), I.end(), std::back_inserter(Sn));
+    std::vector<double> xw(Sn.size(), 0.0);
+    for (size_t a = 0, b = 0; a < S.size(); ++a) {
+      while (Sn[b] != S[a]) ++b;
+      xw[b] = xs[a];
+    }
+    const int64_t nS = (int64_t)Sn.size();
+    load_active(Sn, xw);
+    // 2. APGD on the restricted problem
+    int inner = 0;
+    if (nS > 0) {
+      const double lip = power_iteration(nS) * kLipMargin;
+      double hs[2] = {lip, 1.0};
+      PC_HIP(hipMemcpyAsync(scal.ptr + kScalLip, hs, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+      k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
+      const double tol = std::max(prm.inner_tol_min, prm.inner_tol0 * rel_gap);
+      for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
+        forward_atoms<float>(p, nS, atoms.ptr, V.ptr, true, r.ptr, true, s);
+        adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, g.ptr, s);
+        const bool check = (inner - 1) % kCheck == 0;
+        if (check) {
+          red_partial.ensure(2 * k_resid_blocks(L));
+          k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
+        }
+        k_fista(p, nS, g.ptr, x.ptr, y.ptr, atoms.ptr, scal.ptr, lam, s);
+        if (check) {
+          double h[4];  // ||r_y||^2, Re<V, r_y>, ||y||_1, max |g|
+          read_scal(h, kScalResid, 4);
+          const double py = 0.5 * h[0] + lam * h[2];
+          const double sc = h[3] <= lam ? 1.0 : lam / h[3];
+          const double gy = py - (sc * h[1] - 0.5 * sc * sc * h[0]);
+          if (gy <= tol * py) break;
+        }
+      }
+      inner = std::min(inner, prm.inner_max_iter);
+      xw.resize(nS);
+      PC_HIP(hipMemcpyAsync(xw.data(), x.ptr, nS * 8, hipMemcpyDeviceToHost, s));
+      PC_HIP(hipStreamSynchronize(s));
+    }
+    inner_total += inner;
+    // 3. prune
+    S.clear();
+    xs.clear();
+    for (int64_t a = 0; a < nS; ++a)
+      if (xw[a] != 0.0) {
+        S.push_back(Sn[a]);
+        xs.push_back(xw[a]);
+      }
+    // 4. residual, dirty residual, objective and gap
+    load_active(S, xs);
+    forward_atoms<float>(p, (int64_t)S.size(), atoms.ptr, V.ptr, true, r.ptr, true, s);
+    adjoint_timed(r.ptr);
+    double r2, vr;
+    residual_stats(r2, vr);
+    double l1 = 0;
+    for (double w : xs) l1 += std::fabs(w);
+    P = 0.5 * r2 + lam * l1;
+    const double sc = (eta_inf <= lam) ? 1.0 : lam / eta_inf;
+    gap = P - (sc * vr - 0.5 * sc * sc * r2);
+    rel_gap = P > 0 ? gap / P : 0.0;
+    const double rel_imp = P_prev > 0 ? std::fabs(P - P_prev) / P_prev : 0.0;
+    if (prm.log_every > 0 && (k % prm.log_every == 0))
+      std::fprintf(stderr,
+                   "[pfw] k=%d new=%u active=%zu eta_inf=%.6g obj=%.10g rel_gap=%.3e inner=%d\n",
+                   k, count, S.size(), eta_inf, P, rel_gap, inner);
+    P_prev = P;
+    ++k;
+    if (prm.rel_obj_tol > 0 && rel_imp <= prm.rel_obj_tol) converged = true;
+    if (prm.rel_gap_tol > 0 && rel_gap <= prm.rel_gap_tol) converged = true;
+    if (converged || k >= prm.max_iter) done = true;
+  }
+
+  pc_status fill(pc_solve_result* res) {
+    const int64_t na = (int64_t)S.size();
+    res->natoms = na;
+    res->objective = P;
+    res->rel_gap = rel_gap;
+    res->lambda = lam;
+    res->lambda_max = lmax;
+    res->cert_max = lam > 0 ? eta_inf / lam : 0.0;
+    res->cert_argmax = eta_argmax;
+    res->iters = k;
+    res->inner_iters = inner_total;
+    res->converged = converged ? 1 : 0;
+    res->adjoint_seconds = adj_ms * 1e-3;
+    res->adjoint_calls = adj_calls;
+    if (prm.want_certificate && res->cert && lam > 0)
+      k_scale(p, N, eta.ptr, (float)(1.0 / lam), res->cert, s);
+    PC_HIP(hipStreamSynchronize(s));
+    res->seconds = now() - t0;
+    if (na > res->capacity) {
+      set_last_error("pc_polyclean_solve: result capacity " + std::to_string(res->capacity) +
+                     " < natoms " + std::to_string(na));
+      return PC_ERR_CAPACITY;
+    }
+    if (na > 0) {
+      std::memcpy(res->pix, S.data(), na * sizeof(int32_t));
+      std::memcpy(res->weight, xs.data(), na * sizeof(double));
+    }
+    return converged ? PC_OK : PC_WARN_NOT_CONVERGED;
+  }
+};
+
+static void check_params(const pc_solve_params* prm) {
+  PC_REQUIRE(prm != nullptr, "params is NULL");
+  if (prm->positivity != 0) fail(PC_ERR_UNSUPPORTED, "positivity-constrained solve is not built");
+  PC_REQUIRE(prm->max_iter >= 1, "max_iter must be >= 1");
+  PC_REQUIRE(prm->delta > 0 && prm->delta <= 1, "delta must be in (0, 1]");
+  PC_REQUIRE(prm->lambda > 0 || (prm->alpha > 0 && std::isfinite(prm->alpha)),
+             "lambda > 0 or alpha > 0 is required");
+  PC_REQUIRE(prm->inner_max_iter >= 1, "inner_max_iter must be >= 1");
+  PC_REQUIRE(prm->inner_tol0 >= 0 && prm->inner_tol_min >= 0, "inner tolerances must be >= 0");
+}
+
+}  // namespace pc
+
+using namespace pc;
+
+struct pc_solver {
+  Pfw pfw;
+  pc_solver(pc_plan* p, hipStream_t s, const pc_solve_params& prm) : pfw(p, s, prm) {}
+};
+
+template <typename F>
+static pc_status guarded(const char* fn, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(std::string(fn) + ": " + e.what());
+    return e.status;
+  } catch (const std::exception& e) {
+    set_last_error(std::string(fn) + ": " + e.what());
+    return PC_ERR_DEVICE;
+  }
+}
+
+extern "C" {
+
+PC_API void pc_solve_params_default(pc_solve_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->alpha = 0.01;
+  p->delta = 0.99;
+  p->max_iter = 50;
+  p->inner_tol0 = 0.1;
+  p->inner_tol_min = 1e-8;
+  p->inner_max_iter = 2000;
+}
+
+PC_API pc_status pc_polyclean_solve(pc_plan* plan, const void* vis, const pc_solve_params* prm,
+                                    pc_solve_result* res, void* stream) {
+  return guarded("pc_polyclean_solve", [&] {
+    PC_REQUIRE(plan != nullptr && vis != nullptr && res != nullptr, "NULL argument");
+    PC_REQUIRE(plan->precision == PC_PREC_FP32, "solve needs an FP32 plan");
+    check_params(prm);
+    PC_REQUIRE(res->capacity >= 0, "capacity must be >= 0");
+    if (res->capacity > 0) PC_REQUIRE(res->pix && res->weight, "result arrays are NULL");
+    PC_HIP(hipSetDevice(plan->device));
+    Pfw pfw(plan, (hipStream_t)stream, *prm);
+    pfw.init(vis);
+    while (!pfw.done) pfw.step();
+    return pfw.fill(res);
+  });
+}
+
+PC_API pc_status pc_solver_create(pc_plan* plan, const void* vis, const pc_solve_params* prm,
+                                  void* stream, pc_solver** out) {
+  return guarded("pc_solver_create", [&] {
+    PC_REQUIRE(plan && vis && out, "NULL argument");
+    PC_REQUIRE(plan->precision == PC_PREC_FP32, "solve needs an FP32 plan");
+    check_params(prm);
+    *out = nullptr;
+    PC_HIP(hipSetDevice(plan->device));
+    auto* sv = new pc_solver(plan, (hipStream_t)stream, *prm);
+    try {
+      sv->pfw.init(vis);
+    } catch (...) {
+      delete sv;
+      throw;
+    }
+    *out = sv;
+    return PC_OK;
+  });
+}
+
+PC_API pc_status pc_solver_step(pc_solver* sv, int32_t* done) {
+  return guarded("pc_solver_step", [&] {
+    PC_REQUIRE(sv != nullptr, "solver is NULL");
+    PC_HIP(hipSetDevice(sv->pfw.p->device));
+    sv->pfw.step();
+    if (done) *done = sv->pfw.done ? 1 : 0;
+    return PC_OK;
+  });
+}
+
+PC_API pc_status pc_solver_result(pc_solver* sv, pc_solve_result* res) {
+  return guarded("pc_solver_result", [&] {
+    PC_REQUIRE(sv != nullptr && res != nullptr, "NULL argument");
+    PC_REQUIRE(res->capacity >= 0, "capacity must be >= 0");
+    if (res->capacity > 0) PC_REQUIRE(res->pix && res->weight, "result arrays are NULL");
+    return sv->pfw.fill(res);
+  });
+}
+
+PC_API void pc_solver_destroy(pc_solver* sv) { delete sv; }
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+"""GPU parity of the measurement operators against the FP64 oracle.
+
+Tolerance: 1e-4 relative L2 for every operator output (the accuracy target
+for the operator), identical argmax of the dirty image (lowest index on ties).
+"""
+import numpy as np
+import pytest
+
+from oracle import operator, solver
+from tests.gpu_util import api, problem, ragged_problem, rel_l2, say, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def _adjoint_case(p_uv, n, fov, h, **kw):
+    a = api()
+    plan = a.pc_plan_create(p_uv, n, fov, **kw)
+    img, mx, am = a.pc_adjoint_grid(plan, to_dev(h))
+    torch.cuda.synchronize()
+    return plan, img.cpu().numpy().astype(np.float64), mx, am
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_small", "c3_small"])
+def test_adjoint_grid_dirty_image(name):
+    say("adjoint_grid dirty", name)
+    p, vis = problem(name)
+    plan, img, mx, am = _adjoint_case(p.uv, p.npix, p.fov_rad, vis)
+    want = operator.adjoint(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128))
+    err = rel_l2(img, want)
+    say(name, "rel L2", err, "info", plan.info)
+    assert err <= TOL
+    wmx, wam = solver.argmax_abs(want)
+    assert am == wam
+    assert abs(mx - wmx) <= TOL * wmx
+    assert abs(mx - np.max(np.abs(img))) <= 1e-6 * mx
+
+
+def test_adjoint_grid_split_tiles_present():
+    p, vis = problem("c2_small")
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    assert plan.info["n_partials"] > 0 and plan.info["wraps"] == 1
+
+
+def test_adjoint_grid_partial_band():
+    """Coverage confined to |u dl| < 0.2: the band is a sub-window of the fine
+    grid (input pruning, no periodic wrap)."""
+    say("adjoint_grid partial band")
+    rng = np.random.default_rng(9)
+    n, fov, L = 256, 0.03, 5003
+    d = fov / n
+    uv = rng.normal(0.0, 0.06 / d, size=(L, 2)).clip(-0.2 / d, 0.2 / d)
+    h = (rng.normal(size=L) + 1j * rng.normal(size=L)).astype(np.complex64)
+    plan, img, mx, am = _adjoint_case(uv, n, fov, h)
+    assert plan.info["wraps"] == 0 and plan.info["band_nu"] < plan.info["fine"]
+    want = operator.adjoint(uv, n, fov, h.astype(np.complex128))
+    assert rel_l2(img, want) <= TOL
+    assert am == solver.argmax_abs(want)[1]
+    a = api()
+    x = np.zeros((n, n), np.float32)
+    pix = rng.choice(n * n, 500, replace=False)
+    x.reshape(-1)[pix] = rng.normal(size=500)
+    fx = a.pc_forward_grid(plan, to_dev(x)).cpu().numpy()
+    wantf = operator.forward(uv, n, fov, pix, x.reshape(-1)[pix].astype(np.float64))
+    assert rel_l2(fx, wantf) <= TOL
+
+
+def test_adjoint_grid_ragged_random():
+    say("adjoint_grid ragged")
+    uv, n, fov, h = ragged_problem()
+    plan, img, mx, am = _adjoint_case(uv, n, fov, h)
+    want = operator.adjoint(uv, n, fov, h.astype(np.complex128))
+    assert rel_l2(img, want) <= TOL
+    assert am == solver.argmax_abs(want)[1]
+
+
+def test_adjoint_grid_smallest_grid_and_single_vis():
+    say("adjoint_grid n=16, L=1")
+    uv = np.array([[3.7, -12.25]])
+    h = np.array([1.5 - 0.25j], dtype=np.complex64)
+    plan, img, mx, am = _adjoint_case(uv, 16, 0.2, h)
+    want = operator.adjoint(uv, 16, 0.2, h.astype(np.complex128))
+    assert rel_l2(img, want) <= TOL
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_small"])
+def test_forward_sparse(name):
+    say("forward_sparse", name)
+    p, _ = problem(name)
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    amp32 = p.sky_amp.astype(np.float32)
+    out = a.pc_forward_sparse(plan, to_dev(p.sky_pix.astype(np.int32)), to_dev(amp32))
+    torch.cuda.synchronize()
+    want = operator.forward(p.uv, p.npix, p.fov_rad, p.sky_pix, amp32.astype(np.float64))
+    err = rel_l2(out.cpu().numpy(), want)
+    say(name, "rel L2", err)
+    assert err <= TOL
+
+
+def test_forward_sparse_empty_and_centre():
+    a = api()
+    p, _ = problem("c1")
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    out = a.pc_forward_sparse(plan, to_dev(np.zeros(0, np.int32)), to_dev(np.zeros(0, np.float32)))
+    assert torch.count_nonzero(out).item() == 0
+    c = (p.npix // 2) * p.npix + p.npix // 2
+    out = a.pc_forward_sparse(plan, to_dev(np.array([c], np.int32)), to_dev(np.array([2.5], np.float32)))
+    o = out.cpu().numpy()
+    assert np.allclose(o.real, 2.5, rtol=0, atol=1e-6) and np.allclose(o.imag, 0, atol=1e-6)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_small"])
+def test_adjoint_sparse(name):
+    say("adjoint_sparse", name)
+    p, vis = problem(name)
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    rng = np.random.default_rng(3)
+    pix = np.sort(rng.choice(p.npix ** 2, 300, replace=False)).astype(np.int32)
+    out = a.pc_adjoint_sparse(plan, to_dev(vis), to_dev(pix))
+    torch.cuda.synchronize()
+    want = operator.adjoint_pixels(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128), pix)
+    err = rel_l2(out.cpu().numpy(), want)
+    say(name, "rel L2", err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("name", ["c1", "c3_small"])
+def test_forward_grid_dense(name):
+    say("forward_grid", name)
+    p, _ = problem(name)
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    rng = np.random.default_rng(4)
+    img = np.zeros((p.npix, p.npix), np.float32)
+    pix = rng.choice(p.npix ** 2, min(4000, p.npix ** 2 // 4), replace=False)
+    img.reshape(-1)[pix] = rng.normal(size=pix.size).astype(np.float32)
+    out = a.pc_forward_grid(plan, to_dev(img))
+    torch.cuda.synchronize()
+    want = operator.forward(p.uv, p.npix, p.fov_rad, pix, img.reshape(-1)[pix].astype(np.float64))
+    err = rel_l2(out.cpu().numpy(), want)
+    say(name, "rel L2", err)
+    assert err <= TOL
+
+
+def test_dot_product_gridded_pair():
+    """<Phi_grid x, h> = <x, Phi*_grid h> up to the gridding error."""
+    p, vis = problem("c1")
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(p.npix, p.npix)).astype(np.float32)
+    h = (rng.normal(size=p.nvis) + 1j * rng.normal(size=p.nvis)).astype(np.complex64)
+    fx = a.pc_forward_grid(plan, to_dev(x)).cpu().numpy().astype(np.complex128)
+    ah, _, _ = a.pc_adjoint_grid(plan, to_dev(h), want_max=False)
+    lhs = float(np.vdot(h.astype(np.complex128), fx).real)
+    rhs = float(np.sum(x.astype(np.float64) * ah.cpu().numpy()))
+    assert abs(lhs - rhs) <= 1e-4 * (abs(lhs) + abs(rhs))
+
+
+def test_dual_certificate_fixed_x():
+    say("dual_certificate c2_small")
+    p, vis = problem("c2_small")
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    amp = (0.8 * p.sky_amp).astype(np.float32)
+    lam = 0.05 * 1000.0
+    cert, mx, am = a.pc_dual_certificate(plan, to_dev(vis), to_dev(p.sky_pix.astype(np.int32)),
+                                         to_dev(amp), lam)
+    torch.cuda.synchronize()
+    want = solver.certificate(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128), p.sky_pix,
+                              amp.astype(np.float64), lam)
+    err = rel_l2(cert.cpu().numpy(), want)
+    say("rel L2", err)
+    assert err <= TOL
+    assert am == solver.argmax_abs(want)[1]
+
+
+def test_fp64_twin():
+    say("fp64 twin c1")
+    p, vis = problem("c1")
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad, nufft_eps=1e-12, precision=a.PC_PREC_FP64)
+    v128 = vis.astype(np.complex128)
+    img, mx, am = a.pc_adjoint_grid_f64(plan, to_dev(v128))
+    want = operator.adjoint(p.uv, p.npix, p.fov_rad, v128)
+    err = rel_l2(img.cpu().numpy(), want)
+    say("fp64 adjoint rel L2", err)
+    assert err <= 1e-9
+    out = a.pc_forward_sparse_f64(plan, to_dev(p.sky_pix.astype(np.int32)), to_dev(p.sky_amp))
+    wantf = operator.forward(p.uv, p.npix, p.fov_rad, p.sky_pix, p.sky_amp)
+    errf = rel_l2(out.cpu().numpy(), wantf)
+    say("fp64 forward rel L2", errf)
+    assert errf <= 1e-12
+
+
+def test_precision_mismatch_rejected():
+    p, vis = problem("c1")
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    with pytest.raises(a.PolycleanError) as e:
+        a.pc_adjoint_grid_f64(plan, to_dev(vis.astype(np.complex128)))
+    assert e.value.status == -1
+
+
+@pytest.mark.slow
+def test_adjoint_grid_full_c2_sampled():
+    """Full LOFAR-like size: sampled pixels, centre window and the argmax."""
+    say("adjoint_grid full c2")
+    p, vis = problem("c2")
+    plan, img, mx, am = _adjoint_case(p.uv, p.npix, p.fov_rad, vis)
+    n = p.npix
+    rng = np.random.default_rng(7)
+    samp = rng.choice(n * n, 1024, replace=False)
+    cw = (np.arange(n // 2 - 16, n // 2 + 16)[:, None] * n + np.arange(n // 2 - 16, n // 2 + 16)[None, :]).ravel()
+    pix = np.unique(np.concatenate([samp, cw, [am]]))
+    want = operator.adjoint_pixels(p.uv, n, p.fov_rad, vis.astype(np.complex128), pix)
+    got = img.reshape(-1)[pix]
+    err = rel_l2(got, want)
+    say("full c2 sampled rel L2", err, "info", plan.info)
+    assert err <= TOL
+    # the GPU maximum is at least as large as every sampled oracle value
+    assert np.max(np.abs(want)) <= abs(want[np.searchsorted(pix, am)]) * (1 + TOL)
