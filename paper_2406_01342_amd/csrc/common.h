@@ -147,6 +147,7 @@ struct pc_plan {
   // Spreading work list.
   pc::SpreadChunk* chunks = nullptr;
   pc::FoldItem* fold = nullptr;
+  uint8_t* tile_flags = nullptr;  // [ntv * ntu]: 1 if the tile holds data
   // Fine grid band, pass-A output, split-tile partials.
   void* grid = nullptr;         // complex [nv][nu]
   void* H = nullptr;            // complex [nv][n]

@@ -6,8 +6,10 @@
 // (j / Ns) Ns R + k + r Ns (the autosorting Stockham ordering), so the result
 // is in natural order without a bit-reversal pass.  Stages: one radix-2^(p mod
 // 4) stage first (no twiddles) when p = log2 M is not a multiple of 4, then
-// radix-16 stages.  Twiddles come from a table of exp(+2 pi i t / M), t < M,
-// computed in FP64 on the host and rounded once.
+// radix-16 stages.  Twiddles exp(+2 pi i t / M) come from a two-level table
+// held in LDS: lo[t mod 64] * hi[t / 64], lo[q] = exp(2 pi i q / M) and
+// hi[q] = exp(2 pi i 64 q / M), both computed in FP64 on the host and rounded
+// once (one extra rounding per twiddle).
 #pragma once
 
 #include "common.h"
@@ -23,16 +25,21 @@ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
 // angles (multiples of pi/2) so that no multiplication by 0/1 is emitted.
 template <typename R, int N, int SIGN>
 __device__ __forceinline__ cpx<R> rot(cpx<R> v, int K) {
-  // cos / sin of 2 pi k / 16, k = 0..4 (first quadrant), exact decimal values
-  const double c16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
-                         0.38268343236508977173, 0.0};
+  // cos(2 pi q / 16) for q = 0..4 (first quadrant), as literals so that no
+  // table is materialised
+  auto c16 = [](int q) -> double {
+    return q == 0 ? 1.0
+                  : q == 1 ? 0.92387953251128675613
+                           : q == 2 ? 0.70710678118654752440
+                                    : q == 3 ? 0.38268343236508977173 : 0.0;
+  };
   const int k16 = (K * 16 / N) & 15;  // angle in units of 2 pi / 16
   if (k16 == 0) return v;
   if (k16 == 4) return SIGN > 0 ? cpx<R>{-v.y, v.x} : cpx<R>{v.y, -v.x};
   if (k16 == 8) return {-v.x, -v.y};
   if (k16 == 12) return SIGN > 0 ? cpx<R>{v.y, -v.x} : cpx<R>{-v.y, v.x};
   const int q = k16 & 3, quad = k16 >> 2;
-  R c = (R)c16[q], s = (R)c16[4 - q];
+  R c = (R)c16(q), s = (R)c16(4 - q);
   // rotate (c, s) by quad quarter turns
   for (int t = 0; t < quad; ++t) {
     R nc = -s, ns = c;
@@ -73,8 +80,31 @@ __device__ __forceinline__ void dft(cpx<R>* x) {
 constexpr int ilog2(int m) { return m <= 1 ? 0 : 1 + ilog2(m / 2); }
 constexpr int first_radix(int m) { return (ilog2(m) % 4) ? (1 << (ilog2(m) % 4)) : 16; }
 
+// Entries of the two-level twiddle table for a transform of length M.
+__host__ __device__ constexpr int tw_hi_count(int m) { return m / 64 > 1 ? m / 64 : 1; }
+__host__ __device__ constexpr int tw_count(int m) { return 64 + tw_hi_count(m); }
+
+// Copies the two-level table from global memory into LDS (all threads; ends
+// with a barrier).
+template <typename R, int M, int NT>
+__device__ __forceinline__ void load_twiddles(cpx<R>* lds, const cpx<R>* __restrict__ tw) {
+  for (int i = threadIdx.x; i < tw_count(M); i += NT) lds[i] = tw[i];
+  __syncthreads();
+}
+
+// LDS position of element i of the FFT buffers: one padding slot after every
+// 16 elements, so that the power-of-two strides of the Stockham stages do not
+// map all lanes of a wave onto the same banks.
+__host__ __device__ constexpr int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
+
+template <typename R, int M>
+__device__ __forceinline__ cpx<R> twiddle(const cpx<R>* tws, int t) {
+  return cmul(tws[t & 63], tws[64 + (t >> 6)]);
+}
+
 template <typename R, int RAD, int M, int NB, int NT, int SIGN, int NS>
-__device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   constexpr int NBF = M / RAD;
   constexpr int TOT = NB * NBF;
   constexpr int PER = (TOT + NT - 1) / NT;
@@ -87,11 +117,11 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* __restrict_
       const int k = j & (NS - 1);
       cpx<R> x[RAD];
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) x[r] = buf[b * M + j + r * NBF];
+      for (int r = 0; r < RAD; ++r) x[r] = buf[pidx(b * M + j + r * NBF)];
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < RAD; ++r) {
-          cpx<R> t = tw[r * k * (M / (NS * RAD))];
+          cpx<R> t = twiddle<R, M>(tw, r * k * (M / (NS * RAD)));
           if (SIGN < 0) t.y = -t.y;
           x[r] = cmul(x[r], t);
         }
@@ -110,14 +140,14 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* __restrict_
       const int k = j & (NS - 1);
       const int base = b * M + (j / NS) * NS * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) buf[base + r * NS] = y[q][r];
+      for (int r = 0; r < RAD; ++r) buf[pidx(base + r * NS)] = y[q][r];
     }
   }
   __syncthreads();
 }
 
 template <typename R, int M, int NB, int NT, int SIGN, int NS>
-__device__ __forceinline__ void fft_stages(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+__device__ __forceinline__ void fft_stages(cpx<R>* buf, const cpx<R>* tw) {
   if constexpr (NS < M) {
     constexpr int RAD = (NS == 1) ? first_radix(M) : 16;
     fft_stage<R, RAD, M, NB, NT, SIGN, NS>(buf, tw);
@@ -125,10 +155,11 @@ __device__ __forceinline__ void fft_stages(cpx<R>* buf, const cpx<R>* __restrict
   }
 }
 
-// In-place FFT of NB sequences of length M stored contiguously in LDS.
-// Must be called by all NT threads of the block; ends with a barrier.
+// In-place FFT of NB sequences of length M stored contiguously in LDS, with
+// the twiddle table `tw` in LDS (see load_twiddles).  Must be called by all
+// NT threads of the block; ends with a barrier.
 template <typename R, int M, int NB, int NT, int SIGN>
-__device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft(cpx<R>* buf, const cpx<R>* tw) {
   fft_stages<R, M, NB, NT, SIGN, 1>(buf, tw);
 }
 

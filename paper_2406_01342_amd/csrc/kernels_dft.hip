@@ -93,54 +93,76 @@ __global__ __launch_bounds__(256) void forward_sparse_kernel(
   out[out_perm ? out_perm[k] : k] = o;
 }
 
-// partial[c][p] = sum over visibility chunk c of Re(h_k exp(+2 pi i t_kp)).
-// One thread per atom; the chunk's visibilities are staged in LDS and read
-// as broadcasts.  FP32 (or FP64) accumulation within the chunk.
-constexpr int kVisChunk = 1024;
+// Restricted adjoint, lanes over visibilities: each lane holds kVPT
+// visibilities in registers; for each atom (uniform loop, scalar loads) it
+// sums Re(h_k exp(+2 pi i t_kp)) over its visibilities in R precision, the
+// wave reduces the 64 lane sums, and lane 0 writes the wave's partial to
+// partial[p][wave] (atom-major, so the final sum reads contiguously).  The
+// per-atom sum over waves is done in FP64 by a second kernel, in a fixed
+// order (bitwise reproducible).
+constexpr int kVPT = 4;
+constexpr int kAdjThreads = 256;
+constexpr int kVisChunk = kVPT * kAdjThreads;  // visibilities per workgroup
 
 template <typename R>
-__global__ __launch_bounds__(256) void adjoint_sparse_kernel(
-    int64_t L, int64_t natoms, const double* __restrict__ AB, const cpx<R>* __restrict__ vis,
-    const int32_t* __restrict__ perm, const Atom<R>* __restrict__ atoms,
-    double* __restrict__ partial) {
-  __shared__ double sA[kVisChunk], sB[kVisChunk];
-  __shared__ R sx[kVisChunk], sy[kVisChunk];
-  const int64_t k0 = (int64_t)blockIdx.x * kVisChunk;
-  const int cnt = (int)((L - k0) < kVisChunk ? (L - k0) : kVisChunk);
-  for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-    const int64_t k = k0 + q;
-    sA[q] = AB[2 * k];
-    sB[q] = AB[2 * k + 1];
-    const cpx<R> h = vis[perm ? perm[k] : k];
-    sx[q] = h.x;
-    sy[q] = h.y;
-  }
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  if (p >= natoms) return;
-  const double a = atoms[p].a, b = atoms[p].b;
-  R acc = 0;
-  for (int q = 0; q < cnt; ++q) {
-    double t = fma(sA[q], a, sB[q] * b);
-    t -= rint(t);
-    R s, c;
-    sincos_turns<R>(t, s, c);
-    acc = fma(sx[q], c, acc);
-    acc = fma(-sy[q], s, acc);
-  }
-  partial[(int64_t)blockIdx.x * natoms + p] = (double)acc;
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 template <typename R>
-__global__ void adjoint_sparse_reduce_kernel(int64_t natoms, int nchunks,
-                                             const double* __restrict__ partial,
-                                             const Atom<R>* __restrict__ atoms,
-                                             double* __restrict__ out) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= natoms) return;
+__global__ __launch_bounds__(kAdjThreads) void adjoint_sparse_kernel(
+    int64_t L, int64_t natoms, const double* __restrict__ AB, const cpx<R>* __restrict__ vis,
+    const int32_t* __restrict__ perm, const Atom<R>* __restrict__ atoms,
+    R* __restrict__ partial, int64_t nwaves) {
+  const int64_t k0 = (int64_t)blockIdx.x * kVisChunk + threadIdx.x;
+  double A[kVPT], B[kVPT];
+  R hx[kVPT], hy[kVPT];
+#pragma unroll
+  for (int i = 0; i < kVPT; ++i) {
+    const int64_t k = k0 + (int64_t)i * kAdjThreads;
+    if (k < L) {
+      A[i] = AB[2 * k];
+      B[i] = AB[2 * k + 1];
+      const cpx<R> h = vis[perm ? perm[k] : k];
+      hx[i] = h.x;
+      hy[i] = h.y;
+    } else {
+      A[i] = B[i] = 0.0;
+      hx[i] = hy[i] = R(0);
+    }
+  }
+  const int64_t wave = (int64_t)blockIdx.x * (kAdjThreads / 64) + (threadIdx.x >> 6);
+  const bool lane0 = (threadIdx.x & 63) == 0;
+  for (int64_t p = 0; p < natoms; ++p) {
+    const double a = atoms[p].a, b = atoms[p].b;
+    R acc = 0;
+#pragma unroll
+    for (int i = 0; i < kVPT; ++i) {
+      double t = fma(A[i], a, B[i] * b);
+      t -= rint(t);
+      R s, c;
+      sincos_turns<R>(t, s, c);
+      acc = fma(hx[i], c, acc);
+      acc = fma(-hy[i], s, acc);
+    }
+    acc = wave_sum<R>(acc);
+    if (lane0) partial[p * nwaves + wave] = acc;
+  }
+}
+
+// out[p] = (1/n_p) sum_w partial[p][w], FP64, one wave per atom.
+template <typename R>
+__global__ __launch_bounds__(64) void adjoint_sparse_reduce_kernel(
+    int64_t natoms, int64_t nwaves, const R* __restrict__ partial,
+    const Atom<R>* __restrict__ atoms, double* __restrict__ out) {
+  const int64_t p = blockIdx.x;
+  const R* row = partial + p * nwaves;
   double s = 0;
-  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * natoms + p];
-  out[p] = s * atoms[p].inv_n;
+  for (int64_t w = threadIdx.x; w < nwaves; w += 64) s += (double)row[w];
+  s = wave_sum<double>(s);
+  if (threadIdx.x == 0) out[p] = s * atoms[p].inv_n;
 }
 
 template <typename R>
@@ -166,23 +188,32 @@ void forward_atoms(pc_plan* p, int64_t natoms, const Atom<R>* atoms, const cpx<R
   PC_LAUNCH_CHECK("forward_sparse");
 }
 
+// Partial-sum buffer size, in doubles (the kernels store R values in it).
 int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms) {
-  return ((p->L + kVisChunk - 1) / kVisChunk) * std::max<int64_t>(natoms, 1);
+  const int64_t nwaves = ((p->L + kVisChunk - 1) / kVisChunk) * (kAdjThreads / 64);
+  return nwaves * std::max<int64_t>(natoms, 1);
 }
 
 template <typename R>
 void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                    const Atom<R>* atoms, double* partial, double* out, hipStream_t s) {
   if (natoms <= 0) return;
-  const int nchunks = (int)((p->L + kVisChunk - 1) / kVisChunk);
-  const unsigned nby = (unsigned)((natoms + 255) / 256);
-  ProfScope ps(p, s, "adjoint_sparse",
-               p->L * (16 + 2.0 * sizeof(R)) + 8.0 * nchunks * natoms, (double)p->L * natoms);
-  hipLaunchKernelGGL((adjoint_sparse_kernel<R>), dim3(nchunks, nby), dim3(256), 0, s, p->L, natoms,
-                     p->AB, vis, vis_sorted ? nullptr : p->perm, atoms, partial);
-  PC_LAUNCH_CHECK("adjoint_sparse");
-  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3(nby), dim3(256), 0, s, natoms, nchunks,
-                     partial, atoms, out);
+  const int64_t nblocks = (p->L + kVisChunk - 1) / kVisChunk;
+  const int64_t nwaves = nblocks * (kAdjThreads / 64);
+  R* part = reinterpret_cast<R*>(partial);
+  {
+    ProfScope ps(p, s, sizeof(R) == 4 ? "adjoint_sparse" : "adjoint_sparse_f64",
+                 p->L * (16 + 2.0 * sizeof(R)) + (double)sizeof(R) * nwaves * natoms,
+                 (double)p->L * natoms);
+    hipLaunchKernelGGL((adjoint_sparse_kernel<R>), dim3((unsigned)nblocks), dim3(kAdjThreads), 0, s,
+                       p->L, natoms, p->AB, vis, vis_sorted ? nullptr : p->perm, atoms, part,
+                       nwaves);
+    PC_LAUNCH_CHECK("adjoint_sparse");
+  }
+  ProfScope ps(p, s, "adjoint_sparse_reduce", (double)sizeof(R) * nwaves * natoms,
+               (double)nwaves * natoms);
+  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3((unsigned)natoms), dim3(64), 0, s,
+                     natoms, nwaves, (const R*)part, atoms, out);
   PC_LAUNCH_CHECK("adjoint_sparse_reduce");
 }
 

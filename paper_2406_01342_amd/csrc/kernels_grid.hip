@@ -43,126 +43,302 @@ __device__ __forceinline__ bool tap_local(int base, int t, int M, int wrap, int&
 }
 
 __device__ __forceinline__ int tile_base(int c, int origin, int M, int W, int wrap) {
-  int b = c - origin;
+  int b = c - origin;  // in (-M, M): both are cells of the periodic grid
   if (wrap) {
-    b = ((b % M) + M) % M;
+    if (b < 0) b += M;
     if (b > M - W) b -= M;
   }
   return b;
 }
 
+// Spreading layout: one wave per work item owns the output tile in LDS
+// (planar re/im, row stride kTile + W so that the W x W taps of one
+// visibility fall in distinct banks).  It stages 64 visibilities at a time
+// (one per lane: cell bases, value and the 2W separable kernel weights), then
+// walks them in order with its lanes mapped to the W x W taps.  Each lane
+// accumulates its tap in registers while consecutive visibilities share a
+// first cell (they are sorted by it) and adds the sum into LDS when the cell
+// changes.  No LDS atomics (whose per-lane serialisation made them the
+// bottleneck), and each cell receives its contributions in a fixed order, so
+// the result is bitwise reproducible.  Hot tiles are split across work items
+// upstream.
 template <typename R, int W>
-__global__ __launch_bounds__(256) void spread_kernel(GridGeom g, const SpreadChunk* __restrict__ chunks,
-                                                     const uint32_t* __restrict__ cell,
-                                                     const R* __restrict__ off,
-                                                     const cpx<R>* __restrict__ vals,
-                                                     const int32_t* __restrict__ perm,
-                                                     cpx<R>* __restrict__ grid,
-                                                     cpx<R>* __restrict__ partials) {
-  constexpr int S = kTile + 1;  // padded LDS row stride
-  __shared__ R sre[kTile * S];
-  __shared__ R sim[kTile * S];
-  const SpreadChunk ch = chunks[blockIdx.x];
-  for (int i = threadIdx.x; i < kTile * S; i += blockDim.x) {
-    sre[i] = R(0);
-    sim[i] = R(0);
+struct SpreadCfg {
+  static constexpr int NW = 1;                 // waves per workgroup
+  static constexpr int S = kTile + W;          // LDS row stride
+  static constexpr int TILE = kTile * S;       // reals per plane
+  static constexpr int STG = 64 * (2 * W + 2); // staged reals
+  static constexpr int U = 8;                  // visibilities per inner step
+  static constexpr size_t lds_bytes = sizeof(R) * (2 * TILE + STG) + sizeof(int) * 128;
+};
+
+template <typename R, int W>
+__global__ __launch_bounds__(64) void spread_kernel(
+    GridGeom g, const SpreadChunk* __restrict__ chunks, const uint32_t* __restrict__ cell,
+    const R* __restrict__ off, const cpx<R>* __restrict__ vals, const int32_t* __restrict__ perm,
+    cpx<R>* __restrict__ grid, cpx<R>* __restrict__ partials) {
+  using C = SpreadCfg<R, W>;
+  extern __shared__ unsigned char smem_raw[];
+  const int lane = threadIdx.x;
+  R* tre = reinterpret_cast<R*>(smem_raw);
+  R* tim = tre + C::TILE;
+  R* stg = tim + C::TILE;                             // [64][2W + 2]: ku, kv, re, im
+  int* sbase = reinterpret_cast<int*>(stg + C::STG);  // [64][2]: bu, bv
+  for (int i = lane; i < C::TILE; i += 64) {
+    tre[i] = R(0);
+    tim[i] = R(0);
   }
-  __syncthreads();
+  const SpreadChunk ch = chunks[blockIdx.x];
   const int tv = ch.tile / g.ntu, tu = ch.tile - tv * g.ntu;
   const int ov = g.v0 + tv * kTile, ou = g.u0 + tu * kTile;
   const R inv = R(2) / R(W);
   const R beta = sizeof(R) == 4 ? (R)g.beta : (R)g.beta64;
+  // cumulative range boundaries (named scalars: no dynamic indexing, so no
+  // private-memory spill)
+  const int c1 = ch.end[0] - ch.beg[0];
+  const int c2 = c1 + ch.end[1] - ch.beg[1];
+  const int c3 = c2 + ch.end[2] - ch.beg[2];
+  const int total = c3 + ch.end[3] - ch.beg[3];
+  const int b0 = ch.beg[0], b1 = ch.beg[1] - c1, b2 = ch.beg[2] - c2, b3 = ch.beg[3] - c3;
+  constexpr int NPASS = (W * W + 63) / 64;
+  constexpr int U = C::U;
+  // The global loads of the next batch are issued before the current batch's
+  // tap loop, so their latency overlaps the LDS work.
+  uint32_t nc = 0;
+  R nsu = 0, nsv = 0;
+  cpx<R> nval = {R(0), R(0)};
+  auto fetch = [&](int base) {
+    const int q = base + lane;
+    if (q < total) {
+      const int s = q + (q < c1 ? b0 : q < c2 ? b1 : q < c3 ? b2 : b3);
+      nc = cell[s];
+      nsu = off[2 * s];
+      nsv = off[2 * s + 1];
+      nval = perm ? vals[perm[s]] : vals[s];
+    }
+  };
+  fetch(0);
+  // Visibilities arrive sorted by first cell, so runs sharing a footprint are
+  // summed per tap in registers and written to LDS once per run (a plain
+  // read-add-write: the lanes of one instruction address distinct cells and
+  // a wave's LDS operations complete in order).
+  int cbu = -(1 << 20), cbv = -(1 << 20);
+  R accr[NPASS], acci[NPASS];
+#pragma unroll
+  for (int ps = 0; ps < NPASS; ++ps) accr[ps] = acci[ps] = R(0);
+  auto flush = [&]() {
+#pragma unroll
+    for (int ps = 0; ps < NPASS; ++ps) {
+      const int tap = lane + 64 * ps;
+      const int a = tap / W, b = tap - (tap / W) * W;
+      int y, x;
+      if (tap < W * W && tap_local(cbv, a, g.M, g.wrap, y) && tap_local(cbu, b, g.M, g.wrap, x)) {
+        tre[y * C::S + x] += accr[ps];
+        tim[y * C::S + x] += acci[ps];
+      }
+      accr[ps] = R(0);
+      acci[ps] = R(0);
+    }
+  };
 #pragma unroll 1
-  for (int r = 0; r < 4; ++r) {
-#pragma unroll 1
-    for (int s = ch.beg[r] + (int)threadIdx.x; s < ch.end[r]; s += blockDim.x) {
-      const uint32_t c = cell[s];
-      const int bu = tile_base((int)(c & 0xffffu), ou, g.M, W, g.wrap);
-      const int bv = tile_base((int)(c >> 16), ov, g.M, W, g.wrap);
-      const R su = off[2 * s], sv = off[2 * s + 1];
-      const cpx<R> val = perm ? vals[perm[s]] : vals[s];
-      R ku[W], kv[W];
+  for (int base = 0; base < total; base += 64) {
+    // stage one visibility per lane; lanes past the end stage a visibility
+    // whose taps all fall outside the tile
+    const int q = base + lane;
+    R* my = stg + lane * (2 * W + 2);
+    sbase[2 * lane] = -(1 << 20);  // below -M - W: never maps into a tile
+    sbase[2 * lane + 1] = -(1 << 20);
+    if (q < total) {
+      sbase[2 * lane] = tile_base((int)(nc & 0xffffu), ou, g.M, W, g.wrap);
+      sbase[2 * lane + 1] = tile_base((int)(nc >> 16), ov, g.M, W, g.wrap);
 #pragma unroll
       for (int t = 0; t < W; ++t) {
-        ku[t] = es_kernel<R>((su + R(t)) * inv, beta);
-        kv[t] = es_kernel<R>((sv + R(t)) * inv, beta);
+        my[t] = es_kernel<R>((nsu + R(t)) * inv, beta);
+        my[W + t] = es_kernel<R>((nsv + R(t)) * inv, beta);
+      }
+      my[2 * W] = nval.x;
+      my[2 * W + 1] = nval.y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    fetch(base + 64);
+    const int nb = total - base < 64 ? total - base : 64;
+#pragma unroll 1
+    for (int v0 = 0; v0 < nb; v0 += U) {
+      int bu[U], bv[U];
+      R vr[U], vi[U], wg[U][NPASS];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {  // issue all LDS reads of the step first
+        const R* kw = stg + (v0 + u) * (2 * W + 2);
+        bu[u] = sbase[2 * (v0 + u)];
+        bv[u] = sbase[2 * (v0 + u) + 1];
+        vr[u] = kw[2 * W];
+        vi[u] = kw[2 * W + 1];
+#pragma unroll
+        for (int ps = 0; ps < NPASS; ++ps) {
+          // unconditional reads at clamped indices (lanes past the W x W taps
+          // get a zero weight), so all reads of the step issue back to back
+          const int tap = lane + 64 * ps;
+          const int a = tap / W, b = tap - (tap / W) * W;
+          const int ac = a < W ? a : W - 1;
+          const R live = tap < W * W ? R(1) : R(0);
+          wg[u][ps] = kw[W + ac] * kw[b] * live;
+        }
       }
 #pragma unroll
-      for (int a = 0; a < W; ++a) {
-        int y;
-        if (!tap_local(bv, a, g.M, g.wrap, y)) continue;
-        const R wr = val.x * kv[a], wi = val.y * kv[a];
+      for (int u = 0; u < U; ++u) {
+        if (bu[u] != cbu || bv[u] != cbv) {  // same for every lane of the wave
+          flush();
+          cbu = bu[u];
+          cbv = bv[u];
+        }
 #pragma unroll
-        for (int b = 0; b < W; ++b) {
-          int x;
-          if (!tap_local(bu, b, g.M, g.wrap, x)) continue;
-          atomicAdd(&sre[y * S + x], wr * ku[b]);
-          atomicAdd(&sim[y * S + x], wi * ku[b]);
+        for (int ps = 0; ps < NPASS; ++ps) {
+          accr[ps] = fma(wg[u][ps], vr[u], accr[ps]);
+          acci[ps] = fma(wg[u][ps], vi[u], acci[ps]);
         }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  __syncthreads();
+  flush();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  cpx<R>* dst;
+  size_t stride;
   if (ch.slot < 0) {
-    cpx<R>* dst = grid + (size_t)(tv * kTile) * g.nu + tu * kTile;
-    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
-      const int y = i / kTile, x = i - y * kTile;
-      dst[(size_t)y * g.nu + x] = {sre[y * S + x], sim[y * S + x]};
-    }
+    dst = grid + (size_t)(tv * kTile) * g.nu + tu * kTile;
+    stride = g.nu;
   } else {
-    cpx<R>* dst = partials + (size_t)ch.slot * kTile * kTile;
-    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
-      const int y = i / kTile, x = i - y * kTile;
-      dst[i] = {sre[y * S + x], sim[y * S + x]};
-    }
+    dst = partials + (size_t)ch.slot * kTile * kTile;
+    stride = kTile;
+  }
+  for (int i = lane; i < kTile * kTile; i += 64) {
+    const int y = i / kTile, x = i - y * kTile;
+    dst[(size_t)y * stride + x] = {tre[y * C::S + x], tim[y * C::S + x]};
   }
 }
 
+// Fold of a split tile: 64 cells per workgroup, kFoldSub threads per cell
+// each summing every kFoldSub-th partial (several loads in flight), then the
+// sub-sums are added in a fixed order (bitwise reproducible).
+constexpr int kFoldSub = 8;
+
 template <typename R>
-__global__ __launch_bounds__(256) void fold_kernel(GridGeom g, const FoldItem* __restrict__ items,
-                                                   const cpx<R>* __restrict__ partials,
-                                                   cpx<R>* __restrict__ grid) {
+__global__ __launch_bounds__(64 * kFoldSub) void fold_kernel(GridGeom g,
+                                                           const FoldItem* __restrict__ items,
+                                                           const cpx<R>* __restrict__ partials,
+                                                           cpx<R>* __restrict__ grid) {
+  __shared__ R sx[kFoldSub][64], sy[kFoldSub][64];
   const FoldItem it = items[blockIdx.x];
-  const int tv = it.tile / g.ntu, tu = it.tile - tv * g.ntu;
-  cpx<R>* dst = grid + (size_t)(tv * kTile) * g.nu + tu * kTile;
-  for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
-    R ax = 0, ay = 0;
-    for (int q = 0; q < it.count; ++q) {
-      const cpx<R> v = partials[(size_t)(it.first + q) * kTile * kTile + i];
-      ax += v.x;
-      ay += v.y;
+  const int c = threadIdx.x & 63, sub = threadIdx.x >> 6;
+  const int i = blockIdx.y * 64 + c;
+  const cpx<R>* src = partials + (size_t)it.first * kTile * kTile + i;
+  R ax = 0, ay = 0;
+  int q = sub;
+  for (; q + 3 * kFoldSub < it.count; q += 4 * kFoldSub) {
+    cpx<R> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = src[(size_t)(q + u * kFoldSub) * kTile * kTile];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ax += v[u].x;
+      ay += v[u].y;
     }
+  }
+  for (; q < it.count; q += kFoldSub) {
+    const cpx<R> v = src[(size_t)q * kTile * kTile];
+    ax += v.x;
+    ay += v.y;
+  }
+  sx[sub][c] = ax;
+  sy[sub][c] = ay;
+  __syncthreads();
+  if (sub == 0) {
+    R tx = 0, ty = 0;
+#pragma unroll
+    for (int k = 0; k < kFoldSub; ++k) {
+      tx += sx[k][c];
+      ty += sy[k][c];
+    }
+    const int tv = it.tile / g.ntu, tu = it.tile - tv * g.ntu;
+    cpx<R>* dst = grid + (size_t)(tv * kTile) * g.nu + tu * kTile;
     const int y = i / kTile, x = i - y * kTile;
-    dst[(size_t)y * g.nu + x] = {ax, ay};
+    dst[(size_t)y * g.nu + x] = {tx, ty};
+  }
+}
+
+// Pass-A output layout: columns grouped in blocks of kHB, each block stored
+// row-major over the band rows, so that a pass-B workgroup reading kHB (or
+// fewer) adjacent columns reads one contiguous stretch.
+constexpr int kHB = 8;
+__device__ __forceinline__ size_t h_index(int row, int col, int nv) {
+  return ((size_t)(col / kHB) * nv + row) * kHB + (col % kHB);
+}
+
+// Fills the padded LDS buffer from global memory: element idx (< TOTAL) goes
+// to buf[pidx(lpos(idx))] and is src[addr(idx)], or zero when addr returns a
+// negative value.  Every load of the thread is issued before any result is
+// used (masked elements read a fixed valid address and are zeroed by a
+// select), so the loads are in flight together instead of one round trip per
+// element.
+template <typename R, int TOTAL, int NT, typename A, typename P>
+__device__ __forceinline__ void gather_to_lds(cpx<R>* buf, const cpx<R>* __restrict__ src,
+                                              A addr, P lpos) {
+  constexpr int IT = (TOTAL + NT - 1) / NT;
+  cpx<R> t[IT];
+  int64_t a[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = (int)threadIdx.x + it * NT;
+    a[it] = (TOTAL % NT == 0 || idx < TOTAL) ? addr(idx) : -1;
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) t[it] = src[a[it] >= 0 ? a[it] : 0];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = (int)threadIdx.x + it * NT;
+    if (TOTAL % NT == 0 || idx < TOTAL)
+      buf[pidx(lpos(idx))] = a[it] >= 0 ? t[it] : cpx<R>{R(0), R(0)};
   }
 }
 
 // Pass A of the adjoint: rows of the band grid (fixed v), FFT along u.
 template <typename R, int M, int NB, int NT>
 __global__ __launch_bounds__(NT) void passA_adj_kernel(GridGeom g, const cpx<R>* __restrict__ grid,
+                                                        const uint8_t* __restrict__ tile_flags,
                                                         cpx<R>* __restrict__ H,
                                                         const cpx<R>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  __shared__ cpx<R> tws[tw_count(M)];
+  load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
   const int row0 = blockIdx.x * NB;
-  for (int idx = threadIdx.x; idx < NB * M; idx += NT) {
-    const int b = idx / M, m = idx - b * M;
-    const int row = row0 + b;
-    cpx<R> v = {R(0), R(0)};
-    const int rel = m - g.u0;
-    if (row < g.nv && (unsigned)rel < (unsigned)g.nu) v = grid[(size_t)row * g.nu + rel];
-    buf[idx] = v;
-  }
+  // tiles without data were never written: read them as zeros
+  gather_to_lds<R, NB * M, NT>(
+      buf, grid,
+      [&](int idx) -> int64_t {
+        const int b = idx / M, m = idx - b * M;
+        const int row = row0 + b, rel = m - g.u0;
+        if (row >= g.nv || (unsigned)rel >= (unsigned)g.nu) return -1;
+        if (!tile_flags[(row / kTile) * g.ntu + rel / kTile]) return -1;
+        return (int64_t)row * g.nu + rel;
+      },
+      [](int idx) { return idx; });
   __syncthreads();
-  lds_fft<R, M, NB, NT, +1>(buf, tw);
+  lds_fft<R, M, NB, NT, +1>(buf, tws);
   for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
     const int b = idx / n, i = idx - b * n;
     const int row = row0 + b;
     if (row < g.nv) {
       int f = i - n / 2;
       if (f < 0) f += M;
-      H[(size_t)row * n + i] = buf[b * M + f];
+      H[h_index(row, i, g.nv)] = buf[pidx(b * M + f)];
     }
   }
 }
@@ -181,17 +357,23 @@ __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>*
                                                         unsigned long long* __restrict__ maxkey) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  __shared__ cpx<R> tws[tw_count(M)];
+  load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
   const int i0 = blockIdx.x * NB;
-  for (int idx = threadIdx.x; idx < NB * M; idx += NT) {
-    const int m = idx / NB, b = idx - m * NB;
-    const int rel = m - g.v0;
-    cpx<R> v = {R(0), R(0)};
-    if ((unsigned)rel < (unsigned)g.nv) v = H[(size_t)rel * n + i0 + b];
-    buf[b * M + m] = v;
-  }
+  gather_to_lds<R, NB * M, NT>(
+      buf, H,
+      [&](int idx) -> int64_t {
+        const int m = idx / NB, b = idx - m * NB;
+        const int rel = m - g.v0;
+        return (unsigned)rel < (unsigned)g.nv ? (int64_t)h_index(rel, i0 + b, g.nv) : -1;
+      },
+      [](int idx) {
+        const int m = idx / NB, b = idx - m * NB;
+        return b * M + m;
+      });
   __syncthreads();
-  lds_fft<R, M, NB, NT, +1>(buf, tw);
+  lds_fft<R, M, NB, NT, +1>(buf, tws);
   unsigned long long best = 0;
   const R dl = (R)g.dl;
   for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
@@ -201,7 +383,7 @@ __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>*
     if (f < 0) f += M;
     const R l = (R)(i - n / 2) * dl, mm = (R)(j - n / 2) * dl;
     const R nn = sqrt(R(1) - l * l - mm * mm);
-    const R val = buf[b * M + f].x * corr[i] * corr[j] * scale / nn;
+    const R val = buf[pidx(b * M + f)].x * corr[i] * corr[j] * scale / nn;
     image[(size_t)i * n + j] = val;
     const unsigned long long key = max_key((float)fabs(val), i * n + j);
     best = key > best ? key : best;
@@ -231,6 +413,8 @@ __global__ __launch_bounds__(NT) void passB_fwd_kernel(GridGeom g, const R* __re
                                                         const R* __restrict__ corr) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  __shared__ cpx<R> tws[tw_count(M)];
+  load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
   const int i0 = blockIdx.x * NB;
   const R dl = (R)g.dl;
@@ -244,14 +428,14 @@ __global__ __launch_bounds__(NT) void passB_fwd_kernel(GridGeom g, const R* __re
       const R nn = sqrt(R(1) - l * l - mm * mm);
       v.x = image[(size_t)i * n + j] * corr[i] * corr[j] / nn;
     }
-    buf[idx] = v;
+    buf[pidx(idx)] = v;
   }
   __syncthreads();
-  lds_fft<R, M, NB, NT, -1>(buf, tw);
+  lds_fft<R, M, NB, NT, -1>(buf, tws);
   for (int idx = threadIdx.x; idx < NB * g.nv; idx += NT) {
     const int rel = idx / NB, b = idx - rel * NB;
     int m = g.v0 + rel;
-    H[(size_t)rel * n + i0 + b] = buf[b * M + m];
+    H[h_index(rel, i0 + b, g.nv)] = buf[pidx(b * M + m)];
   }
 }
 
@@ -263,22 +447,26 @@ __global__ __launch_bounds__(NT) void passA_fwd_kernel(GridGeom g, const cpx<R>*
                                                         const cpx<R>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  __shared__ cpx<R> tws[tw_count(M)];
+  load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
   const int row0 = blockIdx.x * NB;
-  for (int idx = threadIdx.x; idx < NB * M; idx += NT) {
-    const int b = idx / M, m = idx - b * M;
-    const int row = row0 + b;
-    int f = m < n / 2 ? m : m - M;
-    cpx<R> v = {R(0), R(0)};
-    if (row < g.nv && f >= -n / 2 && f < n / 2) v = H[(size_t)row * n + f + n / 2];
-    buf[idx] = v;
-  }
+  gather_to_lds<R, NB * M, NT>(
+      buf, H,
+      [&](int idx) -> int64_t {
+        const int b = idx / M, m = idx - b * M;
+        const int row = row0 + b;
+        const int f = m < n / 2 ? m : m - M;
+        if (row >= g.nv || f < -n / 2 || f >= n / 2) return -1;
+        return (int64_t)h_index(row, f + n / 2, g.nv);
+      },
+      [](int idx) { return idx; });
   __syncthreads();
-  lds_fft<R, M, NB, NT, -1>(buf, tw);
+  lds_fft<R, M, NB, NT, -1>(buf, tws);
   for (int idx = threadIdx.x; idx < NB * g.nu; idx += NT) {
     const int b = idx / g.nu, rel = idx - b * g.nu;
     const int row = row0 + b;
-    if (row < g.nv) grid[(size_t)row * g.nu + rel] = buf[b * M + g.u0 + rel];
+    if (row < g.nv) grid[(size_t)row * g.nu + rel] = buf[pidx(b * M + g.u0 + rel)];
   }
 }
 
@@ -297,15 +485,15 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
   const R su = off[2 * s], sv = off[2 * s + 1];
   const R inv = R(2) / R(W);
   const R beta = sizeof(R) == 4 ? (R)g.beta : (R)g.beta64;
-  R ku[W], kv[W];
+  R ku[W];
 #pragma unroll
-  for (int t = 0; t < W; ++t) {
-    ku[t] = es_kernel<R>((su + R(t)) * inv, beta);
-    kv[t] = es_kernel<R>((sv + R(t)) * inv, beta);
-  }
+  for (int t = 0; t < W; ++t) ku[t] = es_kernel<R>((su + R(t)) * inv, beta);
   R ax = 0, ay = 0;
-#pragma unroll
+  // rows: not fully unrolled (W^2 loads in flight would exhaust registers for
+  // wide kernels); the row weight is evaluated in the loop
+#pragma unroll 2
   for (int a = 0; a < W; ++a) {
+    const R kva = es_kernel<R>((sv + R(a)) * inv, beta);
     int y = cv + a - g.v0;
     if (g.wrap && y >= g.M) y -= g.M;
     R rx = 0, ry = 0;
@@ -317,8 +505,8 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
       rx += v.x * ku[b];
       ry += v.y * ku[b];
     }
-    ax += rx * kv[a];
-    ay += ry * kv[a];
+    ax += rx * kva;
+    ay += ry * kva;
   }
   const int64_t d = perm ? perm[s] : s;
   out[d] = {ax, ay};
@@ -332,8 +520,14 @@ __global__ void maxkey_reset_kernel(unsigned long long* k) { *k = 0ull; }
 template <typename R, int W>
 static void launch_spread_w(pc_plan* p, const cpx<R>* vals, const int32_t* perm, hipStream_t s) {
   const double rb = sizeof(R);
+  using C = SpreadCfg<R, W>;
+  static_assert(C::lds_bytes <= 160 * 1024, "spread LDS budget");
+  if (C::lds_bytes > 64 * 1024)
+    PC_HIP(hipFuncSetAttribute((const void*)spread_kernel<R, W>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds_bytes));
   ProfScope ps(p, s, "spread", p->L * (4 + 4 * rb) + 2 * rb * p->g.nu * p->g.nv, (double)p->L);
-  hipLaunchKernelGGL((spread_kernel<R, W>), dim3((unsigned)p->n_chunks), dim3(256), 0, s, p->g,
+  hipLaunchKernelGGL((spread_kernel<R, W>), dim3((unsigned)p->n_chunks), dim3(C::NW * 64),
+                     C::lds_bytes, s, p->g,
                      p->chunks, p->cell, (const R*)p->off, vals, perm, (cpx<R>*)p->grid,
                      (cpx<R>*)p->partials);
   PC_LAUNCH_CHECK("spread");
@@ -355,7 +549,8 @@ static void launch_spread(pc_plan* p, const cpx<R>* vals, const int32_t* perm, h
   if (p->n_fold > 0) {
     const double tb = 2.0 * sizeof(R) * kTile * kTile;
     ProfScope ps(p, s, "fold", tb * (p->n_partials + p->n_fold), (double)p->n_partials);
-    hipLaunchKernelGGL((fold_kernel<R>), dim3((unsigned)p->n_fold), dim3(256), 0, s, p->g, p->fold,
+    hipLaunchKernelGGL((fold_kernel<R>), dim3((unsigned)p->n_fold, kTile * kTile / 64),
+                       dim3(64 * kFoldSub), 0, s, p->g, p->fold,
                        (const cpx<R>*)p->partials, (cpx<R>*)p->grid);
     PC_LAUNCH_CHECK("fold");
   }
@@ -423,13 +618,14 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s) {
   constexpr int NBB = nb_passB<R, M>();
   constexpr int NTB = nt_for<NBB * M / 16>();
   const GridGeom& g = p->g;
-  const size_t lda = (size_t)NBA * M * CB, ldb = (size_t)NBB * M * CB;
+  const size_t lda = (size_t)padded(NBA * M) * CB, ldb = (size_t)padded(NBB * M) * CB;
   const double nvn = (double)g.nv * g.n * CB;
   set_lds((const void*)passA_adj_kernel<R, M, NBA, NTA>, lda);
   {
     ProfScope ps(p, s, "passA_adj", (double)g.nv * g.nu * CB + nvn, (double)g.nv * M);
     hipLaunchKernelGGL((passA_adj_kernel<R, M, NBA, NTA>), dim3((g.nv + NBA - 1) / NBA), dim3(NTA),
-                       lda, s, g, (const cpx<R>*)p->grid, (cpx<R>*)p->H, (const cpx<R>*)p->twiddle);
+                       lda, s, g, (const cpx<R>*)p->grid, p->tile_flags, (cpx<R>*)p->H,
+                       (const cpx<R>*)p->twiddle);
     PC_LAUNCH_CHECK("passA_adj");
   }
   set_lds((const void*)passB_adj_kernel<R, M, NBB, NTB>, ldb);
@@ -448,7 +644,7 @@ static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s) {
   constexpr int NBB = nb_passB<R, M>();
   constexpr int NTB = nt_for<NBB * M / 16>();
   const GridGeom& g = p->g;
-  const size_t lda = (size_t)NBA * M * CB, ldb = (size_t)NBB * M * CB;
+  const size_t lda = (size_t)padded(NBA * M) * CB, ldb = (size_t)padded(NBB * M) * CB;
   const double nvn = (double)g.nv * g.n * CB;
   set_lds((const void*)passB_fwd_kernel<R, M, NBB, NTB>, ldb);
   {

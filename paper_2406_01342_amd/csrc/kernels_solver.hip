@@ -44,16 +44,29 @@ __global__ __launch_bounds__(256) void resid_partial_kernel(int64_t L, const c32
   }
 }
 
-__global__ void resid_final_kernel(int nblocks, const double* __restrict__ partial,
-                                   double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double a = 0, b = 0;
-    for (int i = 0; i < nblocks; ++i) {
-      a += partial[2 * i];
-      b += partial[2 * i + 1];
+// Sum of the block partials by one workgroup in a fixed order.
+__global__ __launch_bounds__(256) void resid_final_kernel(int nblocks,
+                                                          const double* __restrict__ partial,
+                                                          double* __restrict__ out) {
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) {
+    a += partial[2 * i];
+    b += partial[2 * i + 1];
+  }
+  __shared__ double sa[256], sb[256];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
     }
-    out[0] = a;
-    out[1] = b;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sa[0];
+    out[1] = sb[0];
   }
 }
 
@@ -201,7 +214,7 @@ void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial,
   const int nb = k_resid_blocks(L);
   hipLaunchKernelGGL(resid_partial_kernel, dim3(nb), dim3(256), 0, s, L, r, V, partial);
   PC_LAUNCH_CHECK("resid_partial");
-  hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(64), 0, s, nb, partial, out);
+  hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(256), 0, s, nb, partial, out);
   PC_LAUNCH_CHECK("resid_final");
 }
 

@@ -75,10 +75,14 @@ struct Layout {
   std::vector<double> off;              // sorted, interleaved (s_u, s_v)
   std::vector<SpreadChunk> chunks;
   std::vector<FoldItem> fold;
+  std::vector<uint8_t> tile_flags;      // 1 if any footprint reaches the tile
   int64_t n_partials = 0;
 };
 
 static double kernel_beta(int W) { return 2.30 * W; }
+
+// Entries of the FFT's two-level twiddle table (matches the kernels' layout).
+static int twiddle_entries(int M) { return 64 + std::max(1, M / 64); }
 
 static int kernel_width(double eps) {
   if (!(eps > 0)) eps = 1e-5;
@@ -190,7 +194,21 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     c0u[k] = cu;
     c0v[k] = cv;
   }
-  // Stable counting sort by key.
+  // Sort by (tile, spill class, first cell within the tile): a stable counting
+  // sort on the tile-local cell, then a stable counting sort on (tile, class).
+  // Visibilities sharing a first cell end up adjacent, which the spreading
+  // kernel exploits by accumulating them in registers.
+  std::vector<int32_t> order(L);
+  {
+    const int TT = T * T;
+    std::vector<int64_t> c(TT + 1, 0);
+    auto local = [&](int64_t k) {
+      return ((c0v[k] - g.v0) % T) * T + ((c0u[k] - g.u0) % T);
+    };
+    for (int64_t k = 0; k < L; ++k) c[local(k) + 1]++;
+    for (int i = 0; i < TT; ++i) c[i + 1] += c[i];
+    for (int64_t k = 0; k < L; ++k) order[c[local(k)]++] = (int32_t)k;
+  }
   std::vector<int64_t> cnt(ntiles * 4 + 1, 0);
   for (int64_t k = 0; k < L; ++k) cnt[key[k] + 1]++;
   for (int64_t i = 0; i < ntiles * 4; ++i) cnt[i + 1] += cnt[i];
@@ -198,7 +216,10 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
   lay.perm.resize(L);
   {
     std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int64_t k = 0; k < L; ++k) lay.perm[pos[key[k]]++] = (int32_t)k;
+    for (int64_t i = 0; i < L; ++i) {
+      const int32_t k = order[i];
+      lay.perm[pos[key[k]]++] = k;
+    }
   }
   if (full) {
     lay.AB.resize(2 * L);
@@ -214,7 +235,7 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     }
   }
   // Work list.  Split tiles whose gathered count exceeds kChunk.
-  const int64_t kChunk = 2048;
+  const int64_t kChunk = 256;
   auto tid = [&](int tv, int tu) -> int64_t {
     if (g.wrap) {
       tv = (tv + ntv) % ntv;
@@ -225,6 +246,7 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     return (int64_t)tv * ntu + tu;
   };
   auto cls_beg = [&](int64_t t, int c) { return bstart[t * 4 + c]; };
+  lay.tile_flags.assign(ntiles, 0);
   for (int tv = 0; tv < ntv; ++tv)
     for (int tu = 0; tu < ntu; ++tu) {
       const int64_t t = (int64_t)tv * ntu + tu;
@@ -246,6 +268,10 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
       }
       int64_t total = 0;
       for (int r = 0; r < 4; ++r) total += re[r] - rb[r];
+      // Tiles no footprint reaches get no work item and are never written;
+      // the first FFT pass reads them as zeros from the occupancy flags.
+      lay.tile_flags[t] = total > 0 ? 1 : 0;
+      if (total == 0) continue;
       const int64_t nch = std::max<int64_t>(1, (total + kChunk - 1) / kChunk);
       if (nch == 1) {
         SpreadChunk c{};
@@ -281,6 +307,15 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
       }
       lay.n_partials += nch;
     }
+  // Longest work items first: the dense uv core's items start before the
+  // many short ones, which then fill in around them (greedy longest-first).
+  auto work = [](const SpreadChunk& c) {
+    int64_t w = 0;
+    for (int r = 0; r < 4; ++r) w += c.end[r] - c.beg[r];
+    return w;
+  };
+  std::stable_sort(lay.chunks.begin(), lay.chunks.end(),
+                   [&](const SpreadChunk& a, const SpreadChunk& b) { return work(a) > work(b); });
   return lay;
 }
 
@@ -347,10 +382,11 @@ static size_t layout_bytes(const Layout& lay, int prec) {
   add(lay.L * 2 * rb);                       // off
   add(lay.chunks.size() * sizeof(SpreadChunk));
   add(lay.fold.size() * sizeof(FoldItem));
+  add(lay.tile_flags.size());
   add((size_t)g.nu * g.nv * cb);             // grid band
   add((size_t)g.nv * g.n * cb);              // H
   add((size_t)lay.n_partials * kTile * kTile * cb);
-  add((size_t)g.M * cb);                     // twiddles
+  add((size_t)twiddle_entries(g.M) * cb);    // twiddles
   add((size_t)g.n * rb);                     // correction
   add(256);                                  // max key
   add(lay.L * cb);                           // vis scratch
@@ -393,10 +429,11 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     p->off = dalloc(p, L * 2 * rb);
     p->chunks = (SpreadChunk*)dalloc(p, lay.chunks.size() * sizeof(SpreadChunk));
     p->fold = (FoldItem*)dalloc(p, lay.fold.size() * sizeof(FoldItem));
+    p->tile_flags = (uint8_t*)dalloc(p, lay.tile_flags.size());
     p->grid = dalloc(p, (size_t)g.nu * g.nv * cb);
     p->H = dalloc(p, (size_t)g.nv * g.n * cb);
     p->partials = dalloc(p, (size_t)lay.n_partials * kTile * kTile * cb);
-    p->twiddle = dalloc(p, (size_t)g.M * cb);
+    p->twiddle = dalloc(p, (size_t)twiddle_entries(g.M) * cb);
     p->corr = dalloc(p, (size_t)g.n * rb);
     p->maxkey = (unsigned long long*)dalloc(p, 256);
     p->vis_scratch = dalloc(p, L * cb);
@@ -416,28 +453,33 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     if (!lay.chunks.empty())
       PC_HIP(hipMemcpyAsync(p->chunks, lay.chunks.data(), lay.chunks.size() * sizeof(SpreadChunk),
                             hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(p->tile_flags, lay.tile_flags.data(), lay.tile_flags.size(),
+                          hipMemcpyHostToDevice, s));
     if (!lay.fold.empty())
       PC_HIP(hipMemcpyAsync(p->fold, lay.fold.data(), lay.fold.size() * sizeof(FoldItem),
                             hipMemcpyHostToDevice, s));
-    // Twiddles exp(+2 pi i t / M), computed in FP64 and rounded once.
-    std::vector<double> tw64(2 * (size_t)g.M);
-    for (int t = 0; t < g.M; ++t) {
-      // exact symmetric evaluation: reduce t to the first octant
-      const double ang = 2.0 * M_PI * (double)t / g.M;
-      tw64[2 * t] = std::cos(ang);
-      tw64[2 * t + 1] = std::sin(ang);
+    // Two-level twiddle table for exp(+2 pi i t / M): lo[q] = exp(2 pi i q / M),
+    // q < 64, then hi[j] = exp(2 pi i 64 j / M), j < max(1, M / 64); FP64,
+    // rounded once.
+    const int ntw = twiddle_entries(g.M);
+    std::vector<double> tw64(2 * (size_t)ntw);
+    for (int q = 0; q < ntw; ++q) {
+      const double t = q < 64 ? (double)q : 64.0 * (q - 64);
+      const double ang = 2.0 * M_PI * t / g.M;
+      tw64[2 * q] = std::cos(ang);
+      tw64[2 * q + 1] = std::sin(ang);
     }
     std::vector<double> corr64 = correction_table(g);
     std::vector<float> tw32, corr32;
     if (f64) {
-      PC_HIP(hipMemcpyAsync(p->twiddle, tw64.data(), g.M * 16, hipMemcpyHostToDevice, s));
+      PC_HIP(hipMemcpyAsync(p->twiddle, tw64.data(), ntw * 16, hipMemcpyHostToDevice, s));
       PC_HIP(hipMemcpyAsync(p->corr, corr64.data(), g.n * 8, hipMemcpyHostToDevice, s));
     } else {
-      tw32.resize(2 * (size_t)g.M);
+      tw32.resize(2 * (size_t)ntw);
       for (size_t i = 0; i < tw32.size(); ++i) tw32[i] = (float)tw64[i];
       corr32.resize(g.n);
       for (int i = 0; i < g.n; ++i) corr32[i] = (float)corr64[i];
-      PC_HIP(hipMemcpyAsync(p->twiddle, tw32.data(), g.M * 8, hipMemcpyHostToDevice, s));
+      PC_HIP(hipMemcpyAsync(p->twiddle, tw32.data(), ntw * 8, hipMemcpyHostToDevice, s));
       PC_HIP(hipMemcpyAsync(p->corr, corr32.data(), g.n * 4, hipMemcpyHostToDevice, s));
     }
     PC_HIP(hipEventCreate(&p->ev_a));

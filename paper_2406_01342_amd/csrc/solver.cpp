@@ -47,8 +47,10 @@ struct DevArray {
 };
 
 constexpr int kCheck = 4;        // APGD convergence test cadence
-constexpr int kPowerIters = 30;  // power iterations per active set
-constexpr double kLipMargin = 1.01;
+constexpr int kPowerIters = 30;    // power iteration cap per active set
+constexpr int kPowerCheck = 3;     // convergence test cadence
+constexpr double kPowerTol = 1e-4; // relative change of the estimate
+constexpr double kLipMargin = 1.02;
 
 struct Pfw {
   pc_plan* p;
@@ -63,6 +65,8 @@ struct Pfw {
   DevArray<double> x, y, g, v, adj_partial, red_partial, scal;
   std::vector<int32_t> S;
   std::vector<double> xs;
+  std::vector<int32_t> pv_set;  // last power-iteration eigenvector (warm start)
+  std::vector<double> pv_val;
   double lam = 0, lmax = 0, Delta = 0, eta_inf = 0, P_prev = 0, P = 0, rel_gap = 0, gap = 0;
   int64_t eta_argmax = -1;
   int k = 0, inner_total = 0;
@@ -156,15 +160,44 @@ struct Pfw {
     }
   }
 
-  double power_iteration(int64_t nS) {
-    k_power_init(p, nS, v.ptr, atoms.ptr, s);
-    for (int it = 0; it < kPowerIters; ++it) {
+  // Largest eigenvalue of G_S = Re(Phi_S^H Phi_S) by power iteration on the
+  // operator pair, warm-started from the previous active set's eigenvector
+  // (new atoms enter at 1/sqrt(nS)); stops when successive estimates agree
+  // to kPowerTol (tested every kPowerCheck iterations) or after kPowerIters.
+  double power_iteration(const std::vector<int32_t>& set) {
+    const int64_t nS = (int64_t)set.size();
+    std::vector<double> v0(nS, 1.0 / std::sqrt((double)nS));
+    for (size_t a = 0, b = 0; a < pv_set.size() && b < set.size();) {
+      if (pv_set[a] == set[b]) {
+        v0[b] = pv_val[a];
+        ++a;
+        ++b;
+      } else if (pv_set[a] < set[b]) {
+        ++a;
+      } else {
+        ++b;
+      }
+    }
+    double nrm = 0;
+    for (double q : v0) nrm += q * q;
+    nrm = std::sqrt(nrm);
+    for (double& q : v0) q /= nrm;
+    PC_HIP(hipMemcpyAsync(v.ptr, v0.data(), nS * 8, hipMemcpyHostToDevice, s));
+    k_weights(p, nS, v.ptr, atoms.ptr, s);
+    double e[2] = {0, 0};
+    for (int it = 1; it <= kPowerIters; ++it) {
       forward_atoms<float>(p, nS, atoms.ptr, nullptr, true, r.ptr, true, s);
       adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, g.ptr, s);
       k_power(p, nS, g.ptr, v.ptr, atoms.ptr, scal.ptr, s);
+      if (it >= kPowerCheck && (it % kPowerCheck == 0 || it == kPowerIters)) {
+        read_scal(e, kScalEig, 2);
+        if (std::fabs(e[0] - e[1]) <= kPowerTol * e[0]) break;
+      }
     }
-    double e[2];
-    read_scal(e, kScalEig, 2);
+    pv_set = set;
+    pv_val.resize(nS);
+    PC_HIP(hipMemcpyAsync(pv_val.data(), v.ptr, nS * 8, hipMemcpyDeviceToHost, s));
+    PC_HIP(hipStreamSynchronize(s));
     return e[0];
   }
 
@@ -201,7 +234,7 @@ struct Pfw {
     // 2. APGD on the restricted problem
     int inner = 0;
     if (nS > 0) {
-      const double lip = power_iteration(nS) * kLipMargin;
+      const double lip = power_iteration(Sn) * kLipMargin;
       double hs[2] = {lip, 1.0};
       PC_HIP(hipMemcpyAsync(scal.ptr + kScalLip, hs, 2 * sizeof(double), hipMemcpyHostToDevice, s));
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
