@@ -271,6 +271,42 @@ PC_API pc_status pc_solver_step(pc_solver* solver, int32_t* done);
 PC_API pc_status pc_solver_result(pc_solver* solver, pc_solve_result* result);
 PC_API void pc_solver_destroy(pc_solver* solver);
 
+/* ---------------------------------------------------------------------------
+ * Batched serving.  Several solves run at once, each driven by its own host
+ * thread on its own stream (pc_solver_step releases nothing and takes no
+ * global lock).  Solvers attached to one batcher send their gridded adjoints
+ * (the full-grid step 4 of Alg. 2 and the dirty image at creation) through it:
+ * requests that meet while the device is busy are merged into shared
+ * launches (one spreading launch, one fold, one launch per fine-grid size and
+ * FFT pass, whatever the jobs' grid and visibility counts), and the next
+ * merged launch starts as soon as the previous one ends.  Each job's result
+ * is identical to its result alone: the shared launches run the same
+ * per-tile and per-row work as a job's own adjoint.
+ * A batcher serves one device; it outlives every solver attached to it.
+ * ------------------------------------------------------------------------- */
+typedef struct pc_batcher pc_batcher;
+
+typedef struct pc_batcher_stats {
+  int64_t batches;      /* shared launch groups issued */
+  int64_t requests;     /* adjoints served */
+  int64_t visibilities; /* sum of the served plans' visibility counts */
+  int32_t max_batch;    /* most requests merged into one group */
+  int32_t pad;
+  double seconds;       /* device time of the shared launches (HIP events) */
+} pc_batcher_stats;
+
+/* Creates a batcher on `device` with a stream of its own (default priority).
+ * Allocates its launch tables lazily. */
+PC_API pc_status pc_batcher_create(int32_t device, pc_batcher** out);
+PC_API pc_status pc_batcher_get_stats(const pc_batcher* batcher, pc_batcher_stats* stats);
+PC_API void pc_batcher_destroy(pc_batcher* batcher);
+/* pc_solver_create for a solver whose gridded adjoints go through `batcher`
+ * (NULL: same as pc_solver_create).  The plan must live on the batcher's
+ * device.  May be called concurrently from several threads. */
+PC_API pc_status pc_solver_create_batched(pc_plan* plan, const void* vis,
+                                          const pc_solve_params* params, void* stream,
+                                          pc_batcher* batcher, pc_solver** out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,11 @@ class PcKernelStat(C.Structure):
                 ("bytes", C.c_double), ("work", C.c_double)]
 
 
+class PcBatcherStats(C.Structure):
+    _fields_ = [("batches", C.c_int64), ("requests", C.c_int64), ("visibilities", C.c_int64),
+                ("max_batch", C.c_int32), ("pad", C.c_int32), ("seconds", C.c_double)]
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _PD = C.POINTER(C.c_double)
@@ -91,6 +96,11 @@ SIGNATURES = {
     "pc_solver_step": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "pc_solver_result": (C.c_int, [_P, C.POINTER(PcSolveResult)]),
     "pc_solver_destroy": (None, [_P]),
+    "pc_batcher_create": (C.c_int, [C.c_int32, C.POINTER(_P)]),
+    "pc_batcher_get_stats": (C.c_int, [_P, C.POINTER(PcBatcherStats)]),
+    "pc_batcher_destroy": (None, [_P]),
+    "pc_solver_create_batched": (C.c_int, [_P, _P, C.POINTER(PcSolveParams), _P, _P,
+                                           C.POINTER(_P)]),
     "pc_plan_profile": (C.c_int, [_P, C.c_int32]),
     "pc_plan_kernel_stat_count": (C.c_int32, [_P]),
     "pc_plan_kernel_stat": (C.c_int, [_P, C.c_int32, C.POINTER(PcKernelStat)]),

@@ -14,8 +14,8 @@ import torch
 
 from . import _lib
 from ._lib import (PC_PREC_FP32, PC_PREC_FP64, PC_UV_METRES, PC_UV_WAVELENGTHS,  # noqa: F401
-                   PcGeometry, PcKernelStat, PcPlanInfo, PcSolveParams, PcSolveResult,
-                   PolycleanError, check)
+                   PcBatcherStats, PcGeometry, PcKernelStat, PcPlanInfo, PcSolveParams,
+                   PcSolveResult, PolycleanError, check)
 
 LIB = _lib.load()
 
@@ -245,14 +245,104 @@ def pc_polyclean_solve(plan: Plan, vis: torch.Tensor, params: Optional[PcSolvePa
     st = LIB.pc_polyclean_solve(plan.handle, C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")),
                                 C.byref(params), C.byref(res), C.c_void_p(_stream(stream)))
     check(st, "pc_polyclean_solve")
+    return _result_dict(res, st, pix, wgt)
+
+
+def _result_dict(res: PcSolveResult, status: int, pix: np.ndarray, wgt: np.ndarray) -> dict:
     out = {k: getattr(res, k) for k, _ in PcSolveResult._fields_
            if k not in ("pix", "weight", "cert", "capacity")}
     out["lambda"] = out.pop("lambda_")
-    out["status"] = st
+    out["status"] = status
     na = int(res.natoms)
     out["pix"] = pix[:na].astype(np.int64)
     out["weight"] = wgt[:na].copy()
     return out
+
+
+class Batcher:
+    """Owns a pc_batcher handle: merges the gridded adjoints of solvers on
+    different threads into shared launches."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        check(LIB.pc_batcher_create(int(device), C.byref(h)), "pc_batcher_create")
+        self._h = h
+        self.device = int(device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        st = PcBatcherStats()
+        check(LIB.pc_batcher_get_stats(self._h, C.byref(st)), "pc_batcher_get_stats")
+        return {k: getattr(st, k) for k, _ in PcBatcherStats._fields_ if k != "pad"}
+
+    def close(self):
+        if self._h:
+            LIB.pc_batcher_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """Step-wise solve (pc_solver_create[_batched] / step / result / destroy).
+    The solver reads `vis` only during construction."""
+
+    def __init__(self, plan: Plan, vis: torch.Tensor, params: Optional[PcSolveParams] = None,
+                 stream=None, batcher: Optional[Batcher] = None, **kw):
+        if params is None:
+            params = solve_params(**kw)
+        elif kw:
+            raise ValueError("pass either params or keyword parameters")
+        self.plan = plan
+        h = C.c_void_p()
+        dv = C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis"))
+        if batcher is None:
+            st = LIB.pc_solver_create(plan.handle, dv, C.byref(params), C.c_void_p(_stream(stream)),
+                                      C.byref(h))
+            check(st, "pc_solver_create")
+        else:
+            st = LIB.pc_solver_create_batched(plan.handle, dv, C.byref(params),
+                                              C.c_void_p(_stream(stream)), batcher.handle,
+                                              C.byref(h))
+            check(st, "pc_solver_create_batched")
+        self._h = h
+        self.done = False
+
+    def step(self) -> bool:
+        done = C.c_int32(0)
+        check(LIB.pc_solver_step(self._h, C.byref(done)), "pc_solver_step")
+        self.done = bool(done.value)
+        return self.done
+
+    def result(self, capacity: int = 65536) -> dict:
+        pix = np.zeros(capacity, dtype=np.int32)
+        wgt = np.zeros(capacity, dtype=np.float64)
+        res = PcSolveResult()
+        res.capacity = capacity
+        res.pix = pix.ctypes.data_as(C.POINTER(C.c_int32))
+        res.weight = wgt.ctypes.data_as(C.POINTER(C.c_double))
+        res.cert = None
+        st = LIB.pc_solver_result(self._h, C.byref(res))
+        check(st, "pc_solver_result")
+        return _result_dict(res, st, pix, wgt)
+
+    def close(self):
+        if self._h:
+            LIB.pc_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pc_plan_profile(plan: Plan, enable: bool = True) -> None:

@@ -108,6 +108,27 @@ struct Atom {
   R pad;
 };
 
+// Everything the gridded adjoint's kernels need about one plan, for launches
+// that cover the work of several plans at once (FP32 plans).
+struct AdjJob {
+  GridGeom g;
+  const SpreadChunk* chunks;
+  const FoldItem* fold;
+  const uint8_t* flags;
+  const uint32_t* cell;
+  const float* off;
+  const cpx<float>* vals;
+  const int32_t* perm;
+  cpx<float>* grid;
+  cpx<float>* partials;
+  cpx<float>* H;
+  float* image;
+  const cpx<float>* tw;
+  const float* corr;
+  float scale;
+  unsigned long long* maxkey;
+};
+
 // Per-kernel instrumentation (optional): launches bracketed by HIP events on
 // the launch stream, accumulated per kernel name with the algorithmic bytes
 // and work units (visibility-atom pairs, FFT points, ...) of each launch.
@@ -164,6 +185,7 @@ struct pc_plan {
   size_t red_capacity = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   pc::Prof prof;
+  std::vector<int32_t> chunk_work;  // host copy: visibilities per spreading item
 
   std::vector<pc::DeviceBuf> owned;
 };
@@ -199,6 +221,34 @@ void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted,
                   hipStream_t s);
 void maxkey_reset(pc_plan* p, hipStream_t s);
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax);
+// Launch tables of the batched adjoint (device copy and pinned staging),
+// reused from call to call.
+struct BatchCtx {
+  unsigned char* dev = nullptr;
+  size_t dev_bytes = 0;
+  unsigned char* host = nullptr;
+  size_t host_bytes = 0;
+  hipEvent_t done = nullptr;  // completion of the last call's launches
+  bool pending = false;
+  void release();
+};
+// Gridded adjoints of several FP32 plans in shared launches (one spread per
+// kernel width, one fold, one launch per fine-grid size for each FFT pass).
+// vis[j] is in plan order when vis_sorted[j], else in caller order.  The
+// plans' max keys hold each image's maximum afterwards.  Calls on one ctx
+// must not overlap; the function waits for the previous call's launches
+// before it rewrites the tables.
+void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* vis,
+                        const bool* vis_sorted, float* const* images, const float* scales, int n,
+                        hipStream_t s);
+void maxkey_decode(unsigned long long key, double* max_abs, int64_t* argmax);
+
+// batcher.cpp: gridded adjoint of one job through a batcher, which merges
+// the requests of jobs on other host threads into shared launches.  Blocks
+// until the job's image and maximum are ready; `ms` gets the duration of the
+// shared launches.
+void batcher_adjoint(pc_batcher* b, pc_plan* p, const c32* vis_sorted, float* image,
+                     hipStream_t s, double* max_abs, int64_t* argmax, float* ms);
 
 // kernels_dft.hip
 template <typename R>

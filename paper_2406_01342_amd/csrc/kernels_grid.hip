@@ -14,6 +14,7 @@
 //            1/n(l, m) correction, the image write and a fused max |eta|.
 // Forward by interpolation (type-2): the same passes transposed with the
 // opposite sign, then a w x w gather per visibility.
+#include <algorithm>
 #include <cstring>
 
 #include "common.h"
@@ -73,8 +74,8 @@ struct SpreadCfg {
 };
 
 template <typename R, int W>
-__global__ __launch_bounds__(64) void spread_kernel(
-    GridGeom g, const SpreadChunk* __restrict__ chunks, const uint32_t* __restrict__ cell,
+__device__ __forceinline__ void spread_body(
+    const GridGeom& g, const SpreadChunk& ch, const uint32_t* __restrict__ cell,
     const R* __restrict__ off, const cpx<R>* __restrict__ vals, const int32_t* __restrict__ perm,
     cpx<R>* __restrict__ grid, cpx<R>* __restrict__ partials) {
   using C = SpreadCfg<R, W>;
@@ -88,7 +89,6 @@ __global__ __launch_bounds__(64) void spread_kernel(
     tre[i] = R(0);
     tim[i] = R(0);
   }
-  const SpreadChunk ch = chunks[blockIdx.x];
   const int tv = ch.tile / g.ntu, tu = ch.tile - tv * g.ntu;
   const int ov = g.v0 + tv * kTile, ou = g.u0 + tu * kTile;
   const R inv = R(2) / R(W);
@@ -223,18 +223,33 @@ __global__ __launch_bounds__(64) void spread_kernel(
   }
 }
 
+template <typename R, int W>
+__global__ __launch_bounds__(64) void spread_kernel(
+    GridGeom g, const SpreadChunk* __restrict__ chunks, const uint32_t* __restrict__ cell,
+    const R* __restrict__ off, const cpx<R>* __restrict__ vals, const int32_t* __restrict__ perm,
+    cpx<R>* __restrict__ grid, cpx<R>* __restrict__ partials) {
+  spread_body<R, W>(g, chunks[blockIdx.x], cell, off, vals, perm, grid, partials);
+}
+
+// One launch over the work items of several plans: items[b] = (job, item).
+template <int W>
+__global__ __launch_bounds__(64) void spread_batch_kernel(const AdjJob* __restrict__ jobs,
+                                                          const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const AdjJob& J = jobs[it.x];
+  spread_body<float, W>(J.g, J.chunks[it.y], J.cell, J.off, J.vals, J.perm, J.grid, J.partials);
+}
+
 // Fold of a split tile: 64 cells per workgroup, kFoldSub threads per cell
 // each summing every kFoldSub-th partial (several loads in flight), then the
 // sub-sums are added in a fixed order (bitwise reproducible).
 constexpr int kFoldSub = 8;
 
 template <typename R>
-__global__ __launch_bounds__(64 * kFoldSub) void fold_kernel(GridGeom g,
-                                                           const FoldItem* __restrict__ items,
-                                                           const cpx<R>* __restrict__ partials,
-                                                           cpx<R>* __restrict__ grid) {
+__device__ __forceinline__ void fold_body(const GridGeom& g, const FoldItem& it,
+                                          const cpx<R>* __restrict__ partials,
+                                          cpx<R>* __restrict__ grid) {
   __shared__ R sx[kFoldSub][64], sy[kFoldSub][64];
-  const FoldItem it = items[blockIdx.x];
   const int c = threadIdx.x & 63, sub = threadIdx.x >> 6;
   const int i = blockIdx.y * 64 + c;
   const cpx<R>* src = partials + (size_t)it.first * kTile * kTile + i;
@@ -270,6 +285,21 @@ __global__ __launch_bounds__(64 * kFoldSub) void fold_kernel(GridGeom g,
     const int y = i / kTile, x = i - y * kTile;
     dst[(size_t)y * g.nu + x] = {tx, ty};
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(64 * kFoldSub) void fold_kernel(GridGeom g,
+                                                           const FoldItem* __restrict__ items,
+                                                           const cpx<R>* __restrict__ partials,
+                                                           cpx<R>* __restrict__ grid) {
+  fold_body<R>(g, items[blockIdx.x], partials, grid);
+}
+
+__global__ __launch_bounds__(64 * kFoldSub) void fold_batch_kernel(
+    const AdjJob* __restrict__ jobs, const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const AdjJob& J = jobs[it.x];
+  fold_body<float>(J.g, J.fold[it.y], J.partials, J.grid);
 }
 
 // Pass-A output layout: columns grouped in blocks of kHB, each block stored
@@ -309,16 +339,16 @@ __device__ __forceinline__ void gather_to_lds(cpx<R>* buf, const cpx<R>* __restr
 
 // Pass A of the adjoint: rows of the band grid (fixed v), FFT along u.
 template <typename R, int M, int NB, int NT>
-__global__ __launch_bounds__(NT) void passA_adj_kernel(GridGeom g, const cpx<R>* __restrict__ grid,
-                                                        const uint8_t* __restrict__ tile_flags,
-                                                        cpx<R>* __restrict__ H,
-                                                        const cpx<R>* __restrict__ tw) {
+__device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* __restrict__ grid,
+                                               const uint8_t* __restrict__ tile_flags,
+                                               cpx<R>* __restrict__ H,
+                                               const cpx<R>* __restrict__ tw, int rowblock) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
   load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
-  const int row0 = blockIdx.x * NB;
+  const int row0 = rowblock * NB;
   // tiles without data were never written: read them as zeros
   gather_to_lds<R, NB * M, NT>(
       buf, grid,
@@ -343,6 +373,22 @@ __global__ __launch_bounds__(NT) void passA_adj_kernel(GridGeom g, const cpx<R>*
   }
 }
 
+template <typename R, int M, int NB, int NT>
+__global__ __launch_bounds__(NT) void passA_adj_kernel(GridGeom g, const cpx<R>* __restrict__ grid,
+                                                        const uint8_t* __restrict__ tile_flags,
+                                                        cpx<R>* __restrict__ H,
+                                                        const cpx<R>* __restrict__ tw) {
+  passA_adj_body<R, M, NB, NT>(g, grid, tile_flags, H, tw, blockIdx.x);
+}
+
+template <int M, int NB, int NT>
+__global__ __launch_bounds__(NT) void passA_batch_kernel(const AdjJob* __restrict__ jobs,
+                                                          const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const AdjJob& J = jobs[it.x];
+  passA_adj_body<float, M, NB, NT>(J.g, J.grid, J.flags, J.H, J.tw, it.y);
+}
+
 __device__ __forceinline__ unsigned long long max_key(float a, int idx) {
   return ((unsigned long long)__float_as_uint(a) << 32) | (unsigned long long)(0xffffffffu - (unsigned)idx);
 }
@@ -350,17 +396,18 @@ __device__ __forceinline__ unsigned long long max_key(float a, int idx) {
 // Pass B of the adjoint: NB image rows i; FFT along v of H[:, i]; correction;
 // write image rows; fused max |eta| with lowest-index ties.
 template <typename R, int M, int NB, int NT>
-__global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>* __restrict__ H,
-                                                        R* __restrict__ image,
-                                                        const cpx<R>* __restrict__ tw,
-                                                        const R* __restrict__ corr, R scale,
-                                                        unsigned long long* __restrict__ maxkey) {
+__device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* __restrict__ H,
+                                               R* __restrict__ image,
+                                               const cpx<R>* __restrict__ tw,
+                                               const R* __restrict__ corr, R scale,
+                                               unsigned long long* __restrict__ maxkey,
+                                               int iblock) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
   load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
-  const int i0 = blockIdx.x * NB;
+  const int i0 = iblock * NB;
   gather_to_lds<R, NB * M, NT>(
       buf, H,
       [&](int idx) -> int64_t {
@@ -402,6 +449,23 @@ __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>*
     for (int w = 0; w < NT / 64; ++w) m = wbest[w] > m ? wbest[w] : m;
     atomicMax(maxkey, m);
   }
+}
+
+template <typename R, int M, int NB, int NT>
+__global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>* __restrict__ H,
+                                                        R* __restrict__ image,
+                                                        const cpx<R>* __restrict__ tw,
+                                                        const R* __restrict__ corr, R scale,
+                                                        unsigned long long* __restrict__ maxkey) {
+  passB_adj_body<R, M, NB, NT>(g, H, image, tw, corr, scale, maxkey, blockIdx.x);
+}
+
+template <int M, int NB, int NT>
+__global__ __launch_bounds__(NT) void passB_batch_kernel(const AdjJob* __restrict__ jobs,
+                                                          const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const AdjJob& J = jobs[it.x];
+  passB_adj_body<float, M, NB, NT>(J.g, J.H, J.image, J.tw, J.corr, J.scale, J.maxkey, it.y);
 }
 
 // Forward pass B^T: NB image rows i, pre-correct, FFT along v (sign -1),
@@ -513,6 +577,11 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
 }
 
 __global__ void maxkey_reset_kernel(unsigned long long* k) { *k = 0ull; }
+
+__global__ void maxkey_reset_batch_kernel(const AdjJob* __restrict__ jobs, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) *jobs[j].maxkey = 0ull;
+}
 
 // ----------------------------------------------------------------------------
 // Host launchers
@@ -697,6 +766,10 @@ void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax) {
   unsigned long long key = 0;
   PC_HIP(hipMemcpyAsync(&key, p->maxkey, sizeof(key), hipMemcpyDeviceToHost, s));
   PC_HIP(hipStreamSynchronize(s));
+  maxkey_decode(key, max_abs, argmax);
+}
+
+void maxkey_decode(unsigned long long key, double* max_abs, int64_t* argmax) {
   const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)(key & 0xffffffffu);
   float f;
   std::memcpy(&f, &hi, 4);
@@ -716,6 +789,213 @@ template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted, hipStream_t s) {
   dispatch_M<R>(p, false, nullptr, image, R(1), s);
   launch_interp<R>(p, out_sorted ? nullptr : p->perm, vis_out, s);
+}
+
+// ----------------------------------------------------------------------------
+// Batched adjoint across plans
+// ----------------------------------------------------------------------------
+namespace {
+struct Blob {
+  std::vector<unsigned char> bytes;
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+template <int M>
+struct PassShape {
+  static constexpr int CB = sizeof(c32);
+  static constexpr int NBA = (M * CB >= Shapes<float>::lds_a) ? 1 : Shapes<float>::lds_a / (M * CB);
+  static constexpr int NTA = 256;
+  static constexpr int NBB = nb_passB<float, M>();
+  static constexpr int NTB = nt_for<NBB * M / 16>();
+};
+
+int passA_blocks(int M, int nv) {
+  switch (M) {
+#define PC_M(m) case m: return (nv + PassShape<m>::NBA - 1) / PassShape<m>::NBA;
+    PC_M(32) PC_M(64) PC_M(128) PC_M(256) PC_M(512) PC_M(1024) PC_M(2048) PC_M(4096) PC_M(8192)
+    PC_M(16384)
+#undef PC_M
+  }
+  return 0;
+}
+
+int passB_blocks(int M) {
+  switch (M) {
+#define PC_M(m) case m: return (m / 2) / PassShape<m>::NBB;
+    PC_M(32) PC_M(64) PC_M(128) PC_M(256) PC_M(512) PC_M(1024) PC_M(2048) PC_M(4096) PC_M(8192)
+    PC_M(16384)
+#undef PC_M
+  }
+  return 0;
+}
+
+template <int M>
+void launch_pass_batch(bool passA, const AdjJob* jobs, const int2* items, int nitems,
+                       hipStream_t s) {
+  using P = PassShape<M>;
+  if (passA) {
+    const size_t lds = (size_t)padded(P::NBA * M) * P::CB;
+    set_lds((const void*)passA_batch_kernel<M, P::NBA, P::NTA>, lds);
+    hipLaunchKernelGGL((passA_batch_kernel<M, P::NBA, P::NTA>), dim3(nitems), dim3(P::NTA), lds, s,
+                       jobs, items);
+    PC_LAUNCH_CHECK("passA_batch");
+  } else {
+    const size_t lds = (size_t)padded(P::NBB * M) * P::CB;
+    set_lds((const void*)passB_batch_kernel<M, P::NBB, P::NTB>, lds);
+    hipLaunchKernelGGL((passB_batch_kernel<M, P::NBB, P::NTB>), dim3(nitems), dim3(P::NTB), lds, s,
+                       jobs, items);
+    PC_LAUNCH_CHECK("passB_batch");
+  }
+}
+
+void pass_batch(int M, bool passA, const AdjJob* jobs, const int2* items, int nitems,
+                hipStream_t s) {
+  switch (M) {
+#define PC_M(m) case m: launch_pass_batch<m>(passA, jobs, items, nitems, s); return;
+    PC_M(32) PC_M(64) PC_M(128) PC_M(256) PC_M(512) PC_M(1024) PC_M(2048) PC_M(4096) PC_M(8192)
+    PC_M(16384)
+#undef PC_M
+  }
+  fail(PC_ERR_UNSUPPORTED, "fine grid size");
+}
+
+template <int W>
+void launch_spread_batch(const AdjJob* jobs, const int2* items, int nitems, hipStream_t s) {
+  using C = SpreadCfg<float, W>;
+  set_lds((const void*)spread_batch_kernel<W>, C::lds_bytes);
+  hipLaunchKernelGGL((spread_batch_kernel<W>), dim3(nitems), dim3(64), C::lds_bytes, s, jobs, items);
+  PC_LAUNCH_CHECK("spread_batch");
+}
+
+void spread_batch(int W, const AdjJob* jobs, const int2* items, int nitems, hipStream_t s) {
+  switch (W) {
+#define PC_W(w) case w: launch_spread_batch<w>(jobs, items, nitems, s); return;
+    PC_W(2) PC_W(3) PC_W(4) PC_W(5) PC_W(6) PC_W(7) PC_W(8) PC_W(9) PC_W(10) PC_W(11) PC_W(12)
+    PC_W(13) PC_W(14) PC_W(15) PC_W(16)
+#undef PC_W
+  }
+  fail(PC_ERR_UNSUPPORTED, "kernel width");
+}
+}  // namespace
+
+void BatchCtx::release() {
+  if (pending && done) (void)hipEventSynchronize(done);
+  pending = false;
+  if (dev) (void)hipFree(dev);
+  if (host) (void)hipHostFree(host);
+  if (done) (void)hipEventDestroy(done);
+  dev = host = nullptr;
+  dev_bytes = host_bytes = 0;
+  done = nullptr;
+}
+
+void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* vis,
+                        const bool* vis_sorted, float* const* images, const float* scales, int n,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  if (!ctx.done) PC_HIP(hipEventCreateWithFlags(&ctx.done, hipEventDisableTiming));
+  if (ctx.pending) PC_HIP(hipEventSynchronize(ctx.done));
+  // job descriptors and work lists
+  std::vector<AdjJob> jobs(n);
+  std::vector<std::pair<int32_t, int2>> sitems;  // (work, (job, chunk))
+  std::vector<int2> fitems;
+  std::vector<int> Ms, Ws;
+  for (int j = 0; j < n; ++j) {
+    pc_plan* p = plans[j];
+    PC_REQUIRE(p && p->precision == PC_PREC_FP32, "batched adjoint needs FP32 plans");
+    AdjJob& J = jobs[j];
+    J.g = p->g;
+    J.chunks = p->chunks;
+    J.fold = p->fold;
+    J.flags = p->tile_flags;
+    J.cell = p->cell;
+    J.off = (const float*)p->off;
+    J.vals = vis[j];
+    J.perm = vis_sorted[j] ? nullptr : p->perm;
+    J.grid = (c32*)p->grid;
+    J.partials = (c32*)p->partials;
+    J.H = (c32*)p->H;
+    J.image = images[j];
+    J.tw = (const c32*)p->twiddle;
+    J.corr = (const float*)p->corr;
+    J.scale = scales ? scales[j] : 1.0f;
+    J.maxkey = p->maxkey;
+    for (int64_t c = 0; c < p->n_chunks; ++c)
+      sitems.push_back({p->chunk_work[c], make_int2(j, (int)c)});
+    for (int64_t f = 0; f < p->n_fold; ++f) fitems.push_back(make_int2(j, (int)f));
+    if (std::find(Ms.begin(), Ms.end(), p->g.M) == Ms.end()) Ms.push_back(p->g.M);
+    if (std::find(Ws.begin(), Ws.end(), p->g.W) == Ws.end()) Ws.push_back(p->g.W);
+  }
+  // longest spreading items first across all plans
+  std::stable_sort(sitems.begin(), sitems.end(),
+                   [](const std::pair<int32_t, int2>& a, const std::pair<int32_t, int2>& b) {
+                     return a.first > b.first;
+                   });
+  Blob blob;
+  const size_t o_jobs = blob.put(jobs);
+  std::vector<size_t> o_spread(Ws.size()), n_spread(Ws.size());
+  for (size_t w = 0; w < Ws.size(); ++w) {
+    std::vector<int2> it;
+    for (auto& e : sitems)
+      if (plans[e.second.x]->g.W == Ws[w]) it.push_back(e.second);
+    o_spread[w] = blob.put(it);
+    n_spread[w] = it.size();
+  }
+  const size_t o_fold = blob.put(fitems);
+  std::vector<size_t> oA(Ms.size()), nA(Ms.size()), oB(Ms.size()), nB(Ms.size());
+  for (size_t m = 0; m < Ms.size(); ++m) {
+    std::vector<int2> a, b;
+    for (int j = 0; j < n; ++j) {
+      if (plans[j]->g.M != Ms[m]) continue;
+      const int na = passA_blocks(Ms[m], plans[j]->g.nv), nbk = passB_blocks(Ms[m]);
+      for (int r = 0; r < na; ++r) a.push_back(make_int2(j, r));
+      for (int r = 0; r < nbk; ++r) b.push_back(make_int2(j, r));
+    }
+    oA[m] = blob.put(a);
+    nA[m] = a.size();
+    oB[m] = blob.put(b);
+    nB[m] = b.size();
+  }
+  const size_t bytes = blob.bytes.size();
+  if (ctx.host_bytes < bytes) {
+    if (ctx.host) (void)hipHostFree(ctx.host);
+    ctx.host = nullptr;
+    ctx.host_bytes = 0;
+    PC_HIP(hipHostMalloc((void**)&ctx.host, bytes * 2));
+    ctx.host_bytes = bytes * 2;
+  }
+  if (ctx.dev_bytes < bytes) {
+    if (ctx.dev) (void)hipFree(ctx.dev);
+    ctx.dev = nullptr;
+    ctx.dev_bytes = 0;
+    PC_HIP(hipMalloc((void**)&ctx.dev, bytes * 2));
+    ctx.dev_bytes = bytes * 2;
+  }
+  std::memcpy(ctx.host, blob.bytes.data(), bytes);
+  PC_HIP(hipMemcpyAsync(ctx.dev, ctx.host, bytes, hipMemcpyHostToDevice, s));
+  const AdjJob* djobs = (const AdjJob*)(ctx.dev + o_jobs);
+  hipLaunchKernelGGL(maxkey_reset_batch_kernel, dim3((n + 63) / 64), dim3(64), 0, s, djobs, n);
+  PC_LAUNCH_CHECK("maxkey_reset_batch");
+  for (size_t w = 0; w < Ws.size(); ++w)
+    if (n_spread[w])
+      spread_batch(Ws[w], djobs, (const int2*)(ctx.dev + o_spread[w]), (int)n_spread[w], s);
+  if (!fitems.empty()) {
+    hipLaunchKernelGGL(fold_batch_kernel, dim3((unsigned)fitems.size(), kTile * kTile / 64),
+                       dim3(64 * kFoldSub), 0, s, djobs, (const int2*)(ctx.dev + o_fold));
+    PC_LAUNCH_CHECK("fold_batch");
+  }
+  for (size_t m = 0; m < Ms.size(); ++m)
+    if (nA[m]) pass_batch(Ms[m], true, djobs, (const int2*)(ctx.dev + oA[m]), (int)nA[m], s);
+  for (size_t m = 0; m < Ms.size(); ++m)
+    if (nB[m]) pass_batch(Ms[m], false, djobs, (const int2*)(ctx.dev + oB[m]), (int)nB[m], s);
+  PC_HIP(hipEventRecord(ctx.done, s));
+  ctx.pending = true;
 }
 
 template void adjoint_grid<float>(pc_plan*, const c32*, bool, float*, float, hipStream_t);

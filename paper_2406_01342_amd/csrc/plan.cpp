@@ -418,6 +418,12 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     p->n_chunks = (int64_t)lay.chunks.size();
     p->n_partials = lay.n_partials;
     p->n_fold = (int64_t)lay.fold.size();
+    p->chunk_work.resize(lay.chunks.size());
+    for (size_t c = 0; c < lay.chunks.size(); ++c) {
+      int32_t w = 0;
+      for (int r = 0; r < 4; ++r) w += lay.chunks[c].end[r] - lay.chunks[c].beg[r];
+      p->chunk_work[c] = w;
+    }
     const GridGeom& g = lay.g;
     const bool f64 = geom->precision == PC_PREC_FP64;
     const size_t cb = f64 ? 16 : 8, rb = cb / 2;

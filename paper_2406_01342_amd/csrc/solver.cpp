@@ -55,6 +55,7 @@ constexpr double kLipMargin = 1.02;
 struct Pfw {
   pc_plan* p;
   hipStream_t s;
+  pc_batcher* batcher = nullptr;  // shared-launch adjoints when set
   pc_solve_params prm;
   int64_t L, N;
   DevArray<c32> V, r;
@@ -84,6 +85,13 @@ struct Pfw {
   }
 
   void adjoint_timed(const c32* vis_sorted) {
+    if (batcher) {
+      float ms = 0;
+      batcher_adjoint(batcher, p, vis_sorted, eta.ptr, s, &eta_inf, &eta_argmax, &ms);
+      adj_ms += ms;
+      adj_calls++;
+      return;
+    }
     PC_HIP(hipEventRecord(p->ev_a, s));
     adjoint_grid<float>(p, vis_sorted, true, eta.ptr, 1.0f, s);
     PC_HIP(hipEventRecord(p->ev_b, s));
@@ -346,6 +354,23 @@ struct pc_solver {
   pc_solver(pc_plan* p, hipStream_t s, const pc_solve_params& prm) : pfw(p, s, prm) {}
 };
 
+static pc_solver* solver_new(pc_plan* plan, const void* vis, const pc_solve_params* prm,
+                             void* stream, pc_batcher* batcher) {
+  PC_REQUIRE(plan && vis, "NULL argument");
+  PC_REQUIRE(plan->precision == PC_PREC_FP32, "solve needs an FP32 plan");
+  check_params(prm);
+  PC_HIP(hipSetDevice(plan->device));
+  auto* sv = new pc_solver(plan, (hipStream_t)stream, *prm);
+  sv->pfw.batcher = batcher;
+  try {
+    sv->pfw.init(vis);
+  } catch (...) {
+    delete sv;
+    throw;
+  }
+  return sv;
+}
+
 template <typename F>
 static pc_status guarded(const char* fn, F&& f) {
   try {
@@ -391,19 +416,20 @@ PC_API pc_status pc_polyclean_solve(pc_plan* plan, const void* vis, const pc_sol
 PC_API pc_status pc_solver_create(pc_plan* plan, const void* vis, const pc_solve_params* prm,
                                   void* stream, pc_solver** out) {
   return guarded("pc_solver_create", [&] {
-    PC_REQUIRE(plan && vis && out, "NULL argument");
-    PC_REQUIRE(plan->precision == PC_PREC_FP32, "solve needs an FP32 plan");
-    check_params(prm);
+    PC_REQUIRE(out != nullptr, "NULL argument");
     *out = nullptr;
-    PC_HIP(hipSetDevice(plan->device));
-    auto* sv = new pc_solver(plan, (hipStream_t)stream, *prm);
-    try {
-      sv->pfw.init(vis);
-    } catch (...) {
-      delete sv;
-      throw;
-    }
-    *out = sv;
+    *out = solver_new(plan, vis, prm, stream, nullptr);
+    return PC_OK;
+  });
+}
+
+PC_API pc_status pc_solver_create_batched(pc_plan* plan, const void* vis,
+                                          const pc_solve_params* prm, void* stream,
+                                          pc_batcher* batcher, pc_solver** out) {
+  return guarded("pc_solver_create_batched", [&] {
+    PC_REQUIRE(out != nullptr, "NULL argument");
+    *out = nullptr;
+    *out = solver_new(plan, vis, prm, stream, batcher);
     return PC_OK;
   });
 }
