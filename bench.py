@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-reps", type=int, default=50)
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving trace (0 skips the serving leg)")
+    ap.add_argument("--serving-slots", type=int, default=8)
     return ap.parse_args()
 
 
@@ -105,6 +108,73 @@ def cpu_baseline(p, vis, seconds):
     return {"value": m / dt / 1e6, "unit": "Mvis/s", "cores": int(cores), "kind": "oracle",
             "sample": f"FP64 exact adjoint (direct sum as chunked complex GEMM) of the first {m} "
                       f"of {len(v)} visibilities onto the full {p.npix}^2 image, {dt:.1f} s"}
+
+
+def serving_leg(api, torch, n_req, slots):
+    """Serving mix: n_req requests (grids 256^2..2048^2, 1e4-5e5 visibilities,
+    32-128 antennas, 5-200 sources, 20 dB, lambda = 0.05 lambda_max, stop at
+    relative objective change 1e-4 or 100 iterations).  Runs the plain path
+    (one pc_polyclean_solve at a time) and the batched server with every
+    request present at t = 0 (saturation), then the server on Poisson arrival
+    traces at 0.5x and 1.0x the plain path's solves/s.  Plain-path latencies
+    under those traces follow from its measured per-job service times (FIFO,
+    one job at a time)."""
+    import numpy as np
+    import sim
+    from paper_2406_01342_amd import serving
+    t = time.perf_counter()
+    reqs = []
+    for k in range(n_req):
+        p = sim.config_c4_request(k)
+        plan0, vis = synth_inputs(api, torch, p)
+        plan0.close()
+        prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter,
+                   rel_obj_tol=p.rel_obj_tol, rel_gap_tol=p.rel_gap_tol)
+        reqs.append(serving.ImagingRequest(k, 0.0, p.uv, p.npix, p.fov_rad, vis, prm))
+    log(f"serving: {n_req} requests synthesised in {time.perf_counter() - t:.1f} s, "
+        f"{sum(r.uv.shape[0] for r in reqs)} visibilities")
+    be = serving.DeviceBackend(batched=True)
+    # warm the code paths (kernels of every grid size) outside the timed runs
+    for n in (256, 512, 1024, 2048):
+        r0 = next((r for r in reqs if r.npix == n), None)
+        if r0 is not None:
+            be.solve_plain(r0)
+    plain, precs = serving.run_plain(be, reqs)
+    log("serving plain", plain)
+    srv = serving.Server(be, slots=slots)
+    sat = srv.run(reqs)
+    log("serving batched", sat)
+    plain_by = {r.rid: r for r in precs}
+    dobj = max(abs(r.result["objective"] - plain_by[r.rid].result["objective"]) /
+               max(abs(plain_by[r.rid].result["objective"]), 1e-300)
+               for r in srv.records if r.status == "done")
+    service = np.array([r.finished_s - r.admitted_s for r in precs])
+    out = {"workload": "serving mix: grids 256^2-2048^2, 1e4-5e5 visibilities "
+                       "(log-uniform), 32-128 antennas, 5-200 sources, 20 dB, "
+                       "lambda = 0.05 lambda_max, stop at relative objective change 1e-4",
+           "requests": n_req, "slots": slots,
+           "saturation": {"plain": plain, "batched": sat,
+                          "solves_per_s_ratio": sat["solves_per_s"] / plain["solves_per_s"]},
+           "max_rel_objective_diff_batched_vs_plain": dobj}
+    for mult in (0.5, 1.0):
+        rate = mult * plain["solves_per_s"]
+        arr = sim.poisson_arrivals(n_req, rate)
+        for r, a in zip(reqs, arr):
+            r.arrival_s = float(a)
+        srv = serving.Server(be, slots=slots)
+        bat = srv.run(reqs)
+        fin, lat = 0.0, []
+        for a, sv in zip(arr, service):
+            fin = max(a, fin) + sv
+            lat.append(fin - a)
+        lat = np.array(lat)
+        pl = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+              "solves_per_s": n_req / fin}
+        out[f"poisson_{mult}x"] = {"rate_per_s": rate, "batched": bat, "plain_fifo": pl}
+        log(f"serving poisson {mult}x", bat, pl)
+    out["batcher"] = be.stats()
+    be.close_backend()
+    return out
 
 
 def main():
@@ -205,6 +275,10 @@ def main():
         "kernels": sorted(({"name": s_["name"], "launches": s_["launches"], "ms": round(s_["ms"], 3)}
                            for s_ in stats), key=lambda d: -d["ms"])[:8],
     }
+    if args.serving_requests > 0:
+        del plan, dv
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(api, torch, args.serving_requests, args.serving_slots)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(p, vis, args.cpu_seconds)

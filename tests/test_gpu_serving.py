@@ -1,0 +1,100 @@
+"""Batched serving on the GPU: every job's result is the same alone (plain
+pc_polyclean_solve, one job at a time) and in the mix (several solves in
+flight, full-grid adjoints merged by the batcher), and the merged launches
+really served several jobs at once."""
+import numpy as np
+import pytest
+
+import sim
+from oracle import operator
+
+from gpu_util import api, say
+
+pytestmark = pytest.mark.gpu
+
+L_MAX = 40000
+
+
+def requests(n_req):
+    """Serving requests of the heterogeneous mix (grids 256..2048, 32-128
+    antennas, 5-200 sources), cut to at most L_MAX visibilities so that the
+    oracle synthesises their data quickly."""
+    out = []
+    for k in range(n_req):
+        p = sim.config_c4_request(k)
+        L = min(L_MAX, p.uv.shape[0])
+        uv = p.uv[:L]
+        vclean = operator.forward(uv, p.npix, p.fov_rad, p.sky_pix, p.sky_amp)
+        vis = sim.add_noise(vclean, p.noise[:L], p.psnr_db).astype(np.complex64)
+        prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter,
+                   rel_obj_tol=p.rel_obj_tol, rel_gap_tol=p.rel_gap_tol)
+        out.append((p, uv, vis, prm))
+    return out
+
+
+def test_results_alone_equal_results_in_the_mix():
+    a = api()
+    from paper_2406_01342_amd import serving
+    reqs = requests(8)
+    be = serving.DeviceBackend(batched=True)
+    alone = []
+    for k, (p, uv, vis, prm) in enumerate(reqs):
+        say("alone", k, p.npix, uv.shape[0])
+        alone.append(be.solve_plain(serving.ImagingRequest(k, 0.0, uv, p.npix, p.fov_rad, vis,
+                                                           prm)))
+    say("mix of", len(reqs), "jobs on 4 slots")
+    srv = serving.Server(be, slots=4)
+    summary = srv.run([serving.ImagingRequest(k, 0.0, uv, p.npix, p.fov_rad, vis, prm)
+                       for k, (p, uv, vis, prm) in enumerate(reqs)])
+    st = be.stats()
+    say("summary", summary, st)
+    assert summary["completed"] == len(reqs)
+    assert summary["peak_running"] >= 2
+    for rec in srv.records:
+        ra, rm = alone[rec.rid], rec.result
+        assert rm["iters"] == ra["iters"], rec.rid
+        np.testing.assert_array_equal(rm["pix"], ra["pix"])
+        np.testing.assert_allclose(rm["weight"], ra["weight"], rtol=1e-6,
+                                   atol=1e-6 * np.abs(ra["weight"]).max())
+        assert abs(rm["objective"] - ra["objective"]) <= 1e-6 * ra["objective"]
+        assert abs(rm["lambda_max"] - ra["lambda_max"]) <= 1e-6 * ra["lambda_max"]
+        assert rm["cert_argmax"] == ra["cert_argmax"]
+    # every adjoint of the mix went through the batcher, and some were merged
+    assert st["requests"] == sum(r.result["adjoint_calls"] for r in srv.records)
+    assert st["batches"] < st["requests"]
+    assert st["max_batch"] >= 2
+    be.close_backend()
+
+
+def test_batched_solver_single_job_matches_plain():
+    """A batcher with one job gives the plain solver's result (its batches are
+    all of size one)."""
+    a = api()
+    import torch
+    p, uv, vis, prm = requests(1)[0]
+    plan = a.pc_plan_create(uv, p.npix, p.fov_rad)
+    dv = torch.from_numpy(vis).cuda()
+    ref = a.pc_polyclean_solve(plan, dv, **prm)
+    b = a.Batcher(0)
+    sv = a.Solver(plan, dv, batcher=b, **prm)
+    while not sv.step():
+        pass
+    res = sv.result()
+    sv.close()
+    st = b.stats()
+    b.close()
+    assert st["max_batch"] == 1 and st["requests"] == res["adjoint_calls"]
+    np.testing.assert_array_equal(res["pix"], ref["pix"])
+    assert abs(res["objective"] - ref["objective"]) <= 1e-9 * ref["objective"]
+
+
+def test_batcher_rejects_fp64_plan():
+    a = api()
+    import torch
+    rng = np.random.default_rng(3)
+    uv = rng.uniform(-300, 300, size=(500, 2))
+    plan = a.pc_plan_create(uv, 32, 0.02, precision=a.PC_PREC_FP64)
+    b = a.Batcher(0)
+    with pytest.raises(a.PolycleanError):
+        a.Solver(plan, torch.zeros(500, dtype=torch.complex64, device="cuda"), batcher=b)
+    b.close()
