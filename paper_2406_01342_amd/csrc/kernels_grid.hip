@@ -73,6 +73,54 @@ struct SpreadCfg {
   static constexpr size_t lds_bytes = sizeof(R) * (2 * TILE + STG) + sizeof(int) * 128;
 };
 
+// Adds a run's per-tap register sums into the LDS tile and clears them.
+template <typename R, int W, int S, int NPASS>
+__device__ __forceinline__ void spread_flush(const GridGeom& g, int lane, int cbu, int cbv,
+                                             R (&accr)[NPASS], R (&acci)[NPASS], R* tre, R* tim) {
+#pragma unroll
+  for (int ps = 0; ps < NPASS; ++ps) {
+    const int tap = lane + 64 * ps;
+    const int a = tap / W, b = tap - (tap / W) * W;
+    int y, x;
+    if (tap < W * W && tap_local(cbv, a, g.M, g.wrap, y) && tap_local(cbu, b, g.M, g.wrap, x)) {
+      tre[y * S + x] += accr[ps];
+      tim[y * S + x] += acci[ps];
+    }
+    accr[ps] = R(0);
+    acci[ps] = R(0);
+  }
+}
+
+// One staged visibility as fetched from global memory.
+template <typename R>
+struct VisIn {
+  uint32_t cell;
+  R su, sv;
+  cpx<R> val;
+};
+
+// Position in the sorted arrays of the q-th visibility of a work item whose
+// four ranges have cumulative lengths c1 <= c2 <= c3 and offsets b0..b3
+// (plain values, so that no reference is selected at run time).
+__device__ __forceinline__ int chunk_index(int q, int c1, int c2, int c3, int b0, int b1, int b2,
+                                           int b3) {
+  const int add = q < c1 ? b0 : (q < c2 ? b1 : (q < c3 ? b2 : b3));
+  return q + add;
+}
+
+template <typename R>
+__device__ __forceinline__ VisIn<R> fetch_vis(int s, const uint32_t* __restrict__ cell,
+                                              const R* __restrict__ off,
+                                              const cpx<R>* __restrict__ vals,
+                                              const int32_t* __restrict__ perm) {
+  VisIn<R> v;
+  v.cell = cell[s];
+  v.su = off[2 * s];
+  v.sv = off[2 * s + 1];
+  v.val = perm ? vals[perm[s]] : vals[s];
+  return v;
+}
+
 template <typename R, int W>
 __device__ __forceinline__ void spread_body(
     const GridGeom& g, const SpreadChunk& ch, const uint32_t* __restrict__ cell,
@@ -93,8 +141,7 @@ __device__ __forceinline__ void spread_body(
   const int ov = g.v0 + tv * kTile, ou = g.u0 + tu * kTile;
   const R inv = R(2) / R(W);
   const R beta = sizeof(R) == 4 ? (R)g.beta : (R)g.beta64;
-  // cumulative range boundaries (named scalars: no dynamic indexing, so no
-  // private-memory spill)
+  // cumulative range boundaries
   const int c1 = ch.end[0] - ch.beg[0];
   const int c2 = c1 + ch.end[1] - ch.beg[1];
   const int c3 = c2 + ch.end[2] - ch.beg[2];
@@ -104,20 +151,9 @@ __device__ __forceinline__ void spread_body(
   constexpr int U = C::U;
   // The global loads of the next batch are issued before the current batch's
   // tap loop, so their latency overlaps the LDS work.
-  uint32_t nc = 0;
-  R nsu = 0, nsv = 0;
-  cpx<R> nval = {R(0), R(0)};
-  auto fetch = [&](int base) {
-    const int q = base + lane;
-    if (q < total) {
-      const int s = q + (q < c1 ? b0 : q < c2 ? b1 : q < c3 ? b2 : b3);
-      nc = cell[s];
-      nsu = off[2 * s];
-      nsv = off[2 * s + 1];
-      nval = perm ? vals[perm[s]] : vals[s];
-    }
-  };
-  fetch(0);
+  VisIn<R> nx{0u, R(0), R(0), {R(0), R(0)}};
+  if (lane < total)
+    nx = fetch_vis<R>(chunk_index(lane, c1, c2, c3, b0, b1, b2, b3), cell, off, vals, perm);
   // Visibilities arrive sorted by first cell, so runs sharing a footprint are
   // summed per tap in registers and written to LDS once per run (a plain
   // read-add-write: the lanes of one instruction address distinct cells and
@@ -126,20 +162,6 @@ __device__ __forceinline__ void spread_body(
   R accr[NPASS], acci[NPASS];
 #pragma unroll
   for (int ps = 0; ps < NPASS; ++ps) accr[ps] = acci[ps] = R(0);
-  auto flush = [&]() {
-#pragma unroll
-    for (int ps = 0; ps < NPASS; ++ps) {
-      const int tap = lane + 64 * ps;
-      const int a = tap / W, b = tap - (tap / W) * W;
-      int y, x;
-      if (tap < W * W && tap_local(cbv, a, g.M, g.wrap, y) && tap_local(cbu, b, g.M, g.wrap, x)) {
-        tre[y * C::S + x] += accr[ps];
-        tim[y * C::S + x] += acci[ps];
-      }
-      accr[ps] = R(0);
-      acci[ps] = R(0);
-    }
-  };
 #pragma unroll 1
   for (int base = 0; base < total; base += 64) {
     // stage one visibility per lane; lanes past the end stage a visibility
@@ -149,20 +171,21 @@ __device__ __forceinline__ void spread_body(
     sbase[2 * lane] = -(1 << 20);  // below -M - W: never maps into a tile
     sbase[2 * lane + 1] = -(1 << 20);
     if (q < total) {
-      sbase[2 * lane] = tile_base((int)(nc & 0xffffu), ou, g.M, W, g.wrap);
-      sbase[2 * lane + 1] = tile_base((int)(nc >> 16), ov, g.M, W, g.wrap);
+      sbase[2 * lane] = tile_base((int)(nx.cell & 0xffffu), ou, g.M, W, g.wrap);
+      sbase[2 * lane + 1] = tile_base((int)(nx.cell >> 16), ov, g.M, W, g.wrap);
 #pragma unroll
       for (int t = 0; t < W; ++t) {
-        my[t] = es_kernel<R>((nsu + R(t)) * inv, beta);
-        my[W + t] = es_kernel<R>((nsv + R(t)) * inv, beta);
+        my[t] = es_kernel<R>((nx.su + R(t)) * inv, beta);
+        my[W + t] = es_kernel<R>((nx.sv + R(t)) * inv, beta);
       }
-      my[2 * W] = nval.x;
-      my[2 * W + 1] = nval.y;
+      my[2 * W] = nx.val.x;
+      my[2 * W + 1] = nx.val.y;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    fetch(base + 64);
+    if (q + 64 < total)
+      nx = fetch_vis<R>(chunk_index(q + 64, c1, c2, c3, b0, b1, b2, b3), cell, off, vals, perm);
     const int nb = total - base < 64 ? total - base : 64;
 #pragma unroll 1
     for (int v0 = 0; v0 < nb; v0 += U) {
@@ -189,7 +212,7 @@ __device__ __forceinline__ void spread_body(
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (bu[u] != cbu || bv[u] != cbv) {  // same for every lane of the wave
-          flush();
+          spread_flush<R, W, C::S, NPASS>(g, lane, cbu, cbv, accr, acci, tre, tim);
           cbu = bu[u];
           cbv = bv[u];
         }
@@ -204,7 +227,7 @@ __device__ __forceinline__ void spread_body(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  flush();
+  spread_flush<R, W, C::S, NPASS>(g, lane, cbu, cbv, accr, acci, tre, tim);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
