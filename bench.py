@@ -30,9 +30,129 @@ sys.path.insert(0, ROOT)
 
 METRIC = "adjoint Mvis/s (%HBM roofline); solves/s + p50/p99 latency vs plain @1e-4"
 HBM_PEAK_GBS = 8000.0
-# Direct-DFT pair rate ceiling (pairs/s), derived in the design doc from the gfx950
-# VALU issue rates and the instruction mix of one visibility-atom pair.
-DFT_PEAK_GPAIRS = float(os.environ.get("PC_DFT_PEAK_GPAIRS", "0")) or None
+# Direct-DFT pair-rate ceiling of the vector ALUs: 256 CUs x 2.4 GHz x 128
+# FP32 lanes = 78.6e12 FP32 lane-slots/s; one visibility-atom pair costs about
+# 19 slots (FP64 multiply and FMA for the phase at half rate, FP64 round and
+# subtract, FP64->FP32 convert, sin and cos at quarter rate, two FP32 FMA).
+DFT_PEAK_GPAIRS = 78.6e3 / 19.0
+# Source files each kernel is compiled from (with the shared headers): a
+# stored HBM-traffic figure is used only while these are unchanged.
+CSRC = os.path.join(ROOT, "paper_2406_01342_amd", "csrc")
+KERNEL_FILES = {
+    "adjoint_sparse": ["kernels_dft.hip"], "adjoint_sparse_reduce": ["kernels_dft.hip"],
+    "forward_sparse": ["kernels_dft.hip"],
+    "spread": ["kernels_grid.hip", "fft_lds.h"], "fold": ["kernels_grid.hip", "fft_lds.h"],
+    "passA_adj": ["kernels_grid.hip", "fft_lds.h"], "passB_adj": ["kernels_grid.hip", "fft_lds.h"],
+    "fista": ["kernels_solver.hip", "solver_kernels.h"],
+    "power": ["kernels_solver.hip", "solver_kernels.h"],
+}
+# kernel name in the library's statistics -> substring of its symbol
+KERNEL_SYMBOLS = {
+    "adjoint_sparse": "adjoint_sparse_kernel<float>", "forward_sparse": "forward_sparse_kernel<float>",
+    "adjoint_sparse_reduce": "adjoint_sparse_reduce_kernel<float>",
+    "spread": "spread_kernel<float", "fold": "fold_kernel<float>", "passA_adj": "passA_adj_kernel<float",
+    "passB_adj": "passB_adj_kernel<float", "fista": "fista_kernel", "power": "power_kernel",
+}
+PROFILES = os.path.join(ROOT, "profiles")
+COPY_PROBE_BYTES = 512 << 20
+
+
+def kernel_source_hash(name):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_FILES.get(name, []) + ["common.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(name):
+    """HBM bytes per launch of `name` from the committed counter summary, or
+    None when there is none or the kernel's sources changed since."""
+    path = os.path.join(PROFILES, f"traffic_{name}.json")
+    if name not in KERNEL_FILES or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_sha256") != kernel_source_hash(name):
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
+def copy_probe(torch):
+    """One plain device copy of COPY_PROBE_BYTES, the reference dispatch for
+    scaling the FETCH_SIZE / WRITE_SIZE counters to bytes.  The destination
+    is filled after the source, so that none of the source is still in the
+    L2 caches when the copy reads it."""
+    a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def summarize_pmc(kernel, fetch_dir, write_dir, command):
+    """Writes profiles/traffic_<kernel>.json from a FETCH_SIZE run and a
+    WRITE_SIZE run of the same command (KiB per dispatch, scaled by the copy
+    probe's reading of the same counter)."""
+    sym = KERNEL_SYMBOLS[kernel]
+    out = {"kernel": kernel, "symbol": sym, "command": command,
+           "copy_probe_bytes": COPY_PROBE_BYTES}
+    for ctr, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == ctr]
+        kv = [float(r["Counter_Value"]) for r in rows if sym in r["Kernel_Name"]]
+        cp = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+              or "copy" in r["Kernel_Name"].lower()]
+        if not kv or not cp:
+            raise SystemExit(f"{ctr}: no dispatches of {sym} or of the copy probe in {d}")
+        probe = max(cp)
+        factor = COPY_PROBE_BYTES / (probe * 1024.0)
+        out[ctr.lower() + "_kib_per_dispatch"] = sum(kv) / len(kv)
+        out[ctr.lower() + "_dispatches"] = len(kv)
+        out[ctr.lower() + "_copy_probe_kib"] = probe
+        out[ctr.lower() + "_scale"] = factor
+    out["traffic_bytes_per_launch"] = 1024.0 * (
+        out["fetch_size_kib_per_dispatch"] * out["fetch_size_scale"] +
+        out["write_size_kib_per_dispatch"] * out["write_size_scale"])
+    out["source_sha256"] = kernel_source_hash(kernel)
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, f"traffic_{kernel}.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def summarize_trace(trace_dir, out_name, command, top=14):
+    """Writes a short text summary of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
+    with open(f[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+             f"{'kernel':64s} {'calls':>7s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s}"]
+    for r in rows[:top]:
+        name = r["Name"]
+        name = name if len(name) <= 64 else name[:61] + "..."
+        lines.append(f"{name:64s} {int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e3:11.1f} "
+                     f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['Percentage']):6.2f}")
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, out_name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def parse():
@@ -46,6 +166,11 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving trace (0 skips the serving leg)")
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_KERNEL.json from two rocprofv3 --pmc runs")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"),
+                    help="write profiles/OUT_NAME from a rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--command", default="", help="the profiled command, recorded in summaries")
     return ap.parse_args()
 
 
@@ -76,13 +201,13 @@ def dominant_roofline(stats, plan_info):
         achieved = pairs / (avg_ms * 1e-3) / 1e9
         return {"kernel": name, "bound": "alu", "achieved": achieved,
                 "peak": DFT_PEAK_GPAIRS, "unit": "Gpair/s",
-                "frac": (achieved / DFT_PEAK_GPAIRS) if DFT_PEAK_GPAIRS else None,
-                "traffic": None, "avg_ms": avg_ms, "launches": top["launches"],
+                "frac": achieved / DFT_PEAK_GPAIRS,
+                "traffic": stored_traffic(name), "avg_ms": avg_ms, "launches": top["launches"],
                 "work_per_launch": pairs}
     b = top["bytes"] / top["launches"]
     achieved = b / (avg_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(name),
             "avg_ms": avg_ms, "launches": top["launches"], "bytes_per_launch": b}
 
 
@@ -179,6 +304,12 @@ def serving_leg(api, torch, n_req, slots):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.command)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, args.command)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
               "part of this build", file=sys.stderr)
@@ -189,6 +320,7 @@ def main():
     from paper_2406_01342_amd import api
 
     torch.cuda.set_device(0)
+    copy_probe(torch)
     p = sim.config_c2()
     log("workload C2", p.nvis, "visibilities", p.npix, "pixels")
     t = time.perf_counter()

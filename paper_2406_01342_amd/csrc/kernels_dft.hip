@@ -93,76 +93,149 @@ __global__ __launch_bounds__(256) void forward_sparse_kernel(
   out[out_perm ? out_perm[k] : k] = o;
 }
 
-// Restricted adjoint, lanes over visibilities: each lane holds kVPT
-// visibilities in registers; for each atom (uniform loop, scalar loads) it
-// sums Re(h_k exp(+2 pi i t_kp)) over its visibilities in R precision, the
-// wave reduces the 64 lane sums, and lane 0 writes the wave's partial to
-// partial[p][wave] (atom-major, so the final sum reads contiguously).  The
-// per-atom sum over waves is done in FP64 by a second kernel, in a fixed
-// order (bitwise reproducible).
-constexpr int kVPT = 4;
-constexpr int kAdjThreads = 256;
-constexpr int kVisChunk = kVPT * kAdjThreads;  // visibilities per workgroup
+// Restricted adjoint, lanes over atoms.  A workgroup is 4 waves; each wave
+// takes a chunk of K consecutive visibilities and up to 64 atoms.  With at
+// least 64 atoms each lane owns one atom and the whole wave walks the chunk
+// together; with A < 64 atoms (A a power of two) the wave splits into 64/A
+// streams over the chunk, combined by a few lane shuffles at the end.  The
+// chunk is staged through LDS in rounds of kAdjRound visibilities (one
+// coalesced load per lane, double-buffered so that the next round's loads
+// are in flight while the current one is summed); the lanes then read each
+// visibility as an LDS broadcast and keep private running sums, so there is
+// no cross-lane traffic per pair.  The 4 waves' sums are added in LDS and
+// written as one partial per (atom, workgroup); a second kernel sums the
+// partials in FP64 in a fixed order (bitwise reproducible) and applies 1/n.
+constexpr int kAdjRound = 128;
 
-template <typename R>
-__device__ __forceinline__ R wave_sum(R v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+struct AdjShape {
+  int lgA;          // log2 atoms per wave
+  int64_t ngroups;  // atom groups
+  int64_t K;        // visibilities per wave (a multiple of kAdjRound)
+  int64_t nwg;      // workgroups per atom group (grid: ngroups x nwg)
+};
+
+static AdjShape adjoint_shape(int64_t L, int64_t natoms) {
+  AdjShape sh{};
+  // at least 2 atoms per wave, so that the 64/A streams (<= 32) times the
+  // 4-way unroll of the summing loop tile a round of kAdjRound exactly
+  sh.lgA = 1;
+  while ((1 << sh.lgA) < natoms && sh.lgA < 6) ++sh.lgA;
+  const int64_t A = 1 << sh.lgA;
+  sh.ngroups = (natoms + A - 1) / A;
+  // about 8192 waves in all (32 per compute unit, 8 per SIMD)
+  const int64_t waves = std::max<int64_t>(4, 8192 / sh.ngroups);
+  const int64_t K = (L + waves - 1) / waves;
+  sh.K = std::max<int64_t>(kAdjRound, (K + kAdjRound - 1) / kAdjRound * kAdjRound);
+  sh.nwg = (L + 4 * sh.K - 1) / (4 * sh.K);
+  return sh;
 }
 
 template <typename R>
-__global__ __launch_bounds__(kAdjThreads) void adjoint_sparse_kernel(
-    int64_t L, int64_t natoms, const double* __restrict__ AB, const cpx<R>* __restrict__ vis,
-    const int32_t* __restrict__ perm, const Atom<R>* __restrict__ atoms,
-    R* __restrict__ partial, int64_t nwaves) {
-  const int64_t k0 = (int64_t)blockIdx.x * kVisChunk + threadIdx.x;
-  double A[kVPT], B[kVPT];
-  R hx[kVPT], hy[kVPT];
-#pragma unroll
-  for (int i = 0; i < kVPT; ++i) {
-    const int64_t k = k0 + (int64_t)i * kAdjThreads;
-    if (k < L) {
-      A[i] = AB[2 * k];
-      B[i] = AB[2 * k + 1];
-      const cpx<R> h = vis[perm ? perm[k] : k];
-      hx[i] = h.x;
-      hy[i] = h.y;
-    } else {
-      A[i] = B[i] = 0.0;
-      hx[i] = hy[i] = R(0);
-    }
-  }
-  const int64_t wave = (int64_t)blockIdx.x * (kAdjThreads / 64) + (threadIdx.x >> 6);
-  const bool lane0 = (threadIdx.x & 63) == 0;
-  for (int64_t p = 0; p < natoms; ++p) {
-    const double a = atoms[p].a, b = atoms[p].b;
-    R acc = 0;
-#pragma unroll
-    for (int i = 0; i < kVPT; ++i) {
-      double t = fma(A[i], a, B[i] * b);
-      t -= rint(t);
-      R s, c;
-      sincos_turns<R>(t, s, c);
-      acc = fma(hx[i], c, acc);
-      acc = fma(-hy[i], s, acc);
-    }
-    acc = wave_sum<R>(acc);
-    if (lane0) partial[p * nwaves + wave] = acc;
-  }
+struct VisRec {
+  double A, B;
+  cpx<R> h;
+};
+
+template <typename R>
+__device__ __forceinline__ void adj_pair(const VisRec<R>& v, double a, double b, R& acc) {
+  double t = fma(v.A, a, v.B * b);
+  t -= rint(t);
+  R sn, cs;
+  sincos_turns<R>(t, sn, cs);
+  acc = fma(v.h.x, cs, acc);
+  acc = fma(-v.h.y, sn, acc);
 }
 
-// out[p] = (1/n_p) sum_w partial[p][w], FP64, one wave per atom.
 template <typename R>
-__global__ __launch_bounds__(64) void adjoint_sparse_reduce_kernel(
-    int64_t natoms, int64_t nwaves, const R* __restrict__ partial,
-    const Atom<R>* __restrict__ atoms, double* __restrict__ out) {
+__device__ __forceinline__ VisRec<R> load_vis(int64_t k, int64_t k1, const double* __restrict__ AB,
+                                              const cpx<R>* __restrict__ vis,
+                                              const int32_t* __restrict__ perm) {
+  VisRec<R> r{0.0, 0.0, {R(0), R(0)}};  // past the chunk: contributes zero
+  if (k < k1) {
+    r.A = AB[2 * k];
+    r.B = AB[2 * k + 1];
+    r.h = vis[perm ? perm[k] : k];
+  }
+  return r;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void adjoint_sparse_kernel(
+    int64_t L, int64_t natoms, int lgA, int64_t K, int64_t nwg, const double* __restrict__ AB,
+    const cpx<R>* __restrict__ vis, const int32_t* __restrict__ perm,
+    const Atom<R>* __restrict__ atoms, R* __restrict__ partial) {
+  constexpr int T = kAdjRound;
+  constexpr int PER = T / 64;  // staged visibilities per lane and round
+  static_assert(T % 128 == 0, "a round must hold 4 x 32 visibilities");
+  __shared__ VisRec<R> stage[4][2][T];
+  __shared__ R red[4][64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int A = 1 << lgA;
+  const int V = 64 >> lgA;
+  const int ai = lane & (A - 1), st = lane >> lgA;
+  const int64_t grp = (int64_t)blockIdx.x / nwg, wg = (int64_t)blockIdx.x - grp * nwg;
+  const int64_t p = grp * A + ai;
+  const bool live = p < natoms;
+  const double a = atoms[live ? p : 0].a, b = atoms[live ? p : 0].b;
+  const int64_t k0 = (wg * 4 + w) * K;
+  const int64_t k1 = k0 + K < L ? k0 + K : L;
+  const int nround = k1 > k0 ? (int)((k1 - k0 + T - 1) / T) : 0;
+  VisRec<R> nxt[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) nxt[q] = load_vis<R>(k0 + q * 64 + lane, k1, AB, vis, perm);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) stage[w][0][q * 64 + lane] = nxt[q];
+  wave_sync();
+  R acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  for (int j = 0; j < nround; ++j) {
+    const int64_t kn = k0 + (int64_t)(j + 1) * T;
+    if (j + 1 < nround) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) nxt[q] = load_vis<R>(kn + q * 64 + lane, k1, AB, vis, perm);
+    }
+    const VisRec<R>* cur = stage[w][j & 1];
+    for (int i = st; i < T; i += 4 * V) {  // 4 V <= T (V <= 32)
+      adj_pair<R>(cur[i], a, b, acc0);
+      adj_pair<R>(cur[i + V], a, b, acc1);
+      adj_pair<R>(cur[i + 2 * V], a, b, acc2);
+      adj_pair<R>(cur[i + 3 * V], a, b, acc3);
+    }
+    if (j + 1 < nround) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) stage[w][(j + 1) & 1][q * 64 + lane] = nxt[q];
+    }
+    wave_sync();
+  }
+  R acc = (acc0 + acc1) + (acc2 + acc3);
+  for (int o = A; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && lane < A && live)
+    partial[p * nwg + wg] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// out[p] = (1/n_p) sum_c partial[p][c], FP64, one workgroup per atom.
+template <typename R>
+__global__ __launch_bounds__(256) void adjoint_sparse_reduce_kernel(
+    int64_t natoms, int64_t nwg, const R* __restrict__ partial, const Atom<R>* __restrict__ atoms,
+    double* __restrict__ out) {
+  __shared__ double red[4];
   const int64_t p = blockIdx.x;
-  const R* row = partial + p * nwaves;
+  const R* row = partial + p * nwg;
   double s = 0;
-  for (int64_t w = threadIdx.x; w < nwaves; w += 64) s += (double)row[w];
-  s = wave_sum<double>(s);
-  if (threadIdx.x == 0) out[p] = s * atoms[p].inv_n;
+  for (int64_t c = threadIdx.x; c < nwg; c += 256) s += (double)row[c];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[p] = (((red[0] + red[1]) + red[2]) + red[3]) * atoms[p].inv_n;
 }
 
 template <typename R>
@@ -190,30 +263,29 @@ void forward_atoms(pc_plan* p, int64_t natoms, const Atom<R>* atoms, const cpx<R
 
 // Partial-sum buffer size, in doubles (the kernels store R values in it).
 int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms) {
-  const int64_t nwaves = ((p->L + kVisChunk - 1) / kVisChunk) * (kAdjThreads / 64);
-  return nwaves * std::max<int64_t>(natoms, 1);
+  const AdjShape sh = adjoint_shape(p->L, std::max<int64_t>(natoms, 1));
+  return sh.nwg * std::max<int64_t>(natoms, 1);
 }
 
 template <typename R>
 void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                    const Atom<R>* atoms, double* partial, double* out, hipStream_t s) {
   if (natoms <= 0) return;
-  const int64_t nblocks = (p->L + kVisChunk - 1) / kVisChunk;
-  const int64_t nwaves = nblocks * (kAdjThreads / 64);
+  const AdjShape sh = adjoint_shape(p->L, natoms);
   R* part = reinterpret_cast<R*>(partial);
   {
     ProfScope ps(p, s, sizeof(R) == 4 ? "adjoint_sparse" : "adjoint_sparse_f64",
-                 p->L * (16 + 2.0 * sizeof(R)) + (double)sizeof(R) * nwaves * natoms,
+                 p->L * (16 + 2.0 * sizeof(R)) * sh.ngroups + (double)sizeof(R) * sh.nwg * natoms,
                  (double)p->L * natoms);
-    hipLaunchKernelGGL((adjoint_sparse_kernel<R>), dim3((unsigned)nblocks), dim3(kAdjThreads), 0, s,
-                       p->L, natoms, p->AB, vis, vis_sorted ? nullptr : p->perm, atoms, part,
-                       nwaves);
+    hipLaunchKernelGGL((adjoint_sparse_kernel<R>), dim3((unsigned)(sh.nwg * sh.ngroups)),
+                       dim3(256), 0, s, p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, vis,
+                       vis_sorted ? nullptr : p->perm, atoms, part);
     PC_LAUNCH_CHECK("adjoint_sparse");
   }
-  ProfScope ps(p, s, "adjoint_sparse_reduce", (double)sizeof(R) * nwaves * natoms,
-               (double)nwaves * natoms);
-  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3((unsigned)natoms), dim3(64), 0, s,
-                     natoms, nwaves, (const R*)part, atoms, out);
+  ProfScope ps(p, s, "adjoint_sparse_reduce", (double)sizeof(R) * sh.nwg * natoms,
+               (double)sh.nwg * natoms);
+  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3((unsigned)natoms), dim3(256), 0, s,
+                     natoms, sh.nwg, (const R*)part, atoms, out);
   PC_LAUNCH_CHECK("adjoint_sparse_reduce");
 }
 

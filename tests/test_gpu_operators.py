@@ -111,14 +111,17 @@ def test_forward_sparse_empty_and_centre():
     assert np.allclose(o.real, 2.5, rtol=0, atol=1e-6) and np.allclose(o.imag, 0, atol=1e-6)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2_small"])
-def test_adjoint_sparse(name):
-    say("adjoint_sparse", name)
+@pytest.mark.parametrize("name,natoms", [("c1", 1), ("c1", 2), ("c1", 3), ("c1", 7), ("c1", 33),
+                                          ("c1", 64), ("c1", 65), ("c1", 300),
+                                          ("c2_small", 1), ("c2_small", 300)])
+def test_adjoint_sparse(name, natoms):
+    """Every atoms-per-wave shape (1..64 and ragged last groups)."""
+    say("adjoint_sparse", name, natoms)
     p, vis = problem(name)
     a = api()
     plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
     rng = np.random.default_rng(3)
-    pix = np.sort(rng.choice(p.npix ** 2, 300, replace=False)).astype(np.int32)
+    pix = np.sort(rng.choice(p.npix ** 2, natoms, replace=False)).astype(np.int32)
     out = a.pc_adjoint_sparse(plan, to_dev(vis), to_dev(pix))
     torch.cuda.synchronize()
     want = operator.adjoint_pixels(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128), pix)
