@@ -198,6 +198,29 @@ PC_API pc_status pc_adjoint_grid_f64(pc_plan* plan, const void* vis, double* ima
                               double* max_abs, int64_t* argmax, void* stream);
 PC_API pc_status pc_forward_sparse_f64(pc_plan* plan, int64_t natoms, const int32_t* pix,
                                 const double* weight, void* vis_out, void* stream);
+/* Restricted adjoint in double: vis complex128 [nvis] caller order,
+ * out double [natoms]. */
+PC_API pc_status pc_adjoint_sparse_f64(pc_plan* plan, const void* vis, int64_t natoms,
+                                       const int32_t* pix, double* out, void* stream);
+/* Dual certificate in double: vis complex128, weight double, cert double. */
+PC_API pc_status pc_dual_certificate_f64(pc_plan* plan, const void* vis, int64_t natoms,
+                                         const int32_t* pix, const double* weight,
+                                         double lambda, double* cert, double* max_abs,
+                                         int64_t* argmax, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched gridded adjoint: pc_adjoint_grid for njobs FP32 plans of any sizes
+ * on the current device in shared launches (one spreading launch, one fold,
+ * one launch per fine-grid size for each FFT pass).  plans, vis, images
+ * are host arrays of njobs pointers (vis[j] dev complex64 [nvis_j] caller
+ * order, images[j] dev float [npix_j^2]); max_abs / argmax are host arrays
+ * of njobs entries or NULL (then the call returns without waiting).  Every
+ * image equals that plan's pc_adjoint_grid result bit for bit.  Calls are
+ * serialised within the process; a plan must not appear twice in one call.
+ * ------------------------------------------------------------------------- */
+PC_API pc_status pc_adjoint_grid_batch(pc_plan* const* plans, const void* const* vis,
+                                       float* const* images, int32_t njobs, double* max_abs,
+                                       int64_t* argmax, void* stream);
 
 /* ---------------------------------------------------------------------------
  * PolyCLEAN solve (Alg. 2)

@@ -89,6 +89,10 @@ SIGNATURES = {
     "pc_dual_certificate": (C.c_int, [_P, _P, _I64, _P, _P, C.c_double, _P, _PD, _PI64, _P]),
     "pc_adjoint_grid_f64": (C.c_int, [_P, _P, _P, _PD, _PI64, _P]),
     "pc_forward_sparse_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P]),
+    "pc_adjoint_sparse_f64": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "pc_dual_certificate_f64": (C.c_int, [_P, _P, _I64, _P, _P, C.c_double, _P, _PD, _PI64, _P]),
+    "pc_adjoint_grid_batch": (C.c_int, [C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.c_int32,
+                                        _PD, _PI64, _P]),
     "pc_solve_params_default": (None, [C.POINTER(PcSolveParams)]),
     "pc_polyclean_solve": (C.c_int, [_P, _P, C.POINTER(PcSolveParams),
                                      C.POINTER(PcSolveResult), _P]),

@@ -215,6 +215,63 @@ def pc_dual_certificate(plan: Plan, vis: torch.Tensor, pix: torch.Tensor, weight
     return cert, (mx.value if want_max else None), (am.value if want_max else None)
 
 
+def pc_adjoint_sparse_f64(plan: Plan, vis: torch.Tensor, pix: torch.Tensor,
+                          out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    na = int(pix.numel())
+    if out is None:
+        out = _new(plan, (na,), torch.float64)
+    check(LIB.pc_adjoint_sparse_f64(plan.handle,
+                                    C.c_void_p(_dev(vis, torch.complex128, plan.nvis, "vis")), na,
+                                    C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+                                    C.c_void_p(_dev(out, torch.float64, na, "out")),
+                                    C.c_void_p(_stream(stream))), "pc_adjoint_sparse_f64")
+    return out
+
+
+def pc_dual_certificate_f64(plan: Plan, vis: torch.Tensor, pix: torch.Tensor,
+                            weight: torch.Tensor, lam: float, cert: Optional[torch.Tensor] = None,
+                            want_max: bool = True, stream=None):
+    n, na = plan.npix, int(pix.numel())
+    if cert is None:
+        cert = _new(plan, (n, n), torch.float64)
+    mx, am = C.c_double(0), C.c_int64(-1)
+    check(LIB.pc_dual_certificate_f64(plan.handle,
+                                      C.c_void_p(_dev(vis, torch.complex128, plan.nvis, "vis")),
+                                      na, C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+                                      C.c_void_p(_dev(weight, torch.float64, na, "weight")),
+                                      float(lam),
+                                      C.c_void_p(_dev(cert, torch.float64, n * n, "cert")),
+                                      C.byref(mx) if want_max else None,
+                                      C.byref(am) if want_max else None,
+                                      C.c_void_p(_stream(stream))), "pc_dual_certificate_f64")
+    return cert, (mx.value if want_max else None), (am.value if want_max else None)
+
+
+def pc_adjoint_grid_batch(plans, vis, images=None, want_max: bool = True, stream=None):
+    """Gridded adjoints of several FP32 plans in shared launches; returns
+    (images, max_abs list, argmax list)."""
+    n = len(plans)
+    if len(vis) != n:
+        raise ValueError("one visibility tensor per plan")
+    if images is None:
+        images = [_new(p, (p.npix, p.npix), torch.float32) for p in plans]
+    P = (C.c_void_p * max(n, 1))()
+    Vp = (C.c_void_p * max(n, 1))()
+    Ip = (C.c_void_p * max(n, 1))()
+    for j, (p, v, im) in enumerate(zip(plans, vis, images)):
+        P[j] = p.handle.value if isinstance(p.handle, C.c_void_p) else p.handle
+        Vp[j] = _dev(v, torch.complex64, p.nvis, "vis")
+        Ip[j] = _dev(im, torch.float32, p.npix * p.npix, "image")
+    mx = (C.c_double * max(n, 1))()
+    am = (C.c_int64 * max(n, 1))()
+    check(LIB.pc_adjoint_grid_batch(P, Vp, Ip, n, mx if want_max else None,
+                                    am if want_max else None, C.c_void_p(_stream(stream))),
+          "pc_adjoint_grid_batch")
+    if not want_max:
+        return images, None, None
+    return images, [mx[j] for j in range(n)], [am[j] for j in range(n)]
+
+
 def solve_params(**kw) -> PcSolveParams:
     p = PcSolveParams()
     LIB.pc_solve_params_default(C.byref(p))

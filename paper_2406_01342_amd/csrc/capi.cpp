@@ -1,7 +1,10 @@
 // The extern "C" boundary: argument validation, error capture, dispatch.
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -54,6 +57,11 @@ static void check_atoms(const pc_plan* p, int64_t natoms, const void* pix, const
 }
 
 static void set_device(const pc_plan* p) { PC_HIP(hipSetDevice(p->device)); }
+
+// Launch tables of pc_adjoint_grid_batch, per device (calls are serialised).
+constexpr int kMaxDevices = 64;
+static std::mutex g_batch_mutex;
+static BatchCtx g_batch_ctx[kMaxDevices];
 
 }  // namespace pc
 
@@ -152,6 +160,68 @@ pc_status pc_forward_sparse_f64(pc_plan* p, int64_t natoms, const int32_t* pix,
     set_device(p);
     forward_sparse<double>(p, natoms, pix, weight, nullptr, false, (c64*)vis_out, false,
                            (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
+pc_status pc_adjoint_sparse_f64(pc_plan* p, const void* vis, int64_t natoms, const int32_t* pix,
+                                double* out, void* stream) {
+  return guard("pc_adjoint_sparse_f64", [&] {
+    check_plan(p, PC_PREC_FP64);
+    check_atoms(p, natoms, pix, nullptr, false);
+    PC_REQUIRE(vis != nullptr, "vis is NULL");
+    if (natoms > 0) PC_REQUIRE(out != nullptr, "out is NULL");
+    set_device(p);
+    adjoint_sparse<double>(p, (const c64*)vis, false, natoms, pix, out, (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
+pc_status pc_dual_certificate_f64(pc_plan* p, const void* vis, int64_t natoms, const int32_t* pix,
+                                  const double* weight, double lambda, double* cert,
+                                  double* max_abs, int64_t* argmax, void* stream) {
+  return guard("pc_dual_certificate_f64", [&] {
+    check_plan(p, PC_PREC_FP64);
+    check_atoms(p, natoms, pix, weight, true);
+    PC_REQUIRE(vis != nullptr && cert != nullptr, "vis and cert must not be NULL");
+    PC_REQUIRE(std::isfinite(lambda) && lambda > 0, "lambda must be finite and > 0");
+    if (p->g.M > 8192) fail(PC_ERR_UNSUPPORTED, "FP64 twin supports fine grids up to 8192");
+    set_device(p);
+    hipStream_t s = (hipStream_t)stream;
+    c64* r = (c64*)p->vis_scratch;
+    forward_sparse<double>(p, natoms, pix, weight, (const c64*)vis, false, r, true, s);
+    adjoint_grid<double>(p, r, true, cert, 1.0 / lambda, s);
+    if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
+    return PC_OK;
+  });
+}
+
+pc_status pc_adjoint_grid_batch(pc_plan* const* plans, const void* const* vis,
+                                float* const* images, int32_t njobs, double* max_abs,
+                                int64_t* argmax, void* stream) {
+  return guard("pc_adjoint_grid_batch", [&] {
+    PC_REQUIRE(njobs >= 0, "njobs must be >= 0");
+    if (njobs == 0) return PC_OK;
+    PC_REQUIRE(plans && vis && images, "NULL argument");
+    int dev = -1;
+    PC_HIP(hipGetDevice(&dev));
+    for (int j = 0; j < njobs; ++j) {
+      check_plan(plans[j], PC_PREC_FP32);
+      PC_REQUIRE(vis[j] != nullptr && images[j] != nullptr, "vis and image must not be NULL");
+      PC_REQUIRE(plans[j]->device == dev, "every plan must live on the current device");
+      for (int i = 0; i < j; ++i) PC_REQUIRE(plans[i] != plans[j], "a plan appears twice");
+    }
+    PC_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index");
+    std::lock_guard<std::mutex> lk(g_batch_mutex);
+    std::unique_ptr<bool[]> sorted(new bool[njobs]);
+    for (int j = 0; j < njobs; ++j) sorted[j] = false;
+    hipStream_t s = (hipStream_t)stream;
+    adjoint_grid_batch(g_batch_ctx[dev], plans, (const c32* const*)vis, sorted.get(), images,
+                       nullptr, njobs, s);
+    if (max_abs || argmax) {
+      for (int j = 0; j < njobs; ++j)
+        maxkey_read(plans[j], s, max_abs ? max_abs + j : nullptr, argmax ? argmax + j : nullptr);
+    }
     return PC_OK;
   });
 }

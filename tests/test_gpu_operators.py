@@ -226,3 +226,46 @@ def test_adjoint_grid_full_c2_sampled():
     assert err <= TOL
     # the GPU maximum is at least as large as every sampled oracle value
     assert np.max(np.abs(want)) <= abs(want[np.searchsorted(pix, am)]) * (1 + TOL)
+
+
+def test_adjoint_grid_batch_equals_single():
+    """Shared launches over plans of different grid and visibility sizes give
+    every plan's own gridded adjoint bit for bit, and the same maxima."""
+    a = api()
+    cases = []
+    for name in ("c1", "c2_small", "c3_small"):
+        p, vis = problem(name)
+        cases.append((a.pc_plan_create(p.uv, p.npix, p.fov_rad), to_dev(vis)))
+    uv, n, fov, h = ragged_problem()
+    cases.append((a.pc_plan_create(uv, n, fov), to_dev(h)))
+    plans = [c[0] for c in cases]
+    vis = [c[1] for c in cases]
+    say("batched adjoint over", [p.npix for p in plans])
+    singles = []
+    for pl, v in cases:
+        img = torch.empty((pl.npix, pl.npix), dtype=torch.float32, device="cuda")
+        _, mx, am = a.pc_adjoint_grid(pl, v, img)
+        singles.append((img, mx, am))
+    for rep in range(2):  # the second call reuses the launch tables
+        imgs, mxs, ams = a.pc_adjoint_grid_batch(plans, vis)
+        torch.cuda.synchronize()
+        for (img, mx, am), bi, bm, ba in zip(singles, imgs, mxs, ams):
+            assert torch.equal(img, bi)
+            assert mx == bm and am == ba
+    # a single-plan batch and an empty batch
+    imgs, mxs, ams = a.pc_adjoint_grid_batch(plans[:1], vis[:1])
+    assert torch.equal(imgs[0], singles[0][0])
+    assert a.pc_adjoint_grid_batch([], [])[0] == []
+
+
+def test_adjoint_grid_batch_rejects_bad_input():
+    a = api()
+    p, vis = problem("c1")
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    dv = to_dev(vis)
+    with pytest.raises(a.PolycleanError):
+        a.pc_adjoint_grid_batch([plan, plan], [dv, dv])  # the same plan twice
+    plan64 = a.pc_plan_create(p.uv, p.npix, p.fov_rad, precision=a.PC_PREC_FP64)
+    with pytest.raises(a.PolycleanError):
+        a.pc_adjoint_grid_batch([plan64], [dv], images=[torch.empty((p.npix, p.npix),
+                                                                    device="cuda")])
