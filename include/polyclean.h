@@ -239,6 +239,12 @@ typedef struct {
   int32_t positivity;     /* must be 0 (positivity: PC_ERR_UNSUPPORTED)       */
   int32_t want_certificate; /* 1: write mu to result->cert                    */
   int32_t log_every;      /* > 0: print an iteration log line every n iters   */
+  int32_t grid_atoms;     /* active-set size from which the APGD step applies */
+                          /*   Phi_S and Phi_S* through the gridded operators */
+                          /*   (type 2 / type 1, Sect. 5.2) instead of direct */
+                          /*   sums: 0 = the built-in cost crossover, < 0 =   */
+                          /*   never.  The per-iteration residual and gap use */
+                          /*   the gridded forward from 4x that size.         */
 } pc_solve_params;
 
 typedef struct {

@@ -47,7 +47,8 @@ class PcSolveParams(C.Structure):
                 ("max_iter", C.c_int32), ("rel_obj_tol", C.c_double), ("rel_gap_tol", C.c_double),
                 ("inner_tol0", C.c_double), ("inner_tol_min", C.c_double),
                 ("inner_max_iter", C.c_int32), ("positivity", C.c_int32),
-                ("want_certificate", C.c_int32), ("log_every", C.c_int32)]
+                ("want_certificate", C.c_int32), ("log_every", C.c_int32),
+                ("grid_atoms", C.c_int32)]
 
 
 class PcSolveResult(C.Structure):

@@ -198,6 +198,34 @@ __global__ void scale_kernel(int64_t N, const float* __restrict__ in, float s,
   if (j < N) out[j] = in[j] * s;
 }
 
+// img[pix[a]] = vals[a] (vals NULL: 0), for the gridded operators on an
+// active set.
+__global__ void scatter_kernel(int64_t nS, const int32_t* __restrict__ pix,
+                               const double* __restrict__ vals, float* __restrict__ img) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < nS) img[pix[a]] = vals ? (float)vals[a] : 0.0f;
+}
+
+__global__ void gather_img_kernel(int64_t nS, const int32_t* __restrict__ pix,
+                                  const float* __restrict__ img, double* __restrict__ out) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < nS) out[a] = (double)img[pix[a]];
+}
+
+__global__ void fill_kernel(int64_t N, float v, float* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) out[j] = v;
+}
+
+// r = V - r (both in plan order)
+__global__ void rsub_kernel(int64_t L, const cpx<float>* __restrict__ V, cpx<float>* __restrict__ r) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < L) {
+    const cpx<float> v = V[k], m = r[k];
+    r[k] = {v.x - m.x, v.y - m.y};
+  }
+}
+
 // ----------------------------------------------------------------------------
 static unsigned blocks(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
@@ -250,6 +278,30 @@ void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipS
   if (nS <= 0) return;
   hipLaunchKernelGGL(weights_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, x, atoms);
   PC_LAUNCH_CHECK("weights");
+}
+
+void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, float* img,
+               hipStream_t s) {
+  if (nS <= 0) return;
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, pix, vals, img);
+  PC_LAUNCH_CHECK("scatter");
+}
+
+void k_gather_img(pc_plan* p, int64_t nS, const int32_t* pix, const float* img, double* out,
+                  hipStream_t s) {
+  if (nS <= 0) return;
+  hipLaunchKernelGGL(gather_img_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, pix, img, out);
+  PC_LAUNCH_CHECK("gather_img");
+}
+
+void k_fill(pc_plan* p, int64_t N, float v, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, v, out);
+  PC_LAUNCH_CHECK("fill");
+}
+
+void k_rsub(pc_plan* p, int64_t L, const c32* V, c32* r, hipStream_t s) {
+  hipLaunchKernelGGL(rsub_kernel, dim3(blocks(L, 256)), dim3(256), 0, s, L, V, r);
+  PC_LAUNCH_CHECK("rsub");
 }
 
 void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipStream_t s) {

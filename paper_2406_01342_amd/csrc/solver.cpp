@@ -20,6 +20,7 @@
 // nu = min(1, lambda / ||Phi* r||_inf) r.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -60,6 +61,7 @@ struct Pfw {
   int64_t L, N;
   DevArray<c32> V, r;
   DevArray<float> eta;
+  DevArray<float> dimg;  // dense image for the gridded operators (kept zero)
   DevArray<int32_t> cand, pix;
   DevArray<unsigned> cand_count;
   DevArray<Atom<float>> atoms;
@@ -71,6 +73,7 @@ struct Pfw {
   double lam = 0, lmax = 0, Delta = 0, eta_inf = 0, P_prev = 0, P = 0, rel_gap = 0, gap = 0;
   int64_t eta_argmax = -1;
   int k = 0, inner_total = 0;
+  int64_t grid_thr = 0;  // active-set size from which APGD uses gridded operators
   bool done = false, converged = false;
   double adj_ms = 0;
   int adj_calls = 0;
@@ -140,8 +143,52 @@ struct Pfw {
     PC_HIP(hipStreamSynchronize(s));
   }
 
+  // Crossover between the direct sums (cost ~ L nS) and the gridded
+  // operators (cost ~ L + band cells): from the measured rates on gfx950,
+  // about 0.4 ps per visibility-atom pair per direction against 0.2 ns per
+  // visibility plus 8 ps per band cell.
+  int64_t grid_crossover() const {
+    if (prm.grid_atoms > 0) return prm.grid_atoms;
+    if (prm.grid_atoms < 0) return INT64_MAX / 8;
+    const double cells = (double)p->g.nu * (double)p->g.nv;
+    return (int64_t)(500.0 + 20.0 * cells / (double)L);
+  }
+
+  void ensure_dimg() {
+    if (dimg.ptr) return;
+    dimg.ensure(N);
+    k_fill(p, N, 0.0f, dimg.ptr, s);
+  }
+
+  // out = base - Phi_S w (base = V) or Phi_S w (no base), in plan order.  The
+  // direct path takes the weights from the atom table; the gridded one
+  // scatters w into the (zero) dense image, interpolates, and clears it.
+  void op_forward(bool gridded, int64_t nS, const double* w, bool base, c32* out) {
+    if (!gridded) {
+      forward_atoms<float>(p, nS, atoms.ptr, base ? V.ptr : nullptr, true, out, true, s);
+      return;
+    }
+    ensure_dimg();
+    k_scatter(p, nS, pix.ptr, w, dimg.ptr, s);
+    forward_grid<float>(p, dimg.ptr, out, true, s);
+    k_scatter(p, nS, pix.ptr, nullptr, dimg.ptr, s);
+    if (base) k_rsub(p, L, V.ptr, out, s);
+  }
+
+  // g = Phi_S* r (FP64), directly or as the gridded adjoint sampled at S
+  // (eta serves as scratch: it is recomputed after the APGD step).
+  void op_adjoint(bool gridded, int64_t nS, const c32* rr, double* gout) {
+    if (!gridded) {
+      adjoint_atoms<float>(p, rr, true, nS, atoms.ptr, adj_partial.ptr, gout, s);
+      return;
+    }
+    adjoint_grid<float>(p, rr, true, eta.ptr, 1.0f, s);
+    k_gather_img(p, nS, pix.ptr, eta.ptr, gout, s);
+  }
+
   void init(const void* vis_caller) {
     t0 = now();
+    grid_thr = grid_crossover();
     V.ensure(L);
     r.ensure(L);
     eta.ensure(N);
@@ -172,7 +219,7 @@ struct Pfw {
   // operator pair, warm-started from the previous active set's eigenvector
   // (new atoms enter at 1/sqrt(nS)); stops when successive estimates agree
   // to kPowerTol (tested every kPowerCheck iterations) or after kPowerIters.
-  double power_iteration(const std::vector<int32_t>& set) {
+  double power_iteration(const std::vector<int32_t>& set, bool gridded) {
     const int64_t nS = (int64_t)set.size();
     std::vector<double> v0(nS, 1.0 / std::sqrt((double)nS));
     for (size_t a = 0, b = 0; a < pv_set.size() && b < set.size();) {
@@ -194,8 +241,8 @@ struct Pfw {
     k_weights(p, nS, v.ptr, atoms.ptr, s);
     double e[2] = {0, 0};
     for (int it = 1; it <= kPowerIters; ++it) {
-      forward_atoms<float>(p, nS, atoms.ptr, nullptr, true, r.ptr, true, s);
-      adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, g.ptr, s);
+      op_forward(gridded, nS, v.ptr, false, r.ptr);
+      op_adjoint(gridded, nS, r.ptr, g.ptr);
       k_power(p, nS, g.ptr, v.ptr, atoms.ptr, scal.ptr, s);
       if (it >= kPowerCheck && (it % kPowerCheck == 0 || it == kPowerIters)) {
         read_scal(e, kScalEig, 2);
@@ -241,15 +288,16 @@ struct Pfw {
     load_active(Sn, xw);
     // 2. APGD on the restricted problem
     int inner = 0;
+    const bool gridded = nS >= grid_thr;
     if (nS > 0) {
-      const double lip = power_iteration(Sn) * kLipMargin;
+      const double lip = power_iteration(Sn, gridded) * kLipMargin;
       double hs[2] = {lip, 1.0};
       PC_HIP(hipMemcpyAsync(scal.ptr + kScalLip, hs, 2 * sizeof(double), hipMemcpyHostToDevice, s));
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
       const double tol = std::max(prm.inner_tol_min, prm.inner_tol0 * rel_gap);
       for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
-        forward_atoms<float>(p, nS, atoms.ptr, V.ptr, true, r.ptr, true, s);
-        adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, g.ptr, s);
+        op_forward(gridded, nS, y.ptr, true, r.ptr);
+        op_adjoint(gridded, nS, r.ptr, g.ptr);
         const bool check = (inner - 1) % kCheck == 0;
         if (check) {
           red_partial.ensure(2 * k_resid_blocks(L));
@@ -281,7 +329,7 @@ struct Pfw {
       }
     // 4. residual, dirty residual, objective and gap
     load_active(S, xs);
-    forward_atoms<float>(p, (int64_t)S.size(), atoms.ptr, V.ptr, true, r.ptr, true, s);
+    op_forward((int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
     adjoint_timed(r.ptr);
     double r2, vr;
     residual_stats(r2, vr);

@@ -31,5 +31,12 @@ void k_power(pc_plan* p, int64_t nS, const double* gv, double* v, Atom<float>* a
 void k_power_init(pc_plan* p, int64_t nS, double* v, Atom<float>* atoms, hipStream_t s);
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s);
 void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipStream_t s);
+// Gridded-operator helpers for large active sets.
+void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, float* img,
+               hipStream_t s);
+void k_gather_img(pc_plan* p, int64_t nS, const int32_t* pix, const float* img, double* out,
+                  hipStream_t s);
+void k_rsub(pc_plan* p, int64_t L, const c32* V, c32* r, hipStream_t s);
+void k_fill(pc_plan* p, int64_t N, float v, float* out, hipStream_t s);
 
 }  // namespace pc
