@@ -60,6 +60,13 @@ using c64 = cpx<double>;
 constexpr int kTile = 32;
 constexpr int kMaxWidth = 16;
 
+// Spreading register window: a wave's lanes cover a spread_span(W)-wide
+// square of cells, the union of the footprints of all visibilities whose
+// first cell lies in one spread_block(W)-wide square block.  The plan sorts
+// visibilities by that block within each tile.
+__host__ __device__ constexpr int spread_span(int W) { return W <= 8 ? 8 : W; }
+__host__ __device__ constexpr int spread_block(int W) { return spread_span(W) - W + 1; }
+
 // One spreading work item: an output tile plus the (sub)ranges of sorted
 // visibilities that reach it from the tile itself and from its left, upper
 // and upper-left neighbours.  slot >= 0 means the tile is split across

@@ -53,39 +53,69 @@ __device__ __forceinline__ int tile_base(int c, int origin, int M, int W, int wr
 }
 
 // Spreading layout: one wave per work item owns the output tile in LDS
-// (planar re/im, row stride kTile + W so that the W x W taps of one
-// visibility fall in distinct banks).  It stages 64 visibilities at a time
-// (one per lane: cell bases, value and the 2W separable kernel weights), then
-// walks them in order with its lanes mapped to the W x W taps.  Each lane
-// accumulates its tap in registers while consecutive visibilities share a
-// first cell (they are sorted by it) and adds the sum into LDS when the cell
-// changes.  No LDS atomics (whose per-lane serialisation made them the
-// bottleneck), and each cell receives its contributions in a fixed order, so
-// the result is bitwise reproducible.  Hot tiles are split across work items
-// upstream.
+// (planar re/im, row stride kTile + BS).  Its lanes cover a BS x BS window of
+// cells (BS = 8 for kernel widths up to 8, else W): the union of the
+// footprints of every visibility whose first cell lies in one RB x RB block
+// (RB = BS - W + 1; 3 x 3 first cells for W = 6).  Visibilities are sorted by
+// that block, so a run of them shares the window: each lane adds its cell's
+// weight times the value into a register, and the sums go to LDS (a plain
+// read-add-write: the lanes of one instruction address distinct cells and a
+// wave's LDS operations complete in order) only when the block changes.  The
+// wave stages 64 visibilities at a time, one per lane: the block key, the
+// value, and the kernel weights already shifted onto the window's rows and
+// columns (zero outside the visibility's own footprint), so that in the
+// accumulation loop a lane reads its two weights at fixed offsets and spends
+// one multiply and two FMAs per visibility.  No LDS atomics (whose per-lane
+// serialisation made them the bottleneck), and each cell receives its
+// contributions in a fixed order, so the result is bitwise reproducible.
+// Hot tiles are split across work items upstream.
 template <typename R, int W>
 struct SpreadCfg {
-  static constexpr int NW = 1;                 // waves per workgroup
-  static constexpr int S = kTile + W;          // LDS row stride
-  static constexpr int TILE = kTile * S;       // reals per plane
-  static constexpr int STG = 64 * (2 * W + 2); // staged reals
-  static constexpr int U = 8;                  // visibilities per inner step
-  static constexpr size_t lds_bytes = sizeof(R) * (2 * TILE + STG) + sizeof(int) * 128;
+  static constexpr int BS = spread_span(W);      // window side (cells)
+  static constexpr int RB = spread_block(W);     // block side (first cells)
+  static constexpr int NPASS = (BS * BS + 63) / 64;
+  static constexpr int S = kTile + BS;           // LDS row stride
+  static constexpr int TILE = kTile * S;         // reals per plane
+  static constexpr int REC = 2 * BS + 4;         // wy[BS], wx[BS], re, im, key, pad
+  static constexpr int STG = 64 * REC;
+  static constexpr int U = 8;                    // visibilities per inner step
+  static constexpr size_t lds_bytes = sizeof(R) * (2 * TILE + STG);
 };
 
-// Adds a run's per-tap register sums into the LDS tile and clears them.
-template <typename R, int W, int S, int NPASS>
-__device__ __forceinline__ void spread_flush(const GridGeom& g, int lane, int cbu, int cbv,
-                                             R (&accr)[NPASS], R (&acci)[NPASS], R* tre, R* tim) {
+// Block key of a window origin (bu, bv) relative to the tile, both in
+// (-BS, kTile): one integer, so that a run test is a single comparison.
+__device__ __forceinline__ int block_key(int bu, int bv) { return ((bv + 64) << 8) | (bu + 64); }
+constexpr int kNoBlock = -1;
+
+// Adds a run's per-cell register sums into the LDS tile and clears them.
+// single: the periodic grid is one tile wide, so window cells left of (or
+// above) the tile wrap onto its other end.
+template <typename R, int W>
+__device__ __forceinline__ void spread_flush(int lane, int key, bool single, int M,
+                                             R (&accr)[SpreadCfg<R, W>::NPASS],
+                                             R (&acci)[SpreadCfg<R, W>::NPASS], R* tre,
+                                             R* tim) {
+  using C = SpreadCfg<R, W>;
+  if (key != kNoBlock) {
+    const int bu = (key & 0xff) - 64, bv = (key >> 8) - 64;
 #pragma unroll
-  for (int ps = 0; ps < NPASS; ++ps) {
-    const int tap = lane + 64 * ps;
-    const int a = tap / W, b = tap - (tap / W) * W;
-    int y, x;
-    if (tap < W * W && tap_local(cbv, a, g.M, g.wrap, y) && tap_local(cbu, b, g.M, g.wrap, x)) {
-      tre[y * S + x] += accr[ps];
-      tim[y * S + x] += acci[ps];
+    for (int ps = 0; ps < C::NPASS; ++ps) {
+      const int tap = lane + 64 * ps;
+      const int a = tap / C::BS, b = tap - (tap / C::BS) * C::BS;
+      int y = bv + a, x = bu + b;
+      if (single) {
+        y &= kTile - 1;
+        x &= kTile - 1;
+      }
+      if ((C::BS * C::BS % 64 == 0 || tap < C::BS * C::BS) && (unsigned)y < (unsigned)kTile &&
+          (unsigned)x < (unsigned)kTile) {
+        tre[y * C::S + x] += accr[ps];
+        tim[y * C::S + x] += acci[ps];
+      }
     }
+  }
+#pragma unroll
+  for (int ps = 0; ps < C::NPASS; ++ps) {
     accr[ps] = R(0);
     acci[ps] = R(0);
   }
@@ -131,14 +161,10 @@ __device__ __forceinline__ void spread_body(
   const int lane = threadIdx.x;
   R* tre = reinterpret_cast<R*>(smem_raw);
   R* tim = tre + C::TILE;
-  R* stg = tim + C::TILE;                             // [64][2W + 2]: ku, kv, re, im
-  int* sbase = reinterpret_cast<int*>(stg + C::STG);  // [64][2]: bu, bv
-  for (int i = lane; i < C::TILE; i += 64) {
-    tre[i] = R(0);
-    tim[i] = R(0);
-  }
+  R* stg = tim + C::TILE;  // [64][REC]
   const int tv = ch.tile / g.ntu, tu = ch.tile - tv * g.ntu;
   const int ov = g.v0 + tv * kTile, ou = g.u0 + tu * kTile;
+  const bool single = g.wrap && g.M == kTile;
   const R inv = R(2) / R(W);
   const R beta = sizeof(R) == 4 ? (R)g.beta : (R)g.beta64;
   // cumulative range boundaries
@@ -147,39 +173,49 @@ __device__ __forceinline__ void spread_body(
   const int c3 = c2 + ch.end[2] - ch.beg[2];
   const int total = c3 + ch.end[3] - ch.beg[3];
   const int b0 = ch.beg[0], b1 = ch.beg[1] - c1, b2 = ch.beg[2] - c2, b3 = ch.beg[3] - c3;
-  constexpr int NPASS = (W * W + 63) / 64;
+  constexpr int NPASS = C::NPASS;
   constexpr int U = C::U;
-  // The global loads of the next batch are issued before the current batch's
-  // tap loop, so their latency overlaps the LDS work.
+  // The first batch's global loads go out before the tile is cleared; each
+  // later batch's before the current batch's accumulation loop.
   VisIn<R> nx{0u, R(0), R(0), {R(0), R(0)}};
   if (lane < total)
     nx = fetch_vis<R>(chunk_index(lane, c1, c2, c3, b0, b1, b2, b3), cell, off, vals, perm);
-  // Visibilities arrive sorted by first cell, so runs sharing a footprint are
-  // summed per tap in registers and written to LDS once per run (a plain
-  // read-add-write: the lanes of one instruction address distinct cells and
-  // a wave's LDS operations complete in order).
-  int cbu = -(1 << 20), cbv = -(1 << 20);
+  for (int i = lane; i < C::TILE; i += 64) {
+    tre[i] = R(0);
+    tim[i] = R(0);
+  }
+  // per-lane window cell (row a, column b) for each pass
+  int ia[NPASS], ib[NPASS];
+#pragma unroll
+  for (int ps = 0; ps < NPASS; ++ps) {
+    const int tap = lane + 64 * ps;
+    const bool ok = C::BS * C::BS % 64 == 0 || tap < C::BS * C::BS;
+    ia[ps] = ok ? tap / C::BS : 0;
+    ib[ps] = ok ? C::BS + tap - (tap / C::BS) * C::BS : C::BS;  // wx row follows wy
+  }
+  int ckey = kNoBlock;
   R accr[NPASS], acci[NPASS];
 #pragma unroll
   for (int ps = 0; ps < NPASS; ++ps) accr[ps] = acci[ps] = R(0);
 #pragma unroll 1
   for (int base = 0; base < total; base += 64) {
-    // stage one visibility per lane; lanes past the end stage a visibility
-    // whose taps all fall outside the tile
+    // stage one visibility per lane: weights shifted onto the window
     const int q = base + lane;
-    R* my = stg + lane * (2 * W + 2);
-    sbase[2 * lane] = -(1 << 20);  // below -M - W: never maps into a tile
-    sbase[2 * lane + 1] = -(1 << 20);
+    R* my = stg + lane * C::REC;
     if (q < total) {
-      sbase[2 * lane] = tile_base((int)(nx.cell & 0xffffu), ou, g.M, W, g.wrap);
-      sbase[2 * lane + 1] = tile_base((int)(nx.cell >> 16), ov, g.M, W, g.wrap);
+      const int cu = (int)(nx.cell & 0xffffu), cv = (int)(nx.cell >> 16);
+      const int du = cu % C::RB, dv = cv % C::RB;
+      const int bu = tile_base(cu - du, ou, g.M, C::BS, g.wrap);
+      const int bv = tile_base(cv - dv, ov, g.M, C::BS, g.wrap);
 #pragma unroll
-      for (int t = 0; t < W; ++t) {
-        my[t] = es_kernel<R>((nx.su + R(t)) * inv, beta);
-        my[W + t] = es_kernel<R>((nx.sv + R(t)) * inv, beta);
+      for (int j = 0; j < C::BS; ++j) {
+        const int ty = j - dv, tx = j - du;  // tap index of window row / column j
+        my[j] = (ty >= 0 && ty < W) ? es_kernel<R>((nx.sv + R(ty)) * inv, beta) : R(0);
+        my[C::BS + j] = (tx >= 0 && tx < W) ? es_kernel<R>((nx.su + R(tx)) * inv, beta) : R(0);
       }
-      my[2 * W] = nx.val.x;
-      my[2 * W + 1] = nx.val.y;
+      my[2 * C::BS] = nx.val.x;
+      my[2 * C::BS + 1] = nx.val.y;
+      reinterpret_cast<int*>(my)[2 * C::BS + 2] = block_key(bu, bv);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -189,37 +225,32 @@ __device__ __forceinline__ void spread_body(
     const int nb = total - base < 64 ? total - base : 64;
 #pragma unroll 1
     for (int v0 = 0; v0 < nb; v0 += U) {
-      int bu[U], bv[U];
+      int key[U];
       R vr[U], vi[U], wg[U][NPASS];
 #pragma unroll
       for (int u = 0; u < U; ++u) {  // issue all LDS reads of the step first
-        const R* kw = stg + (v0 + u) * (2 * W + 2);
-        bu[u] = sbase[2 * (v0 + u)];
-        bv[u] = sbase[2 * (v0 + u) + 1];
-        vr[u] = kw[2 * W];
-        vi[u] = kw[2 * W + 1];
+        const R* kw = stg + (v0 + u) * C::REC;
+        // records past the batch end hold a stale key and stale weights:
+        // their key is replaced by kNoBlock below and their weights unused
+        key[u] = reinterpret_cast<const int*>(kw)[2 * C::BS + 2];
+        vr[u] = kw[2 * C::BS];
+        vi[u] = kw[2 * C::BS + 1];
 #pragma unroll
-        for (int ps = 0; ps < NPASS; ++ps) {
-          // unconditional reads at clamped indices (lanes past the W x W taps
-          // get a zero weight), so all reads of the step issue back to back
-          const int tap = lane + 64 * ps;
-          const int a = tap / W, b = tap - (tap / W) * W;
-          const int ac = a < W ? a : W - 1;
-          const R live = tap < W * W ? R(1) : R(0);
-          wg[u][ps] = kw[W + ac] * kw[b] * live;
-        }
+        for (int ps = 0; ps < NPASS; ++ps) wg[u][ps] = kw[ia[ps]] * kw[ib[ps]];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (bu[u] != cbu || bv[u] != cbv) {  // same for every lane of the wave
-          spread_flush<R, W, C::S, NPASS>(g, lane, cbu, cbv, accr, acci, tre, tim);
-          cbu = bu[u];
-          cbv = bv[u];
-        }
+        if (v0 + u < nb) {
+          const int k = __builtin_amdgcn_readfirstlane(key[u]);
+          if (k != ckey) {  // same for every lane of the wave
+            spread_flush<R, W>(lane, ckey, single, g.M, accr, acci, tre, tim);
+            ckey = k;
+          }
 #pragma unroll
-        for (int ps = 0; ps < NPASS; ++ps) {
-          accr[ps] = fma(wg[u][ps], vr[u], accr[ps]);
-          acci[ps] = fma(wg[u][ps], vi[u], acci[ps]);
+          for (int ps = 0; ps < NPASS; ++ps) {
+            accr[ps] = fma(wg[u][ps], vr[u], accr[ps]);
+            acci[ps] = fma(wg[u][ps], vi[u], acci[ps]);
+          }
         }
       }
     }
@@ -227,7 +258,7 @@ __device__ __forceinline__ void spread_body(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  spread_flush<R, W, C::S, NPASS>(g, lane, cbu, cbv, accr, acci, tre, tim);
+  spread_flush<R, W>(lane, ckey, single, g.M, accr, acci, tre, tim);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -618,7 +649,7 @@ static void launch_spread_w(pc_plan* p, const cpx<R>* vals, const int32_t* perm,
     PC_HIP(hipFuncSetAttribute((const void*)spread_kernel<R, W>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds_bytes));
   ProfScope ps(p, s, "spread", p->L * (4 + 4 * rb) + 2 * rb * p->g.nu * p->g.nv, (double)p->L);
-  hipLaunchKernelGGL((spread_kernel<R, W>), dim3((unsigned)p->n_chunks), dim3(C::NW * 64),
+  hipLaunchKernelGGL((spread_kernel<R, W>), dim3((unsigned)p->n_chunks), dim3(64),
                      C::lds_bytes, s, p->g,
                      p->chunks, p->cell, (const R*)p->off, vals, perm, (cpx<R>*)p->grid,
                      (cpx<R>*)p->partials);

@@ -194,19 +194,25 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     c0u[k] = cu;
     c0v[k] = cv;
   }
-  // Sort by (tile, spill class, first cell within the tile): a stable counting
-  // sort on the tile-local cell, then a stable counting sort on (tile, class).
-  // Visibilities sharing a first cell end up adjacent, which the spreading
-  // kernel exploits by accumulating them in registers.
+  // Sort by (tile, spill class, first-cell block within the tile): a stable
+  // counting sort on the block of the first cell (square blocks of
+  // spread_block(W) cells on the absolute fine grid, counted from the tile's
+  // first block), then a stable counting sort on (tile, class).  Visibilities
+  // sharing a block end up adjacent, which the spreading kernel exploits by
+  // accumulating them in registers over one window.
   std::vector<int32_t> order(L);
   {
-    const int TT = T * T;
-    std::vector<int64_t> c(TT + 1, 0);
+    const int RB = spread_block(W);
+    const int nbk = T / RB + 2;  // blocks a tile's first cells can fall in, per axis
+    std::vector<int64_t> c((size_t)nbk * nbk + 1, 0);
     auto local = [&](int64_t k) {
-      return ((c0v[k] - g.v0) % T) * T + ((c0u[k] - g.u0) % T);
+      const int32_t ou = g.u0 + ((c0u[k] - g.u0) / T) * T;
+      const int32_t ov = g.v0 + ((c0v[k] - g.v0) / T) * T;
+      const int32_t bu = c0u[k] / RB - ou / RB, bv = c0v[k] / RB - ov / RB;
+      return (int64_t)bv * nbk + bu;
     };
     for (int64_t k = 0; k < L; ++k) c[local(k) + 1]++;
-    for (int i = 0; i < TT; ++i) c[i + 1] += c[i];
+    for (size_t i = 0; i + 1 < c.size(); ++i) c[i + 1] += c[i];
     for (int64_t k = 0; k < L; ++k) order[c[local(k)]++] = (int32_t)k;
   }
   std::vector<int64_t> cnt(ntiles * 4 + 1, 0);
