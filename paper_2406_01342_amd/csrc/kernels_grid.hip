@@ -215,7 +215,7 @@ __device__ __forceinline__ void spread_body(
       }
       my[2 * C::BS] = nx.val.x;
       my[2 * C::BS + 1] = nx.val.y;
-      reinterpret_cast<int*>(my)[2 * C::BS + 2] = block_key(bu, bv);
+      *reinterpret_cast<int*>(&my[2 * C::BS + 2]) = block_key(bu, bv);  // in the R-sized slot
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -232,7 +232,7 @@ __device__ __forceinline__ void spread_body(
         const R* kw = stg + (v0 + u) * C::REC;
         // records past the batch end hold a stale key and stale weights:
         // their key is replaced by kNoBlock below and their weights unused
-        key[u] = reinterpret_cast<const int*>(kw)[2 * C::BS + 2];
+        key[u] = *reinterpret_cast<const int*>(&kw[2 * C::BS + 2]);
         vr[u] = kw[2 * C::BS];
         vi[u] = kw[2 * C::BS + 1];
 #pragma unroll
