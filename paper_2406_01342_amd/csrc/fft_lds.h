@@ -103,11 +103,25 @@ __device__ __forceinline__ cpx<R> twiddle(const cpx<R>* tws, int t) {
   return cmul(tws[t & 63], tws[64 + (t >> 6)]);
 }
 
+// Twiddles w^r, r = 1..RAD-1, from w = w^1 by squaring and one multiply
+// per odd power (at most log2(RAD) + 1 roundings each), instead of one
+// table lookup pair and product per power.
+template <typename R, int RAD>
+__device__ __forceinline__ void twiddle_powers(cpx<R> w1, cpx<R>* w) {
+  w[1] = w1;
+#pragma unroll
+  for (int r = 2; r < RAD; ++r) w[r] = (r & 1) ? cmul(w[r - 1], w1) : cmul(w[r / 2], w[r / 2]);
+}
+
 template <typename R, int RAD, int M, int NB, int NT, int SIGN, int NS>
 __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
   constexpr int NBF = M / RAD;
   constexpr int TOT = NB * NBF;
   constexpr int PER = (TOT + NT - 1) / NT;
+  // padded positions of the stage's strided reads and writes: when the
+  // stride is a multiple of 16 the padding adds a constant per step
+  constexpr bool RD_LIN = NBF % 16 == 0;
+  constexpr bool WR_LIN = NS % 16 == 0;
   cpx<R> y[PER][RAD];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -116,15 +130,17 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
       const int b = bi / NBF, j = bi - b * NBF;
       const int k = j & (NS - 1);
       cpx<R> x[RAD];
+      const int i0 = b * M + j;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) x[r] = buf[pidx(b * M + j + r * NBF)];
+      for (int r = 0; r < RAD; ++r)
+        x[r] = RD_LIN ? buf[pidx(i0) + r * padded(NBF)] : buf[pidx(i0 + r * NBF)];
       if constexpr (NS > 1) {
+        cpx<R> w[RAD];
+        cpx<R> w1 = twiddle<R, M>(tw, k * (M / (NS * RAD)));
+        if (SIGN < 0) w1.y = -w1.y;
+        twiddle_powers<R, RAD>(w1, w);
 #pragma unroll
-        for (int r = 1; r < RAD; ++r) {
-          cpx<R> t = twiddle<R, M>(tw, r * k * (M / (NS * RAD)));
-          if (SIGN < 0) t.y = -t.y;
-          x[r] = cmul(x[r], t);
-        }
+        for (int r = 1; r < RAD; ++r) x[r] = cmul(x[r], w[r]);
       }
       dft<R, RAD, SIGN>(x);
 #pragma unroll
@@ -140,7 +156,12 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
       const int k = j & (NS - 1);
       const int base = b * M + (j / NS) * NS * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) buf[pidx(base + r * NS)] = y[q][r];
+      for (int r = 0; r < RAD; ++r) {
+        if (WR_LIN)
+          buf[pidx(base) + r * padded(NS)] = y[q][r];
+        else
+          buf[pidx(base + r * NS)] = y[q][r];
+      }
     }
   }
   __syncthreads();

@@ -391,7 +391,23 @@ __device__ __forceinline__ void gather_to_lds(cpx<R>* buf, const cpx<R>* __restr
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) in turn:
+// workgroup b runs on XCD b mod 8.  Renumbering so that each XCD receives a
+// contiguous range of logical indices keeps neighbouring work (rows that
+// share cache lines of the pass-A buffer) inside one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_local(int b, int n) {
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Pass A of the adjoint: rows of the band grid (fixed v), FFT along u.
+// Element m of a row sits at LDS position pidx(b M + m); a thread's elements
+// are NT apart, so their positions advance by padded(NT).  The occupancy
+// flags of the workgroup's tile rows are read once into LDS: tiles without
+// data were never written and are read as zeros.
+constexpr int kMaxTileCols = 512;  // fine grids up to 16384 cells per side
 template <typename R, int M, int NB, int NT>
 __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* __restrict__ grid,
                                                const uint8_t* __restrict__ tile_flags,
@@ -400,20 +416,33 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
-  load_twiddles<R, M, NT>(tws, tw);
+  constexpr int TR = (NB + kTile - 1) / kTile + 1;  // tile rows a row block can touch
+  __shared__ uint8_t sflag[TR][kMaxTileCols];
   constexpr int n = M / 2;
   const int row0 = rowblock * NB;
-  // tiles without data were never written: read them as zeros
-  gather_to_lds<R, NB * M, NT>(
-      buf, grid,
-      [&](int idx) -> int64_t {
-        const int b = idx / M, m = idx - b * M;
-        const int row = row0 + b, rel = m - g.u0;
-        if (row >= g.nv || (unsigned)rel >= (unsigned)g.nu) return -1;
-        if (!tile_flags[(row / kTile) * g.ntu + rel / kTile]) return -1;
-        return (int64_t)row * g.nu + rel;
-      },
-      [](int idx) { return idx; });
+  const int tr0 = row0 / kTile;
+  for (int i = threadIdx.x; i < TR * g.ntu; i += NT) {
+    const int r = i / g.ntu, c = i - r * g.ntu;
+    sflag[r][c] = (tr0 + r < g.ntv) ? tile_flags[(tr0 + r) * g.ntu + c] : 0;
+  }
+  load_twiddles<R, M, NT>(tws, tw);  // ends with a barrier
+  static_assert((NB * M) % NT == 0 && NT % 16 == 0, "pass-A gather layout");
+  constexpr int IT = NB * M / NT;
+  cpx<R> t[IT];
+  bool ok[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = (int)threadIdx.x + it * NT;
+    const int b = idx / M, m = idx - b * M;
+    const int row = row0 + b, rel = m - g.u0;
+    ok[it] = row < g.nv && (unsigned)rel < (unsigned)g.nu &&
+             sflag[row / kTile - tr0][rel / kTile] != 0;
+    t[it] = grid[ok[it] ? (size_t)row * g.nu + rel : 0];
+  }
+  const int p0 = pidx((int)threadIdx.x);
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+    buf[p0 + it * padded(NT)] = ok[it] ? t[it] : cpx<R>{R(0), R(0)};
   __syncthreads();
   lds_fft<R, M, NB, NT, +1>(buf, tws);
   for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
@@ -432,13 +461,13 @@ __global__ __launch_bounds__(NT) void passA_adj_kernel(GridGeom g, const cpx<R>*
                                                         const uint8_t* __restrict__ tile_flags,
                                                         cpx<R>* __restrict__ H,
                                                         const cpx<R>* __restrict__ tw) {
-  passA_adj_body<R, M, NB, NT>(g, grid, tile_flags, H, tw, blockIdx.x);
+  passA_adj_body<R, M, NB, NT>(g, grid, tile_flags, H, tw, xcd_local(blockIdx.x, gridDim.x));
 }
 
 template <int M, int NB, int NT>
 __global__ __launch_bounds__(NT) void passA_batch_kernel(const AdjJob* __restrict__ jobs,
                                                           const int2* __restrict__ items) {
-  const int2 it = items[blockIdx.x];
+  const int2 it = items[xcd_local(blockIdx.x, gridDim.x)];
   const AdjJob& J = jobs[it.x];
   passA_adj_body<float, M, NB, NT>(J.g, J.grid, J.flags, J.H, J.tw, it.y);
 }
@@ -462,29 +491,45 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
   load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
   const int i0 = iblock * NB;
-  gather_to_lds<R, NB * M, NT>(
-      buf, H,
-      [&](int idx) -> int64_t {
-        const int m = idx / NB, b = idx - m * NB;
-        const int rel = m - g.v0;
-        return (unsigned)rel < (unsigned)g.nv ? (int64_t)h_index(rel, i0 + b, g.nv) : -1;
-      },
-      [](int idx) {
-        const int m = idx / NB, b = idx - m * NB;
-        return b * M + m;
-      });
+  // element (m, b): band row m - v0 of column i0 + b of the pass-A buffer,
+  // whose kHB-wide column blocks are row-major over the band rows
+  static_assert((NB & (NB - 1)) == 0 && NT % NB == 0, "pass-B layout");
+  constexpr int IT = (NB * M + NT - 1) / NT;
+  constexpr int MSTEP = NT / NB;  // a thread's m advances by this per element
+  const int b = (int)threadIdx.x & (NB - 1), m0 = (int)threadIdx.x / NB;
+  const int col = i0 + b;
+  const cpx<R>* hcol = H + (size_t)(col / kHB) * g.nv * kHB + (col % kHB);
+  cpx<R> t[IT];
+  bool ok[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int m = m0 + it * MSTEP;
+    const int rel = m - g.v0;
+    ok[it] = m < M && (unsigned)rel < (unsigned)g.nv;
+    t[it] = hcol[ok[it] ? (size_t)rel * kHB : 0];
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int m = m0 + it * MSTEP;
+    if ((NB * M) % NT == 0 || m < M) buf[pidx(b * M + m)] = ok[it] ? t[it] : cpx<R>{R(0), R(0)};
+  }
   __syncthreads();
   lds_fft<R, M, NB, NT, +1>(buf, tws);
   unsigned long long best = 0;
   const R dl = (R)g.dl;
   for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
-    const int b = idx / n, j = idx - b * n;
-    const int i = i0 + b;
+    const int bb = idx / n, j = idx - bb * n;
+    const int i = i0 + bb;
     int f = j - n / 2;
     if (f < 0) f += M;
     const R l = (R)(i - n / 2) * dl, mm = (R)(j - n / 2) * dl;
-    const R nn = sqrt(R(1) - l * l - mm * mm);
-    const R val = buf[pidx(b * M + f)].x * corr[i] * corr[j] * scale / nn;
+    R inv_n;
+    if constexpr (sizeof(R) == 4) {
+      inv_n = __builtin_amdgcn_rsqf(R(1) - l * l - mm * mm);
+    } else {
+      inv_n = R(1) / sqrt(R(1) - l * l - mm * mm);
+    }
+    const R val = buf[pidx(bb * M + f)].x * (corr[i] * scale) * corr[j] * inv_n;
     image[(size_t)i * n + j] = val;
     const unsigned long long key = max_key((float)fabs(val), i * n + j);
     best = key > best ? key : best;
@@ -511,13 +556,14 @@ __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>*
                                                         const cpx<R>* __restrict__ tw,
                                                         const R* __restrict__ corr, R scale,
                                                         unsigned long long* __restrict__ maxkey) {
-  passB_adj_body<R, M, NB, NT>(g, H, image, tw, corr, scale, maxkey, blockIdx.x);
+  passB_adj_body<R, M, NB, NT>(g, H, image, tw, corr, scale, maxkey,
+                               xcd_local(blockIdx.x, gridDim.x));
 }
 
 template <int M, int NB, int NT>
 __global__ __launch_bounds__(NT) void passB_batch_kernel(const AdjJob* __restrict__ jobs,
                                                           const int2* __restrict__ items) {
-  const int2 it = items[blockIdx.x];
+  const int2 it = items[xcd_local(blockIdx.x, gridDim.x)];
   const AdjJob& J = jobs[it.x];
   passB_adj_body<float, M, NB, NT>(J.g, J.H, J.image, J.tw, J.corr, J.scale, J.maxkey, it.y);
 }
