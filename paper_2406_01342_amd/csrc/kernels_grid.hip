@@ -755,7 +755,7 @@ static void launch_interp(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStrea
 template <typename R>
 struct Shapes {
   static constexpr int lds_a = 64 * 1024;
-  static constexpr int lds_b = 128 * 1024;
+  static constexpr int lds_b = 64 * 1024;
 };
 
 static void set_lds(const void* kernel, size_t bytes) {
@@ -783,7 +783,7 @@ template <typename R, int M>
 static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s) {
   constexpr int CB = sizeof(cpx<R>);
   constexpr int NBA = (M * CB >= Shapes<R>::lds_a) ? 1 : Shapes<R>::lds_a / (M * CB);
-  constexpr int NTA = 256;
+  constexpr int NTA = nt_for<NBA * M / 16>();
   constexpr int NBB = nb_passB<R, M>();
   constexpr int NTB = nt_for<NBB * M / 16>();
   const GridGeom& g = p->g;
@@ -910,7 +910,7 @@ template <int M>
 struct PassShape {
   static constexpr int CB = sizeof(c32);
   static constexpr int NBA = (M * CB >= Shapes<float>::lds_a) ? 1 : Shapes<float>::lds_a / (M * CB);
-  static constexpr int NTA = 256;
+  static constexpr int NTA = nt_for<NBA * M / 16>();
   static constexpr int NBB = nb_passB<float, M>();
   static constexpr int NTB = nt_for<NBB * M / 16>();
 };
