@@ -48,10 +48,56 @@ struct DevArray {
 };
 
 constexpr int kCheck = 4;        // APGD convergence test cadence
-constexpr int kPowerIters = 30;    // power iteration cap per active set
-constexpr int kPowerCheck = 3;     // convergence test cadence
-constexpr double kPowerTol = 1e-4; // relative change of the estimate
-constexpr double kLipMargin = 1.02;
+constexpr int kLanczosMax = 12;       // Lanczos steps per active set (cap)
+constexpr double kLanczosTol = 1e-3;  // residual bound relative to the estimate
+constexpr double kLipMargin = 1.01;
+
+// Largest eigenvalue and its eigenvector of a small symmetric matrix A
+// (row-major k x k, overwritten) by cyclic Jacobi rotations.
+static double sym_top_eigen(std::vector<double>& A, int k, std::vector<double>& vec) {
+  std::vector<double> V((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        const double q = A[(size_t)i * k + j] * A[(size_t)i * k + j];
+        tot += q;
+        if (i != j) off += q;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[(size_t)p * k + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * k + p], aqq = A[(size_t)q * k + q];
+        const double th = 0.5 * (aqq - app) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int r = 0; r < k; ++r) {  // A <- A J (columns p, q)
+          const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
+          A[(size_t)r * k + p] = c * arp - sn * arq;
+          A[(size_t)r * k + q] = sn * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {  // A <- J^T A (rows p, q)
+          const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
+          A[(size_t)p * k + r] = c * apr - sn * aqr;
+          A[(size_t)q * k + r] = sn * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {  // V <- V J
+          const double vrp = V[(size_t)r * k + p], vrq = V[(size_t)r * k + q];
+          V[(size_t)r * k + p] = c * vrp - sn * vrq;
+          V[(size_t)r * k + q] = sn * vrp + c * vrq;
+        }
+      }
+  }
+  int best = 0;
+  for (int i = 1; i < k; ++i)
+    if (A[(size_t)i * k + i] > A[(size_t)best * k + best]) best = i;
+  vec.resize(k);
+  for (int i = 0; i < k; ++i) vec[i] = V[(size_t)i * k + best];
+  return A[(size_t)best * k + best];
+}
 
 struct Pfw {
   pc_plan* p;
@@ -215,11 +261,16 @@ struct Pfw {
     }
   }
 
-  // Largest eigenvalue of G_S = Re(Phi_S^H Phi_S) by power iteration on the
-  // operator pair, warm-started from the previous active set's eigenvector
-  // (new atoms enter at 1/sqrt(nS)); stops when successive estimates agree
-  // to kPowerTol (tested every kPowerCheck iterations) or after kPowerIters.
-  double power_iteration(const std::vector<int32_t>& set, bool gridded) {
+  // Upper estimate of the largest eigenvalue of G_S = Re(Phi_S^H Phi_S) by
+  // Lanczos iteration on the operator pair, with full reorthogonalisation
+  // (FP64, on the host; the vectors have nS entries), started from the
+  // previous active set's top Ritz vector (new atoms enter at 1/sqrt(nS)).
+  // After step j the top Ritz value theta of the tridiagonal T_j and the
+  // residual bound rho = beta_j |s_j| (s the Ritz vector in the Lanczos
+  // basis) bracket an eigenvalue: |lambda - theta| <= rho.  Stops when
+  // rho <= kLanczosTol theta (or at kLanczosMax steps, or on an invariant
+  // subspace) and returns theta + rho.
+  double top_eigen_bound(const std::vector<int32_t>& set, bool gridded) {
     const int64_t nS = (int64_t)set.size();
     std::vector<double> v0(nS, 1.0 / std::sqrt((double)nS));
     for (size_t a = 0, b = 0; a < pv_set.size() && b < set.size();) {
@@ -237,23 +288,51 @@ struct Pfw {
     for (double q : v0) nrm += q * q;
     nrm = std::sqrt(nrm);
     for (double& q : v0) q /= nrm;
-    PC_HIP(hipMemcpyAsync(v.ptr, v0.data(), nS * 8, hipMemcpyHostToDevice, s));
-    k_weights(p, nS, v.ptr, atoms.ptr, s);
-    double e[2] = {0, 0};
-    for (int it = 1; it <= kPowerIters; ++it) {
+    std::vector<std::vector<double>> Q;
+    Q.push_back(v0);
+    std::vector<double> alpha, beta, w(nS), svec;
+    double theta = 0, rho = 0;
+    for (int j = 0; j < kLanczosMax; ++j) {
+      PC_HIP(hipMemcpyAsync(v.ptr, Q[j].data(), nS * 8, hipMemcpyHostToDevice, s));
+      if (!gridded) k_weights(p, nS, v.ptr, atoms.ptr, s);
       op_forward(gridded, nS, v.ptr, false, r.ptr);
       op_adjoint(gridded, nS, r.ptr, g.ptr);
-      k_power(p, nS, g.ptr, v.ptr, atoms.ptr, scal.ptr, s);
-      if (it >= kPowerCheck && (it % kPowerCheck == 0 || it == kPowerIters)) {
-        read_scal(e, kScalEig, 2);
-        if (std::fabs(e[0] - e[1]) <= kPowerTol * e[0]) break;
+      PC_HIP(hipMemcpyAsync(w.data(), g.ptr, nS * 8, hipMemcpyDeviceToHost, s));
+      PC_HIP(hipStreamSynchronize(s));
+      double a = 0;
+      for (int64_t i = 0; i < nS; ++i) a += Q[j][i] * w[i];
+      alpha.push_back(a);
+      for (int64_t i = 0; i < nS; ++i) w[i] -= a * Q[j][i] + (j > 0 ? beta[j - 1] * Q[j - 1][i] : 0.0);
+      for (int pass = 0; pass < 2; ++pass)  // full reorthogonalisation, twice
+        for (int q = 0; q <= j; ++q) {
+          double d = 0;
+          for (int64_t i = 0; i < nS; ++i) d += Q[q][i] * w[i];
+          for (int64_t i = 0; i < nS; ++i) w[i] -= d * Q[q][i];
+        }
+      double bj = 0;
+      for (double q : w) bj += q * q;
+      bj = std::sqrt(bj);
+      const int k = j + 1;
+      std::vector<double> T((size_t)k * k, 0.0);
+      for (int i = 0; i < k; ++i) {
+        T[(size_t)i * k + i] = alpha[i];
+        if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[i];
       }
+      theta = sym_top_eigen(T, k, svec);
+      rho = bj * std::fabs(svec[k - 1]);
+      const bool invariant = bj <= 1e-14 * std::max(theta, 1e-300) || k >= nS;
+      if (invariant || rho <= kLanczosTol * theta || j + 1 == kLanczosMax) break;
+      beta.push_back(bj);
+      for (double& q : w) q /= bj;
+      Q.push_back(w);
     }
+    // top Ritz vector as the next warm start
+    const int k = (int)svec.size();
     pv_set = set;
-    pv_val.resize(nS);
-    PC_HIP(hipMemcpyAsync(pv_val.data(), v.ptr, nS * 8, hipMemcpyDeviceToHost, s));
-    PC_HIP(hipStreamSynchronize(s));
-    return e[0];
+    pv_val.assign(nS, 0.0);
+    for (int q = 0; q < k; ++q)
+      for (int64_t i = 0; i < nS; ++i) pv_val[i] += svec[q] * Q[q][i];
+    return theta + rho;
   }
 
   void step() {
@@ -290,7 +369,7 @@ struct Pfw {
     int inner = 0;
     const bool gridded = nS >= grid_thr;
     if (nS > 0) {
-      const double lip = power_iteration(Sn, gridded) * kLipMargin;
+      const double lip = top_eigen_bound(Sn, gridded) * kLipMargin;
       double hs[2] = {lip, 1.0};
       PC_HIP(hipMemcpyAsync(scal.ptr + kScalLip, hs, 2 * sizeof(double), hipMemcpyHostToDevice, s));
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
