@@ -209,11 +209,14 @@ __device__ __forceinline__ void spread_body(
       const int du = cu % C::RB, dv = cv % C::RB;
       const int bu = tile_base(cu - du, ou, g.M, C::BS, g.wrap);
       const int bv = tile_base(cv - dv, ov, g.M, C::BS, g.wrap);
+      // the W taps of each axis land at window positions d .. d + W - 1
+      // (d = dv or du < RB); the other BS - W positions are zero
 #pragma unroll
-      for (int j = 0; j < C::BS; ++j) {
-        const int ty = j - dv, tx = j - du;  // tap index of window row / column j
-        my[j] = (ty >= 0 && ty < W) ? es_kernel<R>((nx.sv + R(ty)) * inv, beta) : R(0);
-        my[C::BS + j] = (tx >= 0 && tx < W) ? es_kernel<R>((nx.su + R(tx)) * inv, beta) : R(0);
+      for (int j = 0; j < C::BS; ++j) my[j] = my[C::BS + j] = R(0);
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        my[dv + t] = es_kernel<R>((nx.sv + R(t)) * inv, beta);
+        my[C::BS + du + t] = es_kernel<R>((nx.su + R(t)) * inv, beta);
       }
       my[2 * C::BS] = nx.val.x;
       my[2 * C::BS + 1] = nx.val.y;

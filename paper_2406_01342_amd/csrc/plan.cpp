@@ -240,8 +240,10 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
       lay.off[2 * s + 1] = sv[k];
     }
   }
-  // Work list.  Split tiles whose gathered count exceeds kChunk.
-  const int64_t kChunk = 256;
+  // Work list.  Split tiles whose gathered count exceeds kChunk: 256
+  // visibilities keeps the longest item short when few items exist (the
+  // spread is then bound by its longest work item); with many items the
+  // spread is throughput-bound, and 512 halves the partial tiles to fold.
   auto tid = [&](int tv, int tu) -> int64_t {
     if (g.wrap) {
       tv = (tv + ntv) % ntv;
@@ -252,28 +254,47 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     return (int64_t)tv * ntu + tu;
   };
   auto cls_beg = [&](int64_t t, int c) { return bstart[t * 4 + c]; };
+  // gathered count of each tile: its own visibilities plus the spills of
+  // its left, upper and upper-left neighbours
+  auto gathered = [&](int tv, int tu, int64_t* rb, int64_t* re) {
+    const int64_t t = (int64_t)tv * ntu + tu;
+    for (int r = 0; r < 4; ++r) rb[r] = re[r] = 0;
+    rb[0] = cls_beg(t, 0);
+    re[0] = bstart[t * 4 + 4];  // end of tile t
+    const int64_t tl = tid(tv, tu - 1), tup = tid(tv - 1, tu), tul = tid(tv - 1, tu - 1);
+    if (tl >= 0 && tl != t) {  // left neighbour: classes both + right
+      rb[1] = cls_beg(tl, 2);
+      re[1] = bstart[tl * 4 + 4];
+    }
+    if (tup >= 0 && tup != t) {  // upper neighbour: classes down + both
+      rb[2] = cls_beg(tup, 1);
+      re[2] = cls_beg(tup, 3);
+    }
+    if (tul >= 0 && tul != t) {  // upper-left neighbour: class both
+      rb[3] = cls_beg(tul, 2);
+      re[3] = cls_beg(tul, 3);
+    }
+    int64_t total = 0;
+    for (int r = 0; r < 4; ++r) total += re[r] - rb[r];
+    return total;
+  };
+  int64_t kChunk = 256;
+  {
+    int64_t items512 = 0;
+    for (int tv = 0; tv < ntv; ++tv)
+      for (int tu = 0; tu < ntu; ++tu) {
+        int64_t rb[4], re[4];
+        const int64_t tot = gathered(tv, tu, rb, re);
+        if (tot > 0) items512 += (tot + 511) / 512;
+      }
+    if (items512 >= 7680) kChunk = 512;  // >= 3 waves of work items per wave slot
+  }
   lay.tile_flags.assign(ntiles, 0);
   for (int tv = 0; tv < ntv; ++tv)
     for (int tu = 0; tu < ntu; ++tu) {
       const int64_t t = (int64_t)tv * ntu + tu;
-      int64_t rb[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0};
-      rb[0] = cls_beg(t, 0);
-      re[0] = bstart[t * 4 + 4];  // end of tile t
-      int64_t tl = tid(tv, tu - 1), tup = tid(tv - 1, tu), tul = tid(tv - 1, tu - 1);
-      if (tl >= 0 && tl != t) {  // left neighbour: classes both + right
-        rb[1] = cls_beg(tl, 2);
-        re[1] = bstart[tl * 4 + 4];
-      }
-      if (tup >= 0 && tup != t) {  // upper neighbour: classes down + both
-        rb[2] = cls_beg(tup, 1);
-        re[2] = cls_beg(tup, 3);
-      }
-      if (tul >= 0 && tul != t) {  // upper-left neighbour: class both
-        rb[3] = cls_beg(tul, 2);
-        re[3] = cls_beg(tul, 3);
-      }
-      int64_t total = 0;
-      for (int r = 0; r < 4; ++r) total += re[r] - rb[r];
+      int64_t rb[4], re[4];
+      const int64_t total = gathered(tv, tu, rb, re);
       // Tiles no footprint reaches get no work item and are never written;
       // the first FFT pass reads them as zeros from the occupancy flags.
       lay.tile_flags[t] = total > 0 ? 1 : 0;
