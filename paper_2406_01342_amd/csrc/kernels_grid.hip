@@ -80,7 +80,7 @@ struct SpreadCfg {
   static constexpr int TILE = kTile * S;         // reals per plane
   static constexpr int REC = 2 * BS + 4;         // wy[BS], wx[BS], re, im, key, pad
   static constexpr int STG = 64 * REC;
-  static constexpr int U = 8;                    // visibilities per inner step
+  static constexpr int U = 16;                   // visibilities per inner step
   static constexpr size_t lds_bytes = sizeof(R) * (2 * TILE + STG);
 };
 
