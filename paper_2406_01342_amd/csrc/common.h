@@ -276,5 +276,12 @@ template <typename R>
 void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                    const Atom<R>* atoms, double* partial, double* out, hipStream_t s);
 int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms);
+// Partials per atom of adjoint_atoms (out == NULL leaves them unsummed).
+int64_t adjoint_partial_stride(const pc_plan* p, int64_t natoms);
+// Sum of the restricted adjoint's partials (or g_in) fused with one APGD
+// step; see kernels_dft.hip.
+void reduce_fista(pc_plan* p, int64_t nS, int64_t nwg, const double* partial, const double* g_in,
+                  Atom<float>* atoms, double* x, double* y, double* g_out, double* stat,
+                  double inv_lip, double thr, double mom, hipStream_t s);
 
 }  // namespace pc

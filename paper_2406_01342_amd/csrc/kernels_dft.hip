@@ -238,6 +238,59 @@ __global__ __launch_bounds__(256) void adjoint_sparse_reduce_kernel(
   if (threadIdx.x == 0) out[p] = (((red[0] + red[1]) + red[2]) + red[3]) * atoms[p].inv_n;
 }
 
+// One APGD step on the restricted problem fused with the restricted
+// adjoint's final sum (one workgroup per atom): g_p = (1/n_p) sum_c
+// partial[p][c] in FP64 (or g_in[p] when partial is NULL), then the proximal
+// gradient step from y and the momentum extrapolation
+//   x+ = soft(y + g / L, lambda / L),  y+ = x+ + mom (x+ - x),
+// with the new forward weight y+ / n_p.  stat[p] = |y_p| and
+// stat[nS + p] = |g_p| (at the gradient point) feed the duality-gap test.
+__global__ __launch_bounds__(256) void reduce_fista_kernel(
+    int64_t nS, int64_t nwg, const float* __restrict__ partial, const double* __restrict__ g_in,
+    Atom<float>* __restrict__ atoms, double* __restrict__ x, double* __restrict__ y,
+    double* __restrict__ g_out, double* __restrict__ stat, double inv_lip, double thr,
+    double mom) {
+  __shared__ double red[4];
+  const int64_t p = blockIdx.x;
+  double gp;
+  if (partial) {
+    const float* row = partial + p * nwg;
+    double s = 0;
+    for (int64_t c = threadIdx.x; c < nwg; c += 256) s += (double)row[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    gp = (((red[0] + red[1]) + red[2]) + red[3]) * atoms[p].inv_n;
+  } else {
+    gp = g_in[p];
+  }
+  if (threadIdx.x == 0) {
+    const double yo = y[p], xo = x[p];
+    const double z = yo + gp * inv_lip;
+    const double az = fabs(z) - thr;
+    const double xn = az > 0 ? copysign(az, z) : 0.0;
+    const double yn = xn + mom * (xn - xo);
+    g_out[p] = gp;
+    stat[p] = fabs(yo);
+    stat[nS + p] = fabs(gp);
+    x[p] = xn;
+    y[p] = yn;
+    atoms[p].w = (float)(yn * atoms[p].inv_n);
+  }
+}
+
+void reduce_fista(pc_plan* p, int64_t nS, int64_t nwg, const double* partial, const double* g_in,
+                  Atom<float>* atoms, double* x, double* y, double* g_out, double* stat,
+                  double inv_lip, double thr, double mom, hipStream_t s) {
+  if (nS <= 0) return;
+  ProfScope ps(p, s, "reduce_fista", (double)sizeof(float) * nwg * nS + 64.0 * nS, (double)nS);
+  hipLaunchKernelGGL(reduce_fista_kernel, dim3((unsigned)nS), dim3(256), 0, s, nS, nwg,
+                     reinterpret_cast<const float*>(partial), g_in, atoms, x, y, g_out, stat,
+                     inv_lip, thr, mom);
+  PC_LAUNCH_CHECK("reduce_fista");
+}
+
 template <typename R>
 void prep_atoms_into(pc_plan* p, int64_t natoms, const int32_t* pix, const R* weight,
                      Atom<R>* atoms, hipStream_t s) {
@@ -267,6 +320,10 @@ int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms) {
   return sh.nwg * std::max<int64_t>(natoms, 1);
 }
 
+int64_t adjoint_partial_stride(const pc_plan* p, int64_t natoms) {
+  return adjoint_shape(p->L, std::max<int64_t>(natoms, 1)).nwg;
+}
+
 template <typename R>
 void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                    const Atom<R>* atoms, double* partial, double* out, hipStream_t s) {
@@ -282,6 +339,7 @@ void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natom
                        vis_sorted ? nullptr : p->perm, atoms, part);
     PC_LAUNCH_CHECK("adjoint_sparse");
   }
+  if (!out) return;  // the caller sums the partials (fused with its next step)
   ProfScope ps(p, s, "adjoint_sparse_reduce", (double)sizeof(R) * sh.nwg * natoms,
                (double)sh.nwg * natoms);
   hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3((unsigned)natoms), dim3(256), 0, s,

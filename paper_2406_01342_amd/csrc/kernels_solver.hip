@@ -212,6 +212,24 @@ __global__ void gather_img_kernel(int64_t nS, const int32_t* __restrict__ pix,
   if (a < nS) out[a] = (double)img[pix[a]];
 }
 
+// scal[kScalYL1] = sum_p stat[p], scal[kScalGmax] = max_p stat[nS + p]
+// (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void stat_reduce_kernel(int64_t nS, const double* __restrict__ stat,
+                                                           double* __restrict__ scal) {
+  __shared__ double sh[16];
+  double l1 = 0, mx = 0;
+  for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) {
+    l1 += stat[p];
+    mx = fmax(mx, stat[nS + p]);
+  }
+  l1 = block_sum<1024>(l1, sh);
+  mx = block_max<1024>(mx, sh);
+  if (threadIdx.x == 0) {
+    scal[kScalYL1] = l1;
+    scal[kScalGmax] = mx;
+  }
+}
+
 __global__ void fill_kernel(int64_t N, float v, float* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < N) out[j] = v;
@@ -292,6 +310,12 @@ void k_gather_img(pc_plan* p, int64_t nS, const int32_t* pix, const float* img, 
   if (nS <= 0) return;
   hipLaunchKernelGGL(gather_img_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, pix, img, out);
   PC_LAUNCH_CHECK("gather_img");
+}
+
+void k_stat_reduce(pc_plan* p, int64_t nS, const double* stat, double* scal, hipStream_t s) {
+  ProfScope ps(p, s, "stat_reduce", 16.0 * nS, (double)nS);
+  hipLaunchKernelGGL(stat_reduce_kernel, dim3(1), dim3(1024), 0, s, nS, stat, scal);
+  PC_LAUNCH_CHECK("stat_reduce");
 }
 
 void k_fill(pc_plan* p, int64_t N, float v, float* out, hipStream_t s) {

@@ -111,7 +111,7 @@ struct Pfw {
   DevArray<int32_t> cand, pix;
   DevArray<unsigned> cand_count;
   DevArray<Atom<float>> atoms;
-  DevArray<double> x, y, g, v, adj_partial, red_partial, scal;
+  DevArray<double> x, y, g, v, adj_partial, red_partial, scal, stat;
   std::vector<int32_t> S;
   std::vector<double> xs;
   std::vector<int32_t> pv_set;  // last power-iteration eigenvector (warm start)
@@ -370,20 +370,32 @@ struct Pfw {
     const bool gridded = nS >= grid_thr;
     if (nS > 0) {
       const double lip = top_eigen_bound(Sn, gridded) * kLipMargin;
-      double hs[2] = {lip, 1.0};
-      PC_HIP(hipMemcpyAsync(scal.ptr + kScalLip, hs, 2 * sizeof(double), hipMemcpyHostToDevice, s));
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
       const double tol = std::max(prm.inner_tol_min, prm.inner_tol0 * rel_gap);
+      stat.ensure(2 * nS);
+      const int64_t nwg = adjoint_partial_stride(p, nS);
+      double t = 1.0;  // FISTA momentum sequence, on the host in FP64
       for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
         op_forward(gridded, nS, y.ptr, true, r.ptr);
-        op_adjoint(gridded, nS, r.ptr, g.ptr);
         const bool check = (inner - 1) % kCheck == 0;
         if (check) {
           red_partial.ensure(2 * k_resid_blocks(L));
           k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
         }
-        k_fista(p, nS, g.ptr, x.ptr, y.ptr, atoms.ptr, scal.ptr, lam, s);
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        const double mom = (t - 1.0) / tn;
+        t = tn;
+        if (!gridded) {  // partial sums of Phi_S* r, summed by the fused step
+          adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, nullptr, s);
+          reduce_fista(p, nS, nwg, adj_partial.ptr, nullptr, atoms.ptr, x.ptr, y.ptr, g.ptr,
+                       stat.ptr, 1.0 / lip, lam / lip, mom, s);
+        } else {
+          op_adjoint(true, nS, r.ptr, g.ptr);
+          reduce_fista(p, nS, 0, nullptr, g.ptr, atoms.ptr, x.ptr, y.ptr, g.ptr, stat.ptr,
+                       1.0 / lip, lam / lip, mom, s);
+        }
         if (check) {
+          k_stat_reduce(p, nS, stat.ptr, scal.ptr, s);
           double h[4];  // ||r_y||^2, Re<V, r_y>, ||y||_1, max |g|
           read_scal(h, kScalResid, 4);
           const double py = 0.5 * h[0] + lam * h[2];

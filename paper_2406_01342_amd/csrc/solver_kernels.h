@@ -38,5 +38,6 @@ void k_gather_img(pc_plan* p, int64_t nS, const int32_t* pix, const float* img, 
                   hipStream_t s);
 void k_rsub(pc_plan* p, int64_t L, const c32* V, c32* r, hipStream_t s);
 void k_fill(pc_plan* p, int64_t N, float v, float* out, hipStream_t s);
+void k_stat_reduce(pc_plan* p, int64_t nS, const double* stat, double* scal, hipStream_t s);
 
 }  // namespace pc
