@@ -48,6 +48,41 @@ struct DevArray {
 };
 
 constexpr int kCheck = 4;        // APGD convergence test cadence
+// Pinned host staging for uploads and small readbacks.  Its copies are
+// asynchronous; `fence` records the stream position of the last use so that
+// the buffer is not rewritten while a copy from it may still be pending.
+struct Pinned {
+  unsigned char* ptr = nullptr;
+  size_t cap = 0;
+  hipEvent_t fence = nullptr;
+  bool armed = false;
+  void* get(size_t bytes) {
+    if (armed) PC_HIP(hipEventSynchronize(fence));
+    armed = false;
+    if (bytes > cap) {
+      if (ptr) (void)hipHostFree(ptr);
+      ptr = nullptr;
+      cap = 0;
+      const size_t want = std::max<size_t>(bytes, 2 * cap + 4096);
+      PC_HIP(hipHostMalloc((void**)&ptr, want));
+      cap = want;
+    }
+    return ptr;
+  }
+  void arm(hipStream_t s) {
+    if (!fence) PC_HIP(hipEventCreateWithFlags(&fence, hipEventDisableTiming));
+    PC_HIP(hipEventRecord(fence, s));
+    armed = true;
+  }
+  ~Pinned() {
+    if (fence) {
+      if (armed) (void)hipEventSynchronize(fence);
+      (void)hipEventDestroy(fence);
+    }
+    if (ptr) (void)hipHostFree(ptr);
+  }
+};
+
 constexpr int kLanczosMax = 12;       // Lanczos steps per active set (cap)
 constexpr double kLanczosTol = 1e-3;  // residual bound relative to the estimate
 constexpr double kLipMargin = 1.01;
@@ -112,6 +147,7 @@ struct Pfw {
   DevArray<unsigned> cand_count;
   DevArray<Atom<float>> atoms;
   DevArray<double> x, y, g, v, adj_partial, red_partial, scal, stat;
+  Pinned up, down;  // upload staging, small readbacks
   std::vector<int32_t> S;
   std::vector<double> xs;
   std::vector<int32_t> pv_set;  // last power-iteration eigenvector (warm start)
@@ -155,6 +191,36 @@ struct Pfw {
     eta_argmax = am;
   }
 
+  // Step 4's dirty residual together with ||r||^2 and Re<V, r>: one host
+  // synchronisation for the maximum, the argmax and both statistics.
+  void adjoint_and_stats(const c32* vis_sorted, double& r2, double& vr) {
+    if (batcher) {  // the batcher synchronises on its own
+      adjoint_timed(vis_sorted);
+      residual_stats(r2, vr);
+      return;
+    }
+    PC_HIP(hipEventRecord(p->ev_a, s));
+    adjoint_grid<float>(p, vis_sorted, true, eta.ptr, 1.0f, s);
+    PC_HIP(hipEventRecord(p->ev_b, s));
+    red_partial.ensure(2 * k_resid_blocks(L));
+    k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
+    unsigned char* h = (unsigned char*)down.get(24);
+    PC_HIP(hipMemcpyAsync(h, p->maxkey, 8, hipMemcpyDeviceToHost, s));
+    PC_HIP(hipMemcpyAsync(h + 8, scal.ptr + kScalResid, 16, hipMemcpyDeviceToHost, s));
+    PC_HIP(hipStreamSynchronize(s));
+    unsigned long long key;
+    double st[2];
+    std::memcpy(&key, h, 8);
+    std::memcpy(st, h + 8, 16);
+    maxkey_decode(key, &eta_inf, &eta_argmax);
+    r2 = st[0];
+    vr = st[1];
+    float ms = 0;
+    PC_HIP(hipEventElapsedTime(&ms, p->ev_a, p->ev_b));
+    adj_ms += ms;
+    adj_calls++;
+  }
+
   void read_scal(double* host, int first, int count) {
     PC_HIP(hipMemcpyAsync(host, scal.ptr + first, count * sizeof(double), hipMemcpyDeviceToHost, s));
     PC_HIP(hipStreamSynchronize(s));
@@ -180,13 +246,15 @@ struct Pfw {
     v.ensure(nS);
     adj_partial.ensure(adjoint_partial_count(p, nS));
     if (nS == 0) return;
-    PC_HIP(hipMemcpyAsync(pix.ptr, set.data(), nS * 4, hipMemcpyHostToDevice, s));
-    PC_HIP(hipMemcpyAsync(x.ptr, xs_host.data(), nS * 8, hipMemcpyHostToDevice, s));
-    PC_HIP(hipMemcpyAsync(y.ptr, xs_host.data(), nS * 8, hipMemcpyHostToDevice, s));
+    unsigned char* h = (unsigned char*)up.get(nS * 12);
+    std::memcpy(h, xs_host.data(), nS * 8);
+    std::memcpy(h + nS * 8, set.data(), nS * 4);
+    PC_HIP(hipMemcpyAsync(x.ptr, h, nS * 8, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(y.ptr, h, nS * 8, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(pix.ptr, h + nS * 8, nS * 4, hipMemcpyHostToDevice, s));
+    up.arm(s);
     prep_atoms_into<float>(p, nS, pix.ptr, (const float*)nullptr, atoms.ptr, s);
     k_weights(p, nS, x.ptr, atoms.ptr, s);
-    // pageable host sources: make sure the copies completed before reuse
-    PC_HIP(hipStreamSynchronize(s));
   }
 
   // Crossover between the direct sums (cost ~ L nS) and the gridded
@@ -340,18 +408,31 @@ struct Pfw {
     // 1.a polyatomic exploration: threshold in FP64, compared in FP32
     const double tau = eta_inf - 2.0 * Delta / (k + 2);
     const float tau_f = (float)tau;
+    // the count and the first kFirst candidates come back in one copy pair
+    constexpr int64_t kFirst = 4096;
     unsigned count = 0;
+    std::vector<int32_t> I;
     for (;;) {
       k_select(p, N, eta.ptr, tau_f, cand_count.ptr, cand.ptr, cand.cap, s);
-      PC_HIP(hipMemcpyAsync(&count, cand_count.ptr, 4, hipMemcpyDeviceToHost, s));
+      const int64_t first = std::min<int64_t>(kFirst, cand.cap);
+      unsigned char* h = (unsigned char*)down.get(4 + first * 4);
+      PC_HIP(hipMemcpyAsync(h, cand_count.ptr, 4, hipMemcpyDeviceToHost, s));
+      PC_HIP(hipMemcpyAsync(h + 4, cand.ptr, first * 4, hipMemcpyDeviceToHost, s));
       PC_HIP(hipStreamSynchronize(s));
-      if ((int64_t)count <= cand.cap) break;
-      cand.ensure(count);
-    }
-    std::vector<int32_t> I(count);
-    if (count) {
-      PC_HIP(hipMemcpyAsync(I.data(), cand.ptr, count * 4, hipMemcpyDeviceToHost, s));
-      PC_HIP(hipStreamSynchronize(s));
+      std::memcpy(&count, h, 4);
+      if ((int64_t)count > cand.cap) {
+        cand.ensure(count);
+        continue;
+      }
+      I.resize(count);
+      const int64_t head = std::min<int64_t>(count, first);
+      if (head) std::memcpy(I.data(), h + 4, head * 4);
+      if ((int64_t)count > first) {
+        PC_HIP(hipMemcpyAsync(I.data() + first, cand.ptr + first, (count - first) * 4,
+                              hipMemcpyDeviceToHost, s));
+        PC_HIP(hipStreamSynchronize(s));
+      }
+      break;
     }
     std::sort(I.begin(), I.end());
     // 1.b S u I with warm-start weights (new atoms at zero)
@@ -421,9 +502,8 @@ struct Pfw {
     // 4. residual, dirty residual, objective and gap
     load_active(S, xs);
     op_forward((int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
-    adjoint_timed(r.ptr);
     double r2, vr;
-    residual_stats(r2, vr);
+    adjoint_and_stats(r.ptr, r2, vr);
     double l1 = 0;
     for (double w : xs) l1 += std::fabs(w);
     P = 0.5 * r2 + lam * l1;
