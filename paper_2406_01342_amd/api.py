@@ -378,14 +378,17 @@ class Solver:
         self.done = bool(done.value)
         return self.done
 
-    def result(self, capacity: int = 65536) -> dict:
+    def result(self, capacity: int = 65536, cert: Optional[torch.Tensor] = None) -> dict:
+        """Current iterate; `cert` (device float [n, n]) receives the dual
+        certificate when the solver was created with want_certificate=1."""
         pix = np.zeros(capacity, dtype=np.int32)
         wgt = np.zeros(capacity, dtype=np.float64)
         res = PcSolveResult()
         res.capacity = capacity
         res.pix = pix.ctypes.data_as(C.POINTER(C.c_int32))
         res.weight = wgt.ctypes.data_as(C.POINTER(C.c_double))
-        res.cert = None
+        n = self.plan.npix
+        res.cert = C.c_void_p(_dev(cert, torch.float32, n * n, "cert")) if cert is not None else None
         st = LIB.pc_solver_result(self._h, C.byref(res))
         check(st, "pc_solver_result")
         return _result_dict(res, st, pix, wgt)

@@ -34,6 +34,7 @@ class ImagingRequest:
     fov_rad: float
     vis: np.ndarray             # (L,) complex64, caller order
     params: Dict[str, float] = field(default_factory=dict)
+    want_certificate: bool = False  # return the dual certificate image
 
 
 @dataclass
@@ -91,7 +92,14 @@ class DeviceBackend:
     def footprint(self, req: ImagingRequest) -> int:
         L = int(req.uv.shape[0])
         plan = self.api.pc_plan_footprint(req.uv, req.npix, req.fov_rad)
-        return int(plan) + 24 * L + 4 * req.npix * req.npix + self.FIXED_BYTES
+        cert = 4 * req.npix * req.npix if req.want_certificate else 0
+        return int(plan) + 24 * L + 4 * req.npix * req.npix + cert + self.FIXED_BYTES
+
+    def _params(self, req: ImagingRequest) -> dict:
+        prm = dict(req.params)
+        if req.want_certificate:
+            prm["want_certificate"] = 1
+        return prm
 
     def open(self, req: ImagingRequest):
         torch = self.torch
@@ -100,18 +108,27 @@ class DeviceBackend:
             plan = self.api.pc_plan_create(req.uv, req.npix, req.fov_rad, stream=stream)
             vis = torch.from_numpy(np.ascontiguousarray(req.vis, dtype=np.complex64)).to(
                 self.device, non_blocking=False)
-            solver = self.api.Solver(plan, vis, stream=stream, batcher=self.batcher, **req.params)
+            solver = self.api.Solver(plan, vis, stream=stream, batcher=self.batcher,
+                                     **self._params(req))
             del vis
-        return {"plan": plan, "solver": solver, "stream": stream}
+        return {"plan": plan, "solver": solver, "stream": stream, "req": req}
 
     def step(self, h) -> bool:
         return h["solver"].step()
 
     def close(self, h) -> dict:
-        res = h["solver"].result()
+        req = h["req"]
+        cert = None
+        if req.want_certificate:
+            with self.torch.cuda.stream(h["stream"]):
+                cert = self.torch.empty((req.npix, req.npix), dtype=self.torch.float32,
+                                        device=self.device)
+        res = h["solver"].result(cert=cert)
         h["solver"].close()
         h["stream"].synchronize()
         h["plan"].close()
+        if cert is not None:
+            res["certificate"] = cert  # device image, mu = Phi*(V - Phi x) / lambda
         return res
 
     def solve_plain(self, req: ImagingRequest) -> dict:
@@ -119,7 +136,12 @@ class DeviceBackend:
         torch = self.torch
         plan = self.api.pc_plan_create(req.uv, req.npix, req.fov_rad)
         vis = torch.from_numpy(np.ascontiguousarray(req.vis, dtype=np.complex64)).to(self.device)
-        res = self.api.pc_polyclean_solve(plan, vis, **req.params)
+        cert = None
+        if req.want_certificate:
+            cert = torch.empty((req.npix, req.npix), dtype=torch.float32, device=self.device)
+        res = self.api.pc_polyclean_solve(plan, vis, cert=cert, **self._params(req))
+        if cert is not None:
+            res["certificate"] = cert
         plan.close()
         return res
 

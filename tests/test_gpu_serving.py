@@ -66,6 +66,42 @@ def test_results_alone_equal_results_in_the_mix():
     be.close_backend()
 
 
+def test_memory_budget_admission_and_certificates():
+    """Under a device-memory budget that holds about half of the jobs at once,
+    admission keeps the resident footprint within it, every job completes
+    with its lone result, and the jobs that ask for it get their dual
+    certificate image, equal to the lone solve's."""
+    api()
+    import torch
+    from paper_2406_01342_amd import serving
+    reqs = requests(6)
+    be = serving.DeviceBackend(batched=True)
+    ireqs = [serving.ImagingRequest(k, 0.0, uv, p.npix, p.fov_rad, vis, prm,
+                                    want_certificate=(k % 2 == 0))
+             for k, (p, uv, vis, prm) in enumerate(reqs)]
+    fps = [be.footprint(r) for r in ireqs]
+    budget = max(max(fps), sum(fps) // 2)  # every job fits, not all of them together
+    say("footprints", fps, "budget", budget)
+    alone = [be.solve_plain(r) for r in ireqs]
+    srv = serving.Server(be, slots=6, hbm_budget=budget)
+    summary = srv.run(ireqs)
+    say("summary", summary)
+    assert summary["completed"] == len(ireqs)
+    assert summary["peak_bytes"] <= budget
+    assert summary["peak_running"] < len(ireqs)  # the budget, not the slots, bound it
+    for rec in srv.records:
+        ra, rm = alone[rec.rid], rec.result
+        np.testing.assert_array_equal(rm["pix"], ra["pix"])
+        assert abs(rm["objective"] - ra["objective"]) <= 1e-6 * ra["objective"]
+        if ireqs[rec.rid].want_certificate:
+            ca, cm = ra["certificate"], rm["certificate"]
+            assert torch.allclose(cm, ca, rtol=1e-5, atol=1e-6 * float(ca.abs().max()))
+            assert abs(float(cm.abs().max()) - rm["cert_max"]) <= 1e-5 * rm["cert_max"]
+        else:
+            assert "certificate" not in rm
+    be.close_backend()
+
+
 def test_batched_solver_single_job_matches_plain():
     """A batcher with one job gives the plain solver's result (its batches are
     all of size one)."""
