@@ -269,3 +269,32 @@ def test_adjoint_grid_batch_rejects_bad_input():
     with pytest.raises(a.PolycleanError):
         a.pc_adjoint_grid_batch([plan64], [dv], images=[torch.empty((p.npix, p.npix),
                                                                     device="cuda")])
+
+
+def test_adjoint_grid_16384_fine_grid_sampled():
+    """The largest grid (8192^2 image, 16384^2 fine grid, FP32 only) on a
+    subset of the memory-pressure workload's visibilities, against the
+    oracle's exact sum at sampled pixels (incl. the centre and the argmax)."""
+    import sim as _sim
+    a = api()
+    p = _sim.config_c5_large(n_snap=2)
+    rng = np.random.default_rng(51)
+    ks = np.sort(rng.choice(p.uv.shape[0], 30000, replace=False))
+    uv = p.uv[ks]
+    h = (rng.normal(size=ks.size) + 1j * rng.normal(size=ks.size)).astype(np.complex64)
+    say("adjoint 16384 fine grid", uv.shape[0], p.npix)
+    plan = a.pc_plan_create(uv, p.npix, p.fov_rad)
+    assert plan.info["fine"] == 16384
+    img, mx, am = a.pc_adjoint_grid(plan, to_dev(h))
+    n = p.npix
+    c = n // 2
+    pix = np.unique(np.concatenate([rng.choice(n * n, 48, replace=False),
+                                    [c * n + c, c * n + c + 1, (c + 1) * n + c, am]]))
+    want = operator.adjoint_pixels(uv, n, p.fov_rad, h.astype(np.complex128), pix)
+    got = img.reshape(-1)[torch.from_numpy(pix).cuda()].double().cpu().numpy()
+    err = rel_l2(got, want)
+    say("rel L2 at samples", err)
+    assert err <= TOL
+    # the reported maximum is the image's
+    assert abs(mx - float(img.abs().max())) <= 1e-6 * mx
+    assert abs(float(img.reshape(-1)[am].abs()) - mx) <= 1e-6 * mx
