@@ -35,23 +35,25 @@ HBM_PEAK_GBS = 8000.0
 # 19 slots (FP64 multiply and FMA for the phase at half rate, FP64 round and
 # subtract, FP64->FP32 convert, sin and cos at quarter rate, two FP32 FMA).
 DFT_PEAK_GPAIRS = 78.6e3 / 19.0
+# The one-pass forward + restricted adjoint uses each pair's sin/cos twice: the
+# same 19 slots plus two FP32 FMAs for the adjoint's accumulation.
+FUSED_PEAK_GPAIRS = 78.6e3 / 21.0
 # Source files each kernel is compiled from (with the shared headers): a
 # stored HBM-traffic figure is used only while these are unchanged.
 CSRC = os.path.join(ROOT, "paper_2406_01342_amd", "csrc")
 KERNEL_FILES = {
     "adjoint_sparse": ["kernels_dft.hip"], "adjoint_sparse_reduce": ["kernels_dft.hip"],
-    "forward_sparse": ["kernels_dft.hip"],
+    "forward_sparse": ["kernels_dft.hip"], "forward_adjoint_sparse": ["kernels_dft.hip"],
     "spread": ["kernels_grid.hip", "fft_lds.h"], "fold": ["kernels_grid.hip", "fft_lds.h"],
     "passA_adj": ["kernels_grid.hip", "fft_lds.h"], "passB_adj": ["kernels_grid.hip", "fft_lds.h"],
-    "fista": ["kernels_solver.hip", "solver_kernels.h"],
-    "power": ["kernels_solver.hip", "solver_kernels.h"],
 }
 # kernel name in the library's statistics -> substring of its symbol
 KERNEL_SYMBOLS = {
     "adjoint_sparse": "adjoint_sparse_kernel<float>", "forward_sparse": "forward_sparse_kernel<float>",
     "adjoint_sparse_reduce": "adjoint_sparse_reduce_kernel<float>",
+    "forward_adjoint_sparse": "forward_adjoint_kernel<",
     "spread": "spread_kernel<float", "fold": "fold_kernel<float>", "passA_adj": "passA_adj_kernel<float",
-    "passB_adj": "passB_adj_kernel<float", "fista": "fista_kernel", "power": "power_kernel",
+    "passB_adj": "passB_adj_kernel<float",
 }
 PROFILES = os.path.join(ROOT, "profiles")
 COPY_PROBE_BYTES = 512 << 20
@@ -166,6 +168,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving trace (0 skips the serving leg)")
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the adjoint measurements at the 4096^2 and 8192^2 workloads")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_KERNEL.json from two rocprofv3 --pmc runs")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"),
@@ -196,12 +200,13 @@ def dominant_roofline(stats, plan_info):
     top = max(stats, key=lambda s: s["ms"])
     avg_ms = top["ms"] / top["launches"]
     name = top["name"]
-    if name in ("forward_sparse", "adjoint_sparse"):
+    if name in ("forward_sparse", "adjoint_sparse", "forward_adjoint_sparse"):
         pairs = top["work"] / top["launches"]
         achieved = pairs / (avg_ms * 1e-3) / 1e9
+        peak = FUSED_PEAK_GPAIRS if name == "forward_adjoint_sparse" else DFT_PEAK_GPAIRS
         return {"kernel": name, "bound": "alu", "achieved": achieved,
-                "peak": DFT_PEAK_GPAIRS, "unit": "Gpair/s",
-                "frac": achieved / DFT_PEAK_GPAIRS,
+                "peak": peak, "unit": "Gpair/s",
+                "frac": achieved / peak,
                 "traffic": stored_traffic(name), "avg_ms": avg_ms, "launches": top["launches"],
                 "work_per_launch": pairs}
     b = top["bytes"] / top["launches"]
@@ -233,6 +238,40 @@ def cpu_baseline(p, vis, seconds):
     return {"value": m / dt / 1e6, "unit": "Mvis/s", "cores": int(cores), "kind": "oracle",
             "sample": f"FP64 exact adjoint (direct sum as chunked complex GEMM) of the first {m} "
                       f"of {len(v)} visibilities onto the full {p.npix}^2 image, {dt:.1f} s"}
+
+
+def adjoint_at(api, torch, p, reps, label):
+    """Gridded adjoint throughput on another workload (caller-order input):
+    device time per adjoint (sum of its kernels, library events), Mvis/s and
+    the fraction of HBM peak for the implemented dataflow and for the
+    unpruned 16 L + 100 N byte model."""
+    t = time.perf_counter()
+    plan, vis = synth_inputs(api, torch, p)
+    torch.cuda.synchronize()
+    synth_s = time.perf_counter() - t
+    dv = torch.from_numpy(vis).cuda()
+    img = torch.empty((p.npix, p.npix), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    api.pc_plan_profile(plan, True)
+    for _ in range(reps):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    st = api.pc_plan_kernel_stats(plan)
+    api.pc_plan_profile(plan, False)
+    ms = sum(x["ms"] for x in st) / reps
+    b = sum(x["bytes"] for x in st) / reps
+    n = p.npix
+    f1 = 16 * p.nvis + 100 * n * n
+    out = {"workload": label, "nvis": p.nvis, "npix": n, "fine_grid": plan.info["fine"],
+           "band": [plan.info["band_nu"], plan.info["band_nv"]], "wraps": plan.info["wraps"],
+           "device_ms": ms, "mvis_per_s": p.nvis / ms / 1e3,
+           "algorithmic_bytes": b, "hbm_frac_implemented": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "bytes_model_f1": f1, "hbm_frac_f1": f1 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "kernels_us": {x["name"]: round(1e3 * x["ms"] / x["launches"], 2) for x in st},
+           "setup_s": synth_s}
+    log(label, {k: out[k] for k in ("device_ms", "mvis_per_s", "hbm_frac_implemented")})
+    plan.close()
+    return out
 
 
 def serving_leg(api, torch, n_req, slots):
@@ -407,6 +446,14 @@ def main():
         "kernels": sorted(({"name": s_["name"], "launches": s_["launches"], "ms": round(s_["ms"], 3)}
                            for s_ in stats), key=lambda d: -d["ms"])[:8],
     }
+    if not args.no_other_workloads:
+        out["adjoint_other_workloads"] = [
+            adjoint_at(api, torch, sim.config_c3(), args.adjoint_reps,
+                       "precision workload: 256 stations, 2,088,960 visibilities, 4096^2, FOV 3 deg"),
+            adjoint_at(api, torch, sim.config_c5_large(), max(5, args.adjoint_reps // 5),
+                       "memory-pressure large job: 512 stations x 16 snapshots x 4 channels, "
+                       "8,372,224 visibilities, 8192^2 (16384^2 fine grid), FOV 3 deg"),
+        ]
     if args.serving_requests > 0:
         del plan, dv
         torch.cuda.empty_cache()

@@ -179,6 +179,20 @@ PC_API pc_status pc_forward_grid(pc_plan* plan, const float* image, void* vis_ou
 PC_API pc_status pc_adjoint_sparse(pc_plan* plan, const void* vis, int64_t natoms,
                             const int32_t* pix, double* out, void* stream);
 
+/* Gradient of the data term on the active set, the step that each APGD
+ * iteration of the restricted solve takes (Alg. 2, step 2):
+ *   r = V - Phi_S x,  grad[p] = Re sum_k r_k exp(+j2pi(u_k l_p + v_k m_p)) / n_p,
+ * i.e. Phi_S* (V - Phi_S x), by direct summation.  Up to 64 atoms, one pass
+ * evaluates each visibility-atom phase once for both operators; larger sets
+ * take pc_forward_sparse then pc_adjoint_sparse.
+ * vis dev complex64 [nvis] caller order; pix dev int32 [natoms]; weight dev
+ * float [natoms] (the amplitudes x_p); grad dev double [natoms]; resid dev
+ * complex64 [nvis] caller order or NULL (not returned; must not alias vis).
+ * natoms = 0 gives r = V and no gradient. */
+PC_API pc_status pc_restricted_gradient(pc_plan* plan, const void* vis, int64_t natoms,
+                                        const int32_t* pix, const float* weight, double* grad,
+                                        void* resid, void* stream);
+
 /* Dual certificate mu = Phi*(V - Phi x) / lambda (Eq. dual_certif) of the
  * sparse image x = (pix, weight).  vis dev complex64 [nvis] caller order;
  * cert dev float [npix*npix]; lambda > 0; max_abs/argmax as for

@@ -197,6 +197,25 @@ def pc_adjoint_sparse(plan: Plan, vis: torch.Tensor, pix: torch.Tensor,
     return out
 
 
+def pc_restricted_gradient(plan: Plan, vis: torch.Tensor, pix: torch.Tensor, weight: torch.Tensor,
+                           grad: Optional[torch.Tensor] = None, want_resid: bool = False,
+                           stream=None):
+    """Phi_S* (V - Phi_S x) on the active set (float64 [natoms]) and, on
+    request, the residual V - Phi_S x (complex64 [nvis], caller order)."""
+    na = int(pix.numel())
+    if grad is None:
+        grad = _new(plan, (na,), torch.float64)
+    resid = _new(plan, (plan.nvis,), torch.complex64) if want_resid else None
+    check(LIB.pc_restricted_gradient(
+        plan.handle, C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")), na,
+        C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+        C.c_void_p(_dev(weight, torch.float32, na, "weight")),
+        C.c_void_p(_dev(grad, torch.float64, na, "grad")),
+        C.c_void_p(_dev(resid, torch.complex64, plan.nvis, "resid") if resid is not None else None),
+        C.c_void_p(_stream(stream))), "pc_restricted_gradient")
+    return (grad, resid) if want_resid else grad
+
+
 def pc_dual_certificate(plan: Plan, vis: torch.Tensor, pix: torch.Tensor, weight: torch.Tensor,
                         lam: float, cert: Optional[torch.Tensor] = None, want_max: bool = True,
                         stream=None):

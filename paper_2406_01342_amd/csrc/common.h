@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -226,7 +227,6 @@ void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R sc
 template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted,
                   hipStream_t s);
-void maxkey_reset(pc_plan* p, hipStream_t s);
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax);
 // Launch tables of the batched adjoint (device copy and pinned staging),
 // reused from call to call.
@@ -265,7 +265,13 @@ void forward_sparse(pc_plan* p, int64_t natoms, const int32_t* pix, const R* wei
 template <typename R>
 void adjoint_sparse(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                     const int32_t* pix, double* out, hipStream_t s);
+// Entries of an atom table for natoms atoms: rounded up to a multiple of 8,
+// the padding being zero-weight atoms (the fused pass reads whole groups).
+inline int64_t atom_capacity(int64_t natoms) {
+  return (std::max<int64_t>(natoms, 1) + 7) / 8 * 8;
+}
 // Variants on a prepared atom table (the solver keeps one per active set).
+// prep_atoms_into fills atom_capacity(natoms) entries.
 template <typename R>
 void prep_atoms_into(pc_plan* p, int64_t natoms, const int32_t* pix, const R* weight,
                      Atom<R>* atoms, hipStream_t s);
@@ -275,6 +281,21 @@ void forward_atoms(pc_plan* p, int64_t natoms, const Atom<R>* atoms, const cpx<R
 template <typename R>
 void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                    const Atom<R>* atoms, double* partial, double* out, hipStream_t s);
+template <typename R>
+void reduce_partials(pc_plan* p, int64_t natoms, int64_t nwg, const double* partial,
+                     const Atom<R>* atoms, double* out, hipStream_t s);
+// Forward and restricted adjoint in one pass for 1..64 atoms (FP32):
+// r = base - Phi_S w (or Phi_S w when base is NULL), written to r_out when
+// given, and the partial sums of Phi_S* r, fused_partial_stride() per atom.
+bool fused_supported(int64_t natoms);
+int64_t fused_partial_stride(const pc_plan* p, int64_t natoms);
+void forward_adjoint_atoms(pc_plan* p, int64_t natoms, const Atom<float>* atoms,
+                           const cpx<float>* base, cpx<float>* r_out, double* partial,
+                           hipStream_t s, bool caller_order = false);
+// g = Phi_S* (V - Phi_S x) with r = V - Phi_S x optionally returned (caller
+// order throughout); one pass for 1..64 atoms, else forward then adjoint.
+void restricted_gradient(pc_plan* p, const cpx<float>* vis, int64_t natoms, const int32_t* pix,
+                         const float* weight, double* out, cpx<float>* resid, hipStream_t s);
 int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms);
 // Partials per atom of adjoint_atoms (out == NULL leaves them unsummed).
 int64_t adjoint_partial_stride(const pc_plan* p, int64_t natoms);

@@ -11,15 +11,22 @@
 #include <algorithm>
 #include <cstring>
 
+#include <atomic>
+
 #include "common.h"
 
 namespace pc {
 
 template <typename R>
-__global__ void atom_prep_kernel(int64_t natoms, int n, double dl, const int32_t* __restrict__ pix,
-                                 const R* __restrict__ weight, Atom<R>* __restrict__ atoms) {
+__global__ void atom_prep_kernel(int64_t natoms, int64_t ntotal, int n, double dl,
+                                 const int32_t* __restrict__ pix, const R* __restrict__ weight,
+                                 Atom<R>* __restrict__ atoms) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= natoms) return;
+  if (p >= ntotal) return;
+  if (p >= natoms) {  // padding: the phase-centre pixel with zero weight
+    atoms[p] = Atom<R>{0.0, 0.0, 1.0, R(0), R(0)};
+    return;
+  }
   const int q = pix[p];
   const int i = q / n, j = q - i * n;
   const double a = (double)(i - n / 2), b = (double)(j - n / 2);
@@ -295,8 +302,9 @@ template <typename R>
 void prep_atoms_into(pc_plan* p, int64_t natoms, const int32_t* pix, const R* weight,
                      Atom<R>* atoms, hipStream_t s) {
   if (natoms <= 0) return;
-  hipLaunchKernelGGL((atom_prep_kernel<R>), dim3((unsigned)((natoms + 255) / 256)), dim3(256), 0,
-                     s, natoms, p->g.n, p->g.dl, pix, weight, atoms);
+  const int64_t ntotal = atom_capacity(natoms);
+  hipLaunchKernelGGL((atom_prep_kernel<R>), dim3((unsigned)((ntotal + 255) / 256)), dim3(256), 0,
+                     s, natoms, ntotal, p->g.n, p->g.dl, pix, weight, atoms);
   PC_LAUNCH_CHECK("atom_prep");
 }
 
@@ -314,10 +322,216 @@ void forward_atoms(pc_plan* p, int64_t natoms, const Atom<R>* atoms, const cpx<R
   PC_LAUNCH_CHECK("forward_sparse");
 }
 
+// Forward and restricted adjoint in one pass, for active sets of at most
+// kFusedMaxAtoms atoms (FP32 path).  For each visibility k:
+//   r_k = base_k - sum_p w_p e^{-2 pi i t_kp}   (or the sum itself, no base)
+// and every atom accumulates Re(r_k e^{+2 pi i t_kp}) with the same phase
+// (one FP64 phase and one sin/cos per pair serve both operators).  Lanes run
+// over visibilities, atoms are wave-uniform (scalar loads); each lane keeps
+// the NB cosines and sines of its current visibility and NB running sums in
+// registers.  A wave covers kpw consecutive visibilities and writes one
+// partial per atom, partial[p * nwaves + wave] (FP32; summed in FP64 later,
+// times 1/n_p, in a fixed order).  r is written only when r_out is given.
+// Visibilities are in plan order; base_perm / out_perm (plan -> caller index)
+// read the base from and write r to caller order instead.
+constexpr int kFusedMaxAtoms = 64;
+
+// One step of the recursive-halving lane reduction (compile-time counts, so
+// that the values stay in registers).
+template <int CNT, int D>
+__device__ __forceinline__ void halve_reduce(float* g, int lane) {
+  if constexpr (D >= 1) {
+    if constexpr (CNT > 1) {
+      constexpr int h = CNT / 2;
+      const bool up = (lane & D) != 0;
+#pragma unroll
+      for (int q = 0; q < h; ++q) {
+        const float keep = up ? g[q + h] : g[q];
+        const float send = up ? g[q] : g[q + h];
+        g[q] = keep + __shfl_xor(send, D, 64);
+      }
+      halve_reduce<h, D / 2>(g, lane);
+    } else {
+      g[0] += __shfl_xor(g[0], D, 64);
+      halve_reduce<1, D / 2>(g, lane);
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void forward_adjoint_kernel(
+    int64_t L, int natoms, int64_t kpw, int64_t nwaves, const double* __restrict__ AB,
+    const Atom<float>* __restrict__ atoms, const cpx<float>* __restrict__ base,
+    const int32_t* __restrict__ base_perm, cpx<float>* __restrict__ r_out,
+    const int32_t* __restrict__ out_perm, float* __restrict__ partial) {
+  constexpr int P2 = NB <= 8 ? 8 : (NB <= 16 ? 16 : (NB <= 32 ? 32 : 64));  // reduction width
+  constexpr int SH = P2 == 8 ? 3 : (P2 == 16 ? 2 : (P2 == 32 ? 1 : 0));   // log2(64 / P2)
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wv >= nwaves) return;  // no workgroup barrier below
+  const int64_t k0 = wv * kpw;
+  const int64_t k1 = k0 + kpw < L ? k0 + kpw : L;
+  float g[P2];
+#pragma unroll
+  for (int q = 0; q < P2; ++q) g[q] = 0.f;
+  // the next group's coordinates and base value are loaded one group ahead
+  double An = 0.0, Bn = 0.0;
+  cpx<float> vn{0.f, 0.f};
+  if (k0 + lane < k1) {
+    An = AB[2 * (k0 + lane)];
+    Bn = AB[2 * (k0 + lane) + 1];
+    if (base) vn = base[base_perm ? base_perm[k0 + lane] : k0 + lane];
+  }
+  for (int64_t kb = k0; kb < k1; kb += 64) {
+    const int64_t k = kb + lane;
+    const bool live = k < k1;
+    const double A = An, B = Bn;
+    const cpx<float> v = vn;
+    const int64_t kq = k + 64;
+    if (kq < k1) {
+      An = AB[2 * kq];
+      Bn = AB[2 * kq + 1];
+      if (base) vn = base[base_perm ? base_perm[kq] : kq];
+    }
+    float c[NB], sn[NB];
+    float fr = 0.f, fi = 0.f;
+    // opaque per iteration: the atom loads stay in the loop (as scalar loads
+    // next to their use) instead of being hoisted and kept in spilled SGPRs
+    uint64_t ai = reinterpret_cast<uint64_t>(atoms);
+    asm volatile("" : "+s"(ai));
+    const __attribute__((address_space(4))) Atom<float>* ap =
+        reinterpret_cast<const __attribute__((address_space(4))) Atom<float>*>(ai);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      // entries natoms..NB-1 are zero-weight padding (their sums are never stored)
+      const double aa = ap[q].a, ab = ap[q].b;
+      const float w = ap[q].w;
+      double t = fma(A, aa, B * ab);
+      t -= rint(t);
+      sincos_turns<float>(t, sn[q], c[q]);
+      fr = fmaf(w, c[q], fr);
+      fi = fmaf(w, sn[q], fi);
+    }
+    // sum_p w_p e^{-i theta} = fr - i fi
+    float rx = base ? v.x - fr : fr;
+    float ry = base ? v.y + fi : -fi;
+    if (!live) rx = ry = 0.f;
+    if (r_out && live) r_out[out_perm ? out_perm[k] : k] = {rx, ry};
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      g[q] = fmaf(rx, c[q], g[q]);
+      g[q] = fmaf(-ry, sn[q], g[q]);
+    }
+  }
+  // Sum the P2 values over the 64 lanes by recursive halving: at distance d
+  // a lane keeps one half of its values (the upper half when bit d of its
+  // index is set) and adds its partner's copy of that half.  Lane l ends with
+  // the total of value l >> SH.
+  halve_reduce<P2, 32>(g, lane);
+  const int idx = lane >> SH;
+  if ((lane & ((1 << SH) - 1)) == 0 && idx < natoms) partial[(int64_t)idx * nwaves + wv] = g[0];
+}
+
+struct FusedShape {
+  int nb;          // atoms per pass (template), >= natoms
+  int64_t kpw;     // visibilities per wave (a multiple of 64)
+  int64_t nwaves;  // waves, one partial each per atom
+};
+
+// Waves of forward_adjoint_kernel<NB> resident on the device at once (the
+// kernel is register-limited: 3 NB values per lane), from the runtime's
+// occupancy calculator; cached per device and NB.
+static int64_t fused_resident_waves(int nb) {
+  constexpr int kDev = 64;
+  static std::atomic<int64_t> cache[kDev][kFusedMaxAtoms / 8 + 1];  // zero-initialised
+  int dev = 0;
+  PC_HIP(hipGetDevice(&dev));
+  std::atomic<int64_t>& slot = cache[dev < kDev ? dev : 0][nb / 8];
+  const int64_t known = slot.load(std::memory_order_relaxed);
+  if (known > 0) return known;
+  const void* fn = nullptr;
+  switch (nb) {
+#define PC_NB(n) \
+  case n:        \
+    fn = (const void*)forward_adjoint_kernel<n>; \
+    break;
+    PC_NB(8) PC_NB(16) PC_NB(24) PC_NB(32) PC_NB(40) PC_NB(48) PC_NB(56) PC_NB(64)
+#undef PC_NB
+    default:
+      fail(PC_ERR_UNSUPPORTED, "forward_adjoint_atoms: atoms per pass");
+  }
+  int blocks = 0, cus = 0;
+  PC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 256, 0));
+  PC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t waves = std::max<int64_t>(1, (int64_t)blocks * 4 * cus);
+  slot.store(waves, std::memory_order_relaxed);
+  return waves;
+}
+
+static FusedShape fused_shape(int64_t L, int64_t natoms) {
+  FusedShape f{};
+  f.nb = (int)((natoms + 7) / 8 * 8);
+  // one round of resident waves, each over a contiguous range
+  const int64_t target = fused_resident_waves(f.nb);
+  const int64_t k = (L + target - 1) / target;
+  f.kpw = std::max<int64_t>(64, (k + 63) / 64 * 64);
+  f.nwaves = (L + f.kpw - 1) / f.kpw;
+  return f;
+}
+
+bool fused_supported(int64_t natoms) { return natoms >= 1 && natoms <= kFusedMaxAtoms; }
+
+int64_t fused_partial_stride(const pc_plan* p, int64_t natoms) {
+  return fused_shape(p->L, natoms).nwaves;
+}
+
+void forward_adjoint_atoms(pc_plan* p, int64_t natoms, const Atom<float>* atoms,
+                           const cpx<float>* base, cpx<float>* r_out, double* partial,
+                           hipStream_t s, bool caller_order) {
+  if (!fused_supported(natoms))
+    fail(PC_ERR_INVALID_ARG, "forward_adjoint_atoms: active set of " + std::to_string(natoms) +
+                             " atoms (1.." + std::to_string(kFusedMaxAtoms) + " supported)");
+  const FusedShape f = fused_shape(p->L, natoms);
+  float* part = reinterpret_cast<float*>(partial);
+  ProfScope ps(p, s, "forward_adjoint_sparse",
+               p->L * (16.0 + (base ? 8.0 : 0.0) + (r_out ? 8.0 : 0.0)) +
+                   4.0 * f.nwaves * natoms + 32.0 * natoms,
+               (double)p->L * natoms);
+  const unsigned nblk = (unsigned)((f.nwaves + 3) / 4);
+  const int32_t* perm = caller_order ? p->perm : nullptr;
+  switch (f.nb) {
+#define PC_NB(nb)                                                                              \
+  case nb:                                                                                     \
+    hipLaunchKernelGGL((forward_adjoint_kernel<nb>), dim3(nblk), dim3(256), 0, s, p->L,         \
+                       (int)natoms, f.kpw, f.nwaves, p->AB, atoms, base, perm, r_out, perm,     \
+                       part);                                                                  \
+    break;
+    PC_NB(8) PC_NB(16) PC_NB(24) PC_NB(32) PC_NB(40) PC_NB(48) PC_NB(56) PC_NB(64)
+#undef PC_NB
+    default:
+      fail(PC_ERR_UNSUPPORTED, "forward_adjoint_atoms: atoms per pass");
+  }
+  PC_LAUNCH_CHECK("forward_adjoint_sparse");
+}
+
+// out[p] = (1/n_p) sum_c partial[p * nwg + c] for partials stored as R.
+template <typename R>
+void reduce_partials(pc_plan* p, int64_t natoms, int64_t nwg, const double* partial,
+                     const Atom<R>* atoms, double* out, hipStream_t s) {
+  if (natoms <= 0) return;
+  ProfScope ps(p, s, "adjoint_sparse_reduce", (double)sizeof(R) * nwg * natoms,
+               (double)nwg * natoms);
+  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3((unsigned)natoms), dim3(256), 0, s,
+                     natoms, nwg, reinterpret_cast<const R*>(partial), atoms, out);
+  PC_LAUNCH_CHECK("adjoint_sparse_reduce");
+}
+
 // Partial-sum buffer size, in doubles (the kernels store R values in it).
 int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms) {
-  const AdjShape sh = adjoint_shape(p->L, std::max<int64_t>(natoms, 1));
-  return sh.nwg * std::max<int64_t>(natoms, 1);
+  const int64_t na = std::max<int64_t>(natoms, 1);
+  int64_t nwg = adjoint_shape(p->L, na).nwg;
+  if (fused_supported(na)) nwg = std::max(nwg, fused_shape(p->L, na).nwaves);
+  return nwg * na;  // also holds the fused pass's partials
 }
 
 int64_t adjoint_partial_stride(const pc_plan* p, int64_t natoms) {
@@ -340,27 +554,45 @@ void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natom
     PC_LAUNCH_CHECK("adjoint_sparse");
   }
   if (!out) return;  // the caller sums the partials (fused with its next step)
-  ProfScope ps(p, s, "adjoint_sparse_reduce", (double)sizeof(R) * sh.nwg * natoms,
-               (double)sh.nwg * natoms);
-  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3((unsigned)natoms), dim3(256), 0, s,
-                     natoms, sh.nwg, (const R*)part, atoms, out);
-  PC_LAUNCH_CHECK("adjoint_sparse_reduce");
+  reduce_partials<R>(p, natoms, sh.nwg, partial, atoms, out, s);
 }
 
 template <typename R>
 void forward_sparse(pc_plan* p, int64_t natoms, const int32_t* pix, const R* weight,
                     const cpx<R>* vis_base, bool base_sorted, cpx<R>* out, bool out_sorted,
                     hipStream_t s) {
-  Atom<R>* atoms = (Atom<R>*)ensure_atom_scratch(p, std::max<int64_t>(natoms, 1) * sizeof(Atom<R>));
+  Atom<R>* atoms = (Atom<R>*)ensure_atom_scratch(p, atom_capacity(natoms) * sizeof(Atom<R>));
   prep_atoms_into<R>(p, natoms, pix, weight, atoms, s);
   forward_atoms<R>(p, natoms, atoms, vis_base, base_sorted, out, out_sorted, s);
+}
+
+void restricted_gradient(pc_plan* p, const c32* vis, int64_t natoms, const int32_t* pix,
+                         const float* weight, double* out, c32* resid, hipStream_t s) {
+  if (natoms == 0) {  // r = V
+    if (resid)
+      PC_HIP(hipMemcpyAsync(resid, vis, p->L * sizeof(c32), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  Atom<float>* atoms =
+      (Atom<float>*)ensure_atom_scratch(p, atom_capacity(natoms) * sizeof(Atom<float>));
+  prep_atoms_into<float>(p, natoms, pix, weight, atoms, s);
+  double* partial = ensure_red_scratch(p, (size_t)adjoint_partial_count(p, natoms));
+  if (fused_supported(natoms)) {
+    forward_adjoint_atoms(p, natoms, atoms, vis, resid, partial, s, true);
+    reduce_partials<float>(p, natoms, fused_partial_stride(p, natoms), partial, atoms, out, s);
+    return;
+  }
+  // r in caller order (resid) or in plan order (scratch)
+  c32* r = resid ? resid : (c32*)p->vis_scratch;
+  forward_atoms<float>(p, natoms, atoms, vis, false, r, resid == nullptr, s);
+  adjoint_atoms<float>(p, r, resid == nullptr, natoms, atoms, partial, out, s);
 }
 
 template <typename R>
 void adjoint_sparse(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                     const int32_t* pix, double* out, hipStream_t s) {
   if (natoms == 0) return;
-  Atom<R>* atoms = (Atom<R>*)ensure_atom_scratch(p, std::max<int64_t>(natoms, 1) * sizeof(Atom<R>));
+  Atom<R>* atoms = (Atom<R>*)ensure_atom_scratch(p, atom_capacity(natoms) * sizeof(Atom<R>));
   prep_atoms_into<R>(p, natoms, pix, (const R*)nullptr, atoms, s);
   double* partial = ensure_red_scratch(p, (size_t)adjoint_partial_count(p, natoms));
   adjoint_atoms<R>(p, vis, vis_sorted, natoms, atoms, partial, out, s);
@@ -378,6 +610,8 @@ template void prep_atoms_into<float>(pc_plan*, int64_t, const int32_t*, const fl
                                      hipStream_t);
 template void forward_atoms<float>(pc_plan*, int64_t, const Atom<float>*, const c32*, bool, c32*,
                                    bool, hipStream_t);
+template void reduce_partials<float>(pc_plan*, int64_t, int64_t, const double*, const Atom<float>*,
+                                     double*, hipStream_t);
 template void adjoint_atoms<float>(pc_plan*, const c32*, bool, int64_t, const Atom<float>*,
                                    double*, double*, hipStream_t);
 

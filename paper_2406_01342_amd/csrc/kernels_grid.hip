@@ -286,7 +286,11 @@ template <typename R, int W>
 __global__ __launch_bounds__(64) void spread_kernel(
     GridGeom g, const SpreadChunk* __restrict__ chunks, const uint32_t* __restrict__ cell,
     const R* __restrict__ off, const cpx<R>* __restrict__ vals, const int32_t* __restrict__ perm,
-    cpx<R>* __restrict__ grid, cpx<R>* __restrict__ partials) {
+    cpx<R>* __restrict__ grid, cpx<R>* __restrict__ partials,
+    unsigned long long* __restrict__ maxkey) {
+  // the image maximum that the last pass accumulates starts from zero (reset
+  // here rather than by a launch of its own; the pass runs later on the stream)
+  if (blockIdx.x == 0 && threadIdx.x == 0) *maxkey = 0ull;
   spread_body<R, W>(g, chunks[blockIdx.x], cell, off, vals, perm, grid, partials);
 }
 
@@ -296,13 +300,15 @@ __global__ __launch_bounds__(64) void spread_batch_kernel(const AdjJob* __restri
                                                           const int2* __restrict__ items) {
   const int2 it = items[blockIdx.x];
   const AdjJob& J = jobs[it.x];
+  if (it.y == 0 && threadIdx.x == 0) *J.maxkey = 0ull;  // every job has an item 0
   spread_body<float, W>(J.g, J.chunks[it.y], J.cell, J.off, J.vals, J.perm, J.grid, J.partials);
 }
 
 // Fold of a split tile: 64 cells per workgroup, kFoldSub threads per cell
-// each summing every kFoldSub-th partial (several loads in flight), then the
+// each summing every kFoldSub-th partial (kFoldBurst loads in flight), then the
 // sub-sums are added in a fixed order (bitwise reproducible).
 constexpr int kFoldSub = 8;
+constexpr int kFoldBurst = 4;  // loads in flight per thread
 
 template <typename R>
 __device__ __forceinline__ void fold_body(const GridGeom& g, const FoldItem& it,
@@ -314,12 +320,12 @@ __device__ __forceinline__ void fold_body(const GridGeom& g, const FoldItem& it,
   const cpx<R>* src = partials + (size_t)it.first * kTile * kTile + i;
   R ax = 0, ay = 0;
   int q = sub;
-  for (; q + 3 * kFoldSub < it.count; q += 4 * kFoldSub) {
-    cpx<R> v[4];
+  for (; q + (kFoldBurst - 1) * kFoldSub < it.count; q += kFoldBurst * kFoldSub) {
+    cpx<R> v[kFoldBurst];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = src[(size_t)(q + u * kFoldSub) * kTile * kTile];
+    for (int u = 0; u < kFoldBurst; ++u) v[u] = src[(size_t)(q + u * kFoldSub) * kTile * kTile];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kFoldBurst; ++u) {
       ax += v[u].x;
       ay += v[u].y;
     }
@@ -686,13 +692,6 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
   out[d] = {ax, ay};
 }
 
-__global__ void maxkey_reset_kernel(unsigned long long* k) { *k = 0ull; }
-
-__global__ void maxkey_reset_batch_kernel(const AdjJob* __restrict__ jobs, int n) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) *jobs[j].maxkey = 0ull;
-}
-
 // ----------------------------------------------------------------------------
 // Host launchers
 // ----------------------------------------------------------------------------
@@ -708,7 +707,7 @@ static void launch_spread_w(pc_plan* p, const cpx<R>* vals, const int32_t* perm,
   hipLaunchKernelGGL((spread_kernel<R, W>), dim3((unsigned)p->n_chunks), dim3(64),
                      C::lds_bytes, s, p->g,
                      p->chunks, p->cell, (const R*)p->off, vals, perm, (cpx<R>*)p->grid,
-                     (cpx<R>*)p->partials);
+                     (cpx<R>*)p->partials, p->maxkey);
   PC_LAUNCH_CHECK("spread");
 }
 
@@ -867,10 +866,6 @@ static void dispatch_M(pc_plan* p, bool adjoint, R* img_out, const R* img_in, R 
   }
 }
 
-void maxkey_reset(pc_plan* p, hipStream_t s) {
-  hipLaunchKernelGGL(maxkey_reset_kernel, dim3(1), dim3(1), 0, s, p->maxkey);
-  PC_LAUNCH_CHECK("maxkey_reset");
-}
 
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax) {
   unsigned long long key = 0;
@@ -890,8 +885,7 @@ void maxkey_decode(unsigned long long key, double* max_abs, int64_t* argmax) {
 template <typename R>
 void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R scale,
                   hipStream_t s) {
-  maxkey_reset(p, s);
-  launch_spread<R>(p, vis, vis_sorted ? nullptr : p->perm, s);
+  launch_spread<R>(p, vis, vis_sorted ? nullptr : p->perm, s);  // also clears the max key
   dispatch_M<R>(p, true, image, nullptr, scale, s);
 }
 
@@ -1090,8 +1084,6 @@ void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* 
   std::memcpy(ctx.host, blob.bytes.data(), bytes);
   PC_HIP(hipMemcpyAsync(ctx.dev, ctx.host, bytes, hipMemcpyHostToDevice, s));
   const AdjJob* djobs = (const AdjJob*)(ctx.dev + o_jobs);
-  hipLaunchKernelGGL(maxkey_reset_batch_kernel, dim3((n + 63) / 64), dim3(64), 0, s, djobs, n);
-  PC_LAUNCH_CHECK("maxkey_reset_batch");
   for (size_t w = 0; w < Ws.size(); ++w)
     if (n_spread[w])
       spread_batch(Ws[w], djobs, (const int2*)(ctx.dev + o_spread[w]), (int)n_spread[w], s);

@@ -107,84 +107,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// One FISTA step on the active set (single workgroup):
-//   z = y + g / Lip        (g = Phi_S^*(V - Phi_S y): minus the gradient)
-//   x+ = soft(z, lam / Lip)
-//   t+ = (1 + sqrt(1 + 4 t^2)) / 2,  y+ = x+ + ((t - 1) / t+)(x+ - x)
-// writes the forward weights y+ / n for the next residual, and the
-// statistics ||x+ - x||^2, ||x+||^2, ||y||_1 and max |g| (the last two at the
-// gradient point y, for the restricted duality gap).
-__global__ __launch_bounds__(1024) void fista_kernel(int64_t nS, const double* __restrict__ g,
-                                                     double* __restrict__ x, double* __restrict__ y,
-                                                     Atom<float>* __restrict__ atoms,
-                                                     double* __restrict__ scal, double lam) {
-  __shared__ double sh[16];
-  const double lip = scal[kScalLip];
-  const double t = scal[kScalT];
-  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-  const double mom = (t - 1.0) / tn;
-  const double thr = lam / lip;
-  double d2 = 0, n2 = 0, yl1 = 0, gmax = 0;
-  for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) {
-    yl1 += fabs(y[p]);
-    gmax = fmax(gmax, fabs(g[p]));
-    const double z = y[p] + g[p] / lip;
-    const double az = fabs(z) - thr;
-    const double xn = az > 0 ? copysign(az, z) : 0.0;
-    const double xo = x[p];
-    const double yn = xn + mom * (xn - xo);
-    d2 += (xn - xo) * (xn - xo);
-    n2 += xn * xn;
-    x[p] = xn;
-    y[p] = yn;
-    atoms[p].w = (float)(yn * atoms[p].inv_n);
-  }
-  d2 = block_sum<1024>(d2, sh);
-  n2 = block_sum<1024>(n2, sh);
-  yl1 = block_sum<1024>(yl1, sh);
-  gmax = block_max<1024>(gmax, sh);
-  if (threadIdx.x == 0) {
-    scal[kScalT] = tn;
-    scal[kScalDiff2] = d2;
-    scal[kScalNorm2] = n2;
-    scal[kScalYL1] = yl1;
-    scal[kScalGmax] = gmax;
-  }
-}
-
-// Power iteration on G = Re(Phi_S^H Phi_S): given gv = G v with ||v|| = 1,
-// records ||G v|| and sets v <- G v / ||G v|| as the next forward weights.
-__global__ __launch_bounds__(1024) void power_kernel(int64_t nS, const double* __restrict__ gv,
-                                                     double* __restrict__ v,
-                                                     Atom<float>* __restrict__ atoms,
-                                                     double* __restrict__ scal) {
-  __shared__ double sh[16];
-  double s = 0;
-  for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) s += gv[p] * gv[p];
-  s = block_sum<1024>(s, sh);
-  const double nrm = sqrt(s);
-  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-  for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) {
-    const double vn = gv[p] * inv;
-    v[p] = vn;
-    atoms[p].w = (float)(vn * atoms[p].inv_n);
-  }
-  if (threadIdx.x == 0) {
-    scal[kScalPrevEig] = scal[kScalEig];
-    scal[kScalEig] = nrm;
-  }
-}
-
-// v = 1/sqrt(nS) (deterministic start) as forward weights.
-__global__ void power_init_kernel(int64_t nS, double* __restrict__ v,
-                                  Atom<float>* __restrict__ atoms) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nS) return;
-  const double a = 1.0 / sqrt((double)nS);
-  v[p] = a;
-  atoms[p].w = (float)(a * atoms[p].inv_n);
-}
-
 // Forward weights from an FP64 vector: atoms[p].w = x[p] / n_p.
 __global__ void weights_kernel(int64_t nS, const double* __restrict__ x,
                                Atom<float>* __restrict__ atoms) {
@@ -271,25 +193,6 @@ void k_select(pc_plan* p, int64_t N, const float* eta, float tau, unsigned* coun
   hipLaunchKernelGGL(select_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, eta, tau, count, out,
                      cap);
   PC_LAUNCH_CHECK("select");
-}
-
-void k_fista(pc_plan* p, int64_t nS, const double* g, double* x, double* y, Atom<float>* atoms, double* scal,
-             double lam, hipStream_t s) {
-  ProfScope ps(p, s, "fista", 64.0 * nS, (double)nS);
-  hipLaunchKernelGGL(fista_kernel, dim3(1), dim3(1024), 0, s, nS, g, x, y, atoms, scal, lam);
-  PC_LAUNCH_CHECK("fista");
-}
-
-void k_power(pc_plan* p, int64_t nS, const double* gv, double* v, Atom<float>* atoms, double* scal,
-             hipStream_t s) {
-  ProfScope ps(p, s, "power", 40.0 * nS, (double)nS);
-  hipLaunchKernelGGL(power_kernel, dim3(1), dim3(1024), 0, s, nS, gv, v, atoms, scal);
-  PC_LAUNCH_CHECK("power");
-}
-
-void k_power_init(pc_plan* p, int64_t nS, double* v, Atom<float>* atoms, hipStream_t s) {
-  hipLaunchKernelGGL(power_init_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, v, atoms);
-  PC_LAUNCH_CHECK("power_init");
 }
 
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s) {

@@ -239,7 +239,7 @@ struct Pfw {
   void load_active(const std::vector<int32_t>& set, const std::vector<double>& xs_host) {
     const int64_t nS = (int64_t)set.size();
     pix.ensure(nS);
-    atoms.ensure(nS);
+    atoms.ensure(atom_capacity(nS));
     x.ensure(nS);
     y.ensure(nS);
     g.ensure(nS);
@@ -363,8 +363,14 @@ struct Pfw {
     for (int j = 0; j < kLanczosMax; ++j) {
       PC_HIP(hipMemcpyAsync(v.ptr, Q[j].data(), nS * 8, hipMemcpyHostToDevice, s));
       if (!gridded) k_weights(p, nS, v.ptr, atoms.ptr, s);
-      op_forward(gridded, nS, v.ptr, false, r.ptr);
-      op_adjoint(gridded, nS, r.ptr, g.ptr);
+      if (!gridded && fused_supported(nS)) {  // g = Phi_S* Phi_S v in one pass
+        forward_adjoint_atoms(p, nS, atoms.ptr, nullptr, nullptr, adj_partial.ptr, s);
+        reduce_partials<float>(p, nS, fused_partial_stride(p, nS), adj_partial.ptr, atoms.ptr,
+                               g.ptr, s);
+      } else {
+        op_forward(gridded, nS, v.ptr, false, r.ptr);
+        op_adjoint(gridded, nS, r.ptr, g.ptr);
+      }
       PC_HIP(hipMemcpyAsync(w.data(), g.ptr, nS * 8, hipMemcpyDeviceToHost, s));
       PC_HIP(hipStreamSynchronize(s));
       double a = 0;
@@ -454,11 +460,17 @@ struct Pfw {
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
       const double tol = std::max(prm.inner_tol_min, prm.inner_tol0 * rel_gap);
       stat.ensure(2 * nS);
-      const int64_t nwg = adjoint_partial_stride(p, nS);
+      // small direct sets: forward and restricted adjoint share one pass
+      const bool fused = !gridded && fused_supported(nS);
+      const int64_t nwg = fused ? fused_partial_stride(p, nS) : adjoint_partial_stride(p, nS);
       double t = 1.0;  // FISTA momentum sequence, on the host in FP64
       for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
-        op_forward(gridded, nS, y.ptr, true, r.ptr);
         const bool check = (inner - 1) % kCheck == 0;
+        if (fused)  // r_y is needed only by the convergence test
+          forward_adjoint_atoms(p, nS, atoms.ptr, V.ptr, check ? r.ptr : nullptr, adj_partial.ptr,
+                                s);
+        else
+          op_forward(gridded, nS, y.ptr, true, r.ptr);
         if (check) {
           red_partial.ensure(2 * k_resid_blocks(L));
           k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
@@ -467,7 +479,8 @@ struct Pfw {
         const double mom = (t - 1.0) / tn;
         t = tn;
         if (!gridded) {  // partial sums of Phi_S* r, summed by the fused step
-          adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, nullptr, s);
+          if (!fused)
+            adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, nullptr, s);
           reduce_fista(p, nS, nwg, adj_partial.ptr, nullptr, atoms.ptr, x.ptr, y.ptr, g.ptr,
                        stat.ptr, 1.0 / lip, lam / lip, mom, s);
         } else {

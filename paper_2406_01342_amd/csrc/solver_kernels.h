@@ -5,18 +5,12 @@
 
 namespace pc {
 
-// Slots of the solver's FP64 device scalar block.
+// Slots of the solver's FP64 device scalar block (read back together).
 enum : int {
-  kScalLip = 0,      // step-size constant of the restricted problem
-  kScalT = 1,        // FISTA momentum t
-  kScalDiff2 = 2,    // ||x+ - x||^2 of the last FISTA step
-  kScalNorm2 = 3,    // ||x+||^2
-  kScalEig = 4,      // power iteration: latest ||G v||
-  kScalPrevEig = 5,  // and the previous one
-  kScalResid = 6,    // [6] ||r||^2, [7] Re<V, r>
-  kScalYL1 = 8,      // ||y||_1 at the gradient point of the last FISTA step
-  kScalGmax = 9,     // max_p |(Phi_S^* r)_p| there
-  kScalCount = 10
+  kScalResid = 0,  // [0] ||r||^2, [1] Re<V, r>
+  kScalYL1 = 2,    // ||y||_1 at the gradient point of the last APGD step
+  kScalGmax = 3,   // max_p |(Phi_S^* r)_p| there
+  kScalCount = 4
 };
 
 void k_gather(pc_plan* p, int64_t L, const int32_t* perm, const c32* in, c32* out, hipStream_t s);
@@ -24,11 +18,6 @@ int k_resid_blocks(int64_t L);
 void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial, double* out, hipStream_t s);
 void k_select(pc_plan* p, int64_t N, const float* eta, float tau, unsigned* count, int32_t* out, int64_t cap,
               hipStream_t s);
-void k_fista(pc_plan* p, int64_t nS, const double* g, double* x, double* y, Atom<float>* atoms, double* scal,
-             double lam, hipStream_t s);
-void k_power(pc_plan* p, int64_t nS, const double* gv, double* v, Atom<float>* atoms, double* scal,
-             hipStream_t s);
-void k_power_init(pc_plan* p, int64_t nS, double* v, Atom<float>* atoms, hipStream_t s);
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s);
 void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipStream_t s);
 // Gridded-operator helpers for large active sets.
