@@ -259,6 +259,12 @@ typedef struct {
                           /*   sums: 0 = the built-in cost crossover, < 0 =   */
                           /*   never.  The per-iteration residual and gap use */
                           /*   the gridded forward from 4x that size.         */
+  int32_t gram_atoms;     /* direct active sets up to this size solve the     */
+                          /*   restricted problem in Gram form: the exact     */
+                          /*   G = Re(Phi_S^H Phi_S) (direct sums at pixel    */
+                          /*   offsets) and b = Phi_S* V replace the two      */
+                          /*   operators in each APGD and Lanczos step: 0 =   */
+                          /*   256, < 0 = never.                              */
 } pc_solve_params;
 
 typedef struct {

@@ -48,7 +48,7 @@ class PcSolveParams(C.Structure):
                 ("inner_tol0", C.c_double), ("inner_tol_min", C.c_double),
                 ("inner_max_iter", C.c_int32), ("positivity", C.c_int32),
                 ("want_certificate", C.c_int32), ("log_every", C.c_int32),
-                ("grid_atoms", C.c_int32)]
+                ("grid_atoms", C.c_int32), ("gram_atoms", C.c_int32)]
 
 
 class PcSolveResult(C.Structure):

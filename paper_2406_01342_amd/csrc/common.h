@@ -281,6 +281,10 @@ void forward_atoms(pc_plan* p, int64_t natoms, const Atom<R>* atoms, const cpx<R
 template <typename R>
 void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                    const Atom<R>* atoms, double* partial, double* out, hipStream_t s);
+// Restricted adjoint of plan-order visibilities with FP64 accumulation of the
+// FP32 terms (partial: adjoint_partial_count doubles); out[p] in FP64.
+void adjoint_atoms_acc64(pc_plan* p, const cpx<float>* vis, int64_t natoms,
+                         const Atom<float>* atoms, double* partial, double* out, hipStream_t s);
 template <typename R>
 void reduce_partials(pc_plan* p, int64_t natoms, int64_t nwg, const double* partial,
                      const Atom<R>* atoms, double* out, hipStream_t s);

@@ -143,14 +143,15 @@ struct VisRec {
   cpx<R> h;
 };
 
-template <typename R>
-__device__ __forceinline__ void adj_pair(const VisRec<R>& v, double a, double b, R& acc) {
+// One pair's term Re(h e^{+2 pi i t}) added to acc.
+template <typename R, typename A>
+__device__ __forceinline__ void adj_pair(const VisRec<R>& v, double a, double b, A& acc) {
   double t = fma(v.A, a, v.B * b);
   t -= rint(t);
   R sn, cs;
   sincos_turns<R>(t, sn, cs);
-  acc = fma(v.h.x, cs, acc);
-  acc = fma(-v.h.y, sn, acc);
+  acc = fma((A)v.h.x, (A)cs, acc);
+  acc = fma(-(A)v.h.y, (A)sn, acc);
 }
 
 template <typename R>
@@ -172,16 +173,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R>
+template <typename R, typename Acc>
 __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     int64_t L, int64_t natoms, int lgA, int64_t K, int64_t nwg, const double* __restrict__ AB,
     const cpx<R>* __restrict__ vis, const int32_t* __restrict__ perm,
-    const Atom<R>* __restrict__ atoms, R* __restrict__ partial) {
+    const Atom<R>* __restrict__ atoms, Acc* __restrict__ partial) {
   constexpr int T = kAdjRound;
   constexpr int PER = T / 64;  // staged visibilities per lane and round
   static_assert(T % 128 == 0, "a round must hold 4 x 32 visibilities");
   __shared__ VisRec<R> stage[4][2][T];
-  __shared__ R red[4][64];
+  __shared__ Acc red[4][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int A = 1 << lgA;
@@ -200,6 +201,10 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
 #pragma unroll
   for (int q = 0; q < PER; ++q) stage[w][0][q * 64 + lane] = nxt[q];
   wave_sync();
+  // R accumulators per round (at most T / 4 terms each); with Acc = double
+  // each round's four sums are added into FP64 totals, so that FP32 rounding
+  // only ever applies to short runs (relative error ~1e-9 on long coherent sums)
+  Acc tot0 = 0, tot1 = 0, tot2 = 0, tot3 = 0;
   R acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
   for (int j = 0; j < nround; ++j) {
     const int64_t kn = k0 + (int64_t)(j + 1) * T;
@@ -209,10 +214,17 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     }
     const VisRec<R>* cur = stage[w][j & 1];
     for (int i = st; i < T; i += 4 * V) {  // 4 V <= T (V <= 32)
-      adj_pair<R>(cur[i], a, b, acc0);
-      adj_pair<R>(cur[i + V], a, b, acc1);
-      adj_pair<R>(cur[i + 2 * V], a, b, acc2);
-      adj_pair<R>(cur[i + 3 * V], a, b, acc3);
+      adj_pair<R, R>(cur[i], a, b, acc0);
+      adj_pair<R, R>(cur[i + V], a, b, acc1);
+      adj_pair<R, R>(cur[i + 2 * V], a, b, acc2);
+      adj_pair<R, R>(cur[i + 3 * V], a, b, acc3);
+    }
+    if constexpr (sizeof(Acc) != sizeof(R)) {
+      tot0 += (Acc)acc0;
+      tot1 += (Acc)acc1;
+      tot2 += (Acc)acc2;
+      tot3 += (Acc)acc3;
+      acc0 = acc1 = acc2 = acc3 = 0;
     }
     if (j + 1 < nround) {
 #pragma unroll
@@ -220,7 +232,13 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     }
     wave_sync();
   }
-  R acc = (acc0 + acc1) + (acc2 + acc3);
+  if constexpr (sizeof(Acc) == sizeof(R)) {
+    tot0 = acc0;
+    tot1 = acc1;
+    tot2 = acc2;
+    tot3 = acc3;
+  }
+  Acc acc = (tot0 + tot1) + (tot2 + tot3);
   for (int o = A; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
   red[w][lane] = acc;
   __syncthreads();
@@ -229,13 +247,13 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
 }
 
 // out[p] = (1/n_p) sum_c partial[p][c], FP64, one workgroup per atom.
-template <typename R>
+template <typename P, typename R>
 __global__ __launch_bounds__(256) void adjoint_sparse_reduce_kernel(
-    int64_t natoms, int64_t nwg, const R* __restrict__ partial, const Atom<R>* __restrict__ atoms,
+    int64_t natoms, int64_t nwg, const P* __restrict__ partial, const Atom<R>* __restrict__ atoms,
     double* __restrict__ out) {
   __shared__ double red[4];
   const int64_t p = blockIdx.x;
-  const R* row = partial + p * nwg;
+  const P* row = partial + p * nwg;
   double s = 0;
   for (int64_t c = threadIdx.x; c < nwg; c += 256) s += (double)row[c];
 #pragma unroll
@@ -521,7 +539,7 @@ void reduce_partials(pc_plan* p, int64_t natoms, int64_t nwg, const double* part
   if (natoms <= 0) return;
   ProfScope ps(p, s, "adjoint_sparse_reduce", (double)sizeof(R) * nwg * natoms,
                (double)nwg * natoms);
-  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R>), dim3((unsigned)natoms), dim3(256), 0, s,
+  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<R, R>), dim3((unsigned)natoms), dim3(256), 0, s,
                      natoms, nwg, reinterpret_cast<const R*>(partial), atoms, out);
   PC_LAUNCH_CHECK("adjoint_sparse_reduce");
 }
@@ -548,13 +566,31 @@ void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natom
     ProfScope ps(p, s, sizeof(R) == 4 ? "adjoint_sparse" : "adjoint_sparse_f64",
                  p->L * (16 + 2.0 * sizeof(R)) * sh.ngroups + (double)sizeof(R) * sh.nwg * natoms,
                  (double)p->L * natoms);
-    hipLaunchKernelGGL((adjoint_sparse_kernel<R>), dim3((unsigned)(sh.nwg * sh.ngroups)),
+    hipLaunchKernelGGL((adjoint_sparse_kernel<R, R>), dim3((unsigned)(sh.nwg * sh.ngroups)),
                        dim3(256), 0, s, p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, vis,
                        vis_sorted ? nullptr : p->perm, atoms, part);
     PC_LAUNCH_CHECK("adjoint_sparse");
   }
   if (!out) return;  // the caller sums the partials (fused with its next step)
   reduce_partials<R>(p, natoms, sh.nwg, partial, atoms, out, s);
+}
+
+void adjoint_atoms_acc64(pc_plan* p, const c32* vis, int64_t natoms, const Atom<float>* atoms,
+                         double* partial, double* out, hipStream_t s) {
+  if (natoms <= 0) return;
+  const AdjShape sh = adjoint_shape(p->L, natoms);
+  {
+    ProfScope ps(p, s, "adjoint_sparse_acc64",
+                 p->L * 24.0 * sh.ngroups + 8.0 * sh.nwg * natoms, (double)p->L * natoms);
+    hipLaunchKernelGGL((adjoint_sparse_kernel<float, double>),
+                       dim3((unsigned)(sh.nwg * sh.ngroups)), dim3(256), 0, s, p->L, natoms,
+                       sh.lgA, sh.K, sh.nwg, p->AB, vis, (const int32_t*)nullptr, atoms, partial);
+    PC_LAUNCH_CHECK("adjoint_sparse_acc64");
+  }
+  ProfScope ps(p, s, "adjoint_sparse_reduce", 8.0 * sh.nwg * natoms, (double)sh.nwg * natoms);
+  hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<double, float>), dim3((unsigned)natoms),
+                     dim3(256), 0, s, natoms, sh.nwg, (const double*)partial, atoms, out);
+  PC_LAUNCH_CHECK("adjoint_sparse_reduce");
 }
 
 template <typename R>

@@ -107,6 +107,158 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// One Lanczos step on G = Re(Phi_S^H Phi_S), FP64, one workgroup.  Given
+// g = G q_j: alpha_j = q_j . g, w = g - alpha_j q_j - beta_{j-1} q_{j-1},
+// then w is re-orthogonalised twice against q_0..q_j, beta_j = ||w|| and
+// q_{j+1} = w / beta_j (zero when beta_j = 0).  Q holds kmax + 1 rows of nS;
+// ab[j] = alpha_j and ab[kmax + j] = beta_j; w is scratch [nS].  Every thread
+// works on the same indices throughout, so only the reductions synchronise.
+__global__ __launch_bounds__(256) void lanczos_step_kernel(int64_t nS, int j, int kmax,
+                                                           double* __restrict__ Q,
+                                                           const double* __restrict__ g,
+                                                           double* __restrict__ w,
+                                                           double* __restrict__ ab) {
+  __shared__ double sh[4];
+  const double* qj = Q + (int64_t)j * nS;
+  double a = 0;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) a += qj[i] * g[i];
+  a = block_sum<256>(a, sh);
+  const double bp = j > 0 ? ab[kmax + j - 1] : 0.0;
+  const double* qp = j > 0 ? Q + (int64_t)(j - 1) * nS : qj;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] = g[i] - (a * qj[i] + bp * qp[i]);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int q = 0; q <= j; ++q) {
+      const double* qq = Q + (int64_t)q * nS;
+      double d = 0;
+      for (int64_t i = threadIdx.x; i < nS; i += 256) d += qq[i] * w[i];
+      d = block_sum<256>(d, sh);
+      for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] -= d * qq[i];
+    }
+  double b = 0;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) b += w[i] * w[i];
+  b = sqrt(block_sum<256>(b, sh));
+  if (threadIdx.x == 0) {
+    ab[j] = a;
+    ab[kmax + j] = b;
+  }
+  const double inv = b > 0 ? 1.0 / b : 0.0;
+  double* qn = Q + (int64_t)(j + 1) * nS;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) qn[i] = w[i] * inv;
+}
+
+// (G v)_q for the symmetric G as column q (coalesced across threads), with
+// four independent partial sums so that several loads are in flight.
+__device__ __forceinline__ double gram_col_dot(const double* __restrict__ G,
+                                               const double* __restrict__ v, int64_t nS,
+                                               int64_t q) {
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int64_t p = 0;
+  for (; p + 4 <= nS; p += 4) {
+    s0 += G[p * nS + q] * v[p];
+    s1 += G[(p + 1) * nS + q] * v[p + 1];
+    s2 += G[(p + 2) * nS + q] * v[p + 2];
+    s3 += G[(p + 3) * nS + q] * v[p + 3];
+  }
+  for (; p < nS; ++p) s0 += G[p * nS + q] * v[p];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Gram form of the restricted problem (small direct sets).  G is the exact
+// nS x nS matrix Re(Phi_S^H Phi_S) (symmetric, row-major, FP64) and
+// b = Phi_S^* V, so that Phi_S^*(V - Phi_S y) = b - G y.  One APGD step in one
+// workgroup: g = b - G y, x+ = soft(y + g / L, lambda / L),
+// y+ = x+ + mom (x+ - x).  With stats != NULL the duality-gap inputs at y are
+// stored too: ||V - Phi_S y||^2 = v2 - 2 y.b + y.G y, Re<V, V - Phi_S y> =
+// v2 - y.b, ||y||_1 and max |g| (v2 = ||V||^2).
+__global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const double* __restrict__ G,
+                                                         const double* __restrict__ b,
+                                                         double* __restrict__ x,
+                                                         double* __restrict__ y,
+                                                         double* __restrict__ g_out,
+                                                         double* __restrict__ stats, double v2,
+                                                         double inv_lip, double thr, double mom) {
+  __shared__ double sh[4];
+  double yGy = 0, yb = 0, yl1 = 0, gmax = 0;
+  for (int64_t q = threadIdx.x; q < nS; q += 256) {
+    const double s = gram_col_dot(G, y, nS, q);  // (G y)_q
+    const double gq = b[q] - s;
+    g_out[q] = gq;
+    yGy += y[q] * s;
+    yb += y[q] * b[q];
+    yl1 += fabs(y[q]);
+    gmax = fmax(gmax, fabs(gq));
+  }
+  if (stats) {
+    yGy = block_sum<256>(yGy, sh);
+    yb = block_sum<256>(yb, sh);
+    yl1 = block_sum<256>(yl1, sh);
+    gmax = block_max<256>(gmax, sh);
+    if (threadIdx.x == 0) {
+      stats[0] = v2 - 2.0 * yb + yGy;
+      stats[1] = v2 - yb;
+      stats[2] = yl1;
+      stats[3] = gmax;
+    }
+  }
+  __syncthreads();  // every thread has read all of y
+  for (int64_t q = threadIdx.x; q < nS; q += 256) {
+    const double yo = y[q], xo = x[q];
+    const double z = yo + g_out[q] * inv_lip;
+    const double az = fabs(z) - thr;
+    const double xn = az > 0 ? copysign(az, z) : 0.0;
+    x[q] = xn;
+    y[q] = xn + mom * (xn - xo);
+  }
+}
+
+// Lanczos steps j0..j1-1 on the Gram matrix in one workgroup (the recurrence
+// of lanczos_step_kernel with g = G q_j formed in place).  Q rows 0..j0 are
+// set (row 0: the unit start vector); ab as for lanczos_step_kernel.
+__global__ __launch_bounds__(256) void gram_lanczos_kernel(int64_t nS, int j0, int j1, int kmax,
+                                                           const double* __restrict__ G,
+                                                           double* __restrict__ Q,
+                                                           double* __restrict__ w,
+                                                           double* __restrict__ ab) {
+  __shared__ double sh[4];
+  for (int j = j0; j < j1; ++j) {
+    const double* qj = Q + (int64_t)j * nS;
+    double a = 0;
+    for (int64_t i = threadIdx.x; i < nS; i += 256) {
+      const double s = gram_col_dot(G, qj, nS, i);
+      w[i] = s;  // (G q_j)_i
+      a += qj[i] * s;
+    }
+    a = block_sum<256>(a, sh);
+    const double bp = j > 0 ? ab[kmax + j - 1] : 0.0;
+    const double* qp = j > 0 ? Q + (int64_t)(j - 1) * nS : qj;
+    for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] -= a * qj[i] + bp * qp[i];
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q <= j; ++q) {
+        const double* qq = Q + (int64_t)q * nS;
+        double d = 0;
+        for (int64_t i = threadIdx.x; i < nS; i += 256) d += qq[i] * w[i];
+        d = block_sum<256>(d, sh);
+        for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] -= d * qq[i];
+      }
+    double bn = 0;
+    for (int64_t i = threadIdx.x; i < nS; i += 256) bn += w[i] * w[i];
+    bn = sqrt(block_sum<256>(bn, sh));
+    if (threadIdx.x == 0) {
+      ab[j] = a;
+      ab[kmax + j] = bn;
+    }
+    const double inv = bn > 0 ? 1.0 / bn : 0.0;
+    double* qn = Q + (int64_t)(j + 1) * nS;
+    for (int64_t i = threadIdx.x; i < nS; i += 256) qn[i] = w[i] * inv;
+    __syncthreads();  // q_{j+1} (and ab) complete before the next product
+  }
+}
+
+__global__ void fill_cpx_kernel(int64_t n, float re, float im, c32* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = {re, im};
+}
+
 // Forward weights from an FP64 vector: atoms[p].w = x[p] / n_p.
 __global__ void weights_kernel(int64_t nS, const double* __restrict__ x,
                                Atom<float>* __restrict__ atoms) {
@@ -193,6 +345,36 @@ void k_select(pc_plan* p, int64_t N, const float* eta, float tau, unsigned* coun
   hipLaunchKernelGGL(select_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, eta, tau, count, out,
                      cap);
   PC_LAUNCH_CHECK("select");
+}
+
+void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const double* g, double* w,
+                    double* ab, hipStream_t s) {
+  ProfScope ps(p, s, "lanczos_step", 8.0 * nS * (2.0 * (j + 1) * 2 + 5), (double)nS);
+  hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(256), 0, s, nS, j, kmax, Q, g, w, ab);
+  PC_LAUNCH_CHECK("lanczos_step");
+}
+
+void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
+                  double* g, double* stats, double v2, double inv_lip, double thr, double mom,
+                  hipStream_t s) {
+  ProfScope ps(p, s, "gram_fista", 8.0 * nS * (nS + 6), (double)nS * nS);
+  hipLaunchKernelGGL(gram_fista_kernel, dim3(1), dim3(256), 0, s, nS, G, b, x, y, g, stats, v2,
+                     inv_lip, thr, mom);
+  PC_LAUNCH_CHECK("gram_fista");
+}
+
+void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const double* G, double* Q,
+                    double* w, double* ab, hipStream_t s) {
+  ProfScope ps(p, s, "gram_lanczos", 8.0 * nS * (double)(j1 - j0) * (nS + 30), (double)(j1 - j0));
+  hipLaunchKernelGGL(gram_lanczos_kernel, dim3(1), dim3(256), 0, s, nS, j0, j1, kmax, G, Q, w,
+                     ab);
+  PC_LAUNCH_CHECK("gram_lanczos");
+}
+
+void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_cpx_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, n, re, im, out);
+  PC_LAUNCH_CHECK("fill_cpx");
 }
 
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s) {

@@ -23,6 +23,8 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <limits>
+#include <unordered_map>
 
 #include "common.h"
 #include "solver_kernels.h"
@@ -59,11 +61,11 @@ struct Pinned {
   void* get(size_t bytes) {
     if (armed) PC_HIP(hipEventSynchronize(fence));
     armed = false;
-    if (bytes > cap) {
+    if (bytes > cap) {  // grow geometrically: pinning memory is slow
+      const size_t want = std::max<size_t>(bytes, 2 * cap + 4096);
       if (ptr) (void)hipHostFree(ptr);
       ptr = nullptr;
       cap = 0;
-      const size_t want = std::max<size_t>(bytes, 2 * cap + 4096);
       PC_HIP(hipHostMalloc((void**)&ptr, want));
       cap = want;
     }
@@ -84,6 +86,8 @@ struct Pinned {
 };
 
 constexpr int kLanczosMax = 12;       // Lanczos steps per active set (cap)
+constexpr int kLanczosBatch = 4;      // device steps between host readbacks
+constexpr int kGramAtoms = 256;       // default cap of the Gram form (direct sets)
 constexpr double kLanczosTol = 1e-3;  // residual bound relative to the estimate
 constexpr double kLipMargin = 1.01;
 
@@ -146,7 +150,19 @@ struct Pfw {
   DevArray<int32_t> cand, pix;
   DevArray<unsigned> cand_count;
   DevArray<Atom<float>> atoms;
-  DevArray<double> x, y, g, v, adj_partial, red_partial, scal, stat;
+  DevArray<double> x, y, g, adj_partial, red_partial, scal, stat;
+  DevArray<double> lz_Q, lz_w, lz_ab;  // Lanczos basis rows, scratch, alpha/beta
+  // Gram form of the restricted problem: G = Re(Phi_S^H Phi_S) and b = Phi_S^* V.
+  // For coplanar arrays G_pq = psf(a_p - a_q, b_p - b_q) / (n_p n_q) with
+  // psf(da, db) = sum_k cos 2 pi (A_k da + B_k db), kept per solve by offset.
+  std::unordered_map<uint64_t, double> psf;
+  std::unordered_map<int32_t, double> bcache;  // b_p by pixel
+  std::vector<int32_t> g_set;                  // the set of the last G, and G
+  std::vector<double> g_host;
+  DevArray<double> gram_G, gram_b, psf_val, psf_partial;
+  DevArray<Atom<float>> off_atoms;
+  DevArray<c32> ones;
+  double v2 = 0;  // ||V||^2
   Pinned up, down;  // upload staging, small readbacks
   std::vector<int32_t> S;
   std::vector<double> xs;
@@ -226,6 +242,18 @@ struct Pfw {
     PC_HIP(hipStreamSynchronize(s));
   }
 
+  // Restricted duality gap at the gradient point y from the scalar block
+  // ||r_y||^2, Re<V, r_y>, ||y||_1, max |g| (dual point scaled into the
+  // feasible set); true when it is within tol of the restricted objective.
+  bool gap_test_passes(double tol) {
+    double h[4];
+    read_scal(h, kScalResid, 4);
+    const double py = 0.5 * h[0] + lam * h[2];
+    const double sc = h[3] <= lam ? 1.0 : lam / h[3];
+    const double gy = py - (sc * h[1] - 0.5 * sc * sc * h[0]);
+    return gy <= tol * py;
+  }
+
   void residual_stats(double& r2, double& vr) {
     red_partial.ensure(2 * k_resid_blocks(L));
     k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
@@ -243,7 +271,6 @@ struct Pfw {
     x.ensure(nS);
     y.ensure(nS);
     g.ensure(nS);
-    v.ensure(nS);
     adj_partial.ensure(adjoint_partial_count(p, nS));
     if (nS == 0) return;
     unsigned char* h = (unsigned char*)up.get(nS * 12);
@@ -318,6 +345,7 @@ struct Pfw {
     PC_HIP(hipMemcpyAsync(r.ptr, V.ptr, L * sizeof(c32), hipMemcpyDeviceToDevice, s));
     double r2, vr;
     residual_stats(r2, vr);
+    v2 = r2;
     P_prev = 0.5 * r2;
     P = P_prev;
     const double sc = (eta_inf <= lam) ? 1.0 : lam / eta_inf;
@@ -329,6 +357,122 @@ struct Pfw {
     }
   }
 
+  int64_t gram_cap() const {
+    if (prm.gram_atoms > 0) return prm.gram_atoms;
+    return prm.gram_atoms < 0 ? 0 : kGramAtoms;
+  }
+
+  static uint64_t offset_key(int da, int db) {  // psf(-d) = psf(d): one key for both
+    if (da < 0 || (da == 0 && db < 0)) {
+      da = -da;
+      db = -db;
+    }
+    return ((uint64_t)(uint32_t)da << 32) | (uint32_t)(db + (1 << 30));
+  }
+
+  // G and b for the active set: psf values at offsets not seen before in this
+  // solve come from a restricted adjoint of unit visibilities at the offsets,
+  // b_p for atoms not seen before from a restricted adjoint of V (both with
+  // FP64 totals: the gap test forms ||V - Phi_S y||^2 = ||V||^2 - 2 y.b +
+  // y.G y, which cancels); G is assembled on the host and uploaded with b.
+  void build_gram(const std::vector<int32_t>& set) {
+    const int64_t nS = (int64_t)set.size();
+    const int n = p->g.n;
+    std::vector<int> ai(nS), bi(nS);
+    std::vector<double> inv_n(nS);
+    for (int64_t q = 0; q < nS; ++q) {
+      const int i = set[q] / n, j = set[q] - (set[q] / n) * n;
+      ai[q] = i - n / 2;
+      bi[q] = j - n / 2;
+      const double l = ai[q] * p->g.dl, m = bi[q] * p->g.dl;
+      inv_n[q] = 1.0 / std::sqrt(1.0 - l * l - m * m);
+    }
+    // position of each atom in the previous active set (both sets ascending):
+    // pairs of atoms that were both there keep their entry of the previous G
+    std::vector<int64_t> old(nS, -1);
+    for (size_t a = 0, c = 0; a < (size_t)nS && c < g_set.size();) {
+      if (set[a] == g_set[c]) {
+        old[a] = (int64_t)c;
+        ++a;
+        ++c;
+      } else if (set[a] < g_set[c]) {
+        ++a;
+      } else {
+        ++c;
+      }
+    }
+    std::vector<std::pair<int, int>> miss;
+    for (int64_t a = 0; a < nS; ++a)
+      for (int64_t c = a; c < nS; ++c) {
+        if (old[a] >= 0 && old[c] >= 0) continue;
+        int da = ai[a] - ai[c], db = bi[a] - bi[c];
+        if (psf.emplace(offset_key(da, db), std::numeric_limits<double>::quiet_NaN()).second) {
+          if (da < 0 || (da == 0 && db < 0)) {
+            da = -da;
+            db = -db;
+          }
+          miss.emplace_back(da, db);
+        }
+      }
+    std::vector<int64_t> bmiss;  // atoms whose b_p is not known yet
+    for (int64_t q = 0; q < nS; ++q)
+      if (!bcache.count(set[q])) bmiss.push_back(q);
+    const int64_t nm = (int64_t)miss.size(), nb = (int64_t)bmiss.size();
+    if (nm + nb > 0) {
+      // one table: the offsets (unit amplitude, n = 1), then the new atoms
+      Atom<float>* h = (Atom<float>*)up.get((nm + nb) * sizeof(Atom<float>));
+      for (int64_t m = 0; m < nm; ++m)
+        h[m] = Atom<float>{(double)miss[m].first, (double)miss[m].second, 1.0, 0.f, 0.f};
+      for (int64_t t = 0; t < nb; ++t) {
+        const int64_t q = bmiss[t];
+        h[nm + t] = Atom<float>{(double)ai[q], (double)bi[q], inv_n[q], 0.f, 0.f};
+      }
+      off_atoms.ensure(nm + nb);
+      PC_HIP(hipMemcpyAsync(off_atoms.ptr, h, (nm + nb) * sizeof(Atom<float>),
+                            hipMemcpyHostToDevice, s));
+      up.arm(s);
+      psf_partial.ensure(std::max(adjoint_partial_count(p, nm), adjoint_partial_count(p, nb)));
+      psf_val.ensure(nm + nb);
+      if (nm) {
+        if (!ones.ptr) {
+          ones.ensure(L);
+          k_fill_cpx(p, L, 1.0f, 0.0f, ones.ptr, s);
+        }
+        adjoint_atoms_acc64(p, ones.ptr, nm, off_atoms.ptr, psf_partial.ptr, psf_val.ptr, s);
+      }
+      if (nb)
+        adjoint_atoms_acc64(p, V.ptr, nb, off_atoms.ptr + nm, psf_partial.ptr, psf_val.ptr + nm,
+                            s);
+      double* d = (double*)down.get((nm + nb) * 8);
+      PC_HIP(hipMemcpyAsync(d, psf_val.ptr, (nm + nb) * 8, hipMemcpyDeviceToHost, s));
+      PC_HIP(hipStreamSynchronize(s));
+      for (int64_t m = 0; m < nm; ++m) psf[offset_key(miss[m].first, miss[m].second)] = d[m];
+      for (int64_t t = 0; t < nb; ++t) bcache[set[bmiss[t]]] = d[nm + t];
+    }
+    // G (row-major) and b in one upload; the host keeps G for the next set
+    std::vector<double> Gn((size_t)nS * nS);
+    const int64_t no = (int64_t)g_set.size();
+    for (int64_t a = 0; a < nS; ++a)
+      for (int64_t c = a; c < nS; ++c) {
+        const double v =
+            (old[a] >= 0 && old[c] >= 0)
+                ? g_host[(size_t)old[a] * no + old[c]]
+                : psf.at(offset_key(ai[a] - ai[c], bi[a] - bi[c])) * inv_n[a] * inv_n[c];
+        Gn[(size_t)a * nS + c] = v;
+        Gn[(size_t)c * nS + a] = v;
+      }
+    g_set = set;
+    g_host.swap(Gn);
+    double* G = (double*)up.get((nS * nS + nS) * 8);
+    std::memcpy(G, g_host.data(), (size_t)nS * nS * 8);
+    for (int64_t a = 0; a < nS; ++a) G[nS * nS + a] = bcache.at(set[a]);
+    gram_G.ensure(nS * nS);
+    gram_b.ensure(nS);
+    PC_HIP(hipMemcpyAsync(gram_G.ptr, G, nS * nS * 8, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(gram_b.ptr, G + nS * nS, nS * 8, hipMemcpyHostToDevice, s));
+    up.arm(s);
+  }
+
   // Upper estimate of the largest eigenvalue of G_S = Re(Phi_S^H Phi_S) by
   // Lanczos iteration on the operator pair, with full reorthogonalisation
   // (FP64, on the host; the vectors have nS entries), started from the
@@ -338,7 +482,7 @@ struct Pfw {
   // basis) bracket an eigenvalue: |lambda - theta| <= rho.  Stops when
   // rho <= kLanczosTol theta (or at kLanczosMax steps, or on an invariant
   // subspace) and returns theta + rho.
-  double top_eigen_bound(const std::vector<int32_t>& set, bool gridded) {
+  double top_eigen_bound(const std::vector<int32_t>& set, bool gridded, bool gram) {
     const int64_t nS = (int64_t)set.size();
     std::vector<double> v0(nS, 1.0 / std::sqrt((double)nS));
     for (size_t a = 0, b = 0; a < pv_set.size() && b < set.size();) {
@@ -356,56 +500,80 @@ struct Pfw {
     for (double q : v0) nrm += q * q;
     nrm = std::sqrt(nrm);
     for (double& q : v0) q /= nrm;
-    std::vector<std::vector<double>> Q;
-    Q.push_back(v0);
-    std::vector<double> alpha, beta, w(nS), svec;
+    // The recurrence runs on the device (k_lanczos_step); the host reads
+    // alpha, beta (and the basis) once per batch of steps and applies the
+    // stopping rule to each step of the batch in order, so the result is that
+    // of stopping at the first step that meets it.
+    const int jmax = (int)std::min<int64_t>(kLanczosMax, nS);  // T is at most nS x nS
+    lz_Q.ensure((int64_t)(kLanczosMax + 1) * nS);
+    lz_w.ensure(nS);
+    lz_ab.ensure(2 * kLanczosMax);
+    {
+      double* h = (double*)up.get(nS * 8);
+      std::memcpy(h, v0.data(), nS * 8);
+      PC_HIP(hipMemcpyAsync(lz_Q.ptr, h, nS * 8, hipMemcpyHostToDevice, s));
+      up.arm(s);
+    }
+    std::vector<double> svec, Qh;
     double theta = 0, rho = 0;
-    for (int j = 0; j < kLanczosMax; ++j) {
-      PC_HIP(hipMemcpyAsync(v.ptr, Q[j].data(), nS * 8, hipMemcpyHostToDevice, s));
-      if (!gridded) k_weights(p, nS, v.ptr, atoms.ptr, s);
-      if (!gridded && fused_supported(nS)) {  // g = Phi_S* Phi_S v in one pass
-        forward_adjoint_atoms(p, nS, atoms.ptr, nullptr, nullptr, adj_partial.ptr, s);
-        reduce_partials<float>(p, nS, fused_partial_stride(p, nS), adj_partial.ptr, atoms.ptr,
-                               g.ptr, s);
-      } else {
-        op_forward(gridded, nS, v.ptr, false, r.ptr);
-        op_adjoint(gridded, nS, r.ptr, g.ptr);
-      }
-      PC_HIP(hipMemcpyAsync(w.data(), g.ptr, nS * 8, hipMemcpyDeviceToHost, s));
-      PC_HIP(hipStreamSynchronize(s));
-      double a = 0;
-      for (int64_t i = 0; i < nS; ++i) a += Q[j][i] * w[i];
-      alpha.push_back(a);
-      for (int64_t i = 0; i < nS; ++i) w[i] -= a * Q[j][i] + (j > 0 ? beta[j - 1] * Q[j - 1][i] : 0.0);
-      for (int pass = 0; pass < 2; ++pass)  // full reorthogonalisation, twice
-        for (int q = 0; q <= j; ++q) {
-          double d = 0;
-          for (int64_t i = 0; i < nS; ++i) d += Q[q][i] * w[i];
-          for (int64_t i = 0; i < nS; ++i) w[i] -= d * Q[q][i];
+    int done_steps = 0, kfin = 0;
+    while (kfin == 0) {
+      const int jend = std::min(jmax, done_steps + kLanczosBatch);
+      if (gram)  // the batch's steps in one launch
+        k_gram_lanczos(p, nS, done_steps, jend, kLanczosMax, gram_G.ptr, lz_Q.ptr, lz_w.ptr,
+                       lz_ab.ptr, s);
+      for (int j = gram ? jend : done_steps; j < jend; ++j) {
+        double* qj = lz_Q.ptr + (int64_t)j * nS;
+        if (!gridded) k_weights(p, nS, qj, atoms.ptr, s);
+        if (!gridded && fused_supported(nS)) {  // g = Phi_S* Phi_S q_j in one pass
+          forward_adjoint_atoms(p, nS, atoms.ptr, nullptr, nullptr, adj_partial.ptr, s);
+          reduce_partials<float>(p, nS, fused_partial_stride(p, nS), adj_partial.ptr, atoms.ptr,
+                                 g.ptr, s);
+        } else {
+          op_forward(gridded, nS, qj, false, r.ptr);
+          op_adjoint(gridded, nS, r.ptr, g.ptr);
         }
-      double bj = 0;
-      for (double q : w) bj += q * q;
-      bj = std::sqrt(bj);
-      const int k = j + 1;
-      std::vector<double> T((size_t)k * k, 0.0);
-      for (int i = 0; i < k; ++i) {
-        T[(size_t)i * k + i] = alpha[i];
-        if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[i];
+        k_lanczos_step(p, nS, j, kLanczosMax, lz_Q.ptr, g.ptr, lz_w.ptr, lz_ab.ptr, s);
       }
-      theta = sym_top_eigen(T, k, svec);
-      rho = bj * std::fabs(svec[k - 1]);
-      const bool invariant = bj <= 1e-14 * std::max(theta, 1e-300) || k >= nS;
-      if (invariant || rho <= kLanczosTol * theta || j + 1 == kLanczosMax) break;
-      beta.push_back(bj);
-      for (double& q : w) q /= bj;
-      Q.push_back(w);
+      const size_t qbytes = (size_t)(jend + 1) * nS * 8;
+      const bool basis_now = qbytes <= (512u << 10);  // small: read with the coefficients
+      unsigned char* h = (unsigned char*)down.get(16 * kLanczosMax + (basis_now ? qbytes : 0));
+      PC_HIP(hipMemcpyAsync(h, lz_ab.ptr, 16 * kLanczosMax, hipMemcpyDeviceToHost, s));
+      if (basis_now)
+        PC_HIP(hipMemcpyAsync(h + 16 * kLanczosMax, lz_Q.ptr, qbytes, hipMemcpyDeviceToHost, s));
+      PC_HIP(hipStreamSynchronize(s));
+      const double* alpha = (const double*)h;
+      const double* beta = alpha + kLanczosMax;
+      for (int j = done_steps; j < jend && kfin == 0; ++j) {
+        const int k = j + 1;
+        std::vector<double> T((size_t)k * k, 0.0);
+        for (int i = 0; i < k; ++i) {
+          T[(size_t)i * k + i] = alpha[i];
+          if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = beta[i];
+        }
+        theta = sym_top_eigen(T, k, svec);
+        const double bj = beta[j];
+        rho = bj * std::fabs(svec[k - 1]);
+        const bool invariant = bj <= 1e-14 * std::max(theta, 1e-300) || k >= nS;
+        if (invariant || rho <= kLanczosTol * theta || k == kLanczosMax) kfin = k;
+      }
+      if (kfin) {
+        Qh.resize((size_t)kfin * nS);
+        if (basis_now) {
+          std::memcpy(Qh.data(), h + 16 * kLanczosMax, (size_t)kfin * nS * 8);
+        } else {
+          PC_HIP(hipMemcpyAsync(Qh.data(), lz_Q.ptr, (size_t)kfin * nS * 8,
+                                hipMemcpyDeviceToHost, s));
+          PC_HIP(hipStreamSynchronize(s));
+        }
+      }
+      done_steps = jend;
     }
     // top Ritz vector as the next warm start
-    const int k = (int)svec.size();
     pv_set = set;
     pv_val.assign(nS, 0.0);
-    for (int q = 0; q < k; ++q)
-      for (int64_t i = 0; i < nS; ++i) pv_val[i] += svec[q] * Q[q][i];
+    for (int q = 0; q < kfin; ++q)
+      for (int64_t i = 0; i < nS; ++i) pv_val[i] += svec[q] * Qh[(size_t)q * nS + i];
     return theta + rho;
   }
 
@@ -455,47 +623,57 @@ struct Pfw {
     // 2. APGD on the restricted problem
     int inner = 0;
     const bool gridded = nS >= grid_thr;
+    // small direct sets: the Gram form (one small kernel per step)
+    const bool gram = !gridded && nS > 0 && nS <= gram_cap();
+    if (gram) build_gram(Sn);
     if (nS > 0) {
-      const double lip = top_eigen_bound(Sn, gridded) * kLipMargin;
+      const double lip = top_eigen_bound(Sn, gridded, gram) * kLipMargin;
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
       const double tol = std::max(prm.inner_tol_min, prm.inner_tol0 * rel_gap);
-      stat.ensure(2 * nS);
-      // small direct sets: forward and restricted adjoint share one pass
-      const bool fused = !gridded && fused_supported(nS);
-      const int64_t nwg = fused ? fused_partial_stride(p, nS) : adjoint_partial_stride(p, nS);
       double t = 1.0;  // FISTA momentum sequence, on the host in FP64
-      for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
-        const bool check = (inner - 1) % kCheck == 0;
-        if (fused)  // r_y is needed only by the convergence test
-          forward_adjoint_atoms(p, nS, atoms.ptr, V.ptr, check ? r.ptr : nullptr, adj_partial.ptr,
-                                s);
-        else
-          op_forward(gridded, nS, y.ptr, true, r.ptr);
-        if (check) {
-          red_partial.ensure(2 * k_resid_blocks(L));
-          k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
+      if (gram) {
+        for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
+          const bool check = (inner - 1) % kCheck == 0;
+          const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+          const double mom = (t - 1.0) / tn;
+          t = tn;
+          k_gram_fista(p, nS, gram_G.ptr, gram_b.ptr, x.ptr, y.ptr, g.ptr,
+                       check ? scal.ptr + kScalResid : nullptr, v2, 1.0 / lip, lam / lip, mom, s);
+          if (check && gap_test_passes(tol)) break;
         }
-        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-        const double mom = (t - 1.0) / tn;
-        t = tn;
-        if (!gridded) {  // partial sums of Phi_S* r, summed by the fused step
-          if (!fused)
-            adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, nullptr, s);
-          reduce_fista(p, nS, nwg, adj_partial.ptr, nullptr, atoms.ptr, x.ptr, y.ptr, g.ptr,
-                       stat.ptr, 1.0 / lip, lam / lip, mom, s);
-        } else {
-          op_adjoint(true, nS, r.ptr, g.ptr);
-          reduce_fista(p, nS, 0, nullptr, g.ptr, atoms.ptr, x.ptr, y.ptr, g.ptr, stat.ptr,
-                       1.0 / lip, lam / lip, mom, s);
-        }
-        if (check) {
-          k_stat_reduce(p, nS, stat.ptr, scal.ptr, s);
-          double h[4];  // ||r_y||^2, Re<V, r_y>, ||y||_1, max |g|
-          read_scal(h, kScalResid, 4);
-          const double py = 0.5 * h[0] + lam * h[2];
-          const double sc = h[3] <= lam ? 1.0 : lam / h[3];
-          const double gy = py - (sc * h[1] - 0.5 * sc * sc * h[0]);
-          if (gy <= tol * py) break;
+      } else {
+        stat.ensure(2 * nS);
+        // small direct sets: forward and restricted adjoint share one pass
+        const bool fused = !gridded && fused_supported(nS);
+        const int64_t nwg = fused ? fused_partial_stride(p, nS) : adjoint_partial_stride(p, nS);
+        for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
+          const bool check = (inner - 1) % kCheck == 0;
+          if (fused)  // r_y is needed only by the convergence test
+            forward_adjoint_atoms(p, nS, atoms.ptr, V.ptr, check ? r.ptr : nullptr,
+                                  adj_partial.ptr, s);
+          else
+            op_forward(gridded, nS, y.ptr, true, r.ptr);
+          if (check) {
+            red_partial.ensure(2 * k_resid_blocks(L));
+            k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
+          }
+          const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+          const double mom = (t - 1.0) / tn;
+          t = tn;
+          if (!gridded) {  // partial sums of Phi_S* r, summed by the fused step
+            if (!fused)
+              adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, nullptr, s);
+            reduce_fista(p, nS, nwg, adj_partial.ptr, nullptr, atoms.ptr, x.ptr, y.ptr, g.ptr,
+                         stat.ptr, 1.0 / lip, lam / lip, mom, s);
+          } else {
+            op_adjoint(true, nS, r.ptr, g.ptr);
+            reduce_fista(p, nS, 0, nullptr, g.ptr, atoms.ptr, x.ptr, y.ptr, g.ptr, stat.ptr,
+                         1.0 / lip, lam / lip, mom, s);
+          }
+          if (check) {
+            k_stat_reduce(p, nS, stat.ptr, scal.ptr, s);
+            if (gap_test_passes(tol)) break;
+          }
         }
       }
       inner = std::min(inner, prm.inner_max_iter);

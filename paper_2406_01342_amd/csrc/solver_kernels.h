@@ -19,7 +19,19 @@ void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial,
 void k_select(pc_plan* p, int64_t N, const float* eta, float tau, unsigned* count, int32_t* out, int64_t cap,
               hipStream_t s);
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s);
+// One Lanczos step (see lanczos_step_kernel): g = G q_j given; writes alpha_j,
+// beta_j into ab and q_{j+1} into row j + 1 of Q.
+void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const double* g, double* w,
+                    double* ab, hipStream_t s);
 void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipStream_t s);
+// Gram form of the restricted problem (see gram_fista_kernel): one APGD step,
+// optionally with the duality-gap statistics, and Lanczos steps j0..j1-1.
+void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
+                  double* g, double* stats, double v2, double inv_lip, double thr, double mom,
+                  hipStream_t s);
+void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const double* G, double* Q,
+                    double* w, double* ab, hipStream_t s);
+void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s);
 // Gridded-operator helpers for large active sets.
 void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, float* img,
                hipStream_t s);

@@ -33,13 +33,19 @@ def _fit(p, pix, w):
     return operator.forward(p.uv, p.npix, p.fov_rad, pix, w)
 
 
-def test_solve_c1_converged_matches_oracle():
+# APGD and Lanczos in Gram form (default for direct sets up to 256 atoms),
+# through the operators (gram_atoms < 0), and both within one solve (cap 8)
+GRAM_MODES = [0, -1, 8]
+
+
+@pytest.mark.parametrize("gram", GRAM_MODES)
+def test_solve_c1_converged_matches_oracle(gram):
     """C1 run to a relative gap of 1e-5 on both sides (the FP32 residual floors the
     GPU gap near 5e-6): objective, fit, certificate."""
-    say("solve c1 converged")
+    say("solve c1 converged, gram_atoms", gram)
     p, vis = problem("c1")
     kw = dict(alpha=p.alpha, delta=p.delta, max_iter=300, rel_gap_tol=1e-5)
-    plan, res, cert = _gpu_solve(p, vis, **kw)
+    plan, res, cert = _gpu_solve(p, vis, gram_atoms=gram, **kw)
     ref = _oracle_solve(p, vis, **kw)
     say("gpu", res["objective"], res["rel_gap"], res["iters"], res["natoms"],
         "oracle", ref.objective, ref.rel_gap, ref.iters, ref.pix.size)
@@ -70,11 +76,12 @@ def test_solve_c1_fifty_iterations():
     assert mu[res["cert_argmax"]] >= 1 - 1e-3
 
 
-def test_solve_c2_small_gap_stop():
-    say("solve c2_small")
+@pytest.mark.parametrize("gram", GRAM_MODES)
+def test_solve_c2_small_gap_stop(gram):
+    say("solve c2_small, gram_atoms", gram)
     p, vis = problem("c2_small")
     kw = dict(alpha=p.alpha, delta=p.delta, max_iter=200, rel_gap_tol=1e-4)
-    plan, res, cert = _gpu_solve(p, vis, **kw)
+    plan, res, cert = _gpu_solve(p, vis, gram_atoms=gram, **kw)
     ref = _oracle_solve(p, vis, **kw)
     say("gpu", res["objective"], res["rel_gap"], res["iters"], res["natoms"],
         "oracle", ref.objective, ref.rel_gap, ref.iters, ref.pix.size)
