@@ -85,6 +85,11 @@ __global__ void select_kernel(int64_t N, const float* __restrict__ eta, float ta
 
 __global__ void zero_u32_kernel(unsigned int* p) { *p = 0u; }
 
+__global__ void zero_n_u32_kernel(int64_t n, unsigned int* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_max(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -170,14 +175,24 @@ __device__ __forceinline__ double gram_col_dot(const double* __restrict__ G,
 // y+ = x+ + mom (x+ - x).  With stats != NULL the duality-gap inputs at y are
 // stored too: ||V - Phi_S y||^2 = v2 - 2 y.b + y.G y, Re<V, V - Phi_S y> =
 // v2 - y.b, ||y||_1 and max |g| (v2 = ||V||^2).
+//
+// done[0] != 0 makes the step a no-op (an earlier step passed the test).  When
+// `check` is set, the restricted duality gap at y is tested in the kernel:
+// with P = ||r_y||^2 / 2 + lambda ||y||_1 and the dual point scaled into the
+// feasible set, the step passes when P - D <= tol P; it is still applied, and
+// done = {1, iter} is recorded, so that the host can enqueue several steps and
+// read the outcome once.
 __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const double* __restrict__ G,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ x,
                                                          double* __restrict__ y,
                                                          double* __restrict__ g_out,
                                                          double* __restrict__ stats, double v2,
-                                                         double inv_lip, double thr, double mom) {
+                                                         double inv_lip, double thr, double mom,
+                                                         int check, int iter, double lam,
+                                                         double tol, int* __restrict__ done) {
   __shared__ double sh[4];
+  if (done[0]) return;  // uniform: every thread reads the same flag
   double yGy = 0, yb = 0, yl1 = 0, gmax = 0;
   for (int64_t q = threadIdx.x; q < nS; q += 256) {
     const double s = gram_col_dot(G, y, nS, q);  // (G y)_q
@@ -188,19 +203,25 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
     yl1 += fabs(y[q]);
     gmax = fmax(gmax, fabs(gq));
   }
-  if (stats) {
+  bool passed = false;
+  if (check) {
     yGy = block_sum<256>(yGy, sh);
     yb = block_sum<256>(yb, sh);
     yl1 = block_sum<256>(yl1, sh);
     gmax = block_max<256>(gmax, sh);
+    const double r2 = v2 - 2.0 * yb + yGy, vr = v2 - yb;
+    const double py = 0.5 * r2 + lam * yl1;
+    const double sc = gmax <= lam ? 1.0 : lam / gmax;
+    const double gy = py - (sc * vr - 0.5 * sc * sc * r2);
+    passed = gy <= tol * py;
     if (threadIdx.x == 0) {
-      stats[0] = v2 - 2.0 * yb + yGy;
-      stats[1] = v2 - yb;
+      stats[0] = r2;
+      stats[1] = vr;
       stats[2] = yl1;
       stats[3] = gmax;
     }
   }
-  __syncthreads();  // every thread has read all of y
+  __syncthreads();  // every thread has read all of y (and done[0])
   for (int64_t q = threadIdx.x; q < nS; q += 256) {
     const double yo = y[q], xo = x[q];
     const double z = yo + g_out[q] * inv_lip;
@@ -208,6 +229,10 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
     const double xn = az > 0 ? copysign(az, z) : 0.0;
     x[q] = xn;
     y[q] = xn + mom * (xn - xo);
+  }
+  if (passed && threadIdx.x == 0) {
+    done[1] = iter;
+    done[0] = 1;
   }
 }
 
@@ -356,10 +381,10 @@ void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const do
 
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
                   double* g, double* stats, double v2, double inv_lip, double thr, double mom,
-                  hipStream_t s) {
+                  bool check, int iter, double lam, double tol, int* done, hipStream_t s) {
   ProfScope ps(p, s, "gram_fista", 8.0 * nS * (nS + 6), (double)nS * nS);
   hipLaunchKernelGGL(gram_fista_kernel, dim3(1), dim3(256), 0, s, nS, G, b, x, y, g, stats, v2,
-                     inv_lip, thr, mom);
+                     inv_lip, thr, mom, check ? 1 : 0, iter, lam, tol, done);
   PC_LAUNCH_CHECK("gram_fista");
 }
 
@@ -369,6 +394,12 @@ void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const doub
   hipLaunchKernelGGL(gram_lanczos_kernel, dim3(1), dim3(256), 0, s, nS, j0, j1, kmax, G, Q, w,
                      ab);
   PC_LAUNCH_CHECK("gram_lanczos");
+}
+
+void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zero_n_u32_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, n, out);
+  PC_LAUNCH_CHECK("zero_u32");
 }
 
 void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s) {

@@ -88,6 +88,7 @@ struct Pinned {
 constexpr int kLanczosMax = 12;       // Lanczos steps per active set (cap)
 constexpr int kLanczosBatch = 4;      // device steps between host readbacks
 constexpr int kGramAtoms = 256;       // default cap of the Gram form (direct sets)
+constexpr int kGramChunk = 8;         // Gram-form APGD steps enqueued per readback (first)
 constexpr double kLanczosTol = 1e-3;  // residual bound relative to the estimate
 constexpr double kLipMargin = 1.01;
 
@@ -160,6 +161,7 @@ struct Pfw {
   std::vector<int32_t> g_set;                  // the set of the last G, and G
   std::vector<double> g_host;
   DevArray<double> gram_G, gram_b, psf_val, psf_partial;
+  DevArray<int> gram_done;  // {passed, step} of the device-side gap test
   DevArray<Atom<float>> off_atoms;
   DevArray<c32> ones;
   double v2 = 0;  // ||V||^2
@@ -632,15 +634,35 @@ struct Pfw {
       const double tol = std::max(prm.inner_tol_min, prm.inner_tol0 * rel_gap);
       double t = 1.0;  // FISTA momentum sequence, on the host in FP64
       if (gram) {
-        for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
-          const bool check = (inner - 1) % kCheck == 0;
-          const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-          const double mom = (t - 1.0) / tn;
-          t = tn;
-          k_gram_fista(p, nS, gram_G.ptr, gram_b.ptr, x.ptr, y.ptr, g.ptr,
-                       check ? scal.ptr + kScalResid : nullptr, v2, 1.0 / lip, lam / lip, mom, s);
-          if (check && gap_test_passes(tol)) break;
+        // steps are enqueued in chunks; the kernel applies the gap test and
+        // turns the remaining steps into no-ops, and the host reads the
+        // outcome (and x) once per chunk
+        gram_done.ensure(2);
+        k_zero_u32(p, 2, (unsigned*)gram_done.ptr, s);
+        int issued = 0, stop = 0;
+        unsigned char* h = nullptr;
+        while (stop == 0 && issued < prm.inner_max_iter) {
+          const int chunk = std::min(issued == 0 ? kGramChunk : 2 * kGramChunk,
+                                     prm.inner_max_iter - issued);
+          for (int c = 0; c < chunk; ++c) {
+            const int it = ++issued;
+            const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+            const double mom = (t - 1.0) / tn;
+            t = tn;
+            k_gram_fista(p, nS, gram_G.ptr, gram_b.ptr, x.ptr, y.ptr, g.ptr, scal.ptr + kScalResid,
+                         v2, 1.0 / lip, lam / lip, mom, (it - 1) % kCheck == 0, it, lam, tol,
+                         gram_done.ptr, s);
+          }
+          h = (unsigned char*)down.get(8 + nS * 8);
+          PC_HIP(hipMemcpyAsync(h, gram_done.ptr, 8, hipMemcpyDeviceToHost, s));
+          PC_HIP(hipMemcpyAsync(h + 8, x.ptr, nS * 8, hipMemcpyDeviceToHost, s));
+          PC_HIP(hipStreamSynchronize(s));
+          const int* dn = (const int*)h;
+          if (dn[0]) stop = dn[1];
         }
+        inner = stop ? stop : prm.inner_max_iter;
+        xw.resize(nS);
+        std::memcpy(xw.data(), h + 8, nS * 8);
       } else {
         stat.ensure(2 * nS);
         // small direct sets: forward and restricted adjoint share one pass
@@ -676,10 +698,14 @@ struct Pfw {
           }
         }
       }
-      inner = std::min(inner, prm.inner_max_iter);
-      xw.resize(nS);
-      PC_HIP(hipMemcpyAsync(xw.data(), x.ptr, nS * 8, hipMemcpyDeviceToHost, s));
-      PC_HIP(hipStreamSynchronize(s));
+      if (!gram) {
+        inner = std::min(inner, prm.inner_max_iter);
+        xw.resize(nS);
+        double* hx = (double*)down.get(nS * 8);
+        PC_HIP(hipMemcpyAsync(hx, x.ptr, nS * 8, hipMemcpyDeviceToHost, s));
+        PC_HIP(hipStreamSynchronize(s));
+        std::memcpy(xw.data(), hx, nS * 8);
+      }
     }
     inner_total += inner;
     // 3. prune

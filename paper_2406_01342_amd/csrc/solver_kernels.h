@@ -28,7 +28,8 @@ void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipSt
 // optionally with the duality-gap statistics, and Lanczos steps j0..j1-1.
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
                   double* g, double* stats, double v2, double inv_lip, double thr, double mom,
-                  hipStream_t s);
+                  bool check, int iter, double lam, double tol, int* done, hipStream_t s);
+void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s);
 void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const double* G, double* Q,
                     double* w, double* ab, hipStream_t s);
 void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s);
