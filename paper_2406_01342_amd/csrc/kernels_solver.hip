@@ -284,6 +284,31 @@ __global__ void fill_cpx_kernel(int64_t n, float re, float im, c32* __restrict__
   if (i < n) out[i] = {re, im};
 }
 
+// An active set from one uploaded block [x: nS doubles][pix: nS int32]:
+// x = y = the weights, pix, and the atom table (pixel offsets, 1/n, forward
+// weight x/n; zero-weight phase-centre padding up to ntotal entries).
+__global__ void activate_kernel(int64_t nS, int64_t ntotal, int n, double dl,
+                                const unsigned char* __restrict__ blk, double* __restrict__ x,
+                                double* __restrict__ y, int32_t* __restrict__ pix,
+                                Atom<float>* __restrict__ atoms) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ntotal) return;
+  if (p >= nS) {
+    atoms[p] = Atom<float>{0.0, 0.0, 1.0, 0.f, 0.f};
+    return;
+  }
+  const double xv = reinterpret_cast<const double*>(blk)[p];
+  const int q = reinterpret_cast<const int32_t*>(blk + 8 * nS)[p];
+  x[p] = xv;
+  y[p] = xv;
+  pix[p] = q;
+  const int i = q / n, j = q - i * n;
+  const double a = (double)(i - n / 2), b = (double)(j - n / 2);
+  const double l = a * dl, m = b * dl;
+  const double inv_n = 1.0 / sqrt(1.0 - l * l - m * m);
+  atoms[p] = Atom<float>{a, b, inv_n, (float)(xv * inv_n), 0.f};
+}
+
 // Forward weights from an FP64 vector: atoms[p].w = x[p] / n_p.
 __global__ void weights_kernel(int64_t nS, const double* __restrict__ x,
                                Atom<float>* __restrict__ atoms) {
@@ -394,6 +419,14 @@ void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const doub
   hipLaunchKernelGGL(gram_lanczos_kernel, dim3(1), dim3(256), 0, s, nS, j0, j1, kmax, G, Q, w,
                      ab);
   PC_LAUNCH_CHECK("gram_lanczos");
+}
+
+void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,
+                Atom<float>* atoms, hipStream_t s) {
+  const int64_t ntotal = atom_capacity(nS);
+  hipLaunchKernelGGL(activate_kernel, dim3(blocks(ntotal, 256)), dim3(256), 0, s, nS, ntotal,
+                     p->g.n, p->g.dl, (const unsigned char*)blk, x, y, pix, atoms);
+  PC_LAUNCH_CHECK("activate");
 }
 
 void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s) {

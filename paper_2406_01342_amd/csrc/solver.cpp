@@ -160,8 +160,10 @@ struct Pfw {
   std::unordered_map<int32_t, double> bcache;  // b_p by pixel
   std::vector<int32_t> g_set;                  // the set of the last G, and G
   std::vector<double> g_host;
-  DevArray<double> gram_G, gram_b, psf_val, psf_partial;
+  DevArray<double> gram_blk, psf_val, psf_partial;
+  double *gram_G = nullptr, *gram_b = nullptr, *gram_Q = nullptr;  // inside gram_blk
   DevArray<int> gram_done;  // {passed, step} of the device-side gap test
+  DevArray<double> act_blk;  // uploaded [x | pix] of the active set
   DevArray<Atom<float>> off_atoms;
   DevArray<c32> ones;
   double v2 = 0;  // ||V||^2
@@ -275,15 +277,14 @@ struct Pfw {
     g.ensure(nS);
     adj_partial.ensure(adjoint_partial_count(p, nS));
     if (nS == 0) return;
+    // one upload and one kernel: x = y = weights, pix, atom table
+    act_blk.ensure((nS * 12 + 7) / 8);
     unsigned char* h = (unsigned char*)up.get(nS * 12);
     std::memcpy(h, xs_host.data(), nS * 8);
     std::memcpy(h + nS * 8, set.data(), nS * 4);
-    PC_HIP(hipMemcpyAsync(x.ptr, h, nS * 8, hipMemcpyHostToDevice, s));
-    PC_HIP(hipMemcpyAsync(y.ptr, h, nS * 8, hipMemcpyHostToDevice, s));
-    PC_HIP(hipMemcpyAsync(pix.ptr, h + nS * 8, nS * 4, hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(act_blk.ptr, h, nS * 12, hipMemcpyHostToDevice, s));
     up.arm(s);
-    prep_atoms_into<float>(p, nS, pix.ptr, (const float*)nullptr, atoms.ptr, s);
-    k_weights(p, nS, x.ptr, atoms.ptr, s);
+    k_activate(p, nS, act_blk.ptr, x.ptr, y.ptr, pix.ptr, atoms.ptr, s);
   }
 
   // Crossover between the direct sums (cost ~ L nS) and the gridded
@@ -465,26 +466,24 @@ struct Pfw {
       }
     g_set = set;
     g_host.swap(Gn);
-    double* G = (double*)up.get((nS * nS + nS) * 8);
+    // one device block [G | b | Lanczos basis rows], G, b and the start
+    // vector uploaded together
+    const std::vector<double> v0 = lanczos_start(set);
+    gram_blk.ensure(nS * nS + nS + (int64_t)(kLanczosMax + 1) * nS);
+    gram_G = gram_blk.ptr;
+    gram_b = gram_G + nS * nS;
+    gram_Q = gram_b + nS;
+    double* G = (double*)up.get((nS * nS + 2 * nS) * 8);
     std::memcpy(G, g_host.data(), (size_t)nS * nS * 8);
     for (int64_t a = 0; a < nS; ++a) G[nS * nS + a] = bcache.at(set[a]);
-    gram_G.ensure(nS * nS);
-    gram_b.ensure(nS);
-    PC_HIP(hipMemcpyAsync(gram_G.ptr, G, nS * nS * 8, hipMemcpyHostToDevice, s));
-    PC_HIP(hipMemcpyAsync(gram_b.ptr, G + nS * nS, nS * 8, hipMemcpyHostToDevice, s));
+    std::memcpy(G + nS * nS + nS, v0.data(), nS * 8);
+    PC_HIP(hipMemcpyAsync(gram_blk.ptr, G, (nS * nS + 2 * nS) * 8, hipMemcpyHostToDevice, s));
     up.arm(s);
   }
 
-  // Upper estimate of the largest eigenvalue of G_S = Re(Phi_S^H Phi_S) by
-  // Lanczos iteration on the operator pair, with full reorthogonalisation
-  // (FP64, on the host; the vectors have nS entries), started from the
-  // previous active set's top Ritz vector (new atoms enter at 1/sqrt(nS)).
-  // After step j the top Ritz value theta of the tridiagonal T_j and the
-  // residual bound rho = beta_j |s_j| (s the Ritz vector in the Lanczos
-  // basis) bracket an eigenvalue: |lambda - theta| <= rho.  Stops when
-  // rho <= kLanczosTol theta (or at kLanczosMax steps, or on an invariant
-  // subspace) and returns theta + rho.
-  double top_eigen_bound(const std::vector<int32_t>& set, bool gridded, bool gram) {
+  // Lanczos start vector: the previous top Ritz vector on the atoms both sets
+  // share (else uniform), normalised.
+  std::vector<double> lanczos_start(const std::vector<int32_t>& set) const {
     const int64_t nS = (int64_t)set.size();
     std::vector<double> v0(nS, 1.0 / std::sqrt((double)nS));
     for (size_t a = 0, b = 0; a < pv_set.size() && b < set.size();) {
@@ -502,18 +501,35 @@ struct Pfw {
     for (double q : v0) nrm += q * q;
     nrm = std::sqrt(nrm);
     for (double& q : v0) q /= nrm;
+    return v0;
+  }
+
+  // Upper estimate of the largest eigenvalue of G_S = Re(Phi_S^H Phi_S) by
+  // Lanczos iteration with full reorthogonalisation (FP64 on the device; G_S
+  // applied as the operator pair, or as the matrix in the Gram form), started
+  // from the previous active set's top Ritz vector (lanczos_start).
+  // After step j the top Ritz value theta of the tridiagonal T_j and the
+  // residual bound rho = beta_j |s_j| (s the Ritz vector in the Lanczos
+  // basis) bracket an eigenvalue: |lambda - theta| <= rho.  Stops when
+  // rho <= kLanczosTol theta (or at kLanczosMax steps, or on an invariant
+  // subspace) and returns theta + rho.
+  double top_eigen_bound(const std::vector<int32_t>& set, bool gridded, bool gram) {
+    const int64_t nS = (int64_t)set.size();
     // The recurrence runs on the device (k_lanczos_step); the host reads
     // alpha, beta (and the basis) once per batch of steps and applies the
     // stopping rule to each step of the batch in order, so the result is that
     // of stopping at the first step that meets it.
     const int jmax = (int)std::min<int64_t>(kLanczosMax, nS);  // T is at most nS x nS
-    lz_Q.ensure((int64_t)(kLanczosMax + 1) * nS);
     lz_w.ensure(nS);
     lz_ab.ensure(2 * kLanczosMax);
-    {
+    double* Qd = gram_Q;  // the Gram form uploaded the start vector with G
+    if (!gram) {
+      lz_Q.ensure((int64_t)(kLanczosMax + 1) * nS);
+      Qd = lz_Q.ptr;
+      const std::vector<double> v0 = lanczos_start(set);
       double* h = (double*)up.get(nS * 8);
       std::memcpy(h, v0.data(), nS * 8);
-      PC_HIP(hipMemcpyAsync(lz_Q.ptr, h, nS * 8, hipMemcpyHostToDevice, s));
+      PC_HIP(hipMemcpyAsync(Qd, h, nS * 8, hipMemcpyHostToDevice, s));
       up.arm(s);
     }
     std::vector<double> svec, Qh;
@@ -522,10 +538,9 @@ struct Pfw {
     while (kfin == 0) {
       const int jend = std::min(jmax, done_steps + kLanczosBatch);
       if (gram)  // the batch's steps in one launch
-        k_gram_lanczos(p, nS, done_steps, jend, kLanczosMax, gram_G.ptr, lz_Q.ptr, lz_w.ptr,
-                       lz_ab.ptr, s);
+        k_gram_lanczos(p, nS, done_steps, jend, kLanczosMax, gram_G, Qd, lz_w.ptr, lz_ab.ptr, s);
       for (int j = gram ? jend : done_steps; j < jend; ++j) {
-        double* qj = lz_Q.ptr + (int64_t)j * nS;
+        double* qj = Qd + (int64_t)j * nS;
         if (!gridded) k_weights(p, nS, qj, atoms.ptr, s);
         if (!gridded && fused_supported(nS)) {  // g = Phi_S* Phi_S q_j in one pass
           forward_adjoint_atoms(p, nS, atoms.ptr, nullptr, nullptr, adj_partial.ptr, s);
@@ -535,14 +550,14 @@ struct Pfw {
           op_forward(gridded, nS, qj, false, r.ptr);
           op_adjoint(gridded, nS, r.ptr, g.ptr);
         }
-        k_lanczos_step(p, nS, j, kLanczosMax, lz_Q.ptr, g.ptr, lz_w.ptr, lz_ab.ptr, s);
+        k_lanczos_step(p, nS, j, kLanczosMax, Qd, g.ptr, lz_w.ptr, lz_ab.ptr, s);
       }
       const size_t qbytes = (size_t)(jend + 1) * nS * 8;
       const bool basis_now = qbytes <= (512u << 10);  // small: read with the coefficients
       unsigned char* h = (unsigned char*)down.get(16 * kLanczosMax + (basis_now ? qbytes : 0));
       PC_HIP(hipMemcpyAsync(h, lz_ab.ptr, 16 * kLanczosMax, hipMemcpyDeviceToHost, s));
       if (basis_now)
-        PC_HIP(hipMemcpyAsync(h + 16 * kLanczosMax, lz_Q.ptr, qbytes, hipMemcpyDeviceToHost, s));
+        PC_HIP(hipMemcpyAsync(h + 16 * kLanczosMax, Qd, qbytes, hipMemcpyDeviceToHost, s));
       PC_HIP(hipStreamSynchronize(s));
       const double* alpha = (const double*)h;
       const double* beta = alpha + kLanczosMax;
@@ -564,7 +579,7 @@ struct Pfw {
         if (basis_now) {
           std::memcpy(Qh.data(), h + 16 * kLanczosMax, (size_t)kfin * nS * 8);
         } else {
-          PC_HIP(hipMemcpyAsync(Qh.data(), lz_Q.ptr, (size_t)kfin * nS * 8,
+          PC_HIP(hipMemcpyAsync(Qh.data(), Qd, (size_t)kfin * nS * 8,
                                 hipMemcpyDeviceToHost, s));
           PC_HIP(hipStreamSynchronize(s));
         }
@@ -649,7 +664,7 @@ struct Pfw {
             const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
             const double mom = (t - 1.0) / tn;
             t = tn;
-            k_gram_fista(p, nS, gram_G.ptr, gram_b.ptr, x.ptr, y.ptr, g.ptr, scal.ptr + kScalResid,
+            k_gram_fista(p, nS, gram_G, gram_b, x.ptr, y.ptr, g.ptr, scal.ptr + kScalResid,
                          v2, 1.0 / lip, lam / lip, mom, (it - 1) % kCheck == 0, it, lam, tol,
                          gram_done.ptr, s);
           }

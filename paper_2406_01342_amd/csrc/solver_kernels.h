@@ -30,6 +30,10 @@ void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, doub
                   double* g, double* stats, double v2, double inv_lip, double thr, double mom,
                   bool check, int iter, double lam, double tol, int* done, hipStream_t s);
 void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s);
+// Active set from one device block [x: nS doubles][pix: nS int32]: x, y, pix
+// and the padded atom table (atom_capacity(nS) entries).
+void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,
+                Atom<float>* atoms, hipStream_t s);
 void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const double* G, double* Q,
                     double* w, double* ab, hipStream_t s);
 void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s);
