@@ -214,7 +214,9 @@ def dominant_roofline(stats, plan_info):
                 "work_per_launch": pairs}
     b = top["bytes"] / top["launches"]
     achieved = b / (avg_ms * 1e-3) / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+    # single-workgroup solver steps are bound by latency, not by a unit's peak
+    bound = "latency" if name in ("gram_fista", "gram_lanczos", "lanczos_step") else "hbm"
+    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(name),
             "avg_ms": avg_ms, "launches": top["launches"], "bytes_per_launch": b}
 

@@ -88,7 +88,8 @@ struct Pinned {
 constexpr int kLanczosMax = 12;       // Lanczos steps per active set (cap)
 constexpr int kLanczosBatch = 4;      // device steps between host readbacks
 constexpr int kGramAtoms = 256;       // default cap of the Gram form (direct sets)
-constexpr int kGramChunk = 8;         // Gram-form APGD steps enqueued per readback (first)
+constexpr int kGramChunk = 8;         // Gram-form APGD steps per readback after the first chunk: 2x
+constexpr int kGramNewPairs = 16;     // new sums per atom above which the Gram form is skipped
 constexpr double kLanczosTol = 1e-3;  // residual bound relative to the estimate
 constexpr double kLipMargin = 1.01;
 
@@ -163,6 +164,7 @@ struct Pfw {
   DevArray<double> gram_blk, psf_val, psf_partial;
   double *gram_G = nullptr, *gram_b = nullptr, *gram_Q = nullptr;  // inside gram_blk
   DevArray<int> gram_done;  // {passed, step} of the device-side gap test
+  int last_inner = 1 + kCheck;  // APGD steps of the last Gram-form solve
   DevArray<double> act_blk;  // uploaded [x | pix] of the active set
   DevArray<Atom<float>> off_atoms;
   DevArray<c32> ones;
@@ -378,7 +380,10 @@ struct Pfw {
   // b_p for atoms not seen before from a restricted adjoint of V (both with
   // FP64 totals: the gap test forms ||V - Phi_S y||^2 = ||V||^2 - 2 y.b +
   // y.G y, which cancels); G is assembled on the host and uploaded with b.
-  void build_gram(const std::vector<int32_t>& set) {
+  // Returns false (and changes nothing) when the new point-spread sums would
+  // cost more than kGramNewPairs operator applications on this set: the
+  // operator path is then cheaper for this FW iteration.
+  bool build_gram(const std::vector<int32_t>& set) {
     const int64_t nS = (int64_t)set.size();
     const int n = p->g.n;
     std::vector<int> ai(nS), bi(nS);
@@ -421,6 +426,10 @@ struct Pfw {
     for (int64_t q = 0; q < nS; ++q)
       if (!bcache.count(set[q])) bmiss.push_back(q);
     const int64_t nm = (int64_t)miss.size(), nb = (int64_t)bmiss.size();
+    if (nm + nb > kGramNewPairs * nS) {
+      for (const auto& o : miss) psf.erase(offset_key(o.first, o.second));
+      return false;
+    }
     if (nm + nb > 0) {
       // one table: the offsets (unit amplitude, n = 1), then the new atoms
       Atom<float>* h = (Atom<float>*)up.get((nm + nb) * sizeof(Atom<float>));
@@ -479,6 +488,7 @@ struct Pfw {
     std::memcpy(G + nS * nS + nS, v0.data(), nS * 8);
     PC_HIP(hipMemcpyAsync(gram_blk.ptr, G, (nS * nS + 2 * nS) * 8, hipMemcpyHostToDevice, s));
     up.arm(s);
+    return true;
   }
 
   // Lanczos start vector: the previous top Ritz vector on the atoms both sets
@@ -641,8 +651,7 @@ struct Pfw {
     int inner = 0;
     const bool gridded = nS >= grid_thr;
     // small direct sets: the Gram form (one small kernel per step)
-    const bool gram = !gridded && nS > 0 && nS <= gram_cap();
-    if (gram) build_gram(Sn);
+    const bool gram = !gridded && nS > 0 && nS <= gram_cap() && build_gram(Sn);
     if (nS > 0) {
       const double lip = top_eigen_bound(Sn, gridded, gram) * kLipMargin;
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
@@ -657,7 +666,11 @@ struct Pfw {
         int issued = 0, stop = 0;
         unsigned char* h = nullptr;
         while (stop == 0 && issued < prm.inner_max_iter) {
-          const int chunk = std::min(issued == 0 ? kGramChunk : 2 * kGramChunk,
+          // first chunk: through one test past the previous solve's stopping
+          // step (steps after the passing test are no-ops)
+          const int first = std::max(1, last_inner) + kCheck;
+          const int chunk = std::min(issued == 0 ? std::min(first, 4 * kGramChunk)
+                                                 : 2 * kGramChunk,
                                      prm.inner_max_iter - issued);
           for (int c = 0; c < chunk; ++c) {
             const int it = ++issued;
@@ -676,6 +689,7 @@ struct Pfw {
           if (dn[0]) stop = dn[1];
         }
         inner = stop ? stop : prm.inner_max_iter;
+        last_inner = inner;
         xw.resize(nS);
         std::memcpy(xw.data(), h + 8, nS * 8);
       } else {
