@@ -112,45 +112,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// One Lanczos step on G = Re(Phi_S^H Phi_S), FP64, one workgroup.  Given
-// g = G q_j: alpha_j = q_j . g, w = g - alpha_j q_j - beta_{j-1} q_{j-1},
-// then w is re-orthogonalised twice against q_0..q_j, beta_j = ||w|| and
-// q_{j+1} = w / beta_j (zero when beta_j = 0).  Q holds kmax + 1 rows of nS;
-// ab[j] = alpha_j and ab[kmax + j] = beta_j; w is scratch [nS].  Every thread
-// works on the same indices throughout, so only the reductions synchronise.
-__global__ __launch_bounds__(256) void lanczos_step_kernel(int64_t nS, int j, int kmax,
-                                                           double* __restrict__ Q,
-                                                           const double* __restrict__ g,
-                                                           double* __restrict__ w,
-                                                           double* __restrict__ ab) {
-  __shared__ double sh[4];
-  const double* qj = Q + (int64_t)j * nS;
-  double a = 0;
-  for (int64_t i = threadIdx.x; i < nS; i += 256) a += qj[i] * g[i];
-  a = block_sum<256>(a, sh);
-  const double bp = j > 0 ? ab[kmax + j - 1] : 0.0;
-  const double* qp = j > 0 ? Q + (int64_t)(j - 1) * nS : qj;
-  for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] = g[i] - (a * qj[i] + bp * qp[i]);
-  for (int pass = 0; pass < 2; ++pass)
-    for (int q = 0; q <= j; ++q) {
-      const double* qq = Q + (int64_t)q * nS;
-      double d = 0;
-      for (int64_t i = threadIdx.x; i < nS; i += 256) d += qq[i] * w[i];
-      d = block_sum<256>(d, sh);
-      for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] -= d * qq[i];
-    }
-  double b = 0;
-  for (int64_t i = threadIdx.x; i < nS; i += 256) b += w[i] * w[i];
-  b = sqrt(block_sum<256>(b, sh));
-  if (threadIdx.x == 0) {
-    ab[j] = a;
-    ab[kmax + j] = b;
-  }
-  const double inv = b > 0 ? 1.0 / b : 0.0;
-  double* qn = Q + (int64_t)(j + 1) * nS;
-  for (int64_t i = threadIdx.x; i < nS; i += 256) qn[i] = w[i] * inv;
-}
-
 // (G v)_q for the symmetric G as column q (coalesced across threads), with
 // four independent partial sums so that several loads are in flight.
 __device__ __forceinline__ double gram_col_dot(const double* __restrict__ G,
@@ -236,46 +197,102 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
   }
 }
 
-// Lanczos steps j0..j1-1 on the Gram matrix in one workgroup (the recurrence
-// of lanczos_step_kernel with g = G q_j formed in place).  Q rows 0..j0 are
-// set (row 0: the unit start vector); ab as for lanczos_step_kernel.
+// Sums of cnt <= kLanczosMax + 1 values over the 256 threads of a workgroup
+// (every thread receives the totals); sh holds 4 x (kLanczosMax + 1) doubles.
+constexpr int kLzMaxRows = 13;  // the Lanczos basis has at most 12 + 1 rows
+
+__device__ __forceinline__ void block_sum_multi(double* v, int cnt, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kLzMaxRows; ++q)
+    if (q < cnt) {
+      double t = v[q];
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+      if (lane == 0) sh[wv * kLzMaxRows + q] = t;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kLzMaxRows; ++q)
+    if (q < cnt)
+      v[q] = ((sh[q] + sh[kLzMaxRows + q]) + sh[2 * kLzMaxRows + q]) + sh[3 * kLzMaxRows + q];
+  __syncthreads();
+}
+
+// The part of a Lanczos step after the product: w holds g = G q_j on entry.
+// alpha_j = q_j . g, w = g - alpha_j q_j - beta_{j-1} q_{j-1}, then w is
+// orthogonalised against q_0..q_j by classical Gram-Schmidt applied twice
+// (all projections of a pass reduced together), beta_j = ||w||,
+// q_{j+1} = w / beta_j (zero when beta_j = 0); ab[j] = alpha_j,
+// ab[kmax + j] = beta_j.  Every thread works on the same indices throughout.
+__device__ void lanczos_finish_step(int64_t nS, int j, int kmax, double* __restrict__ Q,
+                                    double* __restrict__ w, double* __restrict__ ab,
+                                    double* sh) {
+  const double* qj = Q + (int64_t)j * nS;
+  double v[kLzMaxRows];
+  v[0] = 0;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) v[0] += qj[i] * w[i];
+  block_sum_multi(v, 1, sh);
+  const double a = v[0];
+  const double bp = j > 0 ? ab[kmax + j - 1] : 0.0;
+  const double* qp = j > 0 ? Q + (int64_t)(j - 1) * nS : qj;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] -= a * qj[i] + bp * qp[i];
+  for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+    for (int q = 0; q < kLzMaxRows; ++q) v[q] = 0;
+    for (int64_t i = threadIdx.x; i < nS; i += 256) {
+      const double wi = w[i];
+#pragma unroll
+      for (int q = 0; q < kLzMaxRows; ++q)
+        if (q <= j) v[q] += Q[(int64_t)q * nS + i] * wi;
+    }
+    block_sum_multi(v, j + 1, sh);
+    for (int64_t i = threadIdx.x; i < nS; i += 256) {
+      double wi = w[i];
+#pragma unroll
+      for (int q = 0; q < kLzMaxRows; ++q)
+        if (q <= j) wi -= v[q] * Q[(int64_t)q * nS + i];
+      w[i] = wi;
+    }
+  }
+  v[0] = 0;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) v[0] += w[i] * w[i];
+  block_sum_multi(v, 1, sh);
+  const double b = sqrt(v[0]);
+  if (threadIdx.x == 0) {
+    ab[j] = a;
+    ab[kmax + j] = b;
+  }
+  const double inv = b > 0 ? 1.0 / b : 0.0;
+  double* qn = Q + (int64_t)(j + 1) * nS;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) qn[i] = w[i] * inv;
+}
+
+// One Lanczos step on G = Re(Phi_S^H Phi_S) given g = G q_j (the operator
+// pair applied by other kernels); Q holds kmax + 1 rows of nS, w is scratch.
+__global__ __launch_bounds__(256) void lanczos_step_kernel(int64_t nS, int j, int kmax,
+                                                           double* __restrict__ Q,
+                                                           const double* __restrict__ g,
+                                                           double* __restrict__ w,
+                                                           double* __restrict__ ab) {
+  __shared__ double sh[4 * kLzMaxRows];
+  for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] = g[i];
+  lanczos_finish_step(nS, j, kmax, Q, w, ab, sh);
+}
+
+// Lanczos steps j0..j1-1 on the Gram matrix in one workgroup, with
+// g = G q_j formed in place.  Q rows 0..j0 are set (row 0: the unit start
+// vector); ab as for lanczos_finish_step.
 __global__ __launch_bounds__(256) void gram_lanczos_kernel(int64_t nS, int j0, int j1, int kmax,
                                                            const double* __restrict__ G,
                                                            double* __restrict__ Q,
                                                            double* __restrict__ w,
                                                            double* __restrict__ ab) {
-  __shared__ double sh[4];
+  __shared__ double sh[4 * kLzMaxRows];
   for (int j = j0; j < j1; ++j) {
     const double* qj = Q + (int64_t)j * nS;
-    double a = 0;
-    for (int64_t i = threadIdx.x; i < nS; i += 256) {
-      const double s = gram_col_dot(G, qj, nS, i);
-      w[i] = s;  // (G q_j)_i
-      a += qj[i] * s;
-    }
-    a = block_sum<256>(a, sh);
-    const double bp = j > 0 ? ab[kmax + j - 1] : 0.0;
-    const double* qp = j > 0 ? Q + (int64_t)(j - 1) * nS : qj;
-    for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] -= a * qj[i] + bp * qp[i];
-    for (int pass = 0; pass < 2; ++pass)
-      for (int q = 0; q <= j; ++q) {
-        const double* qq = Q + (int64_t)q * nS;
-        double d = 0;
-        for (int64_t i = threadIdx.x; i < nS; i += 256) d += qq[i] * w[i];
-        d = block_sum<256>(d, sh);
-        for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] -= d * qq[i];
-      }
-    double bn = 0;
-    for (int64_t i = threadIdx.x; i < nS; i += 256) bn += w[i] * w[i];
-    bn = sqrt(block_sum<256>(bn, sh));
-    if (threadIdx.x == 0) {
-      ab[j] = a;
-      ab[kmax + j] = bn;
-    }
-    const double inv = bn > 0 ? 1.0 / bn : 0.0;
-    double* qn = Q + (int64_t)(j + 1) * nS;
-    for (int64_t i = threadIdx.x; i < nS; i += 256) qn[i] = w[i] * inv;
-    __syncthreads();  // q_{j+1} (and ab) complete before the next product
+    for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] = gram_col_dot(G, qj, nS, i);
+    lanczos_finish_step(nS, j, kmax, Q, w, ab, sh);
+    __syncthreads();  // q_{j+1} complete before the next product
   }
 }
 
