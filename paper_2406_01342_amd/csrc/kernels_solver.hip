@@ -149,11 +149,13 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
                                                          double* __restrict__ y,
                                                          double* __restrict__ g_out,
                                                          double* __restrict__ stats, double v2,
-                                                         double inv_lip, double thr, double mom,
-                                                         int check, int iter, double lam,
-                                                         double tol, int* __restrict__ done) {
+                                                         const double* __restrict__ lipd,
+                                                         double mom, int check, int iter,
+                                                         double lam, double tol,
+                                                         int* __restrict__ done) {
   __shared__ double sh[4];
   if (done[0]) return;  // uniform: every thread reads the same flag
+  const double inv_lip = 1.0 / lipd[0], thr = lam * inv_lip;  // step constant from the device
   double yGy = 0, yb = 0, yl1 = 0, gmax = 0;
   for (int64_t q = threadIdx.x; q < nS; q += 256) {
     const double s = gram_col_dot(G, y, nS, q);  // (G y)_q
@@ -279,20 +281,103 @@ __global__ __launch_bounds__(256) void lanczos_step_kernel(int64_t nS, int j, in
   lanczos_finish_step(nS, j, kmax, Q, w, ab, sh);
 }
 
-// Lanczos steps j0..j1-1 on the Gram matrix in one workgroup, with
-// g = G q_j formed in place.  Q rows 0..j0 are set (row 0: the unit start
-// vector); ab as for lanczos_finish_step.
-__global__ __launch_bounds__(256) void gram_lanczos_kernel(int64_t nS, int j0, int j1, int kmax,
-                                                           const double* __restrict__ G,
-                                                           double* __restrict__ Q,
-                                                           double* __restrict__ w,
-                                                           double* __restrict__ ab) {
+// Top eigenpair of the k x k symmetric tridiagonal T (diagonal al[0..k),
+// off-diagonal be[0..k-1)), by one wave: Sturm-sequence multisection (each
+// of the 64 lanes counts the eigenvalues below its own point of the current
+// bracket; 12 rounds shrink the Gershgorin bracket by 65^12), then the
+// eigenvector from the three-term recurrence (x_0 = 1), normalised.  Every
+// lane returns theta and writes nothing; lane 0 stores s[0..k).
+__device__ double tridiag_top(const double* al, const double* be, int k, double* s) {
+  const int lane = threadIdx.x & 63;
+  double lo = al[0], hi = al[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < k ? fabs(be[i]) : 0.0);
+    lo = fmin(lo, al[i] - r);
+    hi = fmax(hi, al[i] + r);
+  }
+  hi += 1e-300 + 1e-15 * fabs(hi);  // every eigenvalue strictly below hi
+  for (int round = 0; round < 12; ++round) {
+    const double xl = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    int below = 0;  // eigenvalues < xl (signs of the LDL^T pivots of T - xl)
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+      const double off = i > 0 ? be[i - 1] * be[i - 1] / d : 0.0;
+      d = al[i] - xl - off;
+      if (d == 0.0) d = -1e-300;
+      below += d < 0.0;
+    }
+    // the top eigenvalue lies between the last point with fewer than k
+    // eigenvalues below it and the first point with all k below it
+    const unsigned long long all_k = __ballot(below >= k);
+    const int first = all_k ? __ffsll((long long)all_k) - 1 : 64;
+    const double nhi = first < 64 ? __shfl(xl, first, 64) : hi;
+    const double nlo = first > 0 ? __shfl(xl, first - 1, 64) : lo;
+    lo = nlo;
+    hi = nhi;
+  }
+  const double theta = 0.5 * (lo + hi);
+  if (lane == 0) {
+    double xm = 0.0, xc = 1.0, nrm = 1.0;
+    s[0] = 1.0;
+    for (int i = 0; i + 1 < k; ++i) {
+      const double xn = ((theta - al[i]) * xc - (i > 0 ? be[i - 1] * xm : 0.0)) / be[i];
+      s[i + 1] = xn;
+      nrm += xn * xn;
+      xm = xc;
+      xc = xn;
+    }
+    nrm = sqrt(nrm);
+    for (int i = 0; i < k; ++i) s[i] /= nrm;
+  }
+  return theta;
+}
+
+// The whole Lanczos estimate of the Gram form in one workgroup and without a
+// host round trip: steps j = 0.. (Q row 0 holds the unit start vector), and
+// after each one the test of the host version: theta = top eigenvalue of
+// T_{j+1}, rho = beta_j |s_j|; stop when rho <= tol theta, on an invariant
+// subspace (beta_j <= 1e-14 theta, or j + 1 = nS) or at kmax steps.  Writes
+// out[0] = (theta + rho) * margin (the APGD step constant), out[1] = steps,
+// out[2] = theta, out[3] = rho, and ritz = sum_q s_q q_q (the next start).
+__global__ __launch_bounds__(256) void gram_lanczos_full_kernel(
+    int64_t nS, int kmax, double tol, double margin, const double* __restrict__ G,
+    double* __restrict__ Q, double* __restrict__ w, double* __restrict__ ab,
+    double* __restrict__ out, double* __restrict__ ritz) {
   __shared__ double sh[4 * kLzMaxRows];
-  for (int j = j0; j < j1; ++j) {
+  __shared__ double svec[kLzMaxRows];
+  __shared__ double res[3];  // theta, rho, stop flag
+  const int jmax = (int)(nS < kmax ? nS : kmax);
+  int k = 0;
+  for (int j = 0; j < jmax; ++j) {
     const double* qj = Q + (int64_t)j * nS;
     for (int64_t i = threadIdx.x; i < nS; i += 256) w[i] = gram_col_dot(G, qj, nS, i);
     lanczos_finish_step(nS, j, kmax, Q, w, ab, sh);
-    __syncthreads();  // q_{j+1} complete before the next product
+    __syncthreads();  // ab[j], beta_j and q_{j+1} visible to all
+    if (threadIdx.x < 64) {
+      const double theta = tridiag_top(ab, ab + kmax, j + 1, svec);
+      if (threadIdx.x == 0) {
+        const double bj = ab[kmax + j];
+        const double rho = bj * fabs(svec[j]);
+        const bool invariant = bj <= 1e-14 * fmax(theta, 1e-300) || j + 1 >= nS;
+        res[0] = theta;
+        res[1] = rho;
+        res[2] = (invariant || rho <= tol * theta || j + 1 == kmax) ? 1.0 : 0.0;
+      }
+    }
+    __syncthreads();
+    k = j + 1;
+    if (res[2] != 0.0) break;
+  }
+  if (threadIdx.x == 0) {
+    out[0] = (res[0] + res[1]) * margin;
+    out[1] = (double)k;
+    out[2] = res[0];
+    out[3] = res[1];
+  }
+  for (int64_t i = threadIdx.x; i < nS; i += 256) {
+    double v = 0;
+    for (int q = 0; q < k; ++q) v += svec[q] * Q[(int64_t)q * nS + i];
+    ritz[i] = v;
   }
 }
 
@@ -422,20 +507,21 @@ void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const do
 }
 
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
-                  double* g, double* stats, double v2, double inv_lip, double thr, double mom,
-                  bool check, int iter, double lam, double tol, int* done, hipStream_t s) {
+                  double* g, double* stats, double v2, const double* lipd, double mom, bool check,
+                  int iter, double lam, double tol, int* done, hipStream_t s) {
   ProfScope ps(p, s, "gram_fista", 8.0 * nS * (nS + 6), (double)nS * nS);
   hipLaunchKernelGGL(gram_fista_kernel, dim3(1), dim3(256), 0, s, nS, G, b, x, y, g, stats, v2,
-                     inv_lip, thr, mom, check ? 1 : 0, iter, lam, tol, done);
+                     lipd, mom, check ? 1 : 0, iter, lam, tol, done);
   PC_LAUNCH_CHECK("gram_fista");
 }
 
-void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const double* G, double* Q,
-                    double* w, double* ab, hipStream_t s) {
-  ProfScope ps(p, s, "gram_lanczos", 8.0 * nS * (double)(j1 - j0) * (nS + 30), (double)(j1 - j0));
-  hipLaunchKernelGGL(gram_lanczos_kernel, dim3(1), dim3(256), 0, s, nS, j0, j1, kmax, G, Q, w,
-                     ab);
-  PC_LAUNCH_CHECK("gram_lanczos");
+void k_gram_lanczos_full(pc_plan* p, int64_t nS, int kmax, double tol, double margin,
+                         const double* G, double* Q, double* w, double* ab, double* out,
+                         double* ritz, hipStream_t s) {
+  ProfScope ps(p, s, "gram_lanczos", 8.0 * nS * (double)(nS + 30) * 4, (double)nS);
+  hipLaunchKernelGGL(gram_lanczos_full_kernel, dim3(1), dim3(256), 0, s, nS, kmax, tol, margin, G,
+                     Q, w, ab, out, ritz);
+  PC_LAUNCH_CHECK("gram_lanczos_full");
 }
 
 void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,

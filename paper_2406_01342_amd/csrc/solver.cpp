@@ -154,6 +154,7 @@ struct Pfw {
   DevArray<Atom<float>> atoms;
   DevArray<double> x, y, g, adj_partial, red_partial, scal, stat;
   DevArray<double> lz_Q, lz_w, lz_ab;  // Lanczos basis rows, scratch, alpha/beta
+  DevArray<double> lz_out;             // Gram form: {L, steps, theta, rho}, Ritz vector
   // Gram form of the restricted problem: G = Re(Phi_S^H Phi_S) and b = Phi_S^* V.
   // For coplanar arrays G_pq = psf(a_p - a_q, b_p - b_q) / (n_p n_q) with
   // psf(da, db) = sum_k cos 2 pi (A_k da + B_k db), kept per solve by offset.
@@ -523,7 +524,7 @@ struct Pfw {
   // basis) bracket an eigenvalue: |lambda - theta| <= rho.  Stops when
   // rho <= kLanczosTol theta (or at kLanczosMax steps, or on an invariant
   // subspace) and returns theta + rho.
-  double top_eigen_bound(const std::vector<int32_t>& set, bool gridded, bool gram) {
+  double top_eigen_bound(const std::vector<int32_t>& set, bool gridded) {
     const int64_t nS = (int64_t)set.size();
     // The recurrence runs on the device (k_lanczos_step); the host reads
     // alpha, beta (and the basis) once per batch of steps and applies the
@@ -532,10 +533,9 @@ struct Pfw {
     const int jmax = (int)std::min<int64_t>(kLanczosMax, nS);  // T is at most nS x nS
     lz_w.ensure(nS);
     lz_ab.ensure(2 * kLanczosMax);
-    double* Qd = gram_Q;  // the Gram form uploaded the start vector with G
-    if (!gram) {
-      lz_Q.ensure((int64_t)(kLanczosMax + 1) * nS);
-      Qd = lz_Q.ptr;
+    lz_Q.ensure((int64_t)(kLanczosMax + 1) * nS);
+    double* Qd = lz_Q.ptr;
+    {
       const std::vector<double> v0 = lanczos_start(set);
       double* h = (double*)up.get(nS * 8);
       std::memcpy(h, v0.data(), nS * 8);
@@ -547,9 +547,7 @@ struct Pfw {
     int done_steps = 0, kfin = 0;
     while (kfin == 0) {
       const int jend = std::min(jmax, done_steps + kLanczosBatch);
-      if (gram)  // the batch's steps in one launch
-        k_gram_lanczos(p, nS, done_steps, jend, kLanczosMax, gram_G, Qd, lz_w.ptr, lz_ab.ptr, s);
-      for (int j = gram ? jend : done_steps; j < jend; ++j) {
+      for (int j = done_steps; j < jend; ++j) {
         double* qj = Qd + (int64_t)j * nS;
         if (!gridded) k_weights(p, nS, qj, atoms.ptr, s);
         if (!gridded && fused_supported(nS)) {  // g = Phi_S* Phi_S q_j in one pass
@@ -653,7 +651,18 @@ struct Pfw {
     // small direct sets: the Gram form (one small kernel per step)
     const bool gram = !gridded && nS > 0 && nS <= gram_cap() && build_gram(Sn);
     if (nS > 0) {
-      const double lip = top_eigen_bound(Sn, gridded, gram) * kLipMargin;
+      // step constant: on the device for the Gram form (read there by the
+      // APGD kernel, no host round trip), else from the host-driven Lanczos
+      double lip = 0;
+      if (gram) {
+        lz_w.ensure(nS);
+        lz_ab.ensure(2 * kLanczosMax);
+        lz_out.ensure(4 + nS);
+        k_gram_lanczos_full(p, nS, kLanczosMax, kLanczosTol, kLipMargin, gram_G, gram_Q, lz_w.ptr,
+                            lz_ab.ptr, lz_out.ptr, lz_out.ptr + 4, s);
+      } else {
+        lip = top_eigen_bound(Sn, gridded) * kLipMargin;
+      }
       k_weights(p, nS, y.ptr, atoms.ptr, s);  // y = x_warm as forward weights
       const double tol = std::max(prm.inner_tol_min, prm.inner_tol0 * rel_gap);
       double t = 1.0;  // FISTA momentum sequence, on the host in FP64
@@ -678,12 +687,14 @@ struct Pfw {
             const double mom = (t - 1.0) / tn;
             t = tn;
             k_gram_fista(p, nS, gram_G, gram_b, x.ptr, y.ptr, g.ptr, scal.ptr + kScalResid,
-                         v2, 1.0 / lip, lam / lip, mom, (it - 1) % kCheck == 0, it, lam, tol,
+                         v2, lz_out.ptr, mom, (it - 1) % kCheck == 0, it, lam, tol,
                          gram_done.ptr, s);
           }
-          h = (unsigned char*)down.get(8 + nS * 8);
+          // outcome, x, and the Lanczos result with its Ritz vector
+          h = (unsigned char*)down.get(8 + nS * 8 + (4 + nS) * 8);
           PC_HIP(hipMemcpyAsync(h, gram_done.ptr, 8, hipMemcpyDeviceToHost, s));
           PC_HIP(hipMemcpyAsync(h + 8, x.ptr, nS * 8, hipMemcpyDeviceToHost, s));
+          PC_HIP(hipMemcpyAsync(h + 8 + nS * 8, lz_out.ptr, (4 + nS) * 8, hipMemcpyDeviceToHost, s));
           PC_HIP(hipStreamSynchronize(s));
           const int* dn = (const int*)h;
           if (dn[0]) stop = dn[1];
@@ -692,6 +703,9 @@ struct Pfw {
         last_inner = inner;
         xw.resize(nS);
         std::memcpy(xw.data(), h + 8, nS * 8);
+        const double* lz = (const double*)(h + 8 + nS * 8);  // {L, steps, theta, rho}, ritz
+        pv_set = Sn;
+        pv_val.assign(lz + 4, lz + 4 + nS);
       } else {
         stat.ensure(2 * nS);
         // small direct sets: forward and restricted adjoint share one pass

@@ -25,17 +25,20 @@ void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const do
                     double* ab, hipStream_t s);
 void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipStream_t s);
 // Gram form of the restricted problem (see gram_fista_kernel): one APGD step,
-// optionally with the duality-gap statistics, and Lanczos steps j0..j1-1.
+// optionally with the in-kernel duality-gap test.
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
-                  double* g, double* stats, double v2, double inv_lip, double thr, double mom,
-                  bool check, int iter, double lam, double tol, int* done, hipStream_t s);
+                  double* g, double* stats, double v2, const double* lipd, double mom, bool check,
+                  int iter, double lam, double tol, int* done, hipStream_t s);
+// The Gram form's Lanczos estimate with its stopping rule on the device: out =
+// {step constant, steps, theta, rho}, ritz = the top Ritz vector.
+void k_gram_lanczos_full(pc_plan* p, int64_t nS, int kmax, double tol, double margin,
+                         const double* G, double* Q, double* w, double* ab, double* out,
+                         double* ritz, hipStream_t s);
 void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s);
 // Active set from one device block [x: nS doubles][pix: nS int32]: x, y, pix
 // and the padded atom table (atom_capacity(nS) entries).
 void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,
                 Atom<float>* atoms, hipStream_t s);
-void k_gram_lanczos(pc_plan* p, int64_t nS, int j0, int j1, int kmax, const double* G, double* Q,
-                    double* w, double* ab, hipStream_t s);
 void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s);
 // Gridded-operator helpers for large active sets.
 void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, float* img,

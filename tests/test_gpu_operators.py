@@ -133,12 +133,12 @@ def test_adjoint_sparse(name, natoms):
 @pytest.mark.parametrize("name,natoms", [("c1", 1), ("c1", 7), ("c1", 8), ("c1", 9), ("c1", 24),
                                           ("c1", 33), ("c1", 64), ("c1", 65), ("c1", 300),
                                           ("c2_small", 5), ("c2_small", 40), ("c2_small", 64),
-                                          ("ragged", 13), ("c1", 0)])
+                                          ("ragged", 13), ("c1", 0), ("c2", 40)])
 def test_restricted_gradient(name, natoms):
     """Phi_S* (V - Phi_S x) and the residual against the oracle: the one-pass
     kernel at every atoms-per-pass size (8..64, padded groups), the two-pass
     path above 64 atoms, a visibility count that leaves a ragged last wave,
-    and the empty set (r = V)."""
+    the empty set (r = V), and the full LOFAR-like visibility set."""
     say("restricted_gradient", name, natoms)
     if name == "ragged":
         uv, n, fov, vis = ragged_problem()
