@@ -92,6 +92,25 @@ def test_solve_c2_small_gap_stop(gram):
     assert res["cert_max"] <= 1 + 1e-3
 
 
+def test_gram_form_follows_the_operator_form():
+    """With the stopping rules off (12 FW iterations, at most 5 APGD steps
+    each; the restricted gap test can still stop a step once the computed
+    gap reaches zero) the Gram form and the operator form take the same
+    trajectory up to FP32 operator rounding: equal objective to 1e-6."""
+    say("gram vs operator form, fixed steps")
+    p, vis = problem("c2_small")
+    kw = dict(alpha=p.alpha, delta=p.delta, max_iter=12, rel_obj_tol=0.0, rel_gap_tol=0.0,
+              inner_max_iter=5, inner_tol0=0.0, inner_tol_min=1e-300)
+    _, rg, _ = _gpu_solve(p, vis, gram_atoms=0, **kw)
+    _, ro, _ = _gpu_solve(p, vis, gram_atoms=-1, **kw)
+    say("gram", rg["objective"], rg["inner_iters"], rg["natoms"],
+        "operator", ro["objective"], ro["inner_iters"], ro["natoms"])
+    assert rg["iters"] == ro["iters"] == 12
+    assert 12 <= rg["inner_iters"] <= 12 * 5 and 12 <= ro["inner_iters"] <= 12 * 5
+    assert abs(rg["objective"] - ro["objective"]) <= 1e-6 * ro["objective"]
+    assert abs(rg["natoms"] - ro["natoms"]) <= 2
+
+
 @pytest.mark.parametrize("name,grid_atoms", [("c1", 1), ("c1", 8), ("c2_small", 4)])
 def test_solve_gridded_apgd_matches_oracle(name, grid_atoms):
     """Active sets above the crossover apply Phi_S and Phi_S* through the
