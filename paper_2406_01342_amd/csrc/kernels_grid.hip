@@ -367,12 +367,17 @@ __global__ __launch_bounds__(64 * kFoldSub) void fold_batch_kernel(
   fold_body<float>(J.g, J.fold[it.y], J.partials, J.grid);
 }
 
-// Pass-A output layout: columns grouped in blocks of kHB, each block stored
-// row-major over the band rows, so that a pass-B workgroup reading kHB (or
+// Pass-A output layout: columns grouped in blocks of KHB, each block stored
+// row-major over the band rows, so that a pass-B workgroup reading KHB (or
 // fewer) adjacent columns reads one contiguous stretch.
-constexpr int kHB = 8;
+constexpr int kHBLarge = 4;  // block width at fine grids of 8192 and more
+template <int M>
+constexpr int khb_for() {
+  return M >= 8192 ? kHBLarge : 8;
+}
+template <int KHB>
 __device__ __forceinline__ size_t h_index(int row, int col, int nv) {
-  return ((size_t)(col / kHB) * nv + row) * kHB + (col % kHB);
+  return ((size_t)(col / KHB) * nv + row) * KHB + (col % KHB);
 }
 
 // Fills the padded LDS buffer from global memory: element idx (< TOTAL) goes
@@ -462,7 +467,7 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
     if (row < g.nv) {
       int f = i - n / 2;
       if (f < 0) f += M;
-      H[h_index(row, i, g.nv)] = buf[pidx(b * M + f)];
+      H[h_index<khb_for<M>()>(row, i, g.nv)] = buf[pidx(b * M + f)];
     }
   }
 }
@@ -503,13 +508,14 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
   constexpr int n = M / 2;
   const int i0 = iblock * NB;
   // element (m, b): band row m - v0 of column i0 + b of the pass-A buffer,
-  // whose kHB-wide column blocks are row-major over the band rows
+  // whose KHB-wide column blocks are row-major over the band rows
   static_assert((NB & (NB - 1)) == 0 && NT % NB == 0, "pass-B layout");
   constexpr int IT = (NB * M + NT - 1) / NT;
   constexpr int MSTEP = NT / NB;  // a thread's m advances by this per element
   const int b = (int)threadIdx.x & (NB - 1), m0 = (int)threadIdx.x / NB;
   const int col = i0 + b;
-  const cpx<R>* hcol = H + (size_t)(col / kHB) * g.nv * kHB + (col % kHB);
+  constexpr int KHB = khb_for<M>();
+  const cpx<R>* hcol = H + (size_t)(col / KHB) * g.nv * KHB + (col % KHB);
   cpx<R> t[IT];
   bool ok[IT];
 #pragma unroll
@@ -517,7 +523,7 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
     const int m = m0 + it * MSTEP;
     const int rel = m - g.v0;
     ok[it] = m < M && (unsigned)rel < (unsigned)g.nv;
-    t[it] = hcol[ok[it] ? (size_t)rel * kHB : 0];
+    t[it] = hcol[ok[it] ? (size_t)rel * KHB : 0];
   }
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
@@ -615,7 +621,7 @@ __global__ __launch_bounds__(NT) void passB_fwd_kernel(GridGeom g, const R* __re
   for (int idx = threadIdx.x; idx < NB * g.nv; idx += NT) {
     const int rel = idx / NB, b = idx - rel * NB;
     int m = g.v0 + rel;
-    H[h_index(rel, i0 + b, g.nv)] = buf[pidx(b * M + m)];
+    H[h_index<khb_for<M>()>(rel, i0 + b, g.nv)] = buf[pidx(b * M + m)];
   }
 }
 
@@ -638,7 +644,7 @@ __global__ __launch_bounds__(NT) void passA_fwd_kernel(GridGeom g, const cpx<R>*
         const int row = row0 + b;
         const int f = m < n / 2 ? m : m - M;
         if (row >= g.nv || f < -n / 2 || f >= n / 2) return -1;
-        return (int64_t)h_index(row, f + n / 2, g.nv);
+        return (int64_t)h_index<khb_for<M>()>(row, f + n / 2, g.nv);
       },
       [](int idx) { return idx; });
   __syncthreads();
