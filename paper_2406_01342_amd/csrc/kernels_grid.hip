@@ -516,22 +516,67 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
   const int col = i0 + b;
   constexpr int KHB = khb_for<M>();
   const cpx<R>* hcol = H + (size_t)(col / KHB) * g.nv * KHB + (col % KHB);
-  cpx<R> t[IT];
-  bool ok[IT];
+  // Input pruning: with a first radix of 2 or 4 and a band no longer than
+  // M / radix, each first-stage butterfly (inputs j + r M / radix) holds at
+  // most one band row, so the stage is applied while loading: output s of
+  // butterfly j is that row rotated by r s quarter (or half) turns, exactly
+  // what the full stage computes.  The remaining stages follow as usual.
+  constexpr int RAD0 = first_radix(M);
+  constexpr int NBF0 = M / RAD0;
+  bool pruned = false;
+  if constexpr (RAD0 <= 4) {
+    if (g.nv <= NBF0) {  // uniform
+      pruned = true;
+      constexpr int ITJ = (NBF0 + MSTEP - 1) / MSTEP;
+      cpx<R> t[ITJ];
+      int rr[ITJ];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int m = m0 + it * MSTEP;
-    const int rel = m - g.v0;
-    ok[it] = m < M && (unsigned)rel < (unsigned)g.nv;
-    t[it] = hcol[ok[it] ? (size_t)rel * KHB : 0];
+      for (int it = 0; it < ITJ; ++it) {
+        const int j = m0 + it * MSTEP;
+        const int d = g.v0 - j;
+        const int r = d > 0 ? (d + NBF0 - 1) / NBF0 : 0;  // first input at or past v0
+        const int rel = j + r * NBF0 - g.v0;
+        const bool ok = j < NBF0 && r < RAD0 && (unsigned)rel < (unsigned)g.nv;
+        t[it] = hcol[ok ? (size_t)rel * KHB : 0];
+        rr[it] = ok ? r : -1;
+      }
+#pragma unroll
+      for (int it = 0; it < ITJ; ++it) {
+        const int j = m0 + it * MSTEP;
+        if (NBF0 % MSTEP == 0 || j < NBF0) {
+#pragma unroll
+          for (int s = 0; s < RAD0; ++s)
+            buf[pidx(b * M + j * RAD0 + s)] =
+                rr[it] >= 0 ? rot<R, RAD0, +1>(t[it], (rr[it] * s) % RAD0) : cpx<R>{R(0), R(0)};
+        }
+      }
+    }
   }
+  if (!pruned) {
+    cpx<R> t[IT];
+    bool ok[IT];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int m = m0 + it * MSTEP;
-    if ((NB * M) % NT == 0 || m < M) buf[pidx(b * M + m)] = ok[it] ? t[it] : cpx<R>{R(0), R(0)};
+    for (int it = 0; it < IT; ++it) {
+      const int m = m0 + it * MSTEP;
+      const int rel = m - g.v0;
+      ok[it] = m < M && (unsigned)rel < (unsigned)g.nv;
+      t[it] = hcol[ok[it] ? (size_t)rel * KHB : 0];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int m = m0 + it * MSTEP;
+      if ((NB * M) % NT == 0 || m < M) buf[pidx(b * M + m)] = ok[it] ? t[it] : cpx<R>{R(0), R(0)};
+    }
   }
   __syncthreads();
-  lds_fft<R, M, NB, NT, +1>(buf, tws);
+  if constexpr (RAD0 <= 4) {
+    if (pruned)
+      fft_stages<R, M, NB, NT, +1, RAD0>(buf, tws);
+    else
+      lds_fft<R, M, NB, NT, +1>(buf, tws);
+  } else {
+    lds_fft<R, M, NB, NT, +1>(buf, tws);
+  }
   unsigned long long best = 0;
   const R dl = (R)g.dl;
   for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
