@@ -443,24 +443,70 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
   }
   load_twiddles<R, M, NT>(tws, tw);  // ends with a barrier
   static_assert((NB * M) % NT == 0 && NT % 16 == 0, "pass-A gather layout");
-  constexpr int IT = NB * M / NT;
-  cpx<R> t[IT];
-  bool ok[IT];
+  // Input pruning as in pass B: with a first radix of 2 or 4 and a band no
+  // wider than M / radix columns, the first stage is applied while loading.
+  constexpr int RAD0 = first_radix(M);
+  constexpr int NBF0 = M / RAD0;
+  bool pruned = false;
+  if constexpr (RAD0 <= 4) {
+    if (g.nu <= NBF0) {  // uniform
+      pruned = true;
+      constexpr int ITJ = (NB * NBF0 + NT - 1) / NT;
+      cpx<R> t[ITJ];
+      int rr[ITJ];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = (int)threadIdx.x + it * NT;
-    const int b = idx / M, m = idx - b * M;
-    const int row = row0 + b, rel = m - g.u0;
-    ok[it] = row < g.nv && (unsigned)rel < (unsigned)g.nu &&
-             sflag[row / kTile - tr0][rel / kTile] != 0;
-    t[it] = grid[ok[it] ? (size_t)row * g.nu + rel : 0];
+      for (int it = 0; it < ITJ; ++it) {
+        const int e = (int)threadIdx.x + it * NT;
+        const int b = e / NBF0, j = e - b * NBF0;
+        const int row = row0 + b;
+        const int d = g.u0 - j;
+        const int r = d > 0 ? (d + NBF0 - 1) / NBF0 : 0;  // first input at or past u0
+        const int rel = j + r * NBF0 - g.u0;
+        const bool ok = e < NB * NBF0 && row < g.nv && r < RAD0 && (unsigned)rel < (unsigned)g.nu &&
+                        sflag[row / kTile - tr0][rel / kTile] != 0;
+        t[it] = grid[ok ? (size_t)row * g.nu + rel : 0];
+        rr[it] = ok ? r : -1;
+      }
+#pragma unroll
+      for (int it = 0; it < ITJ; ++it) {
+        const int e = (int)threadIdx.x + it * NT;
+        if ((NB * NBF0) % NT == 0 || e < NB * NBF0) {
+          const int b = e / NBF0, j = e - b * NBF0;
+#pragma unroll
+          for (int s = 0; s < RAD0; ++s)
+            buf[pidx(b * M + j * RAD0 + s)] =
+                rr[it] >= 0 ? rot<R, RAD0, +1>(t[it], (rr[it] * s) % RAD0) : cpx<R>{R(0), R(0)};
+        }
+      }
+    }
   }
-  const int p0 = pidx((int)threadIdx.x);
+  if (!pruned) {
+    constexpr int IT = NB * M / NT;
+    cpx<R> t[IT];
+    bool ok[IT];
 #pragma unroll
-  for (int it = 0; it < IT; ++it)
-    buf[p0 + it * padded(NT)] = ok[it] ? t[it] : cpx<R>{R(0), R(0)};
+    for (int it = 0; it < IT; ++it) {
+      const int idx = (int)threadIdx.x + it * NT;
+      const int b = idx / M, m = idx - b * M;
+      const int row = row0 + b, rel = m - g.u0;
+      ok[it] = row < g.nv && (unsigned)rel < (unsigned)g.nu &&
+               sflag[row / kTile - tr0][rel / kTile] != 0;
+      t[it] = grid[ok[it] ? (size_t)row * g.nu + rel : 0];
+    }
+    const int p0 = pidx((int)threadIdx.x);
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+      buf[p0 + it * padded(NT)] = ok[it] ? t[it] : cpx<R>{R(0), R(0)};
+  }
   __syncthreads();
-  lds_fft<R, M, NB, NT, +1>(buf, tws);
+  if constexpr (RAD0 <= 4) {
+    if (pruned)
+      fft_stages<R, M, NB, NT, +1, RAD0>(buf, tws);
+    else
+      lds_fft<R, M, NB, NT, +1>(buf, tws);
+  } else {
+    lds_fft<R, M, NB, NT, +1>(buf, tws);
+  }
   for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
     const int b = idx / n, i = idx - b * n;
     const int row = row0 + b;
