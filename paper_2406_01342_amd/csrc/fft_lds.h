@@ -176,6 +176,68 @@ __device__ __forceinline__ void fft_stages(cpx<R>* buf, const cpx<R>* tw) {
   }
 }
 
+// The last stage (NS * RAD = M), with each output handed to store(b, f, v)
+// (f = frequency index of sequence b) from registers instead of written back
+// to LDS, for the outputs keep(f) selects (for RAD = 16 and a keep that tests
+// ranges of M / 16, decided per r at compile time).  No barrier at the end.
+template <typename R, int RAD, int M, int NB, int NT, int SIGN, int NS, typename Keep,
+          typename Store>
+__device__ __forceinline__ void fft_last_stage(const cpx<R>* buf, const cpx<R>* tw, Keep keep,
+                                               Store store) {
+  static_assert(NS * RAD == M, "last stage");
+  constexpr int NBF = M / RAD;  // == NS: j is its own twiddle index
+  constexpr int TOT = NB * NBF;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr bool RD_LIN = NBF % 16 == 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int bi = (int)threadIdx.x + q * NT;
+    if (TOT % NT == 0 || bi < TOT) {
+      const int b = bi / NBF, j = bi - b * NBF;
+      cpx<R> x[RAD];
+      const int i0 = b * M + j;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r)
+        x[r] = RD_LIN ? buf[pidx(i0) + r * padded(NBF)] : buf[pidx(i0 + r * NBF)];
+      if constexpr (NS > 1) {
+        cpx<R> w[RAD];
+        cpx<R> w1 = twiddle<R, M>(tw, j);
+        if (SIGN < 0) w1.y = -w1.y;
+        twiddle_powers<R, RAD>(w1, w);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) x[r] = cmul(x[r], w[r]);
+      }
+      dft<R, RAD, SIGN>(x);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        const int f = r * NS + j;
+        if (keep(r, f)) store(b, f, x[r]);
+      }
+    }
+  }
+}
+
+template <typename R, int M, int NB, int NT, int SIGN, int NS, typename Keep, typename Store>
+__device__ __forceinline__ void fft_stages_store(cpx<R>* buf, const cpx<R>* tw, Keep keep,
+                                                 Store store) {
+  constexpr int RAD = (NS == 1) ? first_radix(M) : 16;
+  if constexpr (NS * RAD < M) {
+    fft_stage<R, RAD, M, NB, NT, SIGN, NS>(buf, tw);
+    fft_stages_store<R, M, NB, NT, SIGN, NS * RAD>(buf, tw, keep, store);
+  } else {
+    fft_last_stage<R, RAD, M, NB, NT, SIGN, NS>(buf, tw, keep, store);
+  }
+}
+
+// FFT of NB sequences in LDS from stage NS on, the last stage's outputs
+// stored through store(b, f, v) for keep(r, f) (see fft_last_stage); the
+// LDS contents are left undefined.
+template <typename R, int M, int NB, int NT, int SIGN, int NS = 1, typename Keep, typename Store>
+__device__ __forceinline__ void lds_fft_store(cpx<R>* buf, const cpx<R>* tw, Keep keep,
+                                              Store store) {
+  fft_stages_store<R, M, NB, NT, SIGN, NS>(buf, tw, keep, store);
+}
+
 // In-place FFT of NB sequences of length M stored contiguously in LDS, with
 // the twiddle table `tw` in LDS (see load_twiddles).  Must be called by all
 // NT threads of the block; ends with a barrier.

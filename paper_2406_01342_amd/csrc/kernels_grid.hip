@@ -499,22 +499,23 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
       buf[p0 + it * padded(NT)] = ok[it] ? t[it] : cpx<R>{R(0), R(0)};
   }
   __syncthreads();
-  if constexpr (RAD0 <= 4) {
-    if (pruned)
-      fft_stages<R, M, NB, NT, +1, RAD0>(buf, tws);
-    else
-      lds_fft<R, M, NB, NT, +1>(buf, tws);
-  } else {
-    lds_fft<R, M, NB, NT, +1>(buf, tws);
-  }
-  for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
-    const int b = idx / n, i = idx - b * n;
+  // the n central frequencies f in [-n/2, n/2) go to H column i = f + n/2,
+  // stored from the last stage's registers
+  auto keep = [](int, int f) { return 4 * f < M || 4 * f >= 3 * M; };
+  auto store = [&](int b, int f, cpx<R> v) {
     const int row = row0 + b;
     if (row < g.nv) {
-      int f = i - n / 2;
-      if (f < 0) f += M;
-      H[h_index<khb_for<M>()>(row, i, g.nv)] = buf[pidx(b * M + f)];
+      const int i = f < n / 2 ? f + n / 2 : f - M + n / 2;
+      H[h_index<khb_for<M>()>(row, i, g.nv)] = v;
     }
+  };
+  if constexpr (RAD0 <= 4) {
+    if (pruned)
+      lds_fft_store<R, M, NB, NT, +1, RAD0>(buf, tws, keep, store);
+    else
+      lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store);
+  } else {
+    lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store);
   }
 }
 
@@ -615,21 +616,14 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
     }
   }
   __syncthreads();
-  if constexpr (RAD0 <= 4) {
-    if (pruned)
-      fft_stages<R, M, NB, NT, +1, RAD0>(buf, tws);
-    else
-      lds_fft<R, M, NB, NT, +1>(buf, tws);
-  } else {
-    lds_fft<R, M, NB, NT, +1>(buf, tws);
-  }
   unsigned long long best = 0;
   const R dl = (R)g.dl;
-  for (int idx = threadIdx.x; idx < NB * n; idx += NT) {
-    const int bb = idx / n, j = idx - bb * n;
+  // pixel (i, j) from frequency f = j - n/2 (mod M) of column i, stored from
+  // the last stage's registers with the correction and the max key
+  auto keep = [](int, int f) { return 4 * f < M || 4 * f >= 3 * M; };
+  auto store = [&](int bb, int f, cpx<R> v) {
     const int i = i0 + bb;
-    int f = j - n / 2;
-    if (f < 0) f += M;
+    const int j = f < n / 2 ? f + n / 2 : f - M + n / 2;
     const R l = (R)(i - n / 2) * dl, mm = (R)(j - n / 2) * dl;
     R inv_n;
     if constexpr (sizeof(R) == 4) {
@@ -637,10 +631,18 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
     } else {
       inv_n = R(1) / sqrt(R(1) - l * l - mm * mm);
     }
-    const R val = buf[pidx(bb * M + f)].x * (corr[i] * scale) * corr[j] * inv_n;
+    const R val = v.x * (corr[i] * scale) * corr[j] * inv_n;
     image[(size_t)i * n + j] = val;
     const unsigned long long key = max_key((float)fabs(val), i * n + j);
     best = key > best ? key : best;
+  };
+  if constexpr (RAD0 <= 4) {
+    if (pruned)
+      lds_fft_store<R, M, NB, NT, +1, RAD0>(buf, tws, keep, store);
+    else
+      lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store);
+  } else {
+    lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store);
   }
   // block max
   for (int o = 32; o > 0; o >>= 1) {
