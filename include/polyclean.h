@@ -264,7 +264,7 @@ typedef struct {
                           /*   G = Re(Phi_S^H Phi_S) (direct sums at pixel    */
                           /*   offsets) and b = Phi_S* V replace the two      */
                           /*   operators in each APGD and Lanczos step: 0 =   */
-                          /*   256, < 0 = never.                              */
+                          /*   256, < 0 = never, at most 1024.                */
 } pc_solve_params;
 
 typedef struct {

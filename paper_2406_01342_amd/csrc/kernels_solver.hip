@@ -339,13 +339,25 @@ __device__ double tridiag_top(const double* al, const double* be, int k, double*
 // subspace (beta_j <= 1e-14 theta, or j + 1 = nS) or at kmax steps.  Writes
 // out[0] = (theta + rho) * margin (the APGD step constant), out[1] = steps,
 // out[2] = theta, out[3] = rho, and ritz = sum_q s_q q_q (the next start).
+//
+// The basis rows and w live in dynamic LDS ((kmax + 1) nS + nS doubles), and
+// so does G when g_in_lds is set (nS^2 more); Q row 0 is read from Qg.
 __global__ __launch_bounds__(256) void gram_lanczos_full_kernel(
-    int64_t nS, int kmax, double tol, double margin, const double* __restrict__ G,
-    double* __restrict__ Q, double* __restrict__ w, double* __restrict__ ab,
+    int64_t nS, int kmax, double tol, double margin, const double* __restrict__ Gg,
+    const double* __restrict__ Qg, int g_in_lds, double* __restrict__ ab,
     double* __restrict__ out, double* __restrict__ ritz) {
   __shared__ double sh[4 * kLzMaxRows];
   __shared__ double svec[kLzMaxRows];
   __shared__ double res[3];  // theta, rho, stop flag
+  extern __shared__ double dyn[];
+  double* Q = dyn;
+  double* w = Q + (int64_t)(kmax + 1) * nS;
+  double* Gl = w + nS;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) Q[i] = Qg[i];
+  if (g_in_lds)
+    for (int64_t i = threadIdx.x; i < nS * nS; i += 256) Gl[i] = Gg[i];
+  __syncthreads();
+  const double* G = g_in_lds ? Gl : Gg;
   const int jmax = (int)(nS < kmax ? nS : kmax);
   int k = 0;
   for (int j = 0; j < jmax; ++j) {
@@ -516,11 +528,20 @@ void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, doub
 }
 
 void k_gram_lanczos_full(pc_plan* p, int64_t nS, int kmax, double tol, double margin,
-                         const double* G, double* Q, double* w, double* ab, double* out,
-                         double* ritz, hipStream_t s) {
+                         const double* G, const double* Q, double* ab, double* out, double* ritz,
+                         hipStream_t s) {
+  // basis rows and w always in LDS; G too when it fits beside them
+  constexpr size_t kLdsMax = 150 * 1024;
+  const size_t base = (size_t)((kmax + 2) * nS) * 8;
+  const bool g_in_lds = base + (size_t)nS * nS * 8 <= kLdsMax;
+  const size_t lds = base + (g_in_lds ? (size_t)nS * nS * 8 : 0);
+  if (lds > kLdsMax)
+    fail(PC_ERR_UNSUPPORTED, "gram_lanczos: active set of " + std::to_string(nS) + " atoms");
+  PC_HIP(hipFuncSetAttribute((const void*)gram_lanczos_full_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax));
   ProfScope ps(p, s, "gram_lanczos", 8.0 * nS * (double)(nS + 30) * 4, (double)nS);
-  hipLaunchKernelGGL(gram_lanczos_full_kernel, dim3(1), dim3(256), 0, s, nS, kmax, tol, margin, G,
-                     Q, w, ab, out, ritz);
+  hipLaunchKernelGGL(gram_lanczos_full_kernel, dim3(1), dim3(256), lds, s, nS, kmax, tol, margin,
+                     G, Q, g_in_lds ? 1 : 0, ab, out, ritz);
   PC_LAUNCH_CHECK("gram_lanczos_full");
 }
 

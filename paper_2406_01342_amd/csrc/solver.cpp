@@ -363,8 +363,8 @@ struct Pfw {
     }
   }
 
-  int64_t gram_cap() const {
-    if (prm.gram_atoms > 0) return prm.gram_atoms;
+  int64_t gram_cap() const {  // the Gram-form Lanczos holds its basis in LDS
+    if (prm.gram_atoms > 0) return std::min<int64_t>(prm.gram_atoms, kGramLdsAtoms);
     return prm.gram_atoms < 0 ? 0 : kGramAtoms;
   }
 
@@ -655,10 +655,9 @@ struct Pfw {
       // APGD kernel, no host round trip), else from the host-driven Lanczos
       double lip = 0;
       if (gram) {
-        lz_w.ensure(nS);
         lz_ab.ensure(2 * kLanczosMax);
         lz_out.ensure(4 + nS);
-        k_gram_lanczos_full(p, nS, kLanczosMax, kLanczosTol, kLipMargin, gram_G, gram_Q, lz_w.ptr,
+        k_gram_lanczos_full(p, nS, kLanczosMax, kLanczosTol, kLipMargin, gram_G, gram_Q,
                             lz_ab.ptr, lz_out.ptr, lz_out.ptr + 4, s);
       } else {
         lip = top_eigen_bound(Sn, gridded) * kLipMargin;

@@ -31,9 +31,12 @@ void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, doub
                   int iter, double lam, double tol, int* done, hipStream_t s);
 // The Gram form's Lanczos estimate with its stopping rule on the device: out =
 // {step constant, steps, theta, rho}, ritz = the top Ritz vector.
+// The basis and scratch live in LDS (G too for up to ~120 atoms): at most
+// kGramLdsAtoms atoms.
+constexpr int kGramLdsAtoms = 1024;
 void k_gram_lanczos_full(pc_plan* p, int64_t nS, int kmax, double tol, double margin,
-                         const double* G, double* Q, double* w, double* ab, double* out,
-                         double* ritz, hipStream_t s);
+                         const double* G, const double* Q, double* ab, double* out, double* ritz,
+                         hipStream_t s);
 void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s);
 // Active set from one device block [x: nS doubles][pix: nS int32]: x, y, pix
 // and the padded atom table (atom_capacity(nS) entries).
