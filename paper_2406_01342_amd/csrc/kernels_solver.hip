@@ -133,9 +133,10 @@ __device__ __forceinline__ double gram_col_dot(const double* __restrict__ G,
 // nS x nS matrix Re(Phi_S^H Phi_S) (symmetric, row-major, FP64) and
 // b = Phi_S^* V, so that Phi_S^*(V - Phi_S y) = b - G y.  One APGD step in one
 // workgroup: g = b - G y, x+ = soft(y + g / L, lambda / L),
-// y+ = x+ + mom (x+ - x).  With stats != NULL the duality-gap inputs at y are
-// stored too: ||V - Phi_S y||^2 = v2 - 2 y.b + y.G y, Re<V, V - Phi_S y> =
-// v2 - y.b, ||y||_1 and max |g| (v2 = ||V||^2).
+// y+ = x+ + mom (x+ - x), with the step constant L read from lipd[0] (written
+// by the Lanczos kernel).  On `check` steps the duality-gap inputs at y are
+// stored in stats too: ||V - Phi_S y||^2 = v2 - 2 y.b + y.G y,
+// Re<V, V - Phi_S y> = v2 - y.b, ||y||_1 and max |g| (v2 = ||V||^2).
 //
 // done[0] != 0 makes the step a no-op (an earlier step passed the test).  When
 // `check` is set, the restricted duality gap at y is tested in the kernel:
