@@ -6,7 +6,11 @@ out as the real 2L x N matrix A = [Re Phi; Im Phi], and each coordinate is
 minimised exactly in turn:
     x_j <- soft(x_j + a_j^T r / ||a_j||^2, lambda / ||a_j||^2),
 with r = y - A x kept up to date.  Iterates until the relative duality gap is
-below ``gap_tol``.  Shares nothing with the Frank-Wolfe route.
+below ``gap_tol``.  Shares nothing with the Frank-Wolfe route.  With
+``positive`` the coordinates are kept non-negative (the positivity-constrained
+LASSO of the positivity remarks in Sects. 3.1 and 5.1):
+x_j <- max(0, x_j + (a_j^T r - lambda) / ||a_j||^2), and the dual point is
+scaled by the largest positive correlation.
 """
 from __future__ import annotations
 
@@ -27,8 +31,9 @@ def explicit_matrix(uv, npix: int, fov_rad: float) -> np.ndarray:
 
 
 def lasso_cd(A: np.ndarray, y: np.ndarray, lam: float, gap_tol: float = 1e-13,
-             max_sweeps: int = 200000):
-    """Cyclic coordinate descent for 1/2||y - Ax||^2 + lam ||x||_1.
+             max_sweeps: int = 200000, positive: bool = False):
+    """Cyclic coordinate descent for 1/2||y - Ax||^2 + lam ||x||_1 (x >= 0
+    with ``positive``).
 
     Returns (x, objective, relative gap, sweeps)."""
     n = A.shape[1]
@@ -42,14 +47,18 @@ def lasso_cd(A: np.ndarray, y: np.ndarray, lam: float, gap_tol: float = 1e-13,
             if col2[j] == 0.0:
                 continue
             zj = x[j] + float(A[:, j] @ r) / col2[j]
-            xj = np.sign(zj) * max(abs(zj) - lam / col2[j], 0.0)
+            if positive:
+                xj = max(zj - lam / col2[j], 0.0)
+            else:
+                xj = np.sign(zj) * max(abs(zj) - lam / col2[j], 0.0)
             d = xj - x[j]
             if d != 0.0:
                 r -= d * A[:, j]
                 x[j] = xj
         if sweep % 10 == 0 or sweep == 1:
             obj = 0.5 * float(r @ r) + lam * float(np.abs(x).sum())
-            c = float(np.max(np.abs(A.T @ r)))
+            corr = A.T @ r
+            c = float(max(np.max(corr), 0.0)) if positive else float(np.max(np.abs(corr)))
             s = 1.0 if c <= lam else lam / c
             dual = s * float(y @ r) - 0.5 * s * s * float(r @ r)
             rel = (obj - dual) / obj if obj > 0 else 0.0

@@ -33,6 +33,15 @@ Readings of points the paper leaves open (shared with the GPU path):
     at the rescaled residual nu = min(1, lambda / ||Phi* r||_inf) r;
   * ties in the exploration threshold are inclusive (">=", as printed).
 
+Positivity (remarks on positivity in Sects. 3.1 and 5.1): with x >= 0 the
+l1 term is lambda sum x, candidate atoms are placed only at the positive
+maxima of the dirty residual, and the restricted solve keeps x >= 0.  Readings:
+lambda_max = max(0, max_j (Phi* V)_j) (x = 0 is optimal exactly when
+Phi* V <= lambda everywhere); the exploration threshold uses eta itself in
+place of |eta| (and only eta > 0 qualifies); the proximal map is
+max(0, z - t); the dual point is scaled by the largest positive correlation
+max(0, max_j (Phi* r)_j), the one-sided dual constraint.
+
 The restricted problem is solved with the exact normal matrix
 G_S = Re(Phi_S^H Phi_S) and b_S = Phi_S^* V, a different route from the GPU's
 operator applications that computes the same mathematics.
@@ -50,9 +59,21 @@ from .operator import adjoint, forward
 _CHUNK_ELEMS = 1 << 22
 
 
-def soft(z: np.ndarray, t: float) -> np.ndarray:
-    """Proximal map of t ||.||_1 (soft thresholding)."""
+def soft(z: np.ndarray, t: float, positive: bool = False) -> np.ndarray:
+    """Proximal map of t ||.||_1 (soft thresholding); of t ||.||_1 plus the
+    indicator of x >= 0 with ``positive``."""
+    if positive:
+        return np.maximum(z - t, 0.0)
     return np.sign(z) * np.maximum(np.abs(z) - t, 0.0)
+
+
+def dual_scale_norm(g: np.ndarray, positive: bool = False) -> float:
+    """The quantity the dual point is scaled by: ||g||_inf, or max(0, max g)
+    for the one-sided constraint of the positive problem."""
+    g = np.asarray(g)
+    if g.size == 0:
+        return 0.0
+    return float(max(np.max(g), 0.0)) if positive else float(np.max(np.abs(g)))
 
 
 def objective(vis, fit, weight, lam: float) -> float:
@@ -122,7 +143,8 @@ class GramCache:
         return self.G[np.ix_(idx, idx)]
 
 
-def restricted_gap(G: np.ndarray, b: np.ndarray, vv: float, lam: float, y: np.ndarray):
+def restricted_gap(G: np.ndarray, b: np.ndarray, vv: float, lam: float, y: np.ndarray,
+                   positive: bool = False):
     """(P_S(y), gap) of the LASSO restricted to S at y, from the normal
     equations: ||V - Phi_S y||^2 = vv - 2 b.y + y.G.y, Re<V, r> = vv - b.y,
     Phi_S^* r = b - G y (vv = ||V||^2), with the rescaled-residual dual point."""
@@ -130,13 +152,14 @@ def restricted_gap(G: np.ndarray, b: np.ndarray, vv: float, lam: float, y: np.nd
     r2 = vv - 2.0 * float(b @ y) + float(y @ G @ y)
     vr = vv - float(b @ y)
     p = 0.5 * r2 + lam * float(np.sum(np.abs(y)))
-    c = float(np.max(np.abs(gy))) if gy.size else 0.0
+    c = dual_scale_norm(gy, positive)
     s = 1.0 if c <= lam else lam / c
     return p, p - (s * vr - 0.5 * s * s * r2), gy
 
 
 def fista_restricted(G: np.ndarray, b: np.ndarray, vv: float, lam: float, x0: np.ndarray,
-                     tol: float, max_iter: int, lip: Optional[float] = None):
+                     tol: float, max_iter: int, lip: Optional[float] = None,
+                     positive: bool = False):
     """argmin_x 1/2 x^T G x - b^T x + lam ||x||_1 by FISTA (Beck & Teboulle).
 
     Each step evaluates the gradient at the extrapolated point y, takes the
@@ -153,8 +176,8 @@ def fista_restricted(G: np.ndarray, b: np.ndarray, vv: float, lam: float, x0: np
     t = 1.0
     it = 0
     for it in range(1, max_iter + 1):
-        p, gap, gy = restricted_gap(G, b, vv, lam, y)
-        xn = soft(y + gy / lip, lam / lip)
+        p, gap, gy = restricted_gap(G, b, vv, lam, y, positive)
+        xn = soft(y + gy / lip, lam / lip, positive)
         if gap <= tol * p:
             return xn, it
         tn = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
@@ -198,7 +221,7 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
               max_iter: int = 50, rel_obj_tol: float = 0.0,
               rel_gap_tol: float = 0.0, inner_tol0: float = 1e-1,
               inner_tol_min: float = 1e-8, inner_max_iter: int = 2000,
-              dirty: Optional[np.ndarray] = None) -> SolveResult:
+              dirty: Optional[np.ndarray] = None, positivity: bool = False) -> SolveResult:
     """Polyatomic Frank-Wolfe for the point-source LASSO (Alg. 2).
 
     ``alpha`` sets lambda = alpha * lambda_max unless ``lam`` > 0 is given.
@@ -209,7 +232,7 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
     vis = np.asarray(vis, np.complex128)
     if dirty is None:
         dirty = adjoint(uv, npix, fov_rad, vis)
-    lmax = float(np.max(np.abs(dirty)))
+    lmax = dual_scale_norm(dirty, positivity)
     if lam is None or lam <= 0:
         lam = alpha * lmax
     big_delta = (1.0 - delta) * lmax
@@ -222,14 +245,14 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
     p_prev = 0.5 * vv                               # P(x_0 = 0)
     log: List[IterLog] = []
     fit = np.zeros_like(vis)
-    gap0, _ = dual_gap(vis, vis, lmax, p_prev, lam)
+    gap0, _ = dual_gap(vis, vis, lmax, p_prev, lam)  # lmax is the scale at x = 0
     rel_gap = gap0 / p_prev if p_prev > 0 else 0.0
     converged = False
     k = 0
     for k in range(max_iter):
-        a = np.abs(eta).reshape(-1)
+        a = (eta if positivity else np.abs(eta)).reshape(-1)
         tau = float(a.max()) - 2.0 * big_delta / (k + 2)
-        new = np.flatnonzero(a >= tau)
+        new = np.flatnonzero((a >= tau) & (a > 0)) if positivity else np.flatnonzero(a >= tau)
         S_new = np.union1d(S, new)
         xw = np.zeros(S_new.size)
         if S.size:
@@ -237,14 +260,15 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
         gram.ensure(S_new)
         G = gram.sub(S_new)
         tol = max(inner_tol_min, inner_tol0 * rel_gap)
-        x, nin = fista_restricted(G, b_all[S_new], vv, lam, xw, tol, inner_max_iter)
+        x, nin = fista_restricted(G, b_all[S_new], vv, lam, xw, tol, inner_max_iter,
+                                  positive=positivity)
         keep = x != 0.0
         S, x = S_new[keep], x[keep]
         fit = forward(uv, npix, fov_rad, S, x)
         resid = vis - fit
         eta = adjoint(uv, npix, fov_rad, resid)
         p = objective(vis, fit, x, lam)
-        gap, _ = dual_gap(vis, resid, float(np.max(np.abs(eta))), p, lam)
+        gap, _ = dual_gap(vis, resid, dual_scale_norm(eta, positivity), p, lam)
         rel_gap = gap / p if p > 0 else 0.0
         rel_imp = abs(p - p_prev) / p_prev if p_prev > 0 else 0.0
         log.append(IterLog(k, int(S.size), int(new.size), float(a.max()), p, rel_gap, nin))

@@ -156,3 +156,123 @@ def test_stop_rules():
     assert r.converged
     objs = [it.objective for it in r.log]
     assert abs(objs[-1] - objs[-2]) / objs[-2] <= 1e-4
+
+
+# --- positivity (remarks on positivity in Sects. 3.1 and 5.1) ---------------
+
+def _mixed_problem(seed, L=200, n=8, fov=0.25):
+    """Sources of both signs, so that the positive solution differs from the
+    unconstrained one and the dirty residual goes well below -lambda."""
+    rng = np.random.default_rng(seed)
+    uv = rng.uniform(-12, 12, size=(L, 2))
+    pix = rng.choice(n * n, 4, replace=False)
+    amp = np.array([1.5, 1.0, -1.2, -0.8]) * np.exp(0.2 * rng.normal(size=4))
+    V = operator.forward(uv, n, fov, pix, amp)
+    V = V + 0.03 * np.max(np.abs(V)) * (rng.normal(size=L) + 1j * rng.normal(size=L))
+    return uv, n, fov, V
+
+
+def test_positive_prox():
+    z = np.array([-3.0, -1.0, 0.0, 0.5, 2.0])
+    assert np.array_equal(solver.soft(z, 1.0, positive=True), [0.0, 0.0, 0.0, 0.0, 1.0])
+    assert solver.dual_scale_norm(np.array([-5.0, 2.0]), positive=True) == 2.0
+    assert solver.dual_scale_norm(np.array([-5.0, -2.0]), positive=True) == 0.0
+    assert solver.dual_scale_norm(np.array([-5.0, 2.0])) == 5.0
+
+
+def test_positive_cd_matches_bounded_quasi_newton():
+    """The non-negative CD solver against scipy's L-BFGS-B on the smooth
+    bound-constrained form (for x >= 0, lam ||x||_1 = lam sum x)."""
+    from scipy.optimize import minimize
+    uv, n, fov, V = _mixed_problem(31, L=120, n=6)
+    A = brute.explicit_matrix(uv, n, fov)
+    y = np.concatenate([V.real, V.imag])
+    lam = 0.15 * float(np.max(A.T @ y))
+    x, obj, rel, _ = brute.lasso_cd(A, y, lam, positive=True)
+    assert np.all(x >= 0) and rel <= 1e-12
+
+    def f(z):
+        r = y - A @ z
+        return 0.5 * r @ r + lam * z.sum(), -(A.T @ r) + lam
+
+    q = minimize(f, np.zeros(A.shape[1]), jac=True, method="L-BFGS-B",
+                 bounds=[(0, None)] * A.shape[1],
+                 options=dict(ftol=1e-15, gtol=1e-12, maxiter=20000))
+    assert abs(q.fun - obj) <= 1e-8 * obj
+    assert np.linalg.norm(A @ q.x - A @ x) <= 1e-4 * np.linalg.norm(A @ x)
+
+
+def test_positive_orthogonal_design_closed_form():
+    """uv on the DFT frequencies => x_p = max((Phi*V)_p - lam, 0) n_p^2 / n^2
+    (the one-sided threshold), for the PFW and the CD solvers alike."""
+    n, fov = 8, 0.3
+    uv = sim.orthogonal_uv(n, fov)
+    rng = np.random.default_rng(13)
+    V = rng.normal(size=uv.shape[0]) + 1j * rng.normal(size=uv.shape[0])
+    b = operator.adjoint(uv, n, fov, V).reshape(-1)
+    res = solver.pfw_solve(uv, n, fov, V, alpha=0.3, delta=0.5, positivity=True, **TIGHT)
+    assert abs(res.lambda_max - np.max(b)) <= 1e-12 * np.max(b)
+    nn = geometry.n_term(n, fov).reshape(-1)
+    want = np.maximum(b - res.lam, 0.0) * nn ** 2 / n ** 2
+    got = np.zeros(n * n)
+    got[res.pix] = res.weight
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+    assert np.array_equal(res.pix, np.flatnonzero(want))
+    A = brute.explicit_matrix(uv, n, fov)
+    x, _, _, _ = brute.lasso_cd(A, np.concatenate([V.real, V.imag]), res.lam, positive=True)
+    assert np.allclose(x, want, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [40, 41])
+def test_positive_pfw_matches_coordinate_descent(seed):
+    uv, n, fov, V = _mixed_problem(seed)
+    res = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=0.9, positivity=True, **TIGHT)
+    A = brute.explicit_matrix(uv, n, fov)
+    y = np.concatenate([V.real, V.imag])
+    x, obj, rel, _ = brute.lasso_cd(A, y, res.lam, positive=True)
+    assert abs(res.objective - obj) <= 1e-9 * obj
+    fit_cd = A @ x
+    fit_fw = np.concatenate([res.fit.real, res.fit.imag])
+    assert np.linalg.norm(fit_fw - fit_cd) <= 1e-5 * np.linalg.norm(fit_cd)
+    # the constraint is active: the unconstrained optimum is lower
+    free = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=0.9, lam=res.lam, **TIGHT)
+    assert free.objective < res.objective * (1 - 1e-6)
+
+
+def test_positive_one_sided_kkt():
+    """x >= 0; mu <= 1 everywhere with mu = 1 on the support; mu is not
+    bounded below (it goes below -1 at the negative sources); and
+    max(eta) / lambda_max = alpha."""
+    uv, n, fov, V = _mixed_problem(42, L=220, n=10)
+    alpha = 0.08
+    res = solver.pfw_solve(uv, n, fov, V, alpha=alpha, delta=0.9, positivity=True, **TIGHT)
+    assert res.rel_gap <= 1e-12 and res.pix.size > 0
+    assert np.all(res.weight > 0)
+    mu = res.certificate.reshape(-1)
+    assert np.max(mu) <= 1 + 1e-6
+    assert np.allclose(mu[res.pix], 1.0, atol=1e-6, rtol=0)
+    assert np.min(mu) < -1.0
+    assert abs(np.max(res.eta) / res.lambda_max - alpha) <= 1e-6 * alpha
+
+
+def test_positive_lambda_above_lambda_max_gives_zero():
+    uv, n, fov, V = _mixed_problem(43)
+    res = solver.pfw_solve(uv, n, fov, V, alpha=1.0001, delta=0.9, max_iter=5,
+                           rel_gap_tol=1e-12, positivity=True)
+    assert res.pix.size == 0 and res.converged
+    dirty = operator.adjoint(uv, n, fov, V)
+    assert abs(res.lambda_max - np.max(dirty)) <= 1e-14 * np.max(dirty)
+
+
+def test_positive_exploration_takes_the_signed_maximum():
+    """delta = 1 with positivity: the first atom is the argmax of the dirty
+    image itself, even where its most negative value is larger in modulus."""
+    rng = np.random.default_rng(44)
+    n, fov, L = 8, 0.25, 160
+    uv = rng.uniform(-12, 12, size=(L, 2))
+    V = operator.forward(uv, n, fov, [10, 37], [0.6, -2.0])
+    dirty = operator.adjoint(uv, n, fov, V).reshape(-1)
+    assert -dirty.min() > dirty.max() > 0
+    r1 = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=1.0, max_iter=1, positivity=True)
+    assert r1.pix.tolist() == [int(np.argmax(dirty))]
+    assert r1.log[0].n_new == 1
