@@ -40,7 +40,8 @@ lambda_max = max(0, max_j (Phi* V)_j) (x = 0 is optimal exactly when
 Phi* V <= lambda everywhere); the exploration threshold uses eta itself in
 place of |eta| (and only eta > 0 qualifies); the proximal map is
 max(0, z - t); the dual point is scaled by the largest positive correlation
-max(0, max_j (Phi* r)_j), the one-sided dual constraint.
+max(0, max_j (Phi* r)_j), the one-sided dual constraint; the restricted gap
+is tested only at extrapolated points inside x >= 0.
 
 The restricted problem is solved with the exact normal matrix
 G_S = Re(Phi_S^H Phi_S) and b_S = Phi_S^* V, a different route from the GPU's
@@ -167,7 +168,9 @@ def fista_restricted(G: np.ndarray, b: np.ndarray, vv: float, lam: float, x0: np
     eigenvalue of G, and updates the momentum t+ = (1 + sqrt(1 + 4 t^2))/2,
     y+ = x+ + ((t - 1)/t+)(x+ - x).  It stops, returning x+, when the relative
     duality gap of the restricted problem at y is <= tol (x+ is then at least
-    as good as y) or after max_iter steps.  Returns (x, steps).
+    as good as y) or after max_iter steps.  Returns (x, steps).  With
+    ``positive`` the objective is +inf at an extrapolated y outside x >= 0, so
+    the test is taken only at a y >= 0 (x+ is feasible in any case).
     """
     if lip is None:
         lip = float(np.linalg.eigvalsh(G)[-1]) if G.size else 1.0
@@ -178,7 +181,7 @@ def fista_restricted(G: np.ndarray, b: np.ndarray, vv: float, lam: float, x0: np
     for it in range(1, max_iter + 1):
         p, gap, gy = restricted_gap(G, b, vv, lam, y, positive)
         xn = soft(y + gy / lip, lam / lip, positive)
-        if gap <= tol * p:
+        if gap <= tol * p and not (positive and np.any(y < 0)):
             return xn, it
         tn = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
         y = xn + ((t - 1.0) / tn) * (xn - x)
