@@ -250,7 +250,12 @@ typedef struct {
   double inner_tol_min;   /*   duality gap <= max(inner_tol_min, inner_tol0 g), */
                           /*   g = the full problem's relative gap at x_k     */
   int32_t inner_max_iter; /* APGD iteration cap per FW iteration              */
-  int32_t positivity;     /* must be 0 (positivity: PC_ERR_UNSUPPORTED)       */
+  int32_t positivity;     /* 1: x >= 0 (positivity remarks, Sects. 3.1, 5.1): */
+                          /*   lambda_max = max(0, max Phi* V), candidates    */
+                          /*   only where eta >= tau and eta > 0, the prox    */
+                          /*   max(0, z - t), the dual point scaled by the    */
+                          /*   largest positive correlation; cert_max is then */
+                          /*   max mu (mu may go below -1)                    */
   int32_t want_certificate; /* 1: write mu to result->cert                    */
   int32_t log_every;      /* > 0: print an iteration log line every n iters   */
   int32_t grid_atoms;     /* active-set size from which the APGD step applies */
@@ -276,8 +281,8 @@ typedef struct {
   double objective;       /* out: 1/2 ||V - Phi x||^2 + lambda ||x||_1         */
   double rel_gap;         /* out: relative duality gap at the returned x      */
   double lambda;          /* out: lambda used                                 */
-  double lambda_max;      /* out: ||Phi* V||_inf                              */
-  double cert_max;        /* out: ||mu||_inf                                  */
+  double lambda_max;      /* out: ||Phi* V||_inf (positivity: max(0, max))    */
+  double cert_max;        /* out: ||mu||_inf (positivity: max(0, max mu))     */
   int64_t cert_argmax;    /* out: lowest flat index attaining it              */
   int32_t iters;          /* out: FW iterations run                           */
   int32_t inner_iters;    /* out: total APGD iterations                       */

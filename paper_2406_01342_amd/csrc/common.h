@@ -134,6 +134,7 @@ struct AdjJob {
   const cpx<float>* tw;
   const float* corr;
   float scale;
+  int positive;  // max key of max(eta, 0) instead of |eta|
   unsigned long long* maxkey;
 };
 
@@ -186,6 +187,7 @@ struct pc_plan {
   void* corr = nullptr;         // real [n]: (-1)^a / psi(a), a = i - n/2
   // Small scratch.
   unsigned long long* maxkey = nullptr;  // packed (|x| bits, ~index)
+  int max_positive = 0;  // the key holds max(x, 0) in place of |x| (positivity-constrained solve)
   void* vis_scratch = nullptr;  // complex [L] in plan order (residual etc.)
   void* atom_scratch = nullptr; // per-atom staging
   size_t atom_capacity = 0;
@@ -307,6 +309,6 @@ int64_t adjoint_partial_stride(const pc_plan* p, int64_t natoms);
 // step; see kernels_dft.hip.
 void reduce_fista(pc_plan* p, int64_t nS, int64_t nwg, const double* partial, const double* g_in,
                   Atom<float>* atoms, double* x, double* y, double* g_out, double* stat,
-                  double inv_lip, double thr, double mom, hipStream_t s);
+                  double inv_lip, double thr, double mom, bool positive, hipStream_t s);
 
 }  // namespace pc

@@ -270,11 +270,13 @@ __global__ __launch_bounds__(256) void adjoint_sparse_reduce_kernel(
 //   x+ = soft(y + g / L, lambda / L),  y+ = x+ + mom (x+ - x),
 // with the new forward weight y+ / n_p.  stat[p] = |y_p| and
 // stat[nS + p] = |g_p| (at the gradient point) feed the duality-gap test.
+// Under positivity the prox is max(0, z - lambda / L), stat[p] = y_p (signed:
+// the test is skipped while some y_p < 0) and stat[nS + p] = max(g_p, 0).
 __global__ __launch_bounds__(256) void reduce_fista_kernel(
     int64_t nS, int64_t nwg, const float* __restrict__ partial, const double* __restrict__ g_in,
     Atom<float>* __restrict__ atoms, double* __restrict__ x, double* __restrict__ y,
     double* __restrict__ g_out, double* __restrict__ stat, double inv_lip, double thr,
-    double mom) {
+    double mom, int positive) {
   __shared__ double red[4];
   const int64_t p = blockIdx.x;
   double gp;
@@ -293,12 +295,17 @@ __global__ __launch_bounds__(256) void reduce_fista_kernel(
   if (threadIdx.x == 0) {
     const double yo = y[p], xo = x[p];
     const double z = yo + gp * inv_lip;
-    const double az = fabs(z) - thr;
-    const double xn = az > 0 ? copysign(az, z) : 0.0;
+    double xn;
+    if (positive) {
+      xn = z - thr > 0 ? z - thr : 0.0;
+    } else {
+      const double az = fabs(z) - thr;
+      xn = az > 0 ? copysign(az, z) : 0.0;
+    }
     const double yn = xn + mom * (xn - xo);
     g_out[p] = gp;
-    stat[p] = fabs(yo);
-    stat[nS + p] = fabs(gp);
+    stat[p] = positive ? yo : fabs(yo);
+    stat[nS + p] = positive ? fmax(gp, 0.0) : fabs(gp);
     x[p] = xn;
     y[p] = yn;
     atoms[p].w = (float)(yn * atoms[p].inv_n);
@@ -307,12 +314,12 @@ __global__ __launch_bounds__(256) void reduce_fista_kernel(
 
 void reduce_fista(pc_plan* p, int64_t nS, int64_t nwg, const double* partial, const double* g_in,
                   Atom<float>* atoms, double* x, double* y, double* g_out, double* stat,
-                  double inv_lip, double thr, double mom, hipStream_t s) {
+                  double inv_lip, double thr, double mom, bool positive, hipStream_t s) {
   if (nS <= 0) return;
   ProfScope ps(p, s, "reduce_fista", (double)sizeof(float) * nwg * nS + 64.0 * nS, (double)nS);
   hipLaunchKernelGGL(reduce_fista_kernel, dim3((unsigned)nS), dim3(256), 0, s, nS, nwg,
                      reinterpret_cast<const float*>(partial), g_in, atoms, x, y, g_out, stat,
-                     inv_lip, thr, mom);
+                     inv_lip, thr, mom, positive ? 1 : 0);
   PC_LAUNCH_CHECK("reduce_fista");
 }
 

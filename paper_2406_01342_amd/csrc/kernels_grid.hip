@@ -540,14 +540,15 @@ __device__ __forceinline__ unsigned long long max_key(float a, int idx) {
 }
 
 // Pass B of the adjoint: NB image rows i; FFT along v of H[:, i]; correction;
-// write image rows; fused max |eta| with lowest-index ties.
+// write image rows; fused max |eta| (max(eta, 0) with ``positive``, the
+// positivity-constrained solve) with lowest-index ties.
 template <typename R, int M, int NB, int NT>
 __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* __restrict__ H,
                                                R* __restrict__ image,
                                                const cpx<R>* __restrict__ tw,
                                                const R* __restrict__ corr, R scale,
                                                unsigned long long* __restrict__ maxkey,
-                                               int iblock) {
+                                               int positive, int iblock) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
@@ -633,7 +634,9 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
     }
     const R val = v.x * (corr[i] * scale) * corr[j] * inv_n;
     image[(size_t)i * n + j] = val;
-    const unsigned long long key = max_key((float)fabs(val), i * n + j);
+    // positive part: +0 for every val <= 0 (never -0, whose bits would win)
+    const float kv = positive ? (val > R(0) ? (float)val : 0.0f) : (float)fabs(val);
+    const unsigned long long key = max_key(kv, i * n + j);
     best = key > best ? key : best;
   };
   if constexpr (RAD0 <= 4) {
@@ -665,8 +668,9 @@ __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>*
                                                         R* __restrict__ image,
                                                         const cpx<R>* __restrict__ tw,
                                                         const R* __restrict__ corr, R scale,
-                                                        unsigned long long* __restrict__ maxkey) {
-  passB_adj_body<R, M, NB, NT>(g, H, image, tw, corr, scale, maxkey,
+                                                        unsigned long long* __restrict__ maxkey,
+                                                        int positive) {
+  passB_adj_body<R, M, NB, NT>(g, H, image, tw, corr, scale, maxkey, positive,
                                xcd_local(blockIdx.x, gridDim.x));
 }
 
@@ -675,7 +679,8 @@ __global__ __launch_bounds__(NT) void passB_batch_kernel(const AdjJob* __restric
                                                           const int2* __restrict__ items) {
   const int2 it = items[xcd_local(blockIdx.x, gridDim.x)];
   const AdjJob& J = jobs[it.x];
-  passB_adj_body<float, M, NB, NT>(J.g, J.H, J.image, J.tw, J.corr, J.scale, J.maxkey, it.y);
+  passB_adj_body<float, M, NB, NT>(J.g, J.H, J.image, J.tw, J.corr, J.scale, J.maxkey,
+                                   J.positive, it.y);
 }
 
 // Forward pass B^T: NB image rows i, pre-correct, FFT along v (sign -1),
@@ -909,7 +914,7 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s) {
   ProfScope ps(p, s, "passB_adj", nvn + (double)g.n * g.n * sizeof(R), (double)g.n * M);
   hipLaunchKernelGGL((passB_adj_kernel<R, M, NBB, NTB>), dim3((M / 2) / NBB), dim3(NTB), ldb, s, g,
                      (const cpx<R>*)p->H, image, (const cpx<R>*)p->twiddle, (const R*)p->corr,
-                     scale, p->maxkey);
+                     scale, p->maxkey, p->max_positive);
   PC_LAUNCH_CHECK("passB_adj");
 }
 
@@ -1129,6 +1134,7 @@ void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* 
     J.corr = (const float*)p->corr;
     J.scale = scales ? scales[j] : 1.0f;
     J.maxkey = p->maxkey;
+    J.positive = p->max_positive;
     for (int64_t c = 0; c < p->n_chunks; ++c)
       sitems.push_back({p->chunk_work[c], make_int2(j, (int)c)});
     for (int64_t f = 0; f < p->n_fold; ++f) fitems.push_back(make_int2(j, (int)f));

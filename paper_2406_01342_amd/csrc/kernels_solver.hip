@@ -70,14 +70,16 @@ __global__ __launch_bounds__(256) void resid_final_kernel(int nblocks,
   }
 }
 
-// Candidates {j : |eta_j| >= tau} (Alg. 2, step 1.a); order is fixed on the
+// Candidates {j : |eta_j| >= tau} (Alg. 2, step 1.a), or {j : eta_j >= tau,
+// eta_j > 0} under positivity (only positive maxima); order is fixed on the
 // host by sorting.
-__global__ void select_kernel(int64_t N, const float* __restrict__ eta, float tau,
+__global__ void select_kernel(int64_t N, const float* __restrict__ eta, float tau, int positive,
                               unsigned int* __restrict__ count, int32_t* __restrict__ out,
                               int64_t cap) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
-  if (fabsf(eta[j]) >= tau) {
+  const float e = eta[j];
+  if (positive ? (e >= tau && e > 0.0f) : fabsf(e) >= tau) {
     const unsigned int q = atomicAdd(count, 1u);
     if ((int64_t)q < cap) out[q] = (int32_t)j;
   }
@@ -152,20 +154,25 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
                                                          double* __restrict__ stats, double v2,
                                                          const double* __restrict__ lipd,
                                                          double mom, int check, int iter,
-                                                         double lam, double tol,
+                                                         double lam, double tol, int positive,
                                                          int* __restrict__ done) {
   __shared__ double sh[4];
   if (done[0]) return;  // uniform: every thread reads the same flag
   const double inv_lip = 1.0 / lipd[0], thr = lam * inv_lip;  // step constant from the device
-  double yGy = 0, yb = 0, yl1 = 0, gmax = 0;
+  // under positivity: ||y||_1 = sum y on x >= 0, yneg = max(0, -min y) > 0
+  // marks an extrapolated y outside it (objective +inf there: no test), and
+  // the dual scaling uses max(g, 0)
+  double yGy = 0, yb = 0, yl1 = 0, gmax = 0, yneg = 0;
   for (int64_t q = threadIdx.x; q < nS; q += 256) {
     const double s = gram_col_dot(G, y, nS, q);  // (G y)_q
     const double gq = b[q] - s;
+    const double yq = y[q];
     g_out[q] = gq;
-    yGy += y[q] * s;
-    yb += y[q] * b[q];
-    yl1 += fabs(y[q]);
-    gmax = fmax(gmax, fabs(gq));
+    yGy += yq * s;
+    yb += yq * b[q];
+    yl1 += positive ? yq : fabs(yq);
+    yneg = fmax(yneg, -yq);
+    gmax = fmax(gmax, positive ? gq : fabs(gq));
   }
   bool passed = false;
   if (check) {
@@ -173,11 +180,12 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
     yb = block_sum<256>(yb, sh);
     yl1 = block_sum<256>(yl1, sh);
     gmax = block_max<256>(gmax, sh);
+    yneg = block_max<256>(yneg, sh);
     const double r2 = v2 - 2.0 * yb + yGy, vr = v2 - yb;
     const double py = 0.5 * r2 + lam * yl1;
     const double sc = gmax <= lam ? 1.0 : lam / gmax;
     const double gy = py - (sc * vr - 0.5 * sc * sc * r2);
-    passed = gy <= tol * py;
+    passed = gy <= tol * py && !(positive && yneg > 0.0);
     if (threadIdx.x == 0) {
       stats[0] = r2;
       stats[1] = vr;
@@ -189,8 +197,13 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
   for (int64_t q = threadIdx.x; q < nS; q += 256) {
     const double yo = y[q], xo = x[q];
     const double z = yo + g_out[q] * inv_lip;
-    const double az = fabs(z) - thr;
-    const double xn = az > 0 ? copysign(az, z) : 0.0;
+    double xn;
+    if (positive) {
+      xn = z - thr > 0 ? z - thr : 0.0;
+    } else {
+      const double az = fabs(z) - thr;
+      xn = az > 0 ? copysign(az, z) : 0.0;
+    }
     x[q] = xn;
     y[q] = xn + mom * (xn - xo);
   }
@@ -451,21 +464,24 @@ __global__ void gather_img_kernel(int64_t nS, const int32_t* __restrict__ pix,
   if (a < nS) out[a] = (double)img[pix[a]];
 }
 
-// scal[kScalYL1] = sum_p stat[p], scal[kScalGmax] = max_p stat[nS + p]
-// (one workgroup, fixed order).
+// scal[kScalYL1] = sum_p stat[p], scal[kScalGmax] = max(0, max_p stat[nS + p]),
+// scal[kScalYNeg] = max(0, -min_p stat[p]) (one workgroup, fixed order).
 __global__ __launch_bounds__(1024) void stat_reduce_kernel(int64_t nS, const double* __restrict__ stat,
                                                            double* __restrict__ scal) {
   __shared__ double sh[16];
-  double l1 = 0, mx = 0;
+  double l1 = 0, mx = 0, neg = 0;
   for (int64_t p = threadIdx.x; p < nS; p += blockDim.x) {
     l1 += stat[p];
+    neg = fmax(neg, -stat[p]);
     mx = fmax(mx, stat[nS + p]);
   }
   l1 = block_sum<1024>(l1, sh);
   mx = block_max<1024>(mx, sh);
+  neg = block_max<1024>(neg, sh);
   if (threadIdx.x == 0) {
     scal[kScalYL1] = l1;
     scal[kScalGmax] = mx;
+    scal[kScalYNeg] = neg;
   }
 }
 
@@ -503,12 +519,12 @@ void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial,
   PC_LAUNCH_CHECK("resid_final");
 }
 
-void k_select(pc_plan* p, int64_t N, const float* eta, float tau, unsigned* count, int32_t* out, int64_t cap,
-              hipStream_t s) {
+void k_select(pc_plan* p, int64_t N, const float* eta, float tau, bool positive, unsigned* count,
+              int32_t* out, int64_t cap, hipStream_t s) {
   ProfScope ps(p, s, "select", 4.0 * N, (double)N);
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, count);
-  hipLaunchKernelGGL(select_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, eta, tau, count, out,
-                     cap);
+  hipLaunchKernelGGL(select_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, eta, tau,
+                     positive ? 1 : 0, count, out, cap);
   PC_LAUNCH_CHECK("select");
 }
 
@@ -521,10 +537,10 @@ void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const do
 
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
                   double* g, double* stats, double v2, const double* lipd, double mom, bool check,
-                  int iter, double lam, double tol, int* done, hipStream_t s) {
+                  int iter, double lam, double tol, bool positive, int* done, hipStream_t s) {
   ProfScope ps(p, s, "gram_fista", 8.0 * nS * (nS + 6), (double)nS * nS);
   hipLaunchKernelGGL(gram_fista_kernel, dim3(1), dim3(256), 0, s, nS, G, b, x, y, g, stats, v2,
-                     lipd, mom, check ? 1 : 0, iter, lam, tol, done);
+                     lipd, mom, check ? 1 : 0, iter, lam, tol, positive ? 1 : 0, done);
   PC_LAUNCH_CHECK("gram_fista");
 }
 

@@ -140,6 +140,15 @@ static double sym_top_eigen(std::vector<double>& A, int k, std::vector<double>& 
   return A[(size_t)best * k + best];
 }
 
+// The plan's fused maximum reports max(eta, 0) for the length of one of a
+// positivity-constrained solve's adjoints (a plan serves one solve at a time;
+// outside them it reports max |eta|).
+struct PositiveMax {
+  pc_plan* p;
+  PositiveMax(pc_plan* plan, bool on) : p(plan) { p->max_positive = on ? 1 : 0; }
+  ~PositiveMax() { p->max_positive = 0; }
+};
+
 struct Pfw {
   pc_plan* p;
   hipStream_t s;
@@ -180,12 +189,14 @@ struct Pfw {
   int k = 0, inner_total = 0;
   int64_t grid_thr = 0;  // active-set size from which APGD uses gridded operators
   bool done = false, converged = false;
+  bool positive = false;  // x >= 0: signed exploration, one-sided prox and dual scaling
   double adj_ms = 0;
   int adj_calls = 0;
   double t0 = 0;
 
   Pfw(pc_plan* plan, hipStream_t stream, const pc_solve_params& params)
-      : p(plan), s(stream), prm(params), L(plan->L), N((int64_t)plan->g.n * plan->g.n) {}
+      : p(plan), s(stream), prm(params), L(plan->L), N((int64_t)plan->g.n * plan->g.n),
+        positive(params.positivity != 0) {}
 
   static double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -193,6 +204,7 @@ struct Pfw {
   }
 
   void adjoint_timed(const c32* vis_sorted) {
+    PositiveMax pm(p, positive);
     if (batcher) {
       float ms = 0;
       batcher_adjoint(batcher, p, vis_sorted, eta.ptr, s, &eta_inf, &eta_argmax, &ms);
@@ -222,6 +234,7 @@ struct Pfw {
       residual_stats(r2, vr);
       return;
     }
+    PositiveMax pm(p, positive);
     PC_HIP(hipEventRecord(p->ev_a, s));
     adjoint_grid<float>(p, vis_sorted, true, eta.ptr, 1.0f, s);
     PC_HIP(hipEventRecord(p->ev_b, s));
@@ -252,9 +265,11 @@ struct Pfw {
   // Restricted duality gap at the gradient point y from the scalar block
   // ||r_y||^2, Re<V, r_y>, ||y||_1, max |g| (dual point scaled into the
   // feasible set); true when it is within tol of the restricted objective.
+  // Under positivity the objective is +inf at a y outside x >= 0: no pass.
   bool gap_test_passes(double tol) {
-    double h[4];
-    read_scal(h, kScalResid, 4);
+    double h[5];
+    read_scal(h, kScalResid, 5);
+    if (positive && h[4] > 0.0) return false;
     const double py = 0.5 * h[0] + lam * h[2];
     const double sc = h[3] <= lam ? 1.0 : lam / h[3];
     const double gy = py - (sc * h[1] - 0.5 * sc * sc * h[0]);
@@ -612,7 +627,7 @@ struct Pfw {
     unsigned count = 0;
     std::vector<int32_t> I;
     for (;;) {
-      k_select(p, N, eta.ptr, tau_f, cand_count.ptr, cand.ptr, cand.cap, s);
+      k_select(p, N, eta.ptr, tau_f, positive, cand_count.ptr, cand.ptr, cand.cap, s);
       const int64_t first = std::min<int64_t>(kFirst, cand.cap);
       unsigned char* h = (unsigned char*)down.get(4 + first * 4);
       PC_HIP(hipMemcpyAsync(h, cand_count.ptr, 4, hipMemcpyDeviceToHost, s));
@@ -686,7 +701,7 @@ struct Pfw {
             const double mom = (t - 1.0) / tn;
             t = tn;
             k_gram_fista(p, nS, gram_G, gram_b, x.ptr, y.ptr, g.ptr, scal.ptr + kScalResid,
-                         v2, lz_out.ptr, mom, (it - 1) % kCheck == 0, it, lam, tol,
+                         v2, lz_out.ptr, mom, (it - 1) % kCheck == 0, it, lam, tol, positive,
                          gram_done.ptr, s);
           }
           // outcome, x, and the Lanczos result with its Ritz vector
@@ -728,11 +743,11 @@ struct Pfw {
             if (!fused)
               adjoint_atoms<float>(p, r.ptr, true, nS, atoms.ptr, adj_partial.ptr, nullptr, s);
             reduce_fista(p, nS, nwg, adj_partial.ptr, nullptr, atoms.ptr, x.ptr, y.ptr, g.ptr,
-                         stat.ptr, 1.0 / lip, lam / lip, mom, s);
+                         stat.ptr, 1.0 / lip, lam / lip, mom, positive, s);
           } else {
             op_adjoint(true, nS, r.ptr, g.ptr);
             reduce_fista(p, nS, 0, nullptr, g.ptr, atoms.ptr, x.ptr, y.ptr, g.ptr, stat.ptr,
-                         1.0 / lip, lam / lip, mom, s);
+                         1.0 / lip, lam / lip, mom, positive, s);
           }
           if (check) {
             k_stat_reduce(p, nS, stat.ptr, scal.ptr, s);
@@ -814,7 +829,6 @@ struct Pfw {
 
 static void check_params(const pc_solve_params* prm) {
   PC_REQUIRE(prm != nullptr, "params is NULL");
-  if (prm->positivity != 0) fail(PC_ERR_UNSUPPORTED, "positivity-constrained solve is not built");
   PC_REQUIRE(prm->max_iter >= 1, "max_iter must be >= 1");
   PC_REQUIRE(prm->delta > 0 && prm->delta <= 1, "delta must be in (0, 1]");
   PC_REQUIRE(prm->lambda > 0 || (prm->alpha > 0 && std::isfinite(prm->alpha)),

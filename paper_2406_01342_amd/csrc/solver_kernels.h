@@ -9,15 +9,16 @@ namespace pc {
 enum : int {
   kScalResid = 0,  // [0] ||r||^2, [1] Re<V, r>
   kScalYL1 = 2,    // ||y||_1 at the gradient point of the last APGD step
-  kScalGmax = 3,   // max_p |(Phi_S^* r)_p| there
-  kScalCount = 4
+  kScalGmax = 3,   // max_p |(Phi_S^* r)_p| there (max(0, max_p (.)_p) under positivity)
+  kScalYNeg = 4,   // max(0, -min_p y_p): > 0 when y lies outside x >= 0
+  kScalCount = 5
 };
 
 void k_gather(pc_plan* p, int64_t L, const int32_t* perm, const c32* in, c32* out, hipStream_t s);
 int k_resid_blocks(int64_t L);
 void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial, double* out, hipStream_t s);
-void k_select(pc_plan* p, int64_t N, const float* eta, float tau, unsigned* count, int32_t* out, int64_t cap,
-              hipStream_t s);
+void k_select(pc_plan* p, int64_t N, const float* eta, float tau, bool positive, unsigned* count,
+              int32_t* out, int64_t cap, hipStream_t s);
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s);
 // One Lanczos step (see lanczos_step_kernel): g = G q_j given; writes alpha_j,
 // beta_j into ab and q_{j+1} into row j + 1 of Q.
@@ -28,7 +29,7 @@ void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipSt
 // optionally with the in-kernel duality-gap test.
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
                   double* g, double* stats, double v2, const double* lipd, double mom, bool check,
-                  int iter, double lam, double tol, int* done, hipStream_t s);
+                  int iter, double lam, double tol, bool positive, int* done, hipStream_t s);
 // The Gram form's Lanczos estimate with its stopping rule on the device: out =
 // {step constant, steps, theta, rho}, ritz = the top Ritz vector.
 // The basis and scratch live in LDS (G too for up to ~120 atoms): at most

@@ -209,13 +209,98 @@ def test_capacity_error_reports_required_size():
     assert e.value.status == -4
 
 
-def test_positivity_unsupported():
+def _mixed_sign_c1():
+    """C1's array and sky with its second-brightest-listed source negated:
+    the positive solution then differs widely from the unconstrained one and
+    the certificate goes far below -1 there."""
+    p, _ = problem("c1")
+    amp = p.sky_amp.copy()
+    amp[1] = -amp[1]
+    vclean = operator.forward(p.uv, p.npix, p.fov_rad, p.sky_pix, amp)
+    return p, sim.add_noise(vclean, p.noise, p.psnr_db).astype(np.complex64)
+
+
+def _check_positive(p, vis, res, cert, ref, fit_tol=1e-3):
+    assert res["converged"] == 1
+    assert abs(res["objective"] - ref.objective) <= 1e-3 * ref.objective
+    assert abs(res["lambda_max"] - ref.lambda_max) <= 1e-4 * ref.lambda_max
+    assert np.all(res["weight"] > 0)
+    fit = _fit(p, res["pix"], res["weight"])
+    assert rel_l2(fit, ref.fit) <= fit_tol
+    assert rel_l2(cert, ref.certificate) <= fit_tol
+    # one-sided: max mu = 1 (to 1e-3), reached on the oracle's saturation set
+    mu = ref.certificate.reshape(-1)
+    assert res["cert_max"] <= 1 + 1e-3 and res["cert_max"] >= 1 - 1e-3
+    assert mu[res["cert_argmax"]] >= 1 - 1e-3
+    p_or = solver.objective(vis.astype(np.complex128), fit, res["weight"], res["lambda"])
+    assert abs(p_or - res["objective"]) <= 1e-4 * p_or
+
+
+@pytest.mark.parametrize("gram", [0, -1])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_positive_solve_c1_matches_oracle(gram, mixed):
+    """Positivity-constrained solve (remarks on positivity, Sects. 3.1 and
+    5.1) against the oracle's, on C1's sky and on a mixed-sign sky."""
+    say("positive solve c1, mixed", mixed, "gram_atoms", gram)
+    p, vis = _mixed_sign_c1() if mixed else problem("c1")
+    kw = dict(alpha=p.alpha, delta=p.delta, max_iter=300, rel_gap_tol=1e-5)
+    plan, res, cert = _gpu_solve(p, vis, gram_atoms=gram, positivity=1, **kw)
+    ref = _oracle_solve(p, vis, positivity=True, **kw)
+    say("gpu", res["objective"], res["rel_gap"], res["iters"], res["natoms"],
+        "oracle", ref.objective, ref.rel_gap, ref.iters, ref.pix.size)
+    _check_positive(p, vis, res, cert, ref)
+    # the constraint is active in both: mu < -1 somewhere, and the
+    # unconstrained optimum is lower
+    assert ref.certificate.min() < -1.0 and cert.min() < -1.0
+    free = _oracle_solve(p, vis, lam=ref.lam, **kw)
+    assert free.objective < ref.objective * (1 - 1e-4)
+
+
+def test_positive_solve_gridded_apgd_matches_oracle():
+    say("positive solve gridded")
+    p, vis = _mixed_sign_c1()
+    kw = dict(alpha=p.alpha, delta=p.delta, max_iter=300, rel_gap_tol=1e-4)
+    plan, res, cert = _gpu_solve(p, vis, grid_atoms=8, positivity=1, **kw)
+    ref = _oracle_solve(p, vis, positivity=True, **kw)
+    say("gpu", res["objective"], res["rel_gap"], res["iters"], res["natoms"],
+        "oracle", ref.objective, ref.rel_gap, ref.iters, ref.pix.size)
+    _check_positive(p, vis, res, cert, ref, fit_tol=1e-2)
+
+
+def test_positive_solve_orthogonal_closed_form():
+    """uv on the DFT frequencies: x_p = max((Phi* V)_p - lam, 0) n_p^2 / n^2."""
+    say("positive solve orthogonal")
+    n, fov = 32, 0.3
+    uv = sim.orthogonal_uv(n, fov)
+    rng = np.random.default_rng(22)
+    V = (rng.normal(size=uv.shape[0]) + 1j * rng.normal(size=uv.shape[0])).astype(np.complex64)
+    a = api()
+    plan = a.pc_plan_create(uv, n, fov)
+    res = a.pc_polyclean_solve(plan, to_dev(V), alpha=0.5, delta=0.5, max_iter=100,
+                               rel_gap_tol=1e-7, positivity=1)
+    b = operator.adjoint(uv, n, fov, V.astype(np.complex128)).reshape(-1)
+    assert abs(res["lambda_max"] - b.max()) <= 1e-5 * b.max()
+    nn = geometry.n_term(n, fov).reshape(-1)
+    want = np.maximum(b - res["lambda"], 0.0) * nn ** 2 / n ** 2
+    got = np.zeros(n * n)
+    got[res["pix"]] = res["weight"]
+    assert rel_l2(got, want) <= 1e-4
+    assert set(res["pix"].tolist()) == set(np.flatnonzero(want).tolist())
+
+
+def test_positive_flag_is_scoped_to_the_solve():
+    """After a positive solve the plan's adjoint reports max |eta| again
+    (visibilities negated, so that the dirty image's peak is negative)."""
     p, vis = problem("c1")
+    vis = -vis
     a = api()
     plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
-    with pytest.raises(a.PolycleanError) as e:
-        a.pc_polyclean_solve(plan, to_dev(vis), positivity=1)
-    assert e.value.status == -5
+    a.pc_polyclean_solve(plan, to_dev(vis), alpha=p.alpha, delta=p.delta, max_iter=3,
+                         positivity=1)
+    img, mx, am = a.pc_adjoint_grid(plan, to_dev(vis))
+    dirty = np.abs(img.cpu().numpy()).reshape(-1)
+    assert dirty.max() > 1.05 * img.cpu().numpy().max()  # the peak is negative here
+    assert mx == float(dirty.max()) and am == int(np.argmax(dirty))
 
 
 @pytest.mark.slow
