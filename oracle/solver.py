@@ -43,6 +43,12 @@ max(0, z - t); the dual point is scaled by the largest positive correlation
 max(0, max_j (Phi* r)_j), the one-sided dual constraint; the restricted gap
 is tested only at extrapolated points inside x >= 0.
 
+Synthesis dictionary (Sect. 3.2, Eq. lasso-synthesis): with ``dictionary``
+(see dictionary.py) the atoms are the columns of Phi Psi, indexed s N + p;
+eta is replaced by Psi* eta (one image per scale), lambda_max by
+||Psi* Phi* V||_inf, and the restricted normal matrix is formed from the
+atoms' visibility columns Phi(g_s centred on p).
+
 The restricted problem is solved with the exact normal matrix
 G_S = Re(Phi_S^H Phi_S) and b_S = Phi_S^* V, a different route from the GPU's
 operator applications that computes the same mathematics.
@@ -54,6 +60,7 @@ from typing import List, Optional
 
 import numpy as np
 
+from . import dictionary as dic
 from .geometry import pixel_coords
 from .operator import adjoint, forward
 
@@ -144,6 +151,33 @@ class GramCache:
         return self.G[np.ix_(idx, idx)]
 
 
+class DictGramCache:
+    """G = Re(A_S^H A_S) for synthesis atoms, A_a = Phi(Psi e_a) computed by
+    the exact forward over the element's (cropped) pixels; columns are kept
+    per atom."""
+
+    def __init__(self, uv, npix: int, fov_rad: float, dictionary):
+        self.uv, self.npix, self.fov, self.dictionary = uv, npix, fov_rad, dictionary
+        self.cols = {}
+
+    def column(self, a: int) -> np.ndarray:
+        if a not in self.cols:
+            s, p = dic.split_atoms([a], self.npix)
+            pix, val = dic.element_pixels(self.dictionary[int(s[0])], int(p[0]), self.npix)
+            self.cols[a] = forward(self.uv, self.npix, self.fov, pix, val)
+        return self.cols[a]
+
+    def ensure(self, atoms):
+        for a in np.asarray(atoms, np.int64):
+            self.column(int(a))
+
+    def sub(self, atoms) -> np.ndarray:
+        if len(atoms) == 0:
+            return np.zeros((0, 0))
+        C = np.stack([self.column(int(a)) for a in atoms], axis=1)
+        return (C.conj().T @ C).real
+
+
 def restricted_gap(G: np.ndarray, b: np.ndarray, vv: float, lam: float, y: np.ndarray,
                    positive: bool = False):
     """(P_S(y), gap) of the LASSO restricted to S at y, from the normal
@@ -210,7 +244,7 @@ class SolveResult:
     lambda_max: float
     iters: int
     converged: bool
-    eta: np.ndarray          # final dirty residual Phi*(V - Phi x), (n, n)
+    eta: np.ndarray          # final dirty residual Phi*(V - Phi x), (n, n); (S, n, n) = Psi* of it with a dictionary
     fit: np.ndarray          # Phi x, (L,)
     log: List[IterLog]
 
@@ -224,7 +258,8 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
               max_iter: int = 50, rel_obj_tol: float = 0.0,
               rel_gap_tol: float = 0.0, inner_tol0: float = 1e-1,
               inner_tol_min: float = 1e-8, inner_max_iter: int = 2000,
-              dirty: Optional[np.ndarray] = None, positivity: bool = False) -> SolveResult:
+              dirty: Optional[np.ndarray] = None, positivity: bool = False,
+              dictionary=None) -> SolveResult:
     """Polyatomic Frank-Wolfe for the point-source LASSO (Alg. 2).
 
     ``alpha`` sets lambda = alpha * lambda_max unless ``lam`` > 0 is given.
@@ -235,11 +270,14 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
     vis = np.asarray(vis, np.complex128)
     if dirty is None:
         dirty = adjoint(uv, npix, fov_rad, vis)
+    if dictionary is not None:                      # Psi* Phi* V, one image per scale
+        dirty = dic.analysis(dirty, dictionary)
     lmax = dual_scale_norm(dirty, positivity)
     if lam is None or lam <= 0:
         lam = alpha * lmax
     big_delta = (1.0 - delta) * lmax
-    gram = GramCache(uv, npix, fov_rad)
+    gram = (GramCache(uv, npix, fov_rad) if dictionary is None
+            else DictGramCache(uv, npix, fov_rad, dictionary))
     b_all = dirty.reshape(-1)                       # Phi_S^* V = dirty image on S
     S = np.zeros(0, np.int64)
     x = np.zeros(0)
@@ -267,9 +305,16 @@ def pfw_solve(uv, npix: int, fov_rad: float, vis, *, alpha: float = 0.01,
                                   positive=positivity)
         keep = x != 0.0
         S, x = S_new[keep], x[keep]
-        fit = forward(uv, npix, fov_rad, S, x)
+        if dictionary is None:
+            fit = forward(uv, npix, fov_rad, S, x)
+        else:
+            img = dic.synthesis(S, x, dictionary, npix).reshape(-1)
+            nz = np.flatnonzero(img)
+            fit = forward(uv, npix, fov_rad, nz, img[nz])
         resid = vis - fit
         eta = adjoint(uv, npix, fov_rad, resid)
+        if dictionary is not None:
+            eta = dic.analysis(eta, dictionary)
         p = objective(vis, fit, x, lam)
         gap, _ = dual_gap(vis, resid, dual_scale_norm(eta, positivity), p, lam)
         rel_gap = gap / p if p > 0 else 0.0
