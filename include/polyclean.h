@@ -237,6 +237,19 @@ PC_API pc_status pc_adjoint_grid_batch(pc_plan* const* plans, const void* const*
                                        int64_t* argmax, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Adjoint of the synthesis form (Sect. 3.2, Eq. lasso-synthesis): images =
+ * Psi* Phi* vis for the Gaussian dictionary described at pc_solve_params
+ * (n_scales in [1, 8], sigma / gamma host arrays of n_scales doubles).
+ * vis: dev complex64 [nvis] caller order; images: dev float
+ * [n_scales][npix][npix].  max_abs / argmax (host, or NULL): max over all
+ * scales and pixels and the lowest flat index s npix^2 + p attaining it.
+ * FP32 plans.  Returns PC_ERR_INVALID for bad scales.
+ * ------------------------------------------------------------------------- */
+PC_API pc_status pc_adjoint_grid_ms(pc_plan* plan, const void* vis, int32_t n_scales,
+                                    const double* sigma, const double* gamma, float* images,
+                                    double* max_abs, int64_t* argmax, void* stream);
+
+/* ---------------------------------------------------------------------------
  * PolyCLEAN solve (Alg. 2)
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -270,11 +283,25 @@ typedef struct {
                           /*   offsets) and b = Phi_S* V replace the two      */
                           /*   operators in each APGD and Lanczos step: 0 =   */
                           /*   256, < 0 = never, at most 1024.                */
+  int32_t n_scales;       /* 0: point atoms (Eq. lasso).  1..8: the synthesis */
+                          /*   form (Sect. 3.2, Eq. lasso-synthesis) over the */
+                          /*   Gaussian dictionary of Sect. 6.4: element s is */
+                          /*   gamma_s g~_s, g~_s[a,b] ~ exp(-(a^2+b^2)/      */
+                          /*   sigma_s^2) for |a|,|b| <= floor(2 sigma_s),    */
+                          /*   unit l1 norm (sigma_s = 0: one pixel), cropped */
+                          /*   at the image border.  Atoms are s npix^2 + p;  */
+                          /*   lambda_max = ||Psi* Phi* V||_inf; result->cert */
+                          /*   then holds n_scales npix^2 floats (Psi* eta /  */
+                          /*   lambda).  The restricted problem always runs   */
+                          /*   through the gridded operators.                 */
+  double scale_sigma[8];  /* sigma_s in pixels, in [0, 16] (paper: 0, 2, 5, 8) */
+  double scale_gamma[8];  /* gamma_s > 0 (paper: 1.2^s)                       */
 } pc_solve_params;
 
 typedef struct {
   int64_t capacity;       /* in: length of pix/weight                         */
   int32_t* pix;           /* in: host int32 [capacity]; out: active atoms     */
+                          /*   (pixels, or s npix^2 + p with a dictionary)    */
   double* weight;         /* in: host double [capacity]; out: their weights   */
   float* cert;            /* in: dev float [npix^2] or NULL                   */
   int64_t natoms;         /* out: atoms in the solution (required if CAPACITY) */
@@ -293,7 +320,8 @@ typedef struct {
 } pc_solve_result;
 
 /* Fill params with the defaults: alpha 0.01, delta 0.99, max_iter 50,
- * tolerances off, inner_tol0 0.1, inner_tol_min 1e-8, inner_max_iter 2000. */
+ * tolerances off, inner_tol0 0.1, inner_tol_min 1e-8, inner_max_iter 2000,
+ * point atoms (n_scales 0). */
 PC_API void pc_solve_params_default(pc_solve_params* params);
 
 /* Solve the LASSO for the visibilities `vis` (dev complex64 [nvis], caller

@@ -55,6 +55,24 @@ def forward_dense(uv, npix: int, fov_rad: float, image) -> np.ndarray:
     return forward(uv, npix, fov_rad, pix, image.reshape(-1)[pix])
 
 
+def forward_images(uv, npix: int, fov_rad: float, images) -> np.ndarray:
+    """Phi applied to k dense images at once: images (n^2, k) real, flat
+    pixel p = i n + j; returns (L, k) complex128.  The definition of
+    Eq. phi-discrete as one matrix product per chunk of visibilities."""
+    u, v = _as_uv(uv)
+    images = np.asarray(images, np.float64).reshape(npix * npix, -1)
+    l = direction_cosines(npix, fov_rad)
+    li = np.repeat(l, npix)
+    mj = np.tile(l, npix)
+    inv_n = 1.0 / n_term(npix, fov_rad).reshape(-1)
+    out = np.zeros((u.shape[0], images.shape[1]), dtype=np.complex128)
+    step = max(1, _CHUNK_ELEMS // (npix * npix))
+    for s in range(0, u.shape[0], step):
+        e = np.exp(-2j * np.pi * (np.outer(u[s:s + step], li) + np.outer(v[s:s + step], mj)))
+        out[s:s + step] = (e * inv_n[None, :]) @ images
+    return out
+
+
 def adjoint(uv, npix: int, fov_rad: float, h) -> np.ndarray:
     """Phi* h as an (n, n) float64 image (Eq. adjoint-phi), all pixels."""
     u, v = _as_uv(uv)

@@ -62,7 +62,7 @@ import numpy as np
 
 from . import dictionary as dic
 from .geometry import pixel_coords
-from .operator import adjoint, forward
+from .operator import adjoint, forward, forward_images
 
 _CHUNK_ELEMS = 1 << 22
 
@@ -162,14 +162,21 @@ class DictGramCache:
 
     def column(self, a: int) -> np.ndarray:
         if a not in self.cols:
-            s, p = dic.split_atoms([a], self.npix)
-            pix, val = dic.element_pixels(self.dictionary[int(s[0])], int(p[0]), self.npix)
-            self.cols[a] = forward(self.uv, self.npix, self.fov, pix, val)
+            self.ensure([a])
         return self.cols[a]
 
     def ensure(self, atoms):
-        for a in np.asarray(atoms, np.int64):
-            self.column(int(a))
+        new = sorted({int(a) for a in np.asarray(atoms, np.int64)} - set(self.cols))
+        if not new:
+            return
+        W = np.zeros((self.npix * self.npix, len(new)))   # Psi e_a, one image per atom
+        for c, a in enumerate(new):
+            s, p = dic.split_atoms([a], self.npix)
+            pix, val = dic.element_pixels(self.dictionary[int(s[0])], int(p[0]), self.npix)
+            W[pix, c] = val
+        cols = forward_images(self.uv, self.npix, self.fov, W)
+        for c, a in enumerate(new):
+            self.cols[a] = cols[:, c]
 
     def sub(self, atoms) -> np.ndarray:
         if len(atoms) == 0:

@@ -48,7 +48,9 @@ class PcSolveParams(C.Structure):
                 ("inner_tol0", C.c_double), ("inner_tol_min", C.c_double),
                 ("inner_max_iter", C.c_int32), ("positivity", C.c_int32),
                 ("want_certificate", C.c_int32), ("log_every", C.c_int32),
-                ("grid_atoms", C.c_int32), ("gram_atoms", C.c_int32)]
+                ("grid_atoms", C.c_int32), ("gram_atoms", C.c_int32),
+                ("n_scales", C.c_int32), ("scale_sigma", C.c_double * 8),
+                ("scale_gamma", C.c_double * 8)]
 
 
 class PcSolveResult(C.Structure):
@@ -90,6 +92,7 @@ SIGNATURES = {
     "pc_dual_certificate": (C.c_int, [_P, _P, _I64, _P, _P, C.c_double, _P, _PD, _PI64, _P]),
     "pc_restricted_gradient": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P]),
     "pc_adjoint_grid_f64": (C.c_int, [_P, _P, _P, _PD, _PI64, _P]),
+    "pc_adjoint_grid_ms": (C.c_int, [_P, _P, C.c_int32, _PD, _PD, _P, _PD, _PI64, _P]),
     "pc_forward_sparse_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P]),
     "pc_adjoint_sparse_f64": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
     "pc_dual_certificate_f64": (C.c_int, [_P, _P, _I64, _P, _P, C.c_double, _P, _PD, _PI64, _P]),

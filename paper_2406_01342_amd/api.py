@@ -133,6 +133,30 @@ def pc_adjoint_grid(plan: Plan, vis: torch.Tensor, image: Optional[torch.Tensor]
     return image, (mx.value if want_max else None), (am.value if want_max else None)
 
 
+def pc_adjoint_grid_ms(plan: Plan, vis: torch.Tensor, sigma, gamma,
+                       images: Optional[torch.Tensor] = None, want_max: bool = True, stream=None):
+    """Psi* Phi* vis for the Gaussian synthesis dictionary (Sect. 3.2) ->
+    (images [S, n, n] float32, max|.| or None, flat argmax s n^2 + p or None)."""
+    n = plan.npix
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    gam = np.ascontiguousarray(gamma, dtype=np.float64)
+    if sig.shape != gam.shape or sig.ndim != 1:
+        raise ValueError("sigma and gamma must be 1-D of equal length")
+    S = int(sig.size)
+    if images is None:
+        images = _new(plan, (S, n, n), torch.float32)
+    mx, am = C.c_double(0), C.c_int64(-1)
+    check(LIB.pc_adjoint_grid_ms(plan.handle,
+                                 C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")), S,
+                                 sig.ctypes.data_as(C.POINTER(C.c_double)),
+                                 gam.ctypes.data_as(C.POINTER(C.c_double)),
+                                 C.c_void_p(_dev(images, torch.float32, S * n * n, "images")),
+                                 C.byref(mx) if want_max else None,
+                                 C.byref(am) if want_max else None,
+                                 C.c_void_p(_stream(stream))), "pc_adjoint_grid_ms")
+    return images, (mx.value if want_max else None), (am.value if want_max else None)
+
+
 def pc_adjoint_grid_f64(plan: Plan, vis: torch.Tensor, image: Optional[torch.Tensor] = None,
                         want_max: bool = True, stream=None):
     n = plan.npix
@@ -292,8 +316,19 @@ def pc_adjoint_grid_batch(plans, vis, images=None, want_max: bool = True, stream
 
 
 def solve_params(**kw) -> PcSolveParams:
+    """Defaults plus keyword fields; ``scales=(sigmas, gammas)`` sets the
+    synthesis dictionary (n_scales, scale_sigma, scale_gamma)."""
     p = PcSolveParams()
     LIB.pc_solve_params_default(C.byref(p))
+    scales = kw.pop("scales", None)
+    if scales is not None:
+        sig, gam = (list(map(float, a)) for a in scales)
+        if len(sig) != len(gam) or not 1 <= len(sig) <= 8:
+            raise ValueError("scales: 1 to 8 (sigma, gamma) pairs")
+        p.n_scales = len(sig)
+        for i, (a, b) in enumerate(zip(sig, gam)):
+            p.scale_sigma[i] = a
+            p.scale_gamma[i] = b
     for k, v in kw.items():
         key = "lambda_" if k in ("lam", "lambda") else k
         if not hasattr(p, key):
@@ -317,7 +352,8 @@ def pc_polyclean_solve(plan: Plan, vis: torch.Tensor, params: Optional[PcSolvePa
     res.capacity = capacity
     res.pix = pix.ctypes.data_as(C.POINTER(C.c_int32))
     res.weight = wgt.ctypes.data_as(C.POINTER(C.c_double))
-    res.cert = C.c_void_p(_dev(cert, torch.float32, n * n, "cert")) if cert is not None else None
+    ncert = n * n * max(1, params.n_scales)  # Psi* eta / lambda with a dictionary
+    res.cert = C.c_void_p(_dev(cert, torch.float32, ncert, "cert")) if cert is not None else None
     st = LIB.pc_polyclean_solve(plan.handle, C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")),
                                 C.byref(params), C.byref(res), C.c_void_p(_stream(stream)))
     check(st, "pc_polyclean_solve")
@@ -377,6 +413,7 @@ class Solver:
         elif kw:
             raise ValueError("pass either params or keyword parameters")
         self.plan = plan
+        self.n_scales = params.n_scales
         h = C.c_void_p()
         dv = C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis"))
         if batcher is None:
@@ -398,8 +435,9 @@ class Solver:
         return self.done
 
     def result(self, capacity: int = 65536, cert: Optional[torch.Tensor] = None) -> dict:
-        """Current iterate; `cert` (device float [n, n]) receives the dual
-        certificate when the solver was created with want_certificate=1."""
+        """Current iterate; `cert` (device float [n, n], [S, n, n] with a
+        dictionary) receives the dual certificate when the solver was created
+        with want_certificate=1."""
         pix = np.zeros(capacity, dtype=np.int32)
         wgt = np.zeros(capacity, dtype=np.float64)
         res = PcSolveResult()
@@ -407,7 +445,8 @@ class Solver:
         res.pix = pix.ctypes.data_as(C.POINTER(C.c_int32))
         res.weight = wgt.ctypes.data_as(C.POINTER(C.c_double))
         n = self.plan.npix
-        res.cert = C.c_void_p(_dev(cert, torch.float32, n * n, "cert")) if cert is not None else None
+        ncert = n * n * max(1, self.n_scales)
+        res.cert = C.c_void_p(_dev(cert, torch.float32, ncert, "cert")) if cert is not None else None
         st = LIB.pc_solver_result(self._h, C.byref(res))
         check(st, "pc_solver_result")
         return _result_dict(res, st, pix, wgt)

@@ -124,6 +124,26 @@ pc_status pc_adjoint_grid(pc_plan* p, const void* vis, float* image, double* max
   });
 }
 
+pc_status pc_adjoint_grid_ms(pc_plan* p, const void* vis, int32_t n_scales, const double* sigma,
+                             const double* gamma, float* images, double* max_abs,
+                             int64_t* argmax, void* stream) {
+  return guard("pc_adjoint_grid_ms", [&] {
+    check_plan(p, PC_PREC_FP32);
+    PC_REQUIRE(vis != nullptr && images != nullptr, "vis and images must not be NULL");
+    const DictSpec D = make_dict(n_scales, sigma, gamma);
+    PC_REQUIRE((int64_t)D.S * p->g.n * p->g.n < ((int64_t)1 << 31),
+               "n_scales * npix^2 must be < 2^31");
+    set_device(p);
+    hipStream_t s = (hipStream_t)stream;
+    // Phi* vis into the first image (read whole by the row pass before the
+    // column pass writes any scale), then Psi*
+    adjoint_grid<float>(p, (const c32*)vis, false, images, 1.0f, s);
+    dict_analysis(p, D, images, images, false, p->maxkey, s);
+    if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
+    return PC_OK;
+  });
+}
+
 pc_status pc_adjoint_grid_f64(pc_plan* p, const void* vis, double* image, double* max_abs,
                               int64_t* argmax, void* stream) {
   return guard("pc_adjoint_grid_f64", [&] {

@@ -193,6 +193,8 @@ struct pc_plan {
   size_t atom_capacity = 0;
   double* red_scratch = nullptr;  // reduction partials
   size_t red_capacity = 0;
+  void* dict_scratch = nullptr;   // synthesis-dictionary row pass [S][n][n] float
+  size_t dict_capacity = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   pc::Prof prof;
   std::vector<int32_t> chunk_work;  // host copy: visibilities per spreading item
@@ -221,6 +223,35 @@ void* dalloc(pc_plan* p, size_t bytes);
 void plan_release(pc_plan* p);
 void* ensure_atom_scratch(pc_plan* p, size_t bytes);
 double* ensure_red_scratch(pc_plan* p, size_t count);
+float* ensure_dict_scratch(pc_plan* p, size_t count);
+
+// Synthesis dictionary of Gaussian elements (Sect. 3.2; the elements of
+// Sect. 6.4): g_s[a][b] = gamma_s t_s[a] t_s[b], t_s the unit-sum 1-D
+// Gaussian taps exp(-a^2 / sigma_s^2) of half-width h_s = floor(2 sigma_s)
+// (h_s = 0, t = {1}: a single pixel).  Passed to kernels by value.
+constexpr int kDictMaxScales = 8;
+constexpr int kDictMaxHalf = 32;  // sigma <= 16
+constexpr int kDictMaxTaps = 2 * kDictMaxHalf + 1;
+struct DictSpec {
+  int S;
+  int h[kDictMaxScales];
+  float gamma[kDictMaxScales];
+  float taps[kDictMaxScales][kDictMaxTaps];
+};
+// Validates sigma/gamma (fails with PC_ERR_INVALID) and fills the taps in FP64
+// rounded once to FP32.
+DictSpec make_dict(int n_scales, const double* sigma, const double* gamma);
+// out[s][i][j] = sum_{a,b} g_s[a][b] img[i + a][j + b] (zero outside), the
+// adjoint of the cropped synthesis, with the fused maximum key of |out| (of
+// max(out, 0) with positive) over the flat index s n^2 + i n + j in *key.
+void dict_analysis(pc_plan* p, const DictSpec& D, const float* img, float* out, bool positive,
+                   unsigned long long* key, hipStream_t s);
+// img += sum_q w_q g_{s_q} centred on p_q (atoms[q] = s_q n^2 + p_q), cropped.
+void dict_synthesis(pc_plan* p, const DictSpec& D, int64_t nS, const int32_t* atoms,
+                    const double* w, float* img, hipStream_t s);
+// out[q] = (Psi* img)[atoms[q]] in FP64 (the analysis at the active atoms).
+void dict_gather(pc_plan* p, const DictSpec& D, int64_t nS, const int32_t* atoms,
+                 const float* img, double* out, hipStream_t s);
 
 // kernels_grid.hip
 template <typename R>

@@ -430,7 +430,8 @@ __global__ void activate_kernel(int64_t nS, int64_t ntotal, int n, double dl,
   x[p] = xv;
   y[p] = xv;
   pix[p] = q;
-  const int i = q / n, j = q - i * n;
+  const int qp = q % (n * n);  // the centre pixel of a synthesis-dictionary atom
+  const int i = qp / n, j = qp - i * n;
   const double a = (double)(i - n / 2), b = (double)(j - n / 2);
   const double l = a * dl, m = b * dl;
   const double inv_n = 1.0 / sqrt(1.0 - l * l - m * m);

@@ -54,6 +54,10 @@ void* ensure_atom_scratch(pc_plan* p, size_t bytes) {
   return grow(p, &p->atom_scratch, &p->atom_capacity, bytes);
 }
 
+float* ensure_dict_scratch(pc_plan* p, size_t count) {
+  return (float*)grow(p, &p->dict_scratch, &p->dict_capacity, count * sizeof(float));
+}
+
 double* ensure_red_scratch(pc_plan* p, size_t count) {
   size_t cap = p->red_capacity * sizeof(double);
   void* slot = p->red_scratch;

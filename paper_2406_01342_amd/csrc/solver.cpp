@@ -190,13 +190,34 @@ struct Pfw {
   int64_t grid_thr = 0;  // active-set size from which APGD uses gridded operators
   bool done = false, converged = false;
   bool positive = false;  // x >= 0: signed exploration, one-sided prox and dual scaling
+  // Synthesis dictionary (n_scales > 0): atoms s N + p are the columns of
+  // Phi Psi; exploration on Psi* eta, APGD through the gridded operators.
+  bool ms = false;
+  DictSpec dict{};
+  int64_t NA = 0;          // atoms in the dictionary (N without one)
+  DevArray<float> eta_ms;  // Psi* eta, [S][n][n]
   double adj_ms = 0;
   int adj_calls = 0;
   double t0 = 0;
 
   Pfw(pc_plan* plan, hipStream_t stream, const pc_solve_params& params)
       : p(plan), s(stream), prm(params), L(plan->L), N((int64_t)plan->g.n * plan->g.n),
-        positive(params.positivity != 0) {}
+        positive(params.positivity != 0), ms(params.n_scales > 0) {
+    NA = N;
+    if (ms) {
+      dict = make_dict(params.n_scales, params.scale_sigma, params.scale_gamma);
+      NA = (int64_t)dict.S * N;
+      PC_REQUIRE(NA < ((int64_t)1 << 31), "n_scales * npix^2 must be < 2^31");
+    }
+  }
+
+  // The exploration image: eta, or Psi* eta with its maximum (which then
+  // replaces eta's) under a dictionary.
+  float* expl() { return ms ? eta_ms.ptr : eta.ptr; }
+  void ms_explore_sync() {
+    dict_analysis(p, dict, eta.ptr, eta_ms.ptr, positive, p->maxkey, s);
+    maxkey_read(p, s, &eta_inf, &eta_argmax);  // synchronises
+  }
 
   static double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -210,11 +231,13 @@ struct Pfw {
       batcher_adjoint(batcher, p, vis_sorted, eta.ptr, s, &eta_inf, &eta_argmax, &ms);
       adj_ms += ms;
       adj_calls++;
+      if (this->ms) ms_explore_sync();
       return;
     }
     PC_HIP(hipEventRecord(p->ev_a, s));
     adjoint_grid<float>(p, vis_sorted, true, eta.ptr, 1.0f, s);
     PC_HIP(hipEventRecord(p->ev_b, s));
+    if (this->ms) dict_analysis(p, dict, eta.ptr, eta_ms.ptr, positive, p->maxkey, s);
     double mx;
     int64_t am;
     maxkey_read(p, s, &mx, &am);  // synchronises
@@ -238,6 +261,7 @@ struct Pfw {
     PC_HIP(hipEventRecord(p->ev_a, s));
     adjoint_grid<float>(p, vis_sorted, true, eta.ptr, 1.0f, s);
     PC_HIP(hipEventRecord(p->ev_b, s));
+    if (ms) dict_analysis(p, dict, eta.ptr, eta_ms.ptr, positive, p->maxkey, s);
     red_partial.ensure(2 * k_resid_blocks(L));
     k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
     unsigned char* h = (unsigned char*)down.get(24);
@@ -331,9 +355,15 @@ struct Pfw {
       return;
     }
     ensure_dimg();
-    k_scatter(p, nS, pix.ptr, w, dimg.ptr, s);
-    forward_grid<float>(p, dimg.ptr, out, true, s);
-    k_scatter(p, nS, pix.ptr, nullptr, dimg.ptr, s);
+    if (ms) {  // Psi w: weighted elements (overlapping), cleared after use
+      dict_synthesis(p, dict, nS, pix.ptr, w, dimg.ptr, s);
+      forward_grid<float>(p, dimg.ptr, out, true, s);
+      k_fill(p, N, 0.0f, dimg.ptr, s);
+    } else {
+      k_scatter(p, nS, pix.ptr, w, dimg.ptr, s);
+      forward_grid<float>(p, dimg.ptr, out, true, s);
+      k_scatter(p, nS, pix.ptr, nullptr, dimg.ptr, s);
+    }
     if (base) k_rsub(p, L, V.ptr, out, s);
   }
 
@@ -345,7 +375,10 @@ struct Pfw {
       return;
     }
     adjoint_grid<float>(p, rr, true, eta.ptr, 1.0f, s);
-    k_gather_img(p, nS, pix.ptr, eta.ptr, gout, s);
+    if (ms)
+      dict_gather(p, dict, nS, pix.ptr, eta.ptr, gout, s);
+    else
+      k_gather_img(p, nS, pix.ptr, eta.ptr, gout, s);
   }
 
   void init(const void* vis_caller) {
@@ -354,6 +387,7 @@ struct Pfw {
     V.ensure(L);
     r.ensure(L);
     eta.ensure(N);
+    if (ms) eta_ms.ensure(NA);
     scal.ensure(kScalCount);
     cand_count.ensure(1);
     cand.ensure(65536);
@@ -627,7 +661,7 @@ struct Pfw {
     unsigned count = 0;
     std::vector<int32_t> I;
     for (;;) {
-      k_select(p, N, eta.ptr, tau_f, positive, cand_count.ptr, cand.ptr, cand.cap, s);
+      k_select(p, NA, expl(), tau_f, positive, cand_count.ptr, cand.ptr, cand.cap, s);
       const int64_t first = std::min<int64_t>(kFirst, cand.cap);
       unsigned char* h = (unsigned char*)down.get(4 + first * 4);
       PC_HIP(hipMemcpyAsync(h, cand_count.ptr, 4, hipMemcpyDeviceToHost, s));
@@ -662,7 +696,7 @@ struct Pfw {
     load_active(Sn, xw);
     // 2. APGD on the restricted problem
     int inner = 0;
-    const bool gridded = nS >= grid_thr;
+    const bool gridded = ms || nS >= grid_thr;
     // small direct sets: the Gram form (one small kernel per step)
     const bool gram = !gridded && nS > 0 && nS <= gram_cap() && build_gram(Sn);
     if (nS > 0) {
@@ -775,7 +809,7 @@ struct Pfw {
       }
     // 4. residual, dirty residual, objective and gap
     load_active(S, xs);
-    op_forward((int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
+    op_forward(ms || (int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
     double r2, vr;
     adjoint_and_stats(r.ptr, r2, vr);
     double l1 = 0;
@@ -811,7 +845,7 @@ struct Pfw {
     res->adjoint_seconds = adj_ms * 1e-3;
     res->adjoint_calls = adj_calls;
     if (prm.want_certificate && res->cert && lam > 0)
-      k_scale(p, N, eta.ptr, (float)(1.0 / lam), res->cert, s);
+      k_scale(p, NA, expl(), (float)(1.0 / lam), res->cert, s);
     PC_HIP(hipStreamSynchronize(s));
     res->seconds = now() - t0;
     if (na > res->capacity) {
@@ -835,6 +869,8 @@ static void check_params(const pc_solve_params* prm) {
              "lambda > 0 or alpha > 0 is required");
   PC_REQUIRE(prm->inner_max_iter >= 1, "inner_max_iter must be >= 1");
   PC_REQUIRE(prm->inner_tol0 >= 0 && prm->inner_tol_min >= 0, "inner tolerances must be >= 0");
+  PC_REQUIRE(prm->n_scales >= 0 && prm->n_scales <= kDictMaxScales, "n_scales must be in [0, 8]");
+  if (prm->n_scales > 0) (void)make_dict(prm->n_scales, prm->scale_sigma, prm->scale_gamma);
 }
 
 }  // namespace pc

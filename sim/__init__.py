@@ -255,6 +255,24 @@ def config_c5_large(job_id: int = 0, n_ant: int = 512, n_snap: int = 16) -> Prob
                    0.95, 200, 1e-4, 0.0)
 
 
+def config_diffuse(job_id: int = 0, npix: int = 64, n_ant: int = 32, n_snap: int = 8,
+                   n_blob: int = 3, n_src: int = 4) -> Problem:
+    """Diffuse emission for the synthesis dictionary (the setting of Sect. 6.4,
+    scaled down): a 5 km-diameter disk of n_ant antennas, n_snap snapshots over
+    4 h at dec -45 deg, npix^2 pixels of about 0.8 nominal resolutions
+    (FOV 1.2 deg at 64^2), n_blob elliptical Gaussian blobs (axis sigmas
+    npix/16 to npix/8 pixels, peaks ten times those of the precision sky)
+    plus n_src points, 20 dB, alpha 0.02, delta 0.99, stop on a relative
+    improvement of 1e-5."""
+    pos = layout_disk(rng_for(7, job_id, STREAM_LAYOUT), n_ant, 2500.0)
+    srng = rng_for(7, job_id, STREAM_SKY)
+    bp, ba = blob_sky(srng, npix, n_blob, npix / 16, npix / 8)
+    pp, pa = point_sky(srng, npix, n_src)
+    return _problem("DIFFUSE", 7, job_id, pos, 150e6, n_snap, 4.0, -45 * DEG, npix,
+                    1.2 * npix / 64, merge_sparse(pp, pa, bp, 10.0 * ba), 20.0, 0.02, 0.99,
+                    300, 1e-5, 0.0)
+
+
 def config_c5_small(job_id: int = 0) -> Problem:
     """Memory-pressure small job: 64 antennas, 25 snapshots, 512^2, FOV 2 deg."""
     pos = layout_disk(rng_for(6, job_id, STREAM_LAYOUT), 64, 2500.0)

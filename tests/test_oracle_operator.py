@@ -131,3 +131,15 @@ def test_restricted_adjoint_matches_full_on_support():
     full = operator.adjoint(uv, n, fov, h).reshape(-1)
     assert np.allclose(operator.restricted_adjoint(uv, n, fov, h, pix), full[pix],
                        rtol=1e-12, atol=1e-12)
+
+
+def test_forward_images_equals_forward_per_image():
+    """The batched dense forward is the sparse forward applied column by column."""
+    rng = np.random.default_rng(77)
+    n, fov, L = 12, 0.2, 90
+    uv = rng.uniform(-8, 8, size=(L, 2))
+    imgs = rng.normal(size=(n * n, 3))
+    got = operator.forward_images(uv, n, fov, imgs)
+    for c in range(3):
+        want = operator.forward(uv, n, fov, np.arange(n * n), imgs[:, c])
+        assert np.max(np.abs(got[:, c] - want)) <= 1e-12 * np.max(np.abs(want))
