@@ -279,6 +279,60 @@ def adjoint_at(api, torch, p, reps, label):
     return out
 
 
+def dictionary_leg(api, torch, reps):
+    """Synthesis-dictionary path (the paper's four Gaussian scales, sigma 0,
+    2, 5, 8, gamma 1.2^s): Psi* Phi* on the precision workload's 4096^2 image
+    with the stencil kernels' HBM rates, and a synthesis-form solve on the
+    256^2 diffuse workload."""
+    import numpy as np
+    import sim
+    sig, gam = [0.0, 2.0, 5.0, 8.0], [1.2 ** s for s in range(4)]
+    p = sim.config_c3()
+    plan, vis = synth_inputs(api, torch, p)
+    dv = torch.from_numpy(vis).cuda()
+    n = p.npix
+    imgs = torch.empty((4, n, n), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        api.pc_adjoint_grid_ms(plan, dv, sig, gam, imgs, want_max=True)
+    api.pc_plan_profile(plan, True)
+    for _ in range(reps):
+        api.pc_adjoint_grid_ms(plan, dv, sig, gam, imgs, want_max=True)
+    st = api.pc_plan_kernel_stats(plan)
+    api.pc_plan_profile(plan, False)
+    kern = {}
+    for x in st:
+        if x["name"].startswith("dict_"):
+            avg = x["ms"] / x["launches"]
+            gbs = x["bytes"] / x["launches"] / (avg * 1e-3) / 1e9
+            kern[x["name"]] = {"avg_us": round(1e3 * avg, 2), "GB/s": round(gbs, 1),
+                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                               "bytes_per_launch": x["bytes"] / x["launches"]}
+    total_ms = sum(x["ms"] for x in st) / reps
+    out = {"adjoint_ms": {"workload": "precision workload (2,088,960 visibilities, 4096^2), "
+                                      "4 scales",
+                          "device_ms": total_ms, "mvis_per_s": p.nvis / total_ms / 1e3,
+                          "kernels": kern}}
+    log("dictionary adjoint", out["adjoint_ms"])
+    plan.close()
+    del dv, imgs
+    p = sim.config_diffuse(npix=256)
+    plan, vis = synth_inputs(api, torch, p)
+    dv = torch.from_numpy(vis).cuda()
+    prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter, rel_obj_tol=p.rel_obj_tol,
+               scales=(sig, gam))
+    api.pc_polyclean_solve(plan, dv, **prm)  # warm
+    r = api.pc_polyclean_solve(plan, dv, **prm)
+    out["solve"] = {"workload": f"diffuse workload: {p.nvis} visibilities, 256^2, 3 blobs + 4 "
+                                "points, 20 dB, lambda = 0.02 lambda_max, stop at relative "
+                                "improvement 1e-5",
+                    "seconds": r["seconds"], "iters": r["iters"], "natoms": r["natoms"],
+                    "atoms_per_scale": np.bincount(r["pix"] // (256 * 256), minlength=4).tolist(),
+                    "rel_gap": r["rel_gap"], "converged": r["converged"]}
+    log("dictionary solve", out["solve"])
+    plan.close()
+    return out
+
+
 def serving_leg(api, torch, n_req, slots):
     """Serving mix: n_req requests (grids 256^2..2048^2, 1e4-5e5 visibilities,
     32-128 antennas, 5-200 sources, 20 dB, lambda = 0.05 lambda_max, stop at
@@ -460,6 +514,8 @@ def main():
                        "memory-pressure large job: 512 stations x 16 snapshots x 4 channels, "
                        "8,372,224 visibilities, 8192^2 (16384^2 fine grid), FOV 3 deg"),
         ]
+    if not args.no_other_workloads:
+        out["dictionary"] = dictionary_leg(api, torch, max(5, args.adjoint_reps // 4))
     if args.serving_requests > 0:
         del plan, dv
         torch.cuda.empty_cache()

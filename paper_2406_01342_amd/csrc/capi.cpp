@@ -135,10 +135,11 @@ pc_status pc_adjoint_grid_ms(pc_plan* p, const void* vis, int32_t n_scales, cons
                "n_scales * npix^2 must be < 2^31");
     set_device(p);
     hipStream_t s = (hipStream_t)stream;
-    // Phi* vis into the first image (read whole by the row pass before the
-    // column pass writes any scale), then Psi*
-    adjoint_grid<float>(p, (const c32*)vis, false, images, 1.0f, s);
-    dict_analysis(p, D, images, images, false, p->maxkey, s);
+    // Phi* vis into a plan-owned image (every scale reads all of it), then
+    // Psi* into images
+    float* eta = ensure_image_scratch(p);
+    adjoint_grid<float>(p, (const c32*)vis, false, eta, 1.0f, s);
+    dict_analysis(p, D, eta, images, false, p->maxkey, s);
     if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
     return PC_OK;
   });

@@ -193,8 +193,10 @@ struct pc_plan {
   size_t atom_capacity = 0;
   double* red_scratch = nullptr;  // reduction partials
   size_t red_capacity = 0;
-  void* dict_scratch = nullptr;   // synthesis-dictionary row pass [S][n][n] float
-  size_t dict_capacity = 0;
+  void* image_scratch = nullptr;  // [n][n] float (adjoint image before Psi*)
+  size_t image_capacity = 0;
+  void* key_scratch = nullptr;    // per-workgroup max keys of the Psi* tiles
+  size_t key_capacity = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   pc::Prof prof;
   std::vector<int32_t> chunk_work;  // host copy: visibilities per spreading item
@@ -223,7 +225,8 @@ void* dalloc(pc_plan* p, size_t bytes);
 void plan_release(pc_plan* p);
 void* ensure_atom_scratch(pc_plan* p, size_t bytes);
 double* ensure_red_scratch(pc_plan* p, size_t count);
-float* ensure_dict_scratch(pc_plan* p, size_t count);
+float* ensure_image_scratch(pc_plan* p);  // n^2 floats, grown on first use
+unsigned long long* ensure_key_scratch(pc_plan* p, size_t count);  // per-workgroup max keys
 
 // Synthesis dictionary of Gaussian elements (Sect. 3.2; the elements of
 // Sect. 6.4): g_s[a][b] = gamma_s t_s[a] t_s[b], t_s the unit-sum 1-D

@@ -42,72 +42,76 @@ __device__ __forceinline__ void load_taps(const DictSpec& D, int s, float* tl) {
   __syncthreads();
 }
 
-// Row pass (one workgroup per image row i, the row staged in LDS):
-// tmp[s][i][j] = sum_b t_s[b] img[i][j + b].  Clears the key for the column
-// pass that follows on the same stream.
-__global__ __launch_bounds__(256) void dict_rows_kernel(int n, DictSpec D,
-                                                        const float* __restrict__ img,
-                                                        float* __restrict__ tmp,
-                                                        unsigned long long* __restrict__ key) {
-  extern __shared__ float row[];
-  __shared__ float tl[kDictMaxTaps];
-  const int i = blockIdx.x;
-  if (i == 0 && threadIdx.x == 0) *key = 0ull;
-  for (int j = threadIdx.x; j < n; j += 256) row[j] = img[(size_t)i * n + j];
-  const size_t N = (size_t)n * n;
-  for (int s = 0; s < D.S; ++s) {
-    __syncthreads();  // row loaded; previous scale's taps no longer read
-    load_taps(D, s, tl);
-    const int h = D.h[s];
-    for (int j = threadIdx.x; j < n; j += 256) {
-      const int b0 = max(-h, -j), b1 = min(h, n - 1 - j);
-      float acc = 0.0f;
-      for (int b = b0; b <= b1; ++b) acc += tl[b + h] * row[j + b];
-      tmp[s * N + (size_t)i * n + j] = acc;
-    }
-  }
-}
-
 __device__ __forceinline__ unsigned long long dict_key(float a, uint32_t idx) {
   return ((unsigned long long)__float_as_uint(a) << 32) | (unsigned long long)(0xffffffffu - idx);
 }
 
-// Column pass (grid: x over n^2 / 256 pixel blocks, y = scale):
-// out[s][i][j] = gamma_s sum_a t_s[a] tmp[s][i + a][j], loads coalesced along
-// j; fused max key.
-__global__ __launch_bounds__(256) void dict_cols_kernel(int n, DictSpec D,
-                                                        const float* __restrict__ tmp,
+// Psi* for one scale on a kTI x kTJ output tile (grid: column tiles, row
+// tiles).  The (kTI + 2h) x (kTJ + 2h) input window (zeros outside the
+// image) is staged in LDS once; the row pass writes (kTI + 2h) x kTJ partial
+// sums to LDS, the column pass forms the outputs, scales by gamma_s, stores
+// them coalesced and writes the block's maximum key to keys[block].  Threads
+// are 4 rows x 64 columns.  Any half-width up to kDictMaxHalf.
+constexpr int kTI = 64, kTJ = 64;
+
+__global__ __launch_bounds__(256) void dict_tile_kernel(int n, DictSpec D, int s,
+                                                        const float* __restrict__ img,
                                                         float* __restrict__ out, int positive,
-                                                        unsigned long long* __restrict__ key) {
+                                                        unsigned long long* __restrict__ keys) {
+  extern __shared__ float sm[];
   __shared__ float tl[kDictMaxTaps];
   __shared__ unsigned long long wbest[4];
-  const int s = blockIdx.y;
-  load_taps(D, s, tl);
-  const size_t N = (size_t)n * n;
-  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  unsigned long long best = 0;
-  if (e < N) {
-    const int i = (int)(e / n), j = (int)(e - (size_t)i * n);
-    const int h = D.h[s];
-    const int a0 = max(-h, -i), a1 = min(h, n - 1 - i);
-    const float* col = tmp + s * N + j;
+  const int h = D.h[s], W = kTJ + 2 * h, R = kTI + 2 * h;
+  float* win = sm;           // R x W
+  float* mid = sm + R * W;   // R x kTJ
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * kTI, j0 = blockIdx.x * kTJ;
+  if (threadIdx.x == 0)
+    for (int k = 0; k <= 2 * h; ++k) tl[k] = D.taps[s][k];
+  for (int r = ty; r < R; r += 4) {
+    const int gi = i0 - h + r;
+    const bool row_in = gi >= 0 && gi < n;
+    for (int c = tx; c < W; c += 64) {
+      const int gj = j0 - h + c;
+      win[r * W + c] = (row_in && gj >= 0 && gj < n) ? img[(size_t)gi * n + gj] : 0.0f;
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < R; r += 4) {
+    const float* w = win + r * W + tx;
     float acc = 0.0f;
-    for (int a = a0; a <= a1; ++a) acc += tl[a + h] * col[(size_t)(i + a) * n];
-    const float v = D.gamma[s] * acc;
-    out[s * N + e] = v;
-    const float kv = positive ? (v > 0.0f ? v : 0.0f) : fabsf(v);
-    best = dict_key(kv, (uint32_t)(s * N + e));
+    for (int b = 0; b <= 2 * h; ++b) acc += tl[b] * w[b];
+    mid[r * kTJ + tx] = acc;
+  }
+  __syncthreads();
+  const size_t N = (size_t)n * n;
+  const float g = D.gamma[s];
+  unsigned long long best = 0;
+  const int gj = j0 + tx;
+  for (int r = ty; r < kTI; r += 4) {
+    const int gi = i0 + r;
+    const float* m = mid + r * kTJ + tx;
+    float acc = 0.0f;
+    for (int a = 0; a <= 2 * h; ++a) acc += tl[a] * m[a * kTJ];
+    if (gi < n && gj < n) {
+      const float v = g * acc;
+      const size_t e = (size_t)gi * n + gj;
+      out[s * N + e] = v;
+      const float kv = positive ? (v > 0.0f ? v : 0.0f) : fabsf(v);
+      const unsigned long long k = dict_key(kv, (uint32_t)(s * N + e));
+      best = k > best ? k : best;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long other = __shfl_xor(best, o, 64);
     best = other > best ? other : best;
   }
-  if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+  if (tx == 0) wbest[ty] = best;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long m = wbest[0];
     for (int w = 1; w < 4; ++w) m = wbest[w] > m ? wbest[w] : m;
-    atomicMax(key, m);
+    keys[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = m;
   }
 }
 
@@ -165,21 +169,170 @@ __global__ __launch_bounds__(256) void dict_gather_kernel(int n, DictSpec D, int
   if (threadIdx.x == 0) out[q] = (((red[0] + red[1]) + red[2]) + red[3]) * (double)D.gamma[s];
 }
 
+// The same tile for a compile-time half-width H <= 16 (sigma <= 8, every
+// scale of the paper), with the taps in registers and both passes as
+// register sliding windows (a lane forms 16 consecutive outputs from 16 + 2H
+// LDS reads and 16 (2H + 1) FMAs):
+//   vertical:   lane = window column, 16 output rows  -> mid[kTI][W + 1]
+//   horizontal: lane = output row, wave = 16 columns  -> res[kTI][kTJ + 1]
+// (odd row strides keep the lanes of the horizontal pass on distinct banks),
+// then a coalesced store of res with the block's maximum key written to
+// keys[block] (no atomics; reduced by dict_key_reduce_kernel).  Static LDS:
+// max((kTI + 2H) W, kTI (kTJ + 1)) + kTI (W + 1) floats, W = kTJ + 2H (at
+// most 61,696 bytes); res reuses the window.
+template <int H>
+__global__ __launch_bounds__(256) void dict_tile_h_kernel(int n, DictSpec D, int s,
+                                                          const float* __restrict__ img,
+                                                          float* __restrict__ out, int positive,
+                                                          unsigned long long* __restrict__ keys) {
+  constexpr int W = kTJ + 2 * H, R = kTI + 2 * H, T = 2 * H + 1, RB = 16;
+  constexpr int MS = W + 1, RS = kTJ + 1;  // padded strides of mid and res
+  static_assert(kTI == 64 && kTJ == 64, "one lane per output row, four 16-column waves");
+  constexpr int WIN = R * W > kTI * RS ? R * W : kTI * RS;  // res reuses the window
+  __shared__ float win[WIN];
+  __shared__ float mid[kTI * MS];
+  __shared__ unsigned long long wbest[4];
+  float t[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) t[k] = D.taps[s][k];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * kTI, j0 = blockIdx.x * kTJ;
+  {  // every load of the window in flight before the first LDS store
+    constexpr int NL = (R * W + 255) / 256;
+    float v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int idx = threadIdx.x + 256 * k, r = idx / W, c = idx - (idx / W) * W;
+      const int gi = i0 - H + r, gj = j0 - H + c;
+      v[k] = (idx < R * W && gi >= 0 && gi < n && gj >= 0 && gj < n)
+                 ? img[(size_t)gi * n + gj] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int idx = threadIdx.x + 256 * k;
+      if (idx < R * W) win[idx] = v[k];
+    }
+  }
+  __syncthreads();
+  for (int task = threadIdx.x; task < W * (kTI / RB); task += 256) {
+    const int c = task % W, g = task / W;
+    float acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < RB + 2 * H; ++k) {
+      const float v = win[(RB * g + k) * W + c];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (k - r >= 0 && k - r < T) acc[r] += t[k - r] * v;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) mid[(RB * g + r) * MS + c] = acc[r];
+  }
+  __syncthreads();
+  {
+    float* res = win;  // the window is no longer read
+    const float* m = mid + tx * MS + RB * ty;
+    float acc[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c) acc[c] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < RB + 2 * H; ++k) {
+      const float v = m[k];
+#pragma unroll
+      for (int c = 0; c < RB; ++c)
+        if (k - c >= 0 && k - c < T) acc[c] += t[k - c] * v;
+    }
+#pragma unroll
+    for (int c = 0; c < RB; ++c) res[tx * RS + RB * ty + c] = acc[c];
+  }
+  __syncthreads();
+  const size_t N = (size_t)n * n;
+  const float gm = D.gamma[s];
+  unsigned long long best = 0;
+  const int gj = j0 + tx;
+  for (int r = ty; r < kTI; r += 4) {
+    const int gi = i0 + r;
+    if (gi < n && gj < n) {
+      const float v = gm * win[r * RS + tx];
+      const size_t e = (size_t)gi * n + gj;
+      out[s * N + e] = v;
+      const float kv = positive ? (v > 0.0f ? v : 0.0f) : fabsf(v);
+      const unsigned long long kk = dict_key(kv, (uint32_t)(s * N + e));
+      best = kk > best ? kk : best;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(best, o, 64);
+    best = other > best ? other : best;
+  }
+  if (tx == 0) wbest[ty] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mx = wbest[0];
+    for (int w = 1; w < 4; ++w) mx = wbest[w] > mx ? wbest[w] : mx;
+    keys[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = mx;
+  }
+}
+
+// *key = max of count per-workgroup keys (one workgroup).
+__global__ __launch_bounds__(1024) void dict_key_reduce_kernel(int64_t count,
+                                                               const unsigned long long* __restrict__ keys,
+                                                               unsigned long long* __restrict__ key) {
+  __shared__ unsigned long long wb[16];
+  unsigned long long best = 0;
+  for (int64_t i = threadIdx.x; i < count; i += 1024) best = keys[i] > best ? keys[i] : best;
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(best, o, 64);
+    best = other > best ? other : best;
+  }
+  if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = wb[0];
+    for (int w = 1; w < 16; ++w) m = wb[w] > m ? wb[w] : m;
+    *key = m;
+  }
+}
+
+using DictTileFn = void (*)(int, DictSpec, int, const float*, float*, int, unsigned long long*);
+template <int H>
+static DictTileFn tile_fn_upto(int h) {
+  if constexpr (H < 0) {
+    return nullptr;
+  } else {
+    return h == H ? dict_tile_h_kernel<H> : tile_fn_upto<H - 1>(h);
+  }
+}
+
+static void set_lds_bytes(const void* kernel, size_t bytes) {
+  if (bytes > 64 * 1024)
+    PC_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
 void dict_analysis(pc_plan* p, const DictSpec& D, const float* img, float* out, bool positive,
                    unsigned long long* key, hipStream_t s) {
   const int n = p->g.n;
   const size_t N = (size_t)n * n;
-  float* tmp = ensure_dict_scratch(p, (size_t)D.S * N);
-  {
-    ProfScope ps(p, s, "dict_rows", 4.0 * N * (1 + D.S), (double)N * D.S);
-    hipLaunchKernelGGL(dict_rows_kernel, dim3(n), dim3(256), n * sizeof(float), s, n, D, img, tmp,
-                       key);
-    PC_LAUNCH_CHECK("dict_rows");
+  const dim3 grid((n + kTJ - 1) / kTJ, (n + kTI - 1) / kTI);
+  const int64_t nblk = (int64_t)grid.x * grid.y;
+  unsigned long long* keys = ensure_key_scratch(p, (size_t)(nblk * D.S));
+  for (int sc = 0; sc < D.S; ++sc) {
+    const int h = D.h[sc];
+    ProfScope ps(p, s, "dict_analysis", 8.0 * N, (double)N);
+    if (h <= 16) {
+      hipLaunchKernelGGL(tile_fn_upto<16>(h), grid, dim3(256), 0, s, n, D, sc, img, out,
+                         positive ? 1 : 0, keys + sc * nblk);
+    } else {
+      const size_t lds = sizeof(float) * (size_t)(kTI + 2 * h) * (kTJ + 2 * h + kTJ);
+      set_lds_bytes((const void*)dict_tile_kernel, lds);
+      hipLaunchKernelGGL(dict_tile_kernel, grid, dim3(256), lds, s, n, D, sc, img, out,
+                         positive ? 1 : 0, keys + sc * nblk);
+    }
+    PC_LAUNCH_CHECK("dict_analysis");
   }
-  ProfScope ps(p, s, "dict_cols", 8.0 * N * D.S, (double)N * D.S);
-  hipLaunchKernelGGL(dict_cols_kernel, dim3((unsigned)((N + 255) / 256), D.S), dim3(256), 0, s, n,
-                     D, tmp, out, positive ? 1 : 0, key);
-  PC_LAUNCH_CHECK("dict_cols");
+  hipLaunchKernelGGL(dict_key_reduce_kernel, dim3(1), dim3(1024), 0, s, nblk * D.S, keys, key);
+  PC_LAUNCH_CHECK("dict_key_reduce");
 }
 
 void dict_synthesis(pc_plan* p, const DictSpec& D, int64_t nS, const int32_t* atoms,

@@ -54,8 +54,14 @@ void* ensure_atom_scratch(pc_plan* p, size_t bytes) {
   return grow(p, &p->atom_scratch, &p->atom_capacity, bytes);
 }
 
-float* ensure_dict_scratch(pc_plan* p, size_t count) {
-  return (float*)grow(p, &p->dict_scratch, &p->dict_capacity, count * sizeof(float));
+float* ensure_image_scratch(pc_plan* p) {
+  return (float*)grow(p, &p->image_scratch, &p->image_capacity,
+                      sizeof(float) * (size_t)p->g.n * p->g.n);
+}
+
+unsigned long long* ensure_key_scratch(pc_plan* p, size_t count) {
+  return (unsigned long long*)grow(p, &p->key_scratch, &p->key_capacity,
+                                   sizeof(unsigned long long) * count);
 }
 
 double* ensure_red_scratch(pc_plan* p, size_t count) {
