@@ -283,7 +283,7 @@ def dictionary_leg(api, torch, reps):
     """Synthesis-dictionary path (the paper's four Gaussian scales, sigma 0,
     2, 5, 8, gamma 1.2^s): Psi* Phi* on the precision workload's 4096^2 image
     with the stencil kernels' HBM rates, and a synthesis-form solve on the
-    256^2 diffuse workload."""
+    64^2 diffuse workload."""
     import numpy as np
     import sim
     sig, gam = [0.0, 2.0, 5.0, 8.0], [1.2 ** s for s in range(4)]
@@ -315,18 +315,17 @@ def dictionary_leg(api, torch, reps):
     log("dictionary adjoint", out["adjoint_ms"])
     plan.close()
     del dv, imgs
-    p = sim.config_diffuse(npix=256)
+    p = sim.config_diffuse(npix=64)
     plan, vis = synth_inputs(api, torch, p)
     dv = torch.from_numpy(vis).cuda()
-    prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter, rel_obj_tol=p.rel_obj_tol,
-               scales=(sig, gam))
+    prm = dict(alpha=0.05, delta=p.delta, max_iter=300, rel_gap_tol=1e-4, scales=(sig, gam))
     api.pc_polyclean_solve(plan, dv, **prm)  # warm
     r = api.pc_polyclean_solve(plan, dv, **prm)
-    out["solve"] = {"workload": f"diffuse workload: {p.nvis} visibilities, 256^2, 3 blobs + 4 "
-                                "points, 20 dB, lambda = 0.02 lambda_max, stop at relative "
-                                "improvement 1e-5",
+    out["solve"] = {"workload": f"diffuse workload: {p.nvis} visibilities, 64^2, 3 blobs + 4 "
+                                "points, 20 dB, lambda = 0.05 lambda_max, stop at relative "
+                                "duality gap 1e-4",
                     "seconds": r["seconds"], "iters": r["iters"], "natoms": r["natoms"],
-                    "atoms_per_scale": np.bincount(r["pix"] // (256 * 256), minlength=4).tolist(),
+                    "atoms_per_scale": np.bincount(r["pix"] // (64 * 64), minlength=4).tolist(),
                     "rel_gap": r["rel_gap"], "converged": r["converged"]}
     log("dictionary solve", out["solve"])
     plan.close()

@@ -256,17 +256,20 @@ def config_c5_large(job_id: int = 0, n_ant: int = 512, n_snap: int = 16) -> Prob
 
 
 def config_diffuse(job_id: int = 0, npix: int = 64, n_ant: int = 32, n_snap: int = 8,
-                   n_blob: int = 3, n_src: int = 4) -> Problem:
+                   n_blob: int = 0, n_src: int = 4, sig_lo: float = 0.0,
+                   sig_hi: float = 0.0) -> Problem:
     """Diffuse emission for the synthesis dictionary (the setting of Sect. 6.4,
     scaled down): a 5 km-diameter disk of n_ant antennas, n_snap snapshots over
     4 h at dec -45 deg, npix^2 pixels of about 0.8 nominal resolutions
-    (FOV 1.2 deg at 64^2), n_blob elliptical Gaussian blobs (axis sigmas
-    npix/16 to npix/8 pixels, peaks ten times those of the precision sky)
-    plus n_src points, 20 dB, alpha 0.02, delta 0.99, stop on a relative
-    improvement of 1e-5."""
+    (FOV 1.2 deg at 64^2), elliptical Gaussian blobs with peaks ten times
+    those of the precision sky (n_blob of them, axis sigmas sig_lo to sig_hi
+    pixels; by default max(3, npix^2 / 2048) blobs of npix/16 to npix/8
+    pixels) plus n_src points, 20 dB, alpha 0.02, delta 0.99, stop on a
+    relative improvement of 1e-5."""
     pos = layout_disk(rng_for(7, job_id, STREAM_LAYOUT), n_ant, 2500.0)
     srng = rng_for(7, job_id, STREAM_SKY)
-    bp, ba = blob_sky(srng, npix, n_blob, npix / 16, npix / 8)
+    n_blob = n_blob or max(3, npix * npix // 2048)
+    bp, ba = blob_sky(srng, npix, n_blob, sig_lo or npix / 16, sig_hi or npix / 8)
     pp, pa = point_sky(srng, npix, n_src)
     return _problem("DIFFUSE", 7, job_id, pos, 150e6, n_snap, 4.0, -45 * DEG, npix,
                     1.2 * npix / 64, merge_sparse(pp, pa, bp, 10.0 * ba), 20.0, 0.02, 0.99,
