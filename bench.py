@@ -47,6 +47,7 @@ KERNEL_FILES = {
     "adjoint_sparse_acc64": ["kernels_dft.hip"],
     "spread": ["kernels_grid.hip", "fft_lds.h"], "fold": ["kernels_grid.hip", "fft_lds.h"],
     "passA_adj": ["kernels_grid.hip", "fft_lds.h"], "passB_adj": ["kernels_grid.hip", "fft_lds.h"],
+    "dict_analysis": ["kernels_dict.hip"],
 }
 # kernel name in the library's statistics -> substring of its symbol
 KERNEL_SYMBOLS = {
@@ -56,6 +57,7 @@ KERNEL_SYMBOLS = {
     "adjoint_sparse_acc64": "adjoint_sparse_kernel<float, double>",
     "spread": "spread_kernel<float", "fold": "fold_kernel<float>", "passA_adj": "passA_adj_kernel<float",
     "passB_adj": "passB_adj_kernel<float",
+    "dict_analysis": "dict_tile_h_kernel<16>",  # the widest of the paper's scales (sigma 8)
 }
 PROFILES = os.path.join(ROOT, "profiles")
 COPY_PROBE_BYTES = 512 << 20
@@ -172,6 +174,8 @@ def parse():
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-other-workloads", action="store_true",
                     help="skip the adjoint measurements at the 4096^2 and 8192^2 workloads")
+    ap.add_argument("--dictionary-only", action="store_true",
+                    help="run only the synthesis-dictionary leg and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_KERNEL.json from two rocprofv3 --pmc runs")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"),
@@ -311,7 +315,8 @@ def dictionary_leg(api, torch, reps):
     out = {"adjoint_ms": {"workload": "precision workload (2,088,960 visibilities, 4096^2), "
                                       "4 scales",
                           "device_ms": total_ms, "mvis_per_s": p.nvis / total_ms / 1e3,
-                          "kernels": kern}}
+                          "kernels": kern,
+                          "traffic_sigma8_bytes_per_launch": stored_traffic("dict_analysis")}}
     log("dictionary adjoint", out["adjoint_ms"])
     plan.close()
     del dv, imgs
@@ -418,6 +423,10 @@ def main():
 
     torch.cuda.set_device(0)
     copy_probe(torch)
+    if args.dictionary_only:
+        print(json.dumps({"dictionary": dictionary_leg(api, torch, max(5, args.adjoint_reps // 4))}),
+              flush=True)
+        return
     p = sim.config_c2()
     log("workload C2", p.nvis, "visibilities", p.npix, "pixels")
     t = time.perf_counter()

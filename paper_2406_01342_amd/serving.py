@@ -25,6 +25,12 @@ from typing import Callable, Dict, List, Optional
 import numpy as np
 
 
+def _n_scales(req) -> int:
+    """Images per certificate: the dictionary's scale count, else one."""
+    sc = req.params.get("scales")
+    return len(sc[0]) if sc is not None else 1
+
+
 @dataclass
 class ImagingRequest:
     rid: int
@@ -92,8 +98,11 @@ class DeviceBackend:
     def footprint(self, req: ImagingRequest) -> int:
         L = int(req.uv.shape[0])
         plan = self.api.pc_plan_footprint(req.uv, req.npix, req.fov_rad)
-        cert = 4 * req.npix * req.npix if req.want_certificate else 0
-        return int(plan) + 24 * L + 4 * req.npix * req.npix + cert + self.FIXED_BYTES
+        S = _n_scales(req)
+        cert = 4 * S * req.npix * req.npix if req.want_certificate else 0
+        # the dirty residual, plus its per-scale analysis with a dictionary
+        img = 4 * req.npix * req.npix * (1 + (S if "scales" in req.params else 0))
+        return int(plan) + 24 * L + img + cert + self.FIXED_BYTES
 
     def _params(self, req: ImagingRequest) -> dict:
         prm = dict(req.params)
@@ -121,7 +130,8 @@ class DeviceBackend:
         cert = None
         if req.want_certificate:
             with self.torch.cuda.stream(h["stream"]):
-                cert = self.torch.empty((req.npix, req.npix), dtype=self.torch.float32,
+                cert = self.torch.empty((_n_scales(req), req.npix, req.npix),
+                                        dtype=self.torch.float32,
                                         device=self.device)
         res = h["solver"].result(cert=cert)
         h["solver"].close()
@@ -138,7 +148,8 @@ class DeviceBackend:
         vis = torch.from_numpy(np.ascontiguousarray(req.vis, dtype=np.complex64)).to(self.device)
         cert = None
         if req.want_certificate:
-            cert = torch.empty((req.npix, req.npix), dtype=torch.float32, device=self.device)
+            cert = torch.empty((_n_scales(req), req.npix, req.npix), dtype=torch.float32,
+                               device=self.device)
         res = self.api.pc_polyclean_solve(plan, vis, cert=cert, **self._params(req))
         if cert is not None:
             res["certificate"] = cert

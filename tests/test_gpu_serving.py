@@ -66,6 +66,35 @@ def test_results_alone_equal_results_in_the_mix():
     be.close_backend()
 
 
+def test_positive_and_plain_jobs_share_batches():
+    """Positivity-constrained and unconstrained jobs in one mix: the batched
+    adjoint carries each job's own maximum (max(eta, 0) or |eta|), so every
+    job still equals its lone solve."""
+    a = api()
+    from paper_2406_01342_amd import serving
+    reqs = requests(6)
+    for k in (1, 2, 4):
+        reqs[k][3]["positivity"] = 1
+    be = serving.DeviceBackend(batched=True)
+    alone = [be.solve_plain(serving.ImagingRequest(k, 0.0, uv, p.npix, p.fov_rad, vis, prm))
+             for k, (p, uv, vis, prm) in enumerate(reqs)]
+    srv = serving.Server(be, slots=4)
+    summary = srv.run([serving.ImagingRequest(k, 0.0, uv, p.npix, p.fov_rad, vis, prm)
+                       for k, (p, uv, vis, prm) in enumerate(reqs)])
+    st = be.stats()
+    say("summary", summary, st)
+    assert summary["completed"] == len(reqs) and st["max_batch"] >= 2
+    for rec in srv.records:
+        ra, rm = alone[rec.rid], rec.result
+        assert rm["iters"] == ra["iters"], rec.rid
+        np.testing.assert_array_equal(rm["pix"], ra["pix"])
+        assert abs(rm["objective"] - ra["objective"]) <= 1e-6 * ra["objective"]
+        assert rm["lambda_max"] == ra["lambda_max"] and rm["cert_argmax"] == ra["cert_argmax"]
+        if rec.rid in (1, 2, 4):
+            assert np.all(rm["weight"] > 0)
+    be.close_backend()
+
+
 def test_memory_budget_admission_and_certificates():
     """Under a device-memory budget that holds about half of the jobs at once,
     admission keeps the resident footprint within it, every job completes
