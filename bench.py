@@ -175,7 +175,7 @@ def parse():
     ap.add_argument("--no-other-workloads", action="store_true",
                     help="skip the adjoint measurements at the 4096^2 and 8192^2 workloads")
     ap.add_argument("--dictionary-only", action="store_true",
-                    help="run only the synthesis-dictionary leg and print its JSON")
+                    help="run only the synthesis-dictionary adjoint at 4096^2 and print its JSON")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_KERNEL.json from two rocprofv3 --pmc runs")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"),
@@ -283,7 +283,7 @@ def adjoint_at(api, torch, p, reps, label):
     return out
 
 
-def dictionary_leg(api, torch, reps):
+def dictionary_leg(api, torch, reps, with_solve=True):
     """Synthesis-dictionary path (the paper's four Gaussian scales, sigma 0,
     2, 5, 8, gamma 1.2^s): Psi* Phi* on the precision workload's 4096^2 image
     with the stencil kernels' HBM rates, and a synthesis-form solve on the
@@ -320,6 +320,8 @@ def dictionary_leg(api, torch, reps):
     log("dictionary adjoint", out["adjoint_ms"])
     plan.close()
     del dv, imgs
+    if not with_solve:
+        return out
     p = sim.config_diffuse(npix=64)
     plan, vis = synth_inputs(api, torch, p)
     dv = torch.from_numpy(vis).cuda()
@@ -424,8 +426,8 @@ def main():
     torch.cuda.set_device(0)
     copy_probe(torch)
     if args.dictionary_only:
-        print(json.dumps({"dictionary": dictionary_leg(api, torch, max(5, args.adjoint_reps // 4))}),
-              flush=True)
+        print(json.dumps({"dictionary": dictionary_leg(api, torch, max(5, args.adjoint_reps // 4),
+                                                       with_solve=False)}), flush=True)
         return
     p = sim.config_c2()
     log("workload C2", p.nvis, "visibilities", p.npix, "pixels")

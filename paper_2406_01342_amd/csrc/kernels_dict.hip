@@ -42,12 +42,23 @@ __device__ __forceinline__ void load_taps(const DictSpec& D, int s, float* tl) {
   __syncthreads();
 }
 
+// Workgroups are dealt to the XCDs (each with its own L2) round-robin; this
+// renumbering gives each XCD a contiguous range of tiles (row-major over the
+// image), so that the halo rows two neighbouring tiles share are read into
+// one L2.
+__device__ __forceinline__ int dict_tile_order(int b, int nb) {
+  constexpr int kX = 8;
+  const int q = nb / kX, r = nb % kX;
+  const int x = b % kX, k = b / kX;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 __device__ __forceinline__ unsigned long long dict_key(float a, uint32_t idx) {
   return ((unsigned long long)__float_as_uint(a) << 32) | (unsigned long long)(0xffffffffu - idx);
 }
 
-// Psi* for one scale on a kTI x kTJ output tile (grid: column tiles, row
-// tiles).  The (kTI + 2h) x (kTJ + 2h) input window (zeros outside the
+// Psi* for one scale on a kTI x kTJ output tile (one workgroup per tile,
+// tiles ordered per XCD by dict_tile_order).  The (kTI + 2h) x (kTJ + 2h) input window (zeros outside the
 // image) is staged in LDS once; the row pass writes (kTI + 2h) x kTJ partial
 // sums to LDS, the column pass forms the outputs, scales by gamma_s, stores
 // them coalesced and writes the block's maximum key to keys[block].  Threads
@@ -65,7 +76,8 @@ __global__ __launch_bounds__(256) void dict_tile_kernel(int n, DictSpec D, int s
   float* win = sm;           // R x W
   float* mid = sm + R * W;   // R x kTJ
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int i0 = blockIdx.y * kTI, j0 = blockIdx.x * kTJ;
+  const int tb = dict_tile_order(blockIdx.x, gridDim.x), ntx = (n + kTJ - 1) / kTJ;
+  const int i0 = (tb / ntx) * kTI, j0 = (tb - (tb / ntx) * ntx) * kTJ;
   if (threadIdx.x == 0)
     for (int k = 0; k <= 2 * h; ++k) tl[k] = D.taps[s][k];
   for (int r = ty; r < R; r += 4) {
@@ -111,7 +123,7 @@ __global__ __launch_bounds__(256) void dict_tile_kernel(int n, DictSpec D, int s
   if (threadIdx.x == 0) {
     unsigned long long m = wbest[0];
     for (int w = 1; w < 4; ++w) m = wbest[w] > m ? wbest[w] : m;
-    keys[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = m;
+    keys[tb] = m;
   }
 }
 
@@ -196,7 +208,8 @@ __global__ __launch_bounds__(256) void dict_tile_h_kernel(int n, DictSpec D, int
 #pragma unroll
   for (int k = 0; k < T; ++k) t[k] = D.taps[s][k];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int i0 = blockIdx.y * kTI, j0 = blockIdx.x * kTJ;
+  const int tb = dict_tile_order(blockIdx.x, gridDim.x), ntx = (n + kTJ - 1) / kTJ;
+  const int i0 = (tb / ntx) * kTI, j0 = (tb - (tb / ntx) * ntx) * kTJ;
   {  // every load of the window in flight before the first LDS store
     constexpr int NL = (R * W + 255) / 256;
     float v[NL];
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(256) void dict_tile_h_kernel(int n, DictSpec D, int
   if (threadIdx.x == 0) {
     unsigned long long mx = wbest[0];
     for (int w = 1; w < 4; ++w) mx = wbest[w] > mx ? wbest[w] : mx;
-    keys[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = mx;
+    keys[tb] = mx;
   }
 }
 
@@ -314,8 +327,8 @@ void dict_analysis(pc_plan* p, const DictSpec& D, const float* img, float* out, 
                    unsigned long long* key, hipStream_t s) {
   const int n = p->g.n;
   const size_t N = (size_t)n * n;
-  const dim3 grid((n + kTJ - 1) / kTJ, (n + kTI - 1) / kTI);
-  const int64_t nblk = (int64_t)grid.x * grid.y;
+  const int64_t nblk = (int64_t)((n + kTJ - 1) / kTJ) * ((n + kTI - 1) / kTI);
+  const dim3 grid((unsigned)nblk);
   unsigned long long* keys = ensure_key_scratch(p, (size_t)(nblk * D.S));
   for (int sc = 0; sc < D.S; ++sc) {
     const int h = D.h[sc];
