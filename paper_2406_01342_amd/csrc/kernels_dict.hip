@@ -184,24 +184,25 @@ __global__ __launch_bounds__(256) void dict_gather_kernel(int n, DictSpec D, int
 // The same tile for a compile-time half-width H <= 16 (sigma <= 8, every
 // scale of the paper), with the taps in registers and both passes as
 // register sliding windows (a lane forms 16 consecutive outputs from 16 + 2H
-// LDS reads and 16 (2H + 1) FMAs):
-//   vertical:   lane = window column, 16 output rows  -> mid[kTI][W + 1]
+// reads and 16 (2H + 1) FMAs):
+//   vertical:   lane = window column, 16 output rows, reading the image
+//               straight from L2 (loads coalesced along the row, all in
+//               flight)                               -> mid[kTI][W + 1]
 //   horizontal: lane = output row, wave = 16 columns  -> res[kTI][kTJ + 1]
 // (odd row strides keep the lanes of the horizontal pass on distinct banks),
 // then a coalesced store of res with the block's maximum key written to
-// keys[block] (no atomics; reduced by dict_key_reduce_kernel).  Static LDS:
-// max((kTI + 2H) W, kTI (kTJ + 1)) + kTI (W + 1) floats, W = kTJ + 2H (at
-// most 61,696 bytes); res reuses the window.
+// keys[tile] (no atomics; reduced by dict_key_reduce_kernel).  LDS holds only
+// mid (res reuses it): kTI (W + 1) floats, W = kTJ + 2H, at most 24.8 KB, so
+// that six workgroups share a compute unit.
 template <int H>
 __global__ __launch_bounds__(256) void dict_tile_h_kernel(int n, DictSpec D, int s,
                                                           const float* __restrict__ img,
                                                           float* __restrict__ out, int positive,
                                                           unsigned long long* __restrict__ keys) {
-  constexpr int W = kTJ + 2 * H, R = kTI + 2 * H, T = 2 * H + 1, RB = 16;
+  constexpr int W = kTJ + 2 * H, T = 2 * H + 1, RB = 16;
   constexpr int MS = W + 1, RS = kTJ + 1;  // padded strides of mid and res
   static_assert(kTI == 64 && kTJ == 64, "one lane per output row, four 16-column waves");
-  constexpr int WIN = R * W > kTI * RS ? R * W : kTI * RS;  // res reuses the window
-  __shared__ float win[WIN];
+  static_assert(RS <= MS, "res fits in mid");
   __shared__ float mid[kTI * MS];
   __shared__ unsigned long long wbest[4];
   float t[T];
@@ -210,43 +211,32 @@ __global__ __launch_bounds__(256) void dict_tile_h_kernel(int n, DictSpec D, int
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int tb = dict_tile_order(blockIdx.x, gridDim.x), ntx = (n + kTJ - 1) / kTJ;
   const int i0 = (tb / ntx) * kTI, j0 = (tb - (tb / ntx) * ntx) * kTJ;
-  {  // every load of the window in flight before the first LDS store
-    constexpr int NL = (R * W + 255) / 256;
-    float v[NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int idx = threadIdx.x + 256 * k, r = idx / W, c = idx - (idx / W) * W;
-      const int gi = i0 - H + r, gj = j0 - H + c;
-      v[k] = (idx < R * W && gi >= 0 && gi < n && gj >= 0 && gj < n)
-                 ? img[(size_t)gi * n + gj] : 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int idx = threadIdx.x + 256 * k;
-      if (idx < R * W) win[idx] = v[k];
-    }
-  }
-  __syncthreads();
   for (int task = threadIdx.x; task < W * (kTI / RB); task += 256) {
     const int c = task % W, g = task / W;
+    const int gj = j0 - H + c;
+    const bool col_in = gj >= 0 && gj < n;
+    float v[RB + 2 * H];
+#pragma unroll
+    for (int k = 0; k < RB + 2 * H; ++k) {
+      const int gi = i0 - H + RB * g + k;
+      v[k] = (col_in && gi >= 0 && gi < n) ? img[(size_t)gi * n + gj] : 0.0f;
+    }
     float acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = 0.0f;
 #pragma unroll
     for (int k = 0; k < RB + 2 * H; ++k) {
-      const float v = win[(RB * g + k) * W + c];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
-        if (k - r >= 0 && k - r < T) acc[r] += t[k - r] * v;
+        if (k - r >= 0 && k - r < T) acc[r] += t[k - r] * v[k];
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) mid[(RB * g + r) * MS + c] = acc[r];
   }
   __syncthreads();
+  float acc[RB];
   {
-    float* res = win;  // the window is no longer read
     const float* m = mid + tx * MS + RB * ty;
-    float acc[RB];
 #pragma unroll
     for (int c = 0; c < RB; ++c) acc[c] = 0.0f;
 #pragma unroll
@@ -256,9 +246,11 @@ __global__ __launch_bounds__(256) void dict_tile_h_kernel(int n, DictSpec D, int
       for (int c = 0; c < RB; ++c)
         if (k - c >= 0 && k - c < T) acc[c] += t[k - c] * v;
     }
-#pragma unroll
-    for (int c = 0; c < RB; ++c) res[tx * RS + RB * ty + c] = acc[c];
   }
+  __syncthreads();  // every lane has read mid: res overwrites it
+  float* res = mid;
+#pragma unroll
+  for (int c = 0; c < RB; ++c) res[tx * RS + RB * ty + c] = acc[c];
   __syncthreads();
   const size_t N = (size_t)n * n;
   const float gm = D.gamma[s];
@@ -267,7 +259,7 @@ __global__ __launch_bounds__(256) void dict_tile_h_kernel(int n, DictSpec D, int
   for (int r = ty; r < kTI; r += 4) {
     const int gi = i0 + r;
     if (gi < n && gj < n) {
-      const float v = gm * win[r * RS + tx];
+      const float v = gm * res[r * RS + tx];
       const size_t e = (size_t)gi * n + gj;
       out[s * N + e] = v;
       const float kv = positive ? (v > 0.0f ? v : 0.0f) : fabsf(v);
