@@ -30,19 +30,24 @@ def _case(name):
     return p.uv, p.npix, p.fov_rad, vis
 
 
-@pytest.mark.parametrize("name", ["diffuse32", "diffuse64", "c1", "ragged"])
-def test_adjoint_grid_ms_matches_oracle(name):
-    """Psi* Phi* h per scale (elements up to 33 x 33, cropped at the border
+WIDE = ([0.0, 12.0, 16.0], [1.0, 1.5, 2.0])  # half-widths 24 and 32: the generic tile kernel
+
+
+@pytest.mark.parametrize("name,scales", [("diffuse32", PAPER), ("diffuse64", PAPER),
+                                         ("c1", PAPER), ("ragged", PAPER), ("c1", WIDE)],
+                         ids=["diffuse32", "diffuse64", "c1", "ragged", "c1-wide"])
+def test_adjoint_grid_ms_matches_oracle(name, scales):
+    """Psi* Phi* h per scale (elements up to 65 x 65, cropped at the border
     of 32^2 to 128^2 images); maximum and its index over all scales."""
-    say("adjoint ms", name)
+    say("adjoint ms", name, scales)
     uv, n, fov, h = _case(name)
     a = api()
     plan = a.pc_plan_create(uv, n, fov)
-    img, mx, am = a.pc_adjoint_grid_ms(plan, to_dev(h), *PAPER)
+    img, mx, am = a.pc_adjoint_grid_ms(plan, to_dev(h), *scales)
     got = img.cpu().numpy().astype(np.float64)
     want = dic.analysis(operator.adjoint(uv, n, fov, h.astype(np.complex128)),
-                        dic.gaussian_dictionary(*PAPER))
-    errs = [rel_l2(got[s], want[s]) for s in range(4)]
+                        dic.gaussian_dictionary(*scales))
+    errs = [rel_l2(got[s], want[s]) for s in range(len(scales[0]))]
     say("rel l2 per scale", errs)
     assert max(errs) <= 1e-4
     wmax = np.abs(want).max()
