@@ -95,6 +95,48 @@ def test_positive_and_plain_jobs_share_batches():
     be.close_backend()
 
 
+def test_dictionary_jobs_in_the_mix():
+    """Synthesis-form jobs (the paper's four scales) share batches with point-
+    source jobs: each job's full-grid adjoint goes through the batcher and its
+    Psi* runs on its own stream; results equal the lone solves up to the
+    order of the element synthesis's float atomics."""
+    a = api()
+    from paper_2406_01342_amd import serving
+    reqs = requests(6)
+    scales = ([0.0, 2.0, 5.0, 8.0], [1.2 ** s for s in range(4)])
+    ms_ids = (3, 4)  # 256^2 and 512^2 grids
+    for k in ms_ids:
+        reqs[k][3]["scales"] = scales
+    be = serving.DeviceBackend(batched=True)
+    alone = [be.solve_plain(serving.ImagingRequest(k, 0.0, uv, p.npix, p.fov_rad, vis, prm,
+                                                   want_certificate=(k == ms_ids[0])))
+             for k, (p, uv, vis, prm) in enumerate(reqs)]
+    srv = serving.Server(be, slots=4)
+    summary = srv.run([serving.ImagingRequest(k, 0.0, uv, p.npix, p.fov_rad, vis, prm,
+                                              want_certificate=(k == ms_ids[0]))
+                       for k, (p, uv, vis, prm) in enumerate(reqs)])
+    st = be.stats()
+    say("summary", summary, st)
+    assert summary["completed"] == len(reqs) and st["max_batch"] >= 2
+    for rec in srv.records:
+        ra, rm = alone[rec.rid], rec.result
+        say(rec.rid, rm["iters"], ra["iters"], rm["natoms"], ra["natoms"], rm["objective"],
+            ra["objective"])
+        assert abs(rm["objective"] - ra["objective"]) <= 1e-5 * ra["objective"], rec.rid
+        assert abs(rm["lambda_max"] - ra["lambda_max"]) <= 1e-6 * ra["lambda_max"]
+        if rec.rid in ms_ids:
+            n = reqs[rec.rid][0].npix
+            assert np.all(rm["pix"] < 4 * n * n)
+        else:
+            np.testing.assert_array_equal(rm["pix"], ra["pix"])
+    cm = [r.result for r in srv.records if r.rid == ms_ids[0]][0]["certificate"]
+    ca = alone[ms_ids[0]]["certificate"]
+    assert tuple(cm.shape) == (4, reqs[ms_ids[0]][0].npix, reqs[ms_ids[0]][0].npix)
+    d = (cm - ca).abs().max().item()
+    assert d <= 1e-3 * ca.abs().max().item()
+    be.close_backend()
+
+
 def test_memory_budget_admission_and_certificates():
     """Under a device-memory budget that holds about half of the jobs at once,
     admission keeps the resident footprint within it, every job completes
