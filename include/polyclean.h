@@ -310,7 +310,8 @@ typedef struct {
   double lambda;          /* out: lambda used                                 */
   double lambda_max;      /* out: ||Phi* V||_inf (positivity: max(0, max))    */
   double cert_max;        /* out: ||mu||_inf (positivity: max(0, max mu))     */
-  int64_t cert_argmax;    /* out: lowest flat index attaining it              */
+  int64_t cert_argmax;    /* out: lowest flat index attaining it (s npix^2 + p */
+                          /*   with a dictionary)                             */
   int32_t iters;          /* out: FW iterations run                           */
   int32_t inner_iters;    /* out: total APGD iterations                       */
   int32_t converged;      /* out: 1 if a tolerance test stopped the solve     */
