@@ -243,7 +243,7 @@ PC_API pc_status pc_adjoint_grid_batch(pc_plan* const* plans, const void* const*
  * vis: dev complex64 [nvis] caller order; images: dev float
  * [n_scales][npix][npix].  max_abs / argmax (host, or NULL): max over all
  * scales and pixels and the lowest flat index s npix^2 + p attaining it.
- * FP32 plans.  Returns PC_ERR_INVALID for bad scales.
+ * FP32 plans.  Returns PC_ERR_INVALID_ARG for bad scales.
  * ------------------------------------------------------------------------- */
 PC_API pc_status pc_adjoint_grid_ms(pc_plan* plan, const void* vis, int32_t n_scales,
                                     const double* sigma, const double* gamma, float* images,
@@ -296,6 +296,14 @@ typedef struct {
                           /*   through the gridded operators.                 */
   double scale_sigma[8];  /* sigma_s in pixels, in [0, 16] (paper: 0, 2, 5, 8) */
   double scale_gamma[8];  /* gamma_s > 0 (paper: 1.2^s)                       */
+  const int32_t* x0_pix;  /* warm start (host, read during pc_polyclean_solve / */
+  const double* x0_w;     /*   pc_solver_create only): x0_n distinct atoms    */
+  int64_t x0_n;           /*   (pixels, or s npix^2 + p) and finite weights   */
+                          /*   (>= 0 under positivity); the solve continues   */
+                          /*   from this x as its previous iterate (no FW     */
+                          /*   iteration if x0 already meets rel_gap_tol).    */
+                          /*   lambda_max and lambda still come from the      */
+                          /*   data.  x0_n = 0: none                          */
 } pc_solve_params;
 
 typedef struct {

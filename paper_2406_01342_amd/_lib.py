@@ -50,7 +50,8 @@ class PcSolveParams(C.Structure):
                 ("want_certificate", C.c_int32), ("log_every", C.c_int32),
                 ("grid_atoms", C.c_int32), ("gram_atoms", C.c_int32),
                 ("n_scales", C.c_int32), ("scale_sigma", C.c_double * 8),
-                ("scale_gamma", C.c_double * 8)]
+                ("scale_gamma", C.c_double * 8), ("x0_pix", C.POINTER(C.c_int32)),
+                ("x0_w", C.POINTER(C.c_double)), ("x0_n", C.c_int64)]
 
 
 class PcSolveResult(C.Structure):

@@ -317,9 +317,21 @@ def pc_adjoint_grid_batch(plans, vis, images=None, want_max: bool = True, stream
 
 def solve_params(**kw) -> PcSolveParams:
     """Defaults plus keyword fields; ``scales=(sigmas, gammas)`` sets the
-    synthesis dictionary (n_scales, scale_sigma, scale_gamma)."""
+    synthesis dictionary (n_scales, scale_sigma, scale_gamma) and
+    ``x0=(atoms, weights)`` the warm start (the arrays are kept alive with the
+    returned structure)."""
     p = PcSolveParams()
     LIB.pc_solve_params_default(C.byref(p))
+    x0 = kw.pop("x0", None)
+    if x0 is not None:
+        pix = np.ascontiguousarray(x0[0], dtype=np.int32)
+        w = np.ascontiguousarray(x0[1], dtype=np.float64)
+        if pix.shape != w.shape or pix.ndim != 1:
+            raise ValueError("x0: atoms and weights must be 1-D of equal length")
+        p._x0_keep = (pix, w)
+        p.x0_pix = pix.ctypes.data_as(C.POINTER(C.c_int32))
+        p.x0_w = w.ctypes.data_as(C.POINTER(C.c_double))
+        p.x0_n = int(pix.size)
     scales = kw.pop("scales", None)
     if scales is not None:
         sig, gam = (list(map(float, a)) for a in scales)

@@ -58,11 +58,13 @@ __device__ __forceinline__ unsigned long long dict_key(float a, uint32_t idx) {
 }
 
 // Psi* for one scale on a kTI x kTJ output tile (one workgroup per tile,
-// tiles ordered per XCD by dict_tile_order).  The (kTI + 2h) x (kTJ + 2h) input window (zeros outside the
-// image) is staged in LDS once; the row pass writes (kTI + 2h) x kTJ partial
-// sums to LDS, the column pass forms the outputs, scales by gamma_s, stores
-// them coalesced and writes the block's maximum key to keys[block].  Threads
-// are 4 rows x 64 columns.  Any half-width up to kDictMaxHalf.
+// tiles ordered per XCD by dict_tile_order).  The (kTI + 2h) x (kTJ + 2h)
+// input window (zeros outside the image) is staged in LDS once; the row pass
+// writes (kTI + 2h) x kTJ partial sums to LDS, the column pass forms the
+// outputs, scales by gamma_s, stores them coalesced and writes the tile's
+// maximum key to keys[tile].  Threads are 4 rows x 64 columns.  Any
+// half-width up to kDictMaxHalf (used above 16, where the register version
+// would need too many taps and window values per lane).
 constexpr int kTI = 64, kTJ = 64;
 
 __global__ __launch_bounds__(256) void dict_tile_kernel(int n, DictSpec D, int s,

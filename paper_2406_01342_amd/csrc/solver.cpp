@@ -209,6 +209,14 @@ struct Pfw {
       NA = (int64_t)dict.S * N;
       PC_REQUIRE(NA < ((int64_t)1 << 31), "n_scales * npix^2 must be < 2^31");
     }
+    if (params.x0_n > 0) {  // atoms index images on the device: checked here
+      std::vector<int32_t> px(params.x0_pix, params.x0_pix + params.x0_n);
+      std::sort(px.begin(), px.end());
+      PC_REQUIRE(px.front() >= 0 && (int64_t)px.back() < NA,
+                 "x0_pix must lie in [0, npix^2) (times n_scales with a dictionary)");
+      PC_REQUIRE(std::adjacent_find(px.begin(), px.end()) == px.end(),
+                 "x0_pix must not repeat an atom");
+    }
   }
 
   // The exploration image: eta, or Psi* eta with its maximum (which then
@@ -409,6 +417,49 @@ struct Pfw {
     if (!(lmax > 0) || !(lam > 0)) {  // zero data: x = 0 is the solution
       done = true;
       converged = true;
+    } else if (prm.x0_n > 0) {
+      warm_start();
+    }
+  }
+
+  // Residual, dirty residual (and its maximum), objective and duality gap of
+  // the iterate (S, xs): step 4 of Alg. 2, also run once for a warm start.
+  void assess() {
+    load_active(S, xs);
+    op_forward(ms || (int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
+    double r2, vr;
+    adjoint_and_stats(r.ptr, r2, vr);
+    double l1 = 0;
+    for (double w : xs) l1 += std::fabs(w);
+    P = 0.5 * r2 + lam * l1;
+    const double sc = (eta_inf <= lam) ? 1.0 : lam / eta_inf;
+    gap = P - (sc * vr - 0.5 * sc * sc * r2);
+    rel_gap = P > 0 ? gap / P : 0.0;
+  }
+
+  // Warm start: the solve continues from x0 (atoms sorted, zero weights
+  // dropped) as if it were the previous iterate; lambda_max, lambda and
+  // Delta still come from the data alone.  The gap test applies to x0 itself
+  // (zero FW iterations when it passes); the improvement test needs an
+  // iteration.
+  void warm_start() {
+    std::vector<std::pair<int32_t, double>> at;
+    at.reserve((size_t)prm.x0_n);
+    for (int64_t q = 0; q < prm.x0_n; ++q)
+      if (prm.x0_w[q] != 0.0) at.push_back({prm.x0_pix[q], prm.x0_w[q]});
+    std::sort(at.begin(), at.end());
+    S.clear();
+    xs.clear();
+    for (const auto& a : at) {
+      S.push_back(a.first);
+      xs.push_back(a.second);
+    }
+    assess();
+    P_prev = P;
+    // a warm start that already meets the gap tolerance is the answer
+    if (prm.rel_gap_tol > 0 && rel_gap <= prm.rel_gap_tol) {
+      converged = true;
+      done = true;
     }
   }
 
@@ -808,16 +859,7 @@ struct Pfw {
         xs.push_back(xw[a]);
       }
     // 4. residual, dirty residual, objective and gap
-    load_active(S, xs);
-    op_forward(ms || (int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
-    double r2, vr;
-    adjoint_and_stats(r.ptr, r2, vr);
-    double l1 = 0;
-    for (double w : xs) l1 += std::fabs(w);
-    P = 0.5 * r2 + lam * l1;
-    const double sc = (eta_inf <= lam) ? 1.0 : lam / eta_inf;
-    gap = P - (sc * vr - 0.5 * sc * sc * r2);
-    rel_gap = P > 0 ? gap / P : 0.0;
+    assess();
     const double rel_imp = P_prev > 0 ? std::fabs(P - P_prev) / P_prev : 0.0;
     if (prm.log_every > 0 && (k % prm.log_every == 0))
       std::fprintf(stderr,
@@ -871,6 +913,15 @@ static void check_params(const pc_solve_params* prm) {
   PC_REQUIRE(prm->inner_tol0 >= 0 && prm->inner_tol_min >= 0, "inner tolerances must be >= 0");
   PC_REQUIRE(prm->n_scales >= 0 && prm->n_scales <= kDictMaxScales, "n_scales must be in [0, 8]");
   if (prm->n_scales > 0) (void)make_dict(prm->n_scales, prm->scale_sigma, prm->scale_gamma);
+  PC_REQUIRE(prm->x0_n >= 0, "x0_n must be >= 0");
+  if (prm->x0_n > 0) {
+    PC_REQUIRE(prm->x0_pix != nullptr && prm->x0_w != nullptr, "x0_pix / x0_w are NULL");
+    for (int64_t q = 0; q < prm->x0_n; ++q) {
+      PC_REQUIRE(std::isfinite(prm->x0_w[q]), "x0_w must be finite");
+      PC_REQUIRE(prm->positivity == 0 || prm->x0_w[q] >= 0,
+                 "x0_w must be >= 0 under positivity");
+    }
+  }
 }
 
 }  // namespace pc

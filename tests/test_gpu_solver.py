@@ -327,3 +327,50 @@ def test_solve_full_c2_properties():
     assert rel_l2(cert.reshape(-1)[pix], want) <= 1e-3
     p_or = solver.objective(v128, fit, res["weight"], res["lambda"])
     assert abs(p_or - res["objective"]) <= 1e-5 * p_or
+
+
+def test_warm_start_from_the_solution_and_from_a_perturbed_point():
+    """x0 (an interface option of the solve): from the converged solution the
+    gap test passes at once (no FW iteration, same objective: the operators
+    are deterministic); from a perturbed point (weights halved, stray atoms
+    added) the solve reaches the oracle's objective."""
+    say("warm start")
+    p, vis = problem("c1")
+    kw = dict(alpha=p.alpha, delta=p.delta, max_iter=300, rel_gap_tol=1e-5)
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    dv = to_dev(vis)
+    cold = a.pc_polyclean_solve(plan, dv, **kw)
+    warm = a.pc_polyclean_solve(plan, dv, x0=(cold["pix"], cold["weight"]), **kw)
+    say("cold", cold["iters"], cold["objective"], "warm", warm["iters"], warm["objective"])
+    assert warm["converged"] == 1 and warm["iters"] == 0
+    assert warm["objective"] == cold["objective"] and warm["rel_gap"] == cold["rel_gap"]
+    np.testing.assert_array_equal(warm["pix"], cold["pix"])
+    assert warm["lambda_max"] == cold["lambda_max"]
+    rng = np.random.default_rng(5)
+    extra = np.setdiff1d(rng.choice(p.npix ** 2, 12, replace=False), cold["pix"])
+    pix = np.concatenate([cold["pix"], extra])
+    w = np.concatenate([0.5 * cold["weight"], rng.normal(size=extra.size)])
+    pert = a.pc_polyclean_solve(plan, dv, x0=(pix, w), **kw)
+    ref = _oracle_solve(p, vis, **kw)
+    say("perturbed", pert["iters"], pert["objective"], "oracle", ref.objective)
+    assert pert["converged"] == 1
+    assert abs(pert["objective"] - ref.objective) <= 1e-3 * ref.objective
+    # the stray atoms are pruned again (their weights end at zero or move)
+    assert abs(pert["natoms"] - ref.pix.size) <= max(3, ref.pix.size // 10)
+
+
+@pytest.mark.parametrize("case", ["range", "negative-index", "duplicate", "nan", "negative-positive"])
+def test_warm_start_rejects_bad_atoms(case):
+    p, vis = problem("c1")
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    N = p.npix ** 2
+    pix, w, extra = {"range": ([0, N], [1.0, 1.0], {}),
+                     "negative-index": ([-1], [1.0], {}),
+                     "duplicate": ([5, 5], [1.0, 2.0], {}),
+                     "nan": ([5], [float("nan")], {}),
+                     "negative-positive": ([5], [-1.0], {"positivity": 1})}[case]
+    with pytest.raises(a.PolycleanError) as e:
+        a.pc_polyclean_solve(plan, to_dev(vis), x0=(pix, w), max_iter=2, **extra)
+    assert e.value.status == -1
