@@ -298,8 +298,10 @@ __global__ __launch_bounds__(256) void lanczos_step_kernel(int64_t nS, int j, in
 // Top eigenpair of the k x k symmetric tridiagonal T (diagonal al[0..k),
 // off-diagonal be[0..k-1)), by one wave: Sturm-sequence multisection (each
 // of the 64 lanes counts the eigenvalues below its own point of the current
-// bracket; 12 rounds shrink the Gershgorin bracket by 65^12), then the
-// eigenvector from the three-term recurrence (x_0 = 1), normalised.  Every
+// bracket; kSturmRounds = 6 rounds shrink the Gershgorin bracket by
+// 65^6 ~ 7.5e10, far below the 1e-3 residual test and the 1% margin of the
+// step constant), then the eigenvector from the three-term recurrence
+// (x_0 = 1), normalised.  Every
 // lane returns theta and writes nothing; lane 0 stores s[0..k).
 __device__ double tridiag_top(const double* al, const double* be, int k, double* s) {
   const int lane = threadIdx.x & 63;
@@ -310,7 +312,8 @@ __device__ double tridiag_top(const double* al, const double* be, int k, double*
     hi = fmax(hi, al[i] + r);
   }
   hi += 1e-300 + 1e-15 * fabs(hi);  // every eigenvalue strictly below hi
-  for (int round = 0; round < 12; ++round) {
+  constexpr int kSturmRounds = 6;
+  for (int round = 0; round < kSturmRounds; ++round) {
     const double xl = lo + (hi - lo) * (double)(lane + 1) / 65.0;
     int below = 0;  // eigenvalues < xl (signs of the LDL^T pivots of T - xl)
     double d = 1.0;
