@@ -136,3 +136,31 @@ def test_dictionary_rejects_bad_scales(sig, gam):
     if len(sig) <= 8:
         with pytest.raises(a.PolycleanError):
             a.pc_adjoint_grid_ms(plan, to_dev(vis), sig, gam)
+
+
+def test_dictionary_lambda_above_lambda_max_gives_zero():
+    p, vis = _diffuse(32)
+    res, cert = _gpu_solve(p, vis, PAPER, alpha=1.0001, delta=0.9, max_iter=5,
+                           rel_gap_tol=1e-9)
+    want = np.abs(dic.analysis(operator.adjoint(p.uv, p.npix, p.fov_rad,
+                                                 vis.astype(np.complex128)),
+                               dic.gaussian_dictionary(*PAPER))).max()
+    assert res["natoms"] == 0 and res["converged"] == 1 and res["iters"] == 1
+    assert abs(res["lambda_max"] - want) <= 1e-4 * want
+    half = 0.5 * float(np.vdot(vis.astype(np.complex128), vis.astype(np.complex128)).real)
+    assert abs(res["objective"] - half) <= 1e-6 * half
+
+
+def test_adjoint_grid_ms_eight_scales():
+    """The largest dictionary the interface takes: eight scales (half-widths
+    0 and 3 to 9, the register stencil for each)."""
+    uv, n, fov, h = _case("diffuse64")
+    sig, gam = [0.5 * s + (1.0 if s else 0.0) for s in range(8)], [1.1 ** s for s in range(8)]
+    a = api()
+    plan = a.pc_plan_create(uv, n, fov)
+    img, mx, am = a.pc_adjoint_grid_ms(plan, to_dev(h), sig, gam)
+    got = img.cpu().numpy().astype(np.float64)
+    want = dic.analysis(operator.adjoint(uv, n, fov, h.astype(np.complex128)),
+                        dic.gaussian_dictionary(sig, gam))
+    assert max(rel_l2(got[s], want[s]) for s in range(8)) <= 1e-4
+    assert abs(mx - np.abs(want).max()) <= 1e-4 * np.abs(want).max()
