@@ -164,3 +164,36 @@ def test_adjoint_grid_ms_eight_scales():
                         dic.gaussian_dictionary(sig, gam))
     assert max(rel_l2(got[s], want[s]) for s in range(8)) <= 1e-4
     assert abs(mx - np.abs(want).max()) <= 1e-4 * np.abs(want).max()
+
+
+@pytest.mark.slow
+def test_adjoint_grid_ms_full_c3_sampled():
+    """Full precision-workload size (2,088,960 visibilities, 4096^2; the
+    configuration the benchmark times): Psi* Phi* h at sampled outputs of
+    every scale, each formed by the oracle from the exact adjoint over the
+    element's window (a border sample exercises the cropping)."""
+    p = sim.config_c3()
+    pts = np.argsort(-p.sky_amp)[:20]
+    vclean = operator.forward(p.uv, p.npix, p.fov_rad, p.sky_pix[pts], p.sky_amp[pts])
+    vis = sim.add_noise(vclean, p.noise, p.psnr_db).astype(np.complex64)
+    n = p.npix
+    a = api()
+    plan = a.pc_plan_create(p.uv, n, p.fov_rad)
+    say("adjoint ms full c3")
+    img, mx, am = a.pc_adjoint_grid_ms(plan, to_dev(vis), *PAPER)
+    d = dic.gaussian_dictionary(*PAPER)
+    rng = np.random.default_rng(11)
+    samples = [(0, int(q)) for q in rng.choice(n * n, 4, replace=False)]
+    samples += [(1, int(q)) for q in rng.choice(n * n, 2, replace=False)]
+    samples += [(2, int(rng.integers(n * n))), (3, 2 * n + 3)]  # sigma 8 near a corner
+    if am // (n * n) <= 1:
+        samples.append((int(am // (n * n)), int(am % (n * n))))
+    v64 = vis.astype(np.complex128)
+    got, want = [], []
+    for s, q in samples:
+        pix, val = dic.element_pixels(d[s], q, n)
+        want.append(float(val @ operator.adjoint_pixels(p.uv, n, p.fov_rad, v64, pix)))
+        got.append(float(img[s].reshape(-1)[q]))
+    err = rel_l2(np.array(got), np.array(want))
+    say("full c3 dictionary samples", len(samples), "rel L2", err)
+    assert err <= 1e-4
