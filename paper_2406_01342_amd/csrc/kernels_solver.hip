@@ -140,33 +140,31 @@ __device__ __forceinline__ double gram_col_dot(const double* __restrict__ G,
 // stored in stats too: ||V - Phi_S y||^2 = v2 - 2 y.b + y.G y,
 // Re<V, V - Phi_S y> = v2 - y.b, ||y||_1 and max |g| (v2 = ||V||^2).
 //
-// done[0] != 0 makes the step a no-op (an earlier step passed the test).  When
-// `check` is set, the restricted duality gap at y is tested in the kernel:
-// with P = ||r_y||^2 / 2 + lambda ||y||_1 and the dual point scaled into the
+// When `check` is set, the restricted duality gap at y is tested: with
+// P = ||r_y||^2 / 2 + lambda ||y||_1 and the dual point scaled into the
 // feasible set, the step passes when P - D <= tol P; it is still applied, and
-// done = {1, iter} is recorded, so that the host can enqueue several steps and
-// read the outcome once.
-__global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const double* __restrict__ G,
-                                                         const double* __restrict__ b,
-                                                         double* __restrict__ x,
-                                                         double* __restrict__ y,
-                                                         double* __restrict__ g_out,
-                                                         double* __restrict__ stats, double v2,
-                                                         const double* __restrict__ lipd,
-                                                         double mom, int check, int iter,
-                                                         double lam, double tol, int positive,
-                                                         int* __restrict__ done) {
-  __shared__ double sh[4];
-  if (done[0]) return;  // uniform: every thread reads the same flag
-  const double inv_lip = 1.0 / lipd[0], thr = lam * inv_lip;  // step constant from the device
+// done = {1, iter} is recorded.  G may be an LDS copy; ys is the LDS copy
+// of y that the product reads (y itself is kept in step).  Returns with every
+// thread past the step's last read of y (the caller synchronises before the
+// next step).
+__device__ __forceinline__ void gram_fista_step(int64_t nS, const double* __restrict__ G,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ x, double* __restrict__ y,
+                                                double* __restrict__ ys,
+                                                double* __restrict__ g_out,
+                                                double* __restrict__ stats, double v2,
+                                                double inv_lip, double mom, int check, int iter,
+                                                double lam, double tol, int positive,
+                                                int* __restrict__ done, double* sh) {
+  const double thr = lam * inv_lip;
   // under positivity: ||y||_1 = sum y on x >= 0, yneg = max(0, -min y) > 0
   // marks an extrapolated y outside it (objective +inf there: no test), and
   // the dual scaling uses max(g, 0)
   double yGy = 0, yb = 0, yl1 = 0, gmax = 0, yneg = 0;
   for (int64_t q = threadIdx.x; q < nS; q += 256) {
-    const double s = gram_col_dot(G, y, nS, q);  // (G y)_q
+    const double s = gram_col_dot(G, ys, nS, q);  // (G y)_q
     const double gq = b[q] - s;
-    const double yq = y[q];
+    const double yq = ys[q];
     g_out[q] = gq;
     yGy += yq * s;
     yb += yq * b[q];
@@ -193,9 +191,9 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
       stats[3] = gmax;
     }
   }
-  __syncthreads();  // every thread has read all of y (and done[0])
+  __syncthreads();  // every thread has read all of y
   for (int64_t q = threadIdx.x; q < nS; q += 256) {
-    const double yo = y[q], xo = x[q];
+    const double yo = ys[q], xo = x[q];
     const double z = yo + g_out[q] * inv_lip;
     double xn;
     if (positive) {
@@ -204,12 +202,50 @@ __global__ __launch_bounds__(256) void gram_fista_kernel(int64_t nS, const doubl
       const double az = fabs(z) - thr;
       xn = az > 0 ? copysign(az, z) : 0.0;
     }
+    const double yn = xn + mom * (xn - xo);
     x[q] = xn;
-    y[q] = xn + mom * (xn - xo);
+    y[q] = yn;
+    ys[q] = yn;
   }
   if (passed && threadIdx.x == 0) {
     done[1] = iter;
     done[0] = 1;
+  }
+}
+
+// APGD steps it0 + 1 .. it0 + nsteps of the Gram form in one workgroup, the
+// momentum sequence t+ = (1 + sqrt(1 + 4 t^2)) / 2, mom = (t - 1) / t+ carried
+// on the device from t0 (the same FP64 recurrence the host advances), the
+// gap test on every kcheck-th step.  Steps after a passing test (done[0] set,
+// here or by an earlier launch) are skipped.  y is mirrored in LDS for the
+// products, and so is G when g_in_lds is set (loaded once for all steps of
+// the launch): dynamic LDS of nS (+ nS^2) doubles.
+__global__ __launch_bounds__(256) void gram_fista_loop_kernel(
+    int64_t nS, const double* __restrict__ G, const double* __restrict__ b,
+    double* __restrict__ x, double* __restrict__ y, double* __restrict__ g_out,
+    double* __restrict__ stats, double v2, const double* __restrict__ lipd, double t0, int it0,
+    int nsteps, int kcheck, double lam, double tol, int positive, int* __restrict__ done,
+    int g_in_lds) {
+  __shared__ double sh[4];
+  extern __shared__ double dyn[];
+  double* ys = dyn;
+  double* Gl = dyn + nS;
+  for (int64_t i = threadIdx.x; i < nS; i += 256) ys[i] = y[i];
+  if (g_in_lds)
+    for (int64_t i = threadIdx.x; i < nS * nS; i += 256) Gl[i] = G[i];
+  __syncthreads();
+  const double* Gm = g_in_lds ? Gl : G;
+  const double inv_lip = 1.0 / lipd[0];  // step constant from the device
+  double t = t0;
+  for (int c = 0; c < nsteps; ++c) {
+    if (done[0]) return;  // uniform: written before the last barrier
+    const int it = it0 + c + 1;
+    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    const double mom = (t - 1.0) / tn;
+    t = tn;
+    gram_fista_step(nS, Gm, b, x, y, ys, g_out, stats, v2, inv_lip, mom, (it - 1) % kcheck == 0,
+                    it, lam, tol, positive, done, sh);
+    __syncthreads();  // x, y and done written before the next step reads them
   }
 }
 
@@ -540,11 +576,20 @@ void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const do
 }
 
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
-                  double* g, double* stats, double v2, const double* lipd, double mom, bool check,
-                  int iter, double lam, double tol, bool positive, int* done, hipStream_t s) {
-  ProfScope ps(p, s, "gram_fista", 8.0 * nS * (nS + 6), (double)nS * nS);
-  hipLaunchKernelGGL(gram_fista_kernel, dim3(1), dim3(256), 0, s, nS, G, b, x, y, g, stats, v2,
-                     lipd, mom, check ? 1 : 0, iter, lam, tol, positive ? 1 : 0, done);
+                  double* g, double* stats, double v2, const double* lipd, double t0, int it0,
+                  int nsteps, int kcheck, double lam, double tol, bool positive, int* done,
+                  hipStream_t s) {
+  if (nsteps <= 0) return;
+  constexpr size_t kLdsMax = 150 * 1024;
+  const bool g_in_lds = (size_t)(nS + nS * nS) * 8 <= kLdsMax;
+  const size_t lds = (size_t)(nS + (g_in_lds ? nS * nS : 0)) * 8;
+  PC_REQUIRE(lds <= kLdsMax, "gram_fista: active set too large for the Gram form");
+  PC_HIP(hipFuncSetAttribute((const void*)gram_fista_loop_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax));
+  ProfScope ps(p, s, "gram_fista", 8.0 * nS * (nS + 6) * nsteps, (double)nS * nS * nsteps);
+  hipLaunchKernelGGL(gram_fista_loop_kernel, dim3(1), dim3(256), lds, s, nS, G, b, x, y, g, stats,
+                     v2, lipd, t0, it0, nsteps, kcheck, lam, tol, positive ? 1 : 0, done,
+                     g_in_lds ? 1 : 0);
   PC_LAUNCH_CHECK("gram_fista");
 }
 

@@ -780,15 +780,13 @@ struct Pfw {
           const int chunk = std::min(issued == 0 ? std::min(first, 4 * kGramChunk)
                                                  : 2 * kGramChunk,
                                      prm.inner_max_iter - issued);
-          for (int c = 0; c < chunk; ++c) {
-            const int it = ++issued;
-            const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-            const double mom = (t - 1.0) / tn;
-            t = tn;
-            k_gram_fista(p, nS, gram_G, gram_b, x.ptr, y.ptr, g.ptr, scal.ptr + kScalResid,
-                         v2, lz_out.ptr, mom, (it - 1) % kCheck == 0, it, lam, tol, positive,
-                         gram_done.ptr, s);
-          }
+          // one launch runs the chunk's steps; the host advances the same
+          // momentum recurrence for the next chunk's start
+          k_gram_fista(p, nS, gram_G, gram_b, x.ptr, y.ptr, g.ptr, scal.ptr + kScalResid, v2,
+                       lz_out.ptr, t, issued, chunk, kCheck, lam, tol, positive, gram_done.ptr,
+                       s);
+          for (int c = 0; c < chunk; ++c) t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+          issued += chunk;
           // outcome, x, and the Lanczos result with its Ritz vector
           h = (unsigned char*)down.get(8 + nS * 8 + (4 + nS) * 8);
           PC_HIP(hipMemcpyAsync(h, gram_done.ptr, 8, hipMemcpyDeviceToHost, s));

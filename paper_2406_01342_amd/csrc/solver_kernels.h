@@ -25,11 +25,13 @@ void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipS
 void k_lanczos_step(pc_plan* p, int64_t nS, int j, int kmax, double* Q, const double* g, double* w,
                     double* ab, hipStream_t s);
 void k_scale(pc_plan* p, int64_t N, const float* in, float sc, float* out, hipStream_t s);
-// Gram form of the restricted problem (see gram_fista_kernel): one APGD step,
-// optionally with the in-kernel duality-gap test.
+// Gram form of the restricted problem (see gram_fista_loop_kernel): APGD
+// steps it0 + 1 .. it0 + nsteps in one launch from the momentum state t0,
+// with the in-kernel duality-gap test on every kcheck-th step.
 void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, double* x, double* y,
-                  double* g, double* stats, double v2, const double* lipd, double mom, bool check,
-                  int iter, double lam, double tol, bool positive, int* done, hipStream_t s);
+                  double* g, double* stats, double v2, const double* lipd, double t0, int it0,
+                  int nsteps, int kcheck, double lam, double tol, bool positive, int* done,
+                  hipStream_t s);
 // The Gram form's Lanczos estimate with its stopping rule on the device: out =
 // {step constant, steps, theta, rho}, ritz = the top Ritz vector.
 // The basis and scratch live in LDS (G too for up to ~120 atoms): at most
