@@ -175,6 +175,7 @@ struct Pfw {
   double *gram_G = nullptr, *gram_b = nullptr, *gram_Q = nullptr;  // inside gram_blk
   DevArray<int> gram_done;  // {passed, step} of the device-side gap test
   int last_inner = 1 + kCheck;  // APGD steps of the last Gram-form solve
+  int last_lanczos = 0;         // Lanczos steps of the last step-size estimate
   DevArray<double> act_blk;  // uploaded [x | pix] of the active set
   DevArray<Atom<float>> off_atoms;
   DevArray<c32> ones;
@@ -681,6 +682,7 @@ struct Pfw {
         rho = bj * std::fabs(svec[k - 1]);
         const bool invariant = bj <= 1e-14 * std::max(theta, 1e-300) || k >= nS;
         if (invariant || rho <= kLanczosTol * theta || k == kLanczosMax) kfin = k;
+        last_lanczos = k;
       }
       if (kfin) {
         Qh.resize((size_t)kfin * nS);
@@ -801,6 +803,7 @@ struct Pfw {
         xw.resize(nS);
         std::memcpy(xw.data(), h + 8, nS * 8);
         const double* lz = (const double*)(h + 8 + nS * 8);  // {L, steps, theta, rho}, ritz
+        last_lanczos = (int)lz[1];
         pv_set = Sn;
         pv_val.assign(lz + 4, lz + 4 + nS);
       } else {
@@ -861,8 +864,9 @@ struct Pfw {
     const double rel_imp = P_prev > 0 ? std::fabs(P - P_prev) / P_prev : 0.0;
     if (prm.log_every > 0 && (k % prm.log_every == 0))
       std::fprintf(stderr,
-                   "[pfw] k=%d new=%u active=%zu eta_inf=%.6g obj=%.10g rel_gap=%.3e inner=%d\n",
-                   k, count, S.size(), eta_inf, P, rel_gap, inner);
+                   "[pfw] k=%d new=%u active=%zu eta_inf=%.6g obj=%.10g rel_gap=%.3e inner=%d "
+                   "lanczos=%d\n",
+                   k, count, S.size(), eta_inf, P, rel_gap, inner, last_lanczos);
     P_prev = P;
     ++k;
     if (prm.rel_obj_tol > 0 && rel_imp <= prm.rel_obj_tol) converged = true;
