@@ -114,6 +114,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// dst[0..n) = src[0..n) from global memory into LDS by a 256-thread
+// workgroup, eight loads in flight per thread (a plain copy loop waits for
+// each load before its LDS store: one memory latency per element).
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* __restrict__ src,
+                                            int64_t n) {
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 256 < n; i += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[i + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dst[i + u * 256] = v[u];
+  }
+  for (; i < n; i += 256) dst[i] = src[i];
+}
+
 // (G v)_q for the symmetric G as column q (coalesced across threads), with
 // four independent partial sums so that several loads are in flight.
 __device__ __forceinline__ double gram_col_dot(const double* __restrict__ G,
@@ -230,9 +246,8 @@ __global__ __launch_bounds__(256) void gram_fista_loop_kernel(
   extern __shared__ double dyn[];
   double* ys = dyn;
   double* Gl = dyn + nS;
-  for (int64_t i = threadIdx.x; i < nS; i += 256) ys[i] = y[i];
-  if (g_in_lds)
-    for (int64_t i = threadIdx.x; i < nS * nS; i += 256) Gl[i] = G[i];
+  copy_to_lds(ys, y, nS);
+  if (g_in_lds) copy_to_lds(Gl, G, nS * nS);
   __syncthreads();
   const double* Gm = g_in_lds ? Gl : G;
   const double inv_lip = 1.0 / lipd[0];  // step constant from the device
@@ -406,9 +421,8 @@ __global__ __launch_bounds__(256) void gram_lanczos_full_kernel(
   double* Q = dyn;
   double* w = Q + (int64_t)(kmax + 1) * nS;
   double* Gl = w + nS;
-  for (int64_t i = threadIdx.x; i < nS; i += 256) Q[i] = Qg[i];
-  if (g_in_lds)
-    for (int64_t i = threadIdx.x; i < nS * nS; i += 256) Gl[i] = Gg[i];
+  copy_to_lds(Q, Qg, nS);
+  if (g_in_lds) copy_to_lds(Gl, Gg, nS * nS);
   __syncthreads();
   const double* G = g_in_lds ? Gl : Gg;
   const int jmax = (int)(nS < kmax ? nS : kmax);
