@@ -329,6 +329,39 @@ def test_solve_full_c2_properties():
     assert abs(p_or - res["objective"]) <= 1e-5 * p_or
 
 
+@pytest.mark.slow
+def test_positive_solve_full_c2_properties():
+    """Full LOFAR-like size with a third of the sources negated, so that the
+    constraint is active: the gap stop fires, the weights are positive, the
+    certificate is at most one with its maximum at lambda (the one-sided alpha
+    identity) and well below -1 at the negated sources, and it agrees with
+    the oracle's certificate of the returned x on sampled pixels."""
+    say("positive solve full c2, mixed signs")
+    p = sim.config_c2()
+    amp = p.sky_amp * np.where(np.arange(p.sky_amp.size) % 3 == 1, -1.0, 1.0)
+    vclean = operator.forward(p.uv, p.npix, p.fov_rad, p.sky_pix, amp)
+    vis = sim.add_noise(vclean, p.noise, p.psnr_db).astype(np.complex64)
+    plan, res, cert = _gpu_solve(p, vis, alpha=p.alpha, delta=p.delta, max_iter=2000,
+                                 rel_gap_tol=1e-4, positivity=1)
+    say("positive full c2", {k: res[k] for k in ("objective", "rel_gap", "iters", "natoms",
+                                                  "inner_iters", "seconds")})
+    assert res["converged"] == 1 and res["rel_gap"] <= 1e-4
+    assert np.all(res["weight"] > 0)
+    assert res["cert_max"] <= 1 + 1e-3 and cert.max() <= 1 + 1e-3
+    assert abs(res["cert_max"] * res["lambda"] / res["lambda_max"] - p.alpha) <= 2e-3 * p.alpha
+    assert cert.min() < -1.0
+    n = p.npix
+    rng = np.random.default_rng(9)
+    pix = np.unique(np.concatenate([rng.choice(n * n, 512, replace=False), res["pix"][:256],
+                                    [res["cert_argmax"], int(np.argmin(cert))]]))
+    v128 = vis.astype(np.complex128)
+    fit = operator.forward(p.uv, n, p.fov_rad, res["pix"], res["weight"])
+    want = operator.adjoint_pixels(p.uv, n, p.fov_rad, v128 - fit, pix) / res["lambda"]
+    assert rel_l2(cert.reshape(-1)[pix], want) <= 1e-3
+    p_or = solver.objective(v128, fit, res["weight"], res["lambda"])
+    assert abs(p_or - res["objective"]) <= 1e-5 * p_or
+
+
 def test_warm_start_from_the_solution_and_from_a_perturbed_point():
     """x0 (an interface option of the solve): from the converged solution the
     gap test passes at once (no FW iteration, same objective: the operators
