@@ -38,23 +38,28 @@ DFT_PEAK_GPAIRS = 78.6e3 / 19.0
 # The one-pass forward + restricted adjoint uses each pair's sin/cos twice: the
 # same 19 slots plus two FP32 FMAs for the adjoint's accumulation.
 FUSED_PEAK_GPAIRS = 78.6e3 / 21.0
+# The point-spread sums (unit visibilities) need only the cosine and one FMA:
+# 19 - 4 (sin) - 1 (FMA) = 14 slots per pair.
+PSF_PEAK_GPAIRS = 78.6e3 / 14.0
 # Source files each kernel is compiled from (with the shared headers): a
 # stored HBM-traffic figure is used only while these are unchanged.
 CSRC = os.path.join(ROOT, "paper_2406_01342_amd", "csrc")
 KERNEL_FILES = {
     "adjoint_sparse": ["kernels_dft.hip"], "adjoint_sparse_reduce": ["kernels_dft.hip"],
     "forward_sparse": ["kernels_dft.hip"], "forward_adjoint_sparse": ["kernels_dft.hip"],
-    "adjoint_sparse_acc64": ["kernels_dft.hip"],
+    "adjoint_sparse_acc64": ["kernels_dft.hip"], "psf_sums_acc64": ["kernels_dft.hip"],
     "spread": ["kernels_grid.hip", "fft_lds.h"], "fold": ["kernels_grid.hip", "fft_lds.h"],
     "passA_adj": ["kernels_grid.hip", "fft_lds.h"], "passB_adj": ["kernels_grid.hip", "fft_lds.h"],
     "dict_analysis": ["kernels_dict.hip"],
 }
 # kernel name in the library's statistics -> substring of its symbol
 KERNEL_SYMBOLS = {
-    "adjoint_sparse": "adjoint_sparse_kernel<float, float>", "forward_sparse": "forward_sparse_kernel<float>",
+    "adjoint_sparse": "adjoint_sparse_kernel<float, float, false>",
+    "forward_sparse": "forward_sparse_kernel<float>",
     "adjoint_sparse_reduce": "adjoint_sparse_reduce_kernel<float, float>",
     "forward_adjoint_sparse": "forward_adjoint_kernel<",
-    "adjoint_sparse_acc64": "adjoint_sparse_kernel<float, double>",
+    "adjoint_sparse_acc64": "adjoint_sparse_kernel<float, double, false>",
+    "psf_sums_acc64": "adjoint_sparse_kernel<float, double, true>",
     "spread": "spread_kernel<float", "fold": "fold_kernel<float>", "passA_adj": "passA_adj_kernel<float",
     "passB_adj": "passB_adj_kernel<float",
     "dict_analysis": "dict_tile_h_kernel<16>",  # the widest of the paper's scales (sigma 8)
@@ -207,10 +212,11 @@ def dominant_roofline(stats, plan_info):
     avg_ms = top["ms"] / top["launches"]
     name = top["name"]
     if name in ("forward_sparse", "adjoint_sparse", "forward_adjoint_sparse",
-                "adjoint_sparse_acc64"):
+                "adjoint_sparse_acc64", "psf_sums_acc64"):
         pairs = top["work"] / top["launches"]
         achieved = pairs / (avg_ms * 1e-3) / 1e9
-        peak = FUSED_PEAK_GPAIRS if name == "forward_adjoint_sparse" else DFT_PEAK_GPAIRS
+        peak = {"forward_adjoint_sparse": FUSED_PEAK_GPAIRS,
+                "psf_sums_acc64": PSF_PEAK_GPAIRS}.get(name, DFT_PEAK_GPAIRS)
         return {"kernel": name, "bound": "alu", "achieved": achieved,
                 "peak": peak, "unit": "Gpair/s",
                 "frac": achieved / peak,

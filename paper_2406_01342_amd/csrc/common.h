@@ -318,7 +318,8 @@ template <typename R>
 void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natoms,
                    const Atom<R>* atoms, double* partial, double* out, hipStream_t s);
 // Restricted adjoint of plan-order visibilities with FP64 accumulation of the
-// FP32 terms (partial: adjoint_partial_count doubles); out[p] in FP64.
+// FP32 terms (partial: adjoint_partial_count doubles); out[p] in FP64.  vis
+// NULL: every visibility is 1 (the point-spread sums, cosines only).
 void adjoint_atoms_acc64(pc_plan* p, const cpx<float>* vis, int64_t natoms,
                          const Atom<float>* atoms, double* partial, double* out, hipStream_t s);
 template <typename R>

@@ -143,18 +143,28 @@ struct VisRec {
   cpx<R> h;
 };
 
-// One pair's term Re(h e^{+2 pi i t}) added to acc.
-template <typename R, typename A>
+// One pair's term Re(h e^{+2 pi i t}) added to acc; with UNIT h is real (1,
+// or 0 for a record past the chunk), so the term is h cos 2 pi t and the sine
+// is never formed.
+template <typename R, typename A, bool UNIT = false>
 __device__ __forceinline__ void adj_pair(const VisRec<R>& v, double a, double b, A& acc) {
   double t = fma(v.A, a, v.B * b);
   t -= rint(t);
-  R sn, cs;
-  sincos_turns<R>(t, sn, cs);
-  acc = fma((A)v.h.x, (A)cs, acc);
-  acc = fma(-(A)v.h.y, (A)sn, acc);
+  if constexpr (UNIT) {
+    if constexpr (sizeof(R) == 4) {
+      acc = fma((A)v.h.x, (A)__builtin_amdgcn_cosf((float)t), acc);
+    } else {
+      acc = fma((A)v.h.x, (A)cospi(2.0 * t), acc);
+    }
+  } else {
+    R sn, cs;
+    sincos_turns<R>(t, sn, cs);
+    acc = fma((A)v.h.x, (A)cs, acc);
+    acc = fma(-(A)v.h.y, (A)sn, acc);
+  }
 }
 
-template <typename R>
+template <typename R, bool UNIT = false>
 __device__ __forceinline__ VisRec<R> load_vis(int64_t k, int64_t k1, const double* __restrict__ AB,
                                               const cpx<R>* __restrict__ vis,
                                               const int32_t* __restrict__ perm) {
@@ -162,7 +172,10 @@ __device__ __forceinline__ VisRec<R> load_vis(int64_t k, int64_t k1, const doubl
   if (k < k1) {
     r.A = AB[2 * k];
     r.B = AB[2 * k + 1];
-    r.h = vis[perm ? perm[k] : k];
+    if constexpr (UNIT)
+      r.h = {R(1), R(0)};
+    else
+      r.h = vis[perm ? perm[k] : k];
   }
   return r;
 }
@@ -173,7 +186,9 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R, typename Acc>
+// With UNIT every visibility is 1 (vis is not read): the point-spread sums
+// sum_k cos 2 pi (A_k a + B_k b).
+template <typename R, typename Acc, bool UNIT = false>
 __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     int64_t L, int64_t natoms, int lgA, int64_t K, int64_t nwg, const double* __restrict__ AB,
     const cpx<R>* __restrict__ vis, const int32_t* __restrict__ perm,
@@ -197,7 +212,8 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
   const int nround = k1 > k0 ? (int)((k1 - k0 + T - 1) / T) : 0;
   VisRec<R> nxt[PER];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) nxt[q] = load_vis<R>(k0 + q * 64 + lane, k1, AB, vis, perm);
+  for (int q = 0; q < PER; ++q)
+    nxt[q] = load_vis<R, UNIT>(k0 + q * 64 + lane, k1, AB, vis, perm);
 #pragma unroll
   for (int q = 0; q < PER; ++q) stage[w][0][q * 64 + lane] = nxt[q];
   wave_sync();
@@ -210,14 +226,15 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     const int64_t kn = k0 + (int64_t)(j + 1) * T;
     if (j + 1 < nround) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) nxt[q] = load_vis<R>(kn + q * 64 + lane, k1, AB, vis, perm);
+      for (int q = 0; q < PER; ++q)
+        nxt[q] = load_vis<R, UNIT>(kn + q * 64 + lane, k1, AB, vis, perm);
     }
     const VisRec<R>* cur = stage[w][j & 1];
     for (int i = st; i < T; i += 4 * V) {  // 4 V <= T (V <= 32)
-      adj_pair<R, R>(cur[i], a, b, acc0);
-      adj_pair<R, R>(cur[i + V], a, b, acc1);
-      adj_pair<R, R>(cur[i + 2 * V], a, b, acc2);
-      adj_pair<R, R>(cur[i + 3 * V], a, b, acc3);
+      adj_pair<R, R, UNIT>(cur[i], a, b, acc0);
+      adj_pair<R, R, UNIT>(cur[i + V], a, b, acc1);
+      adj_pair<R, R, UNIT>(cur[i + 2 * V], a, b, acc2);
+      adj_pair<R, R, UNIT>(cur[i + 3 * V], a, b, acc3);
     }
     if constexpr (sizeof(Acc) != sizeof(R)) {
       tot0 += (Acc)acc0;
@@ -586,13 +603,21 @@ void adjoint_atoms_acc64(pc_plan* p, const c32* vis, int64_t natoms, const Atom<
                          double* partial, double* out, hipStream_t s) {
   if (natoms <= 0) return;
   const AdjShape sh = adjoint_shape(p->L, natoms);
-  {
+  const dim3 grid((unsigned)(sh.nwg * sh.ngroups));
+  if (vis) {
     ProfScope ps(p, s, "adjoint_sparse_acc64",
                  p->L * 24.0 * sh.ngroups + 8.0 * sh.nwg * natoms, (double)p->L * natoms);
-    hipLaunchKernelGGL((adjoint_sparse_kernel<float, double>),
-                       dim3((unsigned)(sh.nwg * sh.ngroups)), dim3(256), 0, s, p->L, natoms,
-                       sh.lgA, sh.K, sh.nwg, p->AB, vis, (const int32_t*)nullptr, atoms, partial);
+    hipLaunchKernelGGL((adjoint_sparse_kernel<float, double>), grid, dim3(256), 0, s, p->L,
+                       natoms, sh.lgA, sh.K, sh.nwg, p->AB, vis, (const int32_t*)nullptr, atoms,
+                       partial);
     PC_LAUNCH_CHECK("adjoint_sparse_acc64");
+  } else {  // unit visibilities: the point-spread sums
+    ProfScope ps(p, s, "psf_sums_acc64",
+                 p->L * 16.0 * sh.ngroups + 8.0 * sh.nwg * natoms, (double)p->L * natoms);
+    hipLaunchKernelGGL((adjoint_sparse_kernel<float, double, true>), grid, dim3(256), 0, s,
+                       p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, (const c32*)nullptr,
+                       (const int32_t*)nullptr, atoms, partial);
+    PC_LAUNCH_CHECK("psf_sums_acc64");
   }
   ProfScope ps(p, s, "adjoint_sparse_reduce", 8.0 * sh.nwg * natoms, (double)sh.nwg * natoms);
   hipLaunchKernelGGL((adjoint_sparse_reduce_kernel<double, float>), dim3((unsigned)natoms),

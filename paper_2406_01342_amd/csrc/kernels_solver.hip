@@ -460,11 +460,6 @@ __global__ __launch_bounds__(256) void gram_lanczos_full_kernel(
   }
 }
 
-__global__ void fill_cpx_kernel(int64_t n, float re, float im, c32* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = {re, im};
-}
-
 // An active set from one uploaded block [x: nS doubles][pix: nS int32]:
 // x = y = the weights, pix, and the atom table (pixel offsets, 1/n, forward
 // weight x/n; zero-weight phase-centre padding up to ntotal entries).
@@ -637,12 +632,6 @@ void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(zero_n_u32_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, n, out);
   PC_LAUNCH_CHECK("zero_u32");
-}
-
-void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(fill_cpx_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, n, re, im, out);
-  PC_LAUNCH_CHECK("fill_cpx");
 }
 
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s) {

@@ -178,7 +178,6 @@ struct Pfw {
   int last_lanczos = 0;         // Lanczos steps of the last step-size estimate
   DevArray<double> act_blk;  // uploaded [x | pix] of the active set
   DevArray<Atom<float>> off_atoms;
-  DevArray<c32> ones;
   double v2 = 0;  // ||V||^2
   Pinned up, down;  // upload staging, small readbacks
   std::vector<int32_t> S;
@@ -547,13 +546,8 @@ struct Pfw {
       up.arm(s);
       psf_partial.ensure(std::max(adjoint_partial_count(p, nm), adjoint_partial_count(p, nb)));
       psf_val.ensure(nm + nb);
-      if (nm) {
-        if (!ones.ptr) {
-          ones.ensure(L);
-          k_fill_cpx(p, L, 1.0f, 0.0f, ones.ptr, s);
-        }
-        adjoint_atoms_acc64(p, ones.ptr, nm, off_atoms.ptr, psf_partial.ptr, psf_val.ptr, s);
-      }
+      if (nm)  // unit visibilities (none are read): the point-spread sums
+        adjoint_atoms_acc64(p, nullptr, nm, off_atoms.ptr, psf_partial.ptr, psf_val.ptr, s);
       if (nb)
         adjoint_atoms_acc64(p, V.ptr, nb, off_atoms.ptr + nm, psf_partial.ptr, psf_val.ptr + nm,
                             s);

@@ -45,7 +45,6 @@ void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s);
 // and the padded atom table (atom_capacity(nS) entries).
 void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,
                 Atom<float>* atoms, hipStream_t s);
-void k_fill_cpx(pc_plan* p, int64_t n, float re, float im, c32* out, hipStream_t s);
 // Gridded-operator helpers for large active sets.
 void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, float* img,
                hipStream_t s);
