@@ -460,6 +460,107 @@ __global__ __launch_bounds__(256) void gram_lanczos_full_kernel(
   }
 }
 
+// Sum over the 64 lanes of a wave (every lane gets the same value: each
+// butterfly level adds a commutative pair).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same estimate as gram_lanczos_full_kernel for nS <= kLzWaveAtoms: the
+// four waves copy G and the start vector into LDS, then wave 0 alone runs the
+// steps, each lane owning rows lane and lane + 64, with every reduction a
+// wave butterfly (no workgroup barrier inside a step).  Same recurrence, test
+// and outputs; alpha and beta are kept in LDS for the tridiagonal solve and
+// copied to ab at the end.
+constexpr int kLzWaveAtoms = 128;
+__global__ __launch_bounds__(256) void gram_lanczos_wave_kernel(
+    int64_t nS, int kmax, double tol, double margin, const double* __restrict__ Gg,
+    const double* __restrict__ Qg, double* __restrict__ ab, double* __restrict__ out,
+    double* __restrict__ ritz) {
+  __shared__ double svec[kLzMaxRows];
+  __shared__ double al[kLzMaxRows], be[kLzMaxRows];
+  extern __shared__ double dyn[];
+  double* Q = dyn;                            // (kmax + 1) rows of nS
+  double* G = Q + (int64_t)(kmax + 1) * nS;   // nS x nS
+  copy_to_lds(Q, Qg, nS);
+  copy_to_lds(G, Gg, nS * nS);
+  __syncthreads();
+  if (threadIdx.x >= 64) return;  // wave 0 runs the steps
+  const int lane = threadIdx.x;
+  const int i0 = lane, i1 = lane + 64;
+  const bool r0 = i0 < nS, r1 = i1 < nS;
+  const int jmax = (int)(nS < kmax ? nS : kmax);
+  int k = 0;
+  double theta = 0, rho = 0;
+  for (int j = 0; j < jmax; ++j) {
+    const double* qj = Q + (int64_t)j * nS;
+    double w0 = r0 ? gram_col_dot(G, qj, nS, i0) : 0.0;
+    double w1 = r1 ? gram_col_dot(G, qj, nS, i1) : 0.0;
+    const double q0 = r0 ? qj[i0] : 0.0, q1 = r1 ? qj[i1] : 0.0;
+    const double a = wave_sum(q0 * w0 + q1 * w1);
+    const double bp = j > 0 ? be[j - 1] : 0.0;
+    const double* qp = j > 0 ? Q + (int64_t)(j - 1) * nS : qj;
+    w0 -= a * q0 + bp * (r0 ? qp[i0] : 0.0);
+    w1 -= a * q1 + bp * (r1 ? qp[i1] : 0.0);
+    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+      double h[kLzMaxRows];
+#pragma unroll
+      for (int q = 0; q < kLzMaxRows; ++q)
+        if (q <= j) {
+          const double* Qq = Q + (int64_t)q * nS;
+          h[q] = wave_sum((r0 ? Qq[i0] * w0 : 0.0) + (r1 ? Qq[i1] * w1 : 0.0));
+        }
+#pragma unroll
+      for (int q = 0; q < kLzMaxRows; ++q)
+        if (q <= j) {
+          const double* Qq = Q + (int64_t)q * nS;
+          if (r0) w0 -= h[q] * Qq[i0];
+          if (r1) w1 -= h[q] * Qq[i1];
+        }
+    }
+    const double b = sqrt(wave_sum(w0 * w0 + w1 * w1));
+    const double inv = b > 0 ? 1.0 / b : 0.0;
+    double* qn = Q + (int64_t)(j + 1) * nS;
+    if (r0) qn[i0] = w0 * inv;
+    if (r1) qn[i1] = w1 * inv;
+    if (lane == 0) {
+      al[j] = a;
+      be[j] = b;
+    }
+    lds_wave_sync();  // q_{j+1}, al, be visible to the wave
+    theta = tridiag_top(al, be, j + 1, svec);
+    lds_wave_sync();  // svec written by lane 0
+    const double bj = be[j];
+    rho = bj * fabs(svec[j]);
+    const bool invariant = bj <= 1e-14 * fmax(theta, 1e-300) || j + 1 >= nS;
+    k = j + 1;
+    if (invariant || rho <= tol * theta || j + 1 == kmax) break;
+  }
+  if (lane == 0) {
+    out[0] = (theta + rho) * margin;
+    out[1] = (double)k;
+    out[2] = theta;
+    out[3] = rho;
+  }
+  for (int q = lane; q < k; q += 64) {
+    ab[q] = al[q];
+    ab[kmax + q] = be[q];
+  }
+  for (int64_t i = lane; i < nS; i += 64) {
+    double v = 0;
+    for (int q = 0; q < k; ++q) v += svec[q] * Q[(int64_t)q * nS + i];
+    ritz[i] = v;
+  }
+}
+
 // An active set from one uploaded block [x: nS doubles][pix: nS int32]:
 // x = y = the weights, pix, and the atom table (pixel offsets, 1/n, forward
 // weight x/n; zero-weight phase-centre padding up to ntotal entries).
@@ -605,8 +706,18 @@ void k_gram_fista(pc_plan* p, int64_t nS, const double* G, const double* b, doub
 void k_gram_lanczos_full(pc_plan* p, int64_t nS, int kmax, double tol, double margin,
                          const double* G, const double* Q, double* ab, double* out, double* ritz,
                          hipStream_t s) {
-  // basis rows and w always in LDS; G too when it fits beside them
   constexpr size_t kLdsMax = 150 * 1024;
+  if (nS <= kLzWaveAtoms && kmax < kLzMaxRows) {  // one wave, basis and G in LDS
+    const size_t lds = (size_t)((kmax + 1) * nS + nS * nS) * 8;
+    PC_HIP(hipFuncSetAttribute((const void*)gram_lanczos_wave_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax));
+    ProfScope ps(p, s, "gram_lanczos", 8.0 * nS * (double)(nS + 30) * 4, (double)nS);
+    hipLaunchKernelGGL(gram_lanczos_wave_kernel, dim3(1), dim3(256), lds, s, nS, kmax, tol,
+                       margin, G, Q, ab, out, ritz);
+    PC_LAUNCH_CHECK("gram_lanczos_wave");
+    return;
+  }
+  // basis rows and w always in LDS; G too when it fits beside them
   const size_t base = (size_t)((kmax + 2) * nS) * 8;
   const bool g_in_lds = base + (size_t)nS * nS * 8 <= kLdsMax;
   const size_t lds = base + (g_in_lds ? (size_t)nS * nS * 8 : 0);
