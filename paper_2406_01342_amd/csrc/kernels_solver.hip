@@ -85,6 +85,24 @@ __global__ void select_kernel(int64_t N, const float* __restrict__ eta, float ta
   }
 }
 
+// The same selection with the threshold formed on the device from the fused
+// maximum key: tau = max - dec in FP64 (max decoded from the key's high 32
+// bits as the host does), rounded once to FP32, so that the next
+// exploration's candidates are ready with step 4's readback.
+__global__ void select_from_key_kernel(int64_t N, const float* __restrict__ eta,
+                                       const unsigned long long* __restrict__ key, double dec,
+                                       int positive, unsigned int* __restrict__ count,
+                                       int32_t* __restrict__ out, int64_t cap) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const float tau = (float)((double)__uint_as_float((unsigned)(key[0] >> 32)) - dec);
+  const float e = eta[j];
+  if (positive ? (e >= tau && e > 0.0f) : fabsf(e) >= tau) {
+    const unsigned int q = atomicAdd(count, 1u);
+    if ((int64_t)q < cap) out[q] = (int32_t)j;
+  }
+}
+
 __global__ void zero_u32_kernel(unsigned int* p) { *p = 0u; }
 
 __global__ void zero_n_u32_kernel(int64_t n, unsigned int* __restrict__ p) {
@@ -667,6 +685,16 @@ void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial,
   PC_LAUNCH_CHECK("resid_partial");
   hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(256), 0, s, nb, partial, out);
   PC_LAUNCH_CHECK("resid_final");
+}
+
+void k_select_from_key(pc_plan* p, int64_t N, const float* eta, const unsigned long long* key,
+                       double dec, bool positive, unsigned* count, int32_t* out, int64_t cap,
+                       hipStream_t s) {
+  ProfScope ps(p, s, "select", 4.0 * N, (double)N);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, count);
+  hipLaunchKernelGGL(select_from_key_kernel, dim3(blocks(N, 256)), dim3(256), 0, s, N, eta, key,
+                     dec, positive ? 1 : 0, count, out, cap);
+  PC_LAUNCH_CHECK("select_from_key");
 }
 
 void k_select(pc_plan* p, int64_t N, const float* eta, float tau, bool positive, unsigned* count,

@@ -50,6 +50,7 @@ struct DevArray {
 };
 
 constexpr int kCheck = 4;        // APGD convergence test cadence
+constexpr int64_t kFirstCandidates = 4096;  // candidates read back with their count
 // Pinned host staging for uploads and small readbacks.  Its copies are
 // asynchronous; `fence` records the stream position of the last use so that
 // the buffer is not rewritten while a copy from it may still be pending.
@@ -176,6 +177,10 @@ struct Pfw {
   DevArray<int> gram_done;  // {passed, step} of the device-side gap test
   int last_inner = 1 + kCheck;  // APGD steps of the last Gram-form solve
   int last_lanczos = 0;         // Lanczos steps of the last step-size estimate
+  // candidates of the next exploration selected with step 4's readback
+  std::vector<int32_t> pre_I;
+  int pre_k = -1;
+  bool pre_ok = false;
   DevArray<double> act_blk;  // uploaded [x | pix] of the active set
   DevArray<Atom<float>> off_atoms;
   double v2 = 0;  // ||V||^2
@@ -259,7 +264,11 @@ struct Pfw {
 
   // Step 4's dirty residual together with ||r||^2 and Re<V, r>: one host
   // synchronisation for the maximum, the argmax and both statistics.
-  void adjoint_and_stats(const c32* vis_sorted, double& r2, double& vr) {
+  // (Off the batcher, the exploration of iteration k_next is selected on the
+  // device right after this adjoint, from its maximum, and its candidates come
+  // back with the statistics: one host synchronisation for both.)
+  void adjoint_and_stats(const c32* vis_sorted, double& r2, double& vr, int k_next) {
+    pre_ok = false;
     if (batcher) {  // the batcher synchronises on its own
       adjoint_timed(vis_sorted);
       residual_stats(r2, vr);
@@ -272,14 +281,27 @@ struct Pfw {
     if (ms) dict_analysis(p, dict, eta.ptr, eta_ms.ptr, positive, p->maxkey, s);
     red_partial.ensure(2 * k_resid_blocks(L));
     k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
-    unsigned char* h = (unsigned char*)down.get(24);
+    k_select_from_key(p, NA, expl(), p->maxkey, 2.0 * Delta / (k_next + 2), positive,
+                      cand_count.ptr, cand.ptr, cand.cap, s);
+    const int64_t first = std::min<int64_t>(kFirstCandidates, cand.cap);
+    unsigned char* h = (unsigned char*)down.get(28 + first * 4);
     PC_HIP(hipMemcpyAsync(h, p->maxkey, 8, hipMemcpyDeviceToHost, s));
     PC_HIP(hipMemcpyAsync(h + 8, scal.ptr + kScalResid, 16, hipMemcpyDeviceToHost, s));
+    PC_HIP(hipMemcpyAsync(h + 24, cand_count.ptr, 4, hipMemcpyDeviceToHost, s));
+    PC_HIP(hipMemcpyAsync(h + 28, cand.ptr, first * 4, hipMemcpyDeviceToHost, s));
     PC_HIP(hipStreamSynchronize(s));
     unsigned long long key;
     double st[2];
+    unsigned cnt = 0;
     std::memcpy(&key, h, 8);
     std::memcpy(st, h + 8, 16);
+    std::memcpy(&cnt, h + 24, 4);
+    if ((int64_t)cnt <= first) {  // else step() selects again with a larger buffer
+      pre_I.resize(cnt);
+      if (cnt) std::memcpy(pre_I.data(), h + 28, (size_t)cnt * 4);
+      pre_k = k_next;
+      pre_ok = true;
+    }
     maxkey_decode(key, &eta_inf, &eta_argmax);
     r2 = st[0];
     vr = st[1];
@@ -424,11 +446,11 @@ struct Pfw {
 
   // Residual, dirty residual (and its maximum), objective and duality gap of
   // the iterate (S, xs): step 4 of Alg. 2, also run once for a warm start.
-  void assess() {
+  void assess(int k_next) {
     load_active(S, xs);
     op_forward(ms || (int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
     double r2, vr;
-    adjoint_and_stats(r.ptr, r2, vr);
+    adjoint_and_stats(r.ptr, r2, vr, k_next);
     double l1 = 0;
     for (double w : xs) l1 += std::fabs(w);
     P = 0.5 * r2 + lam * l1;
@@ -454,7 +476,7 @@ struct Pfw {
       S.push_back(a.first);
       xs.push_back(a.second);
     }
-    assess();
+    assess(0);
     P_prev = P;
     // a warm start that already meets the gap tolerance is the answer
     if (prm.rel_gap_tol > 0 && rel_gap <= prm.rel_gap_tol) {
@@ -700,14 +722,22 @@ struct Pfw {
 
   void step() {
     if (done) return;
-    // 1.a polyatomic exploration: threshold in FP64, compared in FP32
+    // 1.a polyatomic exploration: threshold in FP64, compared in FP32 (the
+    // candidates may already have come back with step 4's statistics)
     const double tau = eta_inf - 2.0 * Delta / (k + 2);
     const float tau_f = (float)tau;
     // the count and the first kFirst candidates come back in one copy pair
-    constexpr int64_t kFirst = 4096;
+    constexpr int64_t kFirst = kFirstCandidates;
     unsigned count = 0;
     std::vector<int32_t> I;
-    for (;;) {
+    bool have = false;
+    if (pre_ok && pre_k == k) {
+      I.swap(pre_I);
+      count = (unsigned)I.size();
+      have = true;
+    }
+    pre_ok = false;
+    while (!have) {
       k_select(p, NA, expl(), tau_f, positive, cand_count.ptr, cand.ptr, cand.cap, s);
       const int64_t first = std::min<int64_t>(kFirst, cand.cap);
       unsigned char* h = (unsigned char*)down.get(4 + first * 4);
@@ -727,7 +757,7 @@ struct Pfw {
                               hipMemcpyDeviceToHost, s));
         PC_HIP(hipStreamSynchronize(s));
       }
-      break;
+      have = true;
     }
     std::sort(I.begin(), I.end());
     // 1.b S u I with warm-start weights (new atoms at zero)
@@ -854,7 +884,7 @@ struct Pfw {
         xs.push_back(xw[a]);
       }
     // 4. residual, dirty residual, objective and gap
-    assess();
+    assess(k + 1);
     const double rel_imp = P_prev > 0 ? std::fabs(P - P_prev) / P_prev : 0.0;
     if (prm.log_every > 0 && (k % prm.log_every == 0))
       std::fprintf(stderr,

@@ -19,6 +19,10 @@ int k_resid_blocks(int64_t L);
 void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial, double* out, hipStream_t s);
 void k_select(pc_plan* p, int64_t N, const float* eta, float tau, bool positive, unsigned* count,
               int32_t* out, int64_t cap, hipStream_t s);
+// k_select with tau = (max decoded from *key) - dec formed on the device.
+void k_select_from_key(pc_plan* p, int64_t N, const float* eta, const unsigned long long* key,
+                       double dec, bool positive, unsigned* count, int32_t* out, int64_t cap,
+                       hipStream_t s);
 void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipStream_t s);
 // One Lanczos step (see lanczos_step_kernel): g = G q_j given; writes alpha_j,
 // beta_j into ab and q_{j+1} into row j + 1 of Q.
