@@ -478,6 +478,29 @@ __global__ __launch_bounds__(256) void gram_lanczos_full_kernel(
   }
 }
 
+// G, b and the Lanczos start vector of the Gram form from one uploaded block
+// [v0: nS doubles][inv_n: nS doubles][bslot: nS int32][pslot: nS^2 int32]:
+// G[a][c] = psf[pslot[a][c]] inv_n[a] inv_n[c], b[a] = bval[bslot[a]],
+// Q0 = v0 (psf and bval hold the solve's point-spread sums and b_p by slot).
+__global__ void gram_assemble_kernel(int64_t nS, const unsigned char* __restrict__ blk,
+                                     const double* __restrict__ psf,
+                                     const double* __restrict__ bval, double* __restrict__ G,
+                                     double* __restrict__ b, double* __restrict__ Q0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double* v0 = reinterpret_cast<const double*>(blk);
+  const double* inv_n = v0 + nS;
+  const int32_t* bslot = reinterpret_cast<const int32_t*>(blk + 16 * nS);
+  const int32_t* pslot = bslot + nS;
+  if (e < nS * nS) {
+    const int64_t a = e / nS, c = e - (e / nS) * nS;
+    G[e] = psf[pslot[e]] * inv_n[a] * inv_n[c];
+  }
+  if (e < nS) {
+    b[e] = bval[bslot[e]];
+    Q0[e] = v0[e];
+  }
+}
+
 // Sum over the 64 lanes of a wave (every lane gets the same value: each
 // butterfly level adds a commutative pair).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -757,6 +780,14 @@ void k_gram_lanczos_full(pc_plan* p, int64_t nS, int kmax, double tol, double ma
   hipLaunchKernelGGL(gram_lanczos_full_kernel, dim3(1), dim3(256), lds, s, nS, kmax, tol, margin,
                      G, Q, g_in_lds ? 1 : 0, ab, out, ritz);
   PC_LAUNCH_CHECK("gram_lanczos_full");
+}
+
+void k_gram_assemble(pc_plan* p, int64_t nS, const void* blk, const double* psf,
+                     const double* bval, double* G, double* b, double* Q0, hipStream_t s) {
+  if (nS <= 0) return;
+  hipLaunchKernelGGL(gram_assemble_kernel, dim3(blocks(nS * nS, 256)), dim3(256), 0, s, nS,
+                     (const unsigned char*)blk, psf, bval, G, b, Q0);
+  PC_LAUNCH_CHECK("gram_assemble");
 }
 
 void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,

@@ -49,6 +49,29 @@ struct DevArray {
   }
 };
 
+// Device FP64 table that keeps its contents when it grows (the old entries
+// are copied on the stream before the old allocation is released).
+struct KeepDevArray {
+  double* ptr = nullptr;
+  int64_t cap = 0;
+  void ensure(int64_t n, hipStream_t s) {
+    if (n <= cap && ptr) return;
+    const int64_t want = std::max<int64_t>(n, std::max<int64_t>(2 * cap, 1024));
+    double* np = nullptr;
+    PC_HIP(hipMalloc(&np, want * sizeof(double)));
+    if (ptr) {
+      PC_HIP(hipMemcpyAsync(np, ptr, cap * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PC_HIP(hipStreamSynchronize(s));
+      (void)hipFree(ptr);
+    }
+    ptr = np;
+    cap = want;
+  }
+  ~KeepDevArray() {
+    if (ptr) (void)hipFree(ptr);
+  }
+};
+
 constexpr int kCheck = 4;        // APGD convergence test cadence
 constexpr int64_t kFirstCandidates = 4096;  // candidates read back with their count
 // Pinned host staging for uploads and small readbacks.  Its copies are
@@ -168,11 +191,17 @@ struct Pfw {
   // Gram form of the restricted problem: G = Re(Phi_S^H Phi_S) and b = Phi_S^* V.
   // For coplanar arrays G_pq = psf(a_p - a_q, b_p - b_q) / (n_p n_q) with
   // psf(da, db) = sum_k cos 2 pi (A_k da + B_k db), kept per solve by offset.
-  std::unordered_map<uint64_t, double> psf;
-  std::unordered_map<int32_t, double> bcache;  // b_p by pixel
-  std::vector<int32_t> g_set;                  // the set of the last G, and G
-  std::vector<double> g_host;
-  DevArray<double> gram_blk, psf_val, psf_partial;
+  // The point-spread sums and b_p stay on the device, in tables indexed by
+  // slot; the host keeps the slot of every offset and pixel seen in this
+  // solve, and the slot table of the last G (pairs of atoms both there keep
+  // theirs), so that G is gathered on the device without a readback.
+  std::unordered_map<uint64_t, int32_t> psf_slot;
+  std::unordered_map<int32_t, int32_t> b_slot;  // by pixel
+  std::vector<int32_t> g_set;                   // the set of the last G, and its slots
+  std::vector<int32_t> g_slots;
+  KeepDevArray psf_dev, b_dev;
+  int64_t n_psf = 0, n_b = 0;
+  DevArray<double> gram_blk, psf_partial, asm_blk;
   double *gram_G = nullptr, *gram_b = nullptr, *gram_Q = nullptr;  // inside gram_blk
   DevArray<int> gram_done;  // {passed, step} of the device-side gap test
   int last_inner = 1 + kCheck;  // APGD steps of the last Gram-form solve
@@ -184,7 +213,7 @@ struct Pfw {
   DevArray<double> act_blk;  // uploaded [x | pix] of the active set
   DevArray<Atom<float>> off_atoms;
   double v2 = 0;  // ||V||^2
-  Pinned up, down;  // upload staging, small readbacks
+  Pinned up, up_act, down;  // upload staging (Gram form, active set), small readbacks
   std::vector<int32_t> S;
   std::vector<double> xs;
   std::vector<int32_t> pv_set;  // last power-iteration eigenvector (warm start)
@@ -351,11 +380,11 @@ struct Pfw {
     if (nS == 0) return;
     // one upload and one kernel: x = y = weights, pix, atom table
     act_blk.ensure((nS * 12 + 7) / 8);
-    unsigned char* h = (unsigned char*)up.get(nS * 12);
+    unsigned char* h = (unsigned char*)up_act.get(nS * 12);
     std::memcpy(h, xs_host.data(), nS * 8);
     std::memcpy(h + nS * 8, set.data(), nS * 4);
     PC_HIP(hipMemcpyAsync(act_blk.ptr, h, nS * 12, hipMemcpyHostToDevice, s));
-    up.arm(s);
+    up_act.arm(s);
     k_activate(p, nS, act_blk.ptr, x.ptr, y.ptr, pix.ptr, atoms.ptr, s);
   }
 
@@ -532,80 +561,87 @@ struct Pfw {
         ++c;
       }
     }
+    // the slot of every pair's offset: kept from the last G, else looked up,
+    // a new offset getting the next slot
     std::vector<std::pair<int, int>> miss;
-    for (int64_t a = 0; a < nS; ++a)
-      for (int64_t c = a; c < nS; ++c) {
-        if (old[a] >= 0 && old[c] >= 0) continue;
-        int da = ai[a] - ai[c], db = bi[a] - bi[c];
-        if (psf.emplace(offset_key(da, db), std::numeric_limits<double>::quiet_NaN()).second) {
-          if (da < 0 || (da == 0 && db < 0)) {
-            da = -da;
-            db = -db;
-          }
-          miss.emplace_back(da, db);
-        }
-      }
-    std::vector<int64_t> bmiss;  // atoms whose b_p is not known yet
-    for (int64_t q = 0; q < nS; ++q)
-      if (!bcache.count(set[q])) bmiss.push_back(q);
-    const int64_t nm = (int64_t)miss.size(), nb = (int64_t)bmiss.size();
-    if (nm + nb > kGramNewPairs * nS) {
-      for (const auto& o : miss) psf.erase(offset_key(o.first, o.second));
-      return false;
-    }
-    if (nm + nb > 0) {
-      // one table: the offsets (unit amplitude, n = 1), then the new atoms
-      Atom<float>* h = (Atom<float>*)up.get((nm + nb) * sizeof(Atom<float>));
-      for (int64_t m = 0; m < nm; ++m)
-        h[m] = Atom<float>{(double)miss[m].first, (double)miss[m].second, 1.0, 0.f, 0.f};
-      for (int64_t t = 0; t < nb; ++t) {
-        const int64_t q = bmiss[t];
-        h[nm + t] = Atom<float>{(double)ai[q], (double)bi[q], inv_n[q], 0.f, 0.f};
-      }
-      off_atoms.ensure(nm + nb);
-      PC_HIP(hipMemcpyAsync(off_atoms.ptr, h, (nm + nb) * sizeof(Atom<float>),
-                            hipMemcpyHostToDevice, s));
-      up.arm(s);
-      psf_partial.ensure(std::max(adjoint_partial_count(p, nm), adjoint_partial_count(p, nb)));
-      psf_val.ensure(nm + nb);
-      if (nm)  // unit visibilities (none are read): the point-spread sums
-        adjoint_atoms_acc64(p, nullptr, nm, off_atoms.ptr, psf_partial.ptr, psf_val.ptr, s);
-      if (nb)
-        adjoint_atoms_acc64(p, V.ptr, nb, off_atoms.ptr + nm, psf_partial.ptr, psf_val.ptr + nm,
-                            s);
-      double* d = (double*)down.get((nm + nb) * 8);
-      PC_HIP(hipMemcpyAsync(d, psf_val.ptr, (nm + nb) * 8, hipMemcpyDeviceToHost, s));
-      PC_HIP(hipStreamSynchronize(s));
-      for (int64_t m = 0; m < nm; ++m) psf[offset_key(miss[m].first, miss[m].second)] = d[m];
-      for (int64_t t = 0; t < nb; ++t) bcache[set[bmiss[t]]] = d[nm + t];
-    }
-    // G (row-major) and b in one upload; the host keeps G for the next set
-    std::vector<double> Gn((size_t)nS * nS);
+    std::vector<int32_t> slots((size_t)nS * nS);
     const int64_t no = (int64_t)g_set.size();
     for (int64_t a = 0; a < nS; ++a)
       for (int64_t c = a; c < nS; ++c) {
-        const double v =
-            (old[a] >= 0 && old[c] >= 0)
-                ? g_host[(size_t)old[a] * no + old[c]]
-                : psf.at(offset_key(ai[a] - ai[c], bi[a] - bi[c])) * inv_n[a] * inv_n[c];
-        Gn[(size_t)a * nS + c] = v;
-        Gn[(size_t)c * nS + a] = v;
+        int32_t sl;
+        if (old[a] >= 0 && old[c] >= 0) {
+          sl = g_slots[(size_t)old[a] * no + old[c]];
+        } else {
+          int da = ai[a] - ai[c], db = bi[a] - bi[c];
+          const auto ins =
+              psf_slot.emplace(offset_key(da, db), (int32_t)(n_psf + (int64_t)miss.size()));
+          if (ins.second) {
+            if (da < 0 || (da == 0 && db < 0)) {
+              da = -da;
+              db = -db;
+            }
+            miss.emplace_back(da, db);
+          }
+          sl = ins.first->second;
+        }
+        slots[(size_t)a * nS + c] = sl;
+        slots[(size_t)c * nS + a] = sl;
       }
-    g_set = set;
-    g_host.swap(Gn);
-    // one device block [G | b | Lanczos basis rows], G, b and the start
-    // vector uploaded together
+    std::vector<int64_t> bmiss;  // atoms whose b_p is not known yet
+    for (int64_t q = 0; q < nS; ++q)
+      if (!b_slot.count(set[q])) bmiss.push_back(q);
+    const int64_t nm = (int64_t)miss.size(), nb = (int64_t)bmiss.size();
+    if (nm + nb > kGramNewPairs * nS) {
+      for (const auto& o : miss) psf_slot.erase(offset_key(o.first, o.second));
+      return false;
+    }
+    for (int64_t t = 0; t < nb; ++t) b_slot[set[bmiss[t]]] = (int32_t)(n_b + t);
+    // one upload: [offset / atom table | v0 | inv_n | b slots | pair slots]
     const std::vector<double> v0 = lanczos_start(set);
+    const size_t tbytes = (size_t)(nm + nb) * sizeof(Atom<float>);
+    const size_t abytes = (size_t)(16 * nS + 4 * nS + 4 * nS * nS);
+    unsigned char* h = (unsigned char*)up.get(tbytes + abytes);
+    Atom<float>* at = (Atom<float>*)h;
+    for (int64_t m = 0; m < nm; ++m)
+      at[m] = Atom<float>{(double)miss[m].first, (double)miss[m].second, 1.0, 0.f, 0.f};
+    for (int64_t t = 0; t < nb; ++t) {
+      const int64_t q = bmiss[t];
+      at[nm + t] = Atom<float>{(double)ai[q], (double)bi[q], inv_n[q], 0.f, 0.f};
+    }
+    unsigned char* blk = h + tbytes;
+    std::memcpy(blk, v0.data(), (size_t)nS * 8);
+    std::memcpy(blk + 8 * nS, inv_n.data(), (size_t)nS * 8);
+    int32_t* bs = (int32_t*)(blk + 16 * nS);
+    for (int64_t a = 0; a < nS; ++a) bs[a] = b_slot.at(set[a]);
+    std::memcpy(bs + nS, slots.data(), (size_t)nS * nS * 4);
+    if (nm + nb > 0) {
+      off_atoms.ensure(nm + nb);
+      PC_HIP(hipMemcpyAsync(off_atoms.ptr, at, tbytes, hipMemcpyHostToDevice, s));
+    }
+    asm_blk.ensure((int64_t)((abytes + 7) / 8));
+    PC_HIP(hipMemcpyAsync(asm_blk.ptr, blk, abytes, hipMemcpyHostToDevice, s));
+    up.arm(s);
+    if (nm + nb > 0) {  // new sums, written straight into their slots
+      psf_dev.ensure(n_psf + nm, s);
+      b_dev.ensure(n_b + nb, s);
+      psf_partial.ensure(std::max(adjoint_partial_count(p, nm), adjoint_partial_count(p, nb)));
+      if (nm)  // unit visibilities (none are read): the point-spread sums
+        adjoint_atoms_acc64(p, nullptr, nm, off_atoms.ptr, psf_partial.ptr, psf_dev.ptr + n_psf,
+                            s);
+      if (nb)
+        adjoint_atoms_acc64(p, V.ptr, nb, off_atoms.ptr + nm, psf_partial.ptr, b_dev.ptr + n_b,
+                            s);
+      n_psf += nm;
+      n_b += nb;
+    }
+    g_set = set;
+    g_slots.swap(slots);
+    // G, b and the Lanczos start vector gathered on the device
     gram_blk.ensure(nS * nS + nS + (int64_t)(kLanczosMax + 1) * nS);
     gram_G = gram_blk.ptr;
     gram_b = gram_G + nS * nS;
     gram_Q = gram_b + nS;
-    double* G = (double*)up.get((nS * nS + 2 * nS) * 8);
-    std::memcpy(G, g_host.data(), (size_t)nS * nS * 8);
-    for (int64_t a = 0; a < nS; ++a) G[nS * nS + a] = bcache.at(set[a]);
-    std::memcpy(G + nS * nS + nS, v0.data(), nS * 8);
-    PC_HIP(hipMemcpyAsync(gram_blk.ptr, G, (nS * nS + 2 * nS) * 8, hipMemcpyHostToDevice, s));
-    up.arm(s);
+    k_gram_assemble(p, nS, asm_blk.ptr, psf_dev.ptr, b_dev.ptr, gram_G, gram_b, gram_Q, s);
     return true;
   }
 

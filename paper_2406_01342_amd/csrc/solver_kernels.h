@@ -45,6 +45,10 @@ void k_gram_lanczos_full(pc_plan* p, int64_t nS, int kmax, double tol, double ma
                          const double* G, const double* Q, double* ab, double* out, double* ritz,
                          hipStream_t s);
 void k_zero_u32(pc_plan* p, int64_t n, unsigned* out, hipStream_t s);
+// G, b and the Lanczos start vector from one device block (see
+// gram_assemble_kernel) and the per-solve point-spread / b tables.
+void k_gram_assemble(pc_plan* p, int64_t nS, const void* blk, const double* psf,
+                     const double* bval, double* G, double* b, double* Q0, hipStream_t s);
 // Active set from one device block [x: nS doubles][pix: nS int32]: x, y, pix
 // and the padded atom table (atom_capacity(nS) entries).
 void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,
