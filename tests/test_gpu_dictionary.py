@@ -197,3 +197,21 @@ def test_adjoint_grid_ms_full_c3_sampled():
     err = rel_l2(np.array(got), np.array(want))
     say("full c3 dictionary samples", len(samples), "rel L2", err)
     assert err <= 1e-4
+
+
+def test_dictionary_warm_start_from_the_solution():
+    """x0 holds synthesis atoms (s n^2 + p): from the converged solution the
+    gap test passes at once with the same objective."""
+    p, vis = _diffuse(32)
+    kw = dict(alpha=0.05, delta=0.99, max_iter=300, rel_gap_tol=1e-4)
+    a = api()
+    plan = a.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    dv = to_dev(vis)
+    cold = a.pc_polyclean_solve(plan, dv, scales=STEEP, **kw)
+    assert cold["converged"] == 1 and np.any(cold["pix"] >= p.npix ** 2)
+    warm = a.pc_polyclean_solve(plan, dv, scales=STEEP, x0=(cold["pix"], cold["weight"]), **kw)
+    say("cold", cold["iters"], cold["objective"], "warm", warm["iters"], warm["objective"])
+    assert warm["converged"] == 1 and warm["iters"] == 0
+    assert abs(warm["objective"] - cold["objective"]) <= 1e-6 * cold["objective"]
+    with pytest.raises(a.PolycleanError):  # an atom past the last scale
+        a.pc_polyclean_solve(plan, dv, scales=STEEP, x0=([4 * p.npix ** 2], [1.0]), **kw)
