@@ -102,3 +102,28 @@ def test_metres_conversion_matches_wavelengths():
     f1 = _fp(UV * lam, uv_units=1, freq_hz=150e6)
     f2 = _fp(UV)
     assert f1 == f2
+
+
+def test_solve_params_marshalling():
+    """The binding's solve parameters on the host: defaults from the library,
+    the dictionary's scales and the warm start laid out as the header states,
+    and malformed inputs refused before any call."""
+    from paper_2406_01342_amd import api
+    p = api.solve_params()
+    assert (p.alpha, p.delta, p.max_iter, p.inner_max_iter) == (0.01, 0.99, 50, 2000)
+    assert p.n_scales == 0 and p.x0_n == 0 and p.positivity == 0
+    sig, gam = [0.0, 2.0, 5.0, 8.0], [1.2 ** s for s in range(4)]
+    atoms, w = np.array([3, 70000, 9], np.int64), np.array([1.0, 0.5, -2.0])
+    p = api.solve_params(scales=(sig, gam), x0=(atoms, w), positivity=1, lam=3.0)
+    assert p.n_scales == 4 and list(p.scale_sigma)[:4] == sig and list(p.scale_gamma)[:4] == gam
+    assert p.x0_n == 3 and [p.x0_pix[i] for i in range(3)] == [3, 70000, 9]
+    assert [p.x0_w[i] for i in range(3)] == [1.0, 0.5, -2.0]
+    assert p.positivity == 1 and p.lambda_ == 3.0
+    with pytest.raises(ValueError):
+        api.solve_params(scales=([0.0, 1.0], [1.0]))
+    with pytest.raises(ValueError):
+        api.solve_params(scales=([0.0] * 9, [1.0] * 9))
+    with pytest.raises(ValueError):
+        api.solve_params(x0=([1, 2], [1.0]))
+    with pytest.raises(KeyError):
+        api.solve_params(no_such_field=1)
