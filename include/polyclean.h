@@ -193,6 +193,22 @@ PC_API pc_status pc_restricted_gradient(pc_plan* plan, const void* vis, int64_t 
                                         const int32_t* pix, const float* weight, double* grad,
                                         void* resid, void* stream);
 
+/* pc_restricted_gradient for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and bit-identical results, but the
+ * atom table and the partial sums live in a fixed device array of 8 MiB per
+ * GPU (held from the first call on that GPU until the process ends) instead
+ * of plan scratch grown on demand.  The call makes no device allocation.
+ * Limit: 32 B per atom (rounded up to 8 atoms) plus 8 B per atom and
+ * partial-sum slot (a few hundred slots per atom at most) must fit the 8 MiB;
+ * larger requests return PC_ERR_UNSUPPORTED with the size needed.  Every call
+ * on one GPU shares that array, so calls that overlap on one GPU (other
+ * streams, other threads) race; serialise them.  The plan's instrumentation
+ * (pc_plan_profile) must be off: PC_ERR_INVALID_ARG otherwise. */
+PC_API pc_status pc_restricted_gradient_noalloc(pc_plan* plan, const void* vis, int64_t natoms,
+                                                const int32_t* pix, const float* weight,
+                                                double* grad, void* resid, void* stream);
+
 /* Dual certificate mu = Phi*(V - Phi x) / lambda (Eq. dual_certif) of the
  * sparse image x = (pix, weight).  vis dev complex64 [nvis] caller order;
  * cert dev float [npix*npix]; lambda > 0; max_abs/argmax as for

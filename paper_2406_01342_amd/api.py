@@ -240,6 +240,23 @@ def pc_restricted_gradient(plan: Plan, vis: torch.Tensor, pix: torch.Tensor, wei
     return (grad, resid) if want_resid else grad
 
 
+def pc_restricted_gradient_noalloc(plan: Plan, vis: torch.Tensor, pix: torch.Tensor,
+                                   weight: torch.Tensor, grad: torch.Tensor,
+                                   resid: Optional[torch.Tensor] = None, stream=None):
+    """pc_restricted_gradient without device allocation: grad (float64
+    [natoms]) and resid (complex64 [nvis] or None) are caller-allocated; the
+    library's scratch is a fixed per-device array."""
+    na = int(pix.numel())
+    check(LIB.pc_restricted_gradient_noalloc(
+        plan.handle, C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")), na,
+        C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+        C.c_void_p(_dev(weight, torch.float32, na, "weight")),
+        C.c_void_p(_dev(grad, torch.float64, na, "grad")),
+        C.c_void_p(_dev(resid, torch.complex64, plan.nvis, "resid") if resid is not None else None),
+        C.c_void_p(_stream(stream))), "pc_restricted_gradient_noalloc")
+    return grad, resid
+
+
 def pc_dual_certificate(plan: Plan, vis: torch.Tensor, pix: torch.Tensor, weight: torch.Tensor,
                         lam: float, cert: Optional[torch.Tensor] = None, want_max: bool = True,
                         stream=None):

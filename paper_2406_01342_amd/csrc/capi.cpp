@@ -285,6 +285,22 @@ pc_status pc_restricted_gradient(pc_plan* p, const void* vis, int64_t natoms, co
   });
 }
 
+pc_status pc_restricted_gradient_noalloc(pc_plan* p, const void* vis, int64_t natoms,
+                                         const int32_t* pix, const float* weight, double* grad,
+                                         void* resid, void* stream) {
+  return guard("pc_restricted_gradient_noalloc", [&] {
+    check_plan(p, PC_PREC_FP32);
+    check_atoms(p, natoms, pix, weight, true);
+    PC_REQUIRE(vis != nullptr, "vis is NULL");
+    if (natoms > 0) PC_REQUIRE(grad != nullptr, "grad is NULL");
+    PC_REQUIRE(resid == nullptr || resid != vis, "resid must not alias vis");
+    set_device(p);
+    restricted_gradient_noalloc(p, (const c32*)vis, natoms, pix, weight, grad, (c32*)resid,
+                                (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
 pc_status pc_dual_certificate(pc_plan* p, const void* vis, int64_t natoms, const int32_t* pix,
                               const float* weight, double lambda, float* cert, double* max_abs,
                               int64_t* argmax, void* stream) {

@@ -337,6 +337,15 @@ void forward_adjoint_atoms(pc_plan* p, int64_t natoms, const Atom<float>* atoms,
 // order throughout); one pass for 1..64 atoms, else forward then adjoint.
 void restricted_gradient(pc_plan* p, const cpx<float>* vis, int64_t natoms, const int32_t* pix,
                          const float* weight, double* out, cpx<float>* resid, hipStream_t s);
+// The same with the atom table and partial sums in a fixed per-device array of
+// kNoAllocScratchBytes (no device allocation); fails with PC_ERR_UNSUPPORTED
+// when restricted_gradient_scratch_bytes exceeds it.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+size_t restricted_gradient_scratch_bytes(const pc_plan* p, int64_t natoms);
+void restricted_gradient_noalloc(pc_plan* p, const cpx<float>* vis, int64_t natoms,
+                                 const int32_t* pix, const float* weight, double* out,
+                                 cpx<float>* resid, hipStream_t s);
 int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms);
 // Partials per atom of adjoint_atoms (out == NULL leaves them unsummed).
 int64_t adjoint_partial_stride(const pc_plan* p, int64_t natoms);

@@ -12,6 +12,8 @@
 #include <cstring>
 
 #include <atomic>
+#include <mutex>
+#include <string>
 
 #include "common.h"
 
@@ -634,17 +636,13 @@ void forward_sparse(pc_plan* p, int64_t natoms, const int32_t* pix, const R* wei
   forward_atoms<R>(p, natoms, atoms, vis_base, base_sorted, out, out_sorted, s);
 }
 
-void restricted_gradient(pc_plan* p, const c32* vis, int64_t natoms, const int32_t* pix,
-                         const float* weight, double* out, c32* resid, hipStream_t s) {
-  if (natoms == 0) {  // r = V
-    if (resid)
-      PC_HIP(hipMemcpyAsync(resid, vis, p->L * sizeof(c32), hipMemcpyDeviceToDevice, s));
-    return;
-  }
-  Atom<float>* atoms =
-      (Atom<float>*)ensure_atom_scratch(p, atom_capacity(natoms) * sizeof(Atom<float>));
+// The restricted gradient on caller-provided scratch: `atoms` holds
+// atom_capacity(natoms) entries and `partial` adjoint_partial_count doubles.
+static void restricted_gradient_on(pc_plan* p, const c32* vis, int64_t natoms,
+                                   const int32_t* pix, const float* weight, double* out,
+                                   c32* resid, Atom<float>* atoms, double* partial,
+                                   hipStream_t s) {
   prep_atoms_into<float>(p, natoms, pix, weight, atoms, s);
-  double* partial = ensure_red_scratch(p, (size_t)adjoint_partial_count(p, natoms));
   if (fused_supported(natoms)) {
     forward_adjoint_atoms(p, natoms, atoms, vis, resid, partial, s, true);
     reduce_partials<float>(p, natoms, fused_partial_stride(p, natoms), partial, atoms, out, s);
@@ -654,6 +652,82 @@ void restricted_gradient(pc_plan* p, const c32* vis, int64_t natoms, const int32
   c32* r = resid ? resid : (c32*)p->vis_scratch;
   forward_atoms<float>(p, natoms, atoms, vis, false, r, resid == nullptr, s);
   adjoint_atoms<float>(p, r, resid == nullptr, natoms, atoms, partial, out, s);
+}
+
+void restricted_gradient(pc_plan* p, const c32* vis, int64_t natoms, const int32_t* pix,
+                         const float* weight, double* out, c32* resid, hipStream_t s) {
+  if (natoms == 0) {  // r = V
+    if (resid)
+      PC_HIP(hipMemcpyAsync(resid, vis, p->L * sizeof(c32), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  Atom<float>* atoms =
+      (Atom<float>*)ensure_atom_scratch(p, atom_capacity(natoms) * sizeof(Atom<float>));
+  double* partial = ensure_red_scratch(p, (size_t)adjoint_partial_count(p, natoms));
+  restricted_gradient_on(p, vis, natoms, pix, weight, out, resid, atoms, partial, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free restricted gradient, for callers that cannot allocate
+// device memory (code under graph capture, tight serving loops).  The atom
+// table and the partial sums, which restricted_gradient keeps in plan scratch
+// grown on demand, live here in one fixed device array instead.  Each device
+// holds its own copy until the process ends; the host reaches it only through
+// the address hipGetSymbolAddress returns on that device.  Every call on a
+// device shares the array, so calls that overlap on one device race.  Nothing
+// in it needs clearing: each call writes every entry it reads first (the atom
+// table by atom_prep_kernel, each partial by the workgroup or wave owning it).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device.
+static unsigned char* scratch_on_device() {
+  int dev = 0;
+  PC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    fail(PC_ERR_UNSUPPORTED, "device index " + std::to_string(dev) + " beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(PC_ERR_DEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[dev]);
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t restricted_gradient_scratch_bytes(const pc_plan* p, int64_t natoms) {
+  if (natoms <= 0) return 0;
+  return round256((size_t)atom_capacity(natoms) * sizeof(Atom<float>)) +
+         (size_t)adjoint_partial_count(p, natoms) * sizeof(double);
+}
+
+void restricted_gradient_noalloc(pc_plan* p, const c32* vis, int64_t natoms, const int32_t* pix,
+                                 const float* weight, double* out, c32* resid, hipStream_t s) {
+  if (p->prof.on)
+    fail(PC_ERR_INVALID_ARG, "the plan's instrumentation must be off (it creates HIP events)");
+  if (natoms == 0) {  // r = V
+    if (resid)
+      PC_HIP(hipMemcpyAsync(resid, vis, p->L * sizeof(c32), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  const size_t need = restricted_gradient_scratch_bytes(p, natoms);
+  if (need > kNoAllocScratchBytes)
+    fail(PC_ERR_UNSUPPORTED, std::to_string(natoms) + " atoms over " + std::to_string(p->L) +
+                                 " visibilities need " + std::to_string(need) +
+                                 " bytes of scratch, more than the fixed " +
+                                 std::to_string(kNoAllocScratchBytes));
+  unsigned char* base = scratch_on_device();
+  Atom<float>* atoms = reinterpret_cast<Atom<float>*>(base);
+  double* partial = reinterpret_cast<double*>(
+      base + round256((size_t)atom_capacity(natoms) * sizeof(Atom<float>)));
+  restricted_gradient_on(p, vis, natoms, pix, weight, out, resid, atoms, partial, s);
 }
 
 template <typename R>
