@@ -276,3 +276,31 @@ def test_positive_exploration_takes_the_signed_maximum():
     r1 = solver.pfw_solve(uv, n, fov, V, alpha=0.1, delta=1.0, max_iter=1, positivity=True)
     assert r1.pix.tolist() == [int(np.argmax(dirty))]
     assert r1.log[0].n_new == 1
+
+
+def test_argmax_tie_rule_lowest_flat_index():
+    """The certificate / dirty-image peak rule (reading R15): the largest
+    |value| wins and, among exact ties, the lowest flat index; the sign does
+    not break a tie.  Hand-built images whose answer is read off by eye."""
+    img = np.zeros((4, 4))
+    img[1, 1] = -3.0          # flat 5
+    img[0, 2] = 2.9999999     # flat 2: smaller, earlier
+    img[3, 0] = 3.0           # flat 12: ties with flat 5
+    assert solver.argmax_abs(img) == (3.0, 5)
+    img[0, 3] = 3.0           # flat 3 now ties too and comes first
+    assert solver.argmax_abs(img) == (3.0, 3)
+    assert solver.argmax_abs(np.zeros((8, 8))) == (0.0, 0)   # every pixel ties
+    assert solver.argmax_abs(-np.ones(7)) == (1.0, 0)
+
+
+def test_argmax_tie_of_a_zero_residual_certificate():
+    """An exact tie reached through the operator: visibilities equal to the
+    model's own forward leave a zero residual, so the certificate is zero
+    everywhere and the peak is flat index 0."""
+    uv, n, fov, _ = _problem(8)
+    pix = np.array([3, n * n // 2 + 7])
+    w = np.array([1.5, -0.25])
+    V = operator.forward(uv, n, fov, pix, w)
+    mu = solver.certificate(uv, n, fov, V, pix, w, lam=0.3)
+    assert np.all(mu == 0.0)
+    assert solver.argmax_abs(mu) == (0.0, 0)
