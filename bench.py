@@ -181,6 +181,10 @@ def parse():
                     help="skip the adjoint measurements at the 4096^2 and 8192^2 workloads")
     ap.add_argument("--dictionary-only", action="store_true",
                     help="run only the synthesis-dictionary adjoint at 4096^2 and print its JSON")
+    ap.add_argument("--adjoint-only", choices=("c2", "c3", "c5l"),
+                    help="run only the gridded adjoint (caller-order input) at one workload, "
+                         "--adjoint-reps times after 3 warm-up calls, and print its JSON "
+                         "(for profiler runs)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_KERNEL.json from two rocprofv3 --pmc runs")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"),
@@ -431,6 +435,17 @@ def main():
 
     torch.cuda.set_device(0)
     copy_probe(torch)
+    if args.adjoint_only:
+        cfg = {"c2": (sim.config_c2, "LOFAR-like workload: 424,800 visibilities, 1024^2"),
+               "c3": (sim.config_c3, "precision workload: 256 stations, 2,088,960 "
+                                     "visibilities, 4096^2, FOV 3 deg"),
+               "c5l": (sim.config_c5_large, "memory-pressure large job: 512 stations x 16 "
+                                            "snapshots x 4 channels, 8,372,224 visibilities, "
+                                            "8192^2 (16384^2 fine grid), FOV 3 deg")}
+        make, label = cfg[args.adjoint_only]
+        print(json.dumps({"adjoint": adjoint_at(api, torch, make(), args.adjoint_reps, label)}),
+              flush=True)
+        return
     if args.dictionary_only:
         print(json.dumps({"dictionary": dictionary_leg(api, torch, max(5, args.adjoint_reps // 4),
                                                        with_solve=False)}), flush=True)

@@ -253,7 +253,7 @@ PC_API pc_status pc_adjoint_grid_batch(pc_plan* const* plans, const void* const*
                                        int64_t* argmax, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Adjoint of the synthesis form (Sect. 3.2, Eq. lasso-synthesis): images =
+ * Adjoint of the synthesis form (Sect. 4.3, Eq. lasso-synthesis): images =
  * Psi* Phi* vis for the Gaussian dictionary described at pc_solve_params
  * (n_scales in [1, 8], sigma / gamma host arrays of n_scales doubles).
  * vis: dev complex64 [nvis] caller order; images: dev float
@@ -279,7 +279,7 @@ typedef struct {
   double inner_tol_min;   /*   duality gap <= max(inner_tol_min, inner_tol0 g), */
                           /*   g = the full problem's relative gap at x_k     */
   int32_t inner_max_iter; /* APGD iteration cap per FW iteration              */
-  int32_t positivity;     /* 1: x >= 0 (positivity remarks, Sects. 3.1, 5.1): */
+  int32_t positivity;     /* 1: x >= 0 (positivity remarks, Sects. 4.1, 5.1): */
                           /*   lambda_max = max(0, max Phi* V), candidates    */
                           /*   only where eta >= tau and eta > 0, the prox    */
                           /*   max(0, z - t), the dual point scaled by the    */
@@ -300,7 +300,7 @@ typedef struct {
                           /*   operators in each APGD and Lanczos step: 0 =   */
                           /*   256, < 0 = never, at most 1024.                */
   int32_t n_scales;       /* 0: point atoms (Eq. lasso).  1..8: the synthesis */
-                          /*   form (Sect. 3.2, Eq. lasso-synthesis) over the */
+                          /*   form (Sect. 4.3, Eq. lasso-synthesis) over the */
                           /*   Gaussian dictionary of Sect. 6.4: element s is */
                           /*   gamma_s g~_s, g~_s[a,b] ~ exp(-(a^2+b^2)/      */
                           /*   sigma_s^2) for |a|,|b| <= floor(2 sigma_s),    */

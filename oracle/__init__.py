@@ -17,7 +17,7 @@ Estimation in Radio Interferometry"):
   solver    LASSO objective (Eq. lasso), lambda_max and lambda = alpha
             lambda_max (Eqs. lmax, lambda), dual certificate (Eq. dual_certif),
             the Polyatomic Frank-Wolfe iteration (Alg. 2) with an APGD/FISTA
-            restricted solve on the active set (Sect. 3.4 and Sect. 5.1), and
+            restricted solve on the active set (Sect. 4.4 and Sect. 5.1), and
             a standard LASSO duality gap.
   brute     cyclic coordinate descent on the explicit real measurement matrix,
             for tiny problems (an independent route to the LASSO minimiser).

@@ -8,7 +8,7 @@ minimised exactly in turn:
 with r = y - A x kept up to date.  Iterates until the relative duality gap is
 below ``gap_tol``.  Shares nothing with the Frank-Wolfe route.  With
 ``positive`` the coordinates are kept non-negative (the positivity-constrained
-LASSO of the positivity remarks in Sects. 3.1 and 5.1):
+LASSO of the positivity remarks in Sects. 4.1 and 5.1):
 x_j <- max(0, x_j + (a_j^T r - lambda) / ||a_j||^2), and the dual point is
 scaled by the largest positive correlation.
 """

@@ -1,6 +1,6 @@
 """Multi-scale synthesis dictionary (TEST INFRASTRUCTURE; oracle).
 
-Sect. 3.2 (synthesis form, Eqs. params-synthesis and lasso-synthesis): the
+Sect. 4.3 (synthesis form, Eqs. params-synthesis and lasso-synthesis): the
 image is I = Psi theta, and the LASSO is solved for the coefficients theta,
 with lambda_max = ||Psi* Phi* V||_inf.  The dictionary the paper uses for
 diffuse emission (Sect. 6.4, reconstruction methods) has one Gaussian

@@ -15,7 +15,7 @@ Paper passages followed:
             S     = supp(x)                                 (prune)
             stop if a criterion holds.
   * The restricted solve is an accelerated proximal gradient (APGD / FISTA,
-    Sect. 3.4), stopped early with an accuracy that tightens over the FW
+    Sect. 4.4), stopped early with an accuracy that tightens over the FW
     iterations (Sect. 5.1, "The algorithmic steps").
 
 Readings of points the paper leaves open (shared with the GPU path):
@@ -33,7 +33,7 @@ Readings of points the paper leaves open (shared with the GPU path):
     at the rescaled residual nu = min(1, lambda / ||Phi* r||_inf) r;
   * ties in the exploration threshold are inclusive (">=", as printed).
 
-Positivity (remarks on positivity in Sects. 3.1 and 5.1): with x >= 0 the
+Positivity (remarks on positivity in Sects. 4.1 and 5.1): with x >= 0 the
 l1 term is lambda sum x, candidate atoms are placed only at the positive
 maxima of the dirty residual, and the restricted solve keeps x >= 0.  Readings:
 lambda_max = max(0, max_j (Phi* V)_j) (x = 0 is optimal exactly when
@@ -43,7 +43,7 @@ max(0, z - t); the dual point is scaled by the largest positive correlation
 max(0, max_j (Phi* r)_j), the one-sided dual constraint; the restricted gap
 is tested only at extrapolated points inside x >= 0.
 
-Synthesis dictionary (Sect. 3.2, Eq. lasso-synthesis): with ``dictionary``
+Synthesis dictionary (Sect. 4.3, Eq. lasso-synthesis): with ``dictionary``
 (see dictionary.py) the atoms are the columns of Phi Psi, indexed s N + p;
 eta is replaced by Psi* eta (one image per scale), lambda_max by
 ||Psi* Phi* V||_inf, and the restricted normal matrix is formed from the

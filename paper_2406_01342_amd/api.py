@@ -135,7 +135,7 @@ def pc_adjoint_grid(plan: Plan, vis: torch.Tensor, image: Optional[torch.Tensor]
 
 def pc_adjoint_grid_ms(plan: Plan, vis: torch.Tensor, sigma, gamma,
                        images: Optional[torch.Tensor] = None, want_max: bool = True, stream=None):
-    """Psi* Phi* vis for the Gaussian synthesis dictionary (Sect. 3.2) ->
+    """Psi* Phi* vis for the Gaussian synthesis dictionary (Sect. 4.3) ->
     (images [S, n, n] float32, max|.| or None, flat argmax s n^2 + p or None)."""
     n = plan.npix
     sig = np.ascontiguousarray(sigma, dtype=np.float64)

@@ -71,13 +71,21 @@ __host__ __device__ constexpr int spread_block(int W) { return spread_span(W) - 
 // One spreading work item: an output tile plus the (sub)ranges of sorted
 // visibilities that reach it from the tile itself and from its left, upper
 // and upper-left neighbours.  slot >= 0 means the tile is split across
-// several items and this item writes partial tile `slot`.
+// several items and this item writes partial tile `slot`.  FP32 plans with
+// kernel widths up to 8 group items in fours, one workgroup of four waves per
+// group: either four independent items (combine = 0; tile = -1 marks an empty
+// one), or four shares of one tile's visibilities (combine = 1, same tile and
+// slot) whose four LDS tiles the workgroup adds in a fixed order before the
+// single write.
 struct SpreadChunk {
   int32_t tile;
   int32_t slot;
   int32_t beg[4];
   int32_t end[4];
+  int32_t combine;
+  int32_t pad;
 };
+constexpr int kSpreadQuad = 4;  // waves (items) per workgroup of the grouped spread
 
 // A split ("hot") tile: its partial tiles occupy slots [first, first+count).
 struct FoldItem {
@@ -167,6 +175,7 @@ struct pc_plan {
   int64_t L = 0;
   pc::GridGeom g{};
   int64_t n_chunks = 0, n_partials = 0, n_fold = 0;
+  bool spread_quads = false;  // work items grouped in fours (FP32, kernel width <= 8)
   size_t footprint = 0;
 
   // Per-visibility data in plan (tile-sorted) order.
@@ -199,7 +208,7 @@ struct pc_plan {
   size_t key_capacity = 0;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   pc::Prof prof;
-  std::vector<int32_t> chunk_work;  // host copy: visibilities per spreading item
+  std::vector<int32_t> chunk_work;  // host copy: visibilities per spreading workgroup
 
   std::vector<pc::DeviceBuf> owned;
 };
@@ -228,7 +237,7 @@ double* ensure_red_scratch(pc_plan* p, size_t count);
 float* ensure_image_scratch(pc_plan* p);  // n^2 floats, grown on first use
 unsigned long long* ensure_key_scratch(pc_plan* p, size_t count);  // per-workgroup max keys
 
-// Synthesis dictionary of Gaussian elements (Sect. 3.2; the elements of
+// Synthesis dictionary of Gaussian elements (Sect. 4.3; the elements of
 // Sect. 6.4): g_s[a][b] = gamma_s t_s[a] t_s[b], t_s the unit-sum 1-D
 // Gaussian taps exp(-a^2 / sigma_s^2) of half-width h_s = floor(2 sigma_s)
 // (h_s = 0, t = {1}: a single pixel).  Passed to kernels by value.

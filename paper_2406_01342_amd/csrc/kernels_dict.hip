@@ -1,4 +1,4 @@
-// Synthesis dictionary of Gaussian elements (Sect. 3.2, Eqs. params-synthesis
+// Synthesis dictionary of Gaussian elements (Sect. 4.3, Eqs. params-synthesis
 // and lasso-synthesis; the elements of Sect. 6.4).  The dictionary enters the
 // solve only through three image-domain operations around the existing
 // gridded operators: Phi Psi theta = forward_grid(synthesis(theta)) and

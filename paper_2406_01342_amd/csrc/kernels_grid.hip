@@ -282,6 +282,349 @@ __device__ __forceinline__ void spread_body(
   }
 }
 
+// FP32 spreading for kernel widths up to 8, four visibilities per step.
+//
+// The wave's lanes again cover an 8 x 8 window of cells (lane = row a, column
+// b), the union of the footprints of the visibilities whose first cell lies
+// in one RB x RB block, and a run of visibilities sharing a block accumulates
+// in registers.  What differs is how a lane gets its factors.  Each lane
+// stages one visibility of a batch of 64 and writes its weights, already
+// shifted onto the window, into two transposed tables: wy[a][j] (rows), and
+// the column weights times the value as complex pairs, wx[b][j] =
+// (wx_j[b] Re v_j, wx_j[b] Im v_j).  Consecutive visibilities j of one table
+// row are adjacent, so 128-bit LDS reads hand a lane its factors for four
+// visibilities: three reads and eight FMAs per lane for four visibilities
+// (instead of two 32-bit weight reads, the broadcast value and key reads, a
+// multiply and two FMAs per visibility).  Run boundaries are found once per
+// batch (a ballot of "my block differs from my predecessor's"); a group of
+// four with no boundary takes the straight path, a group with one flushes
+// between its visibilities.  Table rows are padded (68 and 132 floats) so
+// that the eight distinct rows a wave reads in one instruction fall in
+// distinct banks; the staging writes one row at a time from all lanes.  The
+// LDS tile holds interleaved complex cells (one 64-bit read-add-write per
+// lane and flush).  Deterministic: each cell receives its terms in a fixed
+// order.
+// Groups of four visibilities whose LDS reads are issued together.
+constexpr int kGroupsAhead = 4;
+
+template <int W>
+struct SpreadG {
+  static constexpr int BS = 8;                  // window side
+  static constexpr int RB = BS - W + 1;         // block side (first cells)
+  static constexpr int S = kTile + 4;           // tile row stride (complex cells)
+  static constexpr int TR = 68;                 // row-weight table row stride (floats)
+  static constexpr int TRX = 132;               // column table row stride (floats)
+  static constexpr int TILE_F = 2 * kTile * S;  // floats
+  static constexpr int TAB_F = BS * (TR + TRX); // floats
+  static constexpr size_t wave_bytes = sizeof(float) * (TILE_F + TAB_F);
+  static constexpr size_t lds_bytes = kSpreadQuad * wave_bytes;
+};
+
+// Exponential-of-semicircle weight of a tap at distance x (cells) from the
+// visibility, in the form the staging evaluates it: with R = W/2,
+// phi = exp(beta (sqrt(1 - (x/R)^2) - 1)) = exp2(c1 sqrt(R^2 - x^2) - c0),
+// c0 = beta log2(e), c1 = c0 / R.  |x| <= R for every tap of a footprint;
+// max(., 0) only absorbs rounding at |x| = R.
+__device__ __forceinline__ float es_weight(float x, float R2, float c1, float c0) {
+  const float q = fmaxf(fmaf(-x, x, R2), 0.0f);
+  return __builtin_amdgcn_exp2f(fmaf(c1, __builtin_amdgcn_sqrtf(q), -c0));
+}
+
+// Accumulates one work item into the wave's LDS region (its tile, then its
+// tables) and leaves the tile there; the caller writes it out.
+// perm: NULL when vals is in plan order, else the plan -> caller map.
+template <int W>
+__device__ __forceinline__ void spread_group_accumulate(
+    const GridGeom& g, const SpreadChunk& ch, const uint32_t* __restrict__ cell,
+    const float* __restrict__ off, const cpx<float>* __restrict__ vals,
+    const int32_t* __restrict__ perm, float* __restrict__ tile, int lane) {
+  using C = SpreadG<W>;
+  static_assert(W >= 2 && W <= 8, "group spreading covers widths 2..8");
+  float* tab = tile + C::TILE_F;        // wy [8][TR]
+  float* tabx = tab + C::BS * C::TR;    // wx v as complex pairs [8][TRX]
+  const int a = lane >> 3, b = lane & 7;
+  const int tv = ch.tile / g.ntu, tu = ch.tile - tv * g.ntu;
+  const int ov = g.v0 + tv * kTile, ou = g.u0 + tu * kTile;
+  const bool single = g.wrap && g.M == kTile;
+  constexpr float R = 0.5f * (float)W;
+  const float c0 = g.beta * 1.44269504088896341f;  // beta log2(e)
+  const float c1 = c0 / R;
+  const int c1n = ch.end[0] - ch.beg[0];
+  const int c2n = c1n + ch.end[1] - ch.beg[1];
+  const int c3n = c2n + ch.end[2] - ch.beg[2];
+  const int total = c3n + ch.end[3] - ch.beg[3];
+  const int b0 = ch.beg[0], b1 = ch.beg[1] - c1n, b2 = ch.beg[2] - c2n, b3 = ch.beg[3] - c3n;
+  {
+    float4* t4 = reinterpret_cast<float4*>(tile);
+    for (int i = lane; i < C::TILE_F / 4; i += 64) t4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  if (total <= 0) return;
+  // Loads run ahead through three record buffers (batch k uses buffer k mod 3).
+  // The cell, offsets and source index of batch k + 3 and the value of batch
+  // k + 2 are issued while batch k is staged and summed; the value of a
+  // caller-order input needs its source index, which was issued a batch
+  // earlier, so no load waits on one issued just before it.  Lanes past the
+  // end load the last record again (no branch around the loads, so that each
+  // wait covers exactly the batch it consumes).
+  struct Raw {
+    uint32_t cell;
+    float2 off;
+    int32_t ld, sidx;  // the loaded index, and the record's plan position
+    cpx<float> val;
+  };
+  // (for a plan-order input the index load reads the cell array instead and
+  // is discarded, so that every path issues the same loads)
+  const int32_t* src_arr = perm ? perm : reinterpret_cast<const int32_t*>(cell);
+  auto load_pre = [&](Raw& rw, int q) {
+    const int sidx = chunk_index(q < total ? q : total - 1, c1n, c2n, c3n, b0, b1, b2, b3);
+    rw.cell = cell[sidx];
+    rw.off = reinterpret_cast<const float2*>(off)[sidx];
+    rw.ld = src_arr[sidx];
+    rw.sidx = sidx;
+  };
+  // (the choice between them is made here, a batch after the index load)
+  auto load_val = [&](Raw& rw) { rw.val = vals[perm ? rw.ld : rw.sidx]; };
+  Raw rb0, rb1, rb2;
+  load_pre(rb0, lane);
+  load_val(rb0);
+  load_pre(rb1, 64 + lane);
+  load_pre(rb2, 128 + lane);
+  load_val(rb1);
+  const float* rwy = tab + a * C::TR;
+  const float* rwx = tabx + b * C::TRX;
+  int ckey = kNoBlock;
+  float accr = 0.f, acci = 0.f;
+  auto flush = [&]() {
+    if (ckey != kNoBlock) {
+      int y = ((ckey >> 8) - 64) + a, x = ((ckey & 0xff) - 64) + b;
+      if (single) {
+        y &= kTile - 1;
+        x &= kTile - 1;
+      }
+      if ((unsigned)y < (unsigned)kTile && (unsigned)x < (unsigned)kTile) {
+        float2* cp = reinterpret_cast<float2*>(tile) + y * C::S + x;
+        float2 o = *cp;
+        o.x += accr;
+        o.y += acci;
+        *cp = o;
+      }
+    }
+    accr = 0.f;
+    acci = 0.f;
+  };
+  // One batch of 64: stage from rk (batch k), reload rk with batch k + 3 and
+  // the value of rk2 (batch k + 2), then sum.
+  auto batch = [&](int base, Raw& rk, Raw& rk2) {
+    const int q = base + lane;
+    const bool valid = q < total;
+    int key = kNoBlock, du = 0, dv = 0;
+    float fy[W], fx[W], vr = 0.f, vi = 0.f;
+    if (valid) {
+      const int cu = (int)(rk.cell & 0xffffu), cv = (int)(rk.cell >> 16);
+      du = cu % C::RB;
+      dv = cv % C::RB;
+      key = block_key(tile_base(cu - du, ou, g.M, C::BS, g.wrap),
+                      tile_base(cv - dv, ov, g.M, C::BS, g.wrap));
+      vr = rk.val.x;
+      vi = rk.val.y;
+      // tap t lies x = s + t cells from the visibility, s in (-R, -R + 1],
+      // so |x| <= R (z = x / R in (-1, 1])
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        fy[t] = es_weight(rk.off.y + (float)t, R * R, c1, c0);
+        fx[t] = es_weight(rk.off.x + (float)t, R * R, c1, c0);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < W; ++t) fy[t] = fx[t] = 0.f;
+    }
+    load_pre(rk, q + 192);
+    load_val(rk2);
+    // run starts: a valid visibility whose block differs from its predecessor's
+    const int prev = __shfl_up(key, 1, 64);
+    const bool start = valid && (lane == 0 ? key != ckey : key != prev);
+    const unsigned long long runs = __ballot(start);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Every lane writes the same table row at once (consecutive addresses, no
+    // bank conflicts): window row a holds tap a - dv of the footprint, or zero
+    // outside it, picked by selects over the RB possible shifts.
+#pragma unroll
+    for (int row = 0; row < C::BS; ++row) {
+      float wy = 0.f, wx = 0.f;
+#pragma unroll
+      for (int d = 0; d < C::RB; ++d) {
+        const int t = row - d;
+        if (t >= 0 && t < W) {
+          wy = dv == d ? fy[t] : wy;
+          wx = du == d ? fx[t] : wx;
+        }
+      }
+      tab[row * C::TR + lane] = wy;
+      *reinterpret_cast<float2*>(tabx + row * C::TRX + 2 * lane) = make_float2(wx * vr, wx * vi);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int ng = ((total - base < 64 ? total - base : 64) + 3) >> 2;  // groups of four
+#pragma unroll 1
+    for (int g4 = 0; g4 < ng; g4 += kGroupsAhead) {
+      float4 y[kGroupsAhead], xr[kGroupsAhead], xi[kGroupsAhead];
+#pragma unroll
+      for (int u = 0; u < kGroupsAhead; ++u) {  // every read of these groups first
+        y[u] = *reinterpret_cast<const float4*>(rwy + 4 * (g4 + u));
+        // (re, im) pairs of visibilities 4g, 4g + 1, then 4g + 2, 4g + 3
+        const float4 p01 = *reinterpret_cast<const float4*>(rwx + 8 * (g4 + u));
+        const float4 p23 = *reinterpret_cast<const float4*>(rwx + 8 * (g4 + u) + 4);
+        xr[u] = make_float4(p01.x, p01.z, p23.x, p23.z);
+        xi[u] = make_float4(p01.y, p01.w, p23.y, p23.w);
+      }
+#pragma unroll
+      for (int u = 0; u < kGroupsAhead; ++u) {
+        const unsigned bits = (unsigned)(runs >> (4 * (g4 + u))) & 0xfu;
+        if (bits == 0u) {  // the group continues the current run
+          accr = fmaf(y[u].x, xr[u].x, accr);
+          acci = fmaf(y[u].x, xi[u].x, acci);
+          accr = fmaf(y[u].y, xr[u].y, accr);
+          acci = fmaf(y[u].y, xi[u].y, acci);
+          accr = fmaf(y[u].z, xr[u].z, accr);
+          acci = fmaf(y[u].z, xi[u].z, acci);
+          accr = fmaf(y[u].w, xr[u].w, accr);
+          acci = fmaf(y[u].w, xi[u].w, acci);
+        } else {
+          const int j0 = 4 * (g4 + u);
+          if (bits & 1u) {
+            flush();
+            ckey = __builtin_amdgcn_readlane(key, j0);
+          }
+          accr = fmaf(y[u].x, xr[u].x, accr);
+          acci = fmaf(y[u].x, xi[u].x, acci);
+          if (bits & 2u) {
+            flush();
+            ckey = __builtin_amdgcn_readlane(key, j0 + 1);
+          }
+          accr = fmaf(y[u].y, xr[u].y, accr);
+          acci = fmaf(y[u].y, xi[u].y, acci);
+          if (bits & 4u) {
+            flush();
+            ckey = __builtin_amdgcn_readlane(key, j0 + 2);
+          }
+          accr = fmaf(y[u].z, xr[u].z, accr);
+          acci = fmaf(y[u].z, xi[u].z, acci);
+          if (bits & 8u) {
+            flush();
+            ckey = __builtin_amdgcn_readlane(key, j0 + 3);
+          }
+          accr = fmaf(y[u].w, xr[u].w, accr);
+          acci = fmaf(y[u].w, xi[u].w, acci);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // the three batches of a step run unconditionally (the later ones may be
+  // empty: no valid lane, zero weights, no groups), so that the loads in
+  // flight are the same on every path and each wait covers just what it needs
+#pragma unroll 1
+  for (int base = 0; base < total; base += 192) {
+    batch(base, rb0, rb2);
+    batch(base + 64, rb1, rb0);
+    batch(base + 128, rb2, rb1);
+  }
+  flush();
+}
+
+// Output address of a work item's tile: the band tile itself, or its
+// partial slot.
+__device__ __forceinline__ cpx<float>* spread_dst(const GridGeom& g, const SpreadChunk& ch,
+                                                  cpx<float>* grid, cpx<float>* partials,
+                                                  size_t& stride) {
+  if (ch.slot < 0) {
+    const int tv = ch.tile / g.ntu, tu = ch.tile - tv * g.ntu;
+    stride = g.nu;
+    return grid + (size_t)(tv * kTile) * g.nu + tu * kTile;
+  }
+  stride = kTile;
+  return partials + (size_t)ch.slot * kTile * kTile;
+}
+
+// A workgroup of four waves over four work items (see SpreadChunk): each
+// wave accumulates its item into its own LDS tile; independent items are
+// written by their own wave, the four shares of a combined tile are added
+// in wave order and written once by the whole workgroup.
+template <int W>
+__device__ __forceinline__ void spread_quad_body(
+    const GridGeom& g, const SpreadChunk* __restrict__ quad, const uint32_t* __restrict__ cell,
+    const float* __restrict__ off, const cpx<float>* __restrict__ vals,
+    const int32_t* __restrict__ perm, cpx<float>* __restrict__ grid,
+    cpx<float>* __restrict__ partials) {
+  using C = SpreadG<W>;
+  constexpr int WAVE_F = C::TILE_F + C::TAB_F;
+  extern __shared__ unsigned char smem_raw[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float* region = reinterpret_cast<float*>(smem_raw);
+  const SpreadChunk& ch = quad[w];
+  const bool combine = quad[0].combine != 0;  // the same for every wave
+  if (ch.tile >= 0)
+    spread_group_accumulate<W>(g, ch, cell, off, vals, perm, region + w * WAVE_F, lane);
+  size_t stride;
+  if (!combine) {
+    if (ch.tile < 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    cpx<float>* dst = spread_dst(g, ch, grid, partials, stride);
+    const float4* t4 = reinterpret_cast<const float4*>(region + w * WAVE_F);
+    for (int i = lane; i < kTile * kTile / 2; i += 64) {  // two cells per lane and step
+      const int y = i / (kTile / 2), x2 = i - y * (kTile / 2);
+      *reinterpret_cast<float4*>(dst + (size_t)y * stride + 2 * x2) = t4[(y * C::S) / 2 + x2];
+    }
+    return;
+  }
+  __syncthreads();
+  cpx<float>* dst = spread_dst(g, quad[0], grid, partials, stride);
+  for (int i = threadIdx.x; i < kTile * kTile / 2; i += 64 * kSpreadQuad) {
+    const int y = i / (kTile / 2), x2 = i - y * (kTile / 2);
+    const int o = (y * C::S) / 2 + x2;
+    float4 v = reinterpret_cast<const float4*>(region)[o];
+#pragma unroll
+    for (int k = 1; k < kSpreadQuad; ++k) {
+      const float4 t = reinterpret_cast<const float4*>(region + k * WAVE_F)[o];
+      v.x += t.x;
+      v.y += t.y;
+      v.z += t.z;
+      v.w += t.w;
+    }
+    *reinterpret_cast<float4*>(dst + (size_t)y * stride + 2 * x2) = v;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * kSpreadQuad) void spread_quad_kernel(
+    GridGeom g, const SpreadChunk* __restrict__ chunks, const uint32_t* __restrict__ cell,
+    const float* __restrict__ off, const cpx<float>* __restrict__ vals,
+    const int32_t* __restrict__ perm, cpx<float>* __restrict__ grid,
+    cpx<float>* __restrict__ partials, unsigned long long* __restrict__ maxkey) {
+  // the image maximum that the last pass accumulates starts from zero
+  if (blockIdx.x == 0 && threadIdx.x == 0) *maxkey = 0ull;
+  spread_quad_body<W>(g, chunks + (size_t)kSpreadQuad * blockIdx.x, cell, off, vals, perm, grid,
+                      partials);
+}
+
+// One launch over the workgroups of several plans: items[b] = (job, group).
+template <int W>
+__global__ __launch_bounds__(64 * kSpreadQuad) void spread_quad_batch_kernel(
+    const AdjJob* __restrict__ jobs, const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const AdjJob& J = jobs[it.x];
+  if (it.y == 0 && threadIdx.x == 0) *J.maxkey = 0ull;  // every job has a group 0
+  spread_quad_body<W>(J.g, J.chunks + (size_t)kSpreadQuad * it.y, J.cell, J.off, J.vals, J.perm,
+                      J.grid, J.partials);
+}
+
 template <typename R, int W>
 __global__ __launch_bounds__(64) void spread_kernel(
     GridGeom g, const SpreadChunk* __restrict__ chunks, const uint32_t* __restrict__ cell,
@@ -799,19 +1142,35 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
 // ----------------------------------------------------------------------------
 // Host launchers
 // ----------------------------------------------------------------------------
+// Algorithmic bytes of one spread: each visibility's value and its two
+// sub-cell offsets read once (4 reals), each band cell written once.
+static double spread_bytes(const pc_plan* p, double rb) {
+  return p->L * 4.0 * rb + 2.0 * rb * p->g.nu * p->g.nv;
+}
+
 template <typename R, int W>
 static void launch_spread_w(pc_plan* p, const cpx<R>* vals, const int32_t* perm, hipStream_t s) {
   const double rb = sizeof(R);
-  using C = SpreadCfg<R, W>;
-  static_assert(C::lds_bytes <= 160 * 1024, "spread LDS budget");
-  if (C::lds_bytes > 64 * 1024)
-    PC_HIP(hipFuncSetAttribute((const void*)spread_kernel<R, W>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds_bytes));
-  ProfScope ps(p, s, "spread", p->L * (4 + 4 * rb) + 2 * rb * p->g.nu * p->g.nv, (double)p->L);
-  hipLaunchKernelGGL((spread_kernel<R, W>), dim3((unsigned)p->n_chunks), dim3(64),
-                     C::lds_bytes, s, p->g,
-                     p->chunks, p->cell, (const R*)p->off, vals, perm, (cpx<R>*)p->grid,
-                     (cpx<R>*)p->partials, p->maxkey);
+  ProfScope ps(p, s, "spread", spread_bytes(p, rb), (double)p->L);
+  if constexpr (sizeof(R) == 4 && W <= 8) {
+    if (!p->spread_quads) fail(PC_ERR_DEVICE, "spread: the plan's work list is not grouped");
+    constexpr size_t lds = SpreadG<W>::lds_bytes;
+    static_assert(lds <= 64 * 1024, "grouped spread LDS budget");
+    hipLaunchKernelGGL((spread_quad_kernel<W>), dim3((unsigned)(p->n_chunks / kSpreadQuad)),
+                       dim3(64 * kSpreadQuad), lds, s, p->g, p->chunks, p->cell,
+                       (const float*)p->off, vals, perm, (c32*)p->grid, (c32*)p->partials,
+                       p->maxkey);
+  } else {
+    constexpr size_t lds = SpreadCfg<R, W>::lds_bytes;
+    static_assert(lds <= 160 * 1024, "spread LDS budget");
+    if (p->spread_quads) fail(PC_ERR_DEVICE, "spread: the plan's work list is grouped");
+    if (lds > 64 * 1024)
+      PC_HIP(hipFuncSetAttribute((const void*)spread_kernel<R, W>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((spread_kernel<R, W>), dim3((unsigned)p->n_chunks), dim3(64), lds, s, p->g,
+                       p->chunks, p->cell, (const R*)p->off, vals, perm, (cpx<R>*)p->grid,
+                       (cpx<R>*)p->partials, p->maxkey);
+  }
   PC_LAUNCH_CHECK("spread");
 }
 
@@ -1075,9 +1434,15 @@ void pass_batch(int M, bool passA, const AdjJob* jobs, const int2* items, int ni
 
 template <int W>
 void launch_spread_batch(const AdjJob* jobs, const int2* items, int nitems, hipStream_t s) {
-  using C = SpreadCfg<float, W>;
-  set_lds((const void*)spread_batch_kernel<W>, C::lds_bytes);
-  hipLaunchKernelGGL((spread_batch_kernel<W>), dim3(nitems), dim3(64), C::lds_bytes, s, jobs, items);
+  if constexpr (W <= 8) {  // grouped work lists: items are (job, workgroup)
+    constexpr size_t lds = SpreadG<W>::lds_bytes;
+    hipLaunchKernelGGL((spread_quad_batch_kernel<W>), dim3(nitems), dim3(64 * kSpreadQuad), lds,
+                       s, jobs, items);
+  } else {
+    constexpr size_t lds = SpreadCfg<float, W>::lds_bytes;
+    set_lds((const void*)spread_batch_kernel<W>, lds);
+    hipLaunchKernelGGL((spread_batch_kernel<W>), dim3(nitems), dim3(64), lds, s, jobs, items);
+  }
   PC_LAUNCH_CHECK("spread_batch");
 }
 
@@ -1135,7 +1500,8 @@ void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* 
     J.scale = scales ? scales[j] : 1.0f;
     J.maxkey = p->maxkey;
     J.positive = p->max_positive;
-    for (int64_t c = 0; c < p->n_chunks; ++c)
+    // one entry per workgroup: a group of four items, or one item
+    for (size_t c = 0; c < p->chunk_work.size(); ++c)
       sitems.push_back({p->chunk_work[c], make_int2(j, (int)c)});
     for (int64_t f = 0; f < p->n_fold; ++f) fitems.push_back(make_int2(j, (int)f));
     if (std::find(Ms.begin(), Ms.end(), p->g.M) == Ms.end()) Ms.push_back(p->g.M);

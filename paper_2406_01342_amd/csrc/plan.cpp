@@ -87,6 +87,8 @@ struct Layout {
   std::vector<FoldItem> fold;
   std::vector<uint8_t> tile_flags;      // 1 if any footprint reaches the tile
   int64_t n_partials = 0;
+  bool quads = false;                   // chunks grouped in fours (see SpreadChunk)
+  std::vector<int32_t> group_work;      // per workgroup: its longest item's visibilities
 };
 
 static double kernel_beta(int W) { return 2.30 * W; }
@@ -250,10 +252,7 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
       lay.off[2 * s + 1] = sv[k];
     }
   }
-  // Work list.  Split tiles whose gathered count exceeds kChunk: 256
-  // visibilities keeps the longest item short when few items exist (the
-  // spread is then bound by its longest work item); with many items the
-  // spread is throughput-bound, and 512 halves the partial tiles to fold.
+  // Work list.
   auto tid = [&](int tv, int tu) -> int64_t {
     if (g.wrap) {
       tv = (tv + ntv) % ntv;
@@ -288,71 +287,180 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     for (int r = 0; r < 4; ++r) total += re[r] - rb[r];
     return total;
   };
-  int64_t kChunk = 256;
-  {
-    int64_t items512 = 0;
-    for (int tv = 0; tv < ntv; ++tv)
-      for (int tu = 0; tu < ntu; ++tu) {
-        int64_t rb[4], re[4];
-        const int64_t tot = gathered(tv, tu, rb, re);
-        if (tot > 0) items512 += (tot + 511) / 512;
+  // Sub-range [q0, q1) of a tile's gathered sequence (its four ranges
+  // concatenated) as an item's four ranges.
+  auto sub_ranges = [](const int64_t* rb, const int64_t* re, int64_t q0, int64_t q1,
+                       SpreadChunk& ch) {
+    int64_t acc = 0;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t len = re[r] - rb[r];
+      const int64_t a = std::max<int64_t>(q0, acc), b = std::min<int64_t>(q1, acc + len);
+      if (b > a) {
+        ch.beg[r] = (int32_t)(rb[r] + (a - acc));
+        ch.end[r] = (int32_t)(rb[r] + (b - acc));
+      } else {
+        ch.beg[r] = ch.end[r] = 0;
       }
-    if (items512 >= 7680) kChunk = 512;  // >= 3 waves of work items per wave slot
-  }
+      acc += len;
+    }
+  };
+  auto work = [](const SpreadChunk& c) {
+    int64_t w = 0;
+    for (int r = 0; r < 4; ++r) w += c.end[r] - c.beg[r];
+    return w;
+  };
+  std::vector<int64_t> totals((size_t)ntiles, 0);
   lay.tile_flags.assign(ntiles, 0);
   for (int tv = 0; tv < ntv; ++tv)
     for (int tu = 0; tu < ntu; ++tu) {
-      const int64_t t = (int64_t)tv * ntu + tu;
       int64_t rb[4], re[4];
-      const int64_t total = gathered(tv, tu, rb, re);
+      const int64_t t = (int64_t)tv * ntu + tu;
+      totals[t] = gathered(tv, tu, rb, re);
       // Tiles no footprint reaches get no work item and are never written;
       // the first FFT pass reads them as zeros from the occupancy flags.
-      lay.tile_flags[t] = total > 0 ? 1 : 0;
+      lay.tile_flags[t] = totals[t] > 0 ? 1 : 0;
+    }
+  lay.quads = geo->precision == PC_PREC_FP32 && W <= 8;
+  if (lay.quads) {
+    // Grouped spread: workgroups of four waves.  A tile with at most kq
+    // visibilities is one wave's item, packed four to a workgroup with items
+    // of similar length; a heavier tile is cut into chunks of at most 4 kq,
+    // each shared by the four waves of one workgroup (combine), which write
+    // the tile itself when one chunk covers it and a partial tile otherwise.
+    // kq, the visibilities per wave, is the largest of 1024, 512, ..., 64 that
+    // still gives at least three rounds of the 512 workgroups resident at once
+    // (two per compute unit), so that the longest work stays short against
+    // the whole launch while the partial tiles to fold stay few.
+    auto groups_for = [&](int64_t kq) {
+      int64_t light = 0, heavy = 0;
+      for (int64_t t = 0; t < ntiles; ++t) {
+        if (totals[t] == 0) continue;
+        if (totals[t] <= kq)
+          ++light;
+        else
+          heavy += (totals[t] + 4 * kq - 1) / (4 * kq);
+      }
+      return heavy + (light + 3) / 4;
+    };
+    int64_t kq = 64;
+    for (int64_t c = 1024; c >= 64; c /= 2)
+      if (groups_for(c) >= 1536) {
+        kq = c;
+        break;
+      }
+    struct Group {
+      int64_t work;
+      SpreadChunk c[4];
+    };
+    std::vector<Group> groups;
+    std::vector<SpreadChunk> light;
+    for (int tv = 0; tv < ntv; ++tv)
+      for (int tu = 0; tu < ntu; ++tu) {
+        const int64_t t = (int64_t)tv * ntu + tu;
+        const int64_t total = totals[t];
+        if (total == 0) continue;
+        int64_t rb[4], re[4];
+        gathered(tv, tu, rb, re);
+        if (total <= kq) {
+          SpreadChunk c{};
+          c.tile = (int32_t)t;
+          c.slot = -1;
+          sub_ranges(rb, re, 0, total, c);
+          light.push_back(c);
+          continue;
+        }
+        const int64_t nch = (total + 4 * kq - 1) / (4 * kq);
+        if (nch > 1) {
+          lay.fold.push_back(FoldItem{(int32_t)t, (int32_t)lay.n_partials, (int32_t)nch, 0});
+        }
+        for (int64_t c = 0; c < nch; ++c) {
+          const int64_t q0 = total * c / nch, q1 = total * (c + 1) / nch;
+          Group gr{};
+          gr.work = 0;
+          for (int w = 0; w < 4; ++w) {
+            SpreadChunk& ch = gr.c[w];
+            ch.tile = (int32_t)t;
+            ch.slot = nch > 1 ? (int32_t)(lay.n_partials + c) : -1;
+            ch.combine = 1;
+            sub_ranges(rb, re, q0 + (q1 - q0) * w / 4, q0 + (q1 - q0) * (w + 1) / 4, ch);
+            gr.work = std::max(gr.work, work(ch));
+          }
+          groups.push_back(gr);
+        }
+        if (nch > 1) lay.n_partials += nch;
+      }
+    std::stable_sort(light.begin(), light.end(), [&](const SpreadChunk& a, const SpreadChunk& b) {
+      return work(a) > work(b);
+    });
+    for (size_t i = 0; i < light.size(); i += 4) {
+      Group gr{};
+      gr.work = work(light[i]);
+      for (int w = 0; w < 4; ++w) {
+        if (i + w < light.size()) {
+          gr.c[w] = light[i + w];
+        } else {
+          gr.c[w] = SpreadChunk{};
+          gr.c[w].tile = -1;
+          gr.c[w].slot = -1;
+        }
+        gr.c[w].combine = 0;
+      }
+      groups.push_back(gr);
+    }
+    // longest workgroups first: the dense uv core's work starts before the
+    // many short items, which then fill in around it (greedy longest-first)
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const Group& a, const Group& b) { return a.work > b.work; });
+    for (const Group& gr : groups) {
+      for (int w = 0; w < 4; ++w) lay.chunks.push_back(gr.c[w]);
+      lay.group_work.push_back((int32_t)gr.work);
+    }
+    return lay;
+  }
+  // One wave per item (FP64 plans, kernel widths above 8).  Split tiles whose
+  // gathered count exceeds kChunk: 256 visibilities keeps the longest item
+  // short when few items exist (the spread is then bound by its longest work
+  // item); with many items the spread is throughput-bound, and 512 halves the
+  // partial tiles to fold.
+  int64_t kChunk = 256;
+  {
+    int64_t items512 = 0;
+    for (int64_t t = 0; t < ntiles; ++t)
+      if (totals[t] > 0) items512 += (totals[t] + 511) / 512;
+    if (items512 >= 7680) kChunk = 512;  // >= 3 waves of work items per wave slot
+  }
+  for (int tv = 0; tv < ntv; ++tv)
+    for (int tu = 0; tu < ntu; ++tu) {
+      const int64_t t = (int64_t)tv * ntu + tu;
+      const int64_t total = totals[t];
       if (total == 0) continue;
+      int64_t rb[4], re[4];
+      gathered(tv, tu, rb, re);
       const int64_t nch = std::max<int64_t>(1, (total + kChunk - 1) / kChunk);
       if (nch == 1) {
         SpreadChunk c{};
         c.tile = (int32_t)t;
         c.slot = -1;
-        for (int r = 0; r < 4; ++r) {
-          c.beg[r] = (int32_t)rb[r];
-          c.end[r] = (int32_t)re[r];
-        }
+        sub_ranges(rb, re, 0, total, c);
         lay.chunks.push_back(c);
         continue;
       }
       FoldItem f{(int32_t)t, (int32_t)lay.n_partials, (int32_t)nch, 0};
       lay.fold.push_back(f);
       for (int64_t c = 0; c < nch; ++c) {
-        const int64_t q0 = total * c / nch, q1 = total * (c + 1) / nch;
         SpreadChunk ch{};
         ch.tile = (int32_t)t;
         ch.slot = (int32_t)(lay.n_partials + c);
-        int64_t acc = 0;
-        for (int r = 0; r < 4; ++r) {
-          const int64_t len = re[r] - rb[r];
-          const int64_t a = std::max<int64_t>(q0, acc), b = std::min<int64_t>(q1, acc + len);
-          if (b > a) {
-            ch.beg[r] = (int32_t)(rb[r] + (a - acc));
-            ch.end[r] = (int32_t)(rb[r] + (b - acc));
-          } else {
-            ch.beg[r] = ch.end[r] = 0;
-          }
-          acc += len;
-        }
+        sub_ranges(rb, re, total * c / nch, total * (c + 1) / nch, ch);
         lay.chunks.push_back(ch);
       }
       lay.n_partials += nch;
     }
   // Longest work items first: the dense uv core's items start before the
   // many short ones, which then fill in around them (greedy longest-first).
-  auto work = [](const SpreadChunk& c) {
-    int64_t w = 0;
-    for (int r = 0; r < 4; ++r) w += c.end[r] - c.beg[r];
-    return w;
-  };
   std::stable_sort(lay.chunks.begin(), lay.chunks.end(),
                    [&](const SpreadChunk& a, const SpreadChunk& b) { return work(a) > work(b); });
+  for (const SpreadChunk& c : lay.chunks) lay.group_work.push_back((int32_t)work(c));
   return lay;
 }
 
@@ -455,12 +563,8 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     p->n_chunks = (int64_t)lay.chunks.size();
     p->n_partials = lay.n_partials;
     p->n_fold = (int64_t)lay.fold.size();
-    p->chunk_work.resize(lay.chunks.size());
-    for (size_t c = 0; c < lay.chunks.size(); ++c) {
-      int32_t w = 0;
-      for (int r = 0; r < 4; ++r) w += lay.chunks[c].end[r] - lay.chunks[c].beg[r];
-      p->chunk_work[c] = w;
-    }
+    p->spread_quads = lay.quads;
+    p->chunk_work = lay.group_work;
     const GridGeom& g = lay.g;
     const bool f64 = geom->precision == PC_PREC_FP64;
     const size_t cb = f64 ? 16 : 8, rb = cb / 2;

@@ -1,4 +1,4 @@
-"""GPU synthesis-dictionary path (Sect. 3.2, Eq. lasso-synthesis; the Gaussian
+"""GPU synthesis-dictionary path (Sect. 4.3, Eq. lasso-synthesis; the Gaussian
 elements of Sect. 6.4) against the FP64 oracle: the adjoint Psi* Phi* for
 every scale, and the synthesis-form solve (objective, fit, certificate over
 all scales, lambda_max = ||Psi* Phi* V||_inf), with and without positivity."""
@@ -109,6 +109,11 @@ def test_dictionary_solve_matches_oracle(scales, positive):
     # the reported objective is that of the returned coefficients
     p_or = solver.objective(vis.astype(np.complex128), fit, res["weight"], res["lambda"])
     assert abs(p_or - res["objective"]) <= 1e-4 * p_or
+    # the certificate of the returned coefficients is the oracle's for them:
+    # Psi* Phi* (V - Phi Psi x) / lambda over every scale (T17, 1e-4)
+    eta = operator.adjoint(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128) - fit)
+    mu_x = dic.analysis(eta, d) / res["lambda"]
+    assert rel_l2(cert, mu_x) <= 1e-4
 
 
 def test_point_scale_dictionary_equals_plain_solve():

@@ -60,6 +60,10 @@ def test_solve_c1_converged_matches_oracle(gram):
     # the objective the GPU reports is the objective of the x it returns
     p_or = solver.objective(vis.astype(np.complex128), fit, res["weight"], res["lambda"])
     assert abs(p_or - res["objective"]) <= 1e-5 * p_or
+    # its certificate is the oracle's certificate of that x (T17, 1e-4)
+    mu_x = solver.certificate(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128), res["pix"],
+                              res["weight"], res["lambda"])
+    assert rel_l2(cert, mu_x) <= 1e-4
 
 
 def test_solve_c1_fifty_iterations():
@@ -90,6 +94,9 @@ def test_solve_c2_small_gap_stop(gram):
     mu = np.abs(ref.certificate).reshape(-1)
     assert mu[res["cert_argmax"]] >= 1 - 1e-3
     assert res["cert_max"] <= 1 + 1e-3
+    mu_x = solver.certificate(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128), res["pix"],
+                              res["weight"], res["lambda"])
+    assert rel_l2(cert, mu_x) <= 1e-4
 
 
 def test_gram_form_follows_the_operator_form():
@@ -193,8 +200,8 @@ def test_step_api_equals_one_shot():
     res.weight = w.ctypes.data_as(C.POINTER(C.c_double))
     a.check(a.LIB.pc_solver_result(h, C.byref(res)), "pc_solver_result")
     a.LIB.pc_solver_destroy(h)
-    # same algorithm; the LDS-atomic gridding sums in a run-dependent order, so
-    # the two runs agree to rounding rather than bitwise
+    # the same algorithm through the same deterministic kernels (the gridding
+    # adds every cell's terms in a fixed order, without atomics)
     assert steps == res.iters
     assert abs(res.objective - one["objective"]) <= 1e-6 * one["objective"]
 
@@ -239,7 +246,7 @@ def _check_positive(p, vis, res, cert, ref, fit_tol=1e-3):
 @pytest.mark.parametrize("gram", [0, -1])
 @pytest.mark.parametrize("mixed", [False, True])
 def test_positive_solve_c1_matches_oracle(gram, mixed):
-    """Positivity-constrained solve (remarks on positivity, Sects. 3.1 and
+    """Positivity-constrained solve (remarks on positivity, Sects. 4.1 and
     5.1) against the oracle's, on C1's sky and on a mixed-sign sky."""
     say("positive solve c1, mixed", mixed, "gram_atoms", gram)
     p, vis = _mixed_sign_c1() if mixed else problem("c1")
@@ -303,11 +310,36 @@ def test_positive_flag_is_scoped_to_the_solve():
     assert mx == float(dirty.max()) and am == int(np.argmax(dirty))
 
 
+def _oracle_check_solution(p, vis, res, cert, positive=False):
+    """The oracle's view of the GPU's returned x at full size: one exact
+    adjoint of V - Phi x gives the certificate (compared over the whole image,
+    relative L2 1e-4, T17) and the exact duality gap (rel gap <= 1e-3 bounds
+    the objective within 1e-3 of the optimum); the GPU's reported objective is
+    that of its x."""
+    n = p.npix
+    v128 = vis.astype(np.complex128)
+    fit = operator.forward(p.uv, n, p.fov_rad, res["pix"], res["weight"])
+    resid = v128 - fit
+    eta = operator.adjoint(p.uv, n, p.fov_rad, resid)
+    mu = eta / res["lambda"]
+    err = rel_l2(cert, mu)
+    p_or = solver.objective(v128, fit, res["weight"], res["lambda"])
+    gap, _ = solver.dual_gap(v128, resid, solver.dual_scale_norm(eta, positive), p_or,
+                             res["lambda"])
+    say("oracle check: cert rel L2", err, "oracle rel gap", gap / p_or, "gpu rel gap",
+        res["rel_gap"])
+    assert err <= 1e-4
+    assert gap / p_or <= 1e-3
+    assert abs(p_or - res["objective"]) <= 1e-5 * p_or
+    return mu
+
+
 @pytest.mark.slow
 def test_solve_full_c2_properties():
     """Full LOFAR-like solve: the gap stop fires, the certificate is at most
-    one (to 1e-3), the alpha identity holds, and the GPU certificate agrees
-    with the oracle's certificate of the returned x on sampled pixels."""
+    one (to 1e-3), the alpha identity holds; the oracle's exact duality gap
+    of the returned x is within 1e-3 and the GPU certificate equals the
+    oracle's certificate of that x over the whole image (1e-4)."""
     say("solve full c2")
     p, vis = problem("c2")
     plan, res, cert = _gpu_solve(p, vis, alpha=p.alpha, delta=p.delta, max_iter=200,
@@ -317,16 +349,8 @@ def test_solve_full_c2_properties():
     assert res["converged"] == 1 and res["rel_gap"] <= 1e-4
     assert res["cert_max"] <= 1 + 1e-3
     assert abs(res["cert_max"] * res["lambda"] / res["lambda_max"] - p.alpha) <= 2e-3 * p.alpha
-    n = p.npix
-    rng = np.random.default_rng(8)
-    pix = np.unique(np.concatenate([rng.choice(n * n, 512, replace=False), res["pix"][:256],
-                                    [res["cert_argmax"]]]))
-    v128 = vis.astype(np.complex128)
-    fit = operator.forward(p.uv, n, p.fov_rad, res["pix"], res["weight"])
-    want = operator.adjoint_pixels(p.uv, n, p.fov_rad, v128 - fit, pix) / res["lambda"]
-    assert rel_l2(cert.reshape(-1)[pix], want) <= 1e-3
-    p_or = solver.objective(v128, fit, res["weight"], res["lambda"])
-    assert abs(p_or - res["objective"]) <= 1e-5 * p_or
+    mu = _oracle_check_solution(p, vis, res, cert)
+    assert abs(mu.reshape(-1)[res["cert_argmax"]]) >= 1 - 1e-3
 
 
 @pytest.mark.slow
@@ -334,8 +358,9 @@ def test_positive_solve_full_c2_properties():
     """Full LOFAR-like size with a third of the sources negated, so that the
     constraint is active: the gap stop fires, the weights are positive, the
     certificate is at most one with its maximum at lambda (the one-sided alpha
-    identity) and well below -1 at the negated sources, and it agrees with
-    the oracle's certificate of the returned x on sampled pixels."""
+    identity) and well below -1 at the negated sources; the oracle's exact
+    one-sided duality gap of the returned x is within 1e-3 and the whole
+    certificate matches the oracle's (1e-4)."""
     say("positive solve full c2, mixed signs")
     p = sim.config_c2()
     amp = p.sky_amp * np.where(np.arange(p.sky_amp.size) % 3 == 1, -1.0, 1.0)
@@ -350,16 +375,8 @@ def test_positive_solve_full_c2_properties():
     assert res["cert_max"] <= 1 + 1e-3 and cert.max() <= 1 + 1e-3
     assert abs(res["cert_max"] * res["lambda"] / res["lambda_max"] - p.alpha) <= 2e-3 * p.alpha
     assert cert.min() < -1.0
-    n = p.npix
-    rng = np.random.default_rng(9)
-    pix = np.unique(np.concatenate([rng.choice(n * n, 512, replace=False), res["pix"][:256],
-                                    [res["cert_argmax"], int(np.argmin(cert))]]))
-    v128 = vis.astype(np.complex128)
-    fit = operator.forward(p.uv, n, p.fov_rad, res["pix"], res["weight"])
-    want = operator.adjoint_pixels(p.uv, n, p.fov_rad, v128 - fit, pix) / res["lambda"]
-    assert rel_l2(cert.reshape(-1)[pix], want) <= 1e-3
-    p_or = solver.objective(v128, fit, res["weight"], res["lambda"])
-    assert abs(p_or - res["objective"]) <= 1e-5 * p_or
+    mu = _oracle_check_solution(p, vis, res, cert, positive=True)
+    assert mu.reshape(-1)[res["cert_argmax"]] >= 1 - 1e-3
 
 
 def test_warm_start_from_the_solution_and_from_a_perturbed_point():

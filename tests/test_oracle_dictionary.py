@@ -1,4 +1,4 @@
-"""Pins for the oracle's multi-scale synthesis dictionary (Sect. 3.2, Eqs.
+"""Pins for the oracle's multi-scale synthesis dictionary (Sect. 4.3, Eqs.
 params-synthesis and lasso-synthesis; the Gaussian elements of Sect. 6.4).
 
 Pinned against: the element's printed definition (unit l1 norm before the

@@ -158,7 +158,7 @@ def test_stop_rules():
     assert abs(objs[-1] - objs[-2]) / objs[-2] <= 1e-4
 
 
-# --- positivity (remarks on positivity in Sects. 3.1 and 5.1) ---------------
+# --- positivity (remarks on positivity in Sects. 4.1 and 5.1) ---------------
 
 def _mixed_problem(seed, L=200, n=8, fov=0.25):
     """Sources of both signs, so that the positive solution differs from the
