@@ -1,22 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: PolyCLEAN solves on the LOFAR-like workload (one MI355X).
+"""Benchmark: PolyCLEAN on the memory-pressure large job (one MI355X).
 
 A step is one full PolyCLEAN solve (Alg. 2: dirty image, polyatomic
-exploration, APGD on the active set with the direct sparse forward and
-restricted adjoint, pruning, dirty residual by the gridded adjoint, duality
-gap stop) of the LOFAR-like problem: 60 stations (48 in a 300 m Gaussian
-core, 12 in a 1-10 km ring), 240 snapshots over 4 h -> 424,800 complex64
-visibilities, 1024^2 grid, FOV 4 deg, 150 log-normal point sources at 20 dB,
-lambda = 0.05 lambda_max, stop at relative duality gap 1e-4.  Inputs are
-synthesised from the seeded generator and resident in HBM before timing; the
-plan (geometry, sort) is built once, outside the timed region, and its build
-time is reported separately.
+exploration, restricted APGD, pruning, full-grid residual adjoint each
+iteration, stopping test, dual certificate returned) of the largest
+single-GPU workload: 512 stations (SKA-low-like core and arms, 40 km), 16
+snapshots x 4 channels (120-180 MHz) stacked -> 8,372,224 complex64
+visibilities, 8192^2 image (16384^2 fine grid), FOV 3 deg, 200 log-normal
+point sources at 20 dB, lambda = 0.05 lambda_max, stop at relative objective
+change 1e-4.  Inputs are synthesised from the seeded generator and resident
+in HBM before timing; the plan is built once, outside the timed region, and
+its build time is reported separately.
 
 value = adjoint throughput in Mvis/s: visibilities gridded per second of
-device time of the gridded adjoint (spread, fold, two FFT passes, correction),
-measured with HIP events by the library around every adjoint of the timed
-solves.  The line also carries solves/s, the per-kernel roofline of the
-dominant kernel of a profiled solve and the FP64 oracle timed on the host.
+device time of the gridded adjoint (spread, fold, two FFT passes, correction
+and maximum), measured with HIP events by the library around every
+full-grid adjoint of the timed solves.  The line also carries the adjoint's
+dominant kernel against the HBM roofline, the other workloads (LOFAR-like
+solves in Gram and operator form, the precision workload's adjoint), the
+direct-DFT pair rates (M2), the serving legs and the FP64 oracle timed on the
+host cores.
 """
 import argparse
 import json
@@ -235,30 +238,6 @@ def dominant_roofline(stats, plan_info):
             "avg_ms": avg_ms, "launches": top["launches"], "bytes_per_launch": b}
 
 
-def cpu_baseline(p, vis, seconds):
-    """FP64 oracle adjoint on a bounded sample (a visibility subset, full
-    image) on the host cores, in Mvis/s."""
-    import numpy as np
-    from oracle import operator
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
-    v = vis.astype(np.complex128)
-    n0 = 2048
-    t = time.perf_counter()
-    operator.adjoint(p.uv[:n0], p.npix, p.fov_rad, v[:n0])
-    dt = time.perf_counter() - t
-    m = int(min(len(v), max(n0, n0 * seconds / max(dt, 1e-3))))
-    t = time.perf_counter()
-    operator.adjoint(p.uv[:m], p.npix, p.fov_rad, v[:m])
-    dt = time.perf_counter() - t
-    return {"value": m / dt / 1e6, "unit": "Mvis/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"FP64 exact adjoint (direct sum as chunked complex GEMM) of the first {m} "
-                      f"of {len(v)} visibilities onto the full {p.npix}^2 image, {dt:.1f} s"}
-
-
 def adjoint_at(api, torch, p, reps, label):
     """Gridded adjoint throughput on another workload (caller-order input):
     device time per adjoint (sum of its kernels, library events), Mvis/s and
@@ -354,10 +333,8 @@ def serving_leg(api, torch, n_req, slots):
     32-128 antennas, 5-200 sources, 20 dB, lambda = 0.05 lambda_max, stop at
     relative objective change 1e-4 or 100 iterations).  Runs the plain path
     (one pc_polyclean_solve at a time) and the batched server with every
-    request present at t = 0 (saturation), then the server on Poisson arrival
-    traces at 0.5x and 1.0x the plain path's solves/s.  Plain-path latencies
-    under those traces follow from its measured per-job service times (FIFO,
-    one job at a time)."""
+    request present at t = 0 (saturation), then both on Poisson arrival
+    traces at 0.5x and 1.0x the plain path's solves/s."""
     import numpy as np
     import sim
     from paper_2406_01342_amd import serving
@@ -387,7 +364,6 @@ def serving_leg(api, torch, n_req, slots):
     dobj = max(abs(r.result["objective"] - plain_by[r.rid].result["objective"]) /
                max(abs(plain_by[r.rid].result["objective"]), 1e-300)
                for r in srv.records if r.status == "done")
-    service = np.array([r.finished_s - r.admitted_s for r in precs])
     out = {"workload": "serving mix: grids 256^2-2048^2, 1e4-5e5 visibilities "
                        "(log-uniform), 32-128 antennas, 5-200 sources, 20 dB, "
                        "lambda = 0.05 lambda_max, stop at relative objective change 1e-4",
@@ -402,18 +378,186 @@ def serving_leg(api, torch, n_req, slots):
             r.arrival_s = float(a)
         srv = serving.Server(be, slots=slots)
         bat = srv.run(reqs)
-        fin, lat = 0.0, []
-        for a, sv in zip(arr, service):
-            fin = max(a, fin) + sv
-            lat.append(fin - a)
-        lat = np.array(lat)
-        pl = {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-              "solves_per_s": n_req / fin}
-        out[f"poisson_{mult}x"] = {"rate_per_s": rate, "batched": bat, "plain_fifo": pl}
+        # the plain path replayed on the same arrival trace (measured, one job
+        # at a time in arrival order)
+        pl, _ = serving.run_plain(be, reqs)
+        out[f"poisson_{mult}x"] = {"rate_per_s": rate, "batched": bat, "plain": pl}
         log(f"serving poisson {mult}x", bat, pl)
     out["batcher"] = be.stats()
     be.close_backend()
     return out
+
+
+ADJ_KERNELS = ("spread", "fold", "passA_adj", "passB_adj")
+
+
+def cpu_model():
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def solve_leg(api, torch, p, plan, dv, prm, steps, warmup, label, with_cert=True):
+    """Warm-up and timed solves of one problem: wall time per solve and the
+    in-solve full-grid adjoint throughput (library events)."""
+    cert = (torch.empty((p.npix, p.npix), dtype=torch.float32, device="cuda")
+            if with_cert else None)
+    kw = dict(prm)
+    if with_cert:
+        kw.update(cert=cert, want_certificate=1)
+    for w in range(warmup):
+        r = api.pc_polyclean_solve(plan, dv, **kw)
+        log(label, "warmup", w, {k: r[k] for k in ("iters", "natoms", "objective", "rel_gap",
+                                                      "seconds")})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for k in range(steps):
+        r = api.pc_polyclean_solve(plan, dv, **kw)
+        results.append(r)
+        log(label, "step", k, {kk: r[kk] for kk in ("iters", "inner_iters", "natoms",
+                                                     "objective", "rel_gap", "seconds",
+                                                     "adjoint_calls")})
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    calls = sum(r["adjoint_calls"] for r in results)
+    adj_s = sum(r["adjoint_seconds"] for r in results)
+    last = results[-1]
+    return {"ms_per_solve": wall / steps * 1e3, "solves_per_s": steps / wall,
+            "adjoint_mvis_per_s": p.nvis * calls / adj_s / 1e6,
+            "adjoint_ms": adj_s / calls * 1e3, "adjoint_calls_per_solve": calls / steps,
+            "iters": last["iters"], "inner_iters": last["inner_iters"],
+            "natoms": last["natoms"], "objective": last["objective"],
+            "rel_gap": last["rel_gap"], "converged": last["converged"],
+            "cert_max": last["cert_max"], "wall_s": wall}
+
+
+def profiled(api, plan, fn):
+    """Per-kernel statistics (library events) of fn()."""
+    api.pc_plan_profile(plan, True)
+    fn()
+    st = api.pc_plan_kernel_stats(plan)
+    api.pc_plan_profile(plan, False)
+    return st
+
+
+def adjoint_roofline(stats):
+    """Roofline object of the gridded adjoint's dominant kernel."""
+    adj = [x for x in stats if x["name"] in ADJ_KERNELS]
+    return dominant_roofline(adj, None)
+
+
+def m2_sweep(api, torch):
+    """M2: direct-DFT pair rates of the forward (a7) and the restricted
+    adjoint (a8) at nS in {100, 1000, 10000} atoms for the visibility counts of
+    the LOFAR-like and precision workloads (their own uv coverage), device
+    time from library events, against the derived vector-ALU ceiling."""
+    import numpy as np
+    import sim
+    out = []
+    for p in (sim.config_c2(), sim.config_c3()):
+        plan = api.pc_plan_create(p.uv, p.npix, p.fov_rad)
+        dv = torch.from_numpy(p.noise.astype(np.complex64)).cuda()
+        rng = np.random.default_rng(11)
+        for ns in (100, 1000, 10000):
+            pix = torch.from_numpy(rng.choice(p.npix * p.npix, ns, replace=False).astype(np.int32)).cuda()
+            w = torch.from_numpy(rng.lognormal(size=ns).astype(np.float32)).cuda()
+            reps = max(2, int(2e10 // (p.nvis * ns)))
+            for _ in range(2):
+                api.pc_forward_sparse(plan, pix, w)
+                api.pc_adjoint_sparse(plan, dv, pix)
+            st = profiled(api, plan, lambda: [(api.pc_forward_sparse(plan, pix, w),
+                                               api.pc_adjoint_sparse(plan, dv, pix))
+                                              for _ in range(reps)])
+            by = {x["name"]: x for x in st}
+            row = {"nvis": p.nvis, "natoms": ns}
+            for key, names in (("forward", ("forward_sparse",)),
+                               ("restricted_adjoint", ("adjoint_sparse", "adjoint_sparse_reduce"))):
+                ms = sum(by[n]["ms"] for n in names if n in by) / reps
+                gp = p.nvis * ns / (ms * 1e-3) / 1e9
+                row[key] = {"us": round(ms * 1e3, 1), "Gpair_per_s": round(gp, 1),
+                            "alu_frac": round(gp / DFT_PEAK_GPAIRS, 3)}
+            out.append(row)
+            log("M2", row)
+        plan.close()
+    return out
+
+
+def c5_mix_leg(api, torch, n_large, n_small):
+    """Memory-pressure mix, scaled down to n_large large jobs (8192^2,
+    8,372,224 visibilities) and n_small small ones (512^2, 50,400), each
+    returning its dual-certificate image, under an HBM budget that holds two
+    large jobs at once (admission by footprint): batched server against the
+    plain one-at-a-time path, all requests present at t = 0."""
+    import sim
+    from paper_2406_01342_amd import serving
+    reqs = []
+    for k in range(n_large + n_small):
+        p = sim.config_c5_large(job_id=k) if k < n_large else sim.config_c5_small(job_id=k)
+        plan0, vis = synth_inputs(api, torch, p)
+        plan0.close()
+        prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter,
+                   rel_obj_tol=p.rel_obj_tol, rel_gap_tol=p.rel_gap_tol)
+        reqs.append(serving.ImagingRequest(k, 0.0, p.uv, p.npix, p.fov_rad, vis, prm,
+                                           want_certificate=True))
+    torch.cuda.empty_cache()
+    be = serving.DeviceBackend(batched=True)
+    big = be.footprint(reqs[0])
+    budget = 2 * big + 8 * be.footprint(reqs[-1])
+    be.solve_plain(reqs[-1])  # warm the small grid's kernels
+    plain, precs = serving.run_plain(be, reqs)
+    log("C5 mix plain", plain)
+    srv = serving.Server(be, slots=8, hbm_budget=budget)
+    bat = srv.run(reqs)
+    log("C5 mix batched", bat)
+    by = {r.rid: r for r in precs}
+    dobj = max(abs(r.result["objective"] - by[r.rid].result["objective"]) /
+               abs(by[r.rid].result["objective"]) for r in srv.records if r.status == "done")
+    be.close_backend()
+    return {"workload": f"memory-pressure mix scaled to {n_large} large jobs (8192^2, 8,372,224 "
+                        f"visibilities) + {n_small} small jobs (512^2, 50,400 visibilities), "
+                        "certificate per job, all at t = 0",
+            "hbm_budget_bytes": budget, "large_job_footprint_bytes": big,
+            "plain": plain, "batched": bat,
+            "solves_per_s_ratio": bat["solves_per_s"] / plain["solves_per_s"],
+            "max_rel_objective_diff_batched_vs_plain": dobj}
+
+
+def cpu_baseline_c5(p, vis, seconds):
+    """FP64 oracle adjoint of a visibility sample onto the full 8192^2 image
+    of the memory-pressure large job, on the host cores, in Mvis/s."""
+    import numpy as np
+    from oracle import operator
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    v = vis.astype(np.complex128)
+    # calibrate the sample size on growing trial sizes (the first call also
+    # pays for thread start-up), then time one call of about `seconds`
+    m, dt = 64, 0.0
+    while dt < 0.1 * seconds and m < len(v):
+        t = time.perf_counter()
+        operator.adjoint(p.uv[:m], p.npix, p.fov_rad, v[:m])
+        dt = time.perf_counter() - t
+        if dt < 0.1 * seconds:
+            m *= 2
+    m = int(min(len(v), max(m, m * seconds / max(dt, 1e-3))))
+    t = time.perf_counter()
+    operator.adjoint(p.uv[:m], p.npix, p.fov_rad, v[:m])
+    dt = time.perf_counter() - t
+    return {"value": m / dt / 1e6, "unit": "Mvis/s", "cores": int(cores), "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"FP64 exact adjoint (direct sum as chunked complex GEMM) of the first {m} "
+                      f"of {len(v)} visibilities of the memory-pressure large job onto its full "
+                      f"{p.npix}^2 image, {dt:.1f} s"}
 
 
 def main():
@@ -450,124 +594,126 @@ def main():
         print(json.dumps({"dictionary": dictionary_leg(api, torch, max(5, args.adjoint_reps // 4),
                                                        with_solve=False)}), flush=True)
         return
-    p = sim.config_c2()
-    log("workload C2", p.nvis, "visibilities", p.npix, "pixels")
-    t = time.perf_counter()
+
+    # ---- headline: the memory-pressure large job, full solves ----------------
+    p = sim.config_c5_large()
+    log("workload C5-large", p.nvis, "visibilities", p.npix, "pixels")
     plan0, vis = synth_inputs(api, torch, p)
-    del plan0
+    plan0.close()
+    torch.cuda.synchronize()
     t = time.perf_counter()
     plan = api.pc_plan_create(p.uv, p.npix, p.fov_rad)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t) * 1e3
     log("plan", f"{plan_ms:.1f} ms", plan.info)
     dv = torch.from_numpy(vis).cuda()
-    prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter, rel_gap_tol=p.rel_gap_tol)
-
-    for w in range(args.warmup):
-        r = api.pc_polyclean_solve(plan, dv, **prm)
-        log("warmup", w, {k: r[k] for k in ("iters", "natoms", "objective", "rel_gap", "seconds")})
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for k in range(args.steps):
-        r = api.pc_polyclean_solve(plan, dv, **prm)
-        results.append(r)
-        log("step", k, {kk: r[kk] for kk in ("iters", "inner_iters", "natoms", "objective",
-                                              "rel_gap", "seconds", "adjoint_calls")})
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    adj_calls = sum(r["adjoint_calls"] for r in results)
-    adj_s = sum(r["adjoint_seconds"] for r in results)
-    value = p.nvis * adj_calls / adj_s / 1e6
-
-    # the positivity-constrained solve of the same data (same kernels, signed
-    # exploration and one-sided prox)
-    api.pc_polyclean_solve(plan, dv, positivity=1, **prm)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    pos = [api.pc_polyclean_solve(plan, dv, positivity=1, **prm) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    pos_ms = (time.perf_counter() - t) / args.steps * 1e3
-    positive_solve = {"ms": pos_ms, "iters": pos[-1]["iters"], "natoms": pos[-1]["natoms"],
-                      "rel_gap": pos[-1]["rel_gap"], "converged": pos[-1]["converged"],
-                      "objective": pos[-1]["objective"]}
-    log("positive solve", positive_solve)
-
-    # standalone adjoint (caller-order input) timed with events on its stream
-    img = torch.empty((p.npix, p.npix), dtype=torch.float32, device="cuda")
-    s = torch.cuda.current_stream()
-    for _ in range(3):
-        api.pc_adjoint_grid(plan, dv, img, want_max=False)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(args.adjoint_reps):
-        api.pc_adjoint_grid(plan, dv, img, want_max=False)
-    e1.record(s)
-    e1.synchronize()
-    adj_ms = e0.elapsed_time(e1) / args.adjoint_reps
-
-    # one profiled solve: per-kernel device time and algorithmic bytes / work
-    api.pc_plan_profile(plan, True)
-    api.pc_polyclean_solve(plan, dv, **prm)
-    stats = api.pc_plan_kernel_stats(plan)
-    api.pc_plan_profile(plan, True)
-    for _ in range(args.adjoint_reps):
-        api.pc_adjoint_grid(plan, dv, img, want_max=False)
-    adj_stats = api.pc_plan_kernel_stats(plan)
-    api.pc_plan_profile(plan, False)
-    roof = dominant_roofline(stats, plan.info)
-    adj_roof = dominant_roofline(adj_stats, plan.info)
-    adj_bytes = sum(st["bytes"] for st in adj_stats) / args.adjoint_reps
-    adj_dev_ms = sum(st["ms"] for st in adj_stats) / args.adjoint_reps
+    prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter, rel_obj_tol=p.rel_obj_tol,
+               rel_gap_tol=p.rel_gap_tol)
+    head = solve_leg(api, torch, p, plan, dv, prm, args.steps, args.warmup, "C5-large")
+    value = head["adjoint_mvis_per_s"]
+    cert = torch.empty((p.npix, p.npix), dtype=torch.float32, device="cuda")
+    stats = profiled(api, plan, lambda: api.pc_polyclean_solve(plan, dv, cert=cert,
+                                                               want_certificate=1, **prm))
+    roof = adjoint_roofline(stats)
+    adj_bytes = sum(x["bytes"] for x in stats if x["name"] in ADJ_KERNELS)
+    adj_launch = max(x["launches"] for x in stats if x["name"] == "spread")
+    adj_ms = sum(x["ms"] for x in stats if x["name"] in ADJ_KERNELS)
     n = p.npix
-    b_model_f1 = 16 * p.nvis + 100 * n * n
     out = {
         "metric": METRIC, "value": value, "unit": "Mvis/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "LOFAR-like PolyCLEAN solve: 60 stations (48-station 300 m "
-                               "Gaussian core + 12 in a 1-10 km ring), 240 snapshots over 4 h, "
-                               "424,800 complex64 visibilities, 1024^2 grid, FOV 4 deg, 150 "
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_solve"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "memory-pressure large job, full PolyCLEAN solve with dual "
+                               "certificate: 512 stations (SKA-low-like core and arms, 40 km), 16 "
+                               "snapshots x 4 channels 120-180 MHz stacked, 8,372,224 complex64 "
+                               "visibilities, 8192^2 image (16384^2 fine grid), FOV 3 deg, 200 "
                                "log-normal sources, 20 dB, lambda = 0.05 lambda_max, stop at "
-                               "relative duality gap 1e-4",
+                               "relative objective change 1e-4",
                    "nvis": p.nvis, "npix": n, "fine_grid": plan.info["fine"],
-                   "kernel_width": plan.info["kernel_width"], "band_wraps": plan.info["wraps"]},
-        # the metric is the gridded adjoint's: its dominant kernel
-        "roofline": adj_roof,
-        "solves_per_s": args.steps / wall,
-        "solve": {"iters": results[-1]["iters"], "inner_iters": results[-1]["inner_iters"],
-                  "natoms": results[-1]["natoms"], "objective": results[-1]["objective"],
-                  "rel_gap": results[-1]["rel_gap"], "adjoint_calls_per_solve": adj_calls / args.steps,
-                  "dominant_kernel": roof},
-        "positive_solve": positive_solve,
+                   "band": [plan.info["band_nu"], plan.info["band_nv"]],
+                   "kernel_width": plan.info["kernel_width"]},
+        "roofline": roof,
+        "solve": head,
         "plan_ms": plan_ms,
-        "adjoint": {"ms_standalone": adj_ms, "mvis_per_s_standalone": p.nvis / adj_ms / 1e3,
-                    "device_ms_sum_of_kernels": adj_dev_ms,
-                    "algorithmic_bytes": adj_bytes, "hbm_frac_implemented": adj_bytes / (adj_dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                    "bytes_model_f1": b_model_f1,
-                    "hbm_frac_f1": b_model_f1 / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "kernels": sorted(({"name": s_["name"], "launches": s_["launches"], "ms": round(s_["ms"], 3)}
-                           for s_ in stats), key=lambda d: -d["ms"])[:8],
+        "adjoint": {"per_launch_ms_sum_of_kernels": adj_ms / adj_launch,
+                    "algorithmic_bytes_per_adjoint": adj_bytes / adj_launch,
+                    "hbm_frac_implemented": adj_bytes / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "bytes_model_f1": 16 * p.nvis + 100 * n * n,
+                    "kernels_us": {x["name"]: round(1e3 * x["ms"] / x["launches"], 2)
+                                   for x in stats if x["name"] in ADJ_KERNELS}},
+        "kernels": sorted(({"name": x["name"], "launches": x["launches"],
+                            "ms": round(x["ms"], 3)} for x in stats),
+                          key=lambda d: -d["ms"])[:10],
+        "alu_ceiling": {"Gpair_per_s": DFT_PEAK_GPAIRS,
+                        "derivation": "256 CUs x 2.4 GHz x 128 FP32 lane-slots per clock = "
+                                      "78.6e12 lane-slots/s (the published 157.3 TFLOP/s FP32 "
+                                      "vector peak counts an FMA as two flops); one "
+                                      "visibility-atom pair of the direct DFT costs about 19 "
+                                      "slots (FP64 phase FMA pair and range reduction at the "
+                                      "78.6 TFLOP/s FP64 rate, FP32 sin and cos at quarter "
+                                      "rate, two FP32 FMAs)"},
     }
-    if not args.no_other_workloads:
-        out["adjoint_other_workloads"] = [
-            adjoint_at(api, torch, sim.config_c3(), args.adjoint_reps,
-                       "precision workload: 256 stations, 2,088,960 visibilities, 4096^2, FOV 3 deg"),
-            adjoint_at(api, torch, sim.config_c5_large(), max(5, args.adjoint_reps // 5),
-                       "memory-pressure large job: 512 stations x 16 snapshots x 4 channels, "
-                       "8,372,224 visibilities, 8192^2 (16384^2 fine grid), FOV 3 deg"),
-        ]
-    if not args.no_other_workloads:
-        out["dictionary"] = dictionary_leg(api, torch, max(5, args.adjoint_reps // 4))
-    if args.serving_requests > 0:
-        del plan, dv
-        torch.cuda.empty_cache()
-        out["serving"] = serving_leg(api, torch, args.serving_requests, args.serving_slots)
+    # standalone adjoint of caller-order visibilities (the dirty image)
+    img = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    s_ = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.adjoint_reps // 5)
+    e0.record(s_)
+    for _ in range(reps):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    e1.record(s_)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["adjoint"]["standalone_caller_order_ms"] = ms
+    out["adjoint"]["standalone_mvis_per_s"] = p.nvis / ms / 1e3
+    log("C5-large adjoint", out["adjoint"])
+    # operator-form solve of the same job (gram_atoms < 0: a7/a8 inside APGD)
+    op = solve_leg(api, torch, p, plan, dv, dict(prm, gram_atoms=-1), max(1, args.steps // 5), 1,
+                   "C5-large operator form")
+    out["solve_operator_form"] = op
+    del dv, img, cert
+    plan.close()
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(p, vis, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline_c5(p, vis, args.cpu_seconds)
+    del vis
+
+    # ---- LOFAR-like solves: Gram form (default), operator form, positivity ----
+    p2 = sim.config_c2()
+    plan2, vis2 = synth_inputs(api, torch, p2)
+    dv2 = torch.from_numpy(vis2).cuda()
+    prm2 = dict(alpha=p2.alpha, delta=p2.delta, max_iter=p2.max_iter,
+                rel_gap_tol=p2.rel_gap_tol)
+    c2 = {"workload": "LOFAR-like: 60 stations (48-station 300 m Gaussian core + 12 in a 1-10 km "
+                      "ring), 240 snapshots over 4 h, 424,800 visibilities, 1024^2, FOV 4 deg, 150 "
+                      "sources, 20 dB, lambda = 0.05 lambda_max, stop at relative duality gap 1e-4"}
+    c2["gram_form"] = solve_leg(api, torch, p2, plan2, dv2, prm2, 10, 2, "C2 gram", False)
+    c2["operator_form"] = solve_leg(api, torch, p2, plan2, dv2, dict(prm2, gram_atoms=-1), 5, 1,
+                                    "C2 operator", False)
+    st2 = profiled(api, plan2, lambda: api.pc_polyclean_solve(plan2, dv2, gram_atoms=-1, **prm2))
+    c2["operator_form"]["dominant_kernel"] = dominant_roofline(st2, None)
+    c2["positive"] = solve_leg(api, torch, p2, plan2, dv2, dict(prm2, positivity=1), 5, 1,
+                               "C2 positive", False)
+    c2["adjoint_standalone"] = adjoint_at(api, torch, p2, args.adjoint_reps,
+                                          "LOFAR-like workload: 424,800 visibilities, 1024^2")
+    out["lofar_like"] = c2
+    plan2.close()
+    del dv2
+
+    if not args.no_other_workloads:
+        out["adjoint_precision_workload"] = adjoint_at(
+            api, torch, sim.config_c3(), args.adjoint_reps,
+            "precision workload: 256 stations, 2,088,960 visibilities, 4096^2, FOV 3 deg")
+        out["m2_direct_dft"] = m2_sweep(api, torch)
+        out["dictionary"] = dictionary_leg(api, torch, max(5, args.adjoint_reps // 4))
+    if args.serving_requests > 0:
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(api, torch, args.serving_requests, args.serving_slots)
+        out["serving_memory_pressure"] = c5_mix_leg(api, torch, 2, 16)
     print(json.dumps(out), flush=True)
 
 

@@ -82,7 +82,9 @@ class DeviceBackend:
     """Runs jobs through the HIP library on one device."""
 
     #: solver state resident per job beyond the plan: sorted visibilities and
-    #: residual (2 x 8 L), dirty-residual image (4 n^2), caller-order upload
+    #: residual (2 x 8 L), dirty-residual image (4 n^2), the dense image of the
+    #: gridded operators (4 n^2, allocated once the active set reaches their
+    #: crossover, and for every synthesis-form solve), caller-order upload
     #: (8 L) and a fixed allowance for candidate lists and atom tables
     FIXED_BYTES = 4 << 20
 
@@ -100,8 +102,9 @@ class DeviceBackend:
         plan = self.api.pc_plan_footprint(req.uv, req.npix, req.fov_rad)
         S = _n_scales(req)
         cert = 4 * S * req.npix * req.npix if req.want_certificate else 0
-        # the dirty residual, plus its per-scale analysis with a dictionary
-        img = 4 * req.npix * req.npix * (1 + (S if "scales" in req.params else 0))
+        # the dirty residual and the gridded operators' dense image, plus the
+        # per-scale analysis with a dictionary
+        img = 4 * req.npix * req.npix * (2 + (S if "scales" in req.params else 0))
         return int(plan) + 24 * L + img + cert + self.FIXED_BYTES
 
     def _params(self, req: ImagingRequest) -> dict:
