@@ -10,7 +10,8 @@ returned separately so both sides use the exact same numbers.
 
 Conventions (paper, Sect. 2.1 "Forward operator" and Sect. 2.2):
   * (u, v, w) are baseline coordinates in wavelengths; the arrays here are
-    coplanar (w = 0), the narrow-field / coplanar remark of Sect. 2.1.
+    coplanar (w = 0), the narrow-field / coplanar remark of Sect. 2.1, except
+    the non-coplanar variant of the LOFAR-like recipe, which keeps w.
   * One Hermitian half is generated: baselines i < j, no autocorrelations.
   * Noise is white complex Gaussian (Sect. 2.1 "Noise model"); its standard
     deviation is set from a peak signal-to-noise ratio as
@@ -79,12 +80,13 @@ def layout_core_arms(rng: np.random.Generator, n_ant: int, core_frac: float,
 # ----------------------------------------------------------------------------
 def earth_rotation_uv(pos_en: np.ndarray, freq_hz: float, n_snap: int,
                       duration_h: float, dec_rad: float,
-                      lat_rad: float = -26.7 * DEG) -> np.ndarray:
+                      lat_rad: float = -26.7 * DEG, keep_w: bool = False) -> np.ndarray:
     """(u, v) in wavelengths for all baselines i<j and snapshots.
 
     Returns an array of shape (n_snap * n_bl, 2), time-major (all baselines of
     snapshot 0, then snapshot 1, ...), which is the order a correlator writes.
-    Hour angles are symmetric about transit.  w is discarded (set to 0).
+    Hour angles are symmetric about transit.  w is discarded (set to 0), or
+    kept as a third column with ``keep_w`` (the non-coplanar case).
     """
     e, nth = pos_en[:, 0], pos_en[:, 1]
     # local (E, N, U=0) -> equatorial (X, Y, Z)
@@ -103,7 +105,11 @@ def earth_rotation_uv(pos_en: np.ndarray, freq_hz: float, n_snap: int,
     sd, cd = math.sin(dec_rad), math.cos(dec_rad)
     u = sh * bx[None, :] + ch * by[None, :]
     v = -sd * ch * bx[None, :] + sd * sh * by[None, :] + cd * bz[None, :]
-    return np.stack([u.reshape(-1) / lam, v.reshape(-1) / lam], axis=1)
+    cols = [u.reshape(-1) / lam, v.reshape(-1) / lam]
+    if keep_w:
+        w = cd * ch * bx[None, :] - cd * sh * by[None, :] + sd * bz[None, :]
+        cols.append(w.reshape(-1) / lam)
+    return np.stack(cols, axis=1)
 
 
 # ----------------------------------------------------------------------------
@@ -197,8 +203,9 @@ class Problem:
 
 
 def _problem(name, cfg_id, job_id, pos, freq, n_snap, dur_h, dec, npix, fov_deg,
-             sky, psnr, alpha, delta, max_iter, rel_obj_tol, rel_gap_tol) -> Problem:
-    uv = earth_rotation_uv(pos, freq, n_snap, dur_h, dec)
+             sky, psnr, alpha, delta, max_iter, rel_obj_tol, rel_gap_tol,
+             keep_w: bool = False) -> Problem:
+    uv = earth_rotation_uv(pos, freq, n_snap, dur_h, dec, keep_w=keep_w)
     pix, amp = sky
     noise = complex_normal(rng_for(cfg_id, job_id, STREAM_NOISE), uv.shape[0])
     return Problem(name, uv, npix, fov_deg * DEG, freq, pix, amp, noise, psnr,
@@ -216,15 +223,18 @@ def config_c1(job_id: int = 0) -> Problem:
 
 
 def config_c2(job_id: int = 0, n_snap: int = 240, npix: int = 1024,
-              n_core: int = 48, n_ring: int = 12, n_src: int = 150) -> Problem:
+              n_core: int = 48, n_ring: int = 12, n_src: int = 150,
+              keep_w: bool = False) -> Problem:
     """LOFAR-like: 48 Gaussian-core (300 m) + 12 ring (1-10 km) stations, 240
     snapshots over 4 h, 1024^2 grid, FOV 4 deg, 150 sources, 20 dB, alpha 0.05,
-    stop at relative dual gap 1e-4.  Smaller variants keep the recipe."""
+    stop at relative dual gap 1e-4.  Smaller variants keep the recipe;
+    ``keep_w`` keeps the baselines' w (the non-coplanar variant, uv then has
+    three columns)."""
     pos = layout_core_ring(rng_for(2, job_id, STREAM_LAYOUT), n_core, 300.0, n_ring,
                            1000.0, 10000.0)
     sky = point_sky(rng_for(2, job_id, STREAM_SKY), npix, n_src)
-    return _problem("C2", 2, job_id, pos, 150e6, n_snap, 4.0, -45 * DEG, npix, 4.0,
-                    sky, 20.0, 0.05, 0.95, 500, 0.0, 1e-4)
+    return _problem("C2W" if keep_w else "C2", 2, job_id, pos, 150e6, n_snap, 4.0, -45 * DEG,
+                    npix, 4.0, sky, 20.0, 0.05, 0.95, 500, 0.0, 1e-4, keep_w=keep_w)
 
 
 def config_c3(job_id: int = 0, n_snap: int = 64, npix: int = 4096, n_ant: int = 256,

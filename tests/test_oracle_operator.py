@@ -143,3 +143,83 @@ def test_forward_images_equals_forward_per_image():
     for c in range(3):
         want = operator.forward(uv, n, fov, np.arange(n * n), imgs[:, c])
         assert np.max(np.abs(got[:, c] - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+# --- the w-term (Sect. 2.1, Eq. phi-plane: W(l, m; w) = exp(-j 2 pi w (n - 1))) ---
+
+def _small_w(seed=0, L=300, n=16, fov=0.6):
+    rng = np.random.default_rng(seed)
+    uvw = rng.uniform(-40, 40, size=(L, 3))
+    return uvw, n, fov, rng
+
+
+def test_w_phase_centre_source_is_constant():
+    """At the phase centre n = 1, so W = 1 whatever w: V_k = a."""
+    uvw, n, fov, _ = _small_w()
+    p = (n // 2) * n + n // 2
+    V = operator.forward(uvw, n, fov, [p], [2.5])
+    assert np.allclose(V, 2.5, rtol=1e-15, atol=0)
+
+
+def test_w_forward_is_the_spherical_phase_in_any_frame():
+    """Eq. phi-sphere referred to the phase centre r0 = (0, 0, 1): a source at
+    direction r = (l, m, n) gives V_k = (a / n) exp(-j 2 pi <r - r0, p_k>),
+    p_k = (u, v, w).  The inner product is evaluated here on 3-vectors rotated
+    into a random orthonormal frame (it is rotation invariant), a route
+    independent of the oracle's tangent-plane formula."""
+    uvw, n, fov, rng = _small_w(1)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    for (i, j) in ((2, 13), (11, 4), (0, 0)):
+        d = fov / n
+        l, m = (i - n // 2) * d, (j - n // 2) * d
+        nn = math.sqrt(1 - l * l - m * m)
+        r = q @ np.array([l, m, nn])
+        r0 = q @ np.array([0.0, 0.0, 1.0])
+        pk = uvw @ q.T
+        want = 0.8 / nn * np.exp(-2j * math.pi * (pk @ (r - r0)))
+        got = operator.forward(uvw, n, fov, [i * n + j], [0.8])
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_w_adjoint_dot_product(seed):
+    """<Phi x, h>_R = <x, Phi* h> with the w-term (dense x, random h)."""
+    uvw, n, fov, rng = _small_w(seed, L=211, n=14, fov=0.8)
+    x = rng.normal(size=(n, n))
+    h = rng.normal(size=uvw.shape[0]) + 1j * rng.normal(size=uvw.shape[0])
+    lhs = float(np.vdot(h, operator.forward_dense(uvw, n, fov, x)).real)
+    rhs = float(np.sum(x * operator.adjoint(uvw, n, fov, h)))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+
+
+def test_w_direct_adjoint_reduces_to_the_coplanar_one():
+    """A negligible w sends the adjoint through the per-pixel direct sum; it
+    must equal the separable (pinned) coplanar evaluation."""
+    uvw, n, fov, rng = _small_w(3, L=250, n=12, fov=0.5)
+    h = rng.normal(size=uvw.shape[0]) + 1j * rng.normal(size=uvw.shape[0])
+    tiny = uvw.copy()
+    tiny[:, 2] = 1e-300
+    a = operator.adjoint(tiny, n, fov, h)
+    b = operator.adjoint(uvw[:, :2], n, fov, h)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+def test_w_dirty_image_at_the_source_pixel():
+    """Phi* Phi delta_p at p itself: every phase cancels, so the value is
+    L / n_p^2 whatever the w of the visibilities."""
+    uvw, n, fov, _ = _small_w(4)
+    for p in (5, 3 * n + 9, n * n - 1):
+        V = operator.forward(uvw, n, fov, [p], [1.0])
+        img = operator.adjoint_pixels(uvw, n, fov, V, [p])
+        _, _, npp = geometry.pixel_coords(np.array([p]), n, fov)
+        assert abs(img[0] - uvw.shape[0] / npp[0] ** 2) <= 1e-12 * uvw.shape[0]
+
+
+def test_generator_w_keeps_the_baseline_length():
+    """Earth rotation only rotates a baseline: u^2 + v^2 + w^2 is the squared
+    baseline length in wavelengths at every snapshot."""
+    p = sim.config_c2(n_snap=5, npix=64, keep_w=True)
+    nbl = 60 * 59 // 2
+    b2 = (p.uv ** 2).sum(axis=1).reshape(5, nbl)
+    assert np.allclose(b2, b2[0][None, :], rtol=1e-12)
+    assert np.max(np.abs(p.uv[:, 2])) > 100.0
