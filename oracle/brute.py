@@ -20,12 +20,16 @@ from .geometry import direction_cosines, n_term
 
 
 def explicit_matrix(uv, npix: int, fov_rad: float) -> np.ndarray:
-    """A = [Re Phi; Im Phi] (2L x N), column p = i*n + j."""
+    """A = [Re Phi; Im Phi] (2L x N), column p = i*n + j; (L, 3) baselines
+    add the w-term phase w (n - 1) of Eq. phi-plane."""
     uv = np.asarray(uv, np.float64)
     l = direction_cosines(npix, fov_rad)
     li = np.repeat(l, npix)
     mj = np.tile(l, npix)
     ph = np.outer(uv[:, 0], li) + np.outer(uv[:, 1], mj)
+    if uv.shape[1] > 2:
+        r2 = li ** 2 + mj ** 2
+        ph += np.outer(uv[:, 2], -r2 / (1.0 + np.sqrt(1.0 - r2)))
     phi = np.exp(-2j * np.pi * ph) / n_term(npix, fov_rad).reshape(-1)[None, :]
     return np.concatenate([phi.real, phi.imag], axis=0)
 

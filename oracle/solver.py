@@ -62,7 +62,7 @@ import numpy as np
 
 from . import dictionary as dic
 from .geometry import pixel_coords
-from .operator import adjoint, forward, forward_images
+from .operator import adjoint, forward, forward_images, n_minus_one
 
 _CHUNK_ELEMS = 1 << 22
 
@@ -104,7 +104,8 @@ class GramCache:
     """Columns of G = Re(Phi^H Phi) for every pixel ever activated.
 
     G[p, q] = Re sum_k exp(+j2pi t_kp) exp(-j2pi t_kq) / (n_p n_q), with
-    t_kp = u_k l_p + v_k m_p.  Computed with complex128 matrix products over
+    t_kp = u_k l_p + v_k m_p (+ w_k (n_p - 1) for (L, 3) baselines, the
+    w-term of Eq. phi-plane).  Computed with complex128 matrix products over
     chunks of visibilities; only pairs involving new pixels are computed.
     """
 
@@ -114,9 +115,14 @@ class GramCache:
         self.pix = np.zeros(0, np.int64)
         self.G = np.zeros((0, 0))
 
-    def _cols(self, pix):
+    def _phase(self, s, step, pix):
+        """t_kp for visibilities s..s+step and pixels pix, and 1/n_p."""
         lp, mp, npp = pixel_coords(pix, self.npix, self.fov)
-        return lp, mp, npp
+        uv = self.uv[s:s + step]
+        ph = np.outer(uv[:, 0], lp) + np.outer(uv[:, 1], mp)
+        if uv.shape[1] > 2:
+            ph += np.outer(uv[:, 2], n_minus_one(lp, mp))
+        return ph, npp
 
     def ensure(self, pix_new: np.ndarray):
         pix_new = np.setdiff1d(np.asarray(pix_new, np.int64), self.pix)
@@ -124,18 +130,16 @@ class GramCache:
             return
         old = self.pix
         allp = np.concatenate([old, pix_new])
-        lo, mo, no = self._cols(old)
-        ln, mn, nn = self._cols(pix_new)
-        u, v = self.uv[:, 0], self.uv[:, 1]
         g_no = np.zeros((pix_new.size, old.size))
         g_nn = np.zeros((pix_new.size, pix_new.size))
         step = max(1, _CHUNK_ELEMS // max(1, allp.size))
-        for s in range(0, u.size, step):
-            us, vs = u[s:s + step], v[s:s + step]
-            en = np.exp(-2j * np.pi * (np.outer(us, ln) + np.outer(vs, mn))) / nn
+        for s in range(0, self.uv.shape[0], step):
+            ph_n, nn = self._phase(s, step, pix_new)
+            en = np.exp(-2j * np.pi * ph_n) / nn
             g_nn += (en.conj().T @ en).real
             if old.size:
-                eo = np.exp(-2j * np.pi * (np.outer(us, lo) + np.outer(vs, mo))) / no
+                ph_o, no = self._phase(s, step, old)
+                eo = np.exp(-2j * np.pi * ph_o) / no
                 g_no += (en.conj().T @ eo).real
         G = np.zeros((allp.size, allp.size))
         G[:old.size, :old.size] = self.G

@@ -115,13 +115,37 @@ struct DeviceBuf {
 };
 
 // One active atom of a sparse image: pixel offsets from the phase centre
-// (a = i - n/2, b = j - n/2), 1/n(l, m), and the forward weight x / n(l, m).
+// (a = i - n/2, b = j - n/2), 1/n(l, m), c = n(l, m) - 1 (the w-term's
+// direction factor, <= 0) and the forward weight x / n(l, m).
 template <typename R>
 struct Atom {
   double a, b;
   double inv_n;
+  double c;
   R w;
   R pad;
+};
+
+// c = n - 1 = -(l^2 + m^2) / (1 + n), without the
+// cancellation of sqrt(1 - r^2) - 1 near the phase centre.
+__host__ __device__ inline double n_minus_one(double l, double m) {
+  const double r2 = l * l + m * m;
+  return -r2 / (1.0 + sqrt(1.0 - r2));
+}
+
+// Planes of the w-stacked gridded adjoint (non-coplanar baselines).  The
+// factor exp(+2 pi i w_k c) of Eq. adjoint-phi is split as
+// exp(2 pi i w_k c_mid) exp(2 pi i w_k c'), c' = c - c_mid in
+// [-half, half]; the second factor is spread over planes w_j = w0 + j dw with
+// the same ES kernel along w (width W, plane units), so that
+//   exp(2 pi i w_k c') ~ sum_j psi((w_k - w_j) / dw) exp(2 pi i w_j c') / Psi(dw c'),
+// Psi the kernel's Fourier transform; dw = 1 / (4 half) keeps |dw c'| <= 1/4,
+// the band the kernel is designed for at upsampling 2.
+struct WStack {
+  int nplanes = 0;  // 0: coplanar plan
+  double w0 = 0, dw = 0;
+  double cmid = 0;
+  int nquad = 0;    // Gauss-Legendre nodes on [0, 1] of the Psi integral
 };
 
 // Everything the gridded adjoint's kernels need about one plan, for launches
@@ -181,6 +205,7 @@ struct pc_plan {
   // Per-visibility data in plan (tile-sorted) order.
   int32_t* perm = nullptr;      // sorted index -> caller index
   double* AB = nullptr;         // [2L] (u dl, v dl) turns per pixel, FP64
+  double* Cw = nullptr;         // [L] w in wavelengths (NULL: coplanar plan)
   uint32_t* cell = nullptr;     // [L] packed first cell (v << 16 | u), absolute
   void* off = nullptr;          // [2L] float or double: (s_u, s_v) offsets
   // Spreading work list.
@@ -198,6 +223,9 @@ struct pc_plan {
   unsigned long long* maxkey = nullptr;  // packed (|x| bits, ~index)
   int max_positive = 0;  // the key holds max(x, 0) in place of |x| (positivity-constrained solve)
   void* vis_scratch = nullptr;  // complex [L] in plan order (residual etc.)
+  pc::WStack ws;                // w-stacking planes (nplanes 0: coplanar)
+  void* wvals = nullptr;        // complex [L]: one plane's weighted visibilities
+  double* wquad = nullptr;      // [2 nquad]: nodes z_q, weights (W/2) w_q phi(z_q)
   void* atom_scratch = nullptr; // per-atom staging
   size_t atom_capacity = 0;
   double* red_scratch = nullptr;  // reduction partials

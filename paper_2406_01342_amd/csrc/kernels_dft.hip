@@ -8,6 +8,10 @@
 // reach ~10^3 turns, beyond FP32's resolution); the reduced value feeds the
 // hardware sine/cosine, whose argument is in revolutions, in FP32.  The FP64
 // twin evaluates sin/cos of 2 pi t in double.
+//
+// Non-coplanar baselines (Sect. 2.1, Eq. phi-plane) add the w-term's phase
+// w_k c_p, c_p = n_p - 1, to t, also in FP64 (template flag HW; the plan then
+// holds w_k in plan order, the atom table c_p).
 #include <algorithm>
 #include <cstring>
 
@@ -26,7 +30,7 @@ __global__ void atom_prep_kernel(int64_t natoms, int64_t ntotal, int n, double d
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ntotal) return;
   if (p >= natoms) {  // padding: the phase-centre pixel with zero weight
-    atoms[p] = Atom<R>{0.0, 0.0, 1.0, R(0), R(0)};
+    atoms[p] = Atom<R>{0.0, 0.0, 1.0, 0.0, R(0), R(0)};
     return;
   }
   const int q = pix[p];
@@ -38,6 +42,7 @@ __global__ void atom_prep_kernel(int64_t natoms, int64_t ntotal, int n, double d
   at.a = a;
   at.b = b;
   at.inv_n = inv_n;
+  at.c = n_minus_one(l, m);
   at.w = weight ? (R)((double)weight[p] * inv_n) : R(0);
   at.pad = R(0);
   atoms[p] = at;
@@ -61,14 +66,16 @@ __device__ __forceinline__ void sincos_turns(double t, R& s, R& c) {
 // out_k = base_k - sum_p w_p exp(-2 pi i t_kp)   (base NULL: no base term)
 // One thread per visibility (plan order); atoms are read with uniform
 // (scalar) loads.
-template <typename R>
+template <typename R, bool HW>
 __global__ __launch_bounds__(256) void forward_sparse_kernel(
-    int64_t L, int64_t natoms, const double* __restrict__ AB, const Atom<R>* __restrict__ atoms,
+    int64_t L, int64_t natoms, const double* __restrict__ AB, const double* __restrict__ Cw,
+    const Atom<R>* __restrict__ atoms,
     const cpx<R>* __restrict__ base, const int32_t* __restrict__ base_perm, R sign_base,
     cpx<R>* __restrict__ out, const int32_t* __restrict__ out_perm) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= L) return;
   const double A = AB[2 * k], B = AB[2 * k + 1];
+  const double C = HW ? Cw[k] : 0.0;
   R re = 0, im = 0;
   int64_t p = 0;
   for (; p + 4 <= natoms; p += 4) {
@@ -76,6 +83,7 @@ __global__ __launch_bounds__(256) void forward_sparse_kernel(
     for (int q = 0; q < 4; ++q) {
       const Atom<R> at = atoms[p + q];
       double t = fma(A, at.a, B * at.b);
+      if constexpr (HW) t = fma(C, at.c, t);
       t -= rint(t);
       R s, c;
       sincos_turns<R>(t, s, c);
@@ -86,6 +94,7 @@ __global__ __launch_bounds__(256) void forward_sparse_kernel(
   for (; p < natoms; ++p) {
     const Atom<R> at = atoms[p];
     double t = fma(A, at.a, B * at.b);
+    if constexpr (HW) t = fma(C, at.c, t);
     t -= rint(t);
     R s, c;
     sincos_turns<R>(t, s, c);
@@ -139,18 +148,25 @@ static AdjShape adjoint_shape(int64_t L, int64_t natoms) {
   return sh;
 }
 
-template <typename R>
+template <typename R, bool HW>
 struct VisRec {
   double A, B;
+  cpx<R> h;
+};
+template <typename R>
+struct VisRec<R, true> {
+  double A, B, C;
   cpx<R> h;
 };
 
 // One pair's term Re(h e^{+2 pi i t}) added to acc; with UNIT h is real (1,
 // or 0 for a record past the chunk), so the term is h cos 2 pi t and the sine
 // is never formed.
-template <typename R, typename A, bool UNIT = false>
-__device__ __forceinline__ void adj_pair(const VisRec<R>& v, double a, double b, A& acc) {
+template <typename R, typename A, bool UNIT, bool HW>
+__device__ __forceinline__ void adj_pair(const VisRec<R, HW>& v, double a, double b, double c,
+                                         A& acc) {
   double t = fma(v.A, a, v.B * b);
+  if constexpr (HW) t = fma(v.C, c, t);
   t -= rint(t);
   if constexpr (UNIT) {
     if constexpr (sizeof(R) == 4) {
@@ -166,14 +182,17 @@ __device__ __forceinline__ void adj_pair(const VisRec<R>& v, double a, double b,
   }
 }
 
-template <typename R, bool UNIT = false>
-__device__ __forceinline__ VisRec<R> load_vis(int64_t k, int64_t k1, const double* __restrict__ AB,
-                                              const cpx<R>* __restrict__ vis,
-                                              const int32_t* __restrict__ perm) {
-  VisRec<R> r{0.0, 0.0, {R(0), R(0)}};  // past the chunk: contributes zero
+template <typename R, bool UNIT, bool HW>
+__device__ __forceinline__ VisRec<R, HW> load_vis(int64_t k, int64_t k1,
+                                                  const double* __restrict__ AB,
+                                                  const double* __restrict__ Cw,
+                                                  const cpx<R>* __restrict__ vis,
+                                                  const int32_t* __restrict__ perm) {
+  VisRec<R, HW> r{};  // past the chunk: contributes zero
   if (k < k1) {
     r.A = AB[2 * k];
     r.B = AB[2 * k + 1];
+    if constexpr (HW) r.C = Cw[k];
     if constexpr (UNIT)
       r.h = {R(1), R(0)};
     else
@@ -190,15 +209,15 @@ __device__ __forceinline__ void wave_sync() {
 
 // With UNIT every visibility is 1 (vis is not read): the point-spread sums
 // sum_k cos 2 pi (A_k a + B_k b).
-template <typename R, typename Acc, bool UNIT = false>
+template <typename R, typename Acc, bool UNIT, bool HW>
 __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     int64_t L, int64_t natoms, int lgA, int64_t K, int64_t nwg, const double* __restrict__ AB,
-    const cpx<R>* __restrict__ vis, const int32_t* __restrict__ perm,
+    const double* __restrict__ Cw, const cpx<R>* __restrict__ vis, const int32_t* __restrict__ perm,
     const Atom<R>* __restrict__ atoms, Acc* __restrict__ partial) {
   constexpr int T = kAdjRound;
   constexpr int PER = T / 64;  // staged visibilities per lane and round
   static_assert(T % 128 == 0, "a round must hold 4 x 32 visibilities");
-  __shared__ VisRec<R> stage[4][2][T];
+  __shared__ VisRec<R, HW> stage[4][2][T];
   __shared__ Acc red[4][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -209,13 +228,14 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
   const int64_t p = grp * A + ai;
   const bool live = p < natoms;
   const double a = atoms[live ? p : 0].a, b = atoms[live ? p : 0].b;
+  const double c = HW ? atoms[live ? p : 0].c : 0.0;
   const int64_t k0 = (wg * 4 + w) * K;
   const int64_t k1 = k0 + K < L ? k0 + K : L;
   const int nround = k1 > k0 ? (int)((k1 - k0 + T - 1) / T) : 0;
-  VisRec<R> nxt[PER];
+  VisRec<R, HW> nxt[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q)
-    nxt[q] = load_vis<R, UNIT>(k0 + q * 64 + lane, k1, AB, vis, perm);
+    nxt[q] = load_vis<R, UNIT, HW>(k0 + q * 64 + lane, k1, AB, Cw, vis, perm);
 #pragma unroll
   for (int q = 0; q < PER; ++q) stage[w][0][q * 64 + lane] = nxt[q];
   wave_sync();
@@ -229,14 +249,14 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     if (j + 1 < nround) {
 #pragma unroll
       for (int q = 0; q < PER; ++q)
-        nxt[q] = load_vis<R, UNIT>(kn + q * 64 + lane, k1, AB, vis, perm);
+        nxt[q] = load_vis<R, UNIT, HW>(kn + q * 64 + lane, k1, AB, Cw, vis, perm);
     }
-    const VisRec<R>* cur = stage[w][j & 1];
+    const VisRec<R, HW>* cur = stage[w][j & 1];
     for (int i = st; i < T; i += 4 * V) {  // 4 V <= T (V <= 32)
-      adj_pair<R, R, UNIT>(cur[i], a, b, acc0);
-      adj_pair<R, R, UNIT>(cur[i + V], a, b, acc1);
-      adj_pair<R, R, UNIT>(cur[i + 2 * V], a, b, acc2);
-      adj_pair<R, R, UNIT>(cur[i + 3 * V], a, b, acc3);
+      adj_pair<R, R, UNIT, HW>(cur[i], a, b, c, acc0);
+      adj_pair<R, R, UNIT, HW>(cur[i + V], a, b, c, acc1);
+      adj_pair<R, R, UNIT, HW>(cur[i + 2 * V], a, b, c, acc2);
+      adj_pair<R, R, UNIT, HW>(cur[i + 3 * V], a, b, c, acc3);
     }
     if constexpr (sizeof(Acc) != sizeof(R)) {
       tot0 += (Acc)acc0;
@@ -358,11 +378,17 @@ void forward_atoms(pc_plan* p, int64_t natoms, const Atom<R>* atoms, const cpx<R
   const unsigned nb = (unsigned)((p->L + 255) / 256);
   const double cb = 2.0 * sizeof(R);
   ProfScope ps(p, s, sizeof(R) == 4 ? "forward_sparse" : "forward_sparse_f64",
-               p->L * (16 + cb + (vis_base ? cb : 0)) + (double)natoms * sizeof(Atom<R>),
+               p->L * (16 + (p->Cw ? 8 : 0) + cb + (vis_base ? cb : 0)) +
+                   (double)natoms * sizeof(Atom<R>),
                (double)p->L * natoms);
-  hipLaunchKernelGGL((forward_sparse_kernel<R>), dim3(nb), dim3(256), 0, s, p->L, natoms, p->AB,
-                     atoms, vis_base, (vis_base && !base_sorted) ? p->perm : nullptr, R(1), out,
-                     out_sorted ? nullptr : p->perm);
+  const int32_t* bperm = (vis_base && !base_sorted) ? p->perm : nullptr;
+  const int32_t* operm = out_sorted ? nullptr : p->perm;
+  if (p->Cw)
+    hipLaunchKernelGGL((forward_sparse_kernel<R, true>), dim3(nb), dim3(256), 0, s, p->L, natoms,
+                       p->AB, p->Cw, atoms, vis_base, bperm, R(1), out, operm);
+  else
+    hipLaunchKernelGGL((forward_sparse_kernel<R, false>), dim3(nb), dim3(256), 0, s, p->L, natoms,
+                       p->AB, p->Cw, atoms, vis_base, bperm, R(1), out, operm);
   PC_LAUNCH_CHECK("forward_sparse");
 }
 
@@ -402,10 +428,10 @@ __device__ __forceinline__ void halve_reduce(float* g, int lane) {
   }
 }
 
-template <int NB>
+template <int NB, bool HW>
 __global__ __launch_bounds__(256) void forward_adjoint_kernel(
     int64_t L, int natoms, int64_t kpw, int64_t nwaves, const double* __restrict__ AB,
-    const Atom<float>* __restrict__ atoms, const cpx<float>* __restrict__ base,
+    const double* __restrict__ Cw, const Atom<float>* __restrict__ atoms, const cpx<float>* __restrict__ base,
     const int32_t* __restrict__ base_perm, cpx<float>* __restrict__ r_out,
     const int32_t* __restrict__ out_perm, float* __restrict__ partial) {
   constexpr int P2 = NB <= 8 ? 8 : (NB <= 16 ? 16 : (NB <= 32 ? 32 : 64));  // reduction width
@@ -419,22 +445,24 @@ __global__ __launch_bounds__(256) void forward_adjoint_kernel(
 #pragma unroll
   for (int q = 0; q < P2; ++q) g[q] = 0.f;
   // the next group's coordinates and base value are loaded one group ahead
-  double An = 0.0, Bn = 0.0;
+  double An = 0.0, Bn = 0.0, Cn = 0.0;
   cpx<float> vn{0.f, 0.f};
   if (k0 + lane < k1) {
     An = AB[2 * (k0 + lane)];
     Bn = AB[2 * (k0 + lane) + 1];
+    if constexpr (HW) Cn = Cw[k0 + lane];
     if (base) vn = base[base_perm ? base_perm[k0 + lane] : k0 + lane];
   }
   for (int64_t kb = k0; kb < k1; kb += 64) {
     const int64_t k = kb + lane;
     const bool live = k < k1;
-    const double A = An, B = Bn;
+    const double A = An, B = Bn, C = Cn;
     const cpx<float> v = vn;
     const int64_t kq = k + 64;
     if (kq < k1) {
       An = AB[2 * kq];
       Bn = AB[2 * kq + 1];
+      if constexpr (HW) Cn = Cw[kq];
       if (base) vn = base[base_perm ? base_perm[kq] : kq];
     }
     float c[NB], sn[NB];
@@ -451,6 +479,7 @@ __global__ __launch_bounds__(256) void forward_adjoint_kernel(
       const double aa = ap[q].a, ab = ap[q].b;
       const float w = ap[q].w;
       double t = fma(A, aa, B * ab);
+      if constexpr (HW) t = fma(C, ap[q].c, t);
       t -= rint(t);
       sincos_turns<float>(t, sn[q], c[q]);
       fr = fmaf(w, c[q], fr);
@@ -485,19 +514,20 @@ struct FusedShape {
 // Waves of forward_adjoint_kernel<NB> resident on the device at once (the
 // kernel is register-limited: 3 NB values per lane), from the runtime's
 // occupancy calculator; cached per device and NB.
-static int64_t fused_resident_waves(int nb) {
+static int64_t fused_resident_waves(int nb, bool hw) {
   constexpr int kDev = 64;
-  static std::atomic<int64_t> cache[kDev][kFusedMaxAtoms / 8 + 1];  // zero-initialised
+  static std::atomic<int64_t> cache[kDev][2][kFusedMaxAtoms / 8 + 1];  // zero-initialised
   int dev = 0;
   PC_HIP(hipGetDevice(&dev));
-  std::atomic<int64_t>& slot = cache[dev < kDev ? dev : 0][nb / 8];
+  std::atomic<int64_t>& slot = cache[dev < kDev ? dev : 0][hw ? 1 : 0][nb / 8];
   const int64_t known = slot.load(std::memory_order_relaxed);
   if (known > 0) return known;
   const void* fn = nullptr;
   switch (nb) {
 #define PC_NB(n) \
   case n:        \
-    fn = (const void*)forward_adjoint_kernel<n>; \
+    fn = hw ? (const void*)forward_adjoint_kernel<n, true>      \
+            : (const void*)forward_adjoint_kernel<n, false>; \
     break;
     PC_NB(8) PC_NB(16) PC_NB(24) PC_NB(32) PC_NB(40) PC_NB(48) PC_NB(56) PC_NB(64)
 #undef PC_NB
@@ -512,11 +542,12 @@ static int64_t fused_resident_waves(int nb) {
   return waves;
 }
 
-static FusedShape fused_shape(int64_t L, int64_t natoms) {
+static FusedShape fused_shape(const pc_plan* p, int64_t natoms) {
+  const int64_t L = p->L;
   FusedShape f{};
   f.nb = (int)((natoms + 7) / 8 * 8);
   // one round of resident waves, each over a contiguous range
-  const int64_t target = fused_resident_waves(f.nb);
+  const int64_t target = fused_resident_waves(f.nb, p->Cw != nullptr);
   const int64_t k = (L + target - 1) / target;
   f.kpw = std::max<int64_t>(64, (k + 63) / 64 * 64);
   f.nwaves = (L + f.kpw - 1) / f.kpw;
@@ -526,7 +557,7 @@ static FusedShape fused_shape(int64_t L, int64_t natoms) {
 bool fused_supported(int64_t natoms) { return natoms >= 1 && natoms <= kFusedMaxAtoms; }
 
 int64_t fused_partial_stride(const pc_plan* p, int64_t natoms) {
-  return fused_shape(p->L, natoms).nwaves;
+  return fused_shape(p, natoms).nwaves;
 }
 
 void forward_adjoint_atoms(pc_plan* p, int64_t natoms, const Atom<float>* atoms,
@@ -535,20 +566,25 @@ void forward_adjoint_atoms(pc_plan* p, int64_t natoms, const Atom<float>* atoms,
   if (!fused_supported(natoms))
     fail(PC_ERR_INVALID_ARG, "forward_adjoint_atoms: active set of " + std::to_string(natoms) +
                              " atoms (1.." + std::to_string(kFusedMaxAtoms) + " supported)");
-  const FusedShape f = fused_shape(p->L, natoms);
+  const FusedShape f = fused_shape(p, natoms);
   float* part = reinterpret_cast<float*>(partial);
   ProfScope ps(p, s, "forward_adjoint_sparse",
-               p->L * (16.0 + (base ? 8.0 : 0.0) + (r_out ? 8.0 : 0.0)) +
-                   4.0 * f.nwaves * natoms + 32.0 * natoms,
+               p->L * (16.0 + (p->Cw ? 8.0 : 0.0) + (base ? 8.0 : 0.0) + (r_out ? 8.0 : 0.0)) +
+                   4.0 * f.nwaves * natoms + (double)sizeof(Atom<float>) * natoms,
                (double)p->L * natoms);
   const unsigned nblk = (unsigned)((f.nwaves + 3) / 4);
   const int32_t* perm = caller_order ? p->perm : nullptr;
   switch (f.nb) {
 #define PC_NB(nb)                                                                              \
   case nb:                                                                                     \
-    hipLaunchKernelGGL((forward_adjoint_kernel<nb>), dim3(nblk), dim3(256), 0, s, p->L,         \
-                       (int)natoms, f.kpw, f.nwaves, p->AB, atoms, base, perm, r_out, perm,     \
-                       part);                                                                  \
+    if (p->Cw)                                                                                 \
+      hipLaunchKernelGGL((forward_adjoint_kernel<nb, true>), dim3(nblk), dim3(256), 0, s, p->L, \
+                         (int)natoms, f.kpw, f.nwaves, p->AB, p->Cw, atoms, base, perm, r_out,  \
+                         perm, part);                                                          \
+    else                                                                                       \
+      hipLaunchKernelGGL((forward_adjoint_kernel<nb, false>), dim3(nblk), dim3(256), 0, s,      \
+                         p->L, (int)natoms, f.kpw, f.nwaves, p->AB, p->Cw, atoms, base, perm,   \
+                         r_out, perm, part);                                                   \
     break;
     PC_NB(8) PC_NB(16) PC_NB(24) PC_NB(32) PC_NB(40) PC_NB(48) PC_NB(56) PC_NB(64)
 #undef PC_NB
@@ -574,7 +610,7 @@ void reduce_partials(pc_plan* p, int64_t natoms, int64_t nwg, const double* part
 int64_t adjoint_partial_count(const pc_plan* p, int64_t natoms) {
   const int64_t na = std::max<int64_t>(natoms, 1);
   int64_t nwg = adjoint_shape(p->L, na).nwg;
-  if (fused_supported(na)) nwg = std::max(nwg, fused_shape(p->L, na).nwaves);
+  if (fused_supported(na)) nwg = std::max(nwg, fused_shape(p, na).nwaves);
   return nwg * na;  // also holds the fused pass's partials
 }
 
@@ -590,11 +626,17 @@ void adjoint_atoms(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t natom
   R* part = reinterpret_cast<R*>(partial);
   {
     ProfScope ps(p, s, sizeof(R) == 4 ? "adjoint_sparse" : "adjoint_sparse_f64",
-                 p->L * (16 + 2.0 * sizeof(R)) * sh.ngroups + (double)sizeof(R) * sh.nwg * natoms,
+                 p->L * (16 + (p->Cw ? 8 : 0) + 2.0 * sizeof(R)) * sh.ngroups +
+                     (double)sizeof(R) * sh.nwg * natoms,
                  (double)p->L * natoms);
-    hipLaunchKernelGGL((adjoint_sparse_kernel<R, R>), dim3((unsigned)(sh.nwg * sh.ngroups)),
-                       dim3(256), 0, s, p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, vis,
-                       vis_sorted ? nullptr : p->perm, atoms, part);
+    const dim3 grid((unsigned)(sh.nwg * sh.ngroups));
+    const int32_t* perm = vis_sorted ? nullptr : p->perm;
+    if (p->Cw)
+      hipLaunchKernelGGL((adjoint_sparse_kernel<R, R, false, true>), grid, dim3(256), 0, s, p->L,
+                         natoms, sh.lgA, sh.K, sh.nwg, p->AB, p->Cw, vis, perm, atoms, part);
+    else
+      hipLaunchKernelGGL((adjoint_sparse_kernel<R, R, false, false>), grid, dim3(256), 0, s, p->L,
+                         natoms, sh.lgA, sh.K, sh.nwg, p->AB, p->Cw, vis, perm, atoms, part);
     PC_LAUNCH_CHECK("adjoint_sparse");
   }
   if (!out) return;  // the caller sums the partials (fused with its next step)
@@ -608,16 +650,23 @@ void adjoint_atoms_acc64(pc_plan* p, const c32* vis, int64_t natoms, const Atom<
   const dim3 grid((unsigned)(sh.nwg * sh.ngroups));
   if (vis) {
     ProfScope ps(p, s, "adjoint_sparse_acc64",
-                 p->L * 24.0 * sh.ngroups + 8.0 * sh.nwg * natoms, (double)p->L * natoms);
-    hipLaunchKernelGGL((adjoint_sparse_kernel<float, double>), grid, dim3(256), 0, s, p->L,
-                       natoms, sh.lgA, sh.K, sh.nwg, p->AB, vis, (const int32_t*)nullptr, atoms,
-                       partial);
+                 p->L * (p->Cw ? 32.0 : 24.0) * sh.ngroups + 8.0 * sh.nwg * natoms,
+                 (double)p->L * natoms);
+    if (p->Cw)
+      hipLaunchKernelGGL((adjoint_sparse_kernel<float, double, false, true>), grid, dim3(256), 0,
+                         s, p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, p->Cw, vis,
+                         (const int32_t*)nullptr, atoms, partial);
+    else
+      hipLaunchKernelGGL((adjoint_sparse_kernel<float, double, false, false>), grid, dim3(256), 0,
+                         s, p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, p->Cw, vis,
+                         (const int32_t*)nullptr, atoms, partial);
     PC_LAUNCH_CHECK("adjoint_sparse_acc64");
-  } else {  // unit visibilities: the point-spread sums
+  } else {  // unit visibilities: the point-spread sums (coplanar plans only)
+    if (p->Cw) fail(PC_ERR_UNSUPPORTED, "point-spread sums of a non-coplanar plan");
     ProfScope ps(p, s, "psf_sums_acc64",
                  p->L * 16.0 * sh.ngroups + 8.0 * sh.nwg * natoms, (double)p->L * natoms);
-    hipLaunchKernelGGL((adjoint_sparse_kernel<float, double, true>), grid, dim3(256), 0, s,
-                       p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, (const c32*)nullptr,
+    hipLaunchKernelGGL((adjoint_sparse_kernel<float, double, true, false>), grid, dim3(256), 0, s,
+                       p->L, natoms, sh.lgA, sh.K, sh.nwg, p->AB, p->Cw, (const c32*)nullptr,
                        (const int32_t*)nullptr, atoms, partial);
     PC_LAUNCH_CHECK("psf_sums_acc64");
   }

@@ -14,8 +14,17 @@
 //            1/n(l, m) correction, the image write and a fused max |eta|.
 // Forward by interpolation (type-2): the same passes transposed with the
 // opposite sign, then a w x w gather per visibility.
+//
+// Non-coplanar baselines (Sect. 2.1, Eq. phi-plane): the adjoint is
+// w-stacked (planes and their kernel in the WStack comment).  Per plane, one
+// small kernel weights the visibilities by the plane's kernel value (zero
+// beyond its reach), the spread and pass A run unchanged, and pass B rotates
+// each output pixel by the plane's phase exp(2 pi i w_j c') and adds the real
+// part into the image; a last kernel divides by Psi(dw c') and takes the
+// maximum.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 
 #include "common.h"
 #include "fft_lds.h"
@@ -885,13 +894,21 @@ __device__ __forceinline__ unsigned long long max_key(float a, int idx) {
 // Pass B of the adjoint: NB image rows i; FFT along v of H[:, i]; correction;
 // write image rows; fused max |eta| (max(eta, 0) with ``positive``, the
 // positivity-constrained solve) with lowest-index ties.
-template <typename R, int M, int NB, int NT>
+// One w-plane of the w-stacked adjoint: its position, the phase reference
+// c_mid, and whether it is the first plane (which writes instead of adding).
+struct WPlane {
+  double wj, cmid;
+  int first;
+};
+
+template <typename R, int M, int NB, int NT, bool WACC = false>
 __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* __restrict__ H,
                                                R* __restrict__ image,
                                                const cpx<R>* __restrict__ tw,
                                                const R* __restrict__ corr, R scale,
                                                unsigned long long* __restrict__ maxkey,
-                                               int positive, int iblock) {
+                                               int positive, int iblock,
+                                               WPlane wp = WPlane{0.0, 0.0, 1}) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
@@ -975,6 +992,17 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
     } else {
       inv_n = R(1) / sqrt(R(1) - l * l - mm * mm);
     }
+    if constexpr (WACC) {
+      // Re(exp(2 pi i w_j c') v), c' = n - 1 - c_mid, phase in FP64
+      double th = wp.wj * (n_minus_one((double)(i - n / 2) * g.dl, (double)(j - n / 2) * g.dl) -
+                           wp.cmid);
+      th -= rint(th);
+      const R sn = (R)__builtin_amdgcn_sinf((float)th), cs = (R)__builtin_amdgcn_cosf((float)th);
+      const R val = (v.x * cs - v.y * sn) * (corr[i] * scale) * corr[j] * inv_n;
+      R* dst = image + (size_t)i * n + j;
+      *dst = wp.first ? val : *dst + val;
+      return;
+    }
     const R val = v.x * (corr[i] * scale) * corr[j] * inv_n;
     image[(size_t)i * n + j] = val;
     // positive part: +0 for every val <= 0 (never -0, whose bits would win)
@@ -990,6 +1018,7 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
   } else {
     lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store);
   }
+  if constexpr (WACC) return;  // the maximum comes after the last plane
   // block max
   for (int o = 32; o > 0; o >>= 1) {
     unsigned long long other = __shfl_xor(best, o, 64);
@@ -1015,6 +1044,82 @@ __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>*
                                                         int positive) {
   passB_adj_body<R, M, NB, NT>(g, H, image, tw, corr, scale, maxkey, positive,
                                xcd_local(blockIdx.x, gridDim.x));
+}
+
+template <typename R, int M, int NB, int NT>
+__global__ __launch_bounds__(NT) void passB_adj_w_kernel(GridGeom g, const cpx<R>* __restrict__ H,
+                                                          R* __restrict__ image,
+                                                          const cpx<R>* __restrict__ tw,
+                                                          const R* __restrict__ corr, R scale,
+                                                          WPlane wp) {
+  passB_adj_body<R, M, NB, NT, true>(g, H, image, tw, corr, scale, nullptr, 0,
+                                     xcd_local(blockIdx.x, gridDim.x), wp);
+}
+
+// Visibility weights of w-plane w_j (plan order): h_k exp(2 pi i w_k c_mid)
+// psi((w_k - w_j) / dw) within the kernel's reach |w_k - w_j| <= (W/2) dw,
+// zero beyond it.  perm: NULL when h is in plan order.
+__global__ __launch_bounds__(256) void wplane_kernel(int64_t L, const double* __restrict__ Cw,
+                                                     const cpx<float>* __restrict__ h,
+                                                     const int32_t* __restrict__ perm, double wj,
+                                                     double inv_dw, double cmid, float R2,
+                                                     float c1, float c0,
+                                                     cpx<float>* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  const double wk = Cw[k];
+  const float t = (float)((wk - wj) * inv_dw);
+  cpx<float> o{0.f, 0.f};
+  if (t * t <= R2) {
+    const cpx<float> v = h[perm ? perm[k] : k];
+    double ph = wk * cmid;
+    ph -= rint(ph);
+    const float sn = __builtin_amdgcn_sinf((float)ph), cs = __builtin_amdgcn_cosf((float)ph);
+    const float q = fmaxf(fmaf(-t, t, R2), 0.0f);
+    const float psi = __builtin_amdgcn_exp2f(fmaf(c1, __builtin_amdgcn_sqrtf(q), -c0));
+    o = {psi * (v.x * cs - v.y * sn), psi * (v.x * sn + v.y * cs)};
+  }
+  out[k] = o;
+}
+
+// Last step of the w-stacked adjoint: image /= Psi(dw c') per pixel, with
+// Psi(xi) = sum_q W w_q phi(z_q) cos(pi W z_q xi) over the nodes z_q in
+// (0, 1] (quad: interleaved node, weight), and the fused maximum key.
+__global__ __launch_bounds__(256) void wfinal_kernel(GridGeom g, WStack ws,
+                                                     const double* __restrict__ quad,
+                                                     float* __restrict__ image,
+                                                     unsigned long long* __restrict__ maxkey,
+                                                     int positive) {
+  const int n = g.n;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long best = 0;
+  if (idx < (int64_t)n * n) {
+    const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    const double xi =
+        ws.dw * (n_minus_one((double)(i - n / 2) * g.dl, (double)(j - n / 2) * g.dl) - ws.cmid);
+    double psi = 0;
+    for (int q = 0; q < ws.nquad; ++q) {
+      float t = (float)(0.5 * g.W * quad[2 * q] * xi);  // pi W z xi radians in turns
+      t -= rintf(t);
+      psi += quad[2 * q + 1] * (double)__builtin_amdgcn_cosf(t);
+    }
+    const float val = (float)((double)image[idx] / psi);
+    image[idx] = val;
+    const float kv = positive ? (val > 0.f ? val : 0.0f) : fabsf(val);
+    best = max_key(kv, (int)idx);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(best, o, 64);
+    best = other > best ? other : best;
+  }
+  __shared__ unsigned long long wbest[4];
+  if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    for (int w = 0; w < 4; ++w) m = wbest[w] > m ? wbest[w] : m;
+    atomicMax(maxkey, m);
+  }
 }
 
 template <int M, int NB, int NT>
@@ -1252,7 +1357,8 @@ constexpr int nt_for() {
 }
 
 template <typename R, int M>
-static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s) {
+static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
+                           const WPlane* wp = nullptr) {
   constexpr int CB = sizeof(cpx<R>);
   constexpr int NBA = (M * CB >= Shapes<R>::lds_a) ? 1 : Shapes<R>::lds_a / (M * CB);
   constexpr int NTA = nt_for<NBA * M / 16>();
@@ -1268,6 +1374,16 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s) {
                        lda, s, g, (const cpx<R>*)p->grid, p->tile_flags, (cpx<R>*)p->H,
                        (const cpx<R>*)p->twiddle);
     PC_LAUNCH_CHECK("passA_adj");
+  }
+  if (wp) {  // one w-plane: rotate, add into the image
+    set_lds((const void*)passB_adj_w_kernel<R, M, NBB, NTB>, ldb);
+    ProfScope ps(p, s, "passB_adj_w", nvn + (double)g.n * g.n * sizeof(R) * (wp->first ? 1 : 2),
+                 (double)g.n * M);
+    hipLaunchKernelGGL((passB_adj_w_kernel<R, M, NBB, NTB>), dim3((M / 2) / NBB), dim3(NTB), ldb,
+                       s, g, (const cpx<R>*)p->H, image, (const cpx<R>*)p->twiddle,
+                       (const R*)p->corr, scale, *wp);
+    PC_LAUNCH_CHECK("passB_adj_w");
+    return;
   }
   set_lds((const void*)passB_adj_kernel<R, M, NBB, NTB>, ldb);
   ProfScope ps(p, s, "passB_adj", nvn + (double)g.n * g.n * sizeof(R), (double)g.n * M);
@@ -1303,12 +1419,12 @@ static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s) {
 
 template <typename R>
 static void dispatch_M(pc_plan* p, bool adjoint, R* img_out, const R* img_in, R scale,
-                       hipStream_t s) {
+                       hipStream_t s, const WPlane* wp = nullptr) {
   switch (p->g.M) {
 #define PC_M(m)                                         \
   case m:                                               \
     if (adjoint)                                        \
-      run_passes_adj<R, m>(p, img_out, scale, s);       \
+      run_passes_adj<R, m>(p, img_out, scale, s, wp);   \
     else                                                \
       run_passes_fwd<R, m>(p, img_in, s);               \
     return;
@@ -1317,7 +1433,7 @@ static void dispatch_M(pc_plan* p, bool adjoint, R* img_out, const R* img_in, R 
     case 16384:
       if constexpr (sizeof(R) == 4) {
         if (adjoint)
-          run_passes_adj<R, 16384>(p, img_out, scale, s);
+          run_passes_adj<R, 16384>(p, img_out, scale, s, wp);
         else
           run_passes_fwd<R, 16384>(p, img_in, s);
         return;
@@ -1345,15 +1461,52 @@ void maxkey_decode(unsigned long long key, double* max_abs, int64_t* argmax) {
   if (argmax) *argmax = (int64_t)(0xffffffffu - lo);
 }
 
+// The w-stacked adjoint: per plane, weights, spread, pass A and the rotating
+// pass B; then the w correction and the maximum.
+static void adjoint_grid_w(pc_plan* p, const c32* vis, bool vis_sorted, float* image, float scale,
+                           hipStream_t s) {
+  const WStack& ws = p->ws;
+  const float R = 0.5f * (float)p->g.W;
+  const float c0 = (float)(p->g.beta64 * 1.4426950408889634);  // beta log2(e)
+  const unsigned nb = (unsigned)((p->L + 255) / 256);
+  for (int j = 0; j < ws.nplanes; ++j) {
+    const WPlane wp{ws.w0 + j * ws.dw, ws.cmid, j == 0 ? 1 : 0};
+    {
+      ProfScope ps(p, s, "wplane", p->L * 24.0, (double)p->L);
+      hipLaunchKernelGGL(wplane_kernel, dim3(nb), dim3(256), 0, s, p->L, p->Cw, vis,
+                         vis_sorted ? nullptr : p->perm, wp.wj, 1.0 / ws.dw, ws.cmid, R * R,
+                         c0 / R, c0, (c32*)p->wvals);
+      PC_LAUNCH_CHECK("wplane");
+    }
+    launch_spread<float>(p, (const c32*)p->wvals, nullptr, s);  // also clears the max key
+    dispatch_M<float>(p, true, image, nullptr, scale, s, &wp);
+  }
+  const int64_t N = (int64_t)p->g.n * p->g.n;
+  ProfScope ps(p, s, "wfinal", 8.0 * N, (double)N);
+  hipLaunchKernelGGL(wfinal_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, p->g, ws,
+                     p->wquad, image, p->maxkey, p->max_positive);
+  PC_LAUNCH_CHECK("wfinal");
+}
+
 template <typename R>
 void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R scale,
                   hipStream_t s) {
+  if (p->Cw) {
+    if constexpr (sizeof(R) == 4) {
+      adjoint_grid_w(p, vis, vis_sorted, image, scale, s);
+      return;
+    }
+    fail(PC_ERR_UNSUPPORTED, "w-stacked adjoint of an FP64 plan");
+  }
   launch_spread<R>(p, vis, vis_sorted ? nullptr : p->perm, s);  // also clears the max key
   dispatch_M<R>(p, true, image, nullptr, scale, s);
 }
 
 template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted, hipStream_t s) {
+  if (p->Cw)
+    fail(PC_ERR_UNSUPPORTED,
+         "the gridded forward operator needs a coplanar plan (w = 0); the direct sums take w");
   dispatch_M<R>(p, false, nullptr, image, R(1), s);
   launch_interp<R>(p, out_sorted ? nullptr : p->perm, vis_out, s);
 }
@@ -1472,6 +1625,37 @@ void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* 
                         const bool* vis_sorted, float* const* images, const float* scales, int n,
                         hipStream_t s) {
   if (n <= 0) return;
+  // w-stacked plans run on their own, ahead of the shared launches
+  {
+    std::vector<int> flat;
+    for (int j = 0; j < n; ++j) {
+      PC_REQUIRE(plans[j] && plans[j]->precision == PC_PREC_FP32, "batched adjoint needs FP32 plans");
+      if (plans[j]->Cw)
+        adjoint_grid<float>(plans[j], vis[j], vis_sorted[j], images[j],
+                            scales ? scales[j] : 1.0f, s);
+      else
+        flat.push_back(j);
+    }
+    if ((int)flat.size() < n) {
+      if (flat.empty()) return;
+      std::vector<pc_plan*> fp;
+      std::vector<const c32*> fv;
+      std::unique_ptr<bool[]> fs(new bool[flat.size()]);
+      std::vector<float*> fi;
+      std::vector<float> fsc;
+      for (size_t q = 0; q < flat.size(); ++q) {
+        const int j = flat[q];
+        fp.push_back(plans[j]);
+        fv.push_back(vis[j]);
+        fs[q] = vis_sorted[j];
+        fi.push_back(images[j]);
+        fsc.push_back(scales ? scales[j] : 1.0f);
+      }
+      adjoint_grid_batch(ctx, fp.data(), fv.data(), fs.get(), fi.data(), fsc.data(),
+                         (int)flat.size(), s);
+      return;
+    }
+  }
   if (!ctx.done) PC_HIP(hipEventCreateWithFlags(&ctx.done, hipEventDisableTiming));
   if (ctx.pending) PC_HIP(hipEventSynchronize(ctx.done));
   // job descriptors and work lists

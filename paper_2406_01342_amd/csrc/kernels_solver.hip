@@ -603,8 +603,8 @@ __global__ __launch_bounds__(256) void gram_lanczos_wave_kernel(
 }
 
 // An active set from one uploaded block [x: nS doubles][pix: nS int32]:
-// x = y = the weights, pix, and the atom table (pixel offsets, 1/n, forward
-// weight x/n; zero-weight phase-centre padding up to ntotal entries).
+// x = y = the weights, pix, and the atom table (pixel offsets, 1/n, n - 1,
+// forward weight x/n; zero-weight phase-centre padding up to ntotal entries).
 __global__ void activate_kernel(int64_t nS, int64_t ntotal, int n, double dl,
                                 const unsigned char* __restrict__ blk, double* __restrict__ x,
                                 double* __restrict__ y, int32_t* __restrict__ pix,
@@ -612,7 +612,7 @@ __global__ void activate_kernel(int64_t nS, int64_t ntotal, int n, double dl,
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ntotal) return;
   if (p >= nS) {
-    atoms[p] = Atom<float>{0.0, 0.0, 1.0, 0.f, 0.f};
+    atoms[p] = Atom<float>{0.0, 0.0, 1.0, 0.0, 0.f, 0.f};
     return;
   }
   const double xv = reinterpret_cast<const double*>(blk)[p];
@@ -625,7 +625,7 @@ __global__ void activate_kernel(int64_t nS, int64_t ntotal, int n, double dl,
   const double a = (double)(i - n / 2), b = (double)(j - n / 2);
   const double l = a * dl, m = b * dl;
   const double inv_n = 1.0 / sqrt(1.0 - l * l - m * m);
-  atoms[p] = Atom<float>{a, b, inv_n, (float)(xv * inv_n), 0.f};
+  atoms[p] = Atom<float>{a, b, inv_n, n_minus_one(l, m), (float)(xv * inv_n), 0.f};
 }
 
 // Forward weights from an FP64 vector: atoms[p].w = x[p] / n_p.

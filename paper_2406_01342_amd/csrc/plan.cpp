@@ -81,6 +81,8 @@ struct Layout {
   int64_t L = 0;
   std::vector<int32_t> perm;            // sorted -> caller
   std::vector<double> AB;               // sorted, interleaved (A, B)
+  std::vector<double> Cw;               // sorted w in wavelengths (empty: coplanar)
+  WStack ws;
   std::vector<uint32_t> cell;           // sorted
   std::vector<double> off;              // sorted, interleaved (s_u, s_v)
   std::vector<SpreadChunk> chunks;
@@ -123,14 +125,42 @@ static void validate(const pc_geometry* g) {
   for (int64_t k = 0; k < g->nvis; ++k) {
     if (!std::isfinite(g->u[k]) || !std::isfinite(g->v[k]))
       fail(PC_ERR_INVALID_ARG, "non-finite uv at index " + std::to_string(k));
-    if (g->w && g->w[k] != 0.0)
-      fail(PC_ERR_INVALID_ARG, "nonzero w at index " + std::to_string(k) +
-                                   " (only coplanar arrays are supported)");
+    if (g->w && !std::isfinite(g->w[k]))
+      fail(PC_ERR_INVALID_ARG, "non-finite w at index " + std::to_string(k));
   }
+}
+
+static bool has_w(const pc_geometry* g) {
+  if (!g->w) return false;
+  for (int64_t k = 0; k < g->nvis; ++k)
+    if (g->w[k] != 0.0) return true;
+  return false;
+}
+
+// Planes of the w-stacked adjoint.  The direction factor c = n - 1 spans
+// [c_min, 0], c_min at the image corner (a = b = -n/2); planes are dw =
+// 1 / (4 half) apart (half = -c_min / 2) and cover [w_min, w_max] with W / 2
+// planes of margin on each side, centred on the w range.
+static WStack w_planes(const GridGeom& g, double wmin, double wmax) {
+  WStack ws;
+  const double lmax = (g.n / 2) * g.dl;
+  const double cmin = n_minus_one(lmax, lmax);
+  const double half = -0.5 * cmin;
+  ws.cmid = -half;
+  ws.dw = 1.0 / (4.0 * half);
+  const double span = (wmax - wmin) / ws.dw;
+  PC_REQUIRE(span < 1e6, "w range needs more than 10^6 planes");
+  ws.nplanes = (int)std::ceil(span) + g.W + 1;
+  ws.w0 = 0.5 * (wmin + wmax) - 0.5 * (ws.nplanes - 1) * ws.dw;
+  ws.nquad = g.W + 60;
+  return ws;
 }
 
 static Layout build_layout(const pc_geometry* geo, bool full) {
   validate(geo);
+  const bool with_w = has_w(geo);
+  if (with_w && geo->precision != PC_PREC_FP32)
+    fail(PC_ERR_UNSUPPORTED, "non-coplanar baselines (w != 0) need an FP32 plan");
   Layout lay;
   const int64_t L = geo->nvis;
   const int n = geo->npix, M = 2 * n, W = kernel_width(geo->nufft_eps);
@@ -237,6 +267,18 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     for (int64_t i = 0; i < L; ++i) {
       const int32_t k = order[i];
       lay.perm[pos[key[k]]++] = k;
+    }
+  }
+  if (with_w) {
+    double wmin = INFINITY, wmax = -INFINITY;
+    for (int64_t k = 0; k < L; ++k) {
+      wmin = std::min(wmin, geo->w[k] * scale);
+      wmax = std::max(wmax, geo->w[k] * scale);
+    }
+    lay.ws = w_planes(g, wmin, wmax);
+    if (full) {
+      lay.Cw.resize(L);
+      for (int64_t s = 0; s < L; ++s) lay.Cw[s] = geo->w[lay.perm[s]] * scale;
     }
   }
   if (full) {
@@ -535,6 +577,11 @@ static size_t layout_bytes(const Layout& lay, int prec) {
   add((size_t)g.n * rb);                     // correction
   add(256);                                  // max key
   add(lay.L * cb);                           // vis scratch
+  if (lay.ws.nplanes > 0) {
+    add(lay.L * 8);                          // w
+    add(lay.L * cb);                         // one plane's weighted visibilities
+    add((size_t)lay.ws.nquad * 16);          // Psi quadrature
+  }
   return b;
 }
 
@@ -584,6 +631,12 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     p->corr = dalloc(p, (size_t)g.n * rb);
     p->maxkey = (unsigned long long*)dalloc(p, 256);
     p->vis_scratch = dalloc(p, L * cb);
+    p->ws = lay.ws;
+    if (lay.ws.nplanes > 0) {
+      p->Cw = (double*)dalloc(p, L * 8);
+      p->wvals = dalloc(p, L * cb);
+      p->wquad = (double*)dalloc(p, (size_t)lay.ws.nquad * 16);
+    }
 
     // Host staging of converted tables; copies complete before return.
     PC_HIP(hipMemcpyAsync(p->perm, lay.perm.data(), L * 4, hipMemcpyHostToDevice, s));
@@ -615,6 +668,22 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
       const double ang = 2.0 * M_PI * t / g.M;
       tw64[2 * q] = std::cos(ang);
       tw64[2 * q + 1] = std::sin(ang);
+    }
+    std::vector<double> wq;
+    if (lay.ws.nplanes > 0) {
+      PC_HIP(hipMemcpyAsync(p->Cw, lay.Cw.data(), L * 8, hipMemcpyHostToDevice, s));
+      // Psi(xi) = (W/2) int_{-1}^{1} phi(z) cos(pi W z xi) dz: the nodes in
+      // (0, 1] of an even Gauss-Legendre rule, each weight doubled
+      std::vector<double> x, w;
+      gauss_legendre(2 * lay.ws.nquad, x, w);
+      for (size_t q = 0; q < x.size(); ++q) {
+        if (x[q] <= 0) continue;
+        const double phi = std::exp(g.beta64 * (std::sqrt(1.0 - x[q] * x[q]) - 1.0));
+        wq.push_back(x[q]);
+        wq.push_back(g.W * w[q] * phi);
+      }
+      PC_REQUIRE((int)wq.size() == 2 * lay.ws.nquad, "quadrature nodes");
+      PC_HIP(hipMemcpyAsync(p->wquad, wq.data(), wq.size() * 8, hipMemcpyHostToDevice, s));
     }
     std::vector<double> corr64 = correction_table(g);
     std::vector<float> tw32, corr32;

@@ -238,6 +238,8 @@ struct Pfw {
       : p(plan), s(stream), prm(params), L(plan->L), N((int64_t)plan->g.n * plan->g.n),
         positive(params.positivity != 0), ms(params.n_scales > 0) {
     NA = N;
+    if (ms && p->Cw)
+      fail(PC_ERR_UNSUPPORTED, "a synthesis dictionary needs a coplanar plan (w = 0)");
     if (ms) {
       dict = make_dict(params.n_scales, params.scale_sigma, params.scale_gamma);
       NA = (int64_t)dict.S * N;
@@ -393,6 +395,7 @@ struct Pfw {
   // about 0.4 ps per visibility-atom pair per direction against 0.2 ns per
   // visibility plus 8 ps per band cell.
   int64_t grid_crossover() const {
+    if (p->Cw) return INT64_MAX / 8;  // no gridded forward with the w-term: direct sums only
     if (prm.grid_atoms > 0) return prm.grid_atoms;
     if (prm.grid_atoms < 0) return INT64_MAX / 8;
     const double cells = (double)p->g.nu * (double)p->g.nv;
@@ -515,6 +518,8 @@ struct Pfw {
   }
 
   int64_t gram_cap() const {  // the Gram-form Lanczos holds its basis in LDS
+    // with the w-term Phi_S* Phi_S is no longer a function of pixel offsets
+    if (p->Cw) return 0;
     if (prm.gram_atoms > 0) return std::min<int64_t>(prm.gram_atoms, kGramLdsAtoms);
     return prm.gram_atoms < 0 ? 0 : kGramAtoms;
   }
@@ -603,10 +608,10 @@ struct Pfw {
     unsigned char* h = (unsigned char*)up.get(tbytes + abytes);
     Atom<float>* at = (Atom<float>*)h;
     for (int64_t m = 0; m < nm; ++m)
-      at[m] = Atom<float>{(double)miss[m].first, (double)miss[m].second, 1.0, 0.f, 0.f};
+      at[m] = Atom<float>{(double)miss[m].first, (double)miss[m].second, 1.0, 0.0, 0.f, 0.f};
     for (int64_t t = 0; t < nb; ++t) {
       const int64_t q = bmiss[t];
-      at[nm + t] = Atom<float>{(double)ai[q], (double)bi[q], inv_n[q], 0.f, 0.f};
+      at[nm + t] = Atom<float>{(double)ai[q], (double)bi[q], inv_n[q], 0.0, 0.f, 0.f};
     }
     unsigned char* blk = h + tbytes;
     std::memcpy(blk, v0.data(), (size_t)nS * 8);

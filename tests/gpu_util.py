@@ -47,6 +47,14 @@ def problem(name: str):
         p = sim.config_c3(n_snap=8, npix=512, n_ant=64, with_blobs=False)
     elif name == "c4_0":
         p = sim.config_c4_request(0)
+    elif name == "c2w":  # non-coplanar variants: uv holds (u, v, w)
+        p = sim.config_c2(keep_w=True)
+    elif name == "c2w_small":
+        p = sim.config_c2(n_snap=24, npix=256, keep_w=True)
+    elif name == "c2w_128":
+        p = sim.config_c2(n_snap=4, npix=128, n_src=10, keep_w=True)
+    elif name == "c2w_64":
+        p = sim.config_c2(n_snap=4, npix=64, n_src=10, keep_w=True)
     else:
         raise KeyError(name)
     vclean = operator.forward(p.uv, p.npix, p.fov_rad, p.sky_pix, p.sky_amp)

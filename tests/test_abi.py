@@ -66,14 +66,21 @@ def test_footprint_rejects_bad_geometry(kw, status):
     assert _status(lambda: _fp(UV, **kw)) == status
 
 
-def test_rejects_nonfinite_and_noncoplanar():
+def test_rejects_nonfinite_and_sizes_w_planes():
     bad = UV.copy()
     bad[17, 1] = np.inf
     assert _status(lambda: _fp(bad)) == -1
     w = np.zeros(len(UV))
-    w[3] = 1.0
+    w[3] = np.nan
     assert _status(lambda: _fp(UV, w=w)) == -1
-    assert _fp(UV, w=np.zeros(len(UV))) > 0
+    flat = _fp(UV, w=np.zeros(len(UV)))
+    assert flat == _fp(UV)  # an all-zero w is a coplanar plan
+    w[3] = 100.0
+    # a non-coplanar plan adds w, one plane's weighted values and the quadrature
+    assert _fp(UV, w=w) >= flat + len(UV) * 16
+    # w-stacking is an FP32 path
+    from paper_2406_01342_amd import api
+    assert _status(lambda: _fp(UV, w=w, precision=api.PC_PREC_FP64)) == -5
 
 
 def test_rejects_empty():

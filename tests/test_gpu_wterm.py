@@ -1,0 +1,188 @@
+"""GPU parity of the w-term (Sect. 2.1, Eq. phi-plane: W = exp(-j 2 pi w (n - 1)))
+against the FP64 oracle: the direct sums with the FP64 w (n - 1) phase, the
+w-stacked gridded adjoint, and a solve on non-coplanar baselines.
+
+Inputs: the LOFAR-like recipe with w kept from the same Earth-rotation
+formulas (4 deg field: the w phase reaches ~4.5 turns at the field corners,
+so ignoring w changes the dirty image by ~40 %).  Tolerances as for the
+coplanar operators: 1e-4 relative L2, identical argmax.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator, solver
+from tests.gpu_util import api, problem, rel_l2, say, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def _plan(p, **kw):
+    return api().pc_plan_create(p.uv[:, :2], p.npix, p.fov_rad, w=p.uv[:, 2], **kw)
+
+
+def _atoms(n, k, seed):
+    """k distinct pixels including the four corners (largest |n - 1|) and the
+    phase centre, with signed weights."""
+    rng = np.random.default_rng(seed)
+    fixed = np.array([0, n - 1, n * (n - 1), n * n - 1, (n // 2) * n + n // 2])[:k]
+    rest = rng.choice(np.setdiff1d(np.arange(n * n), fixed), k - fixed.size, replace=False)
+    pix = np.concatenate([fixed, rest]).astype(np.int32)
+    return pix, rng.normal(size=k).astype(np.float32)
+
+
+@pytest.mark.parametrize("k", [1, 40, 200])
+def test_forward_sparse_w(k):
+    say("forward_sparse with w, atoms", k)
+    p, _ = problem("c2w_small")
+    plan = _plan(p)
+    pix, wt = _atoms(p.npix, k, 1)
+    out = api().pc_forward_sparse(plan, to_dev(pix), to_dev(wt)).cpu().numpy()
+    want = operator.forward(p.uv, p.npix, p.fov_rad, pix, wt.astype(np.float64))
+    assert rel_l2(out, want) <= TOL
+    # the coplanar operator is far from it: the w phase is exercised
+    flat = operator.forward(p.uv[:, :2], p.npix, p.fov_rad, pix, wt.astype(np.float64))
+    if k > 1:
+        assert rel_l2(flat, want) > 0.1
+
+
+@pytest.mark.parametrize("k", [3, 64, 300])
+def test_adjoint_sparse_w(k):
+    say("adjoint_sparse with w, atoms", k)
+    p, vis = problem("c2w_small")
+    plan = _plan(p)
+    pix, _ = _atoms(p.npix, k, 2)
+    out = api().pc_adjoint_sparse(plan, to_dev(vis), to_dev(pix)).cpu().numpy()
+    want = operator.adjoint_pixels(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128), pix)
+    assert rel_l2(out, want) <= TOL
+
+
+@pytest.mark.parametrize("k", [40, 100])
+def test_restricted_gradient_w(k):
+    """Fused forward-adjoint pass (<= 64 atoms) and forward then adjoint."""
+    say("restricted_gradient with w, atoms", k)
+    p, vis = problem("c2w_small")
+    plan = _plan(p)
+    pix, wt = _atoms(p.npix, k, 3)
+    wt *= 50.0
+    g, r = api().pc_restricted_gradient(plan, to_dev(vis), to_dev(pix), to_dev(wt), want_resid=True)
+    v64 = vis.astype(np.complex128)
+    r_want = v64 - operator.forward(p.uv, p.npix, p.fov_rad, pix, wt.astype(np.float64))
+    g_want = operator.adjoint_pixels(p.uv, p.npix, p.fov_rad, r_want, pix)
+    assert rel_l2(r.cpu().numpy(), r_want) <= TOL
+    assert rel_l2(g.cpu().numpy(), g_want) <= TOL
+
+
+def test_adjoint_grid_w_whole_image():
+    """The w-stacked dirty image at 128^2 against the full oracle adjoint."""
+    say("adjoint_grid with w, whole 128^2 image")
+    p, vis = problem("c2w_128")
+    plan = _plan(p)
+    img, mx, am = api().pc_adjoint_grid(plan, to_dev(vis))
+    img = img.cpu().numpy().astype(np.float64)
+    want = operator.adjoint(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128))
+    err = rel_l2(img, want)
+    flat = operator.adjoint(p.uv[:, :2], p.npix, p.fov_rad, vis.astype(np.complex128))
+    say("rel L2", err, "coplanar image differs by", rel_l2(flat, want))
+    assert err <= TOL
+    assert rel_l2(flat, want) > 0.1
+    wmx, wam = solver.argmax_abs(want)
+    assert am == wam and abs(mx - wmx) <= TOL * wmx
+
+
+def _sampled_check(p, vis, img, mx, am, n_rand, seed):
+    rng = np.random.default_rng(seed)
+    n = p.npix
+    pix = np.unique(np.concatenate([
+        rng.choice(n * n, n_rand, replace=False), [0, n - 1, n * (n - 1), n * n - 1],
+        [(n // 2) * n + n // 2, am], np.asarray(p.sky_pix)[:16]]))
+    want = operator.adjoint_pixels(p.uv, n, p.fov_rad, vis.astype(np.complex128), pix)
+    got = img.reshape(-1)[pix].astype(np.float64)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    say("sampled pixels", pix.size, "max err / max", err)
+    assert err <= TOL
+    # the reported maximum is the image's own, and no sampled oracle value beats it
+    assert abs(mx - np.max(np.abs(img))) <= 1e-6 * mx
+    assert np.max(np.abs(want)) <= mx * (1 + TOL)
+
+
+def test_adjoint_grid_w_c2w_small_sampled():
+    say("adjoint_grid with w, 256^2, 42,480 visibilities")
+    p, vis = problem("c2w_small")
+    plan = _plan(p)
+    img, mx, am = api().pc_adjoint_grid(plan, to_dev(vis))
+    _sampled_check(p, vis, img.cpu().numpy(), mx, am, 240, 4)
+
+
+@pytest.mark.slow
+def test_adjoint_grid_w_c2w_full_sampled():
+    """The full non-coplanar LOFAR-like workload: 424,800 visibilities, 1024^2."""
+    say("adjoint_grid with w, full C2W")
+    p, vis = problem("c2w")
+    plan = _plan(p)
+    img, mx, am = api().pc_adjoint_grid(plan, to_dev(vis))
+    _sampled_check(p, vis, img.cpu().numpy(), mx, am, 120, 5)
+
+
+def test_dual_certificate_w():
+    """Certificate of a fixed x (w-stacked adjoint of V - Phi_S x, divided by
+    lambda) against the oracle's, whole image."""
+    say("dual certificate with w")
+    p, vis = problem("c2w_128")
+    plan = _plan(p)
+    pix, wt = _atoms(p.npix, 12, 6)
+    wt = np.abs(wt) * 30.0
+    lam = 1234.5
+    a = api()
+    cert, cmx, cam = a.pc_dual_certificate(plan, to_dev(vis), to_dev(pix), to_dev(wt), lam)
+    want = solver.certificate(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128), pix,
+                              wt.astype(np.float64), lam)
+    assert rel_l2(cert.cpu().numpy(), want) <= TOL
+    assert cam == solver.argmax_abs(want)[1]
+
+
+def test_solve_w_matches_oracle():
+    """PolyCLEAN on non-coplanar baselines (direct sums in APGD, w-stacked
+    exploration) against the oracle's solve: objective 1e-3, and the GPU
+    certificate of its x against the oracle's certificate of that x, 1e-4."""
+    say("solve with w, 64^2")
+    p, vis = problem("c2w_64")
+    a = api()
+    plan = _plan(p)
+    kw = dict(alpha=p.alpha, delta=p.delta, max_iter=200, rel_gap_tol=1e-4)
+    cert = torch.empty((p.npix, p.npix), dtype=torch.float32, device="cuda")
+    res = a.pc_polyclean_solve(plan, to_dev(vis), capacity=65536, cert=cert, want_certificate=1,
+                               **kw)
+    v64 = vis.astype(np.complex128)
+    ref = solver.pfw_solve(p.uv, p.npix, p.fov_rad, v64, **kw)
+    say("gpu", res["objective"], res["rel_gap"], res["iters"], res["natoms"],
+        "oracle", ref.objective, ref.rel_gap, ref.iters, ref.pix.size)
+    assert res["status"] == 0 and res["converged"] == 1
+    assert abs(res["lambda_max"] - ref.lambda_max) <= TOL * ref.lambda_max
+    assert abs(res["objective"] - ref.objective) <= 1e-3 * ref.objective
+    mu_x = solver.certificate(p.uv, p.npix, p.fov_rad, v64, res["pix"], res["weight"],
+                              res["lambda"])
+    assert rel_l2(cert.cpu().numpy().astype(np.float64), mu_x) <= TOL
+    fit = operator.forward(p.uv, p.npix, p.fov_rad, res["pix"], res["weight"])
+    p_or = solver.objective(v64, fit, res["weight"], res["lambda"])
+    assert abs(p_or - res["objective"]) <= 1e-5 * p_or
+
+
+def test_w_unsupported_paths_fail_loudly():
+    """The gridded forward, FP64 plans and the synthesis dictionary need
+    coplanar baselines: each refuses a plan with w instead of ignoring it."""
+    p, vis = problem("c2w_64")
+    a = api()
+    plan = _plan(p)
+    with pytest.raises(RuntimeError, match="coplanar"):
+        a.pc_forward_grid(plan, to_dev(np.zeros((p.npix, p.npix), np.float32)))
+    with pytest.raises(RuntimeError, match="FP32"):
+        _plan(p, precision=a.PC_PREC_FP64)
+    with pytest.raises(RuntimeError, match="coplanar"):
+        a.pc_polyclean_solve(plan, to_dev(vis), scales=([1.0, 2.0], [1.0, 1.0]))
+    # an all-zero w is a coplanar plan
+    p2, vis2 = problem("c2_small")
+    flat = a.pc_plan_create(p2.uv, p2.npix, p2.fov_rad, w=np.zeros(p2.uv.shape[0]))
+    img, _, _ = a.pc_adjoint_grid(flat, to_dev(vis2))
+    x = torch.zeros((p2.npix, p2.npix), dtype=torch.float32, device="cuda")
+    a.pc_forward_grid(flat, x)

@@ -304,3 +304,43 @@ def test_argmax_tie_of_a_zero_residual_certificate():
     mu = solver.certificate(uv, n, fov, V, pix, w, lam=0.3)
     assert np.all(mu == 0.0)
     assert solver.argmax_abs(mu) == (0.0, 0)
+
+
+def _problem_w(seed, L=160, n=8, fov=0.5, n_src=3, noise=0.05):
+    """The same recipe with non-coplanar baselines: w as large as u and v, so
+    that the w-term phase w (n - 1) reaches a sizeable fraction of a turn."""
+    rng = np.random.default_rng(100 + seed)
+    uvw = rng.uniform(-12, 12, size=(L, 3))
+    uvw[:, 2] *= 4.0
+    pix = rng.choice(n * n, n_src, replace=False)
+    amp = np.exp(rng.normal(size=n_src))
+    V = operator.forward(uvw, n, fov, pix, amp)
+    V = V + noise * np.max(np.abs(V)) * (rng.normal(size=L) + 1j * rng.normal(size=L))
+    return uvw, n, fov, V
+
+
+def test_explicit_matrix_with_w_is_the_forward_operator():
+    """The explicit 2L x N matrix reproduces the (pinned) oracle forward with
+    w column by column, and differs from the coplanar matrix."""
+    uvw, n, fov, _ = _problem_w(0)
+    A = brute.explicit_matrix(uvw, n, fov)
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=n * n)
+    V = operator.forward(uvw, n, fov, np.arange(n * n), x)
+    assert np.allclose(A @ x, np.concatenate([V.real, V.imag]), rtol=0, atol=1e-11 * np.abs(V).max())
+    A0 = brute.explicit_matrix(uvw[:, :2], n, fov)
+    assert np.linalg.norm(A - A0) > 0.1 * np.linalg.norm(A0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pfw_matches_coordinate_descent_with_w(seed):
+    """T15 with the w-term: the Frank-Wolfe route (Gram columns with the w
+    phase) and coordinate descent on the explicit matrix agree."""
+    uvw, n, fov, V = _problem_w(seed)
+    res = solver.pfw_solve(uvw, n, fov, V, alpha=0.1, delta=0.9, **TIGHT)
+    A = brute.explicit_matrix(uvw, n, fov)
+    y = np.concatenate([V.real, V.imag])
+    x, obj, rel, _ = brute.lasso_cd(A, y, res.lam)
+    assert abs(res.objective - obj) <= 1e-9 * obj
+    fit_fw = np.concatenate([res.fit.real, res.fit.imag])
+    assert np.linalg.norm(fit_fw - A @ x) <= 1e-5 * np.linalg.norm(A @ x)
