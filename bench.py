@@ -184,6 +184,8 @@ def parse():
                     help="skip the adjoint measurements at the 4096^2 and 8192^2 workloads")
     ap.add_argument("--dictionary-only", action="store_true",
                     help="run only the synthesis-dictionary adjoint at 4096^2 and print its JSON")
+    ap.add_argument("--w-only", action="store_true",
+                    help="only the non-coplanar LOFAR-like leg (w-stacked adjoint, solve)")
     ap.add_argument("--adjoint-only", choices=("c2", "c3", "c5l"),
                     help="run only the gridded adjoint (caller-order input) at one workload, "
                          "--adjoint-reps times after 3 warm-up calls, and print its JSON "
@@ -205,7 +207,8 @@ def synth_inputs(api, torch, p):
     the generator's noise draw scaled to the PSNR (input synthesis only)."""
     import numpy as np
     import sim
-    plan = api.pc_plan_create(p.uv, p.npix, p.fov_rad)
+    plan = api.pc_plan_create(p.uv[:, :2], p.npix, p.fov_rad,
+                              w=p.uv[:, 2] if p.uv.shape[1] > 2 else None)
     pix = torch.from_numpy(p.sky_pix.astype(np.int32)).cuda()
     amp = torch.from_numpy(p.sky_amp.astype(np.float32)).cuda()
     vclean = api.pc_forward_sparse(plan, pix, amp).cpu().numpy().astype(np.complex128)
@@ -268,6 +271,42 @@ def adjoint_at(api, torch, p, reps, label):
            "kernels_us": {x["name"]: round(1e3 * x["ms"] / x["launches"], 2) for x in st},
            "setup_s": synth_s}
     log(label, {k: out[k] for k in ("device_ms", "mvis_per_s", "hbm_frac_implemented")})
+    plan.close()
+    return out
+
+
+def w_leg(api, torch, reps):
+    """The LOFAR-like workload with its baselines' w kept (non-coplanar):
+    the w-stacked adjoint per kernel and a full solve (direct sums with the w
+    phase inside APGD, w-stacked exploration)."""
+    import sim
+    p = sim.config_c2(keep_w=True)
+    t = time.perf_counter()
+    plan, vis = synth_inputs(api, torch, p)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    dv = torch.from_numpy(vis).cuda()
+    img = torch.empty((p.npix, p.npix), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    api.pc_plan_profile(plan, True)
+    for _ in range(reps):
+        api.pc_adjoint_grid(plan, dv, img, want_max=False)
+    st = api.pc_plan_kernel_stats(plan)
+    api.pc_plan_profile(plan, False)
+    ms = sum(x["ms"] for x in st) / reps
+    info = plan.info
+    out = {"workload": "LOFAR-like with w: 424,800 visibilities, 1024^2, FOV 4 deg, w from the "
+                       "Earth-rotation formulas (|w| <= 3,713 wavelengths)",
+           "w_planes": info["w_planes"], "w_step": info["w_step"], "setup_s": setup_s,
+           "adjoint_device_ms": ms, "adjoint_mvis_per_s": p.nvis / ms / 1e3,
+           "adjoint_ms_per_plane": ms / max(1, info["w_planes"]),
+           "kernels_us_per_launch": {x["name"]: round(1e3 * x["ms"] / x["launches"], 2)
+                                     for x in st},
+           "kernels_ms_per_adjoint": {x["name"]: round(x["ms"] / reps, 4) for x in st}}
+    prm = dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter, rel_gap_tol=p.rel_gap_tol)
+    out["solve"] = solve_leg(api, torch, p, plan, dv, prm, 3, 1, "C2 with w", False)
+    log("C2 with w", {k: out[k] for k in ("w_planes", "adjoint_device_ms", "adjoint_mvis_per_s")})
     plan.close()
     return out
 
@@ -590,6 +629,10 @@ def main():
         print(json.dumps({"adjoint": adjoint_at(api, torch, make(), args.adjoint_reps, label)}),
               flush=True)
         return
+    if args.w_only:
+        print(json.dumps({"lofar_like_w": w_leg(api, torch, max(3, args.adjoint_reps // 5))}),
+              flush=True)
+        return
     if args.dictionary_only:
         print(json.dumps({"dictionary": dictionary_leg(api, torch, max(5, args.adjoint_reps // 4),
                                                        with_solve=False)}), flush=True)
@@ -703,6 +746,7 @@ def main():
     out["lofar_like"] = c2
     plan2.close()
     del dv2
+    out["lofar_like_w"] = w_leg(api, torch, max(3, args.adjoint_reps // 5))
 
     if not args.no_other_workloads:
         out["adjoint_precision_workload"] = adjoint_at(

@@ -6,17 +6,27 @@
  * Super-Resolution Imaging and Uncertainty Estimation in Radio
  * Interferometry".  The library computes
  *   - the discrete forward operator Phi (Sect. 2.2, Eq. phi-discrete):
- *       V_k = sum_p x_p / n_p * exp(-j 2 pi (u_k l_p + v_k m_p)),
+ *       V_k = sum_p x_p / n_p * exp(-j 2 pi (u_k l_p + v_k m_p + w_k (n_p - 1))),
  *   - its adjoint Phi* (Sect. 2.2, Eq. adjoint-phi):
- *       eta[i,j] = Re sum_k h_k / n_ij * exp(+j 2 pi (u_k l_i + v_k m_j)),
+ *       eta[i,j] = Re sum_k h_k / n_ij * exp(+j 2 pi (u_k l_i + v_k m_j + w_k (n_ij - 1))),
  *   - the dual certificate mu = Phi*(V - Phi x) / lambda (Sect. 4.2,
  *     Eq. dual_certif),
  *   - the LASSO solve of Eq. lasso by the Polyatomic Frank-Wolfe algorithm
  *     (Sect. 5.1, Alg. 2) with an APGD restricted step,
- * for coplanar arrays (w = 0, the coplanar remark of Sect. 2.1).
+ * The factor exp(-j 2 pi w (n - 1)) is the w-term of Sect. 2.1 (Eq.
+ * phi-plane); with w = 0 (coplanar arrays, or w not given) it is 1.
+ *
+ * Non-coplanar plans (some w != 0): the direct sums (pc_forward_sparse,
+ * pc_adjoint_sparse, pc_restricted_gradient*) add the w phase in FP64; the
+ * gridded adjoint (pc_adjoint_grid, pc_dual_certificate, the solve's
+ * exploration) is w-stacked: planes w_j = w0 + j dw, dw = 1 / (2 |c_min|)
+ * (c_min = n - 1 at the image corner), ceil((w_max - w_min) / dw) + W + 1
+ * planes, each one spread and two FFT passes, so its cost is that many
+ * coplanar adjoints.  FP32 plans only; pc_forward_grid, the FP64 twin and
+ * the synthesis dictionary need coplanar plans (PC_ERR_UNSUPPORTED).
  *
  * Conventions shared by every entry point
- *   Geometry   (u, v) in wavelengths (Sect. 2.1; metres are converted with the
+ *   Geometry   (u, v, w) in wavelengths (Sect. 2.1; metres are converted with the
  *              frequency).  Pixel step dl = fov / npix; l_i = (i - npix/2) dl,
  *              m_j = (j - npix/2) dl, so pixel (npix/2, npix/2) is the phase
  *              centre; n_ij = sqrt(1 - l_i^2 - m_j^2).
@@ -78,7 +88,7 @@ typedef struct {
   int64_t nvis;          /* L > 0: number of visibilities                     */
   const double* u;       /* [nvis] baseline u (units below)                   */
   const double* v;       /* [nvis] baseline v                                 */
-  const double* w;       /* [nvis] or NULL; must be all zero (coplanar)       */
+  const double* w;       /* [nvis] or NULL (NULL or all zero: coplanar)       */
   int32_t uv_units;      /* PC_UV_WAVELENGTHS or PC_UV_METRES                 */
   double freq_hz;        /* observing frequency; used only for PC_UV_METRES   */
   int32_t npix;          /* n: image side, even, 16 <= n <= 8192              */
@@ -104,6 +114,8 @@ typedef struct {
   int64_t n_partials;    /* partial tiles folded for split hot tiles          */
   size_t footprint;      /* device bytes owned by the plan                    */
   int32_t precision;
+  int32_t w_planes;      /* planes of the w-stacked adjoint (0: coplanar)     */
+  double w_first, w_step;/* first plane's w and the plane spacing (wavelengths) */
 } pc_plan_info;
 
 /* Device bytes pc_plan_create would allocate for this geometry (host-only
@@ -116,8 +128,9 @@ PC_API pc_status pc_plan_footprint(const pc_geometry* geom, size_t* bytes);
  * sort and work list, the kernel correction and FFT twiddle tables, and
  * uploads them.  `stream` orders the uploads.  On success *out owns all of it.
  * Errors: PC_ERR_INVALID_ARG (NULL, nvis <= 0, odd or out-of-range npix,
- * fov <= 0, non-finite uv, a nonzero w, a field reaching l^2 + m^2 >= 1),
- * PC_ERR_UNSUPPORTED (upsamp != 2), PC_ERR_OUT_OF_MEMORY, PC_ERR_DEVICE. */
+ * fov <= 0, non-finite u, v or w, a field reaching l^2 + m^2 >= 1),
+ * PC_ERR_UNSUPPORTED (upsamp != 2; a nonzero w with PC_PREC_FP64),
+ * PC_ERR_OUT_OF_MEMORY, PC_ERR_DEVICE. */
 PC_API pc_status pc_plan_create(const pc_geometry* geom, void* stream, pc_plan** out);
 PC_API void pc_plan_destroy(pc_plan* plan);
 PC_API pc_status pc_plan_get_info(const pc_plan* plan, pc_plan_info* info);

@@ -39,7 +39,8 @@ class PcPlanInfo(C.Structure):
                 ("band_u0", C.c_int32), ("band_nu", C.c_int32), ("band_v0", C.c_int32),
                 ("band_nv", C.c_int32), ("wraps", C.c_int32), ("tile", C.c_int32),
                 ("n_tiles", C.c_int64), ("n_chunks", C.c_int64), ("n_partials", C.c_int64),
-                ("footprint", C.c_size_t), ("precision", C.c_int32)]
+                ("footprint", C.c_size_t), ("precision", C.c_int32), ("w_planes", C.c_int32),
+                ("w_first", C.c_double), ("w_step", C.c_double)]
 
 
 class PcSolveParams(C.Structure):

@@ -107,6 +107,9 @@ pc_status pc_plan_get_info(const pc_plan* p, pc_plan_info* info) {
     info->n_partials = p->n_partials;
     info->footprint = p->footprint;
     info->precision = p->precision;
+    info->w_planes = p->ws.nplanes;
+    info->w_first = p->ws.w0;
+    info->w_step = p->ws.dw;
     return PC_OK;
   });
 }

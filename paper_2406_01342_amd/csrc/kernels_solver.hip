@@ -70,6 +70,24 @@ __global__ __launch_bounds__(256) void resid_final_kernel(int nblocks,
   }
 }
 
+// Appends j to out[0..cap) for every lane with pred set: one atomic per wave
+// (the wave's count, taken by its lowest selecting lane), then each lane
+// writes at the base plus the number of selecting lanes below it.
+__device__ __forceinline__ void wave_append(bool pred, int32_t j, unsigned int* __restrict__ count,
+                                            int32_t* __restrict__ out, int64_t cap) {
+  const unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return;  // wave-uniform
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned int base = 0u;
+  if (lane == leader) base = atomicAdd(count, (unsigned int)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (pred) {
+    const unsigned int q = base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
+    if ((int64_t)q < cap) out[q] = j;
+  }
+}
+
 // Candidates {j : |eta_j| >= tau} (Alg. 2, step 1.a), or {j : eta_j >= tau,
 // eta_j > 0} under positivity (only positive maxima); order is fixed on the
 // host by sorting.
@@ -77,12 +95,9 @@ __global__ void select_kernel(int64_t N, const float* __restrict__ eta, float ta
                               unsigned int* __restrict__ count, int32_t* __restrict__ out,
                               int64_t cap) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const float e = eta[j];
-  if (positive ? (e >= tau && e > 0.0f) : fabsf(e) >= tau) {
-    const unsigned int q = atomicAdd(count, 1u);
-    if ((int64_t)q < cap) out[q] = (int32_t)j;
-  }
+  const float e = j < N ? eta[j] : 0.0f;
+  const bool pick = j < N && (positive ? (e >= tau && e > 0.0f) : fabsf(e) >= tau);
+  wave_append(pick, (int32_t)j, count, out, cap);
 }
 
 // The same selection with the threshold formed on the device from the fused
@@ -94,13 +109,10 @@ __global__ void select_from_key_kernel(int64_t N, const float* __restrict__ eta,
                                        int positive, unsigned int* __restrict__ count,
                                        int32_t* __restrict__ out, int64_t cap) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
   const float tau = (float)((double)__uint_as_float((unsigned)(key[0] >> 32)) - dec);
-  const float e = eta[j];
-  if (positive ? (e >= tau && e > 0.0f) : fabsf(e) >= tau) {
-    const unsigned int q = atomicAdd(count, 1u);
-    if ((int64_t)q < cap) out[q] = (int32_t)j;
-  }
+  const float e = j < N ? eta[j] : 0.0f;
+  const bool pick = j < N && (positive ? (e >= tau && e > 0.0f) : fabsf(e) >= tau);
+  wave_append(pick, (int32_t)j, count, out, cap);
 }
 
 __global__ void zero_u32_kernel(unsigned int* p) { *p = 0u; }
