@@ -132,8 +132,31 @@ PC_API pc_status pc_plan_footprint(const pc_geometry* geom, size_t* bytes);
  * PC_ERR_UNSUPPORTED (upsamp != 2; a nonzero w with PC_PREC_FP64),
  * PC_ERR_OUT_OF_MEMORY, PC_ERR_DEVICE. */
 PC_API pc_status pc_plan_create(const pc_geometry* geom, void* stream, pc_plan** out);
+/* Release a plan.  Waits (on the host) for the work that the plan's entry
+ * points queued, as recorded by an event on each stream they were given, and
+ * not for the rest of the device; work queued by
+ * pc_restricted_gradient_noalloc is not recorded (it creates no event), so
+ * its stream must have been synchronised first.  The plan's device buffers go
+ * to a per-device pool that later plans and solvers reuse (by size class; the
+ * pool keeps at most an eighth of the device's memory and is emptied when an
+ * allocation would otherwise fail), so destroying a plan never waits for the
+ * whole device.
+ *
+ * Footprint: pc_plan_footprint and pc_plan_get_info's footprint count what
+ * plan creation allocates (each buffer rounded up to its pool size class).
+ * Entry points add per-call scratch on first use and keep it: the atom table
+ * (40 bytes per atom), the restricted adjoint's partial sums (at most
+ * 8 bytes x atoms x a few hundred) and, for pc_adjoint_grid_ms, one npix^2
+ * float image; info.footprint then reports the larger total. */
 PC_API void pc_plan_destroy(pc_plan* plan);
 PC_API pc_status pc_plan_get_info(const pc_plan* plan, pc_plan_info* info);
+
+/* Frees every buffer parked in the device pool of `device` (see
+ * pc_plan_destroy), for callers that need the memory elsewhere (another
+ * allocator in the process).  hipFree waits for the device.  *released (may
+ * be NULL) gets the bytes freed.  Errors: PC_ERR_INVALID_ARG (device < 0),
+ * PC_ERR_DEVICE. */
+PC_API pc_status pc_device_pool_trim(int32_t device, size_t* released);
 
 /* Per-kernel instrumentation.  While enabled, every kernel the plan launches
  * (operators and solver) is bracketed by HIP events on its stream, and

@@ -85,6 +85,7 @@ SIGNATURES = {
     "pc_plan_footprint": (C.c_int, [C.POINTER(PcGeometry), C.POINTER(C.c_size_t)]),
     "pc_plan_create": (C.c_int, [C.POINTER(PcGeometry), _P, C.POINTER(_P)]),
     "pc_plan_destroy": (None, [_P]),
+    "pc_device_pool_trim": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
     "pc_plan_get_info": (C.c_int, [_P, C.POINTER(PcPlanInfo)]),
     "pc_last_error": (C.c_char_p, []),
     "pc_adjoint_grid": (C.c_int, [_P, _P, _P, _PD, _PI64, _P]),

@@ -96,6 +96,14 @@ def _geometry(uv, npix, fov_rad, w, uv_units, freq_hz, nufft_eps, upsamp, precis
     return g, keep
 
 
+def pc_device_pool_trim(device: int = 0) -> int:
+    """Frees the device buffers parked in the library's pool on ``device``
+    (released plans' and solvers' memory kept for reuse); returns the bytes."""
+    n = C.c_size_t(0)
+    check(LIB.pc_device_pool_trim(int(device), C.byref(n)), "pc_device_pool_trim")
+    return int(n.value)
+
+
 def pc_plan_footprint(uv, npix: int, fov_rad: float, *, w=None, uv_units=PC_UV_WAVELENGTHS,
                       freq_hz: float = 0.0, nufft_eps: float = 1e-5, upsamp: float = 2.0,
                       precision: int = PC_PREC_FP32) -> int:

@@ -10,6 +10,7 @@
 
 extern "C" pc_status pc_plan_footprint_impl(const pc_geometry* geom, size_t* bytes);
 extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, pc_plan** out);
+extern "C" pc_status pc_device_pool_trim_impl(int32_t device, size_t* released);
 
 namespace pc {
 
@@ -58,6 +59,20 @@ static void check_atoms(const pc_plan* p, int64_t natoms, const void* pix, const
 
 static void set_device(const pc_plan* p) { PC_HIP(hipSetDevice(p->device)); }
 
+// Marks the end of an entry point's work on its stream (plan_touch) when the
+// entry point returns, so that pc_plan_destroy can wait for it alone.
+struct Touch {
+  pc_plan* p;
+  hipStream_t s;
+  Touch(pc_plan* plan, void* stream) : p(plan), s((hipStream_t)stream) {}
+  ~Touch() {
+    try {
+      plan_touch(p, s);
+    } catch (...) {
+    }
+  }
+};
+
 // Launch tables of pc_adjoint_grid_batch, per device (calls are serialised).
 constexpr int kMaxDevices = 64;
 static std::mutex g_batch_mutex;
@@ -79,11 +94,22 @@ pc_status pc_plan_create(const pc_geometry* geom, void* stream, pc_plan** out) {
   return guard("pc_plan_create", [&] { return pc_plan_create_impl(geom, stream, out); });
 }
 
+pc_status pc_device_pool_trim(int32_t device, size_t* released) {
+  return guard("pc_device_pool_trim", [&] {
+    PC_REQUIRE(device >= 0, "device must be >= 0");
+    int cur = 0;
+    PC_HIP(hipGetDevice(&cur));
+    PC_HIP(hipSetDevice(device));
+    const pc_status st = pc_device_pool_trim_impl(device, released);
+    PC_HIP(hipSetDevice(cur));
+    return st;
+  });
+}
+
 void pc_plan_destroy(pc_plan* plan) {
   if (!plan) return;
   (void)hipSetDevice(plan->device);
-  (void)hipDeviceSynchronize();
-  plan_release(plan);
+  plan_release(plan);  // waits for the plan's own recorded work, not the device
   delete plan;
 }
 
@@ -120,6 +146,7 @@ pc_status pc_adjoint_grid(pc_plan* p, const void* vis, float* image, double* max
     check_plan(p, PC_PREC_FP32);
     PC_REQUIRE(vis != nullptr && image != nullptr, "vis and image must not be NULL");
     set_device(p);
+    Touch touch(p, stream);
     hipStream_t s = (hipStream_t)stream;
     adjoint_grid<float>(p, (const c32*)vis, false, image, 1.0f, s);
     if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
@@ -137,6 +164,7 @@ pc_status pc_adjoint_grid_ms(pc_plan* p, const void* vis, int32_t n_scales, cons
     PC_REQUIRE((int64_t)D.S * p->g.n * p->g.n < ((int64_t)1 << 31),
                "n_scales * npix^2 must be < 2^31");
     set_device(p);
+    Touch touch(p, stream);
     hipStream_t s = (hipStream_t)stream;
     // Phi* vis into a plan-owned image (every scale reads all of it), then
     // Psi* into images
@@ -155,6 +183,7 @@ pc_status pc_adjoint_grid_f64(pc_plan* p, const void* vis, double* image, double
     PC_REQUIRE(vis != nullptr && image != nullptr, "vis and image must not be NULL");
     if (p->g.M > 8192) fail(PC_ERR_UNSUPPORTED, "FP64 twin supports fine grids up to 8192");
     set_device(p);
+    Touch touch(p, stream);
     hipStream_t s = (hipStream_t)stream;
     adjoint_grid<double>(p, (const c64*)vis, false, image, 1.0, s);
     if (max_abs || argmax) maxkey_read(p, s, max_abs, argmax);
@@ -169,6 +198,7 @@ pc_status pc_forward_sparse(pc_plan* p, int64_t natoms, const int32_t* pix, cons
     check_atoms(p, natoms, pix, weight, true);
     PC_REQUIRE(vis_out != nullptr, "vis_out is NULL");
     set_device(p);
+    Touch touch(p, stream);
     forward_sparse<float>(p, natoms, pix, weight, nullptr, false, (c32*)vis_out, false,
                           (hipStream_t)stream);
     return PC_OK;
@@ -182,6 +212,7 @@ pc_status pc_forward_sparse_f64(pc_plan* p, int64_t natoms, const int32_t* pix,
     check_atoms(p, natoms, pix, weight, true);
     PC_REQUIRE(vis_out != nullptr, "vis_out is NULL");
     set_device(p);
+    Touch touch(p, stream);
     forward_sparse<double>(p, natoms, pix, weight, nullptr, false, (c64*)vis_out, false,
                            (hipStream_t)stream);
     return PC_OK;
@@ -196,6 +227,7 @@ pc_status pc_adjoint_sparse_f64(pc_plan* p, const void* vis, int64_t natoms, con
     PC_REQUIRE(vis != nullptr, "vis is NULL");
     if (natoms > 0) PC_REQUIRE(out != nullptr, "out is NULL");
     set_device(p);
+    Touch touch(p, stream);
     adjoint_sparse<double>(p, (const c64*)vis, false, natoms, pix, out, (hipStream_t)stream);
     return PC_OK;
   });
@@ -211,6 +243,7 @@ pc_status pc_dual_certificate_f64(pc_plan* p, const void* vis, int64_t natoms, c
     PC_REQUIRE(std::isfinite(lambda) && lambda > 0, "lambda must be finite and > 0");
     if (p->g.M > 8192) fail(PC_ERR_UNSUPPORTED, "FP64 twin supports fine grids up to 8192");
     set_device(p);
+    Touch touch(p, stream);
     hipStream_t s = (hipStream_t)stream;
     c64* r = (c64*)p->vis_scratch;
     forward_sparse<double>(p, natoms, pix, weight, (const c64*)vis, false, r, true, s);
@@ -242,6 +275,7 @@ pc_status pc_adjoint_grid_batch(pc_plan* const* plans, const void* const* vis,
     hipStream_t s = (hipStream_t)stream;
     adjoint_grid_batch(g_batch_ctx[dev], plans, (const c32* const*)vis, sorted.get(), images,
                        nullptr, njobs, s);
+    for (int j = 0; j < njobs; ++j) plan_touch(plans[j], s);
     if (max_abs || argmax) {
       for (int j = 0; j < njobs; ++j)
         maxkey_read(plans[j], s, max_abs ? max_abs + j : nullptr, argmax ? argmax + j : nullptr);
@@ -255,6 +289,7 @@ pc_status pc_forward_grid(pc_plan* p, const float* image, void* vis_out, void* s
     check_plan(p, PC_PREC_FP32);
     PC_REQUIRE(image != nullptr && vis_out != nullptr, "image and vis_out must not be NULL");
     set_device(p);
+    Touch touch(p, stream);
     forward_grid<float>(p, image, (c32*)vis_out, false, (hipStream_t)stream);
     return PC_OK;
   });
@@ -268,6 +303,7 @@ pc_status pc_adjoint_sparse(pc_plan* p, const void* vis, int64_t natoms, const i
     PC_REQUIRE(vis != nullptr, "vis is NULL");
     if (natoms > 0) PC_REQUIRE(out != nullptr, "out is NULL");
     set_device(p);
+    Touch touch(p, stream);
     adjoint_sparse<float>(p, (const c32*)vis, false, natoms, pix, out, (hipStream_t)stream);
     return PC_OK;
   });
@@ -282,6 +318,7 @@ pc_status pc_restricted_gradient(pc_plan* p, const void* vis, int64_t natoms, co
     if (natoms > 0) PC_REQUIRE(grad != nullptr, "grad is NULL");
     PC_REQUIRE(resid == nullptr || resid != vis, "resid must not alias vis");
     set_device(p);
+    Touch touch(p, stream);
     restricted_gradient(p, (const c32*)vis, natoms, pix, weight, grad, (c32*)resid,
                         (hipStream_t)stream);
     return PC_OK;
@@ -313,6 +350,7 @@ pc_status pc_dual_certificate(pc_plan* p, const void* vis, int64_t natoms, const
     PC_REQUIRE(vis != nullptr && cert != nullptr, "vis and cert must not be NULL");
     PC_REQUIRE(std::isfinite(lambda) && lambda > 0, "lambda must be finite and > 0");
     set_device(p);
+    Touch touch(p, stream);
     hipStream_t s = (hipStream_t)stream;
     c32* r = (c32*)p->vis_scratch;
     // residual in plan order: r = V - Phi x

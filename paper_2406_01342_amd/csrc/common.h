@@ -239,6 +239,7 @@ struct pc_plan {
   std::vector<int32_t> chunk_work;  // host copy: visibilities per spreading workgroup
 
   std::vector<pc::DeviceBuf> owned;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> touched;  // see plan_touch
 };
 
 namespace pc {
@@ -258,6 +259,22 @@ void prof_reset(pc_plan* p);
 void prof_release(pc_plan* p);
 
 // plan.cpp
+// Per-device pool of device buffers.  Released buffers (a destroyed plan's,
+// a finished solver's, scratch that grew) are kept for reuse instead of being
+// passed to hipFree, which waits for the whole device: in a serving loop every
+// job's end would otherwise drain the other jobs' work.  Buffers are pooled
+// by size class (a power of two times 1, 1.25, 1.5 or 1.75, at most 25 %
+// slack) up to an eighth of the device's memory; beyond that they are freed.
+// pool_trim frees every pooled buffer of a device (returns the bytes).
+// The releaser guarantees that no pending work still uses a released buffer.
+void* pool_alloc(int device, size_t bytes, size_t* got);
+void pool_release(int device, void* ptr, size_t bytes);
+size_t pool_class(size_t bytes);
+size_t pool_trim(int device);
+// Work of a plan's entry points is followed by an event on the call's stream
+// (one per stream the plan has seen); destroying the plan waits for these
+// events only.
+void plan_touch(pc_plan* p, hipStream_t s);
 void* dalloc(pc_plan* p, size_t bytes);
 void plan_release(pc_plan* p);
 void* ensure_atom_scratch(pc_plan* p, size_t bytes);

@@ -10,24 +10,127 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "common.h"
 
 namespace pc {
 
+namespace {
+constexpr int kPoolDevices = 64;
+struct DevicePool {
+  std::mutex mu;
+  std::vector<DeviceBuf> free;  // bytes = the size class
+  size_t held = 0, cap = 0;
+};
+DevicePool g_pool[kPoolDevices];
+}  // namespace
+
+size_t pool_class(size_t bytes) {
+  if (bytes <= 256) return 256;
+  int e = 63 - __builtin_clzll((unsigned long long)(bytes - 1));  // 2^e < bytes <= 2^(e+1)
+  const size_t step = (size_t)1 << (e - 2);                       // quarters of 2^e
+  return (bytes + step - 1) / step * step;
+}
+
+size_t pool_trim(int device);
+
+void* pool_alloc(int device, size_t bytes, size_t* got) {
+  const size_t cls = pool_class(bytes);
+  if (device >= 0 && device < kPoolDevices) {
+    DevicePool& P = g_pool[device];
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto it = P.free.begin(); it != P.free.end(); ++it)
+      if (it->bytes == cls) {
+        void* ptr = it->ptr;
+        P.held -= cls;
+        P.free.erase(it);
+        *got = cls;
+        return ptr;
+      }
+  }
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, cls);
+  if (e != hipSuccess && device >= 0 && device < kPoolDevices) {
+    // out of memory with buffers parked in the pool: give them back and retry
+    (void)hipGetLastError();
+    if (pool_trim(device) > 0) e = hipMalloc(&ptr, cls);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(PC_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(cls) + " bytes failed");
+  }
+  *got = cls;
+  return ptr;
+}
+
+void pool_release(int device, void* ptr, size_t bytes) {
+  if (!ptr) return;
+  if (device >= 0 && device < kPoolDevices) {
+    DevicePool& P = g_pool[device];
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (P.cap == 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) P.cap = tot / 8;
+      else (void)hipGetLastError();
+    }
+    if (bytes == pool_class(bytes) && P.held + bytes <= P.cap) {
+      P.free.push_back({ptr, bytes});
+      P.held += bytes;
+      return;
+    }
+  }
+  (void)hipFree(ptr);
+}
+
+size_t pool_trim(int device) {
+  if (device < 0 || device >= kPoolDevices) return 0;
+  DevicePool& P = g_pool[device];
+  std::vector<DeviceBuf> drop;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    drop.swap(P.free);
+    P.held = 0;
+  }
+  size_t n = 0;
+  for (auto& b : drop) {
+    (void)hipFree(b.ptr);
+    n += b.bytes;
+  }
+  return n;
+}
+
+void plan_touch(pc_plan* p, hipStream_t s) {
+  for (auto& t : p->touched)
+    if (t.first == s) {
+      PC_HIP(hipEventRecord(t.second, s));
+      return;
+    }
+  hipEvent_t ev = nullptr;
+  PC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  p->touched.push_back({s, ev});
+  PC_HIP(hipEventRecord(ev, s));
+}
+
 void* dalloc(pc_plan* p, size_t bytes) {
   if (bytes == 0) bytes = 256;
-  void* ptr = nullptr;
-  PC_HIP(hipMalloc(&ptr, bytes));
-  p->owned.push_back({ptr, bytes});
-  p->footprint += bytes;
+  size_t got = 0;
+  void* ptr = pool_alloc(p->device, bytes, &got);
+  p->owned.push_back({ptr, got});
+  p->footprint += got;
   return ptr;
 }
 
 void plan_release(pc_plan* p) {
   prof_release(p);
-  for (auto& b : p->owned) (void)hipFree(b.ptr);
+  // the plan's own work only (no device-wide wait)
+  for (auto& t : p->touched) {
+    (void)hipEventSynchronize(t.second);
+    (void)hipEventDestroy(t.second);
+  }
+  p->touched.clear();
+  for (auto& b : p->owned) pool_release(p->device, b.ptr, b.bytes);
   p->owned.clear();
   if (p->ev_a) (void)hipEventDestroy(p->ev_a);
   if (p->ev_b) (void)hipEventDestroy(p->ev_b);
@@ -39,6 +142,8 @@ static void* grow(pc_plan* p, void** slot, size_t* cap, size_t bytes) {
     for (auto it = p->owned.begin(); it != p->owned.end(); ++it)
       if (it->ptr == *slot) {
         p->footprint -= it->bytes;
+        // queued work of the current call may still read the old buffer:
+        // hipFree waits for it (growth is rare: scratch reaches its size early)
         (void)hipFree(it->ptr);
         p->owned.erase(it);
         break;
@@ -562,7 +667,7 @@ static size_t layout_bytes(const Layout& lay, int prec) {
   const GridGeom& g = lay.g;
   const size_t cb = prec == PC_PREC_FP64 ? 16 : 8, rb = cb / 2;
   size_t b = 0;
-  auto add = [&](size_t x) { b += std::max<size_t>(x, 256); };
+  auto add = [&](size_t x) { b += pool_class(std::max<size_t>(x, 256)); };
   add(lay.L * 4);                            // perm
   add(lay.L * 16);                           // AB
   add(lay.L * 4);                            // cell
@@ -588,6 +693,13 @@ static size_t layout_bytes(const Layout& lay, int prec) {
 }  // namespace pc
 
 using namespace pc;
+
+extern "C" pc_status pc_device_pool_trim_impl(int32_t device, size_t* released) {
+  PC_REQUIRE(device >= 0, "device must be >= 0");
+  const size_t n = pool_trim(device);
+  if (released) *released = n;
+  return PC_OK;
+}
 
 extern "C" pc_status pc_plan_footprint_impl(const pc_geometry* geom, size_t* bytes) {
   PC_REQUIRE(bytes != nullptr, "bytes is NULL");

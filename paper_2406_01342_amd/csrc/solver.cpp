@@ -35,18 +35,24 @@ template <typename T>
 struct DevArray {
   T* ptr = nullptr;
   int64_t cap = 0;
+  size_t bytes = 0;
+  int dev = -1;
   void ensure(int64_t n) {
     if (n <= cap && ptr) return;
     int64_t want = std::max<int64_t>(n, std::max<int64_t>(2 * cap, 256));
+    // growth mid-solve: queued work may still read the old array, which
+    // hipFree waits for
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     cap = 0;
-    PC_HIP(hipMalloc(&ptr, want * sizeof(T)));
-    cap = want;
+    PC_HIP(hipGetDevice(&dev));
+    size_t got = 0;
+    ptr = static_cast<T*>(pool_alloc(dev, want * sizeof(T), &got));
+    bytes = got;
+    cap = (int64_t)(got / sizeof(T));
   }
-  ~DevArray() {
-    if (ptr) (void)hipFree(ptr);
-  }
+  // to the device pool: the owner has waited for its stream (see ~Pfw)
+  ~DevArray() { pool_release(dev, ptr, bytes); }
 };
 
 // Device FP64 table that keeps its contents when it grows (the old entries
@@ -54,22 +60,24 @@ struct DevArray {
 struct KeepDevArray {
   double* ptr = nullptr;
   int64_t cap = 0;
+  size_t bytes = 0;
+  int dev = -1;
   void ensure(int64_t n, hipStream_t s) {
     if (n <= cap && ptr) return;
     const int64_t want = std::max<int64_t>(n, std::max<int64_t>(2 * cap, 1024));
-    double* np = nullptr;
-    PC_HIP(hipMalloc(&np, want * sizeof(double)));
+    PC_HIP(hipGetDevice(&dev));
+    size_t got = 0;
+    double* np = static_cast<double*>(pool_alloc(dev, want * sizeof(double), &got));
     if (ptr) {
       PC_HIP(hipMemcpyAsync(np, ptr, cap * sizeof(double), hipMemcpyDeviceToDevice, s));
       PC_HIP(hipStreamSynchronize(s));
-      (void)hipFree(ptr);
+      pool_release(dev, ptr, bytes);  // the copy above was its last use
     }
     ptr = np;
-    cap = want;
+    bytes = got;
+    cap = (int64_t)(got / sizeof(double));
   }
-  ~KeepDevArray() {
-    if (ptr) (void)hipFree(ptr);
-  }
+  ~KeepDevArray() { pool_release(dev, ptr, bytes); }
 };
 
 constexpr int kCheck = 4;        // APGD convergence test cadence
@@ -233,6 +241,10 @@ struct Pfw {
   double adj_ms = 0;
   int adj_calls = 0;
   double t0 = 0;
+
+  // The arrays go back to the device pool after this: wait for the solve's
+  // stream first (its own work only, not the whole device).
+  ~Pfw() { (void)hipStreamSynchronize(s); }
 
   Pfw(pc_plan* plan, hipStream_t stream, const pc_solve_params& params)
       : p(plan), s(stream), prm(params), L(plan->L), N((int64_t)plan->g.n * plan->g.n),
@@ -1010,6 +1022,7 @@ static pc_solver* solver_new(pc_plan* plan, const void* vis, const pc_solve_para
   sv->pfw.batcher = batcher;
   try {
     sv->pfw.init(vis);
+    plan_touch(plan, (hipStream_t)stream);
   } catch (...) {
     delete sv;
     throw;
@@ -1085,6 +1098,7 @@ PC_API pc_status pc_solver_step(pc_solver* sv, int32_t* done) {
     PC_REQUIRE(sv != nullptr, "solver is NULL");
     PC_HIP(hipSetDevice(sv->pfw.p->device));
     sv->pfw.step();
+    plan_touch(sv->pfw.p, sv->pfw.s);
     if (done) *done = sv->pfw.done ? 1 : 0;
     return PC_OK;
   });

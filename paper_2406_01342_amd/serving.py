@@ -105,7 +105,8 @@ class DeviceBackend:
         # the dirty residual and the gridded operators' dense image, plus the
         # per-scale analysis with a dictionary
         img = 4 * req.npix * req.npix * (2 + (S if "scales" in req.params else 0))
-        return int(plan) + 24 * L + img + cert + self.FIXED_BYTES
+        # solver arrays come in the device pool's size classes (<= 25 % more)
+        return int(plan) + (5 * (24 * L + img)) // 4 + cert + self.FIXED_BYTES
 
     def _params(self, req: ImagingRequest) -> dict:
         prm = dict(req.params)
