@@ -57,14 +57,14 @@ KERNEL_FILES = {
 }
 # kernel name in the library's statistics -> substring of its symbol
 KERNEL_SYMBOLS = {
-    "adjoint_sparse": "adjoint_sparse_kernel<float, float, false>",
-    "forward_sparse": "forward_sparse_kernel<float>",
+    "adjoint_sparse": "adjoint_sparse_kernel<float, float, false, false>",
+    "forward_sparse": "forward_sparse_kernel<float, false>",
     "adjoint_sparse_reduce": "adjoint_sparse_reduce_kernel<float, float>",
     "forward_adjoint_sparse": "forward_adjoint_kernel<",
-    "adjoint_sparse_acc64": "adjoint_sparse_kernel<float, double, false>",
-    "psf_sums_acc64": "adjoint_sparse_kernel<float, double, true>",
-    "spread": "spread_kernel<float", "fold": "fold_kernel<float>", "passA_adj": "passA_adj_kernel<float",
-    "passB_adj": "passB_adj_kernel<float",
+    "adjoint_sparse_acc64": "adjoint_sparse_kernel<float, double, false, false>",
+    "psf_sums_acc64": "adjoint_sparse_kernel<float, double, true, false>",
+    "spread": "spread_quad_kernel<", "fold": "fold_kernel<float>",
+    "passA_adj": "passA_adj_kernel<float", "passB_adj": "passB_adj_kernel<float",
     "dict_analysis": "dict_tile_h_kernel<16>",  # the widest of the paper's scales (sigma 8)
 }
 PROFILES = os.path.join(ROOT, "profiles")
@@ -146,6 +146,32 @@ def summarize_pmc(kernel, fetch_dir, write_dir, command):
     print(json.dumps(out, indent=1))
 
 
+def summarize_counters(pmc_dirs, out_name, command, top=8):
+    """Writes a short text table of per-dispatch means of every counter found
+    in rocprofv3 --pmc runs (several directories: one per counter pass) for
+    the kernels with the most dispatch time."""
+    import collections
+    sums = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in pmc_dirs:
+        for r in _counter_rows(d):
+            sums[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted(sums, key=lambda k: -sum(len(v) for v in sums[k].values()))
+    ctrs = sorted({c for k in sums for c in sums[k]})
+    lines = ["# rocprofv3 counters, mean per dispatch", f"# command: {command}", ""]
+    keep = [k for k in names if any(s_ in k for s_ in KERNEL_SYMBOLS.values())][:top]
+    for k in keep:
+        short = k if len(k) <= 90 else k[:87] + "..."
+        lines.append(short)
+        for c in ctrs:
+            v = sums[k].get(c)
+            if v:
+                lines.append(f"    {c:28s} {sum(v) / len(v):16.1f}   ({len(v)} dispatches)")
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(os.path.join(PROFILES, out_name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_trace(trace_dir, out_name, command, top=14):
     """Writes a short text summary of a rocprofv3 --kernel-trace --stats run."""
     import csv
@@ -192,6 +218,8 @@ def parse():
                          "(for profiler runs)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("KERNEL", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_KERNEL.json from two rocprofv3 --pmc runs")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="ARG",
+                    help="OUT_NAME PMC_DIR...: write profiles/OUT_NAME from rocprofv3 --pmc runs")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_NAME"),
                     help="write profiles/OUT_NAME from a rocprofv3 --kernel-trace --stats run")
     ap.add_argument("--command", default="", help="the profiled command, recorded in summaries")
@@ -603,6 +631,9 @@ def main():
     args = parse()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.command)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[1:], args.summarize_counters[0], args.command)
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, args.command)
