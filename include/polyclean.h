@@ -435,7 +435,9 @@ typedef struct pc_batcher_stats {
   int64_t visibilities; /* sum of the served plans' visibility counts */
   int32_t max_batch;    /* most requests merged into one group */
   int32_t pad;
-  double seconds;       /* device time of the shared launches (HIP events) */
+  double seconds;       /* device time of the shared adjoints (HIP events) */
+  int64_t forwards;     /* residual forwards (direct sums, step 4) run in
+                           shared launches ahead of the adjoints */
 } pc_batcher_stats;
 
 /* Creates a batcher on `device` with a stream of its own (default priority).

@@ -8,6 +8,10 @@
 // maxima, and wakes them.  Requests posted while a batch runs form the next
 // batch, so a job never waits for another job's iteration to finish, only for
 // the launches already on the device (continuous, iteration-level batching).
+// A request may carry its residual forward (r = V - Phi_S x by the direct
+// sums, step 4 of Alg. 2): the leader then runs the residuals of all such
+// requests in one shared launch over (job, visibility block) items ahead of
+// the shared adjoint, which reads them.
 #include <algorithm>
 #include <condition_variable>
 #include <cstring>
@@ -24,6 +28,7 @@ struct AdjRequest {
   const c32* vis;
   float* image;
   hipStream_t s;
+  const FwdSpec* fwd = nullptr;  // residual to form first into vis (plan order)
   double max_abs = 0;
   int64_t argmax = -1;
   float ms = 0;
@@ -41,6 +46,7 @@ struct pc_batcher {
   hipStream_t stream = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   BatchCtx ctx;
+  BatchCtx fctx;                       // tables of the shared residual forward
   unsigned long long* keys = nullptr;  // pinned, one per request of a batch
   size_t keys_cap = 0;
   std::vector<hipEvent_t> deps;        // per-request stream-order events
@@ -50,9 +56,11 @@ struct pc_batcher {
   std::vector<AdjRequest*> pending;
   bool busy = false;
   pc_batcher_stats stats{};
+  int64_t nfwd_ = 0;  // residual forwards of the batch being executed (leader only)
 
   ~pc_batcher() {
     ctx.release();
+    fctx.release();
     for (hipEvent_t e : deps) (void)hipEventDestroy(e);
     if (keys) (void)hipHostFree(keys);
     if (e0) (void)hipEventDestroy(e0);
@@ -80,6 +88,7 @@ struct pc_batcher {
     std::vector<const c32*> vis(n);
     std::vector<float*> images(n);
     std::vector<float> scales(n, 1.0f);
+    std::vector<FwdJob> fwd;
     int64_t nvis = 0;
     for (int j = 0; j < n; ++j) {
       AdjRequest* r = batch[j];
@@ -89,7 +98,12 @@ struct pc_batcher {
       nvis += r->p->L;
       PC_HIP(hipEventRecord(deps[j], r->s));
       PC_HIP(hipStreamWaitEvent(stream, deps[j], 0));
+      if (r->fwd)
+        fwd.push_back(FwdJob{r->p->AB, r->p->Cw, r->fwd->atoms, r->fwd->base,
+                             const_cast<c32*>(r->vis), r->p->L, r->fwd->natoms});
     }
+    forward_residual_batch(fctx, fwd, stream);
+    nfwd_ = (int64_t)fwd.size();
     std::unique_ptr<bool[]> flags(new bool[n]);
     for (int j = 0; j < n; ++j) flags[j] = true;
     PC_HIP(hipEventRecord(e0, stream));
@@ -135,6 +149,7 @@ struct pc_batcher {
         }
         lk.lock();
         if (st == PC_OK) {
+          stats.forwards += nfwd_;
           stats.batches += 1;
           stats.requests += (int64_t)batch.size();
           stats.visibilities += nvis;
@@ -158,9 +173,11 @@ struct pc_batcher {
 namespace pc {
 
 void batcher_adjoint(pc_batcher* b, pc_plan* p, const c32* vis_sorted, float* image,
-                     hipStream_t s, double* max_abs, int64_t* argmax, float* ms) {
+                     hipStream_t s, double* max_abs, int64_t* argmax, float* ms,
+                     const FwdSpec* fwd) {
   PC_REQUIRE(p->device == b->device, "plan and batcher are on different devices");
-  AdjRequest r{p, vis_sorted, image, s};
+  PC_REQUIRE(p->precision == PC_PREC_FP32, "batched adjoint needs an FP32 plan");
+  AdjRequest r{p, vis_sorted, image, s, fwd};
   b->run(&r);
   if (r.status != PC_OK) fail(r.status, "batched adjoint: " + r.error);
   *max_abs = r.max_abs;

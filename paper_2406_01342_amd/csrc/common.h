@@ -329,6 +329,19 @@ struct BatchCtx {
   bool pending = false;
   void release();
 };
+// Residuals r = V - Phi_S x of several FP32 plans (direct sums, plan order)
+// in one launch over (job, block of 256 visibilities) items; each job rounds
+// exactly as forward_atoms does.  Same ctx rules as adjoint_grid_batch.
+struct FwdJob {
+  const double* AB;
+  const double* Cw;  // NULL: coplanar
+  const Atom<float>* atoms;
+  const cpx<float>* base;
+  cpx<float>* out;
+  int64_t L;
+  int64_t natoms;
+};
+void forward_residual_batch(BatchCtx& ctx, const std::vector<FwdJob>& jobs, hipStream_t s);
 // Gridded adjoints of several FP32 plans in shared launches (one spread per
 // kernel width, one fold, one launch per fine-grid size for each FFT pass).
 // vis[j] is in plan order when vis_sorted[j], else in caller order.  The
@@ -344,8 +357,17 @@ void maxkey_decode(unsigned long long key, double* max_abs, int64_t* argmax);
 // the requests of jobs on other host threads into shared launches.  Blocks
 // until the job's image and maximum are ready; `ms` gets the duration of the
 // shared launches.
+// With fwd, the residual vis_sorted = fwd->base - Phi_S x (direct sums over
+// fwd's atom table) is formed first, in a launch shared with the other
+// requests of the batch that carry one.
+struct FwdSpec {
+  const Atom<float>* atoms;
+  int64_t natoms;
+  const cpx<float>* base;  // plan order
+};
 void batcher_adjoint(pc_batcher* b, pc_plan* p, const c32* vis_sorted, float* image,
-                     hipStream_t s, double* max_abs, int64_t* argmax, float* ms);
+                     hipStream_t s, double* max_abs, int64_t* argmax, float* ms,
+                     const FwdSpec* fwd = nullptr);
 
 // kernels_dft.hip
 template <typename R>

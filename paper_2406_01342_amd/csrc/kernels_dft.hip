@@ -63,20 +63,14 @@ __device__ __forceinline__ void sincos_turns(double t, R& s, R& c) {
   }
 }
 
-// out_k = base_k - sum_p w_p exp(-2 pi i t_kp)   (base NULL: no base term)
-// One thread per visibility (plan order); atoms are read with uniform
-// (scalar) loads.
+// sum_p w_p exp(-2 pi i t_kp) for one visibility (A, B, C = u dl, v dl, w),
+// atoms in order, four at a time; shared by the single-plan and the batched
+// forward so that both round identically.
 template <typename R, bool HW>
-__global__ __launch_bounds__(256) void forward_sparse_kernel(
-    int64_t L, int64_t natoms, const double* __restrict__ AB, const double* __restrict__ Cw,
-    const Atom<R>* __restrict__ atoms,
-    const cpx<R>* __restrict__ base, const int32_t* __restrict__ base_perm, R sign_base,
-    cpx<R>* __restrict__ out, const int32_t* __restrict__ out_perm) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= L) return;
-  const double A = AB[2 * k], B = AB[2 * k + 1];
-  const double C = HW ? Cw[k] : 0.0;
-  R re = 0, im = 0;
+__device__ __forceinline__ void forward_sum(double A, double B, double C, int64_t natoms,
+                                            const Atom<R>* __restrict__ atoms, R& re, R& im) {
+  re = 0;
+  im = 0;
   int64_t p = 0;
   for (; p + 4 <= natoms; p += 4) {
 #pragma unroll
@@ -101,6 +95,21 @@ __global__ __launch_bounds__(256) void forward_sparse_kernel(
     re = fma(at.w, c, re);
     im = fma(-at.w, s, im);
   }
+}
+
+// out_k = base_k - sum_p w_p exp(-2 pi i t_kp)   (base NULL: no base term)
+// One thread per visibility (plan order); atoms are read with uniform
+// (scalar) loads.
+template <typename R, bool HW>
+__global__ __launch_bounds__(256) void forward_sparse_kernel(
+    int64_t L, int64_t natoms, const double* __restrict__ AB, const double* __restrict__ Cw,
+    const Atom<R>* __restrict__ atoms,
+    const cpx<R>* __restrict__ base, const int32_t* __restrict__ base_perm, R sign_base,
+    cpx<R>* __restrict__ out, const int32_t* __restrict__ out_perm) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  R re, im;
+  forward_sum<R, HW>(AB[2 * k], AB[2 * k + 1], HW ? Cw[k] : 0.0, natoms, atoms, re, im);
   cpx<R> o;
   if (base) {
     const cpx<R> b = base[base_perm ? base_perm[k] : k];
@@ -109,6 +118,56 @@ __global__ __launch_bounds__(256) void forward_sparse_kernel(
     o = {re, im};
   }
   out[out_perm ? out_perm[k] : k] = o;
+}
+
+// Residuals r = V - Phi_S x of several plans in one launch (plan order
+// throughout): items[b] = (job, block of 256 visibilities).
+__global__ __launch_bounds__(256) void forward_residual_batch_kernel(
+    const FwdJob* __restrict__ jobs, const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const FwdJob& J = jobs[it.x];
+  const int64_t k = (int64_t)it.y * 256 + threadIdx.x;
+  if (k >= J.L) return;
+  float re, im;
+  if (J.Cw)
+    forward_sum<float, true>(J.AB[2 * k], J.AB[2 * k + 1], J.Cw[k], J.natoms, J.atoms, re, im);
+  else
+    forward_sum<float, false>(J.AB[2 * k], J.AB[2 * k + 1], 0.0, J.natoms, J.atoms, re, im);
+  const cpx<float> b = J.base[k];
+  J.out[k] = {b.x - re, b.y - im};
+}
+
+void forward_residual_batch(BatchCtx& ctx, const std::vector<FwdJob>& jobs, hipStream_t s) {
+  if (jobs.empty()) return;
+  if (!ctx.done) PC_HIP(hipEventCreateWithFlags(&ctx.done, hipEventDisableTiming));
+  if (ctx.pending) PC_HIP(hipEventSynchronize(ctx.done));
+  std::vector<int2> items;
+  for (size_t j = 0; j < jobs.size(); ++j)
+    for (int64_t b = 0; b < (jobs[j].L + 255) / 256; ++b) items.push_back(make_int2((int)j, (int)b));
+  const size_t o_items = (jobs.size() * sizeof(FwdJob) + 255) & ~size_t(255);
+  const size_t bytes = o_items + items.size() * sizeof(int2);
+  if (ctx.host_bytes < bytes) {
+    if (ctx.host) (void)hipHostFree(ctx.host);
+    ctx.host = nullptr;
+    ctx.host_bytes = 0;
+    PC_HIP(hipHostMalloc((void**)&ctx.host, bytes * 2));
+    ctx.host_bytes = bytes * 2;
+  }
+  if (ctx.dev_bytes < bytes) {
+    if (ctx.dev) (void)hipFree(ctx.dev);
+    ctx.dev = nullptr;
+    ctx.dev_bytes = 0;
+    PC_HIP(hipMalloc((void**)&ctx.dev, bytes * 2));
+    ctx.dev_bytes = bytes * 2;
+  }
+  std::memcpy(ctx.host, jobs.data(), jobs.size() * sizeof(FwdJob));
+  std::memcpy(ctx.host + o_items, items.data(), items.size() * sizeof(int2));
+  PC_HIP(hipMemcpyAsync(ctx.dev, ctx.host, bytes, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(forward_residual_batch_kernel, dim3((unsigned)items.size()), dim3(256), 0, s,
+                     (const FwdJob*)ctx.dev, (const int2*)(ctx.dev + o_items));
+  PC_LAUNCH_CHECK("forward_residual_batch");
+  PC_HIP(hipEventRecord(ctx.done, s));
+  ctx.pending = true;
 }
 
 // Restricted adjoint, lanes over atoms.  A workgroup is 4 waves; each wave

@@ -280,11 +280,11 @@ struct Pfw {
         .count();
   }
 
-  void adjoint_timed(const c32* vis_sorted) {
+  void adjoint_timed(const c32* vis_sorted, const FwdSpec* fwd = nullptr) {
     PositiveMax pm(p, positive);
     if (batcher) {
       float ms = 0;
-      batcher_adjoint(batcher, p, vis_sorted, eta.ptr, s, &eta_inf, &eta_argmax, &ms);
+      batcher_adjoint(batcher, p, vis_sorted, eta.ptr, s, &eta_inf, &eta_argmax, &ms, fwd);
       adj_ms += ms;
       adj_calls++;
       if (this->ms) ms_explore_sync();
@@ -492,9 +492,19 @@ struct Pfw {
   // the iterate (S, xs): step 4 of Alg. 2, also run once for a warm start.
   void assess(int k_next) {
     load_active(S, xs);
-    op_forward(ms || (int64_t)S.size() >= 4 * grid_thr, (int64_t)S.size(), x.ptr, true, r.ptr);
+    const bool gridded = ms || (int64_t)S.size() >= 4 * grid_thr;
     double r2, vr;
-    adjoint_and_stats(r.ptr, r2, vr, k_next);
+    if (batcher && !gridded) {
+      // the residual's direct sums run in the batcher's shared launch ahead
+      // of the shared adjoint (the atom table holds x / n after load_active)
+      const FwdSpec fs{atoms.ptr, (int64_t)S.size(), V.ptr};
+      pre_ok = false;
+      adjoint_timed(r.ptr, &fs);
+      residual_stats(r2, vr);
+    } else {
+      op_forward(gridded, (int64_t)S.size(), x.ptr, true, r.ptr);
+      adjoint_and_stats(r.ptr, r2, vr, k_next);
+    }
     double l1 = 0;
     for (double w : xs) l1 += std::fabs(w);
     P = 0.5 * r2 + lam * l1;

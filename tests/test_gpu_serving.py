@@ -53,6 +53,8 @@ def test_results_alone_equal_results_in_the_mix():
     say("summary", summary, st)
     assert summary["completed"] == len(reqs)
     assert summary["peak_running"] >= 2
+    # step 4's residual forwards ran in the batcher's shared launches
+    assert st["forwards"] > 0 and st["forwards"] <= st["requests"]
     for rec in srv.records:
         ra, rm = alone[rec.rid], rec.result
         assert rm["iters"] == ra["iters"], rec.rid
