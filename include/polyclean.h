@@ -430,7 +430,7 @@ PC_API void pc_solver_destroy(pc_solver* solver);
 typedef struct pc_batcher pc_batcher;
 
 typedef struct pc_batcher_stats {
-  int64_t batches;      /* shared launch groups issued */
+  int64_t batches;      /* shared adjoint launch groups issued */
   int64_t requests;     /* adjoints served */
   int64_t visibilities; /* sum of the served plans' visibility counts */
   int32_t max_batch;    /* most requests merged into one group */
@@ -438,6 +438,9 @@ typedef struct pc_batcher_stats {
   double seconds;       /* device time of the shared adjoints (HIP events) */
   int64_t forwards;     /* residual forwards (direct sums, step 4) run in
                            shared launches ahead of the adjoints */
+  int64_t restricted_adjoints; /* restricted adjoints (point-spread sums and
+                           b of new atoms in the Gram form) run in shared
+                           launches */
 } pc_batcher_stats;
 
 /* Creates a batcher on `device` with a stream of its own (default priority).

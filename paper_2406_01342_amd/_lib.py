@@ -73,7 +73,7 @@ class PcKernelStat(C.Structure):
 class PcBatcherStats(C.Structure):
     _fields_ = [("batches", C.c_int64), ("requests", C.c_int64), ("visibilities", C.c_int64),
                 ("max_batch", C.c_int32), ("pad", C.c_int32), ("seconds", C.c_double),
-                ("forwards", C.c_int64)]
+                ("forwards", C.c_int64), ("restricted_adjoints", C.c_int64)]
 
 
 _P = C.c_void_p

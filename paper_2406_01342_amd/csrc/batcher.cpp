@@ -8,7 +8,10 @@
 // maxima, and wakes them.  Requests posted while a batch runs form the next
 // batch, so a job never waits for another job's iteration to finish, only for
 // the launches already on the device (continuous, iteration-level batching).
-// A request may carry its residual forward (r = V - Phi_S x by the direct
+// Solves in the Gram form also post the restricted adjoints of each new
+// active set (point-spread sums and b = Phi_S* V for new atoms, with FP64
+// totals): those of all requests in a batch run in one launch per kind and
+// one for their final sums.  A request may carry its residual forward (r = V - Phi_S x by the direct
 // sums, step 4 of Alg. 2): the leader then runs the residuals of all such
 // requests in one shared launch over (job, visibility block) items ahead of
 // the shared adjoint, which reads them.
@@ -29,6 +32,7 @@ struct AdjRequest {
   float* image;
   hipStream_t s;
   const FwdSpec* fwd = nullptr;  // residual to form first into vis (plan order)
+  const std::vector<AccJob>* acc = nullptr;  // a restricted-adjoint request instead
   double max_abs = 0;
   int64_t argmax = -1;
   float ms = 0;
@@ -47,6 +51,7 @@ struct pc_batcher {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   BatchCtx ctx;
   BatchCtx fctx;                       // tables of the shared residual forward
+  BatchCtx actx;                       // tables of the shared restricted adjoints
   unsigned long long* keys = nullptr;  // pinned, one per request of a batch
   size_t keys_cap = 0;
   std::vector<hipEvent_t> deps;        // per-request stream-order events
@@ -57,10 +62,13 @@ struct pc_batcher {
   bool busy = false;
   pc_batcher_stats stats{};
   int64_t nfwd_ = 0;  // residual forwards of the batch being executed (leader only)
+  int64_t nacc_ = 0;  // restricted-adjoint sums of that batch
+  int nadj_ = 0;      // adjoints of that batch
 
   ~pc_batcher() {
     ctx.release();
     fctx.release();
+    actx.release();
     for (hipEvent_t e : deps) (void)hipEventDestroy(e);
     if (keys) (void)hipHostFree(keys);
     if (e0) (void)hipEventDestroy(e0);
@@ -70,7 +78,27 @@ struct pc_batcher {
 
   // Runs one batch on the shared stream (called by the leader, without the
   // lock held).  Fills each request's result; throws on a HIP failure.
-  void execute(const std::vector<AdjRequest*>& batch, float* ms_out, int64_t* nvis_out) {
+  void execute(const std::vector<AdjRequest*>& all, float* ms_out, int64_t* nvis_out) {
+    const int nall = (int)all.size();
+    while (deps.size() < (size_t)nall) {
+      hipEvent_t e;
+      PC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      deps.push_back(e);
+    }
+    // every requester's queued work first
+    std::vector<AdjRequest*> batch;  // the adjoint requests
+    std::vector<AccJob> acc;         // the restricted-adjoint requests' sums
+    for (int j = 0; j < nall; ++j) {
+      AdjRequest* r = all[j];
+      PC_HIP(hipEventRecord(deps[j], r->s));
+      PC_HIP(hipStreamWaitEvent(stream, deps[j], 0));
+      if (r->acc)
+        acc.insert(acc.end(), r->acc->begin(), r->acc->end());
+      else
+        batch.push_back(r);
+    }
+    adjoint_acc64_batch(actx, acc, stream);
+    nacc_ = (int64_t)acc.size();
     const int n = (int)batch.size();
     if ((size_t)n > keys_cap) {
       if (keys) (void)hipHostFree(keys);
@@ -78,11 +106,6 @@ struct pc_batcher {
       keys_cap = 0;
       PC_HIP(hipHostMalloc((void**)&keys, sizeof(unsigned long long) * 2 * n));
       keys_cap = 2 * n;
-    }
-    while (deps.size() < (size_t)n) {
-      hipEvent_t e;
-      PC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      deps.push_back(e);
     }
     std::vector<pc_plan*> plans(n);
     std::vector<const c32*> vis(n);
@@ -96,32 +119,33 @@ struct pc_batcher {
       vis[j] = r->vis;
       images[j] = r->image;
       nvis += r->p->L;
-      PC_HIP(hipEventRecord(deps[j], r->s));
-      PC_HIP(hipStreamWaitEvent(stream, deps[j], 0));
       if (r->fwd)
         fwd.push_back(FwdJob{r->p->AB, r->p->Cw, r->fwd->atoms, r->fwd->base,
                              const_cast<c32*>(r->vis), r->p->L, r->fwd->natoms});
     }
     forward_residual_batch(fctx, fwd, stream);
     nfwd_ = (int64_t)fwd.size();
-    std::unique_ptr<bool[]> flags(new bool[n]);
-    for (int j = 0; j < n; ++j) flags[j] = true;
-    PC_HIP(hipEventRecord(e0, stream));
-    adjoint_grid_batch(ctx, plans.data(), vis.data(), flags.get(), images.data(), scales.data(), n,
-                       stream);
-    PC_HIP(hipEventRecord(e1, stream));
-    for (int j = 0; j < n; ++j)
-      PC_HIP(hipMemcpyAsync(keys + j, plans[j]->maxkey, sizeof(unsigned long long),
-                            hipMemcpyDeviceToHost, stream));
-    PC_HIP(hipStreamSynchronize(stream));
     float ms = 0;
-    PC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (n > 0) {
+      std::unique_ptr<bool[]> flags(new bool[n]);
+      for (int j = 0; j < n; ++j) flags[j] = true;
+      PC_HIP(hipEventRecord(e0, stream));
+      adjoint_grid_batch(ctx, plans.data(), vis.data(), flags.get(), images.data(), scales.data(),
+                         n, stream);
+      PC_HIP(hipEventRecord(e1, stream));
+      for (int j = 0; j < n; ++j)
+        PC_HIP(hipMemcpyAsync(keys + j, plans[j]->maxkey, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, stream));
+    }
+    PC_HIP(hipStreamSynchronize(stream));
+    if (n > 0) PC_HIP(hipEventElapsedTime(&ms, e0, e1));
     for (int j = 0; j < n; ++j) {
       maxkey_decode(keys[j], &batch[j]->max_abs, &batch[j]->argmax);
       batch[j]->ms = ms;
     }
     *ms_out = ms;
     *nvis_out = nvis;
+    nadj_ = n;
   }
 
   void run(AdjRequest* r) {
@@ -150,8 +174,9 @@ struct pc_batcher {
         lk.lock();
         if (st == PC_OK) {
           stats.forwards += nfwd_;
-          stats.batches += 1;
-          stats.requests += (int64_t)batch.size();
+          stats.restricted_adjoints += nacc_;
+          if (nadj_ > 0) stats.batches += 1;
+          stats.requests += nadj_;
           stats.visibilities += nvis;
           stats.max_batch = std::max(stats.max_batch, (int32_t)batch.size());
           stats.seconds += ms * 1e-3;
@@ -183,6 +208,15 @@ void batcher_adjoint(pc_batcher* b, pc_plan* p, const c32* vis_sorted, float* im
   *max_abs = r.max_abs;
   *argmax = r.argmax;
   *ms = r.ms;
+}
+
+void batcher_restricted_adjoints(pc_batcher* b, pc_plan* p, hipStream_t s,
+                                 const std::vector<AccJob>& sums) {
+  PC_REQUIRE(p->device == b->device, "plan and batcher are on different devices");
+  AdjRequest r{p, nullptr, nullptr, s};
+  r.acc = &sums;
+  b->run(&r);
+  if (r.status != PC_OK) fail(r.status, "batched restricted adjoints: " + r.error);
 }
 
 }  // namespace pc

@@ -342,6 +342,21 @@ struct FwdJob {
   int64_t natoms;
 };
 void forward_residual_batch(BatchCtx& ctx, const std::vector<FwdJob>& jobs, hipStream_t s);
+// Restricted adjoints with FP64 totals (adjoint_atoms_acc64) of several
+// coplanar FP32 plans in shared launches over (job, workgroup) and (job,
+// atom) items, each job rounding exactly as adjoint_atoms_acc64 does: out =
+// Phi_S* vis (vis in plan order, or NULL for unit visibilities, the
+// point-spread sums); partial holds adjoint_partial_count(p, natoms) doubles
+// of the job's own.  Same ctx rules as adjoint_grid_batch.
+struct AccJob {
+  const pc_plan* p;
+  const Atom<float>* atoms;
+  int64_t natoms;
+  const cpx<float>* vis;
+  double* partial;
+  double* out;
+};
+void adjoint_acc64_batch(BatchCtx& ctx, const std::vector<AccJob>& jobs, hipStream_t s);
 // Gridded adjoints of several FP32 plans in shared launches (one spread per
 // kernel width, one fold, one launch per fine-grid size for each FFT pass).
 // vis[j] is in plan order when vis_sorted[j], else in caller order.  The
@@ -368,6 +383,10 @@ struct FwdSpec {
 void batcher_adjoint(pc_batcher* b, pc_plan* p, const c32* vis_sorted, float* image,
                      hipStream_t s, double* max_abs, int64_t* argmax, float* ms,
                      const FwdSpec* fwd = nullptr);
+// The restricted adjoints `sums` (plan p, work ordered after stream s) in the
+// batcher's shared launches; returns when they are done.
+void batcher_restricted_adjoints(pc_batcher* b, pc_plan* p, hipStream_t s,
+                                 const std::vector<AccJob>& sums);
 
 // kernels_dft.hip
 template <typename R>

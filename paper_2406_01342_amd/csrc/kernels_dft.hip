@@ -268,11 +268,14 @@ __device__ __forceinline__ void wave_sync() {
 
 // With UNIT every visibility is 1 (vis is not read): the point-spread sums
 // sum_k cos 2 pi (A_k a + B_k b).
+// One workgroup's share: atom group grp, visibility chunk wg of the 4 K-long
+// chunks (shared by the single-plan and the batched launches, which then
+// round identically).
 template <typename R, typename Acc, bool UNIT, bool HW>
-__global__ __launch_bounds__(256) void adjoint_sparse_kernel(
+__device__ __forceinline__ void adjoint_sparse_body(
     int64_t L, int64_t natoms, int lgA, int64_t K, int64_t nwg, const double* __restrict__ AB,
     const double* __restrict__ Cw, const cpx<R>* __restrict__ vis, const int32_t* __restrict__ perm,
-    const Atom<R>* __restrict__ atoms, Acc* __restrict__ partial) {
+    const Atom<R>* __restrict__ atoms, Acc* __restrict__ partial, int64_t grp, int64_t wg) {
   constexpr int T = kAdjRound;
   constexpr int PER = T / 64;  // staged visibilities per lane and round
   static_assert(T % 128 == 0, "a round must hold 4 x 32 visibilities");
@@ -283,7 +286,6 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
   const int A = 1 << lgA;
   const int V = 64 >> lgA;
   const int ai = lane & (A - 1), st = lane >> lgA;
-  const int64_t grp = (int64_t)blockIdx.x / nwg, wg = (int64_t)blockIdx.x - grp * nwg;
   const int64_t p = grp * A + ai;
   const bool live = p < natoms;
   const double a = atoms[live ? p : 0].a, b = atoms[live ? p : 0].b;
@@ -344,13 +346,23 @@ __global__ __launch_bounds__(256) void adjoint_sparse_kernel(
     partial[p * nwg + wg] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
+template <typename R, typename Acc, bool UNIT, bool HW>
+__global__ __launch_bounds__(256) void adjoint_sparse_kernel(
+    int64_t L, int64_t natoms, int lgA, int64_t K, int64_t nwg, const double* __restrict__ AB,
+    const double* __restrict__ Cw, const cpx<R>* __restrict__ vis, const int32_t* __restrict__ perm,
+    const Atom<R>* __restrict__ atoms, Acc* __restrict__ partial) {
+  const int64_t grp = (int64_t)blockIdx.x / nwg, wg = (int64_t)blockIdx.x - grp * nwg;
+  adjoint_sparse_body<R, Acc, UNIT, HW>(L, natoms, lgA, K, nwg, AB, Cw, vis, perm, atoms, partial,
+                                        grp, wg);
+}
+
 // out[p] = (1/n_p) sum_c partial[p][c], FP64, one workgroup per atom.
 template <typename P, typename R>
-__global__ __launch_bounds__(256) void adjoint_sparse_reduce_kernel(
-    int64_t natoms, int64_t nwg, const P* __restrict__ partial, const Atom<R>* __restrict__ atoms,
-    double* __restrict__ out) {
+__device__ __forceinline__ void adjoint_sparse_reduce_body(int64_t nwg,
+                                                           const P* __restrict__ partial,
+                                                           const Atom<R>* __restrict__ atoms,
+                                                           double* __restrict__ out, int64_t p) {
   __shared__ double red[4];
-  const int64_t p = blockIdx.x;
   const P* row = partial + p * nwg;
   double s = 0;
   for (int64_t c = threadIdx.x; c < nwg; c += 256) s += (double)row[c];
@@ -359,6 +371,43 @@ __global__ __launch_bounds__(256) void adjoint_sparse_reduce_kernel(
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) out[p] = (((red[0] + red[1]) + red[2]) + red[3]) * atoms[p].inv_n;
+}
+
+template <typename P, typename R>
+__global__ __launch_bounds__(256) void adjoint_sparse_reduce_kernel(
+    int64_t natoms, int64_t nwg, const P* __restrict__ partial, const Atom<R>* __restrict__ atoms,
+    double* __restrict__ out) {
+  adjoint_sparse_reduce_body<P, R>(nwg, partial, atoms, out, (int64_t)blockIdx.x);
+}
+
+// Restricted adjoints with FP64 totals of several coplanar FP32 plans in one
+// launch per kind (unit visibilities or not), then one launch for all their
+// final sums: items = (job, workgroup) and (job, atom).
+struct AccJobDev {
+  const double* AB;
+  const cpx<float>* vis;
+  const Atom<float>* atoms;
+  double* partial;
+  double* out;
+  int64_t L, natoms, K, nwg;
+  int lgA, pad;
+};
+
+template <bool UNIT>
+__global__ __launch_bounds__(256) void adjoint_acc64_batch_kernel(const AccJobDev* __restrict__ jobs,
+                                                                  const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const AccJobDev& J = jobs[it.x];
+  const int64_t grp = (int64_t)it.y / J.nwg, wg = (int64_t)it.y - grp * J.nwg;
+  adjoint_sparse_body<float, double, UNIT, false>(J.L, J.natoms, J.lgA, J.K, J.nwg, J.AB, nullptr,
+                                                  J.vis, nullptr, J.atoms, J.partial, grp, wg);
+}
+
+__global__ __launch_bounds__(256) void adjoint_reduce_batch_kernel(const AccJobDev* __restrict__ jobs,
+                                                                   const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const AccJobDev& J = jobs[it.x];
+  adjoint_sparse_reduce_body<double, float>(J.nwg, J.partial, J.atoms, J.out, (int64_t)it.y);
 }
 
 // One APGD step on the restricted problem fused with the restricted
@@ -846,6 +895,68 @@ void adjoint_sparse(pc_plan* p, const cpx<R>* vis, bool vis_sorted, int64_t nato
   prep_atoms_into<R>(p, natoms, pix, (const R*)nullptr, atoms, s);
   double* partial = ensure_red_scratch(p, (size_t)adjoint_partial_count(p, natoms));
   adjoint_atoms<R>(p, vis, vis_sorted, natoms, atoms, partial, out, s);
+}
+
+void adjoint_acc64_batch(BatchCtx& ctx, const std::vector<AccJob>& jobs, hipStream_t s) {
+  std::vector<AccJobDev> dj;
+  std::vector<int2> unit_items, vis_items, red_items;
+  for (const AccJob& a : jobs) {
+    if (a.natoms <= 0) continue;
+    PC_REQUIRE(a.p->precision == PC_PREC_FP32 && !a.p->Cw,
+               "batched restricted adjoints need coplanar FP32 plans");
+    const AdjShape sh = adjoint_shape(a.p->L, a.natoms);
+    const int j = (int)dj.size();
+    dj.push_back(AccJobDev{a.p->AB, a.vis, a.atoms, a.partial, a.out, a.p->L, a.natoms, sh.K,
+                           sh.nwg, sh.lgA, 0});
+    std::vector<int2>& dst = a.vis ? vis_items : unit_items;
+    for (int64_t b = 0; b < sh.ngroups * sh.nwg; ++b) dst.push_back(make_int2(j, (int)b));
+    for (int64_t q = 0; q < a.natoms; ++q) red_items.push_back(make_int2(j, (int)q));
+  }
+  if (dj.empty()) return;
+  if (!ctx.done) PC_HIP(hipEventCreateWithFlags(&ctx.done, hipEventDisableTiming));
+  if (ctx.pending) PC_HIP(hipEventSynchronize(ctx.done));
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_unit = up(dj.size() * sizeof(AccJobDev));
+  const size_t o_vis = o_unit + up(unit_items.size() * sizeof(int2));
+  const size_t o_red = o_vis + up(vis_items.size() * sizeof(int2));
+  const size_t bytes = o_red + red_items.size() * sizeof(int2);
+  if (ctx.host_bytes < bytes) {
+    if (ctx.host) (void)hipHostFree(ctx.host);
+    ctx.host = nullptr;
+    ctx.host_bytes = 0;
+    PC_HIP(hipHostMalloc((void**)&ctx.host, bytes * 2));
+    ctx.host_bytes = bytes * 2;
+  }
+  if (ctx.dev_bytes < bytes) {
+    if (ctx.dev) (void)hipFree(ctx.dev);
+    ctx.dev = nullptr;
+    ctx.dev_bytes = 0;
+    PC_HIP(hipMalloc((void**)&ctx.dev, bytes * 2));
+    ctx.dev_bytes = bytes * 2;
+  }
+  std::memcpy(ctx.host, dj.data(), dj.size() * sizeof(AccJobDev));
+  if (!unit_items.empty())
+    std::memcpy(ctx.host + o_unit, unit_items.data(), unit_items.size() * sizeof(int2));
+  if (!vis_items.empty())
+    std::memcpy(ctx.host + o_vis, vis_items.data(), vis_items.size() * sizeof(int2));
+  std::memcpy(ctx.host + o_red, red_items.data(), red_items.size() * sizeof(int2));
+  PC_HIP(hipMemcpyAsync(ctx.dev, ctx.host, bytes, hipMemcpyHostToDevice, s));
+  const AccJobDev* d = (const AccJobDev*)ctx.dev;
+  if (!unit_items.empty()) {
+    hipLaunchKernelGGL((adjoint_acc64_batch_kernel<true>), dim3((unsigned)unit_items.size()),
+                       dim3(256), 0, s, d, (const int2*)(ctx.dev + o_unit));
+    PC_LAUNCH_CHECK("psf_sums_acc64_batch");
+  }
+  if (!vis_items.empty()) {
+    hipLaunchKernelGGL((adjoint_acc64_batch_kernel<false>), dim3((unsigned)vis_items.size()),
+                       dim3(256), 0, s, d, (const int2*)(ctx.dev + o_vis));
+    PC_LAUNCH_CHECK("adjoint_sparse_acc64_batch");
+  }
+  hipLaunchKernelGGL(adjoint_reduce_batch_kernel, dim3((unsigned)red_items.size()), dim3(256), 0,
+                     s, d, (const int2*)(ctx.dev + o_red));
+  PC_LAUNCH_CHECK("adjoint_reduce_batch");
+  PC_HIP(hipEventRecord(ctx.done, s));
+  ctx.pending = true;
 }
 
 template void forward_sparse<float>(pc_plan*, int64_t, const int32_t*, const float*, const c32*,

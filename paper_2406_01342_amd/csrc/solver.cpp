@@ -220,6 +220,7 @@ struct Pfw {
   bool pre_ok = false;
   DevArray<double> act_blk;  // uploaded [x | pix] of the active set
   DevArray<Atom<float>> off_atoms;
+  DevArray<double> b_partial;  // partials of b's sums when batched beside the psf sums
   double v2 = 0;  // ||V||^2
   Pinned up, up_act, down;  // upload staging (Gram form, active set), small readbacks
   std::vector<int32_t> S;
@@ -652,12 +653,24 @@ struct Pfw {
       psf_dev.ensure(n_psf + nm, s);
       b_dev.ensure(n_b + nb, s);
       psf_partial.ensure(std::max(adjoint_partial_count(p, nm), adjoint_partial_count(p, nb)));
-      if (nm)  // unit visibilities (none are read): the point-spread sums
-        adjoint_atoms_acc64(p, nullptr, nm, off_atoms.ptr, psf_partial.ptr, psf_dev.ptr + n_psf,
-                            s);
-      if (nb)
-        adjoint_atoms_acc64(p, V.ptr, nb, off_atoms.ptr + nm, psf_partial.ptr, b_dev.ptr + n_b,
-                            s);
+      if (batcher) {  // in the batcher's shared launches (each sum its own partials)
+        b_partial.ensure(adjoint_partial_count(p, nb));
+        std::vector<AccJob> sums;
+        if (nm)
+          sums.push_back(AccJob{p, off_atoms.ptr, nm, nullptr, psf_partial.ptr,
+                                psf_dev.ptr + n_psf});
+        if (nb)
+          sums.push_back(AccJob{p, off_atoms.ptr + nm, nb, V.ptr, b_partial.ptr,
+                                b_dev.ptr + n_b});
+        batcher_restricted_adjoints(batcher, p, s, sums);
+      } else {
+        if (nm)  // unit visibilities (none are read): the point-spread sums
+          adjoint_atoms_acc64(p, nullptr, nm, off_atoms.ptr, psf_partial.ptr,
+                              psf_dev.ptr + n_psf, s);
+        if (nb)
+          adjoint_atoms_acc64(p, V.ptr, nb, off_atoms.ptr + nm, psf_partial.ptr,
+                              b_dev.ptr + n_b, s);
+      }
       n_psf += nm;
       n_b += nb;
     }

@@ -53,8 +53,10 @@ def test_results_alone_equal_results_in_the_mix():
     say("summary", summary, st)
     assert summary["completed"] == len(reqs)
     assert summary["peak_running"] >= 2
-    # step 4's residual forwards ran in the batcher's shared launches
+    # step 4's residual forwards and the Gram form's restricted adjoints ran
+    # in the batcher's shared launches
     assert st["forwards"] > 0 and st["forwards"] <= st["requests"]
+    assert st["restricted_adjoints"] > 0
     for rec in srv.records:
         ra, rm = alone[rec.rid], rec.result
         assert rm["iters"] == ra["iters"], rec.rid
@@ -252,3 +254,53 @@ def test_footprint_covers_the_device_memory_of_a_job():
     say("footprint estimate", est, "peak device bytes", used, "atoms", res["natoms"])
     assert res["natoms"] > 4  # the gridded operators were used
     assert used <= est
+
+
+@pytest.mark.slow
+def test_memory_pressure_mix_admission_and_results():
+    """Scaled memory-pressure mix: one large job (8192^2, 8,372,224
+    visibilities) and six small ones (512^2, 50,400), each with its
+    certificate, under a budget of the large footprint plus three small ones:
+    every job completes within the budget, small jobs finish while the large
+    one runs (not queued behind it), and each result equals its plain
+    one-at-a-time solve.  The large job's visibilities are its seeded noise
+    draw alone (its exact forward would take minutes on the host); the small
+    jobs' come from the oracle's forward of their skies plus noise."""
+    api()
+    import torch
+    import sim
+    from paper_2406_01342_amd import serving
+    say("memory-pressure mix")
+    reqs = []
+    big = sim.config_c5_large(job_id=0)
+    reqs.append(serving.ImagingRequest(0, 0.0, big.uv, big.npix, big.fov_rad,
+                                       big.noise.astype(np.complex64),
+                                       dict(alpha=big.alpha, delta=big.delta, max_iter=8),
+                                       want_certificate=True))
+    for k in range(1, 7):
+        p = sim.config_c5_small(job_id=k)
+        v = sim.add_noise(operator.forward(p.uv, p.npix, p.fov_rad, p.sky_pix, p.sky_amp),
+                          p.noise, p.psnr_db).astype(np.complex64)
+        reqs.append(serving.ImagingRequest(k, 0.0, p.uv, p.npix, p.fov_rad, v,
+                                           dict(alpha=p.alpha, delta=p.delta, max_iter=p.max_iter,
+                                                rel_obj_tol=p.rel_obj_tol),
+                                           want_certificate=True))
+    be = serving.DeviceBackend(batched=True)
+    fps = [be.footprint(r) for r in reqs]
+    budget = fps[0] + 3 * max(fps[1:])
+    alone = [be.solve_plain(r) for r in reqs]
+    srv = serving.Server(be, slots=8, hbm_budget=budget)
+    summary = srv.run(reqs)
+    say("footprints", fps[:2], "budget", budget, "summary", summary)
+    assert summary["completed"] == len(reqs)
+    assert summary["peak_bytes"] <= budget
+    assert summary["peak_running"] <= 4
+    recs = {r.rid: r for r in srv.records}
+    assert min(recs[k].finished_s for k in range(1, 7)) < recs[0].finished_s
+    for rid, rec in recs.items():
+        ra, rm = alone[rid], rec.result
+        np.testing.assert_array_equal(rm["pix"], ra["pix"])
+        assert abs(rm["objective"] - ra["objective"]) <= 1e-6 * ra["objective"]
+        ca, cm = ra["certificate"], rm["certificate"]
+        assert torch.allclose(cm, ca, rtol=1e-5, atol=1e-6 * float(ca.abs().max()))
+    be.close_backend()
