@@ -559,7 +559,10 @@ struct Pfw {
   // solve come from a restricted adjoint of unit visibilities at the offsets,
   // b_p for atoms not seen before from a restricted adjoint of V (both with
   // FP64 totals: the gap test forms ||V - Phi_S y||^2 = ||V||^2 - 2 y.b +
-  // y.G y, which cancels); G is assembled on the host and uploaded with b.
+  // y.G y, which cancels), written into per-solve device tables by slot (in
+  // the batcher's shared launches when the solve has one).  The host keeps
+  // only the slot of each offset and pixel and uploads the slot table with the
+  // Lanczos start vector; G, b and that vector are gathered on the device.
   // Returns false (and changes nothing) when the new point-spread sums would
   // cost more than kGramNewPairs operator applications on this set: the
   // operator path is then cheaper for this FW iteration.
