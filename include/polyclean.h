@@ -20,8 +20,9 @@
  * pc_adjoint_sparse, pc_restricted_gradient*) add the w phase in FP64; the
  * gridded adjoint (pc_adjoint_grid, pc_dual_certificate, the solve's
  * exploration) is w-stacked: planes w_j = w0 + j dw, dw = 1 / (2 |c_min|)
- * (c_min = n - 1 at the image corner), ceil((w_max - w_min) / dw) + W + 1
- * planes, each one spread and two FFT passes, so its cost is that many
+ * (c_min = n - 1 at the image corner), ceil((max |w| - min |w|) / dw) + W + 1
+ * planes (a visibility with w < 0 is gridded as its conjugate at (-u, -v,
+ * -w)), each one spread and two FFT passes, so its cost is that many
  * coplanar adjoints.  FP32 plans only; pc_forward_grid, the FP64 twin and
  * the synthesis dictionary need coplanar plans (PC_ERR_UNSUPPORTED).
  *

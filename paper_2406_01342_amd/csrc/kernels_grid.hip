@@ -1058,7 +1058,8 @@ __global__ __launch_bounds__(NT) void passB_adj_w_kernel(GridGeom g, const cpx<R
 
 // Visibility weights of w-plane w_j (plan order): h_k exp(2 pi i w_k c_mid)
 // psi((w_k - w_j) / dw) within the kernel's reach |w_k - w_j| <= (W/2) dw,
-// zero beyond it.  perm: NULL when h is in plan order.
+// zero beyond it; a visibility with w_k < 0 enters as its conjugate at -w_k
+// (the plan grids it at (-u, -v)).  perm: NULL when h is in plan order.
 __global__ __launch_bounds__(256) void wplane_kernel(int64_t L, const double* __restrict__ Cw,
                                                      const cpx<float>* __restrict__ h,
                                                      const int32_t* __restrict__ perm, double wj,
@@ -1067,11 +1068,12 @@ __global__ __launch_bounds__(256) void wplane_kernel(int64_t L, const double* __
                                                      cpx<float>* __restrict__ out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= L) return;
-  const double wk = Cw[k];
+  const double wk = fabs(Cw[k]);
   const float t = (float)((wk - wj) * inv_dw);
   cpx<float> o{0.f, 0.f};
   if (t * t <= R2) {
-    const cpx<float> v = h[perm ? perm[k] : k];
+    cpx<float> v = h[perm ? perm[k] : k];
+    if (Cw[k] < 0.0) v.y = -v.y;
     double ph = wk * cmid;
     ph -= rint(ph);
     const float sn = __builtin_amdgcn_sinf((float)ph), cs = __builtin_amdgcn_cosf((float)ph);

@@ -244,8 +244,8 @@ static bool has_w(const pc_geometry* g) {
 
 // Planes of the w-stacked adjoint.  The direction factor c = n - 1 spans
 // [c_min, 0], c_min at the image corner (a = b = -n/2); planes are dw =
-// 1 / (4 half) apart (half = -c_min / 2) and cover [w_min, w_max] with W / 2
-// planes of margin on each side, centred on the w range.
+// 1 / (4 half) apart (half = -c_min / 2) and cover [w_min, w_max] (of |w|)
+// with W / 2 planes of margin on each side, centred on the range.
 static WStack w_planes(const GridGeom& g, double wmin, double wmax) {
   WStack ws;
   const double lmax = (g.n / 2) * g.dl;
@@ -289,8 +289,14 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     const double a = geo->u[k] * scale * dl, b = geo->v[k] * scale * dl;
     A[k] = a;
     B[k] = b;
-    const double xu = M * (a + 0.5 - std::floor(a + 0.5));
-    const double xv = M * (b + 0.5 - std::floor(b + 0.5));
+    // The gridded adjoint takes Re(h e^{+j2pi(ul + vm + wc)}) = Re(h* e^{+j2pi(-ul - vm - wc)}):
+    // a visibility with w < 0 is gridded as its conjugate at (-u, -v, -w), so
+    // that the w-planes need only cover [min |w|, max |w|].  The direct sums
+    // keep (A, B) as given.
+    const bool flip = with_w && geo->w[k] < 0;
+    const double ga = flip ? -a : a, gb = flip ? -b : b;
+    const double xu = M * (ga + 0.5 - std::floor(ga + 0.5));
+    const double xv = M * (gb + 0.5 - std::floor(gb + 0.5));
     const double mu = std::ceil(xu - 0.5 * W), mv = std::ceil(xv - 0.5 * W);
     c0u[k] = (int32_t)mu;
     c0v[k] = (int32_t)mv;
@@ -376,9 +382,9 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
   }
   if (with_w) {
     double wmin = INFINITY, wmax = -INFINITY;
-    for (int64_t k = 0; k < L; ++k) {
-      wmin = std::min(wmin, geo->w[k] * scale);
-      wmax = std::max(wmax, geo->w[k] * scale);
+    for (int64_t k = 0; k < L; ++k) {  // |w|: negative w is gridded conjugated
+      wmin = std::min(wmin, std::fabs(geo->w[k] * scale));
+      wmax = std::max(wmax, std::fabs(geo->w[k] * scale));
     }
     lay.ws = w_planes(g, wmin, wmax);
     if (full) {

@@ -83,10 +83,11 @@ def test_adjoint_grid_w_whole_image():
     want = operator.adjoint(p.uv, p.npix, p.fov_rad, vis.astype(np.complex128))
     err = rel_l2(img, want)
     # plane geometry as documented: dw = 1 / (2 |c_min|), c_min = n - 1 at the
-    # image corner, ceil((w_max - w_min) / dw) + W + 1 planes
+    # image corner, ceil((max |w| - min |w|) / dw) + W + 1 planes (negative w
+    # is gridded conjugated)
     lmax = (p.npix // 2) * p.fov_rad / p.npix
     dw = 1.0 / (2.0 * abs(float(operator.n_minus_one(lmax, lmax))))
-    w = p.uv[:, 2]
+    w = np.abs(p.uv[:, 2])
     info = plan.info
     assert abs(info["w_step"] - dw) <= 1e-9 * dw
     assert info["w_planes"] == int(np.ceil((w.max() - w.min()) / dw)) + info["kernel_width"] + 1
