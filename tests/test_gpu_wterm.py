@@ -195,3 +195,47 @@ def test_w_unsupported_paths_fail_loudly():
     img, _, _ = a.pc_adjoint_grid(flat, to_dev(vis2))
     x = torch.zeros((p2.npix, p2.npix), dtype=torch.float32, device="cuda")
     a.pc_forward_grid(flat, x)
+
+
+@pytest.mark.parametrize("case", ["single", "all_negative", "constant", "partial_band"])
+def test_adjoint_grid_w_edge_cases(case):
+    """Edge cases of the w-stacked adjoint against the oracle's whole image:
+    one visibility on the smallest grid, every w negative (all conjugated),
+    one common nonzero w (W + 1 planes), and a random ragged set confined to a
+    sub-band of the fine grid (no wrap)."""
+    say("adjoint_grid with w, edge case", case)
+    a = api()
+    rng = np.random.default_rng(21)
+    if case == "single":
+        n, fov = 16, 0.3
+        uvw = np.array([[3.7, -12.25, -40.0]])
+    elif case == "all_negative":
+        n, fov, L = 64, 0.4, 1501
+        d = fov / n
+        uvw = np.column_stack([rng.uniform(-0.45 / d, 0.45 / d, size=(L, 2)),
+                               -rng.uniform(5.0, 60.0, size=L)])
+    elif case == "constant":
+        n, fov, L = 64, 0.4, 777
+        d = fov / n
+        uvw = np.column_stack([rng.uniform(-0.45 / d, 0.45 / d, size=(L, 2)), np.full(L, 37.5)])
+    else:
+        n, fov, L = 128, 0.1, 2003
+        d = fov / n
+        uv = rng.normal(0.0, 0.06 / d, size=(L, 2)).clip(-0.2 / d, 0.2 / d)
+        uvw = np.column_stack([uv, rng.normal(0.0, 300.0, size=L)])
+    L = uvw.shape[0]
+    h = (rng.normal(size=L) + 1j * rng.normal(size=L)).astype(np.complex64)
+    plan = a.pc_plan_create(uvw[:, :2], n, fov, w=uvw[:, 2])
+    info = plan.info
+    assert info["w_planes"] > 0
+    if case == "constant":
+        assert info["w_planes"] == info["kernel_width"] + 1
+    if case == "partial_band":
+        assert info["wraps"] == 0 and info["band_nu"] < info["fine"]
+    img, mx, am = a.pc_adjoint_grid(plan, to_dev(h))
+    img = img.cpu().numpy().astype(np.float64)
+    want = operator.adjoint(uvw, n, fov, h.astype(np.complex128))
+    err = rel_l2(img, want)
+    say(case, "planes", info["w_planes"], "rel L2", err)
+    assert err <= TOL
+    assert am == solver.argmax_abs(want)[1]
