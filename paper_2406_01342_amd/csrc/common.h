@@ -72,11 +72,13 @@ __host__ __device__ constexpr int spread_block(int W) { return spread_span(W) - 
 // visibilities that reach it from the tile itself and from its left, upper
 // and upper-left neighbours.  slot >= 0 means the tile is split across
 // several items and this item writes partial tile `slot`.  FP32 plans with
-// kernel widths up to 8 group items in fours, one workgroup of four waves per
-// group: either four independent items (combine = 0; tile = -1 marks an empty
-// one), or four shares of one tile's visibilities (combine = 1, same tile and
-// slot) whose four LDS tiles the workgroup adds in a fixed order before the
-// single write.
+// kernel widths up to 8 group items by kSpreadQuad, one workgroup of that many
+// waves per group: either independent items (combine = 0; tile = -1 marks an
+// empty one), or shares of one tile's visibilities (combine = 1, same tile and
+// slot) whose LDS tiles the workgroup adds in a fixed order before the single
+// write.  Two waves per workgroup (31 KB of LDS) let five workgroups share a
+// compute unit, ten waves against the eight that four-wave groups (62 KB)
+// allow.
 struct SpreadChunk {
   int32_t tile;
   int32_t slot;
@@ -85,7 +87,7 @@ struct SpreadChunk {
   int32_t combine;
   int32_t pad;
 };
-constexpr int kSpreadQuad = 4;  // waves (items) per workgroup of the grouped spread
+constexpr int kSpreadQuad = 2;  // waves (items) per workgroup of the grouped spread
 
 // A split ("hot") tile: its partial tiles occupy slots [first, first+count).
 struct FoldItem {
@@ -199,7 +201,7 @@ struct pc_plan {
   int64_t L = 0;
   pc::GridGeom g{};
   int64_t n_chunks = 0, n_partials = 0, n_fold = 0;
-  bool spread_quads = false;  // work items grouped in fours (FP32, kernel width <= 8)
+  bool spread_quads = false;  // work items grouped by workgroup (FP32, kernel width <= 8)
   size_t footprint = 0;
 
   // Per-visibility data in plan (tile-sorted) order.

@@ -560,10 +560,10 @@ __device__ __forceinline__ cpx<float>* spread_dst(const GridGeom& g, const Sprea
   return partials + (size_t)ch.slot * kTile * kTile;
 }
 
-// A workgroup of four waves over four work items (see SpreadChunk): each
-// wave accumulates its item into its own LDS tile; independent items are
-// written by their own wave, the four shares of a combined tile are added
-// in wave order and written once by the whole workgroup.
+// A workgroup of kSpreadQuad waves over as many work items (see
+// SpreadChunk): each wave accumulates its item into its own LDS tile;
+// independent items are written by their own wave, the shares of a combined
+// tile are added in wave order and written once by the whole workgroup.
 template <int W>
 __device__ __forceinline__ void spread_quad_body(
     const GridGeom& g, const SpreadChunk* __restrict__ quad, const uint32_t* __restrict__ cell,

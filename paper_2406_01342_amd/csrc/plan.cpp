@@ -194,7 +194,7 @@ struct Layout {
   std::vector<FoldItem> fold;
   std::vector<uint8_t> tile_flags;      // 1 if any footprint reaches the tile
   int64_t n_partials = 0;
-  bool quads = false;                   // chunks grouped in fours (see SpreadChunk)
+  bool quads = false;                   // chunks grouped by workgroup (see SpreadChunk)
   std::vector<int32_t> group_work;      // per workgroup: its longest item's visibilities
 };
 
@@ -475,15 +475,16 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     }
   lay.quads = geo->precision == PC_PREC_FP32 && W <= 8;
   if (lay.quads) {
-    // Grouped spread: workgroups of four waves.  A tile with at most kq
-    // visibilities is one wave's item, packed four to a workgroup with items
-    // of similar length; a heavier tile is cut into chunks of at most 4 kq,
-    // each shared by the four waves of one workgroup (combine), which write
+    // Grouped spread: workgroups of G = kSpreadQuad waves.  A tile with at
+    // most kq visibilities is one wave's item, packed G to a workgroup with
+    // items of similar length; a heavier tile is cut into chunks of at most
+    // 4 kq, each shared by the G waves of one workgroup (combine), which write
     // the tile itself when one chunk covers it and a partial tile otherwise.
-    // kq, the visibilities per wave, is the largest of 1024, 512, ..., 64 that
-    // still gives at least three rounds of the 512 workgroups resident at once
-    // (two per compute unit), so that the longest work stays short against
-    // the whole launch while the partial tiles to fold stay few.
+    // kq is the largest of 1024, 512, ..., 64 that still gives at least 1536
+    // workgroups, so that the longest work stays short against the whole
+    // launch while the partial tiles to fold stay few.
+    constexpr int G = kSpreadQuad;
+    const int64_t min_groups = 1536;
     auto groups_for = [&](int64_t kq) {
       int64_t light = 0, heavy = 0;
       for (int64_t t = 0; t < ntiles; ++t) {
@@ -493,17 +494,17 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
         else
           heavy += (totals[t] + 4 * kq - 1) / (4 * kq);
       }
-      return heavy + (light + 3) / 4;
+      return heavy + (light + G - 1) / G;
     };
     int64_t kq = 64;
     for (int64_t c = 1024; c >= 64; c /= 2)
-      if (groups_for(c) >= 1536) {
+      if (groups_for(c) >= min_groups) {
         kq = c;
         break;
       }
     struct Group {
       int64_t work;
-      SpreadChunk c[4];
+      SpreadChunk c[G];
     };
     std::vector<Group> groups;
     std::vector<SpreadChunk> light;
@@ -530,12 +531,12 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
           const int64_t q0 = total * c / nch, q1 = total * (c + 1) / nch;
           Group gr{};
           gr.work = 0;
-          for (int w = 0; w < 4; ++w) {
+          for (int w = 0; w < G; ++w) {
             SpreadChunk& ch = gr.c[w];
             ch.tile = (int32_t)t;
             ch.slot = nch > 1 ? (int32_t)(lay.n_partials + c) : -1;
             ch.combine = 1;
-            sub_ranges(rb, re, q0 + (q1 - q0) * w / 4, q0 + (q1 - q0) * (w + 1) / 4, ch);
+            sub_ranges(rb, re, q0 + (q1 - q0) * w / G, q0 + (q1 - q0) * (w + 1) / G, ch);
             gr.work = std::max(gr.work, work(ch));
           }
           groups.push_back(gr);
@@ -545,10 +546,10 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     std::stable_sort(light.begin(), light.end(), [&](const SpreadChunk& a, const SpreadChunk& b) {
       return work(a) > work(b);
     });
-    for (size_t i = 0; i < light.size(); i += 4) {
+    for (size_t i = 0; i < light.size(); i += G) {
       Group gr{};
       gr.work = work(light[i]);
-      for (int w = 0; w < 4; ++w) {
+      for (int w = 0; w < G; ++w) {
         if (i + w < light.size()) {
           gr.c[w] = light[i + w];
         } else {
@@ -565,7 +566,7 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
     std::stable_sort(groups.begin(), groups.end(),
                      [](const Group& a, const Group& b) { return a.work > b.work; });
     for (const Group& gr : groups) {
-      for (int w = 0; w < 4; ++w) lay.chunks.push_back(gr.c[w]);
+      for (int w = 0; w < G; ++w) lay.chunks.push_back(gr.c[w]);
       lay.group_work.push_back((int32_t)gr.work);
     }
     return lay;
