@@ -209,6 +209,24 @@ PC_API pc_status pc_forward_sparse(pc_plan* plan, int64_t natoms, const int32_t*
  * interpolation.  image dev float [npix*npix]; vis_out as above. */
 PC_API pc_status pc_forward_grid(pc_plan* plan, const float* image, void* vis_out, void* stream);
 
+/* Row-restricted gridded operators, the gridded form of the restricted
+ * operators Phi_S and Phi_S* of the APGD step (Alg. 2 step 2; Sect. 5.2) for
+ * an active set S whose atoms lie on the image rows a mask selects: only the
+ * transforms of those rows run (their cost scales with the number of rows).
+ * row_mask  host uint32 [ceil(npix/32)], bit i % 32 of word i / 32 set for
+ *           image row i (pixel index i npix + j); bits past npix must be
+ *           clear (-1).  Copied into the plan before the call returns.
+ * pc_forward_grid_rows: pc_forward_grid of an image whose rows with a clear
+ *   bit are zero (they are not read); the result equals pc_forward_grid's.
+ * pc_adjoint_grid_rows: the rows of Phi* vis with a set bit, equal to those
+ *   of pc_adjoint_grid's image; the other rows of image are left unchanged,
+ *   and no maximum is formed.  An empty mask does nothing.  Coplanar plans
+ *   only (-5 for a non-coplanar plan). */
+PC_API pc_status pc_forward_grid_rows(pc_plan* plan, const float* image, const uint32_t* row_mask,
+                                      void* vis_out, void* stream);
+PC_API pc_status pc_adjoint_grid_rows(pc_plan* plan, const void* vis, const uint32_t* row_mask,
+                                      float* image, void* stream);
+
 /* Restricted adjoint Phi_S* (Eq. adjoint-phi at the pixels of S only), by
  * direct summation: out[p] = Re sum_k vis_k exp(+j2pi(u_k l_p + v_k m_p)) / n_p.
  * vis dev complex64 [nvis] caller order; pix dev int32 [natoms];

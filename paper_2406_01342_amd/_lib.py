@@ -92,6 +92,8 @@ SIGNATURES = {
     "pc_adjoint_grid": (C.c_int, [_P, _P, _P, _PD, _PI64, _P]),
     "pc_forward_sparse": (C.c_int, [_P, _I64, _P, _P, _P, _P]),
     "pc_forward_grid": (C.c_int, [_P, _P, _P, _P]),
+    "pc_forward_grid_rows": (C.c_int, [_P, _P, _P, _P, _P]),
+    "pc_adjoint_grid_rows": (C.c_int, [_P, _P, _P, _P, _P]),
     "pc_adjoint_sparse": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
     "pc_dual_certificate": (C.c_int, [_P, _P, _I64, _P, _P, C.c_double, _P, _PD, _PI64, _P]),
     "pc_restricted_gradient": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P]),

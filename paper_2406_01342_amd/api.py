@@ -205,6 +205,54 @@ def pc_forward_sparse_f64(plan: Plan, pix: torch.Tensor, weight: torch.Tensor,
     return out
 
 
+def row_mask(npix: int, rows) -> np.ndarray:
+    """Host row mask (uint32 words, bit i % 32 of word i / 32 for row i) of
+    the image rows ``rows``."""
+    m = np.zeros((npix + 31) // 32, np.uint32)
+    r = np.asarray(rows, dtype=np.int64).reshape(-1)
+    if r.size and (r.min() < 0 or r.max() >= npix):
+        raise ValueError("row index out of range")
+    np.bitwise_or.at(m, r // 32, (np.uint32(1) << (r % 32).astype(np.uint32)))
+    return m
+
+
+def _mask(plan: Plan, mask) -> np.ndarray:
+    m = np.ascontiguousarray(mask, dtype=np.uint32)
+    if m.shape != ((plan.npix + 31) // 32,):
+        raise ValueError(f"row mask must hold {(plan.npix + 31) // 32} uint32 words")
+    return m
+
+
+def pc_forward_grid_rows(plan: Plan, image: torch.Tensor, mask, out: Optional[torch.Tensor] = None,
+                         stream=None) -> torch.Tensor:
+    """pc_forward_grid of an image that is zero outside the rows of ``mask``
+    (see row_mask)."""
+    n = plan.npix
+    m = _mask(plan, mask)
+    if out is None:
+        out = _new(plan, (plan.nvis,), torch.complex64)
+    check(LIB.pc_forward_grid_rows(plan.handle,
+                                   C.c_void_p(_dev(image, torch.float32, n * n, "image")),
+                                   m.ctypes.data_as(C.c_void_p),
+                                   C.c_void_p(_dev(out, torch.complex64, plan.nvis, "out")),
+                                   C.c_void_p(_stream(stream))), "pc_forward_grid_rows")
+    return out
+
+
+def pc_adjoint_grid_rows(plan: Plan, vis: torch.Tensor, mask, image: torch.Tensor,
+                         stream=None) -> torch.Tensor:
+    """The rows of Phi* vis that ``mask`` selects, written into ``image``
+    (the other rows are left as they are)."""
+    n = plan.npix
+    m = _mask(plan, mask)
+    check(LIB.pc_adjoint_grid_rows(plan.handle,
+                                   C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")),
+                                   m.ctypes.data_as(C.c_void_p),
+                                   C.c_void_p(_dev(image, torch.float32, n * n, "image")),
+                                   C.c_void_p(_stream(stream))), "pc_adjoint_grid_rows")
+    return image
+
+
 def pc_forward_grid(plan: Plan, image: torch.Tensor, out: Optional[torch.Tensor] = None,
                     stream=None) -> torch.Tensor:
     n = plan.npix

@@ -295,6 +295,51 @@ pc_status pc_forward_grid(pc_plan* p, const float* image, void* vis_out, void* s
   });
 }
 
+// Copies a caller's host row mask into the plan (on the stream) and counts
+// its rows; bits past npix must be clear.
+static RowMask upload_rows(pc_plan* p, const uint32_t* row_mask, hipStream_t s) {
+  PC_REQUIRE(row_mask != nullptr, "row_mask is NULL");
+  const int n = p->g.n, words = (n + 31) / 32;
+  int64_t count = 0;
+  for (int w = 0; w < words; ++w) {
+    const uint32_t m = row_mask[w];
+    if (w == words - 1 && n % 32) PC_REQUIRE((m >> (n % 32)) == 0, "row_mask has bits past npix");
+    count += __builtin_popcount(m);
+  }
+  PC_HIP(hipMemcpyAsync(p->rowmask, row_mask, (size_t)words * 4, hipMemcpyHostToDevice, s));
+  PC_HIP(hipStreamSynchronize(s));  // the caller's array may go away on return
+  return RowMask{p->rowmask, count};
+}
+
+pc_status pc_forward_grid_rows(pc_plan* p, const float* image, const uint32_t* row_mask,
+                               void* vis_out, void* stream) {
+  return guard("pc_forward_grid_rows", [&] {
+    check_plan(p, PC_PREC_FP32);
+    PC_REQUIRE(image != nullptr && vis_out != nullptr, "image and vis_out must not be NULL");
+    set_device(p);
+    Touch touch(p, stream);
+    hipStream_t s = (hipStream_t)stream;
+    const RowMask rows = upload_rows(p, row_mask, s);
+    forward_grid<float>(p, image, (c32*)vis_out, false, s, rows.count ? &rows : nullptr);
+    return PC_OK;
+  });
+}
+
+pc_status pc_adjoint_grid_rows(pc_plan* p, const void* vis, const uint32_t* row_mask,
+                               float* image, void* stream) {
+  return guard("pc_adjoint_grid_rows", [&] {
+    check_plan(p, PC_PREC_FP32);
+    PC_REQUIRE(vis != nullptr && image != nullptr, "vis and image must not be NULL");
+    if (p->Cw) fail(PC_ERR_UNSUPPORTED, "row-restricted adjoint of a non-coplanar plan");
+    set_device(p);
+    Touch touch(p, stream);
+    hipStream_t s = (hipStream_t)stream;
+    const RowMask rows = upload_rows(p, row_mask, s);
+    if (rows.count) adjoint_grid<float>(p, (const c32*)vis, false, image, 1.0f, s, &rows);
+    return PC_OK;
+  });
+}
+
 pc_status pc_adjoint_sparse(pc_plan* p, const void* vis, int64_t natoms, const int32_t* pix,
                             double* out, void* stream) {
   return guard("pc_adjoint_sparse", [&] {

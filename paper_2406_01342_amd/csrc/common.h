@@ -223,6 +223,7 @@ struct pc_plan {
   void* corr = nullptr;         // real [n]: (-1)^a / psi(a), a = i - n/2
   // Small scratch.
   unsigned long long* maxkey = nullptr;  // packed (|x| bits, ~index)
+  uint32_t* rowmask = nullptr;  // a caller's row mask (after the max key)
   int max_positive = 0;  // the key holds max(x, 0) in place of |x| (positivity-constrained solve)
   void* vis_scratch = nullptr;  // complex [L] in plan order (residual etc.)
   pc::WStack ws;                // w-stacking planes (nplanes 0: coplanar)
@@ -313,12 +314,22 @@ void dict_gather(pc_plan* p, const DictSpec& D, int64_t nS, const int32_t* atoms
                  const float* img, double* out, hipStream_t s);
 
 // kernels_grid.hip
+// Image rows taking part in a gridded operator: bit i % 32 of bits[i / 32]
+// set for row i (ceil(n / 32) words on the device), count = rows set.  For
+// the forward, rows whose bit is clear must be zero and are not read; for
+// the adjoint, only the rows set are computed (the others are left as they
+// were, and no maximum is formed).
+struct RowMask {
+  const uint32_t* bits;
+  int64_t count;
+};
+constexpr int kMaxRowWords = 8192 / 32;  // npix <= 8192
 template <typename R>
 void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R scale,
-                  hipStream_t s);
+                  hipStream_t s, const RowMask* rows = nullptr);
 template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted,
-                  hipStream_t s);
+                  hipStream_t s, const RowMask* rows = nullptr);
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax);
 // Launch tables of the batched adjoint (device copy and pinned staging),
 // reused from call to call.

@@ -770,6 +770,25 @@ __device__ __forceinline__ int xcd_local(int b, int n) {
   return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Row masks (see RowMask): copied into LDS by the passes that test a row per
+// element; the whole-row passes test their workgroup's rows once.
+__device__ __forceinline__ bool row_set(const uint32_t* bits, int i) {
+  return (bits[i >> 5] >> (i & 31)) & 1u;
+}
+template <int NB>
+__device__ __forceinline__ bool any_row_set(const uint32_t* __restrict__ bits, int i0) {
+  bool any = false;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) any |= row_set(bits, i0 + b);
+  return any;
+}
+template <int NT>
+__device__ __forceinline__ void rows_to_lds(uint32_t* smask, const uint32_t* __restrict__ bits,
+                                            int n) {
+  if (bits)
+    for (int i = threadIdx.x; i < (n + 31) / 32; i += NT) smask[i] = bits[i];
+}
+
 // Pass A of the adjoint: rows of the band grid (fixed v), FFT along u.
 // Element m of a row sits at LDS position pidx(b M + m); a thread's elements
 // are NT apart, so their positions advance by padded(NT).  The occupancy
@@ -780,12 +799,15 @@ template <typename R, int M, int NB, int NT>
 __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* __restrict__ grid,
                                                const uint8_t* __restrict__ tile_flags,
                                                cpx<R>* __restrict__ H,
-                                               const cpx<R>* __restrict__ tw, int rowblock) {
+                                               const cpx<R>* __restrict__ tw, int rowblock,
+                                               const uint32_t* __restrict__ rows = nullptr) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
   constexpr int TR = (NB + kTile - 1) / kTile + 1;  // tile rows a row block can touch
   __shared__ uint8_t sflag[TR][kMaxTileCols];
+  __shared__ uint32_t smask[kMaxRowWords];
+  rows_to_lds<NT>(smask, rows, g.n);
   constexpr int n = M / 2;
   const int row0 = rowblock * NB;
   const int tr0 = row0 / kTile;
@@ -854,12 +876,11 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
   // the n central frequencies f in [-n/2, n/2) go to H column i = f + n/2,
   // stored from the last stage's registers
   auto keep = [](int, int f) { return 4 * f < M || 4 * f >= 3 * M; };
+  // (with a row mask, only the columns of the image rows set)
   auto store = [&](int b, int f, cpx<R> v) {
     const int row = row0 + b;
-    if (row < g.nv) {
-      const int i = f < n / 2 ? f + n / 2 : f - M + n / 2;
-      H[h_index<khb_for<M>()>(row, i, g.nv)] = v;
-    }
+    const int i = f < n / 2 ? f + n / 2 : f - M + n / 2;
+    if (row < g.nv && (!rows || row_set(smask, i))) H[h_index<khb_for<M>()>(row, i, g.nv)] = v;
   };
   if constexpr (RAD0 <= 4) {
     if (pruned)
@@ -875,8 +896,10 @@ template <typename R, int M, int NB, int NT>
 __global__ __launch_bounds__(NT) void passA_adj_kernel(GridGeom g, const cpx<R>* __restrict__ grid,
                                                         const uint8_t* __restrict__ tile_flags,
                                                         cpx<R>* __restrict__ H,
-                                                        const cpx<R>* __restrict__ tw) {
-  passA_adj_body<R, M, NB, NT>(g, grid, tile_flags, H, tw, xcd_local(blockIdx.x, gridDim.x));
+                                                        const cpx<R>* __restrict__ tw,
+                                                        const uint32_t* __restrict__ rows) {
+  passA_adj_body<R, M, NB, NT>(g, grid, tile_flags, H, tw, xcd_local(blockIdx.x, gridDim.x),
+                               rows);
 }
 
 template <int M, int NB, int NT>
@@ -908,13 +931,23 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
                                                const R* __restrict__ corr, R scale,
                                                unsigned long long* __restrict__ maxkey,
                                                int positive, int iblock,
-                                               WPlane wp = WPlane{0.0, 0.0, 1}) {
+                                               WPlane wp = WPlane{0.0, 0.0, 1},
+                                               const uint32_t* __restrict__ rows = nullptr) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
-  load_twiddles<R, M, NT>(tws, tw);
   constexpr int n = M / 2;
   const int i0 = iblock * NB;
+  // with a row mask: workgroups without a row set return at once, the others
+  // store only their rows that are set
+  unsigned rowbits = (1u << NB) - 1u;
+  if (rows) {
+    rowbits = 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) rowbits |= (unsigned)row_set(rows, i0 + b) << b;
+    if (rowbits == 0) return;  // the whole workgroup
+  }
+  load_twiddles<R, M, NT>(tws, tw);
   // element (m, b): band row m - v0 of column i0 + b of the pass-A buffer,
   // whose KHB-wide column blocks are row-major over the band rows
   static_assert((NB & (NB - 1)) == 0 && NT % NB == 0, "pass-B layout");
@@ -983,6 +1016,7 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
   // the last stage's registers with the correction and the max key
   auto keep = [](int, int f) { return 4 * f < M || 4 * f >= 3 * M; };
   auto store = [&](int bb, int f, cpx<R> v) {
+    if (!((rowbits >> bb) & 1u)) return;
     const int i = i0 + bb;
     const int j = f < n / 2 ? f + n / 2 : f - M + n / 2;
     const R l = (R)(i - n / 2) * dl, mm = (R)(j - n / 2) * dl;
@@ -1028,7 +1062,7 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
   __syncthreads();
   if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && maxkey) {
     unsigned long long m = 0;
     for (int w = 0; w < NT / 64; ++w) m = wbest[w] > m ? wbest[w] : m;
     atomicMax(maxkey, m);
@@ -1041,9 +1075,10 @@ __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>*
                                                         const cpx<R>* __restrict__ tw,
                                                         const R* __restrict__ corr, R scale,
                                                         unsigned long long* __restrict__ maxkey,
-                                                        int positive) {
+                                                        int positive,
+                                                        const uint32_t* __restrict__ rows) {
   passB_adj_body<R, M, NB, NT>(g, H, image, tw, corr, scale, maxkey, positive,
-                               xcd_local(blockIdx.x, gridDim.x));
+                               xcd_local(blockIdx.x, gridDim.x), WPlane{0.0, 0.0, 1}, rows);
 }
 
 template <typename R, int M, int NB, int NT>
@@ -1133,75 +1168,151 @@ __global__ __launch_bounds__(NT) void passB_batch_kernel(const AdjJob* __restric
                                    J.positive, it.y);
 }
 
+// First stage of a forward transform whose input is the n = M/2 central
+// frequencies of each sequence (slot m holds frequency m for m < M/4 and
+// m - M for m >= 3M/4; the slots between are zero), applied while loading.
+// Butterfly j of the first stage (radix RAD0, inputs j + r M/RAD0) then has
+// fixed nonzero inputs: for RAD0 >= 4 the r < RAD0/4 and r >= 3 RAD0/4, for
+// RAD0 = 2 exactly one (r = 0 when j < M/4, else r = 1).  load(b, c) returns
+// the value at central index c = f + n/2 of sequence b; outputs go where the
+// full stage writes them (b M + j RAD0 + s).  All loads of a thread are issued
+// before the first is used.
+template <typename R, int M, int NB, int NT, int SIGN, typename Load>
+__device__ __forceinline__ void central_first_stage(cpx<R>* buf, Load load) {
+  constexpr int RAD0 = first_radix(M);
+  constexpr int NBF0 = M / RAD0;
+  constexpr int TOT = NB * NBF0;
+  constexpr int IT = (TOT + NT - 1) / NT;
+  constexpr int NZ = RAD0 >= 4 ? RAD0 / 2 : 1;  // nonzero inputs per butterfly
+  static_assert(M >= 32, "central first stage layout");
+  cpx<R> t[IT][NZ];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = (int)threadIdx.x + it * NT;
+    const int ee = (TOT % NT == 0 || e < TOT) ? e : 0;  // a valid element for spare lanes
+    const int b = ee / NBF0, j = ee - b * NBF0;
+    if constexpr (RAD0 == 2) {
+      t[it][0] = load(b, j < M / 4 ? j + M / 4 : j - M / 4);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NZ; ++q) {
+        const int r = q < RAD0 / 4 ? q : q + RAD0 / 2;   // r in [0, RAD0/4) u [3 RAD0/4, RAD0)
+        const int m = j + r * NBF0;
+        t[it][q] = load(b, r < RAD0 / 4 ? m + M / 4 : m - 3 * (M / 4));
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = (int)threadIdx.x + it * NT;
+    if (TOT % NT == 0 || e < TOT) {
+      const int b = e / NBF0, j = e - b * NBF0;
+      const int p0 = b * M + j * RAD0;
+      if constexpr (RAD0 == 2) {
+        const cpx<R> v = t[it][0];
+        buf[pidx(p0)] = v;
+        buf[pidx(p0 + 1)] = j < M / 4 ? v : cpx<R>{-v.x, -v.y};
+      } else if constexpr (RAD0 == 4) {
+        // X_s = x_0 + x_3 w^(3 s)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const cpx<R> u = rot<R, 4, SIGN>(t[it][1], (3 * s) & 3);
+          buf[pidx(p0 + s)] = {t[it][0].x + u.x, t[it][0].y + u.y};
+        }
+      } else {
+        cpx<R> x[RAD0];
+#pragma unroll
+        for (int r = 0; r < RAD0; ++r) x[r] = {R(0), R(0)};
+#pragma unroll
+        for (int q = 0; q < NZ; ++q) x[q < RAD0 / 4 ? q : q + RAD0 / 2] = t[it][q];
+        dft<R, RAD0, SIGN>(x);
+#pragma unroll
+        for (int s = 0; s < RAD0; ++s) buf[pidx(p0 + s)] = x[s];
+      }
+    }
+  }
+}
+
 // Forward pass B^T: NB image rows i, pre-correct, FFT along v (sign -1),
-// keep the band rows: Hf[v_rel][i].
+// keep the band rows: H[v_rel][i] (the pass-A layout).  The first stage is
+// applied while loading (the row's n pixels are the central frequencies) and
+// the band rows are stored from the last stage's registers.
+template <typename R, int M, int NB, int NT>
+__device__ __forceinline__ void passB_fwd_body(const GridGeom& g, const R* __restrict__ image,
+                                               cpx<R>* __restrict__ H,
+                                               const cpx<R>* __restrict__ tw,
+                                               const R* __restrict__ corr, int iblock,
+                                               const uint32_t* __restrict__ rows) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  __shared__ cpx<R> tws[tw_count(M)];
+  constexpr int n = M / 2;
+  const int i0 = iblock * NB;
+  // with a row mask, workgroups of zero rows write nothing (pass A reads
+  // those columns of H as zeros)
+  if (rows && !any_row_set<NB>(rows, i0)) return;
+  load_twiddles<R, M, NT>(tws, tw);
+  const R dl = (R)g.dl;
+  central_first_stage<R, M, NB, NT, -1>(buf, [&](int b, int j) -> cpx<R> {
+    const int i = i0 + b;
+    const R l = (R)(i - n / 2) * dl, mm = (R)(j - n / 2) * dl;
+    R inv_n;
+    if constexpr (sizeof(R) == 4) {
+      inv_n = __builtin_amdgcn_rsqf(R(1) - l * l - mm * mm);
+    } else {
+      inv_n = R(1) / sqrt(R(1) - l * l - mm * mm);
+    }
+    return {image[(size_t)i * n + j] * corr[i] * corr[j] * inv_n, R(0)};
+  });
+  __syncthreads();
+  constexpr int KHB = khb_for<M>();
+  const int v0 = g.v0, nv = g.nv;
+  auto keep = [&](int, int f) { return (unsigned)(f - v0) < (unsigned)nv; };
+  auto store = [&](int b, int f, cpx<R> v) { H[h_index<KHB>(f - v0, i0 + b, nv)] = v; };
+  lds_fft_store<R, M, NB, NT, -1, first_radix(M)>(buf, tws, keep, store);
+}
+
 template <typename R, int M, int NB, int NT>
 __global__ __launch_bounds__(NT) void passB_fwd_kernel(GridGeom g, const R* __restrict__ image,
                                                         cpx<R>* __restrict__ H,
                                                         const cpx<R>* __restrict__ tw,
-                                                        const R* __restrict__ corr) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
-  __shared__ cpx<R> tws[tw_count(M)];
-  load_twiddles<R, M, NT>(tws, tw);
-  constexpr int n = M / 2;
-  const int i0 = blockIdx.x * NB;
-  const R dl = (R)g.dl;
-  for (int idx = threadIdx.x; idx < NB * M; idx += NT) {
-    const int b = idx / M, m = idx - b * M;  // m: frequency slot
-    int f = m < n / 2 ? m : m - M;            // signed frequency b
-    cpx<R> v = {R(0), R(0)};
-    if (f >= -n / 2 && f < n / 2) {
-      const int i = i0 + b, j = f + n / 2;
-      const R l = (R)(i - n / 2) * dl, mm = (R)(j - n / 2) * dl;
-      R inv_n;
-      if constexpr (sizeof(R) == 4) {
-        inv_n = __builtin_amdgcn_rsqf(R(1) - l * l - mm * mm);
-      } else {
-        inv_n = R(1) / sqrt(R(1) - l * l - mm * mm);
-      }
-      v.x = image[(size_t)i * n + j] * corr[i] * corr[j] * inv_n;
-    }
-    buf[pidx(idx)] = v;
-  }
-  __syncthreads();
-  lds_fft<R, M, NB, NT, -1>(buf, tws);
-  for (int idx = threadIdx.x; idx < NB * g.nv; idx += NT) {
-    const int rel = idx / NB, b = idx - rel * NB;
-    int m = g.v0 + rel;
-    H[h_index<khb_for<M>()>(rel, i0 + b, g.nv)] = buf[pidx(b * M + m)];
-  }
+                                                        const R* __restrict__ corr,
+                                                        const uint32_t* __restrict__ rows) {
+  passB_fwd_body<R, M, NB, NT>(g, image, H, tw, corr, xcd_local(blockIdx.x, gridDim.x), rows);
 }
 
-// Forward pass A^T: band rows v; FFT along u (sign -1) of Hf[v][:] placed at
-// the n central frequencies; keep the band columns.
+// Forward pass A^T: NB band rows v; FFT along u (sign -1) of H[v][:] placed
+// at the n central frequencies (first stage applied while loading); the band
+// columns stored from the last stage's registers.
 template <typename R, int M, int NB, int NT>
 __global__ __launch_bounds__(NT) void passA_fwd_kernel(GridGeom g, const cpx<R>* __restrict__ H,
                                                         cpx<R>* __restrict__ grid,
-                                                        const cpx<R>* __restrict__ tw) {
+                                                        const cpx<R>* __restrict__ tw,
+                                                        const uint32_t* __restrict__ rows) {
   extern __shared__ unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
-  load_twiddles<R, M, NT>(tws, tw);
-  constexpr int n = M / 2;
-  const int row0 = blockIdx.x * NB;
-  gather_to_lds<R, NB * M, NT>(
-      buf, H,
-      [&](int idx) -> int64_t {
-        const int b = idx / M, m = idx - b * M;
-        const int row = row0 + b;
-        const int f = m < n / 2 ? m : m - M;
-        if (row >= g.nv || f < -n / 2 || f >= n / 2) return -1;
-        return (int64_t)h_index<khb_for<M>()>(row, f + n / 2, g.nv);
-      },
-      [](int idx) { return idx; });
-  __syncthreads();
-  lds_fft<R, M, NB, NT, -1>(buf, tws);
-  for (int idx = threadIdx.x; idx < NB * g.nu; idx += NT) {
-    const int b = idx / g.nu, rel = idx - b * g.nu;
+  __shared__ uint32_t smask[kMaxRowWords];
+  rows_to_lds<NT>(smask, rows, g.n);
+  load_twiddles<R, M, NT>(tws, tw);  // (its barrier also covers the mask)
+  const int row0 = xcd_local(blockIdx.x, gridDim.x) * NB;
+  constexpr int KHB = khb_for<M>();
+  const int nv = g.nv;
+  central_first_stage<R, M, NB, NT, -1>(buf, [&](int b, int c) -> cpx<R> {
     const int row = row0 + b;
-    if (row < g.nv) grid[(size_t)row * g.nu + rel] = buf[pidx(b * M + g.u0 + rel)];
-  }
+    // H column c is image row c: zero, and not read, when the mask clears it;
+    // rows past the band (last workgroup) read row 0 and are never stored
+    if (rows && !row_set(smask, c)) return {R(0), R(0)};
+    return H[h_index<KHB>(row < nv ? row : 0, c, nv)];
+  });
+  __syncthreads();
+  const int u0 = g.u0, nu = g.nu;
+  auto keep = [&](int, int f) { return (unsigned)(f - u0) < (unsigned)nu; };
+  auto store = [&](int b, int f, cpx<R> v) {
+    const int row = row0 + b;
+    if (row < nv) grid[(size_t)row * nu + (f - u0)] = v;
+  };
+  lds_fft_store<R, M, NB, NT, -1, first_radix(M)>(buf, tws, keep, store);
 }
 
 // Interpolation: V_k = sum of w x w taps of the fine grid (type-2 gather).
@@ -1360,7 +1471,7 @@ constexpr int nt_for() {
 
 template <typename R, int M>
 static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
-                           const WPlane* wp = nullptr) {
+                           const WPlane* wp = nullptr, const RowMask* rows = nullptr) {
   constexpr int CB = sizeof(cpx<R>);
   constexpr int NBA = (M * CB >= Shapes<R>::lds_a) ? 1 : Shapes<R>::lds_a / (M * CB);
   constexpr int NTA = nt_for<NBA * M / 16>();
@@ -1369,12 +1480,18 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
   const GridGeom& g = p->g;
   const size_t lda = (size_t)padded(NBA * M) * CB, ldb = (size_t)padded(NBB * M) * CB;
   const double nvn = (double)g.nv * g.n * CB;
+  // with a row mask: the H columns and image rows of the rows set (the
+  // passes appear under names of their own)
+  const uint32_t* bits = rows ? rows->bits : nullptr;
+  const double nr = rows ? (double)rows->count : (double)g.n;
+  const double nvr = (double)g.nv * nr * CB;
   set_lds((const void*)passA_adj_kernel<R, M, NBA, NTA>, lda);
   {
-    ProfScope ps(p, s, "passA_adj", (double)g.nv * g.nu * CB + nvn, (double)g.nv * M);
+    ProfScope ps(p, s, rows ? "passA_adj_rows" : "passA_adj", (double)g.nv * g.nu * CB + nvr,
+                 (double)g.nv * M);
     hipLaunchKernelGGL((passA_adj_kernel<R, M, NBA, NTA>), dim3((g.nv + NBA - 1) / NBA), dim3(NTA),
                        lda, s, g, (const cpx<R>*)p->grid, p->tile_flags, (cpx<R>*)p->H,
-                       (const cpx<R>*)p->twiddle);
+                       (const cpx<R>*)p->twiddle, bits);
     PC_LAUNCH_CHECK("passA_adj");
   }
   if (wp) {  // one w-plane: rotate, add into the image
@@ -1388,56 +1505,62 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
     return;
   }
   set_lds((const void*)passB_adj_kernel<R, M, NBB, NTB>, ldb);
-  ProfScope ps(p, s, "passB_adj", nvn + (double)g.n * g.n * sizeof(R), (double)g.n * M);
+  ProfScope ps(p, s, rows ? "passB_adj_rows" : "passB_adj",
+               nvr + nr * g.n * sizeof(R), nr * M);
   hipLaunchKernelGGL((passB_adj_kernel<R, M, NBB, NTB>), dim3((M / 2) / NBB), dim3(NTB), ldb, s, g,
                      (const cpx<R>*)p->H, image, (const cpx<R>*)p->twiddle, (const R*)p->corr,
-                     scale, p->maxkey, p->max_positive);
+                     scale, rows ? nullptr : p->maxkey, p->max_positive, bits);
   PC_LAUNCH_CHECK("passB_adj");
 }
 
 template <typename R, int M>
-static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s) {
+static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s,
+                           const RowMask* rows = nullptr) {
   constexpr int CB = sizeof(cpx<R>);
   constexpr int NBA = (M * CB >= Shapes<R>::lds_a) ? 1 : Shapes<R>::lds_a / (M * CB);
-  constexpr int NTA = 256;
+  constexpr int NTA = nt_for<NBA * M / 16>();
   constexpr int NBB = nb_passB<R, M>();
   constexpr int NTB = nt_for<NBB * M / 16>();
   const GridGeom& g = p->g;
   const size_t lda = (size_t)padded(NBA * M) * CB, ldb = (size_t)padded(NBB * M) * CB;
-  const double nvn = (double)g.nv * g.n * CB;
+  const uint32_t* bits = rows ? rows->bits : nullptr;
+  const double nr = rows ? (double)rows->count : (double)g.n;
+  const double nvr = (double)g.nv * nr * CB;
   set_lds((const void*)passB_fwd_kernel<R, M, NBB, NTB>, ldb);
   {
-  ProfScope ps(p, s, "passB_fwd", nvn + (double)g.n * g.n * sizeof(R), (double)g.n * M);
+  ProfScope ps(p, s, rows ? "passB_fwd_rows" : "passB_fwd", nvr + nr * g.n * sizeof(R), nr * M);
   hipLaunchKernelGGL((passB_fwd_kernel<R, M, NBB, NTB>), dim3((M / 2) / NBB), dim3(NTB), ldb, s,
-                     g, image, (cpx<R>*)p->H, (const cpx<R>*)p->twiddle, (const R*)p->corr);
+                     g, image, (cpx<R>*)p->H, (const cpx<R>*)p->twiddle, (const R*)p->corr, bits);
   PC_LAUNCH_CHECK("passB_fwd");
   }
   set_lds((const void*)passA_fwd_kernel<R, M, NBA, NTA>, lda);
-  ProfScope ps(p, s, "passA_fwd", (double)g.nv * g.nu * CB + nvn, (double)g.nv * M);
+  ProfScope ps(p, s, rows ? "passA_fwd_rows" : "passA_fwd", (double)g.nv * g.nu * CB + nvr,
+               (double)g.nv * M);
   hipLaunchKernelGGL((passA_fwd_kernel<R, M, NBA, NTA>), dim3((g.nv + NBA - 1) / NBA), dim3(NTA),
-                     lda, s, g, (const cpx<R>*)p->H, (cpx<R>*)p->grid, (const cpx<R>*)p->twiddle);
+                     lda, s, g, (const cpx<R>*)p->H, (cpx<R>*)p->grid, (const cpx<R>*)p->twiddle,
+                     bits);
   PC_LAUNCH_CHECK("passA_fwd");
 }
 
 template <typename R>
 static void dispatch_M(pc_plan* p, bool adjoint, R* img_out, const R* img_in, R scale,
-                       hipStream_t s, const WPlane* wp = nullptr) {
+                       hipStream_t s, const WPlane* wp = nullptr, const RowMask* rows = nullptr) {
   switch (p->g.M) {
-#define PC_M(m)                                         \
-  case m:                                               \
-    if (adjoint)                                        \
-      run_passes_adj<R, m>(p, img_out, scale, s, wp);   \
-    else                                                \
-      run_passes_fwd<R, m>(p, img_in, s);               \
+#define PC_M(m)                                             \
+  case m:                                                   \
+    if (adjoint)                                            \
+      run_passes_adj<R, m>(p, img_out, scale, s, wp, rows); \
+    else                                                    \
+      run_passes_fwd<R, m>(p, img_in, s, rows);             \
     return;
     PC_M(32) PC_M(64) PC_M(128) PC_M(256) PC_M(512) PC_M(1024) PC_M(2048) PC_M(4096) PC_M(8192)
 #undef PC_M
     case 16384:
       if constexpr (sizeof(R) == 4) {
         if (adjoint)
-          run_passes_adj<R, 16384>(p, img_out, scale, s, wp);
+          run_passes_adj<R, 16384>(p, img_out, scale, s, wp, rows);
         else
-          run_passes_fwd<R, 16384>(p, img_in, s);
+          run_passes_fwd<R, 16384>(p, img_in, s, rows);
         return;
       }
       [[fallthrough]];
@@ -1492,8 +1615,9 @@ static void adjoint_grid_w(pc_plan* p, const c32* vis, bool vis_sorted, float* i
 
 template <typename R>
 void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R scale,
-                  hipStream_t s) {
+                  hipStream_t s, const RowMask* rows) {
   if (p->Cw) {
+    if (rows) fail(PC_ERR_UNSUPPORTED, "a row mask with the w-stacked adjoint");
     if constexpr (sizeof(R) == 4) {
       adjoint_grid_w(p, vis, vis_sorted, image, scale, s);
       return;
@@ -1501,15 +1625,16 @@ void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R sc
     fail(PC_ERR_UNSUPPORTED, "w-stacked adjoint of an FP64 plan");
   }
   launch_spread<R>(p, vis, vis_sorted ? nullptr : p->perm, s);  // also clears the max key
-  dispatch_M<R>(p, true, image, nullptr, scale, s);
+  dispatch_M<R>(p, true, image, nullptr, scale, s, nullptr, rows);
 }
 
 template <typename R>
-void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted, hipStream_t s) {
+void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted, hipStream_t s,
+                  const RowMask* rows) {
   if (p->Cw)
     fail(PC_ERR_UNSUPPORTED,
          "the gridded forward operator needs a coplanar plan (w = 0); the direct sums take w");
-  dispatch_M<R>(p, false, nullptr, image, R(1), s);
+  dispatch_M<R>(p, false, nullptr, image, R(1), s, nullptr, rows);
   launch_interp<R>(p, out_sorted ? nullptr : p->perm, vis_out, s);
 }
 
@@ -1757,9 +1882,13 @@ void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* 
   ctx.pending = true;
 }
 
-template void adjoint_grid<float>(pc_plan*, const c32*, bool, float*, float, hipStream_t);
-template void adjoint_grid<double>(pc_plan*, const c64*, bool, double*, double, hipStream_t);
-template void forward_grid<float>(pc_plan*, const float*, c32*, bool, hipStream_t);
-template void forward_grid<double>(pc_plan*, const double*, c64*, bool, hipStream_t);
+template void adjoint_grid<float>(pc_plan*, const c32*, bool, float*, float, hipStream_t,
+                                  const RowMask*);
+template void adjoint_grid<double>(pc_plan*, const c64*, bool, double*, double, hipStream_t,
+                                   const RowMask*);
+template void forward_grid<float>(pc_plan*, const float*, c32*, bool, hipStream_t,
+                                  const RowMask*);
+template void forward_grid<double>(pc_plan*, const double*, c64*, bool, hipStream_t,
+                                   const RowMask*);
 
 }  // namespace pc

@@ -687,7 +687,7 @@ static size_t layout_bytes(const Layout& lay, int prec) {
   add((size_t)lay.n_partials * kTile * kTile * cb);
   add((size_t)twiddle_entries(g.M) * cb);    // twiddles
   add((size_t)g.n * rb);                     // correction
-  add(256);                                  // max key
+  add(256 + 4 * kMaxRowWords);               // max key, row mask
   add(lay.L * cb);                           // vis scratch
   if (lay.ws.nplanes > 0) {
     add(lay.L * 8);                          // w
@@ -748,7 +748,8 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     p->partials = dalloc(p, (size_t)lay.n_partials * kTile * kTile * cb);
     p->twiddle = dalloc(p, (size_t)twiddle_entries(g.M) * cb);
     p->corr = dalloc(p, (size_t)g.n * rb);
-    p->maxkey = (unsigned long long*)dalloc(p, 256);
+    p->maxkey = (unsigned long long*)dalloc(p, 256 + 4 * kMaxRowWords);
+    p->rowmask = (uint32_t*)((unsigned char*)p->maxkey + 256);
     p->vis_scratch = dalloc(p, L * cb);
     p->ws = lay.ws;
     if (lay.ws.nplanes > 0) {

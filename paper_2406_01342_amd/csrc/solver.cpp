@@ -218,7 +218,8 @@ struct Pfw {
   std::vector<int32_t> pre_I;
   int pre_k = -1;
   bool pre_ok = false;
-  DevArray<double> act_blk;  // uploaded [x | pix] of the active set
+  DevArray<double> act_blk;  // uploaded [x | pix | row mask] of the active set
+  RowMask act_rows{nullptr, 0};  // image rows holding atoms (inside act_blk)
   DevArray<Atom<float>> off_atoms;
   DevArray<double> b_partial;  // partials of b's sums when batched beside the psf sums
   double v2 = 0;  // ||V||^2
@@ -392,27 +393,54 @@ struct Pfw {
     y.ensure(nS);
     g.ensure(nS);
     adj_partial.ensure(adjoint_partial_count(p, nS));
+    act_rows = RowMask{nullptr, 0};
     if (nS == 0) return;
-    // one upload and one kernel: x = y = weights, pix, atom table
-    act_blk.ensure((nS * 12 + 7) / 8);
-    unsigned char* h = (unsigned char*)up_act.get(nS * 12);
+    // one upload and one kernel: x = y = weights, pix, atom table; the mask
+    // of the image rows that hold atoms stays in the block for the gridded
+    // operators
+    const int n = p->g.n;
+    const int64_t words = (n + 31) / 32, moff = (nS * 12 + 7) / 8 * 8;
+    const int64_t bytes = moff + words * 4;
+    act_blk.ensure((bytes + 7) / 8);
+    unsigned char* h = (unsigned char*)up_act.get(bytes);
     std::memcpy(h, xs_host.data(), nS * 8);
     std::memcpy(h + nS * 8, set.data(), nS * 4);
-    PC_HIP(hipMemcpyAsync(act_blk.ptr, h, nS * 12, hipMemcpyHostToDevice, s));
+    uint32_t* mask = (uint32_t*)(h + moff);
+    std::memset(mask, 0, words * 4);
+    int64_t nrows = 0;
+    for (int64_t q = 0; q < nS; ++q) {
+      const int i = set[q] / n;
+      if (!(mask[i >> 5] & (1u << (i & 31)))) ++nrows;
+      mask[i >> 5] |= 1u << (i & 31);
+    }
+    PC_HIP(hipMemcpyAsync(act_blk.ptr, h, bytes, hipMemcpyHostToDevice, s));
     up_act.arm(s);
     k_activate(p, nS, act_blk.ptr, x.ptr, y.ptr, pix.ptr, atoms.ptr, s);
+    act_rows = RowMask{(const uint32_t*)((const unsigned char*)act_blk.ptr + moff), nrows};
   }
 
-  // Crossover between the direct sums (cost ~ L nS) and the gridded
-  // operators (cost ~ L + band cells): from the measured rates on gfx950,
-  // about 0.4 ps per visibility-atom pair per direction against 0.2 ns per
-  // visibility plus 8 ps per band cell.
+  // Crossover between the direct sums and the gridded operators (restricted
+  // to the image rows that hold atoms), per direction, from rates measured on
+  // gfx950: the direct sums about 0.45 ps per visibility-atom pair; the
+  // gridded operators about 28 ps per visibility (spread or interpolation),
+  // 3.4 ps per fine-grid point of the band rows' transforms and 2.7 ps per
+  // fine-grid point of the image rows' transforms (at most one row per
+  // atom), plus 15 us of launches.
   int64_t grid_crossover() const {
     if (p->Cw) return INT64_MAX / 8;  // no gridded forward with the w-term: direct sums only
     if (prm.grid_atoms > 0) return prm.grid_atoms;
     if (prm.grid_atoms < 0) return INT64_MAX / 8;
-    const double cells = (double)p->g.nu * (double)p->g.nv;
-    return (int64_t)(500.0 + 20.0 * cells / (double)L);
+    const double M = (double)p->g.M, Ld = (double)L;
+    const double per_atom = 0.45e-12 * Ld - 2.7e-12 * M;
+    const double fixed = 28e-12 * Ld + 3.4e-12 * (double)p->g.nv * M + 15e-6;
+    if (per_atom <= 0 || fixed / per_atom > 1e12) return INT64_MAX / 8;
+    return (int64_t)std::ceil(fixed / per_atom);
+  }
+
+  // The row mask of the loaded active set for the gridded operators (none
+  // with a dictionary, whose atoms cover several rows).
+  const RowMask* rows_of_set() const {
+    return (!ms && act_rows.bits && act_rows.count > 0) ? &act_rows : nullptr;
   }
 
   void ensure_dimg() {
@@ -436,20 +464,21 @@ struct Pfw {
       k_fill(p, N, 0.0f, dimg.ptr, s);
     } else {
       k_scatter(p, nS, pix.ptr, w, dimg.ptr, s);
-      forward_grid<float>(p, dimg.ptr, out, true, s);
+      forward_grid<float>(p, dimg.ptr, out, true, s, rows_of_set());
       k_scatter(p, nS, pix.ptr, nullptr, dimg.ptr, s);
     }
     if (base) k_rsub(p, L, V.ptr, out, s);
   }
 
   // g = Phi_S* r (FP64), directly or as the gridded adjoint sampled at S
-  // (eta serves as scratch: it is recomputed after the APGD step).
+  // (eta serves as scratch: it is recomputed after the APGD step; only the
+  // rows holding atoms are computed).
   void op_adjoint(bool gridded, int64_t nS, const c32* rr, double* gout) {
     if (!gridded) {
       adjoint_atoms<float>(p, rr, true, nS, atoms.ptr, adj_partial.ptr, gout, s);
       return;
     }
-    adjoint_grid<float>(p, rr, true, eta.ptr, 1.0f, s);
+    adjoint_grid<float>(p, rr, true, eta.ptr, 1.0f, s, rows_of_set());
     if (ms)
       dict_gather(p, dict, nS, pix.ptr, eta.ptr, gout, s);
     else
@@ -852,9 +881,13 @@ struct Pfw {
     load_active(Sn, xw);
     // 2. APGD on the restricted problem
     int inner = 0;
-    const bool gridded = ms || nS >= grid_thr;
-    // small direct sets: the Gram form (one small kernel per step)
-    const bool gram = !gridded && nS > 0 && nS <= gram_cap() && build_gram(Sn);
+    // small sets: the Gram form (one small kernel per step) when its new
+    // point-spread sums are affordable, else the gridded operators from the
+    // crossover on, else the direct sums (a crossover set by the caller
+    // comes before the Gram form)
+    const bool force_grid = ms || (prm.grid_atoms > 0 && nS >= grid_thr);
+    const bool gram = !force_grid && nS > 0 && nS <= gram_cap() && build_gram(Sn);
+    const bool gridded = !gram && (ms || nS >= grid_thr);
     if (nS > 0) {
       // step constant: on the device for the Gram form (read there by the
       // APGD kernel, no host round trip), else from the host-driven Lanczos

@@ -186,6 +186,115 @@ def test_forward_grid_dense(name):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("n", [16, 32, 64, 256, 1024, 2048, 4096, 8192])
+def test_forward_grid_every_first_radix(n):
+    """The gridded forward on fine grids of 32 to 16384 cells, which start
+    their FFTs with every first-stage radix (2, 4, 8, 16) applied while
+    loading: random uv filling the band, an image set at the centre, the
+    corners, the edges and random pixels, against the oracle's exact sum at
+    every visibility."""
+    say("forward_grid sizes", n)
+    a = api()
+    rng = np.random.default_rng(100 + n)
+    fov = 0.02 if n <= 1024 else 0.05
+    d = fov / n
+    L = 20000
+    uv = rng.uniform(-0.49 / d, 0.49 / d, size=(L, 2))
+    c = n // 2
+    pix = np.unique(np.concatenate([
+        [c * n + c, 0, n - 1, (n - 1) * n, n * n - 1, c, c * n, (n - 1) * n + c, c * n + n - 1],
+        rng.choice(n * n, min(48, n * n // 4), replace=False)]))
+    img = np.zeros(n * n, np.float32)
+    img[pix] = rng.normal(size=pix.size).astype(np.float32)
+    plan = a.pc_plan_create(uv, n, fov)
+    assert plan.info["fine"] == 2 * n
+    out = a.pc_forward_grid(plan, to_dev(img.reshape(n, n)))
+    torch.cuda.synchronize()
+    want = operator.forward(uv, n, fov, pix, img[pix].astype(np.float64))
+    err = rel_l2(out.cpu().numpy(), want)
+    say(n, "rel L2", err)
+    assert err <= TOL
+
+
+def _rows_case(n, L=20000, seed=0):
+    rng = np.random.default_rng(700 + n + seed)
+    fov = 0.02 if n <= 1024 else 0.05
+    d = fov / n
+    uv = rng.uniform(-0.49 / d, 0.49 / d, size=(L, 2))
+    h = (rng.normal(size=L) + 1j * rng.normal(size=L)).astype(np.complex64)
+    return rng, uv, fov, h
+
+
+@pytest.mark.parametrize("n", [64, 512, 1024, 4096, 8192])
+def test_forward_grid_rows_equals_full(n):
+    """The row-restricted gridded forward of an image that is zero outside the
+    mask's rows equals the full gridded forward bit for bit (it skips only
+    transforms of zero rows), at fine grids with one and with several rows
+    per pass-B workgroup, including the first and last rows."""
+    say("forward_grid_rows", n)
+    a = api()
+    rng, uv, fov, _ = _rows_case(n)
+    plan = a.pc_plan_create(uv, n, fov)
+    rows = np.unique(np.concatenate([[0, n - 1, n // 2], rng.choice(n, min(40, n // 2), replace=False)]))
+    img = np.zeros((n, n), np.float32)
+    for r in rows:
+        cols = rng.choice(n, 3, replace=False)
+        img[r, cols] = rng.normal(size=3).astype(np.float32)
+    full = a.pc_forward_grid(plan, to_dev(img))
+    part = a.pc_forward_grid_rows(plan, to_dev(img), a.row_mask(n, rows))
+    torch.cuda.synchronize()
+    assert torch.equal(full, part)
+    # a mask with more rows than the image uses gives the same result
+    extra = np.union1d(rows, rng.choice(n, 5, replace=False))
+    part2 = a.pc_forward_grid_rows(plan, to_dev(img), a.row_mask(n, extra))
+    torch.cuda.synchronize()
+    assert torch.equal(full, part2)
+
+
+@pytest.mark.parametrize("n", [64, 512, 1024, 4096, 8192])
+def test_adjoint_grid_rows_equals_full(n):
+    """The row-restricted gridded adjoint writes exactly the mask's rows of
+    the full adjoint's image (bit for bit) and leaves every other row as it
+    was; an empty mask writes nothing."""
+    say("adjoint_grid_rows", n)
+    a = api()
+    rng, uv, fov, h = _rows_case(n, seed=1)
+    plan = a.pc_plan_create(uv, n, fov)
+    full, _, _ = a.pc_adjoint_grid(plan, to_dev(h))
+    rows = np.unique(np.concatenate([[0, n - 1], rng.choice(n, min(40, n // 2), replace=False)]))
+    sentinel = 12345.0
+    img = torch.full((n, n), sentinel, dtype=torch.float32, device="cuda")
+    a.pc_adjoint_grid_rows(plan, to_dev(h), a.row_mask(n, rows), img)
+    torch.cuda.synchronize()
+    sel = torch.from_numpy(rows).cuda()
+    assert torch.equal(img[sel], full[sel])
+    other = np.setdiff1d(np.arange(n), rows)
+    assert bool((img[torch.from_numpy(other).cuda()] == sentinel).all())
+    before = img.clone()
+    a.pc_adjoint_grid_rows(plan, to_dev(h), a.row_mask(n, []), img)
+    torch.cuda.synchronize()
+    assert torch.equal(img, before)
+
+
+def test_grid_rows_reject_bad_masks():
+    """A mask of the wrong length is refused by the binding; a set bit past
+    npix (npix = 16: one word, bits 16..31 past the image) by the library."""
+    a = api()
+    _, uv, fov, h = _rows_case(16, L=500)
+    plan = a.pc_plan_create(uv, 16, fov)
+    img = torch.zeros((16, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        a.pc_adjoint_grid_rows(plan, to_dev(h), np.zeros(2, np.uint32), img)
+    m = a.row_mask(16, [3, 15])
+    a.pc_adjoint_grid_rows(plan, to_dev(h), m, img)
+    m[0] |= np.uint32(1) << np.uint32(20)
+    with pytest.raises(a.PolycleanError) as e:
+        a.pc_forward_grid_rows(plan, img, m)
+    assert e.value.status == -1
+    with pytest.raises(ValueError):
+        a.row_mask(16, [16])
+
+
 def test_dot_product_gridded_pair():
     """<Phi_grid x, h> = <x, Phi*_grid h> up to the gridding error."""
     p, vis = problem("c1")
