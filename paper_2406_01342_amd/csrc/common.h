@@ -89,6 +89,17 @@ struct SpreadChunk {
 };
 constexpr int kSpreadQuad = 2;  // waves (items) per workgroup of the grouped spread
 
+// Interpolation work item: the plan-order visibilities [beg, end) whose first
+// cells lie in `tile` (a tile's own visibilities, in chunks of at most
+// kInterpChunk).
+struct InterpItem {
+  int32_t tile;
+  int32_t beg;
+  int32_t end;
+  int32_t pad;
+};
+constexpr int kInterpChunk = 512;
+
 // A split ("hot") tile: its partial tiles occupy slots [first, first+count).
 struct FoldItem {
   int32_t tile;
@@ -170,6 +181,9 @@ struct AdjJob {
   float scale;
   int positive;  // max key of max(eta, 0) instead of |eta|
   unsigned long long* maxkey;
+  // always NULL (full images), read at run time so that the batched passes
+  // compile to the same code as the single-plan ones (bitwise equal results)
+  const uint32_t* rows;
 };
 
 // Per-kernel instrumentation (optional): launches bracketed by HIP events on
@@ -200,7 +214,7 @@ struct pc_plan {
   int precision = PC_PREC_FP32;
   int64_t L = 0;
   pc::GridGeom g{};
-  int64_t n_chunks = 0, n_partials = 0, n_fold = 0;
+  int64_t n_chunks = 0, n_partials = 0, n_fold = 0, n_interp = 0;
   bool spread_quads = false;  // work items grouped by workgroup (FP32, kernel width <= 8)
   size_t footprint = 0;
 
@@ -214,6 +228,7 @@ struct pc_plan {
   pc::SpreadChunk* chunks = nullptr;
   pc::FoldItem* fold = nullptr;
   uint8_t* tile_flags = nullptr;  // [ntv * ntu]: 1 if the tile holds data
+  pc::InterpItem* interp = nullptr;  // interpolation work list
   // Fine grid band, pass-A output, split-tile partials.
   void* grid = nullptr;         // complex [nv][nu]
   void* H = nullptr;            // complex [nv][n]

@@ -907,7 +907,7 @@ __global__ __launch_bounds__(NT) void passA_batch_kernel(const AdjJob* __restric
                                                           const int2* __restrict__ items) {
   const int2 it = items[xcd_local(blockIdx.x, gridDim.x)];
   const AdjJob& J = jobs[it.x];
-  passA_adj_body<float, M, NB, NT>(J.g, J.grid, J.flags, J.H, J.tw, it.y);
+  passA_adj_body<float, M, NB, NT>(J.g, J.grid, J.flags, J.H, J.tw, it.y, J.rows);
 }
 
 __device__ __forceinline__ unsigned long long max_key(float a, int idx) {
@@ -1165,7 +1165,7 @@ __global__ __launch_bounds__(NT) void passB_batch_kernel(const AdjJob* __restric
   const int2 it = items[xcd_local(blockIdx.x, gridDim.x)];
   const AdjJob& J = jobs[it.x];
   passB_adj_body<float, M, NB, NT>(J.g, J.H, J.image, J.tw, J.corr, J.scale, J.maxkey,
-                                   J.positive, it.y);
+                                   J.positive, it.y, WPlane{0.0, 0.0, 1}, J.rows);
 }
 
 // First stage of a forward transform whose input is the n = M/2 central
@@ -1357,6 +1357,78 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
   out[d] = {ax, ay};
 }
 
+// Interpolation from LDS (FP32, kernel widths up to 16): one wave per work
+// item (InterpItem), a plan-order range of visibilities whose first cells lie
+// in one tile.  The wave copies the tile and the W - 1 cells past its right
+// and lower edges, all that its visibilities' footprints reach, into LDS
+// (cells outside the band as zeros; with a periodic band, wrapped), then each
+// lane sums the W x W taps of one visibility from there, rows of taps in the
+// same order as interp_kernel.
+template <int W>
+struct InterpCfg {
+  static constexpr int S = kTile + W - 1;  // region side (cells)
+  static constexpr int SP = S | 1;         // row stride (odd)
+};
+
+template <int W>
+__global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
+                                                        const InterpItem* __restrict__ items,
+                                                        const uint32_t* __restrict__ cell,
+                                                        const float* __restrict__ off,
+                                                        const c32* __restrict__ grid,
+                                                        const int32_t* __restrict__ perm,
+                                                        c32* __restrict__ out) {
+  using C = InterpCfg<W>;
+  __shared__ float2 reg[C::S * C::SP];
+  const InterpItem it = items[blockIdx.x];
+  const int lane = (int)threadIdx.x;
+  const int tv = it.tile / g.ntu, tu = it.tile - tv * g.ntu;
+  const int rv0 = tv * kTile, ru0 = tu * kTile;  // region origin in the band
+  for (int e = lane; e < C::S * C::S; e += 64) {
+    const int y = e / C::S, x = e - y * C::S;
+    int rv = rv0 + y, ru = ru0 + x;
+    float2 v = make_float2(0.f, 0.f);
+    if (g.wrap) {
+      if (rv >= g.M) rv -= g.M;
+      if (ru >= g.M) ru -= g.M;
+    }
+    if (rv < g.nv && ru < g.nu) {
+      const c32 c = grid[(size_t)rv * g.nu + ru];
+      v = make_float2(c.x, c.y);
+    }
+    reg[y * C::SP + x] = v;
+  }
+  __syncthreads();
+  constexpr float R = 0.5f * (float)W;
+  const float c0 = g.beta * 1.44269504088896341f;  // beta log2(e)
+  const float c1 = c0 / R;
+  const int ou = g.u0 + ru0, ov = g.v0 + rv0;
+  for (int sidx = it.beg + lane; sidx < it.end; sidx += 64) {
+    const uint32_t c = cell[sidx];
+    const int x = (int)(c & 0xffffu) - ou, y = (int)(c >> 16) - ov;  // in [0, kTile)
+    const float2 o = reinterpret_cast<const float2*>(off)[sidx];
+    float ku[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) ku[t] = es_weight(o.x + (float)t, R * R, c1, c0);
+    float ax = 0.f, ay = 0.f;
+    const float2* base = reg + y * C::SP + x;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      const float kva = es_weight(o.y + (float)a, R * R, c1, c0);
+      float rx = 0.f, ry = 0.f;
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        const float2 v = base[a * C::SP + b];
+        rx += v.x * ku[b];
+        ry += v.y * ku[b];
+      }
+      ax += rx * kva;
+      ay += ry * kva;
+    }
+    out[perm ? perm[sidx] : sidx] = {ax, ay};
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Host launchers
 // ----------------------------------------------------------------------------
@@ -1417,11 +1489,17 @@ static void launch_spread(pc_plan* p, const cpx<R>* vals, const int32_t* perm, h
 
 template <typename R, int W>
 static void launch_interp_w(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStream_t s) {
-  const unsigned nb = (unsigned)((p->L + 255) / 256);
   const double rb = sizeof(R);
   ProfScope ps(p, s, "interp", p->L * (4 + 4 * rb) + 2 * rb * p->g.nu * p->g.nv, (double)p->L);
-  hipLaunchKernelGGL((interp_kernel<R, W>), dim3(nb), dim3(256), 0, s, p->g, p->L, p->cell,
-                     (const R*)p->off, (const cpx<R>*)p->grid, perm, out);
+  if constexpr (sizeof(R) == 4) {
+    hipLaunchKernelGGL((interp_lds_kernel<W>), dim3((unsigned)p->n_interp), dim3(64), 0, s, p->g,
+                       p->interp, p->cell, (const float*)p->off, (const c32*)p->grid, perm,
+                       (c32*)out);
+  } else {
+    const unsigned nb = (unsigned)((p->L + 255) / 256);
+    hipLaunchKernelGGL((interp_kernel<R, W>), dim3(nb), dim3(256), 0, s, p->g, p->L, p->cell,
+                       (const R*)p->off, (const cpx<R>*)p->grid, perm, out);
+  }
   PC_LAUNCH_CHECK("interp");
 }
 
@@ -1811,6 +1889,7 @@ void adjoint_grid_batch(BatchCtx& ctx, pc_plan* const* plans, const c32* const* 
     J.scale = scales ? scales[j] : 1.0f;
     J.maxkey = p->maxkey;
     J.positive = p->max_positive;
+    J.rows = nullptr;
     // one entry per workgroup: a group of four items, or one item
     for (size_t c = 0; c < p->chunk_work.size(); ++c)
       sitems.push_back({p->chunk_work[c], make_int2(j, (int)c)});

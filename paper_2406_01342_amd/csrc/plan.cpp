@@ -193,6 +193,7 @@ struct Layout {
   std::vector<SpreadChunk> chunks;
   std::vector<FoldItem> fold;
   std::vector<uint8_t> tile_flags;      // 1 if any footprint reaches the tile
+  std::vector<InterpItem> interp;       // interpolation work list
   int64_t n_partials = 0;
   bool quads = false;                   // chunks grouped by workgroup (see SpreadChunk)
   std::vector<int32_t> group_work;      // per workgroup: its longest item's visibilities
@@ -472,6 +473,12 @@ static Layout build_layout(const pc_geometry* geo, bool full) {
       // Tiles no footprint reaches get no work item and are never written;
       // the first FFT pass reads them as zeros from the occupancy flags.
       lay.tile_flags[t] = totals[t] > 0 ? 1 : 0;
+      // interpolation: the tile's own visibilities (first cell inside it)
+      for (int64_t q = bstart[t * 4]; q < bstart[t * 4 + 4]; q += kInterpChunk)
+        lay.interp.push_back(InterpItem{(int32_t)t, (int32_t)q,
+                                        (int32_t)std::min<int64_t>(q + kInterpChunk,
+                                                                   bstart[t * 4 + 4]),
+                                        0});
     }
   lay.quads = geo->precision == PC_PREC_FP32 && W <= 8;
   if (lay.quads) {
@@ -682,6 +689,7 @@ static size_t layout_bytes(const Layout& lay, int prec) {
   add(lay.chunks.size() * sizeof(SpreadChunk));
   add(lay.fold.size() * sizeof(FoldItem));
   add(lay.tile_flags.size());
+  add(lay.interp.size() * sizeof(InterpItem));
   add((size_t)g.nu * g.nv * cb);             // grid band
   add((size_t)g.nv * g.n * cb);              // H
   add((size_t)lay.n_partials * kTile * kTile * cb);
@@ -729,6 +737,7 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     p->n_chunks = (int64_t)lay.chunks.size();
     p->n_partials = lay.n_partials;
     p->n_fold = (int64_t)lay.fold.size();
+    p->n_interp = (int64_t)lay.interp.size();
     p->spread_quads = lay.quads;
     p->chunk_work = lay.group_work;
     const GridGeom& g = lay.g;
@@ -743,6 +752,7 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
     p->chunks = (SpreadChunk*)dalloc(p, lay.chunks.size() * sizeof(SpreadChunk));
     p->fold = (FoldItem*)dalloc(p, lay.fold.size() * sizeof(FoldItem));
     p->tile_flags = (uint8_t*)dalloc(p, lay.tile_flags.size());
+    p->interp = (InterpItem*)dalloc(p, lay.interp.size() * sizeof(InterpItem));
     p->grid = dalloc(p, (size_t)g.nu * g.nv * cb);
     p->H = dalloc(p, (size_t)g.nv * g.n * cb);
     p->partials = dalloc(p, (size_t)lay.n_partials * kTile * kTile * cb);
@@ -774,6 +784,8 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
       PC_HIP(hipMemcpyAsync(p->chunks, lay.chunks.data(), lay.chunks.size() * sizeof(SpreadChunk),
                             hipMemcpyHostToDevice, s));
     PC_HIP(hipMemcpyAsync(p->tile_flags, lay.tile_flags.data(), lay.tile_flags.size(),
+                          hipMemcpyHostToDevice, s));
+    PC_HIP(hipMemcpyAsync(p->interp, lay.interp.data(), lay.interp.size() * sizeof(InterpItem),
                           hipMemcpyHostToDevice, s));
     if (!lay.fold.empty())
       PC_HIP(hipMemcpyAsync(p->fold, lay.fold.data(), lay.fold.size() * sizeof(FoldItem),
