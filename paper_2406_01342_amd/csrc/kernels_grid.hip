@@ -771,7 +771,10 @@ __device__ __forceinline__ int xcd_local(int b, int n) {
 }
 
 // Row masks (see RowMask): copied into LDS by the passes that test a row per
-// element; the whole-row passes test their workgroup's rows once.
+// element; the whole-row passes test their workgroup's rows once.  The pass
+// kernels carry a MASKED flag only so that launches with a mask appear under
+// their own symbols in traces: the code reads the mask pointer at run time in
+// both, exactly as the batched passes do.
 __device__ __forceinline__ bool row_set(const uint32_t* bits, int i) {
   return (bits[i >> 5] >> (i & 31)) & 1u;
 }
@@ -892,7 +895,7 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
   }
 }
 
-template <typename R, int M, int NB, int NT>
+template <typename R, int M, int NB, int NT, bool MASKED>
 __global__ __launch_bounds__(NT) void passA_adj_kernel(GridGeom g, const cpx<R>* __restrict__ grid,
                                                         const uint8_t* __restrict__ tile_flags,
                                                         cpx<R>* __restrict__ H,
@@ -1069,7 +1072,7 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
   }
 }
 
-template <typename R, int M, int NB, int NT>
+template <typename R, int M, int NB, int NT, bool MASKED>
 __global__ __launch_bounds__(NT) void passB_adj_kernel(GridGeom g, const cpx<R>* __restrict__ H,
                                                         R* __restrict__ image,
                                                         const cpx<R>* __restrict__ tw,
@@ -1272,7 +1275,7 @@ __device__ __forceinline__ void passB_fwd_body(const GridGeom& g, const R* __res
   lds_fft_store<R, M, NB, NT, -1, first_radix(M)>(buf, tws, keep, store);
 }
 
-template <typename R, int M, int NB, int NT>
+template <typename R, int M, int NB, int NT, bool MASKED>
 __global__ __launch_bounds__(NT) void passB_fwd_kernel(GridGeom g, const R* __restrict__ image,
                                                         cpx<R>* __restrict__ H,
                                                         const cpx<R>* __restrict__ tw,
@@ -1284,7 +1287,7 @@ __global__ __launch_bounds__(NT) void passB_fwd_kernel(GridGeom g, const R* __re
 // Forward pass A^T: NB band rows v; FFT along u (sign -1) of H[v][:] placed
 // at the n central frequencies (first stage applied while loading); the band
 // columns stored from the last stage's registers.
-template <typename R, int M, int NB, int NT>
+template <typename R, int M, int NB, int NT, bool MASKED>
 __global__ __launch_bounds__(NT) void passA_fwd_kernel(GridGeom g, const cpx<R>* __restrict__ H,
                                                         cpx<R>* __restrict__ grid,
                                                         const cpx<R>* __restrict__ tw,
@@ -1363,7 +1366,9 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
 // and lower edges, all that its visibilities' footprints reach, into LDS
 // (cells outside the band as zeros; with a periodic band, wrapped), then each
 // lane sums the W x W taps of one visibility from there, rows of taps in the
-// same order as interp_kernel.
+// same order as interp_kernel.  With base (plan order, plan-order output),
+// the output is base - Phi x: the residual, in the same FP32 subtraction a
+// separate pass would do.
 template <int W>
 struct InterpCfg {
   static constexpr int S = kTile + W - 1;  // region side (cells)
@@ -1377,6 +1382,7 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
                                                         const float* __restrict__ off,
                                                         const c32* __restrict__ grid,
                                                         const int32_t* __restrict__ perm,
+                                                        const c32* __restrict__ base,
                                                         c32* __restrict__ out) {
   using C = InterpCfg<W>;
   __shared__ float2 reg[C::S * C::SP];
@@ -1411,21 +1417,26 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
 #pragma unroll
     for (int t = 0; t < W; ++t) ku[t] = es_weight(o.x + (float)t, R * R, c1, c0);
     float ax = 0.f, ay = 0.f;
-    const float2* base = reg + y * C::SP + x;
+    const float2* rp = reg + y * C::SP + x;
 #pragma unroll
     for (int a = 0; a < W; ++a) {
       const float kva = es_weight(o.y + (float)a, R * R, c1, c0);
       float rx = 0.f, ry = 0.f;
 #pragma unroll
       for (int b = 0; b < W; ++b) {
-        const float2 v = base[a * C::SP + b];
+        const float2 v = rp[a * C::SP + b];
         rx += v.x * ku[b];
         ry += v.y * ku[b];
       }
       ax += rx * kva;
       ay += ry * kva;
     }
-    out[perm ? perm[sidx] : sidx] = {ax, ay};
+    if (base) {
+      const c32 v = base[sidx];
+      out[sidx] = {v.x - ax, v.y - ay};
+    } else {
+      out[perm ? perm[sidx] : sidx] = {ax, ay};
+    }
   }
 }
 
@@ -1488,14 +1499,17 @@ static void launch_spread(pc_plan* p, const cpx<R>* vals, const int32_t* perm, h
 }
 
 template <typename R, int W>
-static void launch_interp_w(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStream_t s) {
+static void launch_interp_w(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStream_t s,
+                            const cpx<R>* base) {
   const double rb = sizeof(R);
-  ProfScope ps(p, s, "interp", p->L * (4 + 4 * rb) + 2 * rb * p->g.nu * p->g.nv, (double)p->L);
+  ProfScope ps(p, s, "interp", p->L * (4 + 4 * rb + (base ? 2 * rb : 0)) +
+                                   2 * rb * p->g.nu * p->g.nv, (double)p->L);
   if constexpr (sizeof(R) == 4) {
     hipLaunchKernelGGL((interp_lds_kernel<W>), dim3((unsigned)p->n_interp), dim3(64), 0, s, p->g,
                        p->interp, p->cell, (const float*)p->off, (const c32*)p->grid, perm,
-                       (c32*)out);
+                       (const c32*)base, (c32*)out);
   } else {
+    if (base) fail(PC_ERR_UNSUPPORTED, "FP64 interpolation with a base");
     const unsigned nb = (unsigned)((p->L + 255) / 256);
     hipLaunchKernelGGL((interp_kernel<R, W>), dim3(nb), dim3(256), 0, s, p->g, p->L, p->cell,
                        (const R*)p->off, (const cpx<R>*)p->grid, perm, out);
@@ -1504,11 +1518,12 @@ static void launch_interp_w(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStr
 }
 
 template <typename R>
-static void launch_interp(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStream_t s) {
+static void launch_interp(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStream_t s,
+                          const cpx<R>* base = nullptr) {
   switch (p->g.W) {
 #define PC_W(w) \
   case w:       \
-    launch_interp_w<R, w>(p, perm, out, s); \
+    launch_interp_w<R, w>(p, perm, out, s, base); \
     break;
     PC_W(2) PC_W(3) PC_W(4) PC_W(5) PC_W(6) PC_W(7) PC_W(8) PC_W(9) PC_W(10) PC_W(11) PC_W(12)
     PC_W(13) PC_W(14) PC_W(15) PC_W(16)
@@ -1563,13 +1578,20 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
   const uint32_t* bits = rows ? rows->bits : nullptr;
   const double nr = rows ? (double)rows->count : (double)g.n;
   const double nvr = (double)g.nv * nr * CB;
-  set_lds((const void*)passA_adj_kernel<R, M, NBA, NTA>, lda);
   {
     ProfScope ps(p, s, rows ? "passA_adj_rows" : "passA_adj", (double)g.nv * g.nu * CB + nvr,
                  (double)g.nv * M);
-    hipLaunchKernelGGL((passA_adj_kernel<R, M, NBA, NTA>), dim3((g.nv + NBA - 1) / NBA), dim3(NTA),
-                       lda, s, g, (const cpx<R>*)p->grid, p->tile_flags, (cpx<R>*)p->H,
-                       (const cpx<R>*)p->twiddle, bits);
+#define PC_PASS_A(MASKED)                                                                      \
+  set_lds((const void*)passA_adj_kernel<R, M, NBA, NTA, MASKED>, lda);                         \
+  hipLaunchKernelGGL((passA_adj_kernel<R, M, NBA, NTA, MASKED>), dim3((g.nv + NBA - 1) / NBA), \
+                     dim3(NTA), lda, s, g, (const cpx<R>*)p->grid, p->tile_flags,              \
+                     (cpx<R>*)p->H, (const cpx<R>*)p->twiddle, bits)
+    if (rows) {
+      PC_PASS_A(true);
+    } else {
+      PC_PASS_A(false);
+    }
+#undef PC_PASS_A
     PC_LAUNCH_CHECK("passA_adj");
   }
   if (wp) {  // one w-plane: rotate, add into the image
@@ -1582,12 +1604,19 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
     PC_LAUNCH_CHECK("passB_adj_w");
     return;
   }
-  set_lds((const void*)passB_adj_kernel<R, M, NBB, NTB>, ldb);
   ProfScope ps(p, s, rows ? "passB_adj_rows" : "passB_adj",
                nvr + nr * g.n * sizeof(R), nr * M);
-  hipLaunchKernelGGL((passB_adj_kernel<R, M, NBB, NTB>), dim3((M / 2) / NBB), dim3(NTB), ldb, s, g,
-                     (const cpx<R>*)p->H, image, (const cpx<R>*)p->twiddle, (const R*)p->corr,
-                     scale, rows ? nullptr : p->maxkey, p->max_positive, bits);
+#define PC_PASS_B(MASKED)                                                                       \
+  set_lds((const void*)passB_adj_kernel<R, M, NBB, NTB, MASKED>, ldb);                          \
+  hipLaunchKernelGGL((passB_adj_kernel<R, M, NBB, NTB, MASKED>), dim3((M / 2) / NBB), dim3(NTB), \
+                     ldb, s, g, (const cpx<R>*)p->H, image, (const cpx<R>*)p->twiddle,          \
+                     (const R*)p->corr, scale, rows ? nullptr : p->maxkey, p->max_positive, bits)
+  if (rows) {
+    PC_PASS_B(true);
+  } else {
+    PC_PASS_B(false);
+  }
+#undef PC_PASS_B
   PC_LAUNCH_CHECK("passB_adj");
 }
 
@@ -1604,19 +1633,34 @@ static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s,
   const uint32_t* bits = rows ? rows->bits : nullptr;
   const double nr = rows ? (double)rows->count : (double)g.n;
   const double nvr = (double)g.nv * nr * CB;
-  set_lds((const void*)passB_fwd_kernel<R, M, NBB, NTB>, ldb);
   {
-  ProfScope ps(p, s, rows ? "passB_fwd_rows" : "passB_fwd", nvr + nr * g.n * sizeof(R), nr * M);
-  hipLaunchKernelGGL((passB_fwd_kernel<R, M, NBB, NTB>), dim3((M / 2) / NBB), dim3(NTB), ldb, s,
-                     g, image, (cpx<R>*)p->H, (const cpx<R>*)p->twiddle, (const R*)p->corr, bits);
-  PC_LAUNCH_CHECK("passB_fwd");
+    ProfScope ps(p, s, rows ? "passB_fwd_rows" : "passB_fwd", nvr + nr * g.n * sizeof(R), nr * M);
+#define PC_PASS_BF(MASKED)                                                                      \
+  set_lds((const void*)passB_fwd_kernel<R, M, NBB, NTB, MASKED>, ldb);                          \
+  hipLaunchKernelGGL((passB_fwd_kernel<R, M, NBB, NTB, MASKED>), dim3((M / 2) / NBB), dim3(NTB), \
+                     ldb, s, g, image, (cpx<R>*)p->H, (const cpx<R>*)p->twiddle,                \
+                     (const R*)p->corr, bits)
+    if (rows) {
+      PC_PASS_BF(true);
+    } else {
+      PC_PASS_BF(false);
+    }
+#undef PC_PASS_BF
+    PC_LAUNCH_CHECK("passB_fwd");
   }
-  set_lds((const void*)passA_fwd_kernel<R, M, NBA, NTA>, lda);
   ProfScope ps(p, s, rows ? "passA_fwd_rows" : "passA_fwd", (double)g.nv * g.nu * CB + nvr,
                (double)g.nv * M);
-  hipLaunchKernelGGL((passA_fwd_kernel<R, M, NBA, NTA>), dim3((g.nv + NBA - 1) / NBA), dim3(NTA),
-                     lda, s, g, (const cpx<R>*)p->H, (cpx<R>*)p->grid, (const cpx<R>*)p->twiddle,
-                     bits);
+#define PC_PASS_AF(MASKED)                                                                      \
+  set_lds((const void*)passA_fwd_kernel<R, M, NBA, NTA, MASKED>, lda);                          \
+  hipLaunchKernelGGL((passA_fwd_kernel<R, M, NBA, NTA, MASKED>), dim3((g.nv + NBA - 1) / NBA),  \
+                     dim3(NTA), lda, s, g, (const cpx<R>*)p->H, (cpx<R>*)p->grid,               \
+                     (const cpx<R>*)p->twiddle, bits)
+  if (rows) {
+    PC_PASS_AF(true);
+  } else {
+    PC_PASS_AF(false);
+  }
+#undef PC_PASS_AF
   PC_LAUNCH_CHECK("passA_fwd");
 }
 
@@ -1708,12 +1752,13 @@ void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R sc
 
 template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted, hipStream_t s,
-                  const RowMask* rows) {
+                  const RowMask* rows, const cpx<R>* base) {
   if (p->Cw)
     fail(PC_ERR_UNSUPPORTED,
          "the gridded forward operator needs a coplanar plan (w = 0); the direct sums take w");
+  if (base && !out_sorted) fail(PC_ERR_INVALID_ARG, "forward_grid: a base needs plan order");
   dispatch_M<R>(p, false, nullptr, image, R(1), s, nullptr, rows);
-  launch_interp<R>(p, out_sorted ? nullptr : p->perm, vis_out, s);
+  launch_interp<R>(p, out_sorted ? nullptr : p->perm, vis_out, s, base);
 }
 
 // ----------------------------------------------------------------------------
@@ -1966,8 +2011,8 @@ template void adjoint_grid<float>(pc_plan*, const c32*, bool, float*, float, hip
 template void adjoint_grid<double>(pc_plan*, const c64*, bool, double*, double, hipStream_t,
                                    const RowMask*);
 template void forward_grid<float>(pc_plan*, const float*, c32*, bool, hipStream_t,
-                                  const RowMask*);
+                                  const RowMask*, const c32*);
 template void forward_grid<double>(pc_plan*, const double*, c64*, bool, hipStream_t,
-                                   const RowMask*);
+                                   const RowMask*, const c64*);
 
 }  // namespace pc

@@ -15,7 +15,8 @@
 // gap are FP64.  The restricted solve stops when the relative duality gap
 // of the restricted problem at the gradient point y is <= tau_k =
 // max(tau_min, tau_0 g_k), g_k the full problem's relative gap at the current
-// iterate (tested at steps 1, 1 + kCheck, ...), returning the proximal step
+// iterate (tested at every step when steps are expensive, else at steps 1,
+// 1 + kCheck, ...), returning the proximal step
 // taken from y, or at the iteration cap.  Duality gaps use the dual point
 // nu = min(1, lambda / ||Phi* r||_inf) r.
 #include <algorithm>
@@ -80,7 +81,11 @@ struct KeepDevArray {
   ~KeepDevArray() { pool_release(dev, ptr, bytes); }
 };
 
-constexpr int kCheck = 4;        // APGD convergence test cadence
+constexpr int kCheck = 4;        // APGD convergence test cadence (cheap steps)
+// Direct-sum steps over more visibility-atom pairs than this (about 170 us)
+// are tested every step, as are gridded ones: the test's reduction and host
+// round trip are then small against a step.
+constexpr double kCheckEveryPairs = 5e8;
 constexpr int64_t kFirstCandidates = 4096;  // candidates read back with their count
 // Pinned host staging for uploads and small readbacks.  Its copies are
 // asynchronous; `fence` records the stream position of the last use so that
@@ -462,10 +467,11 @@ struct Pfw {
       dict_synthesis(p, dict, nS, pix.ptr, w, dimg.ptr, s);
       forward_grid<float>(p, dimg.ptr, out, true, s);
       k_fill(p, N, 0.0f, dimg.ptr, s);
-    } else {
+    } else {  // (the residual formed by the interpolation itself)
       k_scatter(p, nS, pix.ptr, w, dimg.ptr, s);
-      forward_grid<float>(p, dimg.ptr, out, true, s, rows_of_set());
+      forward_grid<float>(p, dimg.ptr, out, true, s, rows_of_set(), base ? V.ptr : nullptr);
       k_scatter(p, nS, pix.ptr, nullptr, dimg.ptr, s);
+      return;
     }
     if (base) k_rsub(p, L, V.ptr, out, s);
   }
@@ -522,7 +528,7 @@ struct Pfw {
   // the iterate (S, xs): step 4 of Alg. 2, also run once for a warm start.
   void assess(int k_next) {
     load_active(S, xs);
-    const bool gridded = ms || (int64_t)S.size() >= 4 * grid_thr;
+    const bool gridded = ms || (int64_t)S.size() >= grid_thr;
     double r2, vr;
     if (batcher && !gridded) {
       // the residual's direct sums run in the batcher's shared launch ahead
@@ -947,8 +953,9 @@ struct Pfw {
         // small direct sets: forward and restricted adjoint share one pass
         const bool fused = !gridded && fused_supported(nS);
         const int64_t nwg = fused ? fused_partial_stride(p, nS) : adjoint_partial_stride(p, nS);
+        const int every = (gridded || (double)L * (double)nS > kCheckEveryPairs) ? 1 : kCheck;
         for (inner = 1; inner <= prm.inner_max_iter; ++inner) {
-          const bool check = (inner - 1) % kCheck == 0;
+          const bool check = (inner - 1) % every == 0;
           if (fused)  // r_y is needed only by the convergence test
             forward_adjoint_atoms(p, nS, atoms.ptr, V.ptr, check ? r.ptr : nullptr,
                                   adj_partial.ptr, s);
