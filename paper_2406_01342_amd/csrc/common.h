@@ -342,10 +342,13 @@ constexpr int kMaxRowWords = 8192 / 32;  // npix <= 8192
 template <typename R>
 void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R scale,
                   hipStream_t s, const RowMask* rows = nullptr);
-// With base (plan order; out_sorted, FP32): vis_out = base - Phi image.
+// With base (plan order; out_sorted, FP32): vis_out = base - Phi image, and
+// with stats (2 p->n_interp doubles) the per-work-item sums of |vis_out|^2
+// and Re(conj(base) vis_out), to be summed in order (k_resid_final).
 template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted,
-                  hipStream_t s, const RowMask* rows = nullptr, const cpx<R>* base = nullptr);
+                  hipStream_t s, const RowMask* rows = nullptr, const cpx<R>* base = nullptr,
+                  double* stats = nullptr);
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax);
 // Launch tables of the batched adjoint (device copy and pinned staging),
 // reused from call to call.

@@ -1368,7 +1368,9 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
 // lane sums the W x W taps of one visibility from there, rows of taps in the
 // same order as interp_kernel.  With base (plan order, plan-order output),
 // the output is base - Phi x: the residual, in the same FP32 subtraction a
-// separate pass would do.
+// separate pass would do; with stats as well, each work item also writes
+// its sums of |r|^2 and Re(conj(base) r) in FP64 to stats[2 item], [2 item
+// + 1] (lanes in a fixed order).
 template <int W>
 struct InterpCfg {
   static constexpr int S = kTile + W - 1;  // region side (cells)
@@ -1383,7 +1385,8 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
                                                         const c32* __restrict__ grid,
                                                         const int32_t* __restrict__ perm,
                                                         const c32* __restrict__ base,
-                                                        c32* __restrict__ out) {
+                                                        c32* __restrict__ out,
+                                                        double* __restrict__ stats) {
   using C = InterpCfg<W>;
   __shared__ float2 reg[C::S * C::SP];
   const InterpItem it = items[blockIdx.x];
@@ -1409,6 +1412,7 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
   const float c0 = g.beta * 1.44269504088896341f;  // beta log2(e)
   const float c1 = c0 / R;
   const int ou = g.u0 + ru0, ov = g.v0 + rv0;
+  double r2 = 0.0, vr = 0.0;
   for (int sidx = it.beg + lane; sidx < it.end; sidx += 64) {
     const uint32_t c = cell[sidx];
     const int x = (int)(c & 0xffffu) - ou, y = (int)(c >> 16) - ov;  // in [0, kTile)
@@ -1433,9 +1437,22 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
     }
     if (base) {
       const c32 v = base[sidx];
-      out[sidx] = {v.x - ax, v.y - ay};
+      const c32 r = {v.x - ax, v.y - ay};
+      out[sidx] = r;
+      r2 += (double)r.x * r.x + (double)r.y * r.y;
+      vr += (double)v.x * r.x + (double)v.y * r.y;
     } else {
       out[perm ? perm[sidx] : sidx] = {ax, ay};
+    }
+  }
+  if (stats) {
+    for (int o = 32; o > 0; o >>= 1) {
+      r2 += __shfl_xor(r2, o, 64);
+      vr += __shfl_xor(vr, o, 64);
+    }
+    if (lane == 0) {
+      stats[2 * (size_t)blockIdx.x] = r2;
+      stats[2 * (size_t)blockIdx.x + 1] = vr;
     }
   }
 }
@@ -1500,14 +1517,14 @@ static void launch_spread(pc_plan* p, const cpx<R>* vals, const int32_t* perm, h
 
 template <typename R, int W>
 static void launch_interp_w(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStream_t s,
-                            const cpx<R>* base) {
+                            const cpx<R>* base, double* stats) {
   const double rb = sizeof(R);
   ProfScope ps(p, s, "interp", p->L * (4 + 4 * rb + (base ? 2 * rb : 0)) +
                                    2 * rb * p->g.nu * p->g.nv, (double)p->L);
   if constexpr (sizeof(R) == 4) {
     hipLaunchKernelGGL((interp_lds_kernel<W>), dim3((unsigned)p->n_interp), dim3(64), 0, s, p->g,
                        p->interp, p->cell, (const float*)p->off, (const c32*)p->grid, perm,
-                       (const c32*)base, (c32*)out);
+                       (const c32*)base, (c32*)out, base ? stats : nullptr);
   } else {
     if (base) fail(PC_ERR_UNSUPPORTED, "FP64 interpolation with a base");
     const unsigned nb = (unsigned)((p->L + 255) / 256);
@@ -1519,11 +1536,11 @@ static void launch_interp_w(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStr
 
 template <typename R>
 static void launch_interp(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStream_t s,
-                          const cpx<R>* base = nullptr) {
+                          const cpx<R>* base = nullptr, double* stats = nullptr) {
   switch (p->g.W) {
 #define PC_W(w) \
   case w:       \
-    launch_interp_w<R, w>(p, perm, out, s, base); \
+    launch_interp_w<R, w>(p, perm, out, s, base, stats); \
     break;
     PC_W(2) PC_W(3) PC_W(4) PC_W(5) PC_W(6) PC_W(7) PC_W(8) PC_W(9) PC_W(10) PC_W(11) PC_W(12)
     PC_W(13) PC_W(14) PC_W(15) PC_W(16)
@@ -1752,13 +1769,13 @@ void adjoint_grid(pc_plan* p, const cpx<R>* vis, bool vis_sorted, R* image, R sc
 
 template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted, hipStream_t s,
-                  const RowMask* rows, const cpx<R>* base) {
+                  const RowMask* rows, const cpx<R>* base, double* stats) {
   if (p->Cw)
     fail(PC_ERR_UNSUPPORTED,
          "the gridded forward operator needs a coplanar plan (w = 0); the direct sums take w");
   if (base && !out_sorted) fail(PC_ERR_INVALID_ARG, "forward_grid: a base needs plan order");
   dispatch_M<R>(p, false, nullptr, image, R(1), s, nullptr, rows);
-  launch_interp<R>(p, out_sorted ? nullptr : p->perm, vis_out, s, base);
+  launch_interp<R>(p, out_sorted ? nullptr : p->perm, vis_out, s, base, stats);
 }
 
 // ----------------------------------------------------------------------------
@@ -2011,8 +2028,8 @@ template void adjoint_grid<float>(pc_plan*, const c32*, bool, float*, float, hip
 template void adjoint_grid<double>(pc_plan*, const c64*, bool, double*, double, hipStream_t,
                                    const RowMask*);
 template void forward_grid<float>(pc_plan*, const float*, c32*, bool, hipStream_t,
-                                  const RowMask*, const c32*);
+                                  const RowMask*, const c32*, double*);
 template void forward_grid<double>(pc_plan*, const double*, c64*, bool, hipStream_t,
-                                   const RowMask*, const c64*);
+                                   const RowMask*, const c64*, double*);
 
 }  // namespace pc

@@ -70,6 +70,44 @@ __global__ __launch_bounds__(256) void resid_final_kernel(int nblocks,
   }
 }
 
+// The same sum for many partials (one per interpolation work item): 1024
+// threads, each summing every 1024th pair with four pairs' loads in flight
+// (pairs q, q + 1024, q + 2048, q + 3072 of each round, added in that order),
+// then a tree over the threads.
+__global__ __launch_bounds__(1024) void parts_final_kernel(int nparts,
+                                                           const double2* __restrict__ partial,
+                                                           double* __restrict__ out) {
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < nparts; i += 4 * 1024) {
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = i + u * 1024;
+      v[u] = q < nparts ? partial[q] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a += v[u].x;
+      b += v[u].y;
+    }
+  }
+  __shared__ double sa[1024], sb[1024];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sa[0];
+    out[1] = sb[0];
+  }
+}
+
 // Appends j to out[0..cap) for every lane with pred set: one atomic per wave
 // (the wave's count, taken by its lowest selecting lane), then each lane
 // writes at the base plus the number of selecting lanes below it.
@@ -719,6 +757,13 @@ void k_resid(pc_plan* p, int64_t L, const c32* r, const c32* V, double* partial,
   hipLaunchKernelGGL(resid_partial_kernel, dim3(nb), dim3(256), 0, s, L, r, V, partial);
   PC_LAUNCH_CHECK("resid_partial");
   hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(256), 0, s, nb, partial, out);
+  PC_LAUNCH_CHECK("resid_final");
+}
+
+void k_resid_final(pc_plan* p, int nparts, const double* partial, double* out, hipStream_t s) {
+  ProfScope ps(p, s, "resid_final", 16.0 * nparts, (double)nparts);
+  hipLaunchKernelGGL(parts_final_kernel, dim3(1), dim3(1024), 0, s, nparts,
+                     (const double2*)partial, out);
   PC_LAUNCH_CHECK("resid_final");
 }
 

@@ -225,6 +225,9 @@ struct Pfw {
   bool pre_ok = false;
   DevArray<double> act_blk;  // uploaded [x | pix | row mask] of the active set
   RowMask act_rows{nullptr, 0};  // image rows holding atoms (inside act_blk)
+  // partial residual statistics left in red_partial by the last op_forward
+  // (its interpolation's work items), 0 when it left none
+  int64_t resid_parts = 0;
   DevArray<Atom<float>> off_atoms;
   DevArray<double> b_partial;  // partials of b's sums when batched beside the psf sums
   double v2 = 0;  // ||V||^2
@@ -458,6 +461,7 @@ struct Pfw {
   // direct path takes the weights from the atom table; the gridded one
   // scatters w into the (zero) dense image, interpolates, and clears it.
   void op_forward(bool gridded, int64_t nS, const double* w, bool base, c32* out) {
+    resid_parts = 0;
     if (!gridded) {
       forward_atoms<float>(p, nS, atoms.ptr, base ? V.ptr : nullptr, true, out, true, s);
       return;
@@ -467,10 +471,13 @@ struct Pfw {
       dict_synthesis(p, dict, nS, pix.ptr, w, dimg.ptr, s);
       forward_grid<float>(p, dimg.ptr, out, true, s);
       k_fill(p, N, 0.0f, dimg.ptr, s);
-    } else {  // (the residual formed by the interpolation itself)
+    } else {  // (the residual and its statistics formed by the interpolation itself)
+      if (base) red_partial.ensure(2 * std::max<int64_t>(k_resid_blocks(L), p->n_interp));
       k_scatter(p, nS, pix.ptr, w, dimg.ptr, s);
-      forward_grid<float>(p, dimg.ptr, out, true, s, rows_of_set(), base ? V.ptr : nullptr);
+      forward_grid<float>(p, dimg.ptr, out, true, s, rows_of_set(), base ? V.ptr : nullptr,
+                          base ? red_partial.ptr : nullptr);
       k_scatter(p, nS, pix.ptr, nullptr, dimg.ptr, s);
+      resid_parts = base ? p->n_interp : 0;
       return;
     }
     if (base) k_rsub(p, L, V.ptr, out, s);
@@ -962,8 +969,12 @@ struct Pfw {
           else
             op_forward(gridded, nS, y.ptr, true, r.ptr);
           if (check) {
-            red_partial.ensure(2 * k_resid_blocks(L));
-            k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
+            if (!fused && resid_parts > 0) {
+              k_resid_final(p, (int)resid_parts, red_partial.ptr, scal.ptr + kScalResid, s);
+            } else {
+              red_partial.ensure(2 * k_resid_blocks(L));
+              k_resid(p, L, r.ptr, V.ptr, red_partial.ptr, scal.ptr + kScalResid, s);
+            }
           }
           const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
           const double mom = (t - 1.0) / tn;

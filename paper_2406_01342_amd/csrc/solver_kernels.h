@@ -59,6 +59,8 @@ void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, f
 void k_gather_img(pc_plan* p, int64_t nS, const int32_t* pix, const float* img, double* out,
                   hipStream_t s);
 void k_rsub(pc_plan* p, int64_t L, const c32* V, c32* r, hipStream_t s);
+// Sum in order of nparts (|r|^2, Re<V, r>) partial pairs into out[0..1].
+void k_resid_final(pc_plan* p, int nparts, const double* partial, double* out, hipStream_t s);
 void k_fill(pc_plan* p, int64_t N, float v, float* out, hipStream_t s);
 void k_stat_reduce(pc_plan* p, int64_t nS, const double* stat, double* scal, hipStream_t s);
 
