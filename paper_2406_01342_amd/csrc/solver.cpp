@@ -123,7 +123,8 @@ struct Pinned {
 };
 
 constexpr int kLanczosMax = 12;       // Lanczos steps per active set (cap)
-constexpr int kLanczosBatch = 4;      // device steps between host readbacks
+constexpr int kLanczosBatch = 4;      // device steps between host readbacks (cheap steps;
+                                      // one when a step is expensive, see kCheckEveryPairs)
 constexpr int kGramAtoms = 256;       // default cap of the Gram form (direct sets)
 constexpr int kGramChunk = 8;         // Gram-form APGD steps per readback after the first chunk: 2x
 constexpr int kGramNewPairs = 16;     // new sums per atom above which the Gram form is skipped
@@ -783,8 +784,12 @@ struct Pfw {
     std::vector<double> svec, Qh;
     double theta = 0, rho = 0;
     int done_steps = 0, kfin = 0;
+    // expensive steps are read back one at a time, so that none runs past
+    // the one that meets the stopping rule
+    const int batch =
+        (gridded || (double)L * (double)nS > kCheckEveryPairs) ? 1 : kLanczosBatch;
     while (kfin == 0) {
-      const int jend = std::min(jmax, done_steps + kLanczosBatch);
+      const int jend = std::min(jmax, done_steps + batch);
       for (int j = done_steps; j < jend; ++j) {
         double* qj = Qd + (int64_t)j * nS;
         if (!gridded) k_weights(p, nS, qj, atoms.ptr, s);
