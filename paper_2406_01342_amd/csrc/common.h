@@ -349,6 +349,24 @@ template <typename R>
 void forward_grid(pc_plan* p, const R* image, cpx<R>* vis_out, bool out_sorted,
                   hipStream_t s, const RowMask* rows = nullptr, const cpx<R>* base = nullptr,
                   double* stats = nullptr);
+// The gridded operators of an APGD step over an active set S (FP32,
+// coplanar): its atoms sorted by pixel (pix, nS), the occupied image rows
+// (rowlist: row, first atom, end; nrows) and their mask.  Pass B is
+// evaluated directly at those rows (forward) or atoms (adjoint), pass A with
+// the mask.  forward_grid_set: out (plan order) = base - Phi_S w (Phi_S w
+// without base), stats as forward_grid's.  adjoint_grid_set: gout[q] =
+// (Phi* vis)[pix[q]] in FP64, vis in plan order.
+struct AtomSet {
+  int64_t nS;
+  const int32_t* pix;
+  const int3* rowlist;
+  int64_t nrows;
+  RowMask rows;
+};
+void forward_grid_set(pc_plan* p, const AtomSet& as, const double* w, const c32* base,
+                      double* stats, c32* out, hipStream_t s);
+void adjoint_grid_set(pc_plan* p, const c32* vis, const AtomSet& as, double* gout,
+                      hipStream_t s);
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax);
 // Launch tables of the batched adjoint (device copy and pinned staging),
 // reused from call to call.

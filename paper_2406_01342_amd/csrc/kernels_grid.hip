@@ -1457,6 +1457,84 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
   }
 }
 
+// Pass B evaluated directly for an active set (the APGD's gridded
+// operators).  Its atoms lie on few image rows, a row holding one or two, so
+// instead of a length-M transform per row the needed values are sums over
+// the atoms or over the band rows with phases e^{-/+2 pi i f q / M} (f = j -
+// n/2 the atom's centred column, q = v0 + band row), the product f q reduced
+// mod M exactly in integers and the angle (in turns, |t| <= 1/2) taken by the
+// hardware sine and cosine.  The apodisation and 1/n factors are applied in
+// the order the transform's loading (forward) and epilogue (adjoint) apply
+// them.
+__device__ __forceinline__ float turns_mod(int f, int q, int M) {
+  int t = (f * q) & (M - 1);  // f q mod M (two's complement), f q < 2^31
+  if (t >= M / 2) t -= M;
+  return (float)t / (float)M;  // exact: M is a power of two
+}
+
+__device__ __forceinline__ float inv_n_f32(const GridGeom& g, int i, int j) {
+  const float dl = (float)g.dl;
+  const float l = (float)(i - g.n / 2) * dl, mm = (float)(j - g.n / 2) * dl;
+  return __builtin_amdgcn_rsqf(1.0f - l * l - mm * mm);
+}
+
+// Forward: H[band row][i] = sum over the atoms of row i of c e^{-2 pi i f q / M}
+// for each occupied row i (rowlist: row, first atom, end), atoms sorted by
+// pixel with FP64 weights w.
+template <int KHB>
+__global__ __launch_bounds__(256) void rows_fwd_direct_kernel(GridGeom g,
+                                                              const int3* __restrict__ rowlist,
+                                                              const int32_t* __restrict__ pix,
+                                                              const double* __restrict__ w,
+                                                              const float* __restrict__ corr,
+                                                              c32* __restrict__ H) {
+  const int3 rl = rowlist[blockIdx.y];
+  const int i = rl.x, n = g.n;
+  for (int rel = (int)(blockIdx.x * blockDim.x + threadIdx.x); rel < g.nv;
+       rel += (int)(gridDim.x * blockDim.x)) {
+    const int q = g.v0 + rel;
+    float hx = 0.f, hy = 0.f;
+    for (int a = rl.y; a < rl.z; ++a) {
+      const int j = pix[a] - i * n;
+      const float c = (float)w[a] * corr[i] * corr[j] * inv_n_f32(g, i, j);
+      const float tt = turns_mod(j - n / 2, q, g.M);
+      hx += c * __builtin_amdgcn_cosf(tt);
+      hy -= c * __builtin_amdgcn_sinf(tt);
+    }
+    H[h_index<KHB>(rel, i, g.nv)] = {hx, hy};
+  }
+}
+
+// Adjoint at the atoms: one 256-thread workgroup per atom, g = Re(sum over
+// band rows of H[band row][i] e^{+2 pi i f q / M}) times the corrections, in
+// FP64 out (thread sums combined in a fixed order).
+template <int KHB>
+__global__ __launch_bounds__(256) void atoms_adj_direct_kernel(GridGeom g,
+                                                               const int32_t* __restrict__ pix,
+                                                               const c32* __restrict__ H,
+                                                               const float* __restrict__ corr,
+                                                               double* __restrict__ gout) {
+  const int a = (int)blockIdx.x, t = (int)threadIdx.x;
+  const int pp = pix[a], n = g.n;
+  const int i = pp / n, j = pp - i * n;
+  float acc = 0.f;
+  for (int rel = t; rel < g.nv; rel += 256) {
+    const float tt = turns_mod(j - n / 2, g.v0 + rel, g.M);
+    const c32 h = H[h_index<KHB>(rel, i, g.nv)];
+    acc += h.x * __builtin_amdgcn_cosf(tt) - h.y * __builtin_amdgcn_sinf(tt);
+  }
+  double d = acc;
+  for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+  __shared__ double wsum[4];
+  if ((t & 63) == 0) wsum[t >> 6] = d;
+  __syncthreads();
+  if (t == 0) {
+    const double sum = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    const float v = (float)sum * corr[i] * corr[j] * inv_n_f32(g, i, j);
+    gout[a] = (double)v;
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Host launchers
 // ----------------------------------------------------------------------------
@@ -1581,7 +1659,8 @@ constexpr int nt_for() {
 
 template <typename R, int M>
 static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
-                           const WPlane* wp = nullptr, const RowMask* rows = nullptr) {
+                           const WPlane* wp = nullptr, const RowMask* rows = nullptr,
+                           bool pass_b = true) {
   constexpr int CB = sizeof(cpx<R>);
   constexpr int NBA = (M * CB >= Shapes<R>::lds_a) ? 1 : Shapes<R>::lds_a / (M * CB);
   constexpr int NTA = nt_for<NBA * M / 16>();
@@ -1611,6 +1690,7 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
 #undef PC_PASS_A
     PC_LAUNCH_CHECK("passA_adj");
   }
+  if (!pass_b) return;  // (the caller evaluates pass B itself)
   if (wp) {  // one w-plane: rotate, add into the image
     set_lds((const void*)passB_adj_w_kernel<R, M, NBB, NTB>, ldb);
     ProfScope ps(p, s, "passB_adj_w", nvn + (double)g.n * g.n * sizeof(R) * (wp->first ? 1 : 2),
@@ -1639,7 +1719,7 @@ static void run_passes_adj(pc_plan* p, R* image, R scale, hipStream_t s,
 
 template <typename R, int M>
 static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s,
-                           const RowMask* rows = nullptr) {
+                           const RowMask* rows = nullptr, bool pass_b = true) {
   constexpr int CB = sizeof(cpx<R>);
   constexpr int NBA = (M * CB >= Shapes<R>::lds_a) ? 1 : Shapes<R>::lds_a / (M * CB);
   constexpr int NTA = nt_for<NBA * M / 16>();
@@ -1650,7 +1730,7 @@ static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s,
   const uint32_t* bits = rows ? rows->bits : nullptr;
   const double nr = rows ? (double)rows->count : (double)g.n;
   const double nvr = (double)g.nv * nr * CB;
-  {
+  if (pass_b) {  // (else the caller has written the pass-A buffer's columns)
     ProfScope ps(p, s, rows ? "passB_fwd_rows" : "passB_fwd", nvr + nr * g.n * sizeof(R), nr * M);
 #define PC_PASS_BF(MASKED)                                                                      \
   set_lds((const void*)passB_fwd_kernel<R, M, NBB, NTB, MASKED>, ldb);                          \
@@ -1683,23 +1763,24 @@ static void run_passes_fwd(pc_plan* p, const R* image, hipStream_t s,
 
 template <typename R>
 static void dispatch_M(pc_plan* p, bool adjoint, R* img_out, const R* img_in, R scale,
-                       hipStream_t s, const WPlane* wp = nullptr, const RowMask* rows = nullptr) {
+                       hipStream_t s, const WPlane* wp = nullptr, const RowMask* rows = nullptr,
+                       bool pass_b = true) {
   switch (p->g.M) {
-#define PC_M(m)                                             \
-  case m:                                                   \
-    if (adjoint)                                            \
-      run_passes_adj<R, m>(p, img_out, scale, s, wp, rows); \
-    else                                                    \
-      run_passes_fwd<R, m>(p, img_in, s, rows);             \
+#define PC_M(m)                                                     \
+  case m:                                                           \
+    if (adjoint)                                                    \
+      run_passes_adj<R, m>(p, img_out, scale, s, wp, rows, pass_b); \
+    else                                                            \
+      run_passes_fwd<R, m>(p, img_in, s, rows, pass_b);             \
     return;
     PC_M(32) PC_M(64) PC_M(128) PC_M(256) PC_M(512) PC_M(1024) PC_M(2048) PC_M(4096) PC_M(8192)
 #undef PC_M
     case 16384:
       if constexpr (sizeof(R) == 4) {
         if (adjoint)
-          run_passes_adj<R, 16384>(p, img_out, scale, s, wp, rows);
+          run_passes_adj<R, 16384>(p, img_out, scale, s, wp, rows, pass_b);
         else
-          run_passes_fwd<R, 16384>(p, img_in, s, rows);
+          run_passes_fwd<R, 16384>(p, img_in, s, rows, pass_b);
         return;
       }
       [[fallthrough]];
@@ -1709,6 +1790,45 @@ static void dispatch_M(pc_plan* p, bool adjoint, R* img_out, const R* img_in, R 
   }
 }
 
+
+void forward_grid_set(pc_plan* p, const AtomSet& as, const double* w, const c32* base,
+                      double* stats, c32* out, hipStream_t s) {
+  if (p->Cw || p->precision != PC_PREC_FP32)
+    fail(PC_ERR_UNSUPPORTED, "gridded set operators need a coplanar FP32 plan");
+  const GridGeom& g = p->g;
+  {
+    ProfScope ps(p, s, "passB_fwd_set", 8.0 * g.nv * as.rows.count + 12.0 * as.nS,
+                 (double)g.nv * as.nS);
+    const dim3 grid((unsigned)((g.nv + 255) / 256), (unsigned)as.nrows);
+    if (g.M >= 8192)
+      hipLaunchKernelGGL((rows_fwd_direct_kernel<khb_for<8192>()>), grid, dim3(256), 0, s, g,
+                         as.rowlist, as.pix, w, (const float*)p->corr, (c32*)p->H);
+    else
+      hipLaunchKernelGGL((rows_fwd_direct_kernel<khb_for<4096>()>), grid, dim3(256), 0, s, g,
+                         as.rowlist, as.pix, w, (const float*)p->corr, (c32*)p->H);
+    PC_LAUNCH_CHECK("rows_fwd_direct");
+  }
+  dispatch_M<float>(p, false, nullptr, nullptr, 1.0f, s, nullptr, &as.rows, false);
+  launch_interp<float>(p, nullptr, out, s, base, stats);
+}
+
+void adjoint_grid_set(pc_plan* p, const c32* vis, const AtomSet& as, double* gout,
+                      hipStream_t s) {
+  if (p->Cw || p->precision != PC_PREC_FP32)
+    fail(PC_ERR_UNSUPPORTED, "gridded set operators need a coplanar FP32 plan");
+  const GridGeom& g = p->g;
+  launch_spread<float>(p, vis, nullptr, s);
+  dispatch_M<float>(p, true, nullptr, nullptr, 1.0f, s, nullptr, &as.rows, false);
+  ProfScope ps(p, s, "passB_adj_set", 8.0 * g.nv * as.rows.count + 12.0 * as.nS,
+               (double)g.nv * as.nS);
+  if (g.M >= 8192)
+    hipLaunchKernelGGL((atoms_adj_direct_kernel<khb_for<8192>()>), dim3((unsigned)as.nS),
+                       dim3(256), 0, s, g, as.pix, (const c32*)p->H, (const float*)p->corr, gout);
+  else
+    hipLaunchKernelGGL((atoms_adj_direct_kernel<khb_for<4096>()>), dim3((unsigned)as.nS),
+                       dim3(256), 0, s, g, as.pix, (const c32*)p->H, (const float*)p->corr, gout);
+  PC_LAUNCH_CHECK("atoms_adj_direct");
+}
 
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax) {
   unsigned long long key = 0;

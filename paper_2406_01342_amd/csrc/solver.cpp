@@ -195,7 +195,7 @@ struct Pfw {
   int64_t L, N;
   DevArray<c32> V, r;
   DevArray<float> eta;
-  DevArray<float> dimg;  // dense image for the gridded operators (kept zero)
+  DevArray<float> dimg;  // dense image of the dictionary's synthesis (kept zero)
   DevArray<int32_t> cand, pix;
   DevArray<unsigned> cand_count;
   DevArray<Atom<float>> atoms;
@@ -226,6 +226,8 @@ struct Pfw {
   bool pre_ok = false;
   DevArray<double> act_blk;  // uploaded [x | pix | row mask] of the active set
   RowMask act_rows{nullptr, 0};  // image rows holding atoms (inside act_blk)
+  const int3* act_rowlist = nullptr;  // per occupied row: row, first atom, end
+  int64_t act_nrows = 0;
   // partial residual statistics left in red_partial by the last op_forward
   // (its interpolation's work items), 0 when it left none
   int64_t resid_parts = 0;
@@ -403,29 +405,45 @@ struct Pfw {
     g.ensure(nS);
     adj_partial.ensure(adjoint_partial_count(p, nS));
     act_rows = RowMask{nullptr, 0};
+    act_rowlist = nullptr;
+    act_nrows = 0;
     if (nS == 0) return;
     // one upload and one kernel: x = y = weights, pix, atom table; the mask
     // of the image rows that hold atoms stays in the block for the gridded
     // operators
+    // and the list of occupied rows (the set is sorted by pixel, so each
+    // row's atoms are a range)
     const int n = p->g.n;
+    int64_t nrows = 0;
+    for (int64_t q = 0; q < nS; ++q)
+      if (q == 0 || set[q] / n != set[q - 1] / n) ++nrows;
     const int64_t words = (n + 31) / 32, moff = (nS * 12 + 7) / 8 * 8;
-    const int64_t bytes = moff + words * 4;
+    const int64_t loff = moff + words * 4;
+    const int64_t bytes = loff + nrows * 12;
     act_blk.ensure((bytes + 7) / 8);
     unsigned char* h = (unsigned char*)up_act.get(bytes);
     std::memcpy(h, xs_host.data(), nS * 8);
     std::memcpy(h + nS * 8, set.data(), nS * 4);
     uint32_t* mask = (uint32_t*)(h + moff);
     std::memset(mask, 0, words * 4);
-    int64_t nrows = 0;
+    int32_t* rl = (int32_t*)(h + loff);
+    int64_t r = -1;
     for (int64_t q = 0; q < nS; ++q) {
       const int i = set[q] / n;
-      if (!(mask[i >> 5] & (1u << (i & 31)))) ++nrows;
       mask[i >> 5] |= 1u << (i & 31);
+      if (q == 0 || i != set[q - 1] / n) {
+        ++r;
+        rl[3 * r] = i;
+        rl[3 * r + 1] = (int32_t)q;
+      }
+      rl[3 * r + 2] = (int32_t)(q + 1);
     }
     PC_HIP(hipMemcpyAsync(act_blk.ptr, h, bytes, hipMemcpyHostToDevice, s));
     up_act.arm(s);
     k_activate(p, nS, act_blk.ptr, x.ptr, y.ptr, pix.ptr, atoms.ptr, s);
     act_rows = RowMask{(const uint32_t*)((const unsigned char*)act_blk.ptr + moff), nrows};
+    act_rowlist = (const int3*)((const unsigned char*)act_blk.ptr + loff);
+    act_nrows = nrows;
   }
 
   // Crossover between the direct sums and the gridded operators (restricted
@@ -446,10 +464,10 @@ struct Pfw {
     return (int64_t)std::ceil(fixed / per_atom);
   }
 
-  // The row mask of the loaded active set for the gridded operators (none
-  // with a dictionary, whose atoms cover several rows).
-  const RowMask* rows_of_set() const {
-    return (!ms && act_rows.bits && act_rows.count > 0) ? &act_rows : nullptr;
+  // The loaded active set for the gridded operators (not with a
+  // dictionary, whose atoms cover several pixels each).
+  AtomSet atom_set(int64_t nS) const {
+    return AtomSet{nS, pix.ptr, act_rowlist, act_nrows, act_rows};
   }
 
   void ensure_dimg() {
@@ -460,24 +478,23 @@ struct Pfw {
 
   // out = base - Phi_S w (base = V) or Phi_S w (no base), in plan order.  The
   // direct path takes the weights from the atom table; the gridded one
-  // scatters w into the (zero) dense image, interpolates, and clears it.
+  // evaluates the set's rows directly (with a dictionary: synthesises the
+  // elements into the zero dense image, interpolates, and clears it).
   void op_forward(bool gridded, int64_t nS, const double* w, bool base, c32* out) {
     resid_parts = 0;
     if (!gridded) {
       forward_atoms<float>(p, nS, atoms.ptr, base ? V.ptr : nullptr, true, out, true, s);
       return;
     }
-    ensure_dimg();
     if (ms) {  // Psi w: weighted elements (overlapping), cleared after use
+      ensure_dimg();
       dict_synthesis(p, dict, nS, pix.ptr, w, dimg.ptr, s);
       forward_grid<float>(p, dimg.ptr, out, true, s);
       k_fill(p, N, 0.0f, dimg.ptr, s);
     } else {  // (the residual and its statistics formed by the interpolation itself)
       if (base) red_partial.ensure(2 * std::max<int64_t>(k_resid_blocks(L), p->n_interp));
-      k_scatter(p, nS, pix.ptr, w, dimg.ptr, s);
-      forward_grid<float>(p, dimg.ptr, out, true, s, rows_of_set(), base ? V.ptr : nullptr,
-                          base ? red_partial.ptr : nullptr);
-      k_scatter(p, nS, pix.ptr, nullptr, dimg.ptr, s);
+      forward_grid_set(p, atom_set(nS), w, base ? V.ptr : nullptr,
+                       base ? red_partial.ptr : nullptr, out, s);
       resid_parts = base ? p->n_interp : 0;
       return;
     }
@@ -492,11 +509,12 @@ struct Pfw {
       adjoint_atoms<float>(p, rr, true, nS, atoms.ptr, adj_partial.ptr, gout, s);
       return;
     }
-    adjoint_grid<float>(p, rr, true, eta.ptr, 1.0f, s, rows_of_set());
-    if (ms)
+    if (ms) {
+      adjoint_grid<float>(p, rr, true, eta.ptr, 1.0f, s);
       dict_gather(p, dict, nS, pix.ptr, eta.ptr, gout, s);
-    else
-      k_gather_img(p, nS, pix.ptr, eta.ptr, gout, s);
+    } else {
+      adjoint_grid_set(p, rr, atom_set(nS), gout, s);
+    }
   }
 
   void init(const void* vis_caller) {

@@ -82,10 +82,10 @@ class DeviceBackend:
     """Runs jobs through the HIP library on one device."""
 
     #: solver state resident per job beyond the plan: sorted visibilities and
-    #: residual (2 x 8 L), dirty-residual image (4 n^2), the dense image of the
-    #: gridded operators (4 n^2, allocated once the active set reaches their
-    #: crossover, and for every synthesis-form solve), caller-order upload
-    #: (8 L) and a fixed allowance for candidate lists and atom tables
+    #: residual (2 x 8 L), dirty-residual image (4 n^2), with a dictionary the
+    #: dense synthesis image (4 n^2) and the per-scale analysis (4 S n^2),
+    #: caller-order upload (8 L) and a fixed allowance for candidate lists and
+    #: atom tables
     FIXED_BYTES = 4 << 20
 
     def __init__(self, device: int = 0, batched: bool = True):
@@ -102,9 +102,9 @@ class DeviceBackend:
         plan = self.api.pc_plan_footprint(req.uv, req.npix, req.fov_rad)
         S = _n_scales(req)
         cert = 4 * S * req.npix * req.npix if req.want_certificate else 0
-        # the dirty residual and the gridded operators' dense image, plus the
-        # per-scale analysis with a dictionary
-        img = 4 * req.npix * req.npix * (2 + (S if "scales" in req.params else 0))
+        # the dirty residual, plus the synthesis image and the per-scale
+        # analysis with a dictionary
+        img = 4 * req.npix * req.npix * ((2 + S) if "scales" in req.params else 1)
         # solver arrays come in the device pool's size classes (<= 25 % more)
         return int(plan) + (5 * (24 * L + img)) // 4 + cert + self.FIXED_BYTES
 

@@ -226,8 +226,8 @@ def test_batcher_rejects_fp64_plan():
 
 def test_footprint_covers_the_device_memory_of_a_job():
     """The admission footprint is at least the device memory a job holds at
-    its peak: plan workspace, resident solver state, the gridded operators'
-    dense image (forced here by a low crossover) and the certificate."""
+    its peak: plan workspace, resident solver state (with the gridded
+    operators, forced here by a low crossover) and the certificate."""
     import torch
     a = api()
     from paper_2406_01342_amd import serving
