@@ -756,10 +756,6 @@ def main():
     del dv, img, cert
     plan.close()
     torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline_c5(p, vis, args.cpu_seconds)
-    del vis
 
     # ---- LOFAR-like solves: Gram form (default), operator form, positivity ----
     p2 = sim.config_c2()
@@ -794,6 +790,11 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(api, torch, args.serving_requests, args.serving_slots)
         out["serving_memory_pressure"] = c5_mix_leg(api, torch, 2, 16)
+    # last: the oracle's thread pool on the host cores would otherwise still
+    # compete with the host side of the latency-bound legs above
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline_c5(p, vis, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
