@@ -98,7 +98,7 @@ struct InterpItem {
   int32_t end;
   int32_t pad;
 };
-constexpr int kInterpChunk = 512;
+constexpr int kInterpChunk = 2048;
 
 // A split ("hot") tile: its partial tiles occupy slots [first, first+count).
 struct FoldItem {

@@ -1360,17 +1360,19 @@ __global__ __launch_bounds__(256) void interp_kernel(GridGeom g, int64_t L,
   out[d] = {ax, ay};
 }
 
-// Interpolation from LDS (FP32, kernel widths up to 16): one wave per work
-// item (InterpItem), a plan-order range of visibilities whose first cells lie
-// in one tile.  The wave copies the tile and the W - 1 cells past its right
-// and lower edges, all that its visibilities' footprints reach, into LDS
-// (cells outside the band as zeros; with a periodic band, wrapped), then each
-// lane sums the W x W taps of one visibility from there, rows of taps in the
-// same order as interp_kernel.  With base (plan order, plan-order output),
-// the output is base - Phi x: the residual, in the same FP32 subtraction a
-// separate pass would do; with stats as well, each work item also writes
-// its sums of |r|^2 and Re(conj(base) r) in FP64 to stats[2 item], [2 item
-// + 1] (lanes in a fixed order).
+// Interpolation from LDS (FP32, kernel widths up to 16): one workgroup of
+// kInterpThreads per work item (InterpItem), a plan-order range of
+// visibilities whose first cells lie in one tile.  The workgroup copies the
+// tile and the W - 1 cells past its right and lower edges, all that its
+// visibilities' footprints reach, into LDS (cells outside the band as zeros;
+// with a periodic band, wrapped), then each thread sums the W x W taps of one
+// visibility at a time from there, rows of taps in the same order as
+// interp_kernel.  With base (plan order, plan-order output), the output is
+// base - Phi x: the residual, in the same FP32 subtraction a separate pass
+// would do; with stats as well, each work item also writes its sums of
+// |r|^2 and Re(conj(base) r) in FP64 to stats[2 item], [2 item + 1] (threads
+// combined in a fixed order).
+constexpr int kInterpThreads = 256;
 template <int W>
 struct InterpCfg {
   static constexpr int S = kTile + W - 1;  // region side (cells)
@@ -1378,7 +1380,7 @@ struct InterpCfg {
 };
 
 template <int W>
-__global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
+__global__ __launch_bounds__(kInterpThreads) void interp_lds_kernel(GridGeom g,
                                                         const InterpItem* __restrict__ items,
                                                         const uint32_t* __restrict__ cell,
                                                         const float* __restrict__ off,
@@ -1390,10 +1392,10 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
   using C = InterpCfg<W>;
   __shared__ float2 reg[C::S * C::SP];
   const InterpItem it = items[blockIdx.x];
-  const int lane = (int)threadIdx.x;
+  const int tid = (int)threadIdx.x;
   const int tv = it.tile / g.ntu, tu = it.tile - tv * g.ntu;
   const int rv0 = tv * kTile, ru0 = tu * kTile;  // region origin in the band
-  for (int e = lane; e < C::S * C::S; e += 64) {
+  for (int e = tid; e < C::S * C::S; e += kInterpThreads) {
     const int y = e / C::S, x = e - y * C::S;
     int rv = rv0 + y, ru = ru0 + x;
     float2 v = make_float2(0.f, 0.f);
@@ -1413,7 +1415,7 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
   const float c1 = c0 / R;
   const int ou = g.u0 + ru0, ov = g.v0 + rv0;
   double r2 = 0.0, vr = 0.0;
-  for (int sidx = it.beg + lane; sidx < it.end; sidx += 64) {
+  for (int sidx = it.beg + tid; sidx < it.end; sidx += kInterpThreads) {
     const uint32_t c = cell[sidx];
     const int x = (int)(c & 0xffffu) - ou, y = (int)(c >> 16) - ov;  // in [0, kTile)
     const float2 o = reinterpret_cast<const float2*>(off)[sidx];
@@ -1446,13 +1448,25 @@ __global__ __launch_bounds__(64) void interp_lds_kernel(GridGeom g,
     }
   }
   if (stats) {
+    constexpr int NW = kInterpThreads / 64;
+    __shared__ double wsum[2][NW];
     for (int o = 32; o > 0; o >>= 1) {
       r2 += __shfl_xor(r2, o, 64);
       vr += __shfl_xor(vr, o, 64);
     }
-    if (lane == 0) {
-      stats[2 * (size_t)blockIdx.x] = r2;
-      stats[2 * (size_t)blockIdx.x + 1] = vr;
+    if ((tid & 63) == 0) {
+      wsum[0][tid >> 6] = r2;
+      wsum[1][tid >> 6] = vr;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        a += wsum[0][w];
+        b += wsum[1][w];
+      }
+      stats[2 * (size_t)blockIdx.x] = a;
+      stats[2 * (size_t)blockIdx.x + 1] = b;
     }
   }
 }
@@ -1600,7 +1614,8 @@ static void launch_interp_w(pc_plan* p, const int32_t* perm, cpx<R>* out, hipStr
   ProfScope ps(p, s, "interp", p->L * (4 + 4 * rb + (base ? 2 * rb : 0)) +
                                    2 * rb * p->g.nu * p->g.nv, (double)p->L);
   if constexpr (sizeof(R) == 4) {
-    hipLaunchKernelGGL((interp_lds_kernel<W>), dim3((unsigned)p->n_interp), dim3(64), 0, s, p->g,
+    hipLaunchKernelGGL((interp_lds_kernel<W>), dim3((unsigned)p->n_interp), dim3(kInterpThreads),
+                       0, s, p->g,
                        p->interp, p->cell, (const float*)p->off, (const c32*)p->grid, perm,
                        (const c32*)base, (c32*)out, base ? stats : nullptr);
   } else {
