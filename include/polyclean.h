@@ -75,7 +75,7 @@ typedef enum {
   PC_ERR_OUT_OF_MEMORY = -2, /* device allocation failed                    */
   PC_ERR_DEVICE = -3,        /* a HIP runtime call or kernel launch failed  */
   PC_ERR_CAPACITY = -4,      /* an output array is too small (see result)   */
-  PC_ERR_UNSUPPORTED = -5    /* a valid request this build does not handle  */
+  PC_ERR_UNSUPPORTED = -5    /* a valid request the library does not handle */
 } pc_status;
 
 enum { PC_UV_WAVELENGTHS = 0, PC_UV_METRES = 1 };
