@@ -227,6 +227,19 @@ PC_API pc_status pc_forward_grid_rows(pc_plan* plan, const float* image, const u
 PC_API pc_status pc_adjoint_grid_rows(pc_plan* plan, const void* vis, const uint32_t* row_mask,
                                       float* image, void* stream);
 
+/* The same gradient Phi_S* (V - Phi_S x) by the gridded operators, the form
+ * the solve's APGD step takes for large sets (Alg. 2 step 2; Sect. 5.2):
+ * interpolation from the fine grid, pass A of the FFT over the band rows,
+ * and pass B evaluated directly at the image rows and pixels of S (a row
+ * holds few atoms), so the cost is about one gridded operator pair
+ * whatever the set's size.  Arguments as pc_restricted_gradient (atoms in
+ * any order, repeats allowed); accuracy that of the gridded operators
+ * (relative error ~ nufft_eps).  Coplanar plans only (-5 otherwise).  Reads
+ * pix back to the host and synchronises the stream before returning. */
+PC_API pc_status pc_restricted_gradient_grid(pc_plan* plan, const void* vis, int64_t natoms,
+                                             const int32_t* pix, const float* weight,
+                                             double* grad, void* resid, void* stream);
+
 /* Restricted adjoint Phi_S* (Eq. adjoint-phi at the pixels of S only), by
  * direct summation: out[p] = Re sum_k vis_k exp(+j2pi(u_k l_p + v_k m_p)) / n_p.
  * vis dev complex64 [nvis] caller order; pix dev int32 [natoms];

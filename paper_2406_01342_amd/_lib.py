@@ -97,6 +97,7 @@ SIGNATURES = {
     "pc_adjoint_sparse": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
     "pc_dual_certificate": (C.c_int, [_P, _P, _I64, _P, _P, C.c_double, _P, _PD, _PI64, _P]),
     "pc_restricted_gradient": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P]),
+    "pc_restricted_gradient_grid": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P]),
     "pc_restricted_gradient_noalloc": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P, _P]),
     "pc_adjoint_grid_f64": (C.c_int, [_P, _P, _P, _PD, _PI64, _P]),
     "pc_adjoint_grid_ms": (C.c_int, [_P, _P, C.c_int32, _PD, _PD, _P, _PD, _PI64, _P]),

@@ -296,6 +296,24 @@ def pc_restricted_gradient(plan: Plan, vis: torch.Tensor, pix: torch.Tensor, wei
     return (grad, resid) if want_resid else grad
 
 
+def pc_restricted_gradient_grid(plan: Plan, vis: torch.Tensor, pix: torch.Tensor,
+                                weight: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                                want_resid: bool = False, stream=None):
+    """pc_restricted_gradient by the gridded operators (pass B at the set)."""
+    na = int(pix.numel())
+    if grad is None:
+        grad = _new(plan, (na,), torch.float64)
+    resid = _new(plan, (plan.nvis,), torch.complex64) if want_resid else None
+    check(LIB.pc_restricted_gradient_grid(
+        plan.handle, C.c_void_p(_dev(vis, torch.complex64, plan.nvis, "vis")), na,
+        C.c_void_p(_dev(pix, torch.int32, na, "pix")),
+        C.c_void_p(_dev(weight, torch.float32, na, "weight")),
+        C.c_void_p(_dev(grad, torch.float64, na, "grad")),
+        C.c_void_p(_dev(resid, torch.complex64, plan.nvis, "resid") if resid is not None else None),
+        C.c_void_p(_stream(stream))), "pc_restricted_gradient_grid")
+    return (grad, resid) if want_resid else grad
+
+
 def pc_restricted_gradient_noalloc(plan: Plan, vis: torch.Tensor, pix: torch.Tensor,
                                    weight: torch.Tensor, grad: torch.Tensor,
                                    resid: Optional[torch.Tensor] = None, stream=None):

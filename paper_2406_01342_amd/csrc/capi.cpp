@@ -340,6 +340,24 @@ pc_status pc_adjoint_grid_rows(pc_plan* p, const void* vis, const uint32_t* row_
   });
 }
 
+pc_status pc_restricted_gradient_grid(pc_plan* p, const void* vis, int64_t natoms,
+                                      const int32_t* pix, const float* weight, double* grad,
+                                      void* resid, void* stream) {
+  return guard("pc_restricted_gradient_grid", [&] {
+    check_plan(p, PC_PREC_FP32);
+    check_atoms(p, natoms, pix, weight, true);
+    PC_REQUIRE(vis != nullptr, "vis is NULL");
+    if (natoms > 0) PC_REQUIRE(grad != nullptr, "grad is NULL");
+    PC_REQUIRE(resid == nullptr || resid != vis, "resid must not alias vis");
+    if (p->Cw) fail(PC_ERR_UNSUPPORTED, "gridded restricted gradient of a non-coplanar plan");
+    set_device(p);
+    Touch touch(p, stream);
+    restricted_gradient_grid(p, (const c32*)vis, natoms, pix, weight, grad, (c32*)resid,
+                             (hipStream_t)stream);
+    return PC_OK;
+  });
+}
+
 pc_status pc_adjoint_sparse(pc_plan* p, const void* vis, int64_t natoms, const int32_t* pix,
                             double* out, void* stream) {
   return guard("pc_adjoint_sparse", [&] {

@@ -367,6 +367,10 @@ void forward_grid_set(pc_plan* p, const AtomSet& as, const double* w, const c32*
                       double* stats, c32* out, hipStream_t s);
 void adjoint_grid_set(pc_plan* p, const c32* vis, const AtomSet& as, double* gout,
                       hipStream_t s);
+// Phi_S* (V - Phi_S x) by the set operators above, atoms in caller order
+// (any order, repeats allowed); vis, resid caller order; synchronises.
+void restricted_gradient_grid(pc_plan* p, const c32* vis, int64_t natoms, const int32_t* pix,
+                              const float* weight, double* grad, c32* resid, hipStream_t s);
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax);
 // Launch tables of the batched adjoint (device copy and pinned staging),
 // reused from call to call.

@@ -1845,6 +1845,99 @@ void adjoint_grid_set(pc_plan* p, const c32* vis, const AtomSet& as, double* gou
   PC_LAUNCH_CHECK("atoms_adj_direct");
 }
 
+// Small moves of the gridded restricted gradient: caller-order atoms into
+// pixel order (weights widened to FP64), the gradient back, and visibilities
+// between caller and plan order.
+__global__ void atoms_to_set_kernel(int64_t nS, const int32_t* __restrict__ order,
+                                    const float* __restrict__ weight, double* __restrict__ w) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nS) w[q] = (double)weight[order[q]];
+}
+__global__ void set_to_atoms_kernel(int64_t nS, const int32_t* __restrict__ order,
+                                    const double* __restrict__ g, double* __restrict__ grad) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nS) grad[order[q]] = g[q];
+}
+__global__ void vis_to_plan_kernel(int64_t L, const int32_t* __restrict__ perm,
+                                   const c32* __restrict__ in, c32* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < L) out[k] = in[perm[k]];
+}
+__global__ void vis_to_caller_kernel(int64_t L, const int32_t* __restrict__ perm,
+                                     const c32* __restrict__ in, c32* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < L) out[perm[k]] = in[k];
+}
+
+void restricted_gradient_grid(pc_plan* p, const c32* vis, int64_t natoms, const int32_t* pix,
+                              const float* weight, double* grad, c32* resid, hipStream_t s) {
+  if (p->Cw || p->precision != PC_PREC_FP32)
+    fail(PC_ERR_UNSUPPORTED, "the gridded restricted gradient needs a coplanar FP32 plan");
+  const int64_t L = p->L;
+  const unsigned lb = (unsigned)((L + 255) / 256);
+  if (natoms == 0) {  // r = V
+    if (resid)
+      PC_HIP(hipMemcpyAsync(resid, vis, L * sizeof(c32), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  // the set in pixel order, its occupied rows and their mask, on the host
+  const int n = p->g.n;
+  std::vector<int32_t> hp((size_t)natoms);
+  PC_HIP(hipMemcpyAsync(hp.data(), pix, natoms * 4, hipMemcpyDeviceToHost, s));
+  PC_HIP(hipStreamSynchronize(s));
+  for (int64_t q = 0; q < natoms; ++q)
+    PC_REQUIRE(hp[q] >= 0 && (int64_t)hp[q] < (int64_t)n * n, "pix out of [0, npix^2)");
+  std::vector<int32_t> order((size_t)natoms);
+  for (int64_t q = 0; q < natoms; ++q) order[q] = (int32_t)q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return hp[a] < hp[b]; });
+  const int64_t words = (n + 31) / 32;
+  std::vector<int32_t> rl;
+  std::vector<uint32_t> mask((size_t)words, 0u);
+  for (int64_t q = 0; q < natoms; ++q) {
+    const int i = hp[order[q]] / n;
+    if (q == 0 || i != hp[order[q - 1]] / n) rl.insert(rl.end(), {i, (int32_t)q, 0});
+    rl.back() = (int32_t)(q + 1);
+    mask[i >> 5] |= 1u << (i & 31);
+  }
+  const int64_t nrows = (int64_t)rl.size() / 3;
+  // device scratch: [pixel-order pix | order | rows | mask | w | g | V in plan order]
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t o_ord = al(natoms * 4), o_rows = o_ord + al(natoms * 4);
+  const size_t o_mask = o_rows + al(nrows * 12), o_w = o_mask + al(words * 4);
+  const size_t o_g = o_w + al(natoms * 8), o_v = o_g + al(natoms * 8);
+  const size_t total = o_v + al(L * sizeof(c32));
+  unsigned char* d = (unsigned char*)ensure_atom_scratch(p, total);
+  std::vector<unsigned char> up(o_w);
+  for (int64_t q = 0; q < natoms; ++q) ((int32_t*)up.data())[q] = hp[order[q]];
+  std::memcpy(up.data() + o_ord, order.data(), natoms * 4);
+  std::memcpy(up.data() + o_rows, rl.data(), nrows * 12);
+  std::memcpy(up.data() + o_mask, mask.data(), words * 4);
+  PC_HIP(hipMemcpyAsync(d, up.data(), o_w, hipMemcpyHostToDevice, s));
+  const int32_t* dord = (const int32_t*)(d + o_ord);
+  double* w = (double*)(d + o_w);
+  double* g = (double*)(d + o_g);
+  const unsigned ab = (unsigned)((natoms + 255) / 256);
+  hipLaunchKernelGGL(atoms_to_set_kernel, dim3(ab), dim3(256), 0, s, natoms, dord, weight, w);
+  PC_LAUNCH_CHECK("atoms_to_set");
+  const AtomSet as{natoms, (const int32_t*)d, (const int3*)(d + o_rows), nrows,
+                   RowMask{(const uint32_t*)(d + o_mask), nrows}};
+  // r = V - Phi_S x in plan order, then Phi_S* r
+  c32* vp = (c32*)(d + o_v);
+  c32* r = (c32*)p->vis_scratch;
+  hipLaunchKernelGGL(vis_to_plan_kernel, dim3(lb), dim3(256), 0, s, L, p->perm, vis, vp);
+  PC_LAUNCH_CHECK("vis_to_plan");
+  forward_grid_set(p, as, w, vp, nullptr, r, s);
+  adjoint_grid_set(p, r, as, g, s);
+  hipLaunchKernelGGL(set_to_atoms_kernel, dim3(ab), dim3(256), 0, s, natoms, dord, g, grad);
+  PC_LAUNCH_CHECK("set_to_atoms");
+  if (resid) {
+    hipLaunchKernelGGL(vis_to_caller_kernel, dim3(lb), dim3(256), 0, s, L, p->perm, r, resid);
+    PC_LAUNCH_CHECK("vis_to_caller");
+  }
+  PC_HIP(hipStreamSynchronize(s));  // the host staging above goes out of scope
+}
+
 void maxkey_read(pc_plan* p, hipStream_t s, double* max_abs, int64_t* argmax) {
   unsigned long long key = 0;
   PC_HIP(hipMemcpyAsync(&key, p->maxkey, sizeof(key), hipMemcpyDeviceToHost, s));
