@@ -179,11 +179,17 @@ __device__ __forceinline__ void fft_stages(cpx<R>* buf, const cpx<R>* tw) {
 // The last stage (NS * RAD = M), with each output handed to store(b, f, v)
 // (f = frequency index of sequence b) from registers instead of written back
 // to LDS, for the outputs keep(f) selects (for RAD = 16 and a keep that tests
-// ranges of M / 16, decided per r at compile time).  No barrier at the end.
+// ranges of M / 16, decided per r at compile time).  Butterflies j (outputs
+// j + r NS) for which need(j) is false are skipped whole.  No barrier at the
+// end.
+struct AllNeeded {
+  __device__ bool operator()(int) const { return true; }
+};
+
 template <typename R, int RAD, int M, int NB, int NT, int SIGN, int NS, typename Keep,
-          typename Store>
+          typename Store, typename Need = AllNeeded>
 __device__ __forceinline__ void fft_last_stage(const cpx<R>* buf, const cpx<R>* tw, Keep keep,
-                                               Store store) {
+                                               Store store, Need need = Need{}) {
   static_assert(NS * RAD == M, "last stage");
   constexpr int NBF = M / RAD;  // == NS: j is its own twiddle index
   constexpr int TOT = NB * NBF;
@@ -194,6 +200,7 @@ __device__ __forceinline__ void fft_last_stage(const cpx<R>* buf, const cpx<R>* 
     const int bi = (int)threadIdx.x + q * NT;
     if (TOT % NT == 0 || bi < TOT) {
       const int b = bi / NBF, j = bi - b * NBF;
+      if (!need(j)) continue;
       cpx<R> x[RAD];
       const int i0 = b * M + j;
 #pragma unroll
@@ -217,25 +224,27 @@ __device__ __forceinline__ void fft_last_stage(const cpx<R>* buf, const cpx<R>* 
   }
 }
 
-template <typename R, int M, int NB, int NT, int SIGN, int NS, typename Keep, typename Store>
+template <typename R, int M, int NB, int NT, int SIGN, int NS, typename Keep, typename Store,
+          typename Need>
 __device__ __forceinline__ void fft_stages_store(cpx<R>* buf, const cpx<R>* tw, Keep keep,
-                                                 Store store) {
+                                                 Store store, Need need) {
   constexpr int RAD = (NS == 1) ? first_radix(M) : 16;
   if constexpr (NS * RAD < M) {
     fft_stage<R, RAD, M, NB, NT, SIGN, NS>(buf, tw);
-    fft_stages_store<R, M, NB, NT, SIGN, NS * RAD>(buf, tw, keep, store);
+    fft_stages_store<R, M, NB, NT, SIGN, NS * RAD>(buf, tw, keep, store, need);
   } else {
-    fft_last_stage<R, RAD, M, NB, NT, SIGN, NS>(buf, tw, keep, store);
+    fft_last_stage<R, RAD, M, NB, NT, SIGN, NS>(buf, tw, keep, store, need);
   }
 }
 
 // FFT of NB sequences in LDS from stage NS on, the last stage's outputs
-// stored through store(b, f, v) for keep(r, f) (see fft_last_stage); the
-// LDS contents are left undefined.
-template <typename R, int M, int NB, int NT, int SIGN, int NS = 1, typename Keep, typename Store>
+// stored through store(b, f, v) for keep(r, f), its butterflies j run only
+// where need(j) (see fft_last_stage); the LDS contents are left undefined.
+template <typename R, int M, int NB, int NT, int SIGN, int NS = 1, typename Keep, typename Store,
+          typename Need = AllNeeded>
 __device__ __forceinline__ void lds_fft_store(cpx<R>* buf, const cpx<R>* tw, Keep keep,
-                                              Store store) {
-  fft_stages_store<R, M, NB, NT, SIGN, NS>(buf, tw, keep, store);
+                                              Store store, Need need = Need{}) {
+  fft_stages_store<R, M, NB, NT, SIGN, NS>(buf, tw, keep, store, need);
 }
 
 // In-place FFT of NB sequences of length M stored contiguously in LDS, with

@@ -885,13 +885,23 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
     const int i = f < n / 2 ? f + n / 2 : f - M + n / 2;
     if (row < g.nv && (!rows || row_set(smask, i))) H[h_index<khb_for<M>()>(row, i, g.nv)] = v;
   };
+  // a last-stage butterfly j (outputs j + r M/16) keeps the columns
+  // i = j + t M/16, t = 0..7: with a row mask, one whose eight columns are all
+  // cleared is skipped whole
+  auto need = [&](int j) {
+    if (!rows) return true;
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) any |= row_set(smask, j + t * (M / 16));
+    return any;
+  };
   if constexpr (RAD0 <= 4) {
     if (pruned)
-      lds_fft_store<R, M, NB, NT, +1, RAD0>(buf, tws, keep, store);
+      lds_fft_store<R, M, NB, NT, +1, RAD0>(buf, tws, keep, store, need);
     else
-      lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store);
+      lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store, need);
   } else {
-    lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store);
+    lds_fft_store<R, M, NB, NT, +1>(buf, tws, keep, store, need);
   }
 }
 
