@@ -693,18 +693,6 @@ __global__ void scale_kernel(int64_t N, const float* __restrict__ in, float s,
 
 // img[pix[a]] = vals[a] (vals NULL: 0), for the gridded operators on an
 // active set.
-__global__ void scatter_kernel(int64_t nS, const int32_t* __restrict__ pix,
-                               const double* __restrict__ vals, float* __restrict__ img) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a < nS) img[pix[a]] = vals ? (float)vals[a] : 0.0f;
-}
-
-__global__ void gather_img_kernel(int64_t nS, const int32_t* __restrict__ pix,
-                                  const float* __restrict__ img, double* __restrict__ out) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a < nS) out[a] = (double)img[pix[a]];
-}
-
 // scal[kScalYL1] = sum_p stat[p], scal[kScalGmax] = max(0, max_p stat[nS + p]),
 // scal[kScalYNeg] = max(0, -min_p stat[p]) (one workgroup, fixed order).
 __global__ __launch_bounds__(1024) void stat_reduce_kernel(int64_t nS, const double* __restrict__ stat,
@@ -865,20 +853,6 @@ void k_weights(pc_plan* p, int64_t nS, const double* x, Atom<float>* atoms, hipS
   if (nS <= 0) return;
   hipLaunchKernelGGL(weights_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, x, atoms);
   PC_LAUNCH_CHECK("weights");
-}
-
-void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, float* img,
-               hipStream_t s) {
-  if (nS <= 0) return;
-  hipLaunchKernelGGL(scatter_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, pix, vals, img);
-  PC_LAUNCH_CHECK("scatter");
-}
-
-void k_gather_img(pc_plan* p, int64_t nS, const int32_t* pix, const float* img, double* out,
-                  hipStream_t s) {
-  if (nS <= 0) return;
-  hipLaunchKernelGGL(gather_img_kernel, dim3(blocks(nS, 256)), dim3(256), 0, s, nS, pix, img, out);
-  PC_LAUNCH_CHECK("gather_img");
 }
 
 void k_stat_reduce(pc_plan* p, int64_t nS, const double* stat, double* scal, hipStream_t s) {

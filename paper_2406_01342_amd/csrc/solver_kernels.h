@@ -53,11 +53,6 @@ void k_gram_assemble(pc_plan* p, int64_t nS, const void* blk, const double* psf,
 // and the padded atom table (atom_capacity(nS) entries).
 void k_activate(pc_plan* p, int64_t nS, const void* blk, double* x, double* y, int32_t* pix,
                 Atom<float>* atoms, hipStream_t s);
-// Gridded-operator helpers for large active sets.
-void k_scatter(pc_plan* p, int64_t nS, const int32_t* pix, const double* vals, float* img,
-               hipStream_t s);
-void k_gather_img(pc_plan* p, int64_t nS, const int32_t* pix, const float* img, double* out,
-                  hipStream_t s);
 void k_rsub(pc_plan* p, int64_t L, const c32* V, c32* r, hipStream_t s);
 // Sum in order of nparts (|r|^2, Re<V, r>) partial pairs into out[0..1].
 void k_resid_final(pc_plan* p, int nparts, const double* partial, double* out, hipStream_t s);
