@@ -121,9 +121,10 @@ def test_gram_form_follows_the_operator_form():
 @pytest.mark.parametrize("name,grid_atoms", [("c1", 1), ("c1", 8), ("c2_small", 4)])
 def test_solve_gridded_apgd_matches_oracle(name, grid_atoms):
     """Active sets above the crossover apply Phi_S and Phi_S* through the
-    gridded operators (type 2 / type 1) inside APGD, and from 4x that size
-    also for the per-iteration residual.  Forced low here so that the whole
-    solve runs that way; the result must still match the direct oracle."""
+    gridded operators (type 2 / type 1, pass B evaluated at the set) inside
+    APGD and for the per-iteration residual.  Forced low here so that the
+    whole solve runs that way; the result must still match the direct
+    oracle."""
     say("solve gridded", name, grid_atoms)
     p, vis = problem(name)
     kw = dict(alpha=p.alpha, delta=p.delta, max_iter=300, rel_gap_tol=1e-4)
@@ -141,6 +142,37 @@ def test_solve_gridded_apgd_matches_oracle(name, grid_atoms):
     # the reported objective is that of the returned x (exact forward)
     p_or = solver.objective(vis.astype(np.complex128), fit, res["weight"], res["lambda"])
     assert abs(p_or - res["objective"]) <= 1e-4 * p_or
+
+
+def test_gridded_solve_at_a_large_grid_matches_the_direct_solve():
+    """A 4096^2 image (8192^2 fine grid: the pass-A buffer's 4-column blocks
+    and the direct pass B at the set's rows and pixels), 30,000 random
+    visibilities of 25 point sources: the solve with every restricted
+    operator gridded (crossover 1) against the solve with direct sums only;
+    objectives within 1e-3, and the gridded solve's reported objective equal
+    to the oracle's evaluation of its returned x."""
+    a = api()
+    rng = np.random.default_rng(77)
+    n, fov, L = 4096, 0.05, 30000
+    d = fov / n
+    uv = rng.uniform(-0.45 / d, 0.45 / d, size=(L, 2))
+    pix = rng.choice(n * n, 25, replace=False)
+    amp = rng.lognormal(size=25) * 10.0
+    clean = operator.forward(uv, n, fov, pix, amp)
+    vis = (clean + 0.05 * np.sqrt(np.mean(np.abs(clean) ** 2)) *
+           (rng.normal(size=L) + 1j * rng.normal(size=L)) / np.sqrt(2)).astype(np.complex64)
+    plan = a.pc_plan_create(uv, n, fov)
+    assert plan.info["fine"] == 8192
+    kw = dict(alpha=0.05, delta=0.99, max_iter=12, rel_gap_tol=1e-4, gram_atoms=-1, capacity=4096)
+    dv = to_dev(vis)
+    rg = a.pc_polyclean_solve(plan, dv, grid_atoms=1, **kw)
+    rd = a.pc_polyclean_solve(plan, dv, grid_atoms=-1, **kw)
+    say("gridded", rg["objective"], rg["iters"], rg["natoms"], "direct", rd["objective"],
+        rd["iters"], rd["natoms"])
+    assert abs(rg["objective"] - rd["objective"]) <= 1e-3 * rd["objective"]
+    fit = operator.forward(uv, n, fov, rg["pix"], rg["weight"])
+    p_or = solver.objective(vis.astype(np.complex128), fit, rg["weight"], rg["lambda"])
+    assert abs(p_or - rg["objective"]) <= 1e-4 * p_or
 
 
 def test_solve_orthogonal_design_closed_form():
