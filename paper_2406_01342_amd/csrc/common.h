@@ -160,6 +160,9 @@ struct WStack {
   double cmid = 0;
   int nquad = 0;    // Gauss-Legendre nodes on [0, 1] of the Psi integral
 };
+// Terms of the Chebyshev series of Psi that the w-stacked adjoint's final
+// division evaluates (the plan checks the series against the quadrature).
+constexpr int kPsiCheb = 40;
 
 // Everything the gridded adjoint's kernels need about one plan, for launches
 // that cover the work of several plans at once (FP32 plans).
@@ -243,7 +246,7 @@ struct pc_plan {
   void* vis_scratch = nullptr;  // complex [L] in plan order (residual etc.)
   pc::WStack ws;                // w-stacking planes (nplanes 0: coplanar)
   void* wvals = nullptr;        // complex [L]: one plane's weighted visibilities
-  double* wquad = nullptr;      // [2 nquad]: nodes z_q, weights (W/2) w_q phi(z_q)
+  double* wquad = nullptr;      // [2 nquad] doubles: Psi's Chebyshev series (kPsiCheb terms)
   void* atom_scratch = nullptr; // per-atom staging
   size_t atom_capacity = 0;
   double* red_scratch = nullptr;  // reduction partials

@@ -1132,31 +1132,40 @@ __global__ __launch_bounds__(256) void wplane_kernel(int64_t L, const double* __
   out[k] = o;
 }
 
-// Last step of the w-stacked adjoint: image /= Psi(dw c') per pixel, with
-// Psi(xi) = sum_q W w_q phi(z_q) cos(pi W z_q xi) over the nodes z_q in
-// (0, 1] (quad: interleaved node, weight), and the fused maximum key.
+// Last step of the w-stacked adjoint: image /= Psi(dw c') per pixel, and
+// the fused maximum key.  Psi(xi) = sum_q W w_q phi(z_q) cos(pi W z_q xi)
+// (the quadrature of the kernel's Fourier integral) is evaluated as its
+// Chebyshev series in 4 xi (xi = dw (c' - c_mid) lies in [-1/4, 1/4]):
+// cheb[k], k < kPsiCheb, by Clenshaw's recurrence in FP64.
 __global__ __launch_bounds__(256) void wfinal_kernel(GridGeom g, WStack ws,
-                                                     const double* __restrict__ quad,
+                                                     const double* __restrict__ cheb,
                                                      float* __restrict__ image,
                                                      unsigned long long* __restrict__ maxkey,
                                                      int positive) {
+  // a grid-stride loop over a capped grid: one atomic per workgroup on the
+  // single key, so few workgroups (thousands contending for one address
+  // took most of the kernel's time)
   const int n = g.n;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long best = 0;
-  if (idx < (int64_t)n * n) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
     const double xi =
         ws.dw * (n_minus_one((double)(i - n / 2) * g.dl, (double)(j - n / 2) * g.dl) - ws.cmid);
-    double psi = 0;
-    for (int q = 0; q < ws.nquad; ++q) {
-      float t = (float)(0.5 * g.W * quad[2 * q] * xi);  // pi W z xi radians in turns
-      t -= rintf(t);
-      psi += quad[2 * q + 1] * (double)__builtin_amdgcn_cosf(t);
+    const double x = fmin(fmax(4.0 * xi, -1.0), 1.0);
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = kPsiCheb - 1; k >= 1; --k) {
+      const double b0 = fma(2.0 * x, b1, cheb[k] - b2);
+      b2 = b1;
+      b1 = b0;
     }
+    const double psi = fma(x, b1, cheb[0] - b2);
     const float val = (float)((double)image[idx] / psi);
     image[idx] = val;
     const float kv = positive ? (val > 0.f ? val : 0.0f) : fabsf(val);
-    best = max_key(kv, (int)idx);
+    const unsigned long long key = max_key(kv, (int)idx);
+    best = key > best ? key : best;
   }
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long other = __shfl_xor(best, o, 64);
@@ -1985,7 +1994,8 @@ static void adjoint_grid_w(pc_plan* p, const c32* vis, bool vis_sorted, float* i
   }
   const int64_t N = (int64_t)p->g.n * p->g.n;
   ProfScope ps(p, s, "wfinal", 8.0 * N, (double)N);
-  hipLaunchKernelGGL(wfinal_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, p->g, ws,
+  const unsigned nbf = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+  hipLaunchKernelGGL(wfinal_kernel, dim3(nbf), dim3(256), 0, s, p->g, ws,
                      p->wquad, image, p->maxkey, p->max_positive);
   PC_LAUNCH_CHECK("wfinal");
 }

@@ -815,7 +815,38 @@ extern "C" pc_status pc_plan_create_impl(const pc_geometry* geom, void* stream, 
         wq.push_back(g.W * w[q] * phi);
       }
       PC_REQUIRE((int)wq.size() == 2 * lay.ws.nquad, "quadrature nodes");
-      PC_HIP(hipMemcpyAsync(p->wquad, wq.data(), wq.size() * 8, hipMemcpyHostToDevice, s));
+      // the device evaluates Psi on xi in [-1/4, 1/4] (the range of
+      // dw (c' - c_mid)) as a Chebyshev series in 4 xi, interpolated at the
+      // Chebyshev points; checked here against the quadrature itself
+      auto psi = [&](double xi) {
+        double sum = 0.0;
+        for (int q = 0; q < lay.ws.nquad; ++q)
+          sum += wq[2 * q + 1] * std::cos(M_PI * g.W * wq[2 * q] * xi);
+        return sum;
+      };
+      constexpr int K = kPsiCheb;
+      std::vector<double> fv(K), cheb(K, 0.0);
+      for (int j = 0; j < K; ++j) fv[j] = psi(0.25 * std::cos(M_PI * (j + 0.5) / K));
+      for (int k = 0; k < K; ++k) {
+        double acc = 0.0;
+        for (int j = 0; j < K; ++j) acc += fv[j] * std::cos(M_PI * k * (j + 0.5) / K);
+        cheb[k] = (k == 0 ? 1.0 : 2.0) * acc / K;
+      }
+      for (int t = 0; t <= 64; ++t) {
+        const double x = -1.0 + t / 32.0;
+        double b1 = 0.0, b2 = 0.0;
+        for (int k = K - 1; k >= 1; --k) {
+          const double b0 = 2.0 * x * b1 - b2 + cheb[k];
+          b2 = b1;
+          b1 = b0;
+        }
+        const double ser = x * b1 - b2 + cheb[0], ref = psi(0.25 * x);
+        PC_REQUIRE(std::fabs(ser - ref) <= 1e-12 * std::fabs(psi(0.0)),
+                   "Chebyshev series of the w correction");
+      }
+      PC_REQUIRE(K <= 2 * lay.ws.nquad, "w correction table size");
+      PC_HIP(hipMemcpyAsync(p->wquad, cheb.data(), K * 8, hipMemcpyHostToDevice, s));
+      PC_HIP(hipStreamSynchronize(s));  // (cheb is a local)
     }
     std::vector<double> corr64 = correction_table(g);
     std::vector<float> tw32, corr32;
