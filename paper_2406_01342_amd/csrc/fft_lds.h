@@ -17,14 +17,14 @@
 namespace pc {
 
 template <typename R>
-__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+__host__ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
 // exp(SIGN 2 pi i K / N) applied to v, with exact handling of the trivial
 // angles (multiples of pi/2) so that no multiplication by 0/1 is emitted.
 template <typename R, int N, int SIGN>
-__device__ __forceinline__ cpx<R> rot(cpx<R> v, int K) {
+__host__ __device__ __forceinline__ cpx<R> rot(cpx<R> v, int K) {
   // cos(2 pi q / 16) for q = 0..4 (first quadrant), as literals so that no
   // table is materialised
   auto c16 = [](int q) -> double {
@@ -52,7 +52,7 @@ __device__ __forceinline__ cpx<R> rot(cpx<R> v, int K) {
 
 // In-register DFT of length N (N = 2, 4, 8, 16) with sign SIGN, radix-2 DIT.
 template <typename R, int N, int SIGN>
-__device__ __forceinline__ void dft(cpx<R>* x) {
+__host__ __device__ __forceinline__ void dft(cpx<R>* x) {
   if constexpr (N == 1) {
     return;
   } else if constexpr (N == 2) {
@@ -103,14 +103,62 @@ __device__ __forceinline__ cpx<R> twiddle(const cpx<R>* tws, int t) {
   return cmul(tws[t & 63], tws[64 + (t >> 6)]);
 }
 
-// Twiddles w^r, r = 1..RAD-1, from w = w^1 by squaring and one multiply
-// per odd power (at most log2(RAD) + 1 roundings each), instead of one
-// table lookup pair and product per power.
-template <typename R, int RAD>
-__device__ __forceinline__ void twiddle_powers(cpx<R> w1, cpx<R>* w) {
-  w[1] = w1;
+// Radix-2 butterfly with twiddle t in fused multiply-adds:
+// (a, b) <- (a + t b, a - t b), the difference formed as 2a - (a + t b)
+// (six instructions instead of a product, a sum and a difference).
+template <typename R>
+__host__ __device__ __forceinline__ R fmar(R a, R b, R c) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void bfly_tw(cpx<R>& a, cpx<R>& b, cpx<R> t) {
+  const cpx<R> p = {fmar(t.x, b.x, fmar(-t.y, b.y, a.x)), fmar(t.x, b.y, fmar(t.y, b.x, a.y))};
+  b = {fmar(R(2), a.x, -p.x), fmar(R(2), a.y, -p.y)};
+  a = p;
+}
+
+// Twiddled DFT of length N (a power of two) in registers:
+// x[f] <- sum_r x[r] (u exp(SIGN 2 pi i f / N))^r, the input twiddles u^r of a
+// Stockham stage folded into the transform.  Splitting r into even and odd
+// gives two twiddled DFTs of length N/2 with twiddle u^2, joined by
+// butterflies with t_f = u exp(SIGN 2 pi i f / N) (t_{f + N/4} = t_f i^SIGN),
+// so the stage costs log2(N) squarings and a few constant rotations of u
+// instead of N - 2 products forming the powers and N - 1 applying them.
+template <typename R, int N, int SIGN>
+__host__ __device__ __forceinline__ void dft_tw(cpx<R>* x, cpx<R> u) {
+  if constexpr (N > 1) {
+    cpx<R> e[N / 2], o[N / 2];
 #pragma unroll
-  for (int r = 2; r < RAD; ++r) w[r] = (r & 1) ? cmul(w[r - 1], w1) : cmul(w[r / 2], w[r / 2]);
+    for (int i = 0; i < N / 2; ++i) {
+      e[i] = x[2 * i];
+      o[i] = x[2 * i + 1];
+    }
+    if constexpr (N > 2) {
+      const cpx<R> u2 = cmul(u, u);
+      dft_tw<R, N / 2, SIGN>(e, u2);
+      dft_tw<R, N / 2, SIGN>(o, u2);
+    }
+    cpx<R> t[N / 2];
+#pragma unroll
+    for (int f = 0; f < N / 2; ++f) {
+      if (N == 2 || f < N / 4) {
+        t[f] = rot<R, N, SIGN>(u, f);
+      } else {
+        const cpx<R> v = t[f - N / 4];
+        t[f] = SIGN > 0 ? cpx<R>{-v.y, v.x} : cpx<R>{v.y, -v.x};
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < N / 2; ++f) {
+      bfly_tw(e[f], o[f], t[f]);
+      x[f] = e[f];
+      x[f + N / 2] = o[f];
+    }
+  }
 }
 
 template <typename R, int RAD, int M, int NB, int NT, int SIGN, int NS>
@@ -135,14 +183,12 @@ __device__ __forceinline__ void fft_stage(cpx<R>* buf, const cpx<R>* tw) {
       for (int r = 0; r < RAD; ++r)
         x[r] = RD_LIN ? buf[pidx(i0) + r * padded(NBF)] : buf[pidx(i0 + r * NBF)];
       if constexpr (NS > 1) {
-        cpx<R> w[RAD];
         cpx<R> w1 = twiddle<R, M>(tw, k * (M / (NS * RAD)));
         if (SIGN < 0) w1.y = -w1.y;
-        twiddle_powers<R, RAD>(w1, w);
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) x[r] = cmul(x[r], w[r]);
+        dft_tw<R, RAD, SIGN>(x, w1);
+      } else {
+        dft<R, RAD, SIGN>(x);
       }
-      dft<R, RAD, SIGN>(x);
 #pragma unroll
       for (int r = 0; r < RAD; ++r) y[q][r] = x[r];
     }
@@ -207,14 +253,12 @@ __device__ __forceinline__ void fft_last_stage(const cpx<R>* buf, const cpx<R>* 
       for (int r = 0; r < RAD; ++r)
         x[r] = RD_LIN ? buf[pidx(i0) + r * padded(NBF)] : buf[pidx(i0 + r * NBF)];
       if constexpr (NS > 1) {
-        cpx<R> w[RAD];
         cpx<R> w1 = twiddle<R, M>(tw, j);
         if (SIGN < 0) w1.y = -w1.y;
-        twiddle_powers<R, RAD>(w1, w);
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) x[r] = cmul(x[r], w[r]);
+        dft_tw<R, RAD, SIGN>(x, w1);
+      } else {
+        dft<R, RAD, SIGN>(x);
       }
-      dft<R, RAD, SIGN>(x);
 #pragma unroll
       for (int r = 0; r < RAD; ++r) {
         const int f = r * NS + j;
