@@ -39,8 +39,14 @@
  *   Memory     every buffer argument marked "dev" is device memory on the
  *              plan's GPU; "host" is ordinary host memory.  The caller owns all
  *              input and output buffers; the library never frees them.  The
- *              plan owns its workspace (allocated once in pc_plan_create, size
- *              reported by pc_plan_footprint).
+ *              plan owns its workspace: pc_plan_create allocates what
+ *              pc_plan_footprint reports; per-call scratch that depends on the
+ *              request (atom tables and partial sums of the direct sums, sized
+ *              by the number of atoms; the dirty-image buffer and per-scale
+ *              keys of pc_adjoint_grid_ms; the row and atom tables of
+ *              pc_restricted_gradient_grid) is added on first use and kept,
+ *              and pc_plan_get_info's `footprint` is the total held at the
+ *              time.  pc_restricted_gradient_noalloc adds none.
  *   Streams    `stream` is a hipStream_t passed as void* (NULL = the null
  *              stream).  Calls are asynchronous on it, except that any host
  *              scalar output (max_abs, argmax, solve results) synchronises the
