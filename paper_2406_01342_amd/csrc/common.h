@@ -49,8 +49,12 @@ void set_last_error(const std::string& msg);
 // ----------------------------------------------------------------------------
 // Complex value types (interleaved, matching complex64 / complex128 buffers).
 // ----------------------------------------------------------------------------
+// Aligned to its own size, so that a complex value moves in one 64-bit (FP32)
+// or 128-bit (FP64) access: LDS then serves a wave's consecutive elements
+// without bank conflicts, where two 32-bit halves at an 8-byte stride
+// conflicted two ways.
 template <typename R>
-struct cpx {
+struct alignas(2 * sizeof(R)) cpx {
   R x, y;
 };
 using c32 = cpx<float>;

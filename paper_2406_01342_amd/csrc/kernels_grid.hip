@@ -168,7 +168,7 @@ __device__ __forceinline__ void spread_body(
     const R* __restrict__ off, const cpx<R>* __restrict__ vals, const int32_t* __restrict__ perm,
     cpx<R>* __restrict__ grid, cpx<R>* __restrict__ partials) {
   using C = SpreadCfg<R, W>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x;
   R* tre = reinterpret_cast<R*>(smem_raw);
   R* tim = tre + C::TILE;
@@ -572,7 +572,7 @@ __device__ __forceinline__ void spread_quad_body(
     cpx<float>* __restrict__ partials) {
   using C = SpreadG<W>;
   constexpr int WAVE_F = C::TILE_F + C::TAB_F;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* region = reinterpret_cast<float*>(smem_raw);
   const SpreadChunk& ch = quad[w];
@@ -804,7 +804,7 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
                                                cpx<R>* __restrict__ H,
                                                const cpx<R>* __restrict__ tw, int rowblock,
                                                const uint32_t* __restrict__ rows = nullptr) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
   constexpr int TR = (NB + kTile - 1) / kTile + 1;  // tile rows a row block can touch
@@ -946,7 +946,7 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
                                                int positive, int iblock,
                                                WPlane wp = WPlane{0.0, 0.0, 1},
                                                const uint32_t* __restrict__ rows = nullptr) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
   constexpr int n = M / 2;
@@ -1265,7 +1265,7 @@ __device__ __forceinline__ void passB_fwd_body(const GridGeom& g, const R* __res
                                                const cpx<R>* __restrict__ tw,
                                                const R* __restrict__ corr, int iblock,
                                                const uint32_t* __restrict__ rows) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
   constexpr int n = M / 2;
@@ -1311,7 +1311,7 @@ __global__ __launch_bounds__(NT) void passA_fwd_kernel(GridGeom g, const cpx<R>*
                                                         cpx<R>* __restrict__ grid,
                                                         const cpx<R>* __restrict__ tw,
                                                         const uint32_t* __restrict__ rows) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
   __shared__ cpx<R> tws[tw_count(M)];
   __shared__ uint32_t smask[kMaxRowWords];
