@@ -719,6 +719,25 @@ __global__ __launch_bounds__(64 * kFoldSub) void fold_batch_kernel(
   fold_body<float>(J.g, J.fold[it.y], J.partials, J.grid);
 }
 
+// v exp(+2 pi i q / RAD) for a runtime q >= 0 and RAD = 2 or 4: half turns as
+// sign changes, quarter turns as a swap of the parts plus sign changes, all
+// as selects (the pruned first stage's outputs are band values rotated so).
+// Exact; a zero v may come out as -0.
+template <typename R, int RAD>
+__device__ __forceinline__ cpx<R> turns_pos(cpx<R> v, int q) {
+  static_assert(RAD == 2 || RAD == 4, "half or quarter turns");
+  if constexpr (RAD == 2) {
+    const bool neg = (q & 1) != 0;
+    return {neg ? -v.x : v.x, neg ? -v.y : v.y};
+  } else {
+    q &= 3;
+    const bool sw = (q & 1) != 0;
+    const R a = sw ? v.y : v.x, b = sw ? v.x : v.y;
+    const bool na = ((q + 1) & 2) != 0, nb = (q & 2) != 0;  // q = 1, 2 and q = 2, 3
+    return {na ? -a : a, nb ? -b : b};
+  }
+}
+
 // Pass-A output layout: columns grouped in blocks of KHB, each block stored
 // row-major over the band rows, so that a pass-B workgroup reading KHB (or
 // fewer) adjacent columns reads one contiguous stretch.
@@ -841,8 +860,9 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
         const int rel = j + r * NBF0 - g.u0;
         const bool ok = e < NB * NBF0 && row < g.nv && r < RAD0 && (unsigned)rel < (unsigned)g.nu &&
                         sflag[row / kTile - tr0][rel / kTile] != 0;
-        t[it] = grid[ok ? (size_t)row * g.nu + rel : 0];
-        rr[it] = ok ? r : -1;
+        const cpx<R> v = grid[ok ? (size_t)row * g.nu + rel : 0];
+        t[it] = ok ? v : cpx<R>{R(0), R(0)};
+        rr[it] = ok ? r : 0;
       }
 #pragma unroll
       for (int it = 0; it < ITJ; ++it) {
@@ -851,8 +871,7 @@ __device__ __forceinline__ void passA_adj_body(const GridGeom& g, const cpx<R>* 
           const int b = e / NBF0, j = e - b * NBF0;
 #pragma unroll
           for (int s = 0; s < RAD0; ++s)
-            buf[pidx(b * M + j * RAD0 + s)] =
-                rr[it] >= 0 ? rot<R, RAD0, +1>(t[it], (rr[it] * s) % RAD0) : cpx<R>{R(0), R(0)};
+            buf[pidx(b * M + j * RAD0 + s)] = turns_pos<R, RAD0>(t[it], rr[it] * s);
         }
       }
     }
@@ -991,8 +1010,9 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
         const int r = d > 0 ? (d + NBF0 - 1) / NBF0 : 0;  // first input at or past v0
         const int rel = j + r * NBF0 - g.v0;
         const bool ok = j < NBF0 && r < RAD0 && (unsigned)rel < (unsigned)g.nv;
-        t[it] = hcol[ok ? (size_t)rel * KHB : 0];
-        rr[it] = ok ? r : -1;
+        const cpx<R> v = hcol[ok ? (size_t)rel * KHB : 0];
+        t[it] = ok ? v : cpx<R>{R(0), R(0)};
+        rr[it] = ok ? r : 0;
       }
 #pragma unroll
       for (int it = 0; it < ITJ; ++it) {
@@ -1000,8 +1020,7 @@ __device__ __forceinline__ void passB_adj_body(const GridGeom& g, const cpx<R>* 
         if (NBF0 % MSTEP == 0 || j < NBF0) {
 #pragma unroll
           for (int s = 0; s < RAD0; ++s)
-            buf[pidx(b * M + j * RAD0 + s)] =
-                rr[it] >= 0 ? rot<R, RAD0, +1>(t[it], (rr[it] * s) % RAD0) : cpx<R>{R(0), R(0)};
+            buf[pidx(b * M + j * RAD0 + s)] = turns_pos<R, RAD0>(t[it], rr[it] * s);
         }
       }
     }
